@@ -1,0 +1,397 @@
+"""Seeded synthetic inputs: vessel geometries and cell placements.
+
+This module is the one thing the HIP path and the CPU oracle both consume. It holds none
+of the method's arithmetic (no lattice Boltzmann, no shape function, no forces): it
+voxelises simple vessels and places rigid oblate ellipsoids without overlap, from a seed.
+
+Geometry convention: arrays are shaped (nz, ny, nx) so that the flat index is
+n = x + nx*(y + ny*z); node (x, y, z) sits at the point (x, y, z); 1 = solid.
+
+Placement rule: centres uniform in the fluid region, orientations uniform on SO(3)
+(normalised Gaussian quaternions), by random sequential addition vectorised in batches. A
+candidate is rejected when
+  * the node nearest its centre is solid;
+  * it meets an already placed cell: for ellipsoids with shape matrices
+    A = Q diag(a^2) Q^T, the Perram-Wertheim contact function at lambda = 1/2,
+    c = r^T (A_i + A_j)^-1 r / 2, is below s^2 (s = 1: no contact);
+  * it meets a wall mesh point: the point lies inside the ellipsoid grown to semi-axes
+    sqrt(2 (a^2 + a_wall^2)) (the same contact function with a sphere of radius a_wall).
+Random sequential addition jams below blood hematocrits (about 0.3 in a wide tube, less in
+narrow ones), so when the attempt budget runs out the pair scale s is lowered, to 0.97 at most (a slight
+soft overlap of the kind a small Gay-Berne energy scale permits, keeping the initial pair
+forces well below the plasma's stability bound), and the achieved count and hematocrit are
+returned.
+"""
+from __future__ import annotations
+
+import hashlib
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+from scipy.spatial import cKDTree
+
+
+# ---- geometries ----------------------------------------------------------------------------
+def tube(nx: int, ny: int, nz: int, radius: float) -> np.ndarray:
+    """Straight tube along z: fluid where (x-cx)^2 + (y-cy)^2 < R^2, c = (n-1)/2."""
+    x = np.arange(nx) - (nx - 1) / 2.0
+    y = np.arange(ny) - (ny - 1) / 2.0
+    r2 = x[None, :] ** 2 + y[:, None] ** 2
+    fluid2d = r2 < radius * radius
+    return np.broadcast_to(~fluid2d, (nz, ny, nx)).astype(np.uint8).copy()
+
+
+def slab(nx: int, ny: int, nz: int) -> np.ndarray:
+    """Plane channel: solid rows y = 0 and y = ny - 1, fluid elsewhere."""
+    s = np.zeros((nz, ny, nx), dtype=np.uint8)
+    s[:, 0, :] = 1
+    s[:, ny - 1, :] = 1
+    return s
+
+
+def _capsule_fluid(P, a, b, radius):
+    """Points within `radius` of the segment a-b. P: (..., 3)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    ab = b - a
+    t = np.clip(((P - a) @ ab) / float(ab @ ab), 0.0, 1.0)
+    d = P - (a + t[..., None] * ab)
+    return (d * d).sum(-1) < radius * radius
+
+
+def y_bifurcation(nx: int, ny: int, nz: int, r_parent: float, r_daughter: float,
+                  z_branch: float, angle_deg: float = 30.0) -> np.ndarray:
+    """Parent tube along z from z = 0 to z_branch, two daughters leaving the branch point at
+    +/- angle to +z in the x-z plane up to the top face (union of capsules)."""
+    cx, cy = (nx - 1) / 2.0, (ny - 1) / 2.0
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    P = np.stack([xx, yy, zz], -1).astype(np.float64)
+    # parent, extended below the inlet face so the inlet plane is a full disc
+    fl = _capsule_fluid(P, (cx, cy, -r_parent - 2.0), (cx, cy, z_branch), r_parent)
+    th = math.radians(angle_deg)
+    L = (nz - 1 - z_branch) / math.cos(th) + r_daughter + 2.0
+    for sgn in (-1.0, 1.0):
+        end = (cx + sgn * L * math.sin(th), cy, z_branch + L * math.cos(th))
+        fl |= _capsule_fluid(P, (cx, cy, z_branch), end, r_daughter)
+    solid = (~fl).astype(np.uint8)
+    return solid
+
+
+def elbow(nx: int, ny: int, nz: int, radius: float, bend_radius: float) -> np.ndarray:
+    """Single 90-degree bend: a tube along +z from the bottom face, a quarter torus of
+    centre-line radius `bend_radius` in the x-z plane, then a tube along +x to the x face."""
+    cy = (ny - 1) / 2.0
+    x0 = radius + 2.0
+    z0 = nz - 1 - bend_radius - radius - 2.0
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    P = np.stack([xx, yy, zz], -1).astype(np.float64)
+    fl = _capsule_fluid(P, (x0, cy, -radius - 2.0), (x0, cy, z0), radius)
+    # quarter torus: centre of curvature at (x0 + Rb, cy, z0)
+    cxb, czb = x0 + bend_radius, z0
+    dx, dz = xx - cxb, zz - czb
+    ang_ok = (dx <= 0) & (dz >= 0)
+    rho = np.sqrt(dx * dx + dz * dz)
+    tor = ((rho - bend_radius) ** 2 + (yy - cy) ** 2) < radius * radius
+    fl |= tor & ang_ok
+    fl |= _capsule_fluid(P, (x0 + bend_radius, cy, z0 + bend_radius),
+                         (nx + radius + 2.0, cy, z0 + bend_radius), radius)
+    return (~fl).astype(np.uint8)
+
+
+# ---- placement -----------------------------------------------------------------------------
+def random_rotations(rng: np.random.Generator, n: int) -> np.ndarray:
+    """n rotation matrices uniform on SO(3), (n, 3, 3); columns are the body axes."""
+    q = rng.normal(size=(n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = q.T
+    M = np.empty((n, 3, 3))
+    M[:, 0, 0] = 1 - 2 * (y * y + z * z)
+    M[:, 0, 1] = 2 * (x * y - w * z)
+    M[:, 0, 2] = 2 * (x * z + w * y)
+    M[:, 1, 0] = 2 * (x * y + w * z)
+    M[:, 1, 1] = 1 - 2 * (x * x + z * z)
+    M[:, 1, 2] = 2 * (y * z - w * x)
+    M[:, 2, 0] = 2 * (x * z - w * y)
+    M[:, 2, 1] = 2 * (y * z + w * x)
+    M[:, 2, 2] = 1 - 2 * (x * x + y * y)
+    return M
+
+
+def boundary_points(solid: np.ndarray, periodic) -> np.ndarray:
+    """Solid voxels with a fluid voxel among their 26 neighbours, as (m, 3) xyz."""
+    s = solid.astype(bool)
+    fl = ~s
+    near = np.zeros_like(s)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if dx == dy == dz == 0:
+                    continue
+                sh = np.roll(fl, (dz, dy, dx), axis=(0, 1, 2))
+                # non-periodic axes: rolled-in faces are not neighbours
+                for ax, d, per in ((0, dz, periodic[2]), (1, dy, periodic[1]), (2, dx, periodic[0])):
+                    if d and not per:
+                        idx = [slice(None)] * 3
+                        idx[ax] = 0 if d > 0 else -1
+                        sh[tuple(idx)] = False
+                near |= sh
+    z, y, x = np.nonzero(s & near)
+    return np.stack([x, y, z], 1).astype(np.float64)
+
+
+def _min_image(d: np.ndarray, box: np.ndarray, periodic) -> np.ndarray:
+    for a in range(3):
+        if periodic[a]:
+            d[..., a] -= box[a] * np.round(d[..., a] / box[a])
+    return d
+
+
+def _contact(r: np.ndarray, Ai: np.ndarray, Aj: np.ndarray) -> np.ndarray:
+    """Perram-Wertheim contact function at lambda = 1/2: r^T (Ai + Aj)^-1 r / 2."""
+    H = Ai + Aj
+    x = np.linalg.solve(H, r[..., None])[..., 0]
+    return 0.5 * (r * x).sum(-1)
+
+
+@dataclass
+class Placement:
+    R: np.ndarray          # (n, 3) centres
+    Q: np.ndarray          # (n, 9) row-major orientation, columns = body axes
+    hematocrit: float      # achieved volume fraction of the fluid region
+    s_pair: float          # final pair contact scale (1 = no contact between cells)
+    attempts: int
+
+
+def hematocrit_count(solid: np.ndarray, axes, H: float) -> int:
+    v = 4.0 / 3.0 * math.pi * axes[0] * axes[1] * axes[2]
+    return int(round(H * float((solid == 0).sum()) / v))
+
+
+class _Packer:
+    """Hard-ellipsoid packing state: overlap tests only, no forces or potentials."""
+
+    def __init__(self, solid, axes, periodic, a_wall, rng):
+        nz, ny, nx = solid.shape
+        self.box = np.array([nx, ny, nz], dtype=np.float64)
+        self.per = tuple(bool(p) for p in periodic)
+        self.axes = np.asarray(axes, dtype=np.float64)
+        self.S2 = np.diag(self.axes ** 2)
+        amax = float(self.axes.max())
+        self.r_pair = math.sqrt(4.0 * amax * amax)
+        self.r_wall = math.sqrt(2.0 * (amax * amax + a_wall * a_wall))
+        self.fluid = solid == 0
+        self.rng = rng
+        self.Aw = (a_wall * a_wall) * np.eye(3)
+        wall = boundary_points(solid, periodic)
+        self.wall = wall
+        self.wtree = _tree(wall, self.box, self.per) if len(wall) else None
+        zf, yf, xf = np.nonzero(self.fluid)
+        self.lo = np.array([xf.min(), yf.min(), zf.min()], dtype=np.float64) - 0.5
+        self.hi = np.array([xf.max(), yf.max(), zf.max()], dtype=np.float64) + 0.5
+        for a in range(3):
+            if self.per[a]:
+                self.lo[a], self.hi[a] = 0.0, self.box[a]
+
+    def shape(self, Q):
+        return Q @ self.S2 @ np.transpose(Q, (0, 2, 1))
+
+    def centre_ok(self, c):
+        ci = np.floor(c + 0.5).astype(np.int64)
+        ok = np.ones(len(c), dtype=bool)
+        for a in range(3):
+            n = int(self.box[a])
+            if self.per[a]:
+                ci[:, a] %= n
+            else:
+                ok &= (ci[:, a] >= 0) & (ci[:, a] < n)
+                ci[:, a] = np.clip(ci[:, a], 0, n - 1)
+        return ok & self.fluid[ci[:, 2], ci[:, 1], ci[:, 0]]
+
+    def walls_ok(self, c, A, ok):
+        if self.wtree is None:
+            return ok
+        idx = np.nonzero(ok)[0]
+        if not len(idx):
+            return ok
+        d1, _ = self.wtree.query(_tc(c[idx], self.box, self.per), k=1)
+        idx = idx[d1 < self.r_wall]
+        k = 64
+        while len(idx):
+            dist, j = self.wtree.query(_tc(c[idx], self.box, self.per), k=k,
+                                       distance_upper_bound=self.r_wall)
+            full = np.isfinite(dist[:, -1])
+            if full.any() and k < 1024:
+                k *= 2
+                continue
+            rows, cols = np.nonzero(np.isfinite(dist))
+            if len(rows):
+                d = _min_image(c[idx[rows]] - self.wall[j[rows, cols]], self.box, self.per)
+                bad = _contact(d, A[idx[rows]], np.broadcast_to(self.Aw, (len(rows), 3, 3))) < 1.0
+                ok[np.unique(idx[rows[bad]])] = False
+            break
+        return ok
+
+    def pairs_ok(self, c, A, ok, Rs, As, s2, exclude=None):
+        """Reject candidates within contact scale^2 s2 of placed cells (skip `exclude`)."""
+        idx = np.nonzero(ok)[0]
+        if not len(idx) or not len(Rs):
+            return ok
+        tree = _tree(Rs, self.box, self.per)
+        k = 32
+        while True:
+            dist, j = tree.query(_tc(c[idx], self.box, self.per), k=min(k, len(Rs)),
+                                 distance_upper_bound=self.r_pair)
+            if dist.ndim == 1:
+                dist, j = dist[:, None], j[:, None]
+            if np.isfinite(dist[:, -1]).any() and k < len(Rs):
+                k *= 2
+                continue
+            break
+        rows, cols = np.nonzero(np.isfinite(dist))
+        jj = j[rows, cols]
+        if exclude is not None:
+            keep = jj != exclude[idx[rows]]
+            rows, jj = rows[keep], jj[keep]
+        if len(rows):
+            d = _min_image(c[idx[rows]] - Rs[jj], self.box, self.per)
+            bad = _contact(d, A[idx[rows]], As[jj]) < s2
+            ok[np.unique(idx[rows[bad]])] = False
+        return ok
+
+    def min_pair_contact(self, Rs, As):
+        if len(Rs) < 2:
+            return np.inf
+        tree = _tree(Rs, self.box, self.per)
+        pr = tree.query_pairs(self.r_pair, output_type="ndarray")
+        if not len(pr):
+            return np.inf
+        d = _min_image(Rs[pr[:, 0]] - Rs[pr[:, 1]], self.box, self.per)
+        return float(_contact(d, As[pr[:, 0]], As[pr[:, 1]]).min())
+
+
+def place_cells(solid: np.ndarray, axes, n_target: int, seed: int, periodic=(0, 0, 1),
+                a_wall: float = 0.5, s_start: float = 1.0, s_floor: float = 0.97,
+                batch: int = 8192, rsa_attempts_per_cell: int = 16) -> Placement:
+    """Random sequential addition at pair contact scale s, lowered from s_start in steps
+    of 0.01 down to s_floor each time the attempt budget of a level runs out."""
+    rng = np.random.default_rng(seed)
+    pk = _Packer(solid, axes, periodic, a_wall, rng)
+    box, per = pk.box, pk.per
+    Rs = np.zeros((0, 3))
+    As = np.zeros((0, 3, 3))
+    Qs = np.zeros((0, 3, 3))
+    s = s_start
+    attempts = 0
+    budget = rsa_attempts_per_cell * max(n_target, 1)
+    while len(Rs) < n_target:
+        B = int(min(batch, 4 * (n_target - len(Rs)) + 64))
+        c = pk.lo + rng.random((B, 3)) * (pk.hi - pk.lo)
+        Qc = random_rotations(rng, B)
+        attempts += B
+        Ac = pk.shape(Qc)
+        ok = pk.centre_ok(c)
+        ok = pk.walls_ok(c, Ac, ok)
+        ok = pk.pairs_ok(c, Ac, ok, Rs, As, s * s)
+        idx = np.nonzero(ok)[0]
+        accepted = []
+        if len(idx):
+            bt = _tree(c[idx], box, per)
+            prs = bt.query_pairs(pk.r_pair, output_type="ndarray")
+            conflict = {}
+            if len(prs):
+                a_, b_ = idx[prs[:, 0]], idx[prs[:, 1]]
+                d = _min_image(c[a_] - c[b_], box, per)
+                bad = _contact(d, Ac[a_], Ac[b_]) < s * s
+                for x, y in zip(a_[bad], b_[bad]):
+                    lo_, hi_ = (x, y) if x < y else (y, x)
+                    conflict.setdefault(hi_, []).append(lo_)
+            acc = set()
+            for k in idx:
+                if any(j in acc for j in conflict.get(k, ())):
+                    continue
+                acc.add(k)
+                accepted.append(k)
+                if len(Rs) + len(accepted) >= n_target:
+                    break
+        if accepted:
+            acc = np.array(accepted)
+            Rs = np.concatenate([Rs, _wrap(c[acc], box, per)])
+            As = np.concatenate([As, Ac[acc]])
+            Qs = np.concatenate([Qs, Qc[acc]])
+        if attempts > budget:
+            if s <= s_floor + 1e-12:
+                break
+            s = max(s_floor, round(s - 0.01, 2))
+            budget = attempts + rsa_attempts_per_cell * max(n_target - len(Rs), 1)
+    v = 4.0 / 3.0 * math.pi * float(np.prod(pk.axes))
+    H = len(Rs) * v / float(pk.fluid.sum())
+    return Placement(R=Rs, Q=Qs.reshape(-1, 9), hematocrit=H, s_pair=s, attempts=attempts)
+
+
+def _wrap(c, box, periodic):
+    c = c.copy()
+    for a in range(3):
+        if periodic[a]:
+            c[:, a] %= box[a]
+    return c
+
+
+def _tc(pts, box, periodic):
+    """Tree coordinates: wrapped on periodic axes, shifted by +32 on the others."""
+    p = _wrap(pts, box, periodic)
+    for a in range(3):
+        if not periodic[a]:
+            p[:, a] += 32.0
+    return p
+
+
+def _tree(pts, box, periodic):
+    if any(periodic):
+        # cKDTree periodic boxes need every axis; non-periodic axes get a box wide enough
+        # that no wrap can bring two points closer than the query radius
+        bs = np.array([box[a] if periodic[a] else 4.0 * box[a] + 128.0 for a in range(3)])
+        return cKDTree(_tc(pts, box, periodic), boxsize=bs)
+    return cKDTree(_tc(pts, box, periodic))
+
+
+# ---- named workloads -------------------------------------------------------------------------
+AXES = (4.0, 4.0, 1.5)
+
+
+def _cache_dir():
+    d = os.environ.get("LBRBC_INPUT_CACHE",
+                       os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                    ".input_cache"))
+    return d
+
+
+def cached_placement(key: str, make):
+    """Placement memoised on disk (an .npz per key); regenerated when absent."""
+    d = _cache_dir()
+    fn = os.path.join(d, hashlib.sha1(key.encode()).hexdigest()[:16] + ".npz")
+    if os.path.exists(fn):
+        z = np.load(fn)
+        return Placement(R=z["R"], Q=z["Q"], hematocrit=float(z["H"]), s_pair=float(z["s"]),
+                         attempts=int(z["att"]))
+    pl = make()
+    try:
+        os.makedirs(d, exist_ok=True)
+        tmp = fn + f".{os.getpid()}.tmp.npz"
+        np.savez(tmp, R=pl.R, Q=pl.Q, H=pl.hematocrit, s=pl.s_pair, att=pl.attempts)
+        os.replace(tmp, fn)
+    except OSError:
+        pass
+    return pl
+
+
+def tube_workload(nx, ny, nz, radius, hematocrit=None, n_cells=None, seed=1107, **kw):
+    """Tube geometry plus seeded cells. Returns (solid, Placement)."""
+    solid = tube(nx, ny, nz, radius)
+    if n_cells is None:
+        n_cells = hematocrit_count(solid, AXES, hematocrit or 0.0)
+    key = f"tube:{nx}:{ny}:{nz}:{radius}:{n_cells}:{seed}:{sorted(kw.items())}:v1"
+    pl = cached_placement(key, lambda: place_cells(solid, AXES, n_cells, seed,
+                                                   periodic=(0, 0, 1), **kw))
+    return solid, pl
