@@ -1,0 +1,184 @@
+/*
+ * lbrbc.h -- C ABI of the MI355X (gfx950) library for the coupled plasma / rigid red-blood-
+ * cell time step of S. Melchionna, "A model for red blood cells in simulations of
+ * large-scale blood flows" (2011).
+ *
+ * One time step advances, on the GPU and on the caller's HIP stream:
+ *   rigid-body first half (App. A, steps 1-4) -> cell list -> node->cell coverage map ->
+ *   interpolation of velocity, vorticity and stress onto each cell (Sec. II B, Eqs. 16-21)
+ *   -> Gay-Berne cell-cell and cell-wall forces (Sec. II E, Eqs. 24-28; App. B) ->
+ *   rigid-body second half (App. A, steps 5-7) -> fused spreading of the back-reaction G
+ *   with the local relaxation time (Sec. II B; Sec. II D, Eq. 23) and D3Q19 pull
+ *   stream-collide with body force and halfway bounce-back (Sec. II A, Eqs. 1-8).
+ *
+ * Conventions (all lattice units, h = 1, mesh spacing 1, c^2 = 1/3):
+ *   - node (x, y, z) has flat index n = x + nx*(y + ny*z) and sits at the point (x, y, z);
+ *   - host arrays: solid[n] (uint8, 1 = solid); per node vectors [n*3 + a]; stress per node
+ *     [n*6 + k], k = xx, yy, zz, xy, xz, yz; populations [p*N + n] (unshifted f);
+ *   - D3Q19 order: 0 rest; 1-6 = +x, -x, +y, -y, +z, -z; 7-18 = (+1,+1,0), (-1,-1,0),
+ *     (+1,-1,0), (-1,+1,0), (+1,0,+1), (-1,0,-1), (+1,0,-1), (-1,0,+1), (0,+1,+1),
+ *     (0,-1,-1), (0,+1,-1), (0,-1,+1);
+ *   - a cell's orientation Q is row-major 3x3 whose columns are the body axes n, t, g in
+ *     the lab frame (Sec. II B, Eq. 9); V is lab frame, Omega is body frame.
+ *
+ * Ownership: every host pointer is read or written only during the call. Device memory
+ * comes from the caller as one arena (e.g. a torch uint8 tensor) of at least
+ * lb_query_footprint() bytes; the library never allocates or frees device memory, and the
+ * arena and the stream must outlive the context. lb_destroy frees host state only.
+ *
+ * Errors: every call returns lb_status; nothing throws across the ABI. Invalid arguments
+ * give LB_EINVAL synchronously. Faults found on the device (non-finite or non-positive
+ * density, |u| > 0.3, a Gay-Berne pair at rho_ij <= 0, a full coverage slot) set a flag
+ * word in the arena; the next synchronising call (lb_sync, lb_observe, any getter)
+ * returns it, after which the context answers LB_ESTATE to lb_step until lb_load or
+ * lb_set_fields. lb_last_error() gives a message for the last failure.
+ */
+#ifndef LBRBC_H
+#define LBRBC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lb_ctx_s* lb_ctx;
+
+typedef enum {
+    LB_OK = 0,
+    LB_EINVAL = 1,
+    LB_ENOMEM = 2,      /* arena too small */
+    LB_EHIP = 3,        /* a HIP runtime call failed */
+    LB_EUNSTABLE = 4,   /* non-finite or non-positive density, or |u| > 0.3 */
+    LB_EOVERLAP = 5,    /* Gay-Berne pair or cell-wall pair at rho <= 0 (singular) */
+    LB_ECAPACITY = 6,   /* more covering cells at a node than map_cap, or support too big */
+    LB_ESTATE = 7       /* context poisoned by an earlier device fault */
+} lb_status;
+
+typedef enum { LB_F64 = 0, LB_F32 = 1, LB_BF16 = 2, LB_F16 = 3 } lb_storage;
+
+typedef struct lb_config {
+    int nx, ny, nz;
+    int periodic[3];      /* 1: periodic axis; 0: box faces are walls (outside = solid) */
+    int storage;          /* lb_storage of the shifted populations f - w; F64 computes in
+                             double, the others in float */
+    double f16_scale;     /* LB_F16: stored value = scale * (f - w); a power of two */
+    int forcing;          /* 0: second-order (Guo) body-force term; 1: Eq. 4 as printed */
+    double tau0;          /* plasma relaxation time T0 > 1/2 (nu = (T0 - 1/2)/3) */
+    double delta_visc;    /* viscosity enhancement Delta (Eq. 23) */
+    double kappa;         /* smoothness exponent kappa (Eq. 23) */
+    double g_ext[3];      /* uniform body-force density on fluid nodes */
+    double gammaT, gammaR;/* coupling rates (Eqs. 14-15), per unit mass / inertia */
+    double alpha;         /* elongational torque factor (Eq. 16) */
+    double mass;          /* cell mass M */
+    double inertia[3];    /* body-frame principal moments */
+    double vort_scale;    /* factor on the smeared vorticity (1: full curl as printed) */
+    double xi[3];         /* shape-function radii (support |y_a| < xi_a in body frame) */
+    double axes[3];       /* Gay-Berne semi-axes (body frame) */
+    double eps0;          /* Gay-Berne energy scale */
+    double a_wall;        /* wall particle radius */
+    double sigmin_wall;   /* sigma_min of a cell-wall pair */
+    int wall_particles;   /* 1: wall mesh points repel the cells (Sec. II E, last par.) */
+    int open_z;           /* 1: z faces are pressure boundaries (inlet z = 0, outlet top) */
+    double rho_in, rho_out;
+    int map_cap;          /* coverage slots per node, 1..12 (0 = 12) */
+} lb_config;
+
+typedef struct lb_rbc {
+    double R[3];          /* centre, lab frame */
+    double Q[9];          /* orientation, row-major, columns = body axes */
+    double V[3];          /* velocity, lab frame */
+    double Omega[3];      /* angular velocity, body frame */
+} lb_rbc;
+
+typedef struct lb_observables {
+    double mass;          /* sum of populations over fluid nodes */
+    double momentum[3];   /* sum of f c over fluid nodes (post-collision) */
+    double flow_rate;     /* mean over z-slices of the summed u_z */
+    double eta_app;       /* pi R^4 g_z / (8 Q), R from the mean fluid cross-section */
+    double wss_mean;      /* wall shear stress over wall-adjacent fluid nodes */
+    double wss_max;
+    double wss_time_mean; /* time average of wss_mean since lb_wss_accumulate(ctx, 1) */
+    long long step;
+    unsigned flags;       /* device fault bits: 1 unstable, 2 overlap, 4 capacity */
+    long long n_fluid;
+    int n_wall_nodes;
+    int n_rbc;
+} lb_observables;
+
+/* Bytes of device arena needed for this configuration (solid: host, nx*ny*nz bytes). */
+lb_status lb_query_footprint(const lb_config* cfg, const uint8_t* solid, int n_rbc,
+                             size_t* arena_bytes);
+
+/* Build a context: fluid at rest (f = w, u = sigma = 0), cells from `cells` (host, copied),
+ * F^comb(0) and tau^comb(0) from the Gay-Berne forces at t = 0 (the fluid is at rest).
+ * arena: device pointer, >= footprint bytes, 256-byte aligned. hip_stream: hipStream_t
+ * (NULL = default stream). Synchronises the stream before returning. */
+lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cells, int n_rbc,
+                  void* arena, size_t arena_bytes, void* hip_stream, lb_ctx* out);
+
+/* Enqueue nsteps full coupled steps on the stream (asynchronous). */
+lb_status lb_step(lb_ctx ctx, int nsteps);
+
+/* Coupling only, at the current state, no time advance (asynchronous): cell list,
+ * coverage map, interpolation sums, hydrodynamic force/torque from the current V and
+ * Omega, and the spread force density and local relaxation time per node (readable with
+ * lb_get_fields). */
+lb_status rbc_couple(lb_ctx ctx);
+
+/* Cell list and Gay-Berne forces at the current positions (synchronous).
+ * F: host [3*n_rbc] lab force; T: host [3*n_rbc] body-frame torque. Either may be NULL. */
+lb_status rbc_collide(lb_ctx ctx, double* F, double* T);
+
+/* Synchronous reads. */
+lb_status lb_observe(lb_ctx ctx, lb_observables* out);
+/* Wall shear stress at each wall-adjacent fluid node, ascending node index. wss: host
+ * [*n] or NULL to query the count; node: host [*n] or NULL. With time != 0, the time
+ * average since lb_wss_accumulate(ctx, 1). */
+lb_status lb_wall_shear_stress(lb_ctx ctx, int time, double* wss, long long* node, int* n);
+lb_status lb_apparent_viscosity(lb_ctx ctx, double* eta_app);
+/* Start (on != 0, resetting the sums) or stop per-step FP64 accumulation of the WSS. */
+lb_status lb_wss_accumulate(lb_ctx ctx, int on);
+
+/* Host copies of the fields; any pointer may be NULL. f: [19*N] unshifted populations
+ * (post-collision of the last step); u: [3N]; sigma: [6N]; g: [3N] spread force density
+ * and relax: [N] local relaxation time from the last rbc_couple. */
+lb_status lb_get_fields(lb_ctx ctx, double* f, double* u, double* sigma, double* g,
+                        double* relax);
+/* Overwrite the fluid state from host arrays (any may be NULL); clears a device fault. */
+lb_status lb_set_fields(lb_ctx ctx, const double* f, const double* u, const double* sigma);
+
+lb_status rbc_get_state(lb_ctx ctx, lb_rbc* out, int n);
+lb_status rbc_set_state(lb_ctx ctx, const lb_rbc* in, int n);
+/* Per cell, 22 doubles: S, u~[3], w~[3], T^S[3] (lab), F^hyd[3] (lab), T^hyd[3] (lab),
+ * F^comb[3] (lab), tau^comb[3] (body). */
+lb_status rbc_get_coupling(lb_ctx ctx, double* out22, int n);
+/* Cell grid and list: ncell[3]; off[ncells + 1]; ids[n_rbc] ascending per cell. */
+lb_status rbc_get_cells(lb_ctx ctx, int* ncell, int* off, int* ids);
+/* Coverage map as CSR over all nodes, ids ascending per node: off[N + 1] (may be NULL),
+ * ids[*len] (NULL to query *len). */
+lb_status rbc_get_map(lb_ctx ctx, int* off, int* ids, long long* len);
+
+/* Checkpoint of the full dynamic state (populations in storage precision, fields, cells,
+ * combined forces, step count). buf == NULL: *bytes = size needed. */
+lb_status lb_save(lb_ctx ctx, void* buf, size_t* bytes);
+lb_status lb_load(lb_ctx ctx, const void* buf, size_t bytes);
+
+/* Serving: enqueue nsteps[i] steps for each of n contexts, interleaved step by step so
+ * the contexts' kernels overlap on the device. Contexts may use different streams. */
+lb_status lb_batch_step(lb_ctx* ctxs, const int* nsteps, int n);
+
+lb_status lb_sync(lb_ctx ctx);
+const char* lb_last_error(lb_ctx ctx);
+void lb_destroy(lb_ctx ctx);
+
+/* Average device duration (ms) of the stream-collide kernel over the last lb_step call
+ * that was timed (lb_set_timing(ctx, 1)); 0 if none. */
+lb_status lb_set_timing(lb_ctx ctx, int on);
+lb_status lb_kernel_time(lb_ctx ctx, double* sc_ms, double* step_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

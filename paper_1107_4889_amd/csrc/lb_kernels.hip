@@ -1,0 +1,446 @@
+// lb_kernels.hip -- per-node kernels: fused spreading + D3Q19 pull stream-collide,
+// open z boundaries, the spread-field probe and the FP64 reductions (gfx950).
+#include <climits>
+
+#include "lbrbc_device.h"
+#include "lbrbc_internal.h"
+
+namespace lbrbc {
+
+// ---- spreading at one node (Sec. II B back-reaction G; Sec. II D, Eq. 23) -----------------
+// g = g_ext - sum_i [F_i dhat_i - 1/2 T_i x grad(dhat_i)], theta = sum_i [1 - (1 - raw_i)^kappa]
+// over the covering cells in ascending id order (fixed order: bitwise repeatable). The
+// torque term carries the sign that hands the plasma -T_i of angular momentum.
+template <typename RT>
+__device__ __forceinline__ void spread_at(int x, int y, int z, long long n, uint32_t w,
+                                          const int* __restrict__ ids,
+                                          const Gather<RT>* __restrict__ gat, const KParams& kp,
+                                          RT g[3], RT& theta)
+{
+    g[0] = (RT)kp.gext[0];
+    g[1] = (RT)kp.gext[1];
+    g[2] = (RT)kp.gext[2];
+    theta = RT(0);
+    int cnt = (int)(w >> 24);
+    if (cnt > kp.cap) cnt = kp.cap;
+    if (cnt == 0) return;
+    int id[CAP_MAX];
+#pragma unroll
+    for (int k = 0; k < CAP_MAX; ++k) id[k] = (k < cnt) ? ids[(long long)k * kp.ld + n] : INT_MAX;
+    // odd-even transposition sort (static indices keep the ids in registers)
+#pragma unroll
+    for (int r = 0; r < CAP_MAX; ++r) {
+#pragma unroll
+        for (int k = (r & 1); k + 1 < CAP_MAX; k += 2) {
+            int a = min(id[k], id[k + 1]), b = max(id[k], id[k + 1]);
+            id[k] = a;
+            id[k + 1] = b;
+        }
+    }
+    const RT s0 = RT(2.0 / kp.xi[0]), s1 = RT(2.0 / kp.xi[1]), s2 = RT(2.0 / kp.xi[2]);
+    // an axis neighbour x +/- e_b that is solid has zero kernel: x + e_x is the pull source
+    // of direction 2 (c = -e_x), x - e_x of direction 1, and so on
+    const bool sxp = w & (1u << 2), sxm = w & (1u << 1), syp = w & (1u << 4),
+               sym = w & (1u << 3), szp = w & (1u << 6), szm = w & (1u << 5);
+    for (int k = 0; k < cnt; ++k) {
+        const int i = id[0];
+#pragma unroll
+        for (int j = 0; j + 1 < CAP_MAX; ++j) id[j] = id[j + 1];
+        const Gather<RT>& G = gat[i];
+        const RT dx = (RT)min_img((double)x - G.R[0], (double)kp.nx, kp.per[0]);
+        const RT dy = (RT)min_img((double)y - G.R[1], (double)kp.ny, kp.per[1]);
+        const RT dz = (RT)min_img((double)z - G.R[2], (double)kp.nz, kp.per[2]);
+        RT Q[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) Q[j] = G.Q[j];
+        const RT y0 = Q[0] * dx + Q[3] * dy + Q[6] * dz;
+        const RT y1 = Q[1] * dx + Q[4] * dy + Q[7] * dz;
+        const RT y2 = Q[2] * dx + Q[5] * dy + Q[8] * dz;
+        auto raw = [&](RT a, RT b, RT c) { return peskin(a * s0) * peskin(b * s1) * peskin(c * s2); };
+        const RT r0 = raw(y0, y1, y2);
+        const RT rpx = sxp ? RT(0) : raw(y0 + Q[0], y1 + Q[1], y2 + Q[2]);
+        const RT rmx = sxm ? RT(0) : raw(y0 - Q[0], y1 - Q[1], y2 - Q[2]);
+        const RT rpy = syp ? RT(0) : raw(y0 + Q[3], y1 + Q[4], y2 + Q[5]);
+        const RT rmy = sym ? RT(0) : raw(y0 - Q[3], y1 - Q[4], y2 - Q[5]);
+        const RT rpz = szp ? RT(0) : raw(y0 + Q[6], y1 + Q[7], y2 + Q[8]);
+        const RT rmz = szm ? RT(0) : raw(y0 - Q[6], y1 - Q[7], y2 - Q[8]);
+        const RT invS = G.invS;
+        const RT dh = r0 * invS;
+        const RT gr0 = RT(0.5) * (rpx - rmx) * invS;
+        const RT gr1 = RT(0.5) * (rpy - rmy) * invS;
+        const RT gr2 = RT(0.5) * (rpz - rmz) * invS;
+        const RT T0 = G.T[0], T1 = G.T[1], T2 = G.T[2];
+        const RT tg0 = T1 * gr2 - T2 * gr1;
+        const RT tg1 = T2 * gr0 - T0 * gr2;
+        const RT tg2 = T0 * gr1 - T1 * gr0;
+        g[0] -= G.F[0] * dh - RT(0.5) * tg0;
+        g[1] -= G.F[1] * dh - RT(0.5) * tg1;
+        g[2] -= G.F[2] * dh - RT(0.5) * tg2;
+        theta += RT(1) - ipow_or_pow(RT(1) - r0, kp.kappa, kp.kappa_int);
+    }
+}
+
+template <int P>
+__device__ __forceinline__ long long pull_src(int x, int y, int z, int xm, int xp, int ym, int yp,
+                                              int zm, int zp, const KParams& kp)
+{
+    // source of direction P is x - c_P
+    const int xs = cx_(P) == 1 ? xm : (cx_(P) == -1 ? xp : x);
+    const int ys = cy_(P) == 1 ? ym : (cy_(P) == -1 ? yp : y);
+    const int zs = cz_(P) == 1 ? zm : (cz_(P) == -1 ? zp : z);
+    return (long long)xs + (long long)kp.nx * ((long long)ys + (long long)kp.ny * zs);
+}
+
+template <typename ST, typename RT, int P>
+__device__ __forceinline__ void pull_one(RT* f, const ST* __restrict__ fin, long long n, uint32_t w,
+                                         int x, int y, int z, int xm, int xp, int ym, int yp,
+                                         int zm, int zp, const KParams& kp)
+{
+    constexpr int O = opp_(P);
+    if (w & (1u << P)) f[P] = Store<ST, RT>::ld(fin, (long long)O * kp.ld + n, kp.f16_inv);
+    else f[P] = Store<ST, RT>::ld(fin, (long long)P * kp.ld + pull_src<P>(x, y, z, xm, xp, ym, yp, zm, zp, kp), kp.f16_inv);
+}
+
+template <typename ST, typename RT, int... Ps>
+__device__ __forceinline__ void pull_all(RT* f, const ST* __restrict__ fin, long long n, uint32_t w,
+                                         int x, int y, int z, int xm, int xp, int ym, int yp,
+                                         int zm, int zp, const KParams& kp,
+                                         std::integer_sequence<int, Ps...>)
+{
+    (pull_one<ST, RT, Ps>(f, fin, n, w, x, y, z, xm, xp, ym, yp, zm, zp, kp), ...);
+}
+
+template <typename RT>
+__device__ __forceinline__ RT feq_shift(int p, RT drho, RT rho, RT ux, RT uy, RT uz, RT usq)
+{
+    // shifted equilibrium f^eq - w (Eq. 3, c^2 = 1/3)
+    const RT uc = RT(cx_(p)) * ux + RT(cy_(p)) * uy + RT(cz_(p)) * uz;
+    return RT(w_(p)) * (drho + rho * (RT(3) * uc + RT(4.5) * uc * uc - RT(1.5) * usq));
+}
+
+// ---- fused spreading + stream + collide (Sec. II A, Eqs. 1-8) -----------------------------
+// One thread per node; SoA planes f[p*ld + n] of the shifted populations f - w.
+template <typename ST, typename RT>
+__global__ __launch_bounds__(256) void k_stream_collide(
+    const ST* __restrict__ fin, ST* __restrict__ fout, const uint32_t* __restrict__ nodeword,
+    const int* __restrict__ ids, const Gather<RT>* __restrict__ gat, RT* __restrict__ uout,
+    RT* __restrict__ sout, KParams kp, unsigned* __restrict__ err)
+{
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= kp.N) return;
+    const uint32_t w = nodeword[n];
+    if (!(w & NW_FLUID) || (w & NW_OPEN)) return;
+    const int x = (int)(n % kp.nx);
+    const long long yz = n / kp.nx;
+    const int y = (int)(yz % kp.ny);
+    const int z = (int)(yz / kp.ny);
+    const int xm = x == 0 ? kp.nx - 1 : x - 1, xp = x == kp.nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? kp.ny - 1 : y - 1, yp = y == kp.ny - 1 ? 0 : y + 1;
+    const int zm = z == 0 ? kp.nz - 1 : z - 1, zp = z == kp.nz - 1 ? 0 : z + 1;
+
+    RT f[19];
+    pull_all<ST, RT>(f, fin, n, w, x, y, z, xm, xp, ym, yp, zm, zp, kp,
+                     std::make_integer_sequence<int, 19>{});
+
+    RT g[3], theta;
+    spread_at<RT>(x, y, z, n, w, ids, gat, kp, g, theta);
+
+    RT drho = RT(0), mx = RT(0), my = RT(0), mz = RT(0);
+#pragma unroll
+    for (int p = 0; p < 19; ++p) {
+        drho += f[p];
+        mx += RT(cx_(p)) * f[p];
+        my += RT(cy_(p)) * f[p];
+        mz += RT(cz_(p)) * f[p];
+    }
+    const RT rho = RT(1) + drho;
+    const RT irho = RT(1) / rho;
+    const RT ux = (mx + RT(0.5) * g[0]) * irho;
+    const RT uy = (my + RT(0.5) * g[1]) * irho;
+    const RT uz = (mz + RT(0.5) * g[2]) * irho;
+    const RT usq = ux * ux + uy * uy + uz * uz;
+    const RT T = (RT)kp.tau0 + (RT)kp.delta * theta;
+    const RT om = RT(1) / T;
+    const RT kf = kp.forcing == 1 ? RT(1) : RT(1) - RT(0.5) * om;
+    const RT k2 = kp.forcing == 1 ? RT(4.5) : RT(9);      // 1/(2c^4) or 1/c^4
+    const RT k3 = kp.forcing == 1 ? RT(1.5) : RT(3);      // c^2/(2c^4) or c^2/c^4
+    const RT gu = g[0] * ux + g[1] * uy + g[2] * uz;
+    RT sxx = 0, syy = 0, szz = 0, sxy = 0, sxz = 0, syz = 0;
+#pragma unroll
+    for (int p = 0; p < 19; ++p) {
+        const RT fe = feq_shift<RT>(p, drho, rho, ux, uy, uz, usq);
+        const RT neq = f[p] - fe;
+        const RT gc = RT(cx_(p)) * g[0] + RT(cy_(p)) * g[1] + RT(cz_(p)) * g[2];
+        const RT uc = RT(cx_(p)) * ux + RT(cy_(p)) * uy + RT(cz_(p)) * uz;
+        const RT Fp = kf * RT(w_(p)) * (RT(3) * gc + k2 * gc * uc - k3 * gu);
+        Store<ST, RT>::st(fout, (long long)p * kp.ld + n, f[p] - om * neq + Fp, kp.f16_scale);
+        if (cx_(p) * cx_(p)) sxx += neq;
+        if (cy_(p) * cy_(p)) syy += neq;
+        if (cz_(p) * cz_(p)) szz += neq;
+        if (cx_(p) * cy_(p)) sxy += RT(cx_(p) * cy_(p)) * neq;
+        if (cx_(p) * cz_(p)) sxz += RT(cx_(p) * cz_(p)) * neq;
+        if (cy_(p) * cz_(p)) syz += RT(cy_(p) * cz_(p)) * neq;
+    }
+    // stress of the non-equilibrium part: sigma = -(1 - 1/(2T)) sum c c (f - f^eq)
+    const RT ks = -(RT(1) - RT(0.5) * om);
+    __builtin_nontemporal_store(ux, uout + n);
+    __builtin_nontemporal_store(uy, uout + kp.ld + n);
+    __builtin_nontemporal_store(uz, uout + 2 * kp.ld + n);
+    __builtin_nontemporal_store(ks * sxx, sout + n);
+    __builtin_nontemporal_store(ks * syy, sout + kp.ld + n);
+    __builtin_nontemporal_store(ks * szz, sout + 2 * kp.ld + n);
+    __builtin_nontemporal_store(ks * sxy, sout + 3 * kp.ld + n);
+    __builtin_nontemporal_store(ks * sxz, sout + 4 * kp.ld + n);
+    __builtin_nontemporal_store(ks * syz, sout + 5 * kp.ld + n);
+    if (!(rho > RT(0)) || !(usq <= RT(0.09))) atomicOr(err, ERR_UNSTABLE);
+}
+
+// ---- open z faces: non-equilibrium extrapolation (Guo, Zheng & Shi 2002) ------------------
+template <typename ST, typename RT>
+__global__ __launch_bounds__(256) void k_open_bc(
+    const ST* __restrict__ fin, ST* __restrict__ fout, const uint32_t* __restrict__ nodeword,
+    const long long* __restrict__ plane_nodes, int nplane, const int* __restrict__ ids,
+    const Gather<RT>* __restrict__ gat, RT* __restrict__ uout, RT* __restrict__ sout, KParams kp)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nplane) return;
+    const long long n = plane_nodes[k];
+    const uint32_t w = nodeword[n];
+    const int x = (int)(n % kp.nx);
+    const long long yz = n / kp.nx;
+    const int y = (int)(yz % kp.ny);
+    const int z = (int)(yz / kp.ny);
+    const int zi = z == 0 ? 1 : kp.nz - 2;
+    const long long ni = (long long)x + (long long)kp.nx * ((long long)y + (long long)kp.ny * zi);
+    const uint32_t wi = nodeword[ni];
+    const RT rb = z == 0 ? (RT)kp.rho_in : (RT)kp.rho_out;
+    RT gb[3], thb;
+    spread_at<RT>(x, y, z, n, w, ids, gat, kp, gb, thb);
+    const RT om = RT(1) / ((RT)kp.tau0 + (RT)kp.delta * thb);
+#pragma unroll
+    for (int a = 0; a < 6; ++a) sout[(long long)a * kp.ld + n] = RT(0);
+    if (!(wi & NW_FLUID)) {
+        for (int p = 0; p < 19; ++p)
+            Store<ST, RT>::st(fout, (long long)p * kp.ld + n, RT(w_(p)) * (rb - RT(1)), kp.f16_scale);
+        for (int a = 0; a < 3; ++a) uout[(long long)a * kp.ld + n] = RT(0);
+        return;
+    }
+    const int xm = x == 0 ? kp.nx - 1 : x - 1, xp = x == kp.nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? kp.ny - 1 : y - 1, yp = y == kp.ny - 1 ? 0 : y + 1;
+    const int zm = zi - 1, zp = zi + 1;
+    RT f[19];
+    pull_all<ST, RT>(f, fin, ni, wi, x, y, zi, xm, xp, ym, yp, zm, zp, kp,
+                     std::make_integer_sequence<int, 19>{});
+    RT gi[3], thi;
+    spread_at<RT>(x, y, zi, ni, wi, ids, gat, kp, gi, thi);
+    RT drho = 0, mx = 0, my = 0, mz = 0;
+    for (int p = 0; p < 19; ++p) {
+        drho += f[p];
+        mx += RT(cx_(p)) * f[p];
+        my += RT(cy_(p)) * f[p];
+        mz += RT(cz_(p)) * f[p];
+    }
+    const RT rho = RT(1) + drho;
+    const RT ux = (mx + RT(0.5) * gi[0]) / rho, uy = (my + RT(0.5) * gi[1]) / rho,
+             uz = (mz + RT(0.5) * gi[2]) / rho;
+    const RT usq = ux * ux + uy * uy + uz * uz;
+    for (int p = 0; p < 19; ++p) {
+        const RT feb = feq_shift<RT>(p, rb - RT(1), rb, ux, uy, uz, usq);
+        const RT fei = feq_shift<RT>(p, drho, rho, ux, uy, uz, usq);
+        Store<ST, RT>::st(fout, (long long)p * kp.ld + n, feb + (RT(1) - om) * (f[p] - fei), kp.f16_scale);
+    }
+    uout[n] = ux;
+    uout[kp.ld + n] = uy;
+    uout[2 * kp.ld + n] = uz;
+}
+
+// ---- spread-field probe: g and T per fluid node (same device function as the step) -------
+template <typename RT>
+__global__ __launch_bounds__(256) void k_spread_field(const uint32_t* __restrict__ nodeword,
+                                                      const int* __restrict__ ids,
+                                                      const Gather<RT>* __restrict__ gat,
+                                                      RT* __restrict__ gout, RT* __restrict__ tout,
+                                                      KParams kp)
+{
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= kp.N) return;
+    const uint32_t w = nodeword[n];
+    if (!(w & NW_FLUID)) {
+        gout[n] = gout[kp.ld + n] = gout[2 * kp.ld + n] = RT(0);
+        tout[n] = (RT)kp.tau0;
+        return;
+    }
+    const int x = (int)(n % kp.nx);
+    const long long yz = n / kp.nx;
+    const int y = (int)(yz % kp.ny);
+    const int z = (int)(yz / kp.ny);
+    RT g[3], th;
+    spread_at<RT>(x, y, z, n, w, ids, gat, kp, g, th);
+    gout[n] = g[0];
+    gout[kp.ld + n] = g[1];
+    gout[2 * kp.ld + n] = g[2];
+    tout[n] = (RT)kp.tau0 + (RT)kp.delta * th;
+}
+
+// ---- coverage counters: clear the count byte, keep the static bits ------------------------
+__global__ __launch_bounds__(256) void k_clear_counts(uint32_t* __restrict__ nodeword, long long N)
+{
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n < N) {
+        const uint32_t w = nodeword[n];
+        if (w >> 24) nodeword[n] = w & NW_STATIC;
+    }
+}
+
+// ---- FP64 reductions: mass, momentum, summed u_z (two passes, fixed order) --------------
+template <typename ST, typename RT>
+__global__ __launch_bounds__(256) void k_observe_partials(const ST* __restrict__ f,
+                                                          const uint32_t* __restrict__ nodeword,
+                                                          const RT* __restrict__ u, KParams kp,
+                                                          double* __restrict__ partials)
+{
+    double acc[6] = {0, 0, 0, 0, 0, 0};   // mass, px, py, pz, sum uz, n_fluid
+    for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < kp.N;
+         n += (long long)gridDim.x * blockDim.x) {
+        if (!(nodeword[n] & NW_FLUID)) continue;
+        double m = 0, px = 0, py = 0, pz = 0;
+        for (int p = 0; p < 19; ++p) {
+            const double v = (double)Store<ST, RT>::ld(f, (long long)p * kp.ld + n, kp.f16_inv);
+            m += v;
+            px += cx_(p) * v;
+            py += cy_(p) * v;
+            pz += cz_(p) * v;
+        }
+        acc[0] += 1.0 + m;
+        acc[1] += px;
+        acc[2] += py;
+        acc[3] += pz;
+        acc[4] += (double)u[2 * kp.ld + n];
+        acc[5] += 1.0;
+    }
+    __shared__ double red[6][256];
+    for (int a = 0; a < 6; ++a) red[a][threadIdx.x] = acc[a];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int a = 0; a < 6; ++a) red[a][threadIdx.x] += red[a][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 6; ++a) partials[(long long)a * gridDim.x + blockIdx.x] = red[a][0];
+}
+
+__global__ void k_observe_final(const double* __restrict__ partials, int nblk, double* __restrict__ out)
+{
+    // one thread per quantity, fixed order
+    const int a = threadIdx.x;
+    if (a < 6) {
+        double s = 0;
+        for (int b = 0; b < nblk; ++b) s += partials[(long long)a * nblk + b];
+        out[a] = s;
+    }
+}
+
+// ---- wall shear stress at wall-adjacent nodes (FP64) ----------------------------------------
+template <typename RT>
+__global__ __launch_bounds__(256) void k_wss(const RT* __restrict__ sig,
+                                             const long long* __restrict__ wn_node,
+                                             const double* __restrict__ wn_nrm, int nwn, KParams kp,
+                                             double* __restrict__ wss, double* __restrict__ acc,
+                                             int accumulate)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nwn) return;
+    const long long n = wn_node[k];
+    double s[6];
+    for (int a = 0; a < 6; ++a) s[a] = (double)sig[(long long)a * kp.ld + n];
+    const double n0 = wn_nrm[3 * k], n1 = wn_nrm[3 * k + 1], n2 = wn_nrm[3 * k + 2];
+    const double t0 = s[0] * n0 + s[3] * n1 + s[4] * n2;
+    const double t1 = s[3] * n0 + s[1] * n1 + s[5] * n2;
+    const double t2 = s[4] * n0 + s[5] * n1 + s[2] * n2;
+    const double tn = t0 * n0 + t1 * n1 + t2 * n2;
+    const double r0 = t0 - tn * n0, r1 = t1 - tn * n1, r2 = t2 - tn * n2;
+    const double v = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
+    if (wss) wss[k] = v;
+    if (accumulate) acc[k] += v;
+}
+
+// ---- launchers ---------------------------------------------------------------------------------
+template <typename ST, typename RT>
+void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword, const int* ids,
+                           const void* gat, void* u, void* sig, const KParams& kp, unsigned* err,
+                           hipStream_t st)
+{
+    const unsigned blocks = (unsigned)((kp.N + 255) / 256);
+    hipLaunchKernelGGL((k_stream_collide<ST, RT>), dim3(blocks), dim3(256), 0, st,
+                       (const ST*)fin, (ST*)fout, nodeword, ids, (const Gather<RT>*)gat, (RT*)u,
+                       (RT*)sig, kp, err);
+}
+
+template <typename ST, typename RT>
+void launch_open_bc(const void* fin, void* fout, const uint32_t* nodeword, const long long* planes,
+                    int nplane, const int* ids, const void* gat, void* u, void* sig,
+                    const KParams& kp, hipStream_t st)
+{
+    if (nplane <= 0) return;
+    hipLaunchKernelGGL((k_open_bc<ST, RT>), dim3((nplane + 255) / 256), dim3(256), 0, st,
+                       (const ST*)fin, (ST*)fout, nodeword, planes, nplane, ids,
+                       (const Gather<RT>*)gat, (RT*)u, (RT*)sig, kp);
+}
+
+template <typename RT>
+void launch_spread_field(const uint32_t* nodeword, const int* ids, const void* gat, void* g,
+                         void* t, const KParams& kp, hipStream_t st)
+{
+    const unsigned blocks = (unsigned)((kp.N + 255) / 256);
+    hipLaunchKernelGGL((k_spread_field<RT>), dim3(blocks), dim3(256), 0, st, nodeword, ids,
+                       (const Gather<RT>*)gat, (RT*)g, (RT*)t, kp);
+}
+
+void launch_clear_counts(uint32_t* nodeword, long long N, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_clear_counts, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
+                       nodeword, N);
+}
+
+template <typename ST, typename RT>
+void launch_observe(const void* f, const uint32_t* nodeword, const void* u, const KParams& kp,
+                    double* partials, int nblk, double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_observe_partials<ST, RT>), dim3(nblk), dim3(256), 0, st, (const ST*)f,
+                       nodeword, (const RT*)u, kp, partials);
+    hipLaunchKernelGGL(k_observe_final, dim3(1), dim3(64), 0, st, partials, nblk, out);
+}
+
+template <typename RT>
+void launch_wss(const void* sig, const long long* wn_node, const double* wn_nrm, int nwn,
+                const KParams& kp, double* wss, double* acc, int accumulate, hipStream_t st)
+{
+    if (nwn <= 0) return;
+    hipLaunchKernelGGL((k_wss<RT>), dim3((nwn + 255) / 256), dim3(256), 0, st, (const RT*)sig,
+                       wn_node, wn_nrm, nwn, kp, wss, acc, accumulate);
+}
+
+#define INST_ST(ST, RT)                                                                           \
+    template void launch_stream_collide<ST, RT>(const void*, void*, const uint32_t*, const int*,  \
+                                                const void*, void*, void*, const KParams&,        \
+                                                unsigned*, hipStream_t);                          \
+    template void launch_open_bc<ST, RT>(const void*, void*, const uint32_t*, const long long*,   \
+                                         int, const int*, const void*, void*, void*,              \
+                                         const KParams&, hipStream_t);                            \
+    template void launch_observe<ST, RT>(const void*, const uint32_t*, const void*,               \
+                                         const KParams&, double*, int, double*, hipStream_t);
+INST_ST(double, double)
+INST_ST(float, float)
+INST_ST(bf16_t, float)
+INST_ST(_Float16, float)
+template void launch_spread_field<double>(const uint32_t*, const int*, const void*, void*, void*,
+                                          const KParams&, hipStream_t);
+template void launch_spread_field<float>(const uint32_t*, const int*, const void*, void*, void*,
+                                         const KParams&, hipStream_t);
+template void launch_wss<double>(const void*, const long long*, const double*, int,
+                                 const KParams&, double*, double*, int, hipStream_t);
+template void launch_wss<float>(const void*, const long long*, const double*, int,
+                                const KParams&, double*, double*, int, hipStream_t);
+
+}  // namespace lbrbc

@@ -1,0 +1,1013 @@
+// lbrbc_api.hip -- C ABI of the MI355X library: arena layout, host-side geometry tables,
+// step orchestration on the caller's stream, getters/setters, checkpoints, timing.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/lbrbc.h"
+#include "lbrbc_device.h"
+#include "lbrbc_internal.h"
+
+using namespace lbrbc;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr int OBS_BLOCKS = 1024;
+constexpr int MAX_TIMED = 4096;
+
+size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+int storage_bytes(int s) { return s == LB_F64 ? 8 : (s == LB_F32 ? 4 : 2); }
+int real_bytes(int s) { return s == LB_F64 ? 8 : 4; }
+
+// ---- host geometry tables --------------------------------------------------------------------
+struct Geometry {
+    long long N = 0, ld = 0, n_fluid = 0;
+    std::vector<uint32_t> nodeword;
+    std::vector<int> wall_xyz;       // solid nodes with a fluid D3Q19 neighbour
+    std::vector<long long> wn_node;  // wall-adjacent fluid nodes
+    std::vector<double> wn_nrm;
+    std::vector<long long> planes;   // open-boundary plane nodes
+    int ncell[3] = {1, 1, 1};
+    double cedge[3] = {1, 1, 1};
+    double rc = 0;
+    std::vector<int> wcell_off, wcell_ids;
+    int tile_max = 0;
+};
+
+long long node_at(const lb_config& c, int x, int y, int z)
+{
+    if (x < 0 || x >= c.nx) { if (!c.periodic[0]) return -1; x = ((x % c.nx) + c.nx) % c.nx; }
+    if (y < 0 || y >= c.ny) { if (!c.periodic[1]) return -1; y = ((y % c.ny) + c.ny) % c.ny; }
+    if (z < 0 || z >= c.nz) { if (!c.periodic[2]) return -1; z = ((z % c.nz) + c.nz) % c.nz; }
+    return (long long)x + (long long)c.nx * ((long long)y + (long long)c.ny * z);
+}
+
+std::string validate(const lb_config& c, int n_rbc)
+{
+    if (c.nx < 1 || c.ny < 1 || c.nz < 1) return "lattice dimensions must be positive";
+    if (c.storage < LB_F64 || c.storage > LB_F16) return "unknown storage";
+    if (!(c.tau0 > 0.5)) return "tau0 must exceed 1/2";
+    if (c.forcing != 0 && c.forcing != 1) return "forcing must be 0 or 1";
+    if (c.map_cap < 0 || c.map_cap > CAP_MAX) return "map_cap must be in 0..12";
+    if (c.storage == LB_F16 && !(c.f16_scale > 0)) return "f16_scale must be positive";
+    if (c.open_z && c.periodic[2]) return "open z faces need a non-periodic z axis";
+    if (c.open_z && c.nz < 3) return "open z faces need nz >= 3";
+    if (n_rbc < 0) return "negative cell count";
+    if (n_rbc > 0) {
+        if (!(c.mass > 0) || !(c.inertia[0] > 0) || !(c.inertia[1] > 0) || !(c.inertia[2] > 0))
+            return "mass and inertia must be positive";
+        if (!(c.xi[0] > 0) || !(c.xi[1] > 0) || !(c.xi[2] > 0)) return "xi must be positive";
+        if (!(c.axes[0] > 0) || !(c.axes[1] > 0) || !(c.axes[2] > 0)) return "axes must be positive";
+        if (!(c.eps0 > 0)) return "eps0 must be positive";
+        if (c.kappa < 0) return "kappa must be non-negative";
+    }
+    return "";
+}
+
+std::string build_geometry(const lb_config& c, const uint8_t* solid, int n_rbc, Geometry& g)
+{
+    g.N = (long long)c.nx * c.ny * c.nz;
+    g.ld = (g.N + 255) / 256 * 256;
+    g.nodeword.assign((size_t)g.N, 0u);
+    auto is_fluid = [&](int x, int y, int z) {
+        long long m = node_at(c, x, y, z);
+        return m >= 0 && !solid[m];
+    };
+    for (int z = 0; z < c.nz; ++z)
+        for (int y = 0; y < c.ny; ++y)
+            for (int x = 0; x < c.nx; ++x) {
+                const long long n = (long long)x + (long long)c.nx * ((long long)y + (long long)c.ny * z);
+                if (solid[n]) {
+                    bool adj = false;
+                    for (int p = 1; p < 19; ++p)
+                        if (is_fluid(x + cx_(p), y + cy_(p), z + cz_(p))) adj = true;
+                    if (adj) {
+                        g.wall_xyz.push_back(x);
+                        g.wall_xyz.push_back(y);
+                        g.wall_xyz.push_back(z);
+                    }
+                    continue;
+                }
+                uint32_t w = NW_FLUID;
+                double nv[3] = {0, 0, 0};
+                bool wadj = false;
+                for (int p = 1; p < 19; ++p) {
+                    if (!is_fluid(x - cx_(p), y - cy_(p), z - cz_(p))) w |= 1u << p;
+                    const long long m = node_at(c, x + cx_(p), y + cy_(p), z + cz_(p));
+                    if (m >= 0 && solid[m]) {
+                        wadj = true;
+                        nv[0] += w_(p) * cx_(p);
+                        nv[1] += w_(p) * cy_(p);
+                        nv[2] += w_(p) * cz_(p);
+                    }
+                }
+                if (wadj) {
+                    w |= NW_WALLADJ;
+                    const double len = std::sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+                    g.wn_node.push_back(n);
+                    for (int a = 0; a < 3; ++a) g.wn_nrm.push_back(len > 0 ? nv[a] / len : 0.0);
+                }
+                if (c.open_z && (z == 0 || z == c.nz - 1)) {
+                    w |= NW_OPEN;
+                    g.planes.push_back(n);
+                }
+                g.nodeword[n] = w;
+                g.n_fluid++;
+            }
+    // cell grid: r_c bounds every Gay-Berne cut-off (cell-cell and cell-wall)
+    const double amax = std::max(c.axes[0], std::max(c.axes[1], c.axes[2]));
+    const double amin = std::min(c.axes[0], std::min(c.axes[1], c.axes[2]));
+    const double sm = std::sqrt(4.0 * amin * amin);
+    const double shift = std::pow(2.0, 1.0 / 6.0) - 1.0;
+    const double rc_cc = std::sqrt(4.0 * amax * amax) + shift * sm;
+    const double rc_cw = std::sqrt(2.0 * (amax * amax + c.a_wall * c.a_wall)) + shift * c.sigmin_wall;
+    g.rc = std::max(rc_cc, rc_cw);
+    const int L[3] = {c.nx, c.ny, c.nz};
+    for (int a = 0; a < 3; ++a) {
+        int m = (int)std::floor(L[a] / g.rc);
+        if (m < 1) m = 1;
+        g.ncell[a] = m;
+        g.cedge[a] = (double)L[a] / m;
+    }
+    const int nc = g.ncell[0] * g.ncell[1] * g.ncell[2];
+    const int nwall = (int)g.wall_xyz.size() / 3;
+    std::vector<int> cnt(nc, 0), wc(nwall);
+    auto cell_of = [&](double v, int a) {
+        int q = (int)std::floor(v / g.cedge[a]);
+        return std::min(std::max(q, 0), g.ncell[a] - 1);
+    };
+    for (int k = 0; k < nwall; ++k) {
+        wc[k] = cell_of(g.wall_xyz[3 * k], 0) +
+                g.ncell[0] * (cell_of(g.wall_xyz[3 * k + 1], 1) + g.ncell[1] * cell_of(g.wall_xyz[3 * k + 2], 2));
+        cnt[wc[k]]++;
+    }
+    g.wcell_off.assign(nc + 1, 0);
+    for (int q = 0; q < nc; ++q) g.wcell_off[q + 1] = g.wcell_off[q] + cnt[q];
+    g.wcell_ids.assign(std::max(nwall, 1), 0);
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (int k = 0; k < nwall; ++k) g.wcell_ids[g.wcell_off[wc[k]] + cnt[wc[k]]++] = k;
+    // support tile bound (support box plus one node on each side, plus rounding)
+    const double r = std::sqrt(c.xi[0] * c.xi[0] + c.xi[1] * c.xi[1] + c.xi[2] * c.xi[2]);
+    g.tile_max = 2 * (int)std::ceil(r) + 5;
+    if (n_rbc > 0) {
+        // the double-precision interpolation tile (tile_max^3 values) must fit 64 KiB of LDS
+        if (g.tile_max > 20) return "shape-function support too large for the LDS tile";
+        for (int a = 0; a < 3; ++a)
+            if (c.periodic[a] && L[a] < g.tile_max + 2) return "periodic axis shorter than a support tile";
+        for (int a = 0; a < 3; ++a)
+            if (c.periodic[a] && L[a] <= 2.0 * g.rc) return "periodic axis shorter than twice the cut-off";
+    }
+    return "";
+}
+
+// ---- arena layout --------------------------------------------------------------------------
+struct Layout {
+    size_t fA, fB, u, sig, gdbg, tdbg, nodeword, map_ids, st, cp, gat, cellid, cell_cnt, cell_off,
+        cell_ids, wall_xyz, wcell_off, wcell_ids, wn_node, wn_nrm, wss, wss_acc, planes, partials,
+        obs_out, err, total;
+};
+
+Layout layout(const lb_config& c, const Geometry& g, int n_rbc)
+{
+    Layout L{};
+    const size_t ss = storage_bytes(c.storage), rs = real_bytes(c.storage);
+    const int cap = c.map_cap == 0 ? CAP_MAX : c.map_cap;
+    const size_t nc = (size_t)g.ncell[0] * g.ncell[1] * g.ncell[2];
+    const size_t nwall = g.wall_xyz.size() / 3, nwn = g.wn_node.size();
+    const size_t ld = (size_t)g.ld;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o += up(std::max<size_t>(bytes, 1));
+        return at;
+    };
+    L.fA = take(19 * ld * ss);
+    L.fB = take(19 * ld * ss);
+    L.u = take(3 * ld * rs);
+    L.sig = take(6 * ld * rs);
+    L.gdbg = take(3 * ld * rs);
+    L.tdbg = take(ld * rs);
+    L.nodeword = take(ld * 4);
+    L.map_ids = take(n_rbc > 0 ? (size_t)cap * ld * 4 : 4);
+    L.st = take(n_rbc * sizeof(RbcState));
+    L.cp = take(n_rbc * sizeof(RbcCouple));
+    L.gat = take(n_rbc * (rs == 8 ? sizeof(Gather<double>) : sizeof(Gather<float>)));
+    L.cellid = take(n_rbc * 4);
+    L.cell_cnt = take(nc * 4);
+    L.cell_off = take((nc + 1) * 4);
+    L.cell_ids = take(n_rbc * 4);
+    L.wall_xyz = take(nwall * 3 * 4);
+    L.wcell_off = take((nc + 1) * 4);
+    L.wcell_ids = take(std::max<size_t>(nwall, 1) * 4);
+    L.wn_node = take(nwn * 8);
+    L.wn_nrm = take(nwn * 3 * 8);
+    L.wss = take(nwn * 8);
+    L.wss_acc = take(nwn * 8);
+    L.planes = take(g.planes.size() * 8);
+    L.partials = take(6 * OBS_BLOCKS * 8);
+    L.obs_out = take(8 * 8);
+    L.err = take(4);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+struct lb_ctx_s {
+    lb_config cfg;
+    KParams kp;
+    Geometry geo;
+    Layout lay;
+    hipStream_t stream = nullptr;
+    char* base = nullptr;
+    void *fA = nullptr, *fB = nullptr;
+    CellBuffers cb{};
+    long long step = 0;
+    int nrbc = 0;
+    bool poisoned = false;
+    unsigned fault = 0;
+    int wss_on = 0;
+    long long wss_count = 0;
+    std::string last_error;
+    // timing of the stream-collide kernel and of whole steps
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> sc_pairs;
+    hipEvent_t step_t0 = nullptr, step_t1 = nullptr;
+    int timed_steps = 0;
+    bool step_t0_set = false;
+
+    template <typename T>
+    T* at(size_t off) { return reinterpret_cast<T*>(base + off); }
+};
+
+namespace {
+
+// message of the last lb_init / lb_query_footprint failure (no context exists then)
+std::string g_init_error;
+
+lb_status fail(lb_ctx c, lb_status s, const std::string& msg)
+{
+    if (c) c->last_error = msg;
+    else g_init_error = msg;
+    return s;
+}
+
+lb_status init_fail(lb_ctx c, lb_status s, const std::string& msg)
+{
+    delete c;
+    g_init_error = msg;
+    return s;
+}
+
+#define HIPCHK(ctx, expr)                                                                        \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail(ctx, LB_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));       \
+    } while (0)
+
+// dispatch on the storage type
+template <typename F>
+void with_types(int storage, F&& f)
+{
+    switch (storage) {
+    case LB_F64: f((double*)nullptr, (double*)nullptr); break;
+    case LB_F32: f((float*)nullptr, (float*)nullptr); break;
+    case LB_BF16: f((bf16_t*)nullptr, (float*)nullptr); break;
+    default: f((_Float16*)nullptr, (float*)nullptr); break;
+    }
+}
+
+// host conversions of one stored population value to/from the shifted float value
+double load_stored(const void* p, size_t i, int storage, double inv)
+{
+    switch (storage) {
+    case LB_F64: return ((const double*)p)[i];
+    case LB_F32: return ((const float*)p)[i];
+    case LB_BF16: {
+        uint32_t u = (uint32_t)((const uint16_t*)p)[i] << 16;
+        float f;
+        std::memcpy(&f, &u, 4);
+        return f;
+    }
+    default: return (double)(float)((const _Float16*)p)[i] * inv;
+    }
+}
+
+void store_value(void* p, size_t i, int storage, double v, double scale)
+{
+    switch (storage) {
+    case LB_F64: ((double*)p)[i] = v; break;
+    case LB_F32: ((float*)p)[i] = (float)v; break;
+    case LB_BF16: {
+        float f = (float)v;
+        uint32_t u;
+        std::memcpy(&u, &f, 4);
+        uint16_t r = ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu))
+                         ? 0x7fc0
+                         : (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+        ((uint16_t*)p)[i] = r;
+        break;
+    }
+    default: ((_Float16*)p)[i] = (_Float16)(float)(v * scale); break;
+    }
+}
+
+double load_real(const void* p, size_t i, int storage)
+{
+    return storage == LB_F64 ? ((const double*)p)[i] : (double)((const float*)p)[i];
+}
+void store_real(void* p, size_t i, int storage, double v)
+{
+    if (storage == LB_F64) ((double*)p)[i] = v;
+    else ((float*)p)[i] = (float)v;
+}
+
+lb_status check_fault(lb_ctx c)
+{
+    unsigned e = 0;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(&e, c->cb.err, 4, hipMemcpyDeviceToHost));
+    if (e) {
+        c->fault |= e;
+        c->poisoned = true;
+        if (e & ERR_OVERLAP) return fail(c, LB_EOVERLAP, "Gay-Berne pair at rho <= 0 (singular overlap)");
+        if (e & ERR_UNSTABLE) return fail(c, LB_EUNSTABLE, "non-finite or non-positive density, or |u| > 0.3");
+        return fail(c, LB_ECAPACITY, "coverage slots per node or support tile exhausted");
+    }
+    return LB_OK;
+}
+
+void enqueue_cells_and_map(lb_ctx c)
+{
+    hipStream_t s = c->stream;
+    launch_cell_list(c->cb, c->kp, s);
+    launch_clear_counts(c->cb.nodeword, c->kp.N, s);
+    launch_map_fill(c->cb, c->kp, s);
+}
+
+void enqueue_step(lb_ctx c)
+{
+    hipStream_t s = c->stream;
+    const KParams& kp = c->kp;
+    c->cb.u = c->at<void>(c->lay.u);
+    c->cb.sig = c->at<void>(c->lay.sig);
+    with_types(c->cfg.storage, [&](auto* sp, auto* rp) {
+        using ST = std::remove_pointer_t<decltype(sp)>;
+        using RT = std::remove_pointer_t<decltype(rp)>;
+        if (c->nrbc > 0) {
+            launch_rb_first_half(c->cb, kp, s);
+            enqueue_cells_and_map(c);
+            launch_couple<RT>(c->cb, kp, s);
+            launch_gay_berne(c->cb, kp, s);
+            launch_rb_second_half<RT>(c->cb, kp, 1, s);
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (c->timing && (int)c->sc_pairs.size() < MAX_TIMED && c->ev_pool.size() >= 2) {
+            e0 = c->ev_pool.back();
+            c->ev_pool.pop_back();
+            e1 = c->ev_pool.back();
+            c->ev_pool.pop_back();
+            (void)hipEventRecord(e0, s);
+        }
+        launch_stream_collide<ST, RT>(c->fA, c->fB, c->cb.nodeword, c->cb.map_ids, c->cb.gat,
+                                      c->at<void>(c->lay.u), c->at<void>(c->lay.sig), kp, c->cb.err, s);
+        if (e0) {
+            (void)hipEventRecord(e1, s);
+            c->sc_pairs.emplace_back(e0, e1);
+        }
+        if (!c->geo.planes.empty())
+            launch_open_bc<ST, RT>(c->fA, c->fB, c->cb.nodeword, c->at<long long>(c->lay.planes),
+                                   (int)c->geo.planes.size(), c->cb.map_ids, c->cb.gat,
+                                   c->at<void>(c->lay.u), c->at<void>(c->lay.sig), kp, s);
+        if (c->wss_on)
+            launch_wss<RT>(c->at<void>(c->lay.sig), c->at<long long>(c->lay.wn_node),
+                           c->at<double>(c->lay.wn_nrm), (int)c->geo.wn_node.size(), kp, nullptr,
+                           c->at<double>(c->lay.wss_acc), 1, s);
+    });
+    if (c->wss_on) c->wss_count++;
+    std::swap(c->fA, c->fB);
+    c->step++;
+}
+
+}  // namespace
+
+extern "C" {
+
+lb_status lb_query_footprint(const lb_config* cfg, const uint8_t* solid, int n_rbc, size_t* bytes)
+{
+    if (!cfg || !solid || !bytes) return fail(nullptr, LB_EINVAL, "null argument");
+    std::string msg = validate(*cfg, n_rbc);
+    Geometry g;
+    if (msg.empty()) msg = build_geometry(*cfg, solid, n_rbc, g);
+    if (!msg.empty()) return fail(nullptr, LB_EINVAL, msg);
+    *bytes = layout(*cfg, g, n_rbc).total;
+    return LB_OK;
+}
+
+lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cells, int n_rbc,
+                  void* arena, size_t arena_bytes, void* hip_stream, lb_ctx* out)
+{
+    if (!cfg || !solid || !out || (n_rbc > 0 && !cells) || !arena) return LB_EINVAL;
+    *out = nullptr;
+    lb_ctx c = new lb_ctx_s();
+    c->cfg = *cfg;
+    if (c->cfg.map_cap == 0) c->cfg.map_cap = CAP_MAX;
+    std::string msg = validate(c->cfg, n_rbc);
+    if (msg.empty()) msg = build_geometry(c->cfg, solid, n_rbc, c->geo);
+    if (!msg.empty()) return init_fail(c, LB_EINVAL, msg);
+    if ((reinterpret_cast<uintptr_t>(arena) % ALIGN) != 0)
+        return init_fail(c, LB_EINVAL, "arena must be 256-byte aligned");
+    c->lay = layout(c->cfg, c->geo, n_rbc);
+    if (arena_bytes < c->lay.total) return init_fail(c, LB_ENOMEM, "arena smaller than the footprint");
+    c->stream = (hipStream_t)hip_stream;
+    c->base = (char*)arena;
+    c->nrbc = n_rbc;
+    const lb_config& C = c->cfg;
+    const Geometry& g = c->geo;
+    KParams& kp = c->kp;
+    std::memset(&kp, 0, sizeof kp);
+    kp.nx = C.nx; kp.ny = C.ny; kp.nz = C.nz;
+    for (int a = 0; a < 3; ++a) kp.per[a] = C.periodic[a] ? 1 : 0;
+    kp.N = g.N;
+    kp.ld = g.ld;
+    kp.forcing = C.forcing;
+    kp.cap = C.map_cap;
+    kp.tau0 = C.tau0; kp.delta = C.delta_visc; kp.kappa = C.kappa;
+    kp.kappa_int = (C.kappa == std::floor(C.kappa) && C.kappa >= 0 && C.kappa <= 64) ? (int)C.kappa : -1;
+    for (int a = 0; a < 3; ++a) {
+        kp.gext[a] = C.g_ext[a];
+        kp.inertia[a] = C.inertia[a];
+        kp.xi[a] = C.xi[a];
+        kp.axes[a] = C.axes[a];
+        kp.ncell[a] = g.ncell[a];
+        kp.cedge[a] = g.cedge[a];
+    }
+    kp.gammaT = C.gammaT; kp.gammaR = C.gammaR; kp.alpha = C.alpha; kp.mass = C.mass;
+    kp.vort_scale = C.vort_scale;
+    kp.eps0 = C.eps0; kp.a_wall = C.a_wall; kp.sigmin_wall = C.sigmin_wall;
+    kp.wall_particles = C.wall_particles;
+    kp.open_z = C.open_z; kp.rho_in = C.rho_in; kp.rho_out = C.rho_out;
+    kp.f16_scale = C.storage == LB_F16 ? (float)C.f16_scale : 1.0f;
+    kp.f16_inv = 1.0f / kp.f16_scale;
+    kp.nrbc = n_rbc;
+    kp.rc = g.rc;
+    kp.tile_max = g.tile_max;
+
+    const Layout& L = c->lay;
+    c->fA = c->at<void>(L.fA);
+    c->fB = c->at<void>(L.fB);
+    CellBuffers& b = c->cb;
+    b.st = c->at<RbcState>(L.st);
+    b.cp = c->at<RbcCouple>(L.cp);
+    b.gat = c->at<void>(L.gat);
+    b.cellid = c->at<int>(L.cellid);
+    b.cell_cnt = c->at<int>(L.cell_cnt);
+    b.cell_off = c->at<int>(L.cell_off);
+    b.cell_ids = c->at<int>(L.cell_ids);
+    b.wall_xyz = c->at<int>(L.wall_xyz);
+    b.wcell_off = c->at<int>(L.wcell_off);
+    b.wcell_ids = c->at<int>(L.wcell_ids);
+    b.nodeword = c->at<uint32_t>(L.nodeword);
+    b.map_ids = c->at<int>(L.map_ids);
+    b.u = c->at<void>(L.u);
+    b.sig = c->at<void>(L.sig);
+    b.err = c->at<unsigned>(L.err);
+
+    hipStream_t s = c->stream;
+    auto h2d = [&](size_t off, const void* src, size_t bytes) {
+        return bytes ? hipMemcpyAsync(c->base + off, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
+    };
+    // rest state: shifted populations zero, fields zero
+    hipError_t e = hipMemsetAsync(c->base, 0, L.total, s);
+    if (e != hipSuccess) return init_fail(c, LB_EHIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
+    std::vector<uint32_t> nw(g.ld, 0u);
+    std::copy(g.nodeword.begin(), g.nodeword.end(), nw.begin());
+    e = e ? e : h2d(L.nodeword, nw.data(), nw.size() * 4);
+    e = e ? e : h2d(L.wall_xyz, g.wall_xyz.data(), g.wall_xyz.size() * 4);
+    e = e ? e : h2d(L.wcell_off, g.wcell_off.data(), g.wcell_off.size() * 4);
+    e = e ? e : h2d(L.wcell_ids, g.wcell_ids.data(), g.wcell_ids.size() * 4);
+    e = e ? e : h2d(L.wn_node, g.wn_node.data(), g.wn_node.size() * 8);
+    e = e ? e : h2d(L.wn_nrm, g.wn_nrm.data(), g.wn_nrm.size() * 8);
+    e = e ? e : h2d(L.planes, g.planes.data(), g.planes.size() * 8);
+    std::vector<RbcState> hs(n_rbc);
+    for (int i = 0; i < n_rbc; ++i) {
+        RbcState& r = hs[i];
+        std::memset(&r, 0, sizeof r);
+        for (int a = 0; a < 3; ++a) {
+            double v = cells[i].R[a];
+            if (C.periodic[a]) {
+                const double Lh = a == 0 ? C.nx : (a == 1 ? C.ny : C.nz);
+                if (v >= Lh) v -= Lh;
+                else if (v < 0.0) v += Lh;
+            }
+            r.R[a] = v;
+            r.V[a] = cells[i].V[a];
+            r.Om[a] = cells[i].Omega[a];
+        }
+        for (int a = 0; a < 9; ++a) r.Q[a] = cells[i].Q[a];
+    }
+    e = e ? e : h2d(L.st, hs.data(), hs.size() * sizeof(RbcState));
+    if (e != hipSuccess) return init_fail(c, LB_EHIP, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+    if (n_rbc > 0) {
+        // start-up: F^comb(0) = F^mech(0), tau^comb(0) = tau^mech(0) (fluid at rest)
+        launch_cell_list(b, kp, s);
+        launch_gay_berne(b, kp, s);
+        launch_init_combined(b, kp, s);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return init_fail(c, LB_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return init_fail(c, LB_EHIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+    unsigned err = 0;
+    e = hipMemcpy(&err, b.err, 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return init_fail(c, LB_EHIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+    if (err & ERR_OVERLAP) return init_fail(c, LB_EOVERLAP, "Gay-Berne pair at rho <= 0 in the initial state");
+    *out = c;
+    return LB_OK;
+}
+
+lb_status lb_step(lb_ctx c, int nsteps)
+{
+    if (!c || nsteps < 0) return LB_EINVAL;
+    if (c->poisoned) return fail(c, LB_ESTATE, "context poisoned by a device fault");
+    if (c->timing && !c->step_t0_set && nsteps > 0) {
+        (void)hipEventRecord(c->step_t0, c->stream);
+        c->step_t0_set = true;
+    }
+    for (int k = 0; k < nsteps; ++k) enqueue_step(c);
+    if (c->timing && nsteps > 0) {
+        (void)hipEventRecord(c->step_t1, c->stream);
+        c->timed_steps += nsteps;
+    }
+    HIPCHK(c, hipGetLastError());
+    return LB_OK;
+}
+
+lb_status lb_batch_step(lb_ctx* ctxs, const int* nsteps, int n)
+{
+    if (!ctxs || !nsteps || n < 0) return LB_EINVAL;
+    int most = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i] || nsteps[i] < 0) return LB_EINVAL;
+        if (ctxs[i]->poisoned) return LB_ESTATE;
+        most = std::max(most, nsteps[i]);
+    }
+    for (int k = 0; k < most; ++k)
+        for (int i = 0; i < n; ++i)
+            if (k < nsteps[i]) enqueue_step(ctxs[i]);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? LB_OK : LB_EHIP;
+}
+
+lb_status rbc_couple(lb_ctx c)
+{
+    if (!c) return LB_EINVAL;
+    if (c->nrbc > 0) {
+        enqueue_cells_and_map(c);
+        with_types(c->cfg.storage, [&](auto*, auto* rp) {
+            using RT = std::remove_pointer_t<decltype(rp)>;
+            launch_couple<RT>(c->cb, c->kp, c->stream);
+            launch_rb_second_half<RT>(c->cb, c->kp, 0, c->stream);
+        });
+    }
+    with_types(c->cfg.storage, [&](auto*, auto* rp) {
+        using RT = std::remove_pointer_t<decltype(rp)>;
+        launch_spread_field<RT>(c->cb.nodeword, c->cb.map_ids, c->cb.gat, c->at<void>(c->lay.gdbg),
+                                c->at<void>(c->lay.tdbg), c->kp, c->stream);
+    });
+    HIPCHK(c, hipGetLastError());
+    return LB_OK;
+}
+
+lb_status rbc_collide(lb_ctx c, double* F, double* T)
+{
+    if (!c) return LB_EINVAL;
+    if (c->nrbc == 0) return LB_OK;
+    launch_cell_list(c->cb, c->kp, c->stream);
+    launch_gay_berne(c->cb, c->kp, c->stream);
+    lb_status st = check_fault(c);
+    std::vector<RbcCouple> cp(c->nrbc);
+    HIPCHK(c, hipMemcpy(cp.data(), c->cb.cp, cp.size() * sizeof(RbcCouple), hipMemcpyDeviceToHost));
+    for (int i = 0; i < c->nrbc; ++i)
+        for (int a = 0; a < 3; ++a) {
+            if (F) F[3 * i + a] = cp[i].Fm[a];
+            if (T) T[3 * i + a] = cp[i].Tm[a];
+        }
+    return st;
+}
+
+lb_status lb_sync(lb_ctx c)
+{
+    if (!c) return LB_EINVAL;
+    return check_fault(c);
+}
+
+lb_status lb_observe(lb_ctx c, lb_observables* o)
+{
+    if (!c || !o) return LB_EINVAL;
+    std::memset(o, 0, sizeof *o);
+    with_types(c->cfg.storage, [&](auto* sp, auto* rp) {
+        using ST = std::remove_pointer_t<decltype(sp)>;
+        using RT = std::remove_pointer_t<decltype(rp)>;
+        launch_observe<ST, RT>(c->fA, c->cb.nodeword, c->at<void>(c->lay.u), c->kp,
+                               c->at<double>(c->lay.partials), OBS_BLOCKS, c->at<double>(c->lay.obs_out),
+                               c->stream);
+        launch_wss<RT>(c->at<void>(c->lay.sig), c->at<long long>(c->lay.wn_node),
+                       c->at<double>(c->lay.wn_nrm), (int)c->geo.wn_node.size(), c->kp,
+                       c->at<double>(c->lay.wss), nullptr, 0, c->stream);
+    });
+    lb_status st = check_fault(c);
+    double r[6];
+    HIPCHK(c, hipMemcpy(r, c->at<double>(c->lay.obs_out), sizeof r, hipMemcpyDeviceToHost));
+    const size_t nwn = c->geo.wn_node.size();
+    std::vector<double> w(nwn), acc(nwn);
+    if (nwn) {
+        HIPCHK(c, hipMemcpy(w.data(), c->at<double>(c->lay.wss), nwn * 8, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(acc.data(), c->at<double>(c->lay.wss_acc), nwn * 8, hipMemcpyDeviceToHost));
+    }
+    o->mass = r[0];
+    o->momentum[0] = r[1];
+    o->momentum[1] = r[2];
+    o->momentum[2] = r[3];
+    o->flow_rate = r[4] / c->cfg.nz;
+    const double area = (double)c->geo.n_fluid / c->cfg.nz;
+    const double Rt = std::sqrt(area / M_PI);
+    o->eta_app = o->flow_rate != 0.0 ? M_PI * std::pow(Rt, 4.0) * c->cfg.g_ext[2] / (8.0 * o->flow_rate) : 0.0;
+    double sum = 0, mx = 0, asum = 0;
+    for (size_t k = 0; k < nwn; ++k) {
+        sum += w[k];
+        mx = std::max(mx, w[k]);
+        asum += acc[k];
+    }
+    o->wss_mean = nwn ? sum / nwn : 0.0;
+    o->wss_max = mx;
+    o->wss_time_mean = (nwn && c->wss_count) ? asum / (double)nwn / (double)c->wss_count : 0.0;
+    o->step = c->step;
+    o->flags = c->fault;
+    o->n_fluid = c->geo.n_fluid;
+    o->n_wall_nodes = (int)nwn;
+    o->n_rbc = c->nrbc;
+    return st;
+}
+
+lb_status lb_wall_shear_stress(lb_ctx c, int time, double* wss, long long* node, int* n)
+{
+    if (!c || !n) return LB_EINVAL;
+    const int nwn = (int)c->geo.wn_node.size();
+    *n = nwn;
+    if (node)
+        for (int k = 0; k < nwn; ++k) node[k] = c->geo.wn_node[k];
+    if (!wss) return LB_OK;
+    if (time) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        std::vector<double> acc(nwn);
+        if (nwn) HIPCHK(c, hipMemcpy(acc.data(), c->at<double>(c->lay.wss_acc), nwn * 8, hipMemcpyDeviceToHost));
+        for (int k = 0; k < nwn; ++k) wss[k] = c->wss_count ? acc[k] / (double)c->wss_count : 0.0;
+        return check_fault(c);
+    }
+    with_types(c->cfg.storage, [&](auto*, auto* rp) {
+        using RT = std::remove_pointer_t<decltype(rp)>;
+        launch_wss<RT>(c->at<void>(c->lay.sig), c->at<long long>(c->lay.wn_node),
+                       c->at<double>(c->lay.wn_nrm), nwn, c->kp, c->at<double>(c->lay.wss), nullptr, 0,
+                       c->stream);
+    });
+    lb_status st = check_fault(c);
+    if (nwn) HIPCHK(c, hipMemcpy(wss, c->at<double>(c->lay.wss), nwn * 8, hipMemcpyDeviceToHost));
+    return st;
+}
+
+lb_status lb_apparent_viscosity(lb_ctx c, double* eta)
+{
+    if (!c || !eta) return LB_EINVAL;
+    lb_observables o;
+    lb_status st = lb_observe(c, &o);
+    *eta = o.eta_app;
+    return st;
+}
+
+lb_status lb_wss_accumulate(lb_ctx c, int on)
+{
+    if (!c) return LB_EINVAL;
+    if (on) {
+        const size_t nwn = c->geo.wn_node.size();
+        if (nwn) HIPCHK(c, hipMemsetAsync(c->at<double>(c->lay.wss_acc), 0, nwn * 8, c->stream));
+        c->wss_count = 0;
+    }
+    c->wss_on = on ? 1 : 0;
+    return LB_OK;
+}
+
+lb_status lb_get_fields(lb_ctx c, double* f, double* u, double* sigma, double* g, double* relax)
+{
+    if (!c) return LB_EINVAL;
+    lb_status st = check_fault(c);
+    const int S = c->cfg.storage;
+    const size_t N = (size_t)c->kp.N, ld = (size_t)c->kp.ld;
+    const size_t rs = real_bytes(S);
+    if (f) {
+        std::vector<char> h(19 * ld * storage_bytes(S));
+        HIPCHK(c, hipMemcpy(h.data(), c->fA, h.size(), hipMemcpyDeviceToHost));
+        const double inv = S == LB_F16 ? 1.0 / c->cfg.f16_scale : 1.0;
+        for (int p = 0; p < 19; ++p)
+            for (size_t n = 0; n < N; ++n) f[p * N + n] = w_(p) + load_stored(h.data(), p * ld + n, S, inv);
+    }
+    auto planes = [&](size_t off, int k, double* out) -> lb_status {
+        std::vector<char> h(k * ld * rs);
+        HIPCHK(c, hipMemcpy(h.data(), c->base + off, h.size(), hipMemcpyDeviceToHost));
+        for (int a = 0; a < k; ++a)
+            for (size_t n = 0; n < N; ++n) out[n * k + a] = load_real(h.data(), a * ld + n, S);
+        return LB_OK;
+    };
+    lb_status r;
+    if (u && (r = planes(c->lay.u, 3, u)) != LB_OK) return r;
+    if (sigma && (r = planes(c->lay.sig, 6, sigma)) != LB_OK) return r;
+    if (g && (r = planes(c->lay.gdbg, 3, g)) != LB_OK) return r;
+    if (relax && (r = planes(c->lay.tdbg, 1, relax)) != LB_OK) return r;
+    return st;
+}
+
+lb_status lb_set_fields(lb_ctx c, const double* f, const double* u, const double* sigma)
+{
+    if (!c) return LB_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int S = c->cfg.storage;
+    const size_t N = (size_t)c->kp.N, ld = (size_t)c->kp.ld;
+    const size_t rs = real_bytes(S);
+    if (f) {
+        std::vector<char> h(19 * ld * storage_bytes(S), 0);
+        const double scale = S == LB_F16 ? c->cfg.f16_scale : 1.0;
+        for (int p = 0; p < 19; ++p)
+            for (size_t n = 0; n < N; ++n) store_value(h.data(), p * ld + n, S, f[p * N + n] - w_(p), scale);
+        HIPCHK(c, hipMemcpy(c->fA, h.data(), h.size(), hipMemcpyHostToDevice));
+    }
+    auto planes = [&](size_t off, int k, const double* in) -> lb_status {
+        std::vector<char> h(k * ld * rs, 0);
+        for (int a = 0; a < k; ++a)
+            for (size_t n = 0; n < N; ++n) store_real(h.data(), a * ld + n, S, in[n * k + a]);
+        HIPCHK(c, hipMemcpy(c->base + off, h.data(), h.size(), hipMemcpyHostToDevice));
+        return LB_OK;
+    };
+    lb_status r;
+    if (u && (r = planes(c->lay.u, 3, u)) != LB_OK) return r;
+    if (sigma && (r = planes(c->lay.sig, 6, sigma)) != LB_OK) return r;
+    HIPCHK(c, hipMemset(c->cb.err, 0, 4));
+    c->poisoned = false;
+    c->fault = 0;
+    return LB_OK;
+}
+
+lb_status rbc_get_state(lb_ctx c, lb_rbc* out, int n)
+{
+    if (!c || (n > 0 && !out) || n > c->nrbc) return LB_EINVAL;
+    lb_status st = check_fault(c);
+    std::vector<RbcState> h(n);
+    if (n) HIPCHK(c, hipMemcpy(h.data(), c->cb.st, n * sizeof(RbcState), hipMemcpyDeviceToHost));
+    for (int i = 0; i < n; ++i) {
+        for (int a = 0; a < 3; ++a) {
+            out[i].R[a] = h[i].R[a];
+            out[i].V[a] = h[i].V[a];
+            out[i].Omega[a] = h[i].Om[a];
+        }
+        for (int a = 0; a < 9; ++a) out[i].Q[a] = h[i].Q[a];
+    }
+    return st;
+}
+
+lb_status rbc_set_state(lb_ctx c, const lb_rbc* in, int n)
+{
+    if (!c || n != c->nrbc || (n > 0 && !in)) return LB_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<RbcState> h(n);
+    if (n) HIPCHK(c, hipMemcpy(h.data(), c->cb.st, n * sizeof(RbcState), hipMemcpyDeviceToHost));
+    for (int i = 0; i < n; ++i) {
+        for (int a = 0; a < 3; ++a) {
+            h[i].R[a] = in[i].R[a];
+            h[i].V[a] = in[i].V[a];
+            h[i].Om[a] = in[i].Omega[a];
+        }
+        for (int a = 0; a < 9; ++a) h[i].Q[a] = in[i].Q[a];
+    }
+    if (n) HIPCHK(c, hipMemcpy(c->cb.st, h.data(), n * sizeof(RbcState), hipMemcpyHostToDevice));
+    return LB_OK;
+}
+
+lb_status rbc_get_coupling(lb_ctx c, double* o, int n)
+{
+    if (!c || (n > 0 && !o) || n > c->nrbc) return LB_EINVAL;
+    lb_status st = check_fault(c);
+    std::vector<RbcState> hs(n);
+    std::vector<RbcCouple> hc(n);
+    if (n) {
+        HIPCHK(c, hipMemcpy(hs.data(), c->cb.st, n * sizeof(RbcState), hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(hc.data(), c->cb.cp, n * sizeof(RbcCouple), hipMemcpyDeviceToHost));
+    }
+    for (int i = 0; i < n; ++i) {
+        double* r = o + 22 * i;
+        r[0] = hc[i].S;
+        for (int a = 0; a < 3; ++a) {
+            r[1 + a] = hc[i].ut[a];
+            r[4 + a] = hc[i].wt[a];
+            r[7 + a] = hc[i].TS[a];
+            r[10 + a] = hc[i].Fh[a];
+            r[13 + a] = hc[i].Th[a];
+            r[16 + a] = hs[i].Fc[a];
+            r[19 + a] = hs[i].Tc[a];
+        }
+    }
+    return st;
+}
+
+lb_status rbc_get_cells(lb_ctx c, int* ncell, int* off, int* ids)
+{
+    if (!c) return LB_EINVAL;
+    lb_status st = check_fault(c);
+    const int nc = c->kp.ncell[0] * c->kp.ncell[1] * c->kp.ncell[2];
+    if (ncell)
+        for (int a = 0; a < 3; ++a) ncell[a] = c->kp.ncell[a];
+    if (off) HIPCHK(c, hipMemcpy(off, c->cb.cell_off, (nc + 1) * 4, hipMemcpyDeviceToHost));
+    if (ids && c->nrbc) HIPCHK(c, hipMemcpy(ids, c->cb.cell_ids, c->nrbc * 4, hipMemcpyDeviceToHost));
+    return st;
+}
+
+lb_status rbc_get_map(lb_ctx c, int* off, int* ids, long long* len)
+{
+    if (!c || !len) return LB_EINVAL;
+    lb_status st = check_fault(c);
+    const size_t N = (size_t)c->kp.N, ld = (size_t)c->kp.ld;
+    std::vector<uint32_t> nw(N);
+    HIPCHK(c, hipMemcpy(nw.data(), c->cb.nodeword, N * 4, hipMemcpyDeviceToHost));
+    long long tot = 0;
+    for (size_t n = 0; n < N; ++n) tot += std::min<int>(nw[n] >> 24, c->kp.cap);
+    if (!ids) {
+        *len = tot;
+        if (off) {
+            off[0] = 0;
+            for (size_t n = 0; n < N; ++n) off[n + 1] = off[n] + std::min<int>(nw[n] >> 24, c->kp.cap);
+        }
+        return st;
+    }
+    if (*len < tot) return LB_EINVAL;
+    std::vector<int> slots;
+    if (c->nrbc) {
+        slots.resize((size_t)c->kp.cap * ld);
+        HIPCHK(c, hipMemcpy(slots.data(), c->cb.map_ids, slots.size() * 4, hipMemcpyDeviceToHost));
+    }
+    long long k = 0;
+    if (off) off[0] = 0;
+    for (size_t n = 0; n < N; ++n) {
+        const int cnt = std::min<int>(nw[n] >> 24, c->kp.cap);
+        const long long b = k;
+        for (int s = 0; s < cnt; ++s) ids[k++] = slots[(size_t)s * ld + n];
+        std::sort(ids + b, ids + k);
+        if (off) off[n + 1] = (int)k;
+    }
+    *len = tot;
+    return st;
+}
+
+// checkpoint: header, populations (storage precision), u, sigma, cell states, WSS sums
+struct CkptHeader {
+    char magic[8];
+    int version, storage, nrbc, nwn;
+    long long N, step, wss_count;
+    int wss_on, pad;
+};
+
+lb_status lb_save(lb_ctx c, void* buf, size_t* bytes)
+{
+    if (!c || !bytes) return LB_EINVAL;
+    const size_t ld = (size_t)c->kp.ld;
+    const size_t fb = 19 * ld * storage_bytes(c->cfg.storage), rb = 9 * ld * real_bytes(c->cfg.storage);
+    const size_t sb = c->nrbc * sizeof(RbcState), wb = c->geo.wn_node.size() * 8;
+    const size_t need = sizeof(CkptHeader) + fb + rb + sb + wb;
+    if (!buf) {
+        *bytes = need;
+        return LB_OK;
+    }
+    if (*bytes < need) return LB_EINVAL;
+    lb_status st = check_fault(c);
+    CkptHeader h{};
+    std::memcpy(h.magic, "LBRBCCK1", 8);
+    h.version = 1;
+    h.storage = c->cfg.storage;
+    h.nrbc = c->nrbc;
+    h.nwn = (int)c->geo.wn_node.size();
+    h.N = c->kp.N;
+    h.step = c->step;
+    h.wss_count = c->wss_count;
+    h.wss_on = c->wss_on;
+    char* p = (char*)buf;
+    std::memcpy(p, &h, sizeof h);
+    p += sizeof h;
+    HIPCHK(c, hipMemcpy(p, c->fA, fb, hipMemcpyDeviceToHost));
+    p += fb;
+    HIPCHK(c, hipMemcpy(p, c->base + c->lay.u, 3 * ld * real_bytes(c->cfg.storage), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(p + 3 * ld * real_bytes(c->cfg.storage), c->base + c->lay.sig,
+                        6 * ld * real_bytes(c->cfg.storage), hipMemcpyDeviceToHost));
+    p += rb;
+    if (sb) HIPCHK(c, hipMemcpy(p, c->cb.st, sb, hipMemcpyDeviceToHost));
+    p += sb;
+    if (wb) HIPCHK(c, hipMemcpy(p, c->at<double>(c->lay.wss_acc), wb, hipMemcpyDeviceToHost));
+    *bytes = need;
+    return st;
+}
+
+lb_status lb_load(lb_ctx c, const void* buf, size_t bytes)
+{
+    if (!c || !buf || bytes < sizeof(CkptHeader)) return LB_EINVAL;
+    CkptHeader h;
+    std::memcpy(&h, buf, sizeof h);
+    const size_t ld = (size_t)c->kp.ld;
+    const size_t fb = 19 * ld * storage_bytes(c->cfg.storage), rb = 9 * ld * real_bytes(c->cfg.storage);
+    const size_t sb = c->nrbc * sizeof(RbcState), wb = c->geo.wn_node.size() * 8;
+    if (std::memcmp(h.magic, "LBRBCCK1", 8) != 0 || h.storage != c->cfg.storage || h.nrbc != c->nrbc ||
+        h.N != c->kp.N || h.nwn != (int)c->geo.wn_node.size() ||
+        bytes < sizeof h + fb + rb + sb + wb)
+        return fail(c, LB_EINVAL, "checkpoint does not match this context");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const char* p = (const char*)buf + sizeof h;
+    HIPCHK(c, hipMemcpy(c->fA, p, fb, hipMemcpyHostToDevice));
+    p += fb;
+    HIPCHK(c, hipMemcpy(c->base + c->lay.u, p, 3 * ld * real_bytes(c->cfg.storage), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->base + c->lay.sig, p + 3 * ld * real_bytes(c->cfg.storage),
+                        6 * ld * real_bytes(c->cfg.storage), hipMemcpyHostToDevice));
+    p += rb;
+    if (sb) HIPCHK(c, hipMemcpy(c->cb.st, p, sb, hipMemcpyHostToDevice));
+    p += sb;
+    if (wb) HIPCHK(c, hipMemcpy(c->at<double>(c->lay.wss_acc), p, wb, hipMemcpyHostToDevice));
+    c->step = h.step;
+    c->wss_count = h.wss_count;
+    c->wss_on = h.wss_on;
+    HIPCHK(c, hipMemset(c->cb.err, 0, 4));
+    c->poisoned = false;
+    c->fault = 0;
+    return LB_OK;
+}
+
+const char* lb_last_error(lb_ctx c) { return c ? c->last_error.c_str() : g_init_error.c_str(); }
+
+lb_status lb_set_timing(lb_ctx c, int on)
+{
+    if (!c) return LB_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (auto& pr : c->sc_pairs) {
+        c->ev_pool.push_back(pr.first);
+        c->ev_pool.push_back(pr.second);
+    }
+    c->sc_pairs.clear();
+    c->timed_steps = 0;
+    c->step_t0_set = false;
+    if (on && c->ev_pool.empty()) {
+        for (int k = 0; k < 2 * MAX_TIMED; ++k) {
+            hipEvent_t e;
+            HIPCHK(c, hipEventCreate(&e));
+            c->ev_pool.push_back(e);
+        }
+        HIPCHK(c, hipEventCreate(&c->step_t0));
+        HIPCHK(c, hipEventCreate(&c->step_t1));
+    }
+    c->timing = on != 0;
+    return LB_OK;
+}
+
+lb_status lb_kernel_time(lb_ctx c, double* sc_ms, double* step_ms)
+{
+    if (!c) return LB_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double tot = 0;
+    for (auto& pr : c->sc_pairs) {
+        float ms = 0;
+        HIPCHK(c, hipEventElapsedTime(&ms, pr.first, pr.second));
+        tot += ms;
+    }
+    if (sc_ms) *sc_ms = c->sc_pairs.empty() ? 0.0 : tot / c->sc_pairs.size();
+    if (step_ms) {
+        float ms = 0;
+        if (c->timed_steps > 0 && c->step_t0_set) HIPCHK(c, hipEventElapsedTime(&ms, c->step_t0, c->step_t1));
+        *step_ms = c->timed_steps > 0 ? ms / c->timed_steps : 0.0;
+    }
+    return LB_OK;
+}
+
+void lb_destroy(lb_ctx c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& pr : c->sc_pairs) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->step_t0) (void)hipEventDestroy(c->step_t0);
+    if (c->step_t1) (void)hipEventDestroy(c->step_t1);
+    delete c;
+}
+
+}  // extern "C"

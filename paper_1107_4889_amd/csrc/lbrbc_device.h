@@ -1,0 +1,183 @@
+// lbrbc_device.h -- device-side types and helpers of the MI355X library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbrbc {
+
+// ---- D3Q19 (Sec. II A) -------------------------------------------------------------------
+// 0 rest; 1-6 axis speeds; 7-18 face diagonals; opposite speeds adjacent.
+__host__ __device__ constexpr int cx_(int p)
+{
+    constexpr int t[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    return t[p];
+}
+__host__ __device__ constexpr int cy_(int p)
+{
+    constexpr int t[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    return t[p];
+}
+__host__ __device__ constexpr int cz_(int p)
+{
+    constexpr int t[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    return t[p];
+}
+__host__ __device__ constexpr int opp_(int p) { return p == 0 ? 0 : ((p & 1) ? p + 1 : p - 1); }
+__host__ __device__ constexpr double w_(int p)
+{
+    return p == 0 ? 1.0 / 3.0 : (p < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+// ---- node word ---------------------------------------------------------------------------
+// bits 0-18: bit p set <=> the pull source x - c_p is solid or outside a wall face
+// bit 19: fluid node; bit 20: has an in-box solid neighbour (wall-adjacent);
+// bit 21: open-boundary plane node; bits 24-31: number of covering cells this step.
+constexpr uint32_t NW_FLUID = 1u << 19;
+constexpr uint32_t NW_WALLADJ = 1u << 20;
+constexpr uint32_t NW_OPEN = 1u << 21;
+constexpr uint32_t NW_CNT_ONE = 1u << 24;
+constexpr uint32_t NW_STATIC = 0x00FFFFFFu;
+constexpr int CAP_MAX = 12;
+
+// device fault bits
+constexpr unsigned ERR_UNSTABLE = 1u, ERR_OVERLAP = 2u, ERR_CAPACITY = 4u;
+
+// ---- parameters (kernel argument, by value) ----------------------------------------------
+struct KParams {
+    int nx, ny, nz;
+    int per[3];
+    long long N;      // nodes
+    long long ld;     // plane stride (N rounded up)
+    int forcing;
+    int cap;
+    double tau0, delta, kappa;
+    int kappa_int;    // kappa if it is an integer in [0, 64], else -1
+    double gext[3];
+    double gammaT, gammaR, alpha, mass, inertia[3], vort_scale;
+    double xi[3], axes[3], eps0, a_wall, sigmin_wall;
+    int wall_particles;
+    int open_z;
+    double rho_in, rho_out;
+    float f16_scale, f16_inv;
+    int nrbc;
+    int ncell[3];
+    double cedge[3];
+    double rc;
+    int tile_max;     // LDS tile edge bound
+};
+
+// ---- per-cell records ---------------------------------------------------------------------
+struct RbcState {        // FP64, lab frame except Om (body) and Tc (body)
+    double R[3], Q[9], V[3], Om[3];
+    double Fc[3], Tc[3];     // combined force (lab) / torque (body)
+    double Vh[3], Omh[3];    // after the first half
+};
+struct RbcCouple {       // interpolation results and forces
+    double S, ut[3], wt[3], TS[3];
+    double Fm[3], Tm[3];     // Gay-Berne force (lab), torque (body)
+    double Fh[3], Th[3];     // hydrodynamic force / torque (lab)
+};
+// Gather record read by the per-node spreading: centre in FP64, the rest in the compute
+// precision. 96 B (float) / 160 B (double).
+template <typename RT>
+struct alignas(16) Gather {
+    double R[3];
+    RT Q[9];
+    RT invS;
+    RT F[3];
+    RT T[3];
+    RT pad;
+};
+
+// ---- storage conversions ------------------------------------------------------------------
+struct bf16_t { uint16_t v; };
+
+template <typename ST, typename RT>
+struct Store;
+template <>
+struct Store<double, double> {
+    __device__ static double ld(const double* p, long long i, float) { return p[i]; }
+    __device__ static void st(double* p, long long i, double v, float) { __builtin_nontemporal_store(v, p + i); }
+};
+template <>
+struct Store<float, float> {
+    __device__ static float ld(const float* p, long long i, float) { return p[i]; }
+    __device__ static void st(float* p, long long i, float v, float) { __builtin_nontemporal_store(v, p + i); }
+};
+template <>
+struct Store<bf16_t, float> {
+    __device__ static float ld(const bf16_t* p, long long i, float)
+    {
+        uint32_t u = (uint32_t)reinterpret_cast<const uint16_t*>(p)[i] << 16;
+        return __uint_as_float(u);
+    }
+    __device__ static void st(bf16_t* p, long long i, float v, float)
+    {
+        // round to nearest even on the upper 16 bits
+        uint32_t u = __float_as_uint(v);
+        uint16_t r;
+        if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) r = 0x7fc0;
+        else r = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+        __builtin_nontemporal_store(r, reinterpret_cast<uint16_t*>(p) + i);
+    }
+};
+template <>
+struct Store<_Float16, float> {
+    __device__ static float ld(const _Float16* p, long long i, float inv) { return (float)p[i] * inv; }
+    __device__ static void st(_Float16* p, long long i, float v, float scale)
+    {
+        __builtin_nontemporal_store((_Float16)(v * scale), p + i);
+    }
+};
+
+// ---- Peskin four-point kernel at r = 2|y|/xi (the normalised 1-D profile) ----------------
+template <typename RT>
+__device__ __forceinline__ RT peskin(RT r)
+{
+    r = fabs(r);
+    if (r <= RT(1)) return (RT(3) - RT(2) * r + sqrt(RT(1) + RT(4) * r - RT(4) * r * r)) * RT(0.125);
+    if (r < RT(2)) return (RT(5) - RT(2) * r - sqrt(RT(-7) + RT(12) * r - RT(4) * r * r)) * RT(0.125);
+    return RT(0);
+}
+
+__device__ __forceinline__ double min_img(double d, double L, int per)
+{
+    if (per) {
+        if (d > 0.5 * L) d -= L;
+        else if (d < -0.5 * L) d += L;
+    }
+    return d;
+}
+
+// body coordinates y = Q^T d, each component summed left to right with no contraction, so
+// that the support test |y_a| < xi_a is reproducible bit for bit
+__device__ __forceinline__ void body_coords_exact(const double* Q, double d0, double d1, double d2,
+                                                  double y[3])
+{
+#pragma clang fp contract(off)
+    for (int a = 0; a < 3; ++a) {
+        double t0 = Q[0 * 3 + a] * d0;
+        double t1 = Q[1 * 3 + a] * d1;
+        double t2 = Q[2 * 3 + a] * d2;
+        y[a] = (t0 + t1) + t2;
+    }
+}
+
+template <typename RT>
+__device__ __forceinline__ RT ipow_or_pow(RT b, double kappa, int kint)
+{
+    if (kint >= 0) {
+        RT r = RT(1), x = b;
+        int k = kint;
+        while (k) {
+            if (k & 1) r *= x;
+            x *= x;
+            k >>= 1;
+        }
+        return r;
+    }
+    return pow(b, (RT)kappa);
+}
+
+}  // namespace lbrbc

@@ -1,0 +1,629 @@
+// rbc_kernels.hip -- per-cell kernels (gfx950): rigid-body halves, cell list, node->cell
+// coverage map, interpolation onto the cells, Gay-Berne forces.
+#include <climits>
+
+#include "lbrbc_device.h"
+#include "lbrbc_internal.h"
+
+namespace lbrbc {
+
+__device__ __forceinline__ void mat_vec(const double* M, const double* v, double* o)
+{
+    for (int r = 0; r < 3; ++r) o[r] = M[3 * r] * v[0] + M[3 * r + 1] * v[1] + M[3 * r + 2] * v[2];
+}
+__device__ __forceinline__ void matT_vec(const double* M, const double* v, double* o)
+{
+    for (int c = 0; c < 3; ++c) o[c] = M[c] * v[0] + M[3 + c] * v[1] + M[6 + c] * v[2];
+}
+__device__ __forceinline__ void cross3(const double* a, const double* b, double* o)
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+__device__ __forceinline__ double box_len(const KParams& kp, int a)
+{
+    return a == 0 ? (double)kp.nx : (a == 1 ? (double)kp.ny : (double)kp.nz);
+}
+
+// ---- S1: rigid-body first half (App. A, steps 1-4) ------------------------------------------
+// half kick, half-step friction, drift (wrapped on periodic axes), five free sub-rotations
+// n/2, t/2, g, t/2, n/2 about the body axes: Rot = Rot_k(-f h Omega_k), pi <- Rot pi,
+// Q <- Q Rot^T (Q' = Q hat(Omega)).
+__global__ __launch_bounds__(128) void k_rb_first_half(RbcState* __restrict__ st, KParams kp)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kp.nrbc) return;
+    RbcState s = st[i];
+    const double eT = exp(-kp.gammaT * 0.5), eR = exp(-kp.gammaR * 0.5);
+    for (int a = 0; a < 3; ++a) {
+        s.V[a] += 0.5 / kp.mass * s.Fc[a];
+        s.Om[a] += 0.5 * s.Tc[a] / kp.inertia[a];
+    }
+    for (int a = 0; a < 3; ++a) {
+        s.V[a] *= eT;
+        s.Om[a] *= eR;
+    }
+    for (int a = 0; a < 3; ++a) {
+        s.R[a] += s.V[a];
+        if (kp.per[a]) {
+            const double L = box_len(kp, a);
+            if (s.R[a] >= L) s.R[a] -= L;
+            else if (s.R[a] < 0.0) s.R[a] += L;
+        }
+    }
+    const int seq[5] = {0, 1, 2, 1, 0};
+    const double frac[5] = {0.5, 0.5, 1.0, 0.5, 0.5};
+    for (int stp = 0; stp < 5; ++stp) {
+        const int k = seq[stp];
+        const double phi = frac[stp] * s.Om[k];
+        double c, sn;
+        sincos(-phi, &sn, &c);
+        double M[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if (k == 0) { M[0] = 1; M[4] = c; M[5] = -sn; M[7] = sn; M[8] = c; }
+        if (k == 1) { M[4] = 1; M[0] = c; M[2] = sn; M[6] = -sn; M[8] = c; }
+        if (k == 2) { M[8] = 1; M[0] = c; M[1] = -sn; M[3] = sn; M[4] = c; }
+        double pi[3], pn[3], Qn[9];
+        for (int a = 0; a < 3; ++a) pi[a] = kp.inertia[a] * s.Om[a];
+        mat_vec(M, pi, pn);
+        for (int a = 0; a < 3; ++a) s.Om[a] = pn[a] / kp.inertia[a];
+        for (int r = 0; r < 3; ++r)
+            for (int cc = 0; cc < 3; ++cc)
+                Qn[3 * r + cc] = s.Q[3 * r] * M[3 * cc] + s.Q[3 * r + 1] * M[3 * cc + 1] +
+                                 s.Q[3 * r + 2] * M[3 * cc + 2];
+        for (int a = 0; a < 9; ++a) s.Q[a] = Qn[a];
+    }
+    for (int a = 0; a < 3; ++a) {
+        s.Vh[a] = s.V[a];
+        s.Omh[a] = s.Om[a];
+    }
+    st[i] = s;
+}
+
+// ---- S2: cell list (counting sort, ids ascending per cell) --------------------------------
+__device__ __forceinline__ int cell_coord(const KParams& kp, int a, double x)
+{
+    int c = (int)floor(x / kp.cedge[a]);
+    if (c < 0) c = 0;
+    if (c >= kp.ncell[a]) c = kp.ncell[a] - 1;
+    return c;
+}
+
+__global__ __launch_bounds__(256) void k_cells_bin(const RbcState* __restrict__ st, int* cellid,
+                                                   int* cnt, KParams kp)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kp.nrbc) return;
+    const double* R = st[i].R;
+    const int c = cell_coord(kp, 0, R[0]) +
+                  kp.ncell[0] * (cell_coord(kp, 1, R[1]) + kp.ncell[1] * cell_coord(kp, 2, R[2]));
+    cellid[i] = c;
+    atomicAdd(cnt + c, 1);
+}
+
+// exclusive scan of n ints in one block of 1024 threads; also clears `cnt`
+__global__ __launch_bounds__(1024) void k_scan_clear(int* cnt, int* off, int n)
+{
+    __shared__ int part[1024];
+    const int t = threadIdx.x;
+    const int chunk = (n + 1023) / 1024;
+    const int b = t * chunk, e = min(n, b + chunk);
+    int s = 0;
+    for (int k = b; k < e; ++k) s += cnt[k];
+    part[t] = s;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const int v = t >= d ? part[t - d] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - s;
+    for (int k = b; k < e; ++k) {
+        const int c = cnt[k];
+        off[k] = run;
+        run += c;
+        cnt[k] = 0;
+    }
+    if (t == 1023) off[n] = part[1023];
+}
+
+__global__ __launch_bounds__(256) void k_cells_scatter(const int* __restrict__ cellid,
+                                                       const int* __restrict__ off, int* fill,
+                                                       int* ids, int nrbc)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrbc) return;
+    const int c = cellid[i];
+    ids[off[c] + atomicAdd(fill + c, 1)] = i;
+}
+
+__global__ __launch_bounds__(256) void k_cells_sort(const int* __restrict__ off, int* ids, int ncells)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    const int b = off[c], e = off[c + 1];
+    for (int k = b + 1; k < e; ++k) {
+        const int v = ids[k];
+        int j = k - 1;
+        while (j >= b && ids[j] > v) {
+            ids[j + 1] = ids[j];
+            --j;
+        }
+        ids[j + 1] = v;
+    }
+}
+
+// ---- support tile of one cell --------------------------------------------------------------
+// The support |y_a| < xi_a lies within |x_a - R_a| < ext_a = sum_b |Q_ab| xi_b; the tile adds
+// one node on each side (the halo of the central-difference gradient).
+struct Tile {
+    int lo[3], sz[3];
+};
+
+__device__ __forceinline__ void support_tile(const RbcState& s, const KParams& kp, Tile& t)
+{
+    for (int a = 0; a < 3; ++a) {
+        const double ext = fabs(s.Q[3 * a]) * kp.xi[0] + fabs(s.Q[3 * a + 1]) * kp.xi[1] +
+                           fabs(s.Q[3 * a + 2]) * kp.xi[2];
+        const int lo = (int)floor(s.R[a] - ext) - 1;
+        const int hi = (int)ceil(s.R[a] + ext) + 1;
+        t.lo[a] = lo;
+        t.sz[a] = hi - lo + 1;
+    }
+}
+
+// node index of tile position (unwrapped X); -1 outside a non-periodic face
+__device__ __forceinline__ long long tile_node(const KParams& kp, int X, int Y, int Z, int& xw,
+                                               int& yw, int& zw)
+{
+    if (X < 0 || X >= kp.nx) { if (!kp.per[0]) return -1; X = ((X % kp.nx) + kp.nx) % kp.nx; }
+    if (Y < 0 || Y >= kp.ny) { if (!kp.per[1]) return -1; Y = ((Y % kp.ny) + kp.ny) % kp.ny; }
+    if (Z < 0 || Z >= kp.nz) { if (!kp.per[2]) return -1; Z = ((Z % kp.nz) + kp.nz) % kp.nz; }
+    xw = X;
+    yw = Y;
+    zw = Z;
+    return (long long)X + (long long)kp.nx * ((long long)Y + (long long)kp.ny * Z);
+}
+
+__device__ __forceinline__ void body_of_node(const RbcState& s, const KParams& kp, int xw, int yw,
+                                             int zw, double y[3])
+{
+    const double d0 = min_img((double)xw - s.R[0], (double)kp.nx, kp.per[0]);
+    const double d1 = min_img((double)yw - s.R[1], (double)kp.ny, kp.per[1]);
+    const double d2 = min_img((double)zw - s.R[2], (double)kp.nz, kp.per[2]);
+    body_coords_exact(s.Q, d0, d1, d2, y);
+}
+
+// ---- S3: node -> cell coverage map ---------------------------------------------------------
+// covered(x, i) <=> x fluid and (x, or a fluid axis neighbour of x, inside the support of i)
+__global__ __launch_bounds__(256) void k_map_fill(const RbcState* __restrict__ st,
+                                                  uint32_t* __restrict__ nodeword, int* __restrict__ ids,
+                                                  KParams kp, unsigned* err)
+{
+    extern __shared__ unsigned char flag[];
+    __shared__ Tile T;
+    const int i = blockIdx.x;
+    const RbcState& s = st[i];
+    if (threadIdx.x == 0) support_tile(s, kp, T);
+    __syncthreads();
+    if (T.sz[0] > kp.tile_max || T.sz[1] > kp.tile_max || T.sz[2] > kp.tile_max) {
+        if (threadIdx.x == 0) atomicOr(err, ERR_CAPACITY);
+        return;
+    }
+    const int sx = T.sz[0], sy = T.sz[1], total = T.sz[0] * T.sz[1] * T.sz[2];
+    for (int t = threadIdx.x; t < total; t += blockDim.x) {
+        const int tx = t % sx, ty = (t / sx) % sy, tz = t / (sx * sy);
+        int xw, yw, zw;
+        const long long n = tile_node(kp, T.lo[0] + tx, T.lo[1] + ty, T.lo[2] + tz, xw, yw, zw);
+        unsigned char in = 0;
+        if (n >= 0 && (nodeword[n] & NW_FLUID)) {
+            double y[3];
+            body_of_node(s, kp, xw, yw, zw, y);
+            in = fabs(y[0]) < kp.xi[0] && fabs(y[1]) < kp.xi[1] && fabs(y[2]) < kp.xi[2];
+        }
+        flag[t] = in;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < total; t += blockDim.x) {
+        const int tx = t % sx, ty = (t / sx) % sy, tz = t / (sx * sy);
+        int xw, yw, zw;
+        const long long n = tile_node(kp, T.lo[0] + tx, T.lo[1] + ty, T.lo[2] + tz, xw, yw, zw);
+        if (n < 0 || !(nodeword[n] & NW_FLUID)) continue;
+        const bool cov = flag[t] || (tx > 0 && flag[t - 1]) || (tx < sx - 1 && flag[t + 1]) ||
+                         (ty > 0 && flag[t - sx]) || (ty < sy - 1 && flag[t + sx]) ||
+                         (tz > 0 && flag[t - sx * sy]) || (tz < T.sz[2] - 1 && flag[t + sx * sy]);
+        if (!cov) continue;
+        const uint32_t old = atomicAdd(nodeword + n, NW_CNT_ONE);
+        const int slot = (int)(old >> 24);
+        if (slot < kp.cap) ids[(long long)slot * kp.ld + n] = i;
+        else atomicOr(err, ERR_CAPACITY);
+    }
+}
+
+// ---- S4: interpolation onto each cell (Eqs. 16-21) ------------------------------------------
+template <typename RT>
+__device__ __forceinline__ RT block_sum(RT v, RT* red)
+{
+    // 256 threads, wave64: shuffle inside the wave, then across the four waves
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    RT r = red[0] + red[1] + red[2] + red[3];
+    return r;
+}
+
+template <typename RT>
+__device__ __forceinline__ RT u_node(const RT* __restrict__ u, const uint32_t* __restrict__ nw,
+                                     const KParams& kp, int X, int Y, int Z, int a)
+{
+    int xw, yw, zw;
+    const long long n = tile_node(kp, X, Y, Z, xw, yw, zw);
+    if (n < 0 || !(nw[n] & NW_FLUID)) return RT(0);
+    return u[(long long)a * kp.ld + n];
+}
+
+template <typename RT>
+__global__ __launch_bounds__(256) void k_couple(const RbcState* __restrict__ st,
+                                                RbcCouple* __restrict__ cp,
+                                                const uint32_t* __restrict__ nodeword,
+                                                const RT* __restrict__ u, const RT* __restrict__ sig,
+                                                KParams kp, unsigned* err)
+{
+    extern __shared__ unsigned char smem[];
+    RT* raw = reinterpret_cast<RT*>(smem);
+    __shared__ Tile T;
+    __shared__ RT red[4];
+    const int i = blockIdx.x;
+    const RbcState& s = st[i];
+    if (threadIdx.x == 0) support_tile(s, kp, T);
+    __syncthreads();
+    if (T.sz[0] > kp.tile_max || T.sz[1] > kp.tile_max || T.sz[2] > kp.tile_max) {
+        if (threadIdx.x == 0) atomicOr(err, ERR_CAPACITY);
+        return;
+    }
+    const int sx = T.sz[0], sy = T.sz[1], sxy = sx * sy, total = sxy * T.sz[2];
+    const RT s0 = RT(2.0 / kp.xi[0]), s1 = RT(2.0 / kp.xi[1]), s2 = RT(2.0 / kp.xi[2]);
+    RT part = RT(0);
+    for (int t = threadIdx.x; t < total; t += blockDim.x) {
+        const int tx = t % sx, ty = (t / sx) % sy, tz = t / sxy;
+        int xw, yw, zw;
+        const long long n = tile_node(kp, T.lo[0] + tx, T.lo[1] + ty, T.lo[2] + tz, xw, yw, zw);
+        RT r = RT(0);
+        if (n >= 0 && (nodeword[n] & NW_FLUID)) {
+            double y[3];
+            body_of_node(s, kp, xw, yw, zw, y);
+            r = peskin((RT)y[0] * s0) * peskin((RT)y[1] * s1) * peskin((RT)y[2] * s2);
+        }
+        raw[t] = r;
+        part += r;
+    }
+    const RT S = block_sum(part, red);
+    __syncthreads();
+    const RT invS = S > RT(0) ? RT(1) / S : RT(0);
+    RT acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int t = threadIdx.x; t < total; t += blockDim.x) {
+        const RT r = raw[t];
+        if (!(r > RT(0))) continue;
+        const int tx = t % sx, ty = (t / sx) % sy, tz = t / sxy;
+        const int X = T.lo[0] + tx, Y = T.lo[1] + ty, Z = T.lo[2] + tz;
+        int xw, yw, zw;
+        const long long n = tile_node(kp, X, Y, Z, xw, yw, zw);
+        const RT dh = r * invS;
+        // nodes with r > 0 are inside the support, so their tile neighbours exist
+        const RT gx = RT(0.5) * (raw[t + 1] - raw[t - 1]) * invS;
+        const RT gy = RT(0.5) * (raw[t + sx] - raw[t - sx]) * invS;
+        const RT gz = RT(0.5) * (raw[t + sxy] - raw[t - sxy]) * invS;
+        acc[0] += dh * u[n];
+        acc[1] += dh * u[kp.ld + n];
+        acc[2] += dh * u[2 * kp.ld + n];
+        // vorticity: curl of u by central differences, u = 0 on solid nodes
+        const RT wx = RT(0.5) * (u_node(u, nodeword, kp, X, Y + 1, Z, 2) - u_node(u, nodeword, kp, X, Y - 1, Z, 2)) -
+                      RT(0.5) * (u_node(u, nodeword, kp, X, Y, Z + 1, 1) - u_node(u, nodeword, kp, X, Y, Z - 1, 1));
+        const RT wy = RT(0.5) * (u_node(u, nodeword, kp, X, Y, Z + 1, 0) - u_node(u, nodeword, kp, X, Y, Z - 1, 0)) -
+                      RT(0.5) * (u_node(u, nodeword, kp, X + 1, Y, Z, 2) - u_node(u, nodeword, kp, X - 1, Y, Z, 2));
+        const RT wz = RT(0.5) * (u_node(u, nodeword, kp, X + 1, Y, Z, 1) - u_node(u, nodeword, kp, X - 1, Y, Z, 1)) -
+                      RT(0.5) * (u_node(u, nodeword, kp, X, Y + 1, Z, 0) - u_node(u, nodeword, kp, X, Y - 1, Z, 0));
+        acc[3] += dh * wx;
+        acc[4] += dh * wy;
+        acc[5] += dh * wz;
+        // elongational torque: alpha dhat (sigma . n^) x (x - R), n^ = grad/|grad|
+        const RT gl = sqrt(gx * gx + gy * gy + gz * gz);
+        const RT nx_ = gl > RT(0) ? gx / gl : RT(0), ny_ = gl > RT(0) ? gy / gl : RT(0),
+                 nz_ = gl > RT(0) ? gz / gl : RT(0);
+        const RT sxx = sig[n], syy = sig[kp.ld + n], szz = sig[2 * kp.ld + n];
+        const RT sxy_ = sig[3 * kp.ld + n], sxz = sig[4 * kp.ld + n], syz = sig[5 * kp.ld + n];
+        const RT t0 = sxx * nx_ + sxy_ * ny_ + sxz * nz_;
+        const RT t1 = sxy_ * nx_ + syy * ny_ + syz * nz_;
+        const RT t2 = sxz * nx_ + syz * ny_ + szz * nz_;
+        const RT d0 = (RT)min_img((double)xw - s.R[0], (double)kp.nx, kp.per[0]);
+        const RT d1 = (RT)min_img((double)yw - s.R[1], (double)kp.ny, kp.per[1]);
+        const RT d2 = (RT)min_img((double)zw - s.R[2], (double)kp.nz, kp.per[2]);
+        const RT al = (RT)kp.alpha * dh;
+        acc[6] += al * (t1 * d2 - t2 * d1);
+        acc[7] += al * (t2 * d0 - t0 * d2);
+        acc[8] += al * (t0 * d1 - t1 * d0);
+    }
+    RT tot[9];
+    for (int a = 0; a < 9; ++a) {
+        tot[a] = block_sum(acc[a], red);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        RbcCouple& c = cp[i];
+        c.S = (double)S;
+        for (int a = 0; a < 3; ++a) {
+            c.ut[a] = (double)tot[a];
+            c.wt[a] = (double)tot[3 + a];
+            c.TS[a] = (double)tot[6 + a];
+        }
+    }
+}
+
+// ---- S5: Gay-Berne forces and torques (Sec. II E, Eqs. 24-28; App. B) -----------------------
+// F on i = -du/dR |R^ - (1/R^2) du/dphi [k - (k.R^) R^], k = H^-1 R_ij, H = A_i + A_j;
+// torques tau_i = (1/R) R_ci x f_k, R_ci = -A_i k, f_k = -(1/R) du/dphi k (lab frame).
+__device__ int gb_pair(const KParams& kp, const double* rij, const double* Qi, const double* Qj,
+                       int wall, double* F, double* ti)
+{
+    double Ai[9], H[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double a = 0.0, b = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                const double ax2 = kp.axes[k] * kp.axes[k];
+                a += Qi[3 * r + k] * ax2 * Qi[3 * c + k];
+                if (!wall) b += Qj[3 * r + k] * ax2 * Qj[3 * c + k];
+            }
+            if (wall) b = (r == c) ? kp.a_wall * kp.a_wall : 0.0;
+            Ai[3 * r + c] = a;
+            H[3 * r + c] = a + b;
+        }
+    const double det = H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
+                       H[2] * (H[3] * H[7] - H[4] * H[6]);
+    double Hi[9];
+    Hi[0] = (H[4] * H[8] - H[5] * H[7]) / det;
+    Hi[1] = (H[2] * H[7] - H[1] * H[8]) / det;
+    Hi[2] = (H[1] * H[5] - H[2] * H[4]) / det;
+    Hi[3] = (H[5] * H[6] - H[3] * H[8]) / det;
+    Hi[4] = (H[0] * H[8] - H[2] * H[6]) / det;
+    Hi[5] = (H[2] * H[3] - H[0] * H[5]) / det;
+    Hi[6] = (H[3] * H[7] - H[4] * H[6]) / det;
+    Hi[7] = (H[1] * H[6] - H[0] * H[7]) / det;
+    Hi[8] = (H[0] * H[4] - H[1] * H[3]) / det;
+    const double R = sqrt(rij[0] * rij[0] + rij[1] * rij[1] + rij[2] * rij[2]);
+    if (!(R > 0.0)) return 1;
+    double rh[3], kap[3];
+    for (int k = 0; k < 3; ++k) rh[k] = rij[k] / R;
+    mat_vec(Hi, rij, kap);
+    const double phi = 0.5 * (rh[0] * kap[0] + rh[1] * kap[1] + rh[2] * kap[2]) / R;
+    const double sigma = 1.0 / sqrt(phi);
+    const double amin = fmin(kp.axes[0], fmin(kp.axes[1], kp.axes[2]));
+    const double smin = wall ? kp.sigmin_wall : sqrt(4.0 * amin * amin);
+    const double rho = (R - sigma + smin) / smin;
+    if (!(rho > 0.0)) return 1;
+    const double r2 = rho * rho, r6 = r2 * r2 * r2;
+    if (r6 > 2.0) return 0;
+    const double ir6 = 1.0 / r6, ir7 = ir6 / rho, ir13 = ir7 * ir6;
+    const double core = -24.0 * kp.eps0 * (2.0 * ir13 - ir7);
+    const double dudr = core / smin;
+    const double dudphi = core * sigma * sigma * sigma / (2.0 * smin);
+    const double kr = kap[0] * rh[0] + kap[1] * rh[1] + kap[2] * rh[2];
+    for (int k = 0; k < 3; ++k) F[k] += -dudr * rh[k] - dudphi / (R * R) * (kap[k] - kr * rh[k]);
+    double Aik[3], fk[3], c[3];
+    mat_vec(Ai, kap, Aik);
+    for (int k = 0; k < 3; ++k) {
+        fk[k] = -dudphi / R * kap[k];
+        Aik[k] = -Aik[k];
+    }
+    cross3(Aik, fk, c);
+    for (int k = 0; k < 3; ++k) ti[k] += c[k] / R;
+    return 0;
+}
+
+__global__ __launch_bounds__(128) void k_gay_berne(const RbcState* __restrict__ st,
+                                                   RbcCouple* __restrict__ cp,
+                                                   const int* __restrict__ cell_off,
+                                                   const int* __restrict__ cell_ids,
+                                                   const int* __restrict__ wall_xyz,
+                                                   const int* __restrict__ wcell_off,
+                                                   const int* __restrict__ wcell_ids, KParams kp,
+                                                   unsigned* err)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kp.nrbc) return;
+    const double* Ri = st[i].R;
+    const double* Qi = st[i].Q;
+    double F[3] = {0, 0, 0}, tl[3] = {0, 0, 0};
+    int lst[3][3], cnt[3];
+    int cc[3];
+    for (int a = 0; a < 3; ++a) {
+        cc[a] = cell_coord(kp, a, Ri[a]);
+        const int m = kp.ncell[a];
+        cnt[a] = 0;
+        if (m < 3) {
+            for (int q = 0; q < m; ++q) lst[a][cnt[a]++] = q;
+        } else {
+            for (int d = -1; d <= 1; ++d) {
+                int v = cc[a] + d;
+                if (v < 0 || v >= m) {
+                    if (!kp.per[a]) continue;
+                    v = (v + m) % m;
+                }
+                lst[a][cnt[a]++] = v;
+            }
+        }
+    }
+    const double rc2 = kp.rc * kp.rc;
+    bool bad = false;
+    for (int kz = 0; kz < cnt[2]; ++kz)
+        for (int ky = 0; ky < cnt[1]; ++ky)
+            for (int kx = 0; kx < cnt[0]; ++kx) {
+                const int c = lst[0][kx] + kp.ncell[0] * (lst[1][ky] + kp.ncell[1] * lst[2][kz]);
+                for (int e = cell_off[c]; e < cell_off[c + 1]; ++e) {
+                    const int j = cell_ids[e];
+                    if (j == i) continue;
+                    double r[3];
+                    for (int a = 0; a < 3; ++a)
+                        r[a] = min_img(Ri[a] - st[j].R[a], box_len(kp, a), kp.per[a]);
+                    if (r[0] * r[0] + r[1] * r[1] + r[2] * r[2] > rc2) continue;
+                    bad |= gb_pair(kp, r, Qi, st[j].Q, 0, F, tl) != 0;
+                }
+                if (!kp.wall_particles) continue;
+                for (int e = wcell_off[c]; e < wcell_off[c + 1]; ++e) {
+                    const int wq = wcell_ids[e];
+                    double r[3];
+                    for (int a = 0; a < 3; ++a)
+                        r[a] = min_img(Ri[a] - (double)wall_xyz[3 * wq + a], box_len(kp, a), kp.per[a]);
+                    if (r[0] * r[0] + r[1] * r[1] + r[2] * r[2] > rc2) continue;
+                    bad |= gb_pair(kp, r, Qi, nullptr, 1, F, tl) != 0;
+                }
+            }
+    if (bad) atomicOr(err, ERR_OVERLAP);
+    double tb[3];
+    matT_vec(Qi, tl, tb);
+    for (int a = 0; a < 3; ++a) {
+        cp[i].Fm[a] = F[a];
+        cp[i].Tm[a] = tb[a];
+    }
+}
+
+// ---- S6: combined force/torque, hydrodynamic force/torque, second half --------------------
+// F^comb = F^mech + gT M u~; tau^comb = tau^mech + Q^T T^S + gR I (s Q^T w~);
+// F^hyd = -M gT (V^1/2 - u~); T^hyd = Q [-gR I (Omega^1/2 - s Q^T w~)] + T^S (lab).
+template <typename RT>
+__global__ __launch_bounds__(128) void k_rb_second_half(RbcState* __restrict__ st,
+                                                        RbcCouple* __restrict__ cp,
+                                                        Gather<RT>* __restrict__ gat, KParams kp,
+                                                        int integrate)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kp.nrbc) return;
+    RbcState s = st[i];
+    RbcCouple c = cp[i];
+    double wb[3], tsb[3], tb[3], tl[3];
+    matT_vec(s.Q, c.wt, wb);
+    matT_vec(s.Q, c.TS, tsb);
+    const double* Vh = integrate ? s.Vh : s.V;
+    const double* Oh = integrate ? s.Omh : s.Om;
+    for (int a = 0; a < 3; ++a) {
+        c.Fh[a] = -kp.mass * kp.gammaT * (Vh[a] - c.ut[a]);
+        tb[a] = -kp.gammaR * kp.inertia[a] * (Oh[a] - kp.vort_scale * wb[a]);
+    }
+    mat_vec(s.Q, tb, tl);
+    for (int a = 0; a < 3; ++a) c.Th[a] = tl[a] + c.TS[a];
+    if (integrate) {
+        const double eT = exp(-kp.gammaT * 0.5), eR = exp(-kp.gammaR * 0.5);
+        for (int a = 0; a < 3; ++a) {
+            s.Fc[a] = c.Fm[a] + kp.gammaT * kp.mass * c.ut[a];
+            s.Tc[a] = c.Tm[a] + tsb[a] + kp.gammaR * kp.inertia[a] * kp.vort_scale * wb[a];
+            s.V[a] *= eT;
+            s.Om[a] *= eR;
+            s.V[a] += 0.5 / kp.mass * s.Fc[a];
+            s.Om[a] += 0.5 * s.Tc[a] / kp.inertia[a];
+        }
+        st[i] = s;
+    }
+    for (int a = 0; a < 3; ++a) {
+        cp[i].Fh[a] = c.Fh[a];
+        cp[i].Th[a] = c.Th[a];
+    }
+    Gather<RT> G;
+    for (int a = 0; a < 3; ++a) {
+        G.R[a] = s.R[a];
+        G.F[a] = (RT)c.Fh[a];
+        G.T[a] = (RT)c.Th[a];
+    }
+    for (int a = 0; a < 9; ++a) G.Q[a] = (RT)s.Q[a];
+    G.invS = c.S > 0.0 ? (RT)(1.0 / c.S) : RT(0);
+    G.pad = RT(0);
+    gat[i] = G;
+}
+
+__global__ void k_init_combined(RbcState* __restrict__ st, const RbcCouple* __restrict__ cp, int nrbc)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrbc) return;
+    for (int a = 0; a < 3; ++a) {
+        st[i].Fc[a] = cp[i].Fm[a];
+        st[i].Tc[a] = cp[i].Tm[a];
+    }
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, long long n)
+{
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = v;
+}
+
+// ---- launchers ---------------------------------------------------------------------------------
+static inline unsigned nblk(long long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+void launch_fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t st)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_u32, dim3(nblk(n, 256)), dim3(256), 0, st, p, v, n);
+}
+
+void launch_rb_first_half(const CellBuffers& b, const KParams& kp, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rb_first_half, dim3(nblk(kp.nrbc, 128)), dim3(128), 0, st, b.st, kp);
+}
+
+void launch_cell_list(const CellBuffers& b, const KParams& kp, hipStream_t st)
+{
+    const int nc = kp.ncell[0] * kp.ncell[1] * kp.ncell[2];
+    // cell_cnt is all zero here: k_scan_clear leaves it so, and init clears it once
+    hipLaunchKernelGGL(k_cells_bin, dim3(nblk(kp.nrbc, 256)), dim3(256), 0, st, b.st, b.cellid,
+                       b.cell_cnt, kp);
+    hipLaunchKernelGGL(k_scan_clear, dim3(1), dim3(1024), 0, st, b.cell_cnt, b.cell_off, nc);
+    hipLaunchKernelGGL(k_cells_scatter, dim3(nblk(kp.nrbc, 256)), dim3(256), 0, st, b.cellid,
+                       b.cell_off, b.cell_cnt, b.cell_ids, kp.nrbc);
+    hipLaunchKernelGGL(k_cells_sort, dim3(nblk(nc, 256)), dim3(256), 0, st, b.cell_off,
+                       b.cell_ids, nc);
+    // leave the fill counters at zero for the next call
+    launch_fill_u32(reinterpret_cast<uint32_t*>(b.cell_cnt), 0u, nc, st);
+}
+
+void launch_map_fill(const CellBuffers& b, const KParams& kp, hipStream_t st)
+{
+    const size_t lds = (size_t)kp.tile_max * kp.tile_max * kp.tile_max;
+    hipLaunchKernelGGL(k_map_fill, dim3(kp.nrbc), dim3(256), lds, st, b.st, b.nodeword,
+                       b.map_ids, kp, b.err);
+}
+
+template <typename RT>
+void launch_couple(const CellBuffers& b, const KParams& kp, hipStream_t st)
+{
+    const size_t lds = (size_t)kp.tile_max * kp.tile_max * kp.tile_max * sizeof(RT);
+    hipLaunchKernelGGL((k_couple<RT>), dim3(kp.nrbc), dim3(256), lds, st, b.st, b.cp, b.nodeword,
+                       (const RT*)b.u, (const RT*)b.sig, kp, b.err);
+}
+
+void launch_gay_berne(const CellBuffers& b, const KParams& kp, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gay_berne, dim3(nblk(kp.nrbc, 128)), dim3(128), 0, st, b.st, b.cp,
+                       b.cell_off, b.cell_ids, b.wall_xyz, b.wcell_off, b.wcell_ids, kp, b.err);
+}
+
+template <typename RT>
+void launch_rb_second_half(const CellBuffers& b, const KParams& kp, int integrate, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_rb_second_half<RT>), dim3(nblk(kp.nrbc, 128)), dim3(128), 0, st, b.st,
+                       b.cp, (Gather<RT>*)b.gat, kp, integrate);
+}
+
+void launch_init_combined(const CellBuffers& b, const KParams& kp, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_init_combined, dim3(nblk(kp.nrbc, 128)), dim3(128), 0, st, b.st, b.cp,
+                       kp.nrbc);
+}
+
+template void launch_couple<double>(const CellBuffers&, const KParams&, hipStream_t);
+template void launch_couple<float>(const CellBuffers&, const KParams&, hipStream_t);
+template void launch_rb_second_half<double>(const CellBuffers&, const KParams&, int, hipStream_t);
+template void launch_rb_second_half<float>(const CellBuffers&, const KParams&, int, hipStream_t);
+
+}  // namespace lbrbc

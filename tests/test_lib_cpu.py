@@ -1,0 +1,59 @@
+"""Host-side checks of the HIP library that need no GPU: it loads, exports every symbol the
+header declares, and rejects invalid configurations synchronously."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbrbc.h")
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1107_4889_amd import lbrbc
+
+    text = open(HEADER).read()
+    declared = set(re.findall(r"^\s*(?:lb_status|void|const char\*)\s+(\w+)\s*\(", text, re.M))
+    assert len(declared) >= 20
+    lib = ctypes.CDLL(lbrbc.LIB_PATH)
+    missing = [s for s in sorted(declared) if not hasattr(lib, s)]
+    assert not missing, missing
+    assert declared == set(lbrbc.SYMBOLS)
+
+
+def _cfg(**kw):
+    from paper_1107_4889_amd import lbrbc
+    d = dict(nx=16, ny=16, nz=32, periodic=(0, 0, 1), tau0=0.8)
+    d.update(kw)
+    return lbrbc.make_config(d)
+
+
+def test_footprint_and_validation_on_host():
+    from paper_1107_4889_amd import lbrbc, synth
+
+    solid = synth.tube(16, 16, 32, 6.0)
+    b32 = lbrbc.lb_query_footprint(_cfg(storage="f32"), solid, 10)
+    b64 = lbrbc.lb_query_footprint(_cfg(storage="f64"), solid, 10)
+    b16 = lbrbc.lb_query_footprint(_cfg(storage="bf16"), solid, 10)
+    N = 16 * 16 * 32
+    assert b64 > b32 > b16 >= 2 * 19 * N * 2
+    for bad in (dict(tau0=0.5), dict(map_cap=13), dict(storage=7), dict(open_z=1),
+                dict(nx=0), dict(xi=(0, 1, 1))):
+        with pytest.raises(lbrbc.LbError) as e:
+            lbrbc.lb_query_footprint(_cfg(**bad), solid, 10)
+        assert e.value.status == lbrbc.LB_EINVAL
+    # a periodic axis shorter than a support tile is rejected when cells are present
+    with pytest.raises(lbrbc.LbError):
+        lbrbc.lb_query_footprint(_cfg(nz=12), synth.tube(16, 16, 12, 6.0), 3)
+    assert lbrbc.lb_query_footprint(_cfg(nz=12), synth.tube(16, 16, 12, 6.0), 0) > 0
+
+
+def test_null_arguments_are_rejected():
+    from paper_1107_4889_amd import lbrbc
+    L = lbrbc._lib
+    assert L.lb_step(None, 1) == lbrbc.LB_EINVAL
+    assert L.lb_sync(None) == lbrbc.LB_EINVAL
+    assert L.rbc_couple(None) == lbrbc.LB_EINVAL
+    assert L.lb_query_footprint(None, None, 0, None) == lbrbc.LB_EINVAL
