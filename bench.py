@@ -1,0 +1,189 @@
+#!/usr/bin/env python
+"""Benchmark of the coupled plasma / rigid-RBC time step on one MI355X.
+
+Workload (default): a straight tube of radius 60 lu along z in a 128x128x512 box (periodic
+in z, body-force driven g = 1e-6, T0 = 0.8), cells of semi-axes (4, 4, 1.5) placed from
+seed 1107 at the target hematocrit 0.35 (the achieved count is reported), FP32 shifted
+populations with FP32 arithmetic. One step = every stage of the hot path: rigid-body first
+half, cell list, coverage map, interpolation, Gay-Berne forces, rigid-body second half,
+fused spreading + stream-collide.
+
+Prints one JSON line: MLUPS of the whole step (fluid-node updates per second), the
+stream-collide kernel's roofline against HBM (algorithmic bytes per launch over its mean
+HIP-event duration on the library's stream), and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+STORAGE_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha1()
+    for f in ("lb_kernels.hip", "lbrbc_device.h"):
+        h.update(open(os.path.join(ROOT, "paper_1107_4889_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:12]
+
+
+def measured_traffic(workload: str, storage: str):
+    """HBM bytes per stream-collide launch from the committed rocprofv3 counter summary,
+    or None when the kernel source changed since the counters were taken."""
+    fn = os.path.join(ROOT, "profiles", f"traffic_stream_collide_{workload}_{storage}.json")
+    if not os.path.exists(fn):
+        return None
+    d = json.load(open(fn))
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def workload(name: str, storage: str):
+    from paper_1107_4889_amd import synth
+
+    if name == "tube128":
+        nx, ny, nz, R, H, T0 = 128, 128, 512, 60.0, 0.35, 0.8
+        solid, pl = synth.tube_workload(nx, ny, nz, R, hematocrit=H, seed=1107)
+    elif name == "tube32":
+        nx, ny, nz, R, H, T0 = 32, 32, 64, 14.0, None, 1.0
+        solid, pl = synth.tube_workload(nx, ny, nz, R, n_cells=110, seed=1107)
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    cfg = dict(nx=nx, ny=ny, nz=nz, periodic=(0, 0, 1), tau0=T0, g_ext=(0.0, 0.0, 1e-6),
+               storage=storage, f16_scale=2.0 ** 21)
+    desc = (f"tube {nx}x{ny}x{nz} R={R:g} periodic z, {len(pl.R)} cells (H={pl.hematocrit:.3f}"
+            f"{'' if H is None else f', target {H}'}), {storage} shifted storage, T0={T0}, g=1e-6")
+    return cfg, solid, pl, desc
+
+
+def cpu_baseline(cfg, solid, pl, n_fluid: int):
+    """The FP64 oracle, as it stands, on one coupled step of the same workload."""
+    from oracle import oracle as orc
+
+    ocfg = {k: v for k, v in cfg.items() if k not in ("storage", "f16_scale")}
+    o = orc.Oracle(ocfg, solid, R=pl.R, Q=pl.Q)
+    t0 = time.perf_counter()
+    st = o.step(1)
+    dt = time.perf_counter() - t0
+    if st != 0:
+        return None
+    return {"value": round(n_fluid / dt / 1e6, 4), "unit": "MLUPS", "cores": orc.num_threads(),
+            "kind": "oracle",
+            "sample": f"1 coupled step of the same workload (all stages, {n_fluid} fluid nodes, "
+                      f"{len(pl.R)} cells) after set-up; {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--storage", default="f32", choices=list(STORAGE_BYTES))
+    ap.add_argument("--workload", default="tube128")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain device copy of 1 GiB (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the hot path runs "
+              "on a single MI355X; a multi-GPU run would shard the lattice in z-slabs)",
+              file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import torch
+
+    if args.copy_calibration:
+        n = 1 << 30
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}), flush=True)
+        return
+
+    from paper_1107_4889_amd import lbrbc
+
+    cfg, solid, pl, desc = workload(args.workload, args.storage)
+    print(f"[bench] {desc}", file=sys.stderr, flush=True)
+    sim = lbrbc.Simulation(cfg, solid, R=pl.R, Q=pl.Q)
+    n_fluid = int((solid == 0).sum())
+
+    sim.lb_step(args.warmup)
+    torch.cuda.synchronize()
+    sim.lb_sync()
+    sim.lb_set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.lb_step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sc_ms, step_ev_ms = sim.lb_kernel_time()
+    sim.lb_set_timing(False)
+    sim.lb_sync()
+    obs = sim.lb_observe()
+    print(f"[bench] timed {args.steps} steps in {t1 - t0:.3f} s; stream-collide {sc_ms:.4f} ms/launch",
+          file=sys.stderr, flush=True)
+
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    mlups = n_fluid * args.steps / (t1 - t0) / 1e6
+    alg_bytes = n_fluid * 2 * 19 * STORAGE_BYTES[args.storage]
+    achieved = alg_bytes / (sc_ms * 1e-3) / 1e9 if sc_ms > 0 else 0.0
+    line = {
+        "metric": "MLUPS & achieved HBM GB/s (LBM+RBC step); p50/p99 request latency",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.storage == "f64" else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": desc,
+            "lattice": [cfg["nx"], cfg["ny"], cfg["nz"]],
+            "n_fluid": n_fluid,
+            "n_cells": int(len(pl.R)),
+            "hematocrit": round(pl.hematocrit, 4),
+            "storage": args.storage,
+            "parallelism": "single GPU",
+        },
+        "stream_collide": {
+            "mlups": round(n_fluid / (sc_ms * 1e-3) / 1e6, 2) if sc_ms > 0 else None,
+            "ms_per_launch": round(sc_ms, 5),
+            "algorithmic_bytes_per_lu": 2 * 19 * STORAGE_BYTES[args.storage],
+            "hbm_gbs_algorithmic": round(achieved, 1),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": measured_traffic(args.workload, args.storage),
+        },
+        "observables": {"flow_rate": obs.flow_rate, "eta_app": obs.eta_app,
+                        "wss_mean": obs.wss_mean, "mass": obs.mass},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on one step of the same workload", file=sys.stderr,
+              flush=True)
+        line["cpu_baseline"] = cpu_baseline(cfg, solid, pl, n_fluid)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -25,6 +25,18 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ---------------------------------------------------------------------------------- */
 /* D3Q19 lattice (Sec. II A): c0 = 0 (w = 1/3), six first neighbours (w = 1/18), twelve

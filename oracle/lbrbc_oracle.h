@@ -98,6 +98,9 @@ int orc_wall_shear_stress(const orc_sim* s, long* node, double* wss);
 /* Momentum exchanged with the walls by bounce-back during the last step (lab). */
 void orc_wall_momentum(const orc_sim* s, double out3[3]);
 
+/* Threads the oracle's parallel loops use (OpenMP; 1 without it). */
+int orc_num_threads(void);
+
 /* Primitives exposed for closed-form tests. */
 void   orc_lattice(int c[19][3], double w[19]);
 double orc_peskin(double r);

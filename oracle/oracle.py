@@ -80,6 +80,8 @@ def lib():
         L.orc_num_wall_particles.argtypes = [ctypes.c_void_p]
         L.orc_wall_shear_stress.argtypes = [ctypes.c_void_p, _L, _D]
         L.orc_lattice.argtypes = [_I, _D]
+        L.orc_num_threads.restype = ctypes.c_int
+        L.orc_num_threads.argtypes = []
         L.orc_peskin.restype = ctypes.c_double
         L.orc_peskin.argtypes = [ctypes.c_double]
         L.orc_feq.restype = ctypes.c_double
@@ -249,6 +251,10 @@ def lattice():
     w = (ctypes.c_double * 19)()
     lib().orc_lattice(ctypes.cast(c, _I), ctypes.cast(w, _D))
     return np.array(list(c), dtype=np.int64).reshape(19, 3), np.array(list(w))
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 def peskin(r: float) -> float:

@@ -9,11 +9,12 @@ namespace lbrbc {
 
 // ---- spreading at one node (Sec. II B back-reaction G; Sec. II D, Eq. 23) -----------------
 // g = g_ext - sum_i [F_i dhat_i - 1/2 T_i x grad(dhat_i)], theta = sum_i [1 - (1 - raw_i)^kappa]
-// over the covering cells in ascending id order (fixed order: bitwise repeatable). The
-// torque term carries the sign that hands the plasma -T_i of angular momentum.
+// over the covering cells in ascending id order (a fixed order: bitwise repeatable). Each
+// coverage slot holds the cell id and (raw, grad raw) written by the per-cell pass; dhat =
+// raw / S_i. The torque term carries the sign that hands the plasma -T_i of angular momentum.
 template <typename RT>
-__device__ __forceinline__ void spread_at(int x, int y, int z, long long n, uint32_t w,
-                                          const int* __restrict__ ids,
+__device__ __forceinline__ void spread_at(unsigned n, uint32_t w, const int* __restrict__ ids,
+                                          const RT* __restrict__ vals,
                                           const Gather<RT>* __restrict__ gat, const KParams& kp,
                                           RT g[3], RT& theta)
 {
@@ -24,85 +25,66 @@ __device__ __forceinline__ void spread_at(int x, int y, int z, long long n, uint
     int cnt = (int)(w >> 24);
     if (cnt > kp.cap) cnt = kp.cap;
     if (cnt == 0) return;
-    int id[CAP_MAX];
+    // sort keys (id << 4 | slot) in registers: odd-even transposition with static indices
+    int key[CAP_MAX];
 #pragma unroll
-    for (int k = 0; k < CAP_MAX; ++k) id[k] = (k < cnt) ? ids[(long long)k * kp.ld + n] : INT_MAX;
-    // odd-even transposition sort (static indices keep the ids in registers)
+    for (int k = 0; k < CAP_MAX; ++k)
+        key[k] = (k < cnt) ? ((ids[(size_t)k * kp.ld + n] << 4) | k) : INT_MAX;
 #pragma unroll
     for (int r = 0; r < CAP_MAX; ++r) {
 #pragma unroll
         for (int k = (r & 1); k + 1 < CAP_MAX; k += 2) {
-            int a = min(id[k], id[k + 1]), b = max(id[k], id[k + 1]);
-            id[k] = a;
-            id[k + 1] = b;
+            const int a = min(key[k], key[k + 1]), b = max(key[k], key[k + 1]);
+            key[k] = a;
+            key[k + 1] = b;
         }
     }
-    const RT s0 = RT(2.0 / kp.xi[0]), s1 = RT(2.0 / kp.xi[1]), s2 = RT(2.0 / kp.xi[2]);
-    // an axis neighbour x +/- e_b that is solid has zero kernel: x + e_x is the pull source
-    // of direction 2 (c = -e_x), x - e_x of direction 1, and so on
-    const bool sxp = w & (1u << 2), sxm = w & (1u << 1), syp = w & (1u << 4),
-               sym = w & (1u << 3), szp = w & (1u << 6), szm = w & (1u << 5);
     for (int k = 0; k < cnt; ++k) {
-        const int i = id[0];
+        const int kk = key[0];
 #pragma unroll
-        for (int j = 0; j + 1 < CAP_MAX; ++j) id[j] = id[j + 1];
+        for (int j = 0; j + 1 < CAP_MAX; ++j) key[j] = key[j + 1];
+        const int i = kk >> 4, slot = kk & 15;
+        const RT* v = vals + 4 * ((size_t)slot * kp.ld + n);
+        const RT r0 = v[0], gx = v[1], gy = v[2], gz = v[3];
         const Gather<RT>& G = gat[i];
-        const RT dx = (RT)min_img((double)x - G.R[0], (double)kp.nx, kp.per[0]);
-        const RT dy = (RT)min_img((double)y - G.R[1], (double)kp.ny, kp.per[1]);
-        const RT dz = (RT)min_img((double)z - G.R[2], (double)kp.nz, kp.per[2]);
-        RT Q[9];
-#pragma unroll
-        for (int j = 0; j < 9; ++j) Q[j] = G.Q[j];
-        const RT y0 = Q[0] * dx + Q[3] * dy + Q[6] * dz;
-        const RT y1 = Q[1] * dx + Q[4] * dy + Q[7] * dz;
-        const RT y2 = Q[2] * dx + Q[5] * dy + Q[8] * dz;
-        auto raw = [&](RT a, RT b, RT c) { return peskin(a * s0) * peskin(b * s1) * peskin(c * s2); };
-        const RT r0 = raw(y0, y1, y2);
-        const RT rpx = sxp ? RT(0) : raw(y0 + Q[0], y1 + Q[1], y2 + Q[2]);
-        const RT rmx = sxm ? RT(0) : raw(y0 - Q[0], y1 - Q[1], y2 - Q[2]);
-        const RT rpy = syp ? RT(0) : raw(y0 + Q[3], y1 + Q[4], y2 + Q[5]);
-        const RT rmy = sym ? RT(0) : raw(y0 - Q[3], y1 - Q[4], y2 - Q[5]);
-        const RT rpz = szp ? RT(0) : raw(y0 + Q[6], y1 + Q[7], y2 + Q[8]);
-        const RT rmz = szm ? RT(0) : raw(y0 - Q[6], y1 - Q[7], y2 - Q[8]);
         const RT invS = G.invS;
         const RT dh = r0 * invS;
-        const RT gr0 = RT(0.5) * (rpx - rmx) * invS;
-        const RT gr1 = RT(0.5) * (rpy - rmy) * invS;
-        const RT gr2 = RT(0.5) * (rpz - rmz) * invS;
+        const RT gr0 = gx * invS, gr1 = gy * invS, gr2 = gz * invS;
         const RT T0 = G.T[0], T1 = G.T[1], T2 = G.T[2];
-        const RT tg0 = T1 * gr2 - T2 * gr1;
-        const RT tg1 = T2 * gr0 - T0 * gr2;
-        const RT tg2 = T0 * gr1 - T1 * gr0;
-        g[0] -= G.F[0] * dh - RT(0.5) * tg0;
-        g[1] -= G.F[1] * dh - RT(0.5) * tg1;
-        g[2] -= G.F[2] * dh - RT(0.5) * tg2;
+        g[0] -= G.F[0] * dh - RT(0.5) * (T1 * gr2 - T2 * gr1);
+        g[1] -= G.F[1] * dh - RT(0.5) * (T2 * gr0 - T0 * gr2);
+        g[2] -= G.F[2] * dh - RT(0.5) * (T0 * gr1 - T1 * gr0);
         theta += RT(1) - ipow_or_pow(RT(1) - r0, kp.kappa, kp.kappa_int);
     }
 }
 
 template <int P>
-__device__ __forceinline__ long long pull_src(int x, int y, int z, int xm, int xp, int ym, int yp,
-                                              int zm, int zp, const KParams& kp)
+__device__ __forceinline__ unsigned pull_src(int x, int y, int z, int xm, int xp, int ym, int yp,
+                                             int zm, int zp, const KParams& kp)
 {
     // source of direction P is x - c_P
     const int xs = cx_(P) == 1 ? xm : (cx_(P) == -1 ? xp : x);
     const int ys = cy_(P) == 1 ? ym : (cy_(P) == -1 ? yp : y);
     const int zs = cz_(P) == 1 ? zm : (cz_(P) == -1 ? zp : z);
-    return (long long)xs + (long long)kp.nx * ((long long)ys + (long long)kp.ny * zs);
+    return (unsigned)xs + (unsigned)kp.nx * ((unsigned)ys + (unsigned)kp.ny * (unsigned)zs);
 }
 
+// one population: a uniform plane base (scalar registers) plus a 32-bit per-lane offset;
+// the bounce-back source is the opposite population at the node itself
 template <typename ST, typename RT, int P>
-__device__ __forceinline__ void pull_one(RT* f, const ST* __restrict__ fin, long long n, uint32_t w,
+__device__ __forceinline__ void pull_one(RT* f, const ST* __restrict__ fin, unsigned n, uint32_t w,
                                          int x, int y, int z, int xm, int xp, int ym, int yp,
                                          int zm, int zp, const KParams& kp)
 {
     constexpr int O = opp_(P);
-    if (w & (1u << P)) f[P] = Store<ST, RT>::ld(fin, (long long)O * kp.ld + n, kp.f16_inv);
-    else f[P] = Store<ST, RT>::ld(fin, (long long)P * kp.ld + pull_src<P>(x, y, z, xm, xp, ym, yp, zm, zp, kp), kp.f16_inv);
+    const bool bb = w & (1u << P);
+    const ST* plane = fin + (size_t)(bb ? O : P) * (size_t)kp.ld;
+    const unsigned off = bb ? n : pull_src<P>(x, y, z, xm, xp, ym, yp, zm, zp, kp);
+    f[P] = Store<ST, RT>::ld(plane, off, kp.f16_inv);
 }
 
 template <typename ST, typename RT, int... Ps>
-__device__ __forceinline__ void pull_all(RT* f, const ST* __restrict__ fin, long long n, uint32_t w,
+__device__ __forceinline__ void pull_all(RT* f, const ST* __restrict__ fin, unsigned n, uint32_t w,
                                          int x, int y, int z, int xm, int xp, int ym, int yp,
                                          int zm, int zp, const KParams& kp,
                                          std::integer_sequence<int, Ps...>)
@@ -120,20 +102,21 @@ __device__ __forceinline__ RT feq_shift(int p, RT drho, RT rho, RT ux, RT uy, RT
 
 // ---- fused spreading + stream + collide (Sec. II A, Eqs. 1-8) -----------------------------
 // One thread per node; SoA planes f[p*ld + n] of the shifted populations f - w.
+// Launch: blocks of 64 x 4 threads (a wavefront spans 64 consecutive x), grid
+// (ceil(nx/64), ceil(ny/4), nz): no integer division, 32-bit node offsets.
 template <typename ST, typename RT>
 __global__ __launch_bounds__(256) void k_stream_collide(
     const ST* __restrict__ fin, ST* __restrict__ fout, const uint32_t* __restrict__ nodeword,
-    const int* __restrict__ ids, const Gather<RT>* __restrict__ gat, RT* __restrict__ uout,
-    RT* __restrict__ sout, KParams kp, unsigned* __restrict__ err)
+    const int* __restrict__ ids, const RT* __restrict__ vals, const Gather<RT>* __restrict__ gat,
+    RT* __restrict__ uout, RT* __restrict__ sout, KParams kp, unsigned* __restrict__ err)
 {
-    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= kp.N) return;
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= kp.nx || y >= kp.ny) return;
+    const unsigned n = (unsigned)x + (unsigned)kp.nx * ((unsigned)y + (unsigned)kp.ny * (unsigned)z);
     const uint32_t w = nodeword[n];
     if (!(w & NW_FLUID) || (w & NW_OPEN)) return;
-    const int x = (int)(n % kp.nx);
-    const long long yz = n / kp.nx;
-    const int y = (int)(yz % kp.ny);
-    const int z = (int)(yz / kp.ny);
     const int xm = x == 0 ? kp.nx - 1 : x - 1, xp = x == kp.nx - 1 ? 0 : x + 1;
     const int ym = y == 0 ? kp.ny - 1 : y - 1, yp = y == kp.ny - 1 ? 0 : y + 1;
     const int zm = z == 0 ? kp.nz - 1 : z - 1, zp = z == kp.nz - 1 ? 0 : z + 1;
@@ -143,7 +126,7 @@ __global__ __launch_bounds__(256) void k_stream_collide(
                      std::make_integer_sequence<int, 19>{});
 
     RT g[3], theta;
-    spread_at<RT>(x, y, z, n, w, ids, gat, kp, g, theta);
+    spread_at<RT>(n, w, ids, vals, gat, kp, g, theta);
 
     RT drho = RT(0), mx = RT(0), my = RT(0), mz = RT(0);
 #pragma unroll
@@ -173,7 +156,7 @@ __global__ __launch_bounds__(256) void k_stream_collide(
         const RT gc = RT(cx_(p)) * g[0] + RT(cy_(p)) * g[1] + RT(cz_(p)) * g[2];
         const RT uc = RT(cx_(p)) * ux + RT(cy_(p)) * uy + RT(cz_(p)) * uz;
         const RT Fp = kf * RT(w_(p)) * (RT(3) * gc + k2 * gc * uc - k3 * gu);
-        Store<ST, RT>::st(fout, (long long)p * kp.ld + n, f[p] - om * neq + Fp, kp.f16_scale);
+        Store<ST, RT>::st(fout + (size_t)p * (size_t)kp.ld, n, f[p] - om * neq + Fp, kp.f16_scale);
         if (cx_(p) * cx_(p)) sxx += neq;
         if (cy_(p) * cy_(p)) syy += neq;
         if (cz_(p) * cz_(p)) szz += neq;
@@ -183,15 +166,16 @@ __global__ __launch_bounds__(256) void k_stream_collide(
     }
     // stress of the non-equilibrium part: sigma = -(1 - 1/(2T)) sum c c (f - f^eq)
     const RT ks = -(RT(1) - RT(0.5) * om);
+    const size_t ld = (size_t)kp.ld;
     __builtin_nontemporal_store(ux, uout + n);
-    __builtin_nontemporal_store(uy, uout + kp.ld + n);
-    __builtin_nontemporal_store(uz, uout + 2 * kp.ld + n);
+    __builtin_nontemporal_store(uy, (uout + ld) + n);
+    __builtin_nontemporal_store(uz, (uout + 2 * ld) + n);
     __builtin_nontemporal_store(ks * sxx, sout + n);
-    __builtin_nontemporal_store(ks * syy, sout + kp.ld + n);
-    __builtin_nontemporal_store(ks * szz, sout + 2 * kp.ld + n);
-    __builtin_nontemporal_store(ks * sxy, sout + 3 * kp.ld + n);
-    __builtin_nontemporal_store(ks * sxz, sout + 4 * kp.ld + n);
-    __builtin_nontemporal_store(ks * syz, sout + 5 * kp.ld + n);
+    __builtin_nontemporal_store(ks * syy, (sout + ld) + n);
+    __builtin_nontemporal_store(ks * szz, (sout + 2 * ld) + n);
+    __builtin_nontemporal_store(ks * sxy, (sout + 3 * ld) + n);
+    __builtin_nontemporal_store(ks * sxz, (sout + 4 * ld) + n);
+    __builtin_nontemporal_store(ks * syz, (sout + 5 * ld) + n);
     if (!(rho > RT(0)) || !(usq <= RT(0.09))) atomicOr(err, ERR_UNSTABLE);
 }
 
@@ -200,7 +184,8 @@ template <typename ST, typename RT>
 __global__ __launch_bounds__(256) void k_open_bc(
     const ST* __restrict__ fin, ST* __restrict__ fout, const uint32_t* __restrict__ nodeword,
     const long long* __restrict__ plane_nodes, int nplane, const int* __restrict__ ids,
-    const Gather<RT>* __restrict__ gat, RT* __restrict__ uout, RT* __restrict__ sout, KParams kp)
+    const RT* __restrict__ vals, const Gather<RT>* __restrict__ gat, RT* __restrict__ uout,
+    RT* __restrict__ sout, KParams kp)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nplane) return;
@@ -215,7 +200,7 @@ __global__ __launch_bounds__(256) void k_open_bc(
     const uint32_t wi = nodeword[ni];
     const RT rb = z == 0 ? (RT)kp.rho_in : (RT)kp.rho_out;
     RT gb[3], thb;
-    spread_at<RT>(x, y, z, n, w, ids, gat, kp, gb, thb);
+    spread_at<RT>((unsigned)n, w, ids, vals, gat, kp, gb, thb);
     const RT om = RT(1) / ((RT)kp.tau0 + (RT)kp.delta * thb);
 #pragma unroll
     for (int a = 0; a < 6; ++a) sout[(long long)a * kp.ld + n] = RT(0);
@@ -229,10 +214,10 @@ __global__ __launch_bounds__(256) void k_open_bc(
     const int ym = y == 0 ? kp.ny - 1 : y - 1, yp = y == kp.ny - 1 ? 0 : y + 1;
     const int zm = zi - 1, zp = zi + 1;
     RT f[19];
-    pull_all<ST, RT>(f, fin, ni, wi, x, y, zi, xm, xp, ym, yp, zm, zp, kp,
+    pull_all<ST, RT>(f, fin, (unsigned)ni, wi, x, y, zi, xm, xp, ym, yp, zm, zp, kp,
                      std::make_integer_sequence<int, 19>{});
     RT gi[3], thi;
-    spread_at<RT>(x, y, zi, ni, wi, ids, gat, kp, gi, thi);
+    spread_at<RT>((unsigned)ni, wi, ids, vals, gat, kp, gi, thi);
     RT drho = 0, mx = 0, my = 0, mz = 0;
     for (int p = 0; p < 19; ++p) {
         drho += f[p];
@@ -258,6 +243,7 @@ __global__ __launch_bounds__(256) void k_open_bc(
 template <typename RT>
 __global__ __launch_bounds__(256) void k_spread_field(const uint32_t* __restrict__ nodeword,
                                                       const int* __restrict__ ids,
+                                                      const RT* __restrict__ vals,
                                                       const Gather<RT>* __restrict__ gat,
                                                       RT* __restrict__ gout, RT* __restrict__ tout,
                                                       KParams kp)
@@ -270,12 +256,8 @@ __global__ __launch_bounds__(256) void k_spread_field(const uint32_t* __restrict
         tout[n] = (RT)kp.tau0;
         return;
     }
-    const int x = (int)(n % kp.nx);
-    const long long yz = n / kp.nx;
-    const int y = (int)(yz % kp.ny);
-    const int z = (int)(yz / kp.ny);
     RT g[3], th;
-    spread_at<RT>(x, y, z, n, w, ids, gat, kp, g, th);
+    spread_at<RT>((unsigned)n, w, ids, vals, gat, kp, g, th);
     gout[n] = g[0];
     gout[kp.ld + n] = g[1];
     gout[2 * kp.ld + n] = g[2];
@@ -368,33 +350,33 @@ __global__ __launch_bounds__(256) void k_wss(const RT* __restrict__ sig,
 // ---- launchers ---------------------------------------------------------------------------------
 template <typename ST, typename RT>
 void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword, const int* ids,
-                           const void* gat, void* u, void* sig, const KParams& kp, unsigned* err,
-                           hipStream_t st)
+                           const void* vals, const void* gat, void* u, void* sig,
+                           const KParams& kp, unsigned* err, hipStream_t st)
 {
-    const unsigned blocks = (unsigned)((kp.N + 255) / 256);
-    hipLaunchKernelGGL((k_stream_collide<ST, RT>), dim3(blocks), dim3(256), 0, st,
-                       (const ST*)fin, (ST*)fout, nodeword, ids, (const Gather<RT>*)gat, (RT*)u,
+    const dim3 grid((unsigned)((kp.nx + 63) / 64), (unsigned)((kp.ny + 3) / 4), (unsigned)kp.nz);
+    hipLaunchKernelGGL((k_stream_collide<ST, RT>), grid, dim3(64, 4, 1), 0, st, (const ST*)fin,
+                       (ST*)fout, nodeword, ids, (const RT*)vals, (const Gather<RT>*)gat, (RT*)u,
                        (RT*)sig, kp, err);
 }
 
 template <typename ST, typename RT>
 void launch_open_bc(const void* fin, void* fout, const uint32_t* nodeword, const long long* planes,
-                    int nplane, const int* ids, const void* gat, void* u, void* sig,
-                    const KParams& kp, hipStream_t st)
+                    int nplane, const int* ids, const void* vals, const void* gat, void* u,
+                    void* sig, const KParams& kp, hipStream_t st)
 {
     if (nplane <= 0) return;
     hipLaunchKernelGGL((k_open_bc<ST, RT>), dim3((nplane + 255) / 256), dim3(256), 0, st,
-                       (const ST*)fin, (ST*)fout, nodeword, planes, nplane, ids,
+                       (const ST*)fin, (ST*)fout, nodeword, planes, nplane, ids, (const RT*)vals,
                        (const Gather<RT>*)gat, (RT*)u, (RT*)sig, kp);
 }
 
 template <typename RT>
-void launch_spread_field(const uint32_t* nodeword, const int* ids, const void* gat, void* g,
-                         void* t, const KParams& kp, hipStream_t st)
+void launch_spread_field(const uint32_t* nodeword, const int* ids, const void* vals,
+                         const void* gat, void* g, void* t, const KParams& kp, hipStream_t st)
 {
     const unsigned blocks = (unsigned)((kp.N + 255) / 256);
     hipLaunchKernelGGL((k_spread_field<RT>), dim3(blocks), dim3(256), 0, st, nodeword, ids,
-                       (const Gather<RT>*)gat, (RT*)g, (RT*)t, kp);
+                       (const RT*)vals, (const Gather<RT>*)gat, (RT*)g, (RT*)t, kp);
 }
 
 void launch_clear_counts(uint32_t* nodeword, long long N, hipStream_t st)
@@ -423,10 +405,10 @@ void launch_wss(const void* sig, const long long* wn_node, const double* wn_nrm,
 
 #define INST_ST(ST, RT)                                                                           \
     template void launch_stream_collide<ST, RT>(const void*, void*, const uint32_t*, const int*,  \
-                                                const void*, void*, void*, const KParams&,        \
-                                                unsigned*, hipStream_t);                          \
+                                                const void*, const void*, void*, void*,           \
+                                                const KParams&, unsigned*, hipStream_t);          \
     template void launch_open_bc<ST, RT>(const void*, void*, const uint32_t*, const long long*,   \
-                                         int, const int*, const void*, void*, void*,              \
+                                         int, const int*, const void*, const void*, void*, void*, \
                                          const KParams&, hipStream_t);                            \
     template void launch_observe<ST, RT>(const void*, const uint32_t*, const void*,               \
                                          const KParams&, double*, int, double*, hipStream_t);
@@ -434,10 +416,10 @@ INST_ST(double, double)
 INST_ST(float, float)
 INST_ST(bf16_t, float)
 INST_ST(_Float16, float)
-template void launch_spread_field<double>(const uint32_t*, const int*, const void*, void*, void*,
-                                          const KParams&, hipStream_t);
-template void launch_spread_field<float>(const uint32_t*, const int*, const void*, void*, void*,
-                                         const KParams&, hipStream_t);
+template void launch_spread_field<double>(const uint32_t*, const int*, const void*, const void*,
+                                          void*, void*, const KParams&, hipStream_t);
+template void launch_spread_field<float>(const uint32_t*, const int*, const void*, const void*,
+                                         void*, void*, const KParams&, hipStream_t);
 template void launch_wss<double>(const void*, const long long*, const double*, int,
                                  const KParams&, double*, double*, int, hipStream_t);
 template void launch_wss<float>(const void*, const long long*, const double*, int,

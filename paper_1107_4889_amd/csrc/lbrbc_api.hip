@@ -58,6 +58,7 @@ std::string validate(const lb_config& c, int n_rbc)
     if (c.open_z && c.periodic[2]) return "open z faces need a non-periodic z axis";
     if (c.open_z && c.nz < 3) return "open z faces need nz >= 3";
     if (n_rbc < 0) return "negative cell count";
+    if (n_rbc >= (1 << 27)) return "at most 2^27 - 1 cells (coverage sort keys)";
     if (n_rbc > 0) {
         if (!(c.mass > 0) || !(c.inertia[0] > 0) || !(c.inertia[1] > 0) || !(c.inertia[2] > 0))
             return "mass and inertia must be positive";
@@ -167,7 +168,7 @@ std::string build_geometry(const lb_config& c, const uint8_t* solid, int n_rbc, 
 
 // ---- arena layout --------------------------------------------------------------------------
 struct Layout {
-    size_t fA, fB, u, sig, gdbg, tdbg, nodeword, map_ids, st, cp, gat, cellid, cell_cnt, cell_off,
+    size_t fA, fB, u, sig, gdbg, tdbg, nodeword, map_ids, map_vals, st, cp, gat, cellid, cell_cnt, cell_off,
         cell_ids, wall_xyz, wcell_off, wcell_ids, wn_node, wn_nrm, wss, wss_acc, planes, partials,
         obs_out, err, total;
 };
@@ -194,6 +195,7 @@ Layout layout(const lb_config& c, const Geometry& g, int n_rbc)
     L.tdbg = take(ld * rs);
     L.nodeword = take(ld * 4);
     L.map_ids = take(n_rbc > 0 ? (size_t)cap * ld * 4 : 4);
+    L.map_vals = take(n_rbc > 0 ? (size_t)cap * ld * 4 * rs : 4);
     L.st = take(n_rbc * sizeof(RbcState));
     L.cp = take(n_rbc * sizeof(RbcCouple));
     L.gat = take(n_rbc * (rs == 8 ? sizeof(Gather<double>) : sizeof(Gather<float>)));
@@ -344,12 +346,14 @@ lb_status check_fault(lb_ctx c)
     return LB_OK;
 }
 
-void enqueue_cells_and_map(lb_ctx c)
+// cell list, coverage map and interpolation onto the cells (one pass per cell)
+template <typename RT>
+void enqueue_cells_map_couple(lb_ctx c)
 {
     hipStream_t s = c->stream;
     launch_cell_list(c->cb, c->kp, s);
     launch_clear_counts(c->cb.nodeword, c->kp.N, s);
-    launch_map_fill(c->cb, c->kp, s);
+    launch_map_couple<RT>(c->cb, c->kp, s);
 }
 
 void enqueue_step(lb_ctx c)
@@ -363,8 +367,7 @@ void enqueue_step(lb_ctx c)
         using RT = std::remove_pointer_t<decltype(rp)>;
         if (c->nrbc > 0) {
             launch_rb_first_half(c->cb, kp, s);
-            enqueue_cells_and_map(c);
-            launch_couple<RT>(c->cb, kp, s);
+            enqueue_cells_map_couple<RT>(c);
             launch_gay_berne(c->cb, kp, s);
             launch_rb_second_half<RT>(c->cb, kp, 1, s);
         }
@@ -376,15 +379,16 @@ void enqueue_step(lb_ctx c)
             c->ev_pool.pop_back();
             (void)hipEventRecord(e0, s);
         }
-        launch_stream_collide<ST, RT>(c->fA, c->fB, c->cb.nodeword, c->cb.map_ids, c->cb.gat,
-                                      c->at<void>(c->lay.u), c->at<void>(c->lay.sig), kp, c->cb.err, s);
+        launch_stream_collide<ST, RT>(c->fA, c->fB, c->cb.nodeword, c->cb.map_ids, c->cb.map_vals,
+                                      c->cb.gat, c->at<void>(c->lay.u), c->at<void>(c->lay.sig), kp,
+                                      c->cb.err, s);
         if (e0) {
             (void)hipEventRecord(e1, s);
             c->sc_pairs.emplace_back(e0, e1);
         }
         if (!c->geo.planes.empty())
             launch_open_bc<ST, RT>(c->fA, c->fB, c->cb.nodeword, c->at<long long>(c->lay.planes),
-                                   (int)c->geo.planes.size(), c->cb.map_ids, c->cb.gat,
+                                   (int)c->geo.planes.size(), c->cb.map_ids, c->cb.map_vals, c->cb.gat,
                                    c->at<void>(c->lay.u), c->at<void>(c->lay.sig), kp, s);
         if (c->wss_on)
             launch_wss<RT>(c->at<void>(c->lay.sig), c->at<long long>(c->lay.wn_node),
@@ -458,6 +462,13 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
     kp.f16_inv = 1.0f / kp.f16_scale;
     kp.nrbc = n_rbc;
     kp.rc = g.rc;
+    {
+        const double amax = std::max(C.axes[0], std::max(C.axes[1], C.axes[2]));
+        const double amin = std::min(C.axes[0], std::min(C.axes[1], C.axes[2]));
+        const double shift = std::pow(2.0, 1.0 / 6.0) - 1.0;
+        kp.rc_pair = std::sqrt(4.0 * amax * amax) + shift * std::sqrt(4.0 * amin * amin);
+        kp.rc_wall = std::sqrt(2.0 * (amax * amax + C.a_wall * C.a_wall)) + shift * C.sigmin_wall;
+    }
     kp.tile_max = g.tile_max;
 
     const Layout& L = c->lay;
@@ -476,6 +487,7 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
     b.wcell_ids = c->at<int>(L.wcell_ids);
     b.nodeword = c->at<uint32_t>(L.nodeword);
     b.map_ids = c->at<int>(L.map_ids);
+    b.map_vals = c->at<void>(L.map_vals);
     b.u = c->at<void>(L.u);
     b.sig = c->at<void>(L.sig);
     b.err = c->at<unsigned>(L.err);
@@ -569,18 +581,14 @@ lb_status lb_batch_step(lb_ctx* ctxs, const int* nsteps, int n)
 lb_status rbc_couple(lb_ctx c)
 {
     if (!c) return LB_EINVAL;
-    if (c->nrbc > 0) {
-        enqueue_cells_and_map(c);
-        with_types(c->cfg.storage, [&](auto*, auto* rp) {
-            using RT = std::remove_pointer_t<decltype(rp)>;
-            launch_couple<RT>(c->cb, c->kp, c->stream);
-            launch_rb_second_half<RT>(c->cb, c->kp, 0, c->stream);
-        });
-    }
     with_types(c->cfg.storage, [&](auto*, auto* rp) {
         using RT = std::remove_pointer_t<decltype(rp)>;
-        launch_spread_field<RT>(c->cb.nodeword, c->cb.map_ids, c->cb.gat, c->at<void>(c->lay.gdbg),
-                                c->at<void>(c->lay.tdbg), c->kp, c->stream);
+        if (c->nrbc > 0) {
+            enqueue_cells_map_couple<RT>(c);
+            launch_rb_second_half<RT>(c->cb, c->kp, 0, c->stream);
+        }
+        launch_spread_field<RT>(c->cb.nodeword, c->cb.map_ids, c->cb.map_vals, c->cb.gat,
+                                c->at<void>(c->lay.gdbg), c->at<void>(c->lay.tdbg), c->kp, c->stream);
     });
     HIPCHK(c, hipGetLastError());
     return LB_OK;

@@ -63,7 +63,9 @@ struct KParams {
     int nrbc;
     int ncell[3];
     double cedge[3];
-    double rc;
+    double rc;        // cell-list cut-off (bounds every pair kind)
+    double rc_pair;   // cell-cell Gay-Berne cut-off bound
+    double rc_wall;   // cell-wall Gay-Berne cut-off bound
     int tile_max;     // LDS tile edge bound
 };
 
@@ -78,14 +80,12 @@ struct RbcCouple {       // interpolation results and forces
     double Fm[3], Tm[3];     // Gay-Berne force (lab), torque (body)
     double Fh[3], Th[3];     // hydrodynamic force / torque (lab)
 };
-// Gather record read by the per-node spreading: centre in FP64, the rest in the compute
-// precision. 96 B (float) / 160 B (double).
+// Record read by the per-node spreading: hydrodynamic force and torque (lab) and 1/S in
+// the compute precision (32 B for float, 64 B for double).
 template <typename RT>
 struct alignas(16) Gather {
-    double R[3];
-    RT Q[9];
-    RT invS;
     RT F[3];
+    RT invS;
     RT T[3];
     RT pad;
 };

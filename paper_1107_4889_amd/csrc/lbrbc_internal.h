@@ -13,15 +13,15 @@ namespace lbrbc {
 // per-node kernels (lb_kernels.hip)
 template <typename ST, typename RT>
 void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword, const int* ids,
-                           const void* gat, void* u, void* sig, const KParams& kp, unsigned* err,
-                           hipStream_t st);
+                           const void* vals, const void* gat, void* u, void* sig,
+                           const KParams& kp, unsigned* err, hipStream_t st);
 template <typename ST, typename RT>
 void launch_open_bc(const void* fin, void* fout, const uint32_t* nodeword, const long long* planes,
-                    int nplane, const int* ids, const void* gat, void* u, void* sig,
-                    const KParams& kp, hipStream_t st);
+                    int nplane, const int* ids, const void* vals, const void* gat, void* u,
+                    void* sig, const KParams& kp, hipStream_t st);
 template <typename RT>
-void launch_spread_field(const uint32_t* nodeword, const int* ids, const void* gat, void* g,
-                         void* t, const KParams& kp, hipStream_t st);
+void launch_spread_field(const uint32_t* nodeword, const int* ids, const void* vals,
+                         const void* gat, void* g, void* t, const KParams& kp, hipStream_t st);
 void launch_clear_counts(uint32_t* nodeword, long long N, hipStream_t st);
 template <typename ST, typename RT>
 void launch_observe(const void* f, const uint32_t* nodeword, const void* u, const KParams& kp,
@@ -43,7 +43,8 @@ struct CellBuffers {
     const int* wcell_off; // [ncells + 1]
     const int* wcell_ids; // [nwall]
     uint32_t* nodeword;
-    int* map_ids;         // [cap * ld]
+    int* map_ids;         // [cap * ld] cell id per coverage slot
+    void* map_vals;       // [cap * ld * 4] RT: raw kernel and its gradient per slot
     const void* u;        // [3 * ld] RT
     const void* sig;      // [6 * ld] RT
     unsigned* err;
@@ -51,9 +52,8 @@ struct CellBuffers {
 
 void launch_rb_first_half(const CellBuffers& b, const KParams& kp, hipStream_t st);
 void launch_cell_list(const CellBuffers& b, const KParams& kp, hipStream_t st);
-void launch_map_fill(const CellBuffers& b, const KParams& kp, hipStream_t st);
 template <typename RT>
-void launch_couple(const CellBuffers& b, const KParams& kp, hipStream_t st);
+void launch_map_couple(const CellBuffers& b, const KParams& kp, hipStream_t st);
 void launch_gay_berne(const CellBuffers& b, const KParams& kp, hipStream_t st);
 template <typename RT>
 void launch_rb_second_half(const CellBuffers& b, const KParams& kp, int integrate, hipStream_t st);

@@ -174,75 +174,35 @@ __device__ __forceinline__ void support_tile(const RbcState& s, const KParams& k
     }
 }
 
-// node index of tile position (unwrapped X); -1 outside a non-periodic face
-__device__ __forceinline__ long long tile_node(const KParams& kp, int X, int Y, int Z, int& xw,
-                                               int& yw, int& zw)
+// wrap a tile coordinate into the box (a tile is never longer than a periodic axis);
+// returns false outside a non-periodic face
+__device__ __forceinline__ bool wrap_coord(int& X, int L, int per)
 {
-    if (X < 0 || X >= kp.nx) { if (!kp.per[0]) return -1; X = ((X % kp.nx) + kp.nx) % kp.nx; }
-    if (Y < 0 || Y >= kp.ny) { if (!kp.per[1]) return -1; Y = ((Y % kp.ny) + kp.ny) % kp.ny; }
-    if (Z < 0 || Z >= kp.nz) { if (!kp.per[2]) return -1; Z = ((Z % kp.nz) + kp.nz) % kp.nz; }
-    xw = X;
-    yw = Y;
-    zw = Z;
-    return (long long)X + (long long)kp.nx * ((long long)Y + (long long)kp.ny * Z);
+    if (X < 0) {
+        if (!per) return false;
+        X += L;
+    } else if (X >= L) {
+        if (!per) return false;
+        X -= L;
+    }
+    return true;
 }
 
-__device__ __forceinline__ void body_of_node(const RbcState& s, const KParams& kp, int xw, int yw,
-                                             int zw, double y[3])
+__device__ __forceinline__ unsigned node_of(const KParams& kp, int X, int Y, int Z)
 {
-    const double d0 = min_img((double)xw - s.R[0], (double)kp.nx, kp.per[0]);
-    const double d1 = min_img((double)yw - s.R[1], (double)kp.ny, kp.per[1]);
-    const double d2 = min_img((double)zw - s.R[2], (double)kp.nz, kp.per[2]);
-    body_coords_exact(s.Q, d0, d1, d2, y);
+    return (unsigned)X + (unsigned)kp.nx * ((unsigned)Y + (unsigned)kp.ny * (unsigned)Z);
 }
 
-// ---- S3: node -> cell coverage map ---------------------------------------------------------
-// covered(x, i) <=> x fluid and (x, or a fluid axis neighbour of x, inside the support of i)
-__global__ __launch_bounds__(256) void k_map_fill(const RbcState* __restrict__ st,
-                                                  uint32_t* __restrict__ nodeword, int* __restrict__ ids,
-                                                  KParams kp, unsigned* err)
+// block index -> position in the spatially sorted cell order, so that each XCD (blocks are
+// dealt to the eight XCDs round-robin) works on one contiguous, spatially compact chunk and
+// its L2 keeps the shared lattice lines; the grid is a multiple of 8 blocks
+__device__ __forceinline__ int xcd_chunk_index(int units_per_block)
 {
-    extern __shared__ unsigned char flag[];
-    __shared__ Tile T;
-    const int i = blockIdx.x;
-    const RbcState& s = st[i];
-    if (threadIdx.x == 0) support_tile(s, kp, T);
-    __syncthreads();
-    if (T.sz[0] > kp.tile_max || T.sz[1] > kp.tile_max || T.sz[2] > kp.tile_max) {
-        if (threadIdx.x == 0) atomicOr(err, ERR_CAPACITY);
-        return;
-    }
-    const int sx = T.sz[0], sy = T.sz[1], total = T.sz[0] * T.sz[1] * T.sz[2];
-    for (int t = threadIdx.x; t < total; t += blockDim.x) {
-        const int tx = t % sx, ty = (t / sx) % sy, tz = t / (sx * sy);
-        int xw, yw, zw;
-        const long long n = tile_node(kp, T.lo[0] + tx, T.lo[1] + ty, T.lo[2] + tz, xw, yw, zw);
-        unsigned char in = 0;
-        if (n >= 0 && (nodeword[n] & NW_FLUID)) {
-            double y[3];
-            body_of_node(s, kp, xw, yw, zw, y);
-            in = fabs(y[0]) < kp.xi[0] && fabs(y[1]) < kp.xi[1] && fabs(y[2]) < kp.xi[2];
-        }
-        flag[t] = in;
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < total; t += blockDim.x) {
-        const int tx = t % sx, ty = (t / sx) % sy, tz = t / (sx * sy);
-        int xw, yw, zw;
-        const long long n = tile_node(kp, T.lo[0] + tx, T.lo[1] + ty, T.lo[2] + tz, xw, yw, zw);
-        if (n < 0 || !(nodeword[n] & NW_FLUID)) continue;
-        const bool cov = flag[t] || (tx > 0 && flag[t - 1]) || (tx < sx - 1 && flag[t + 1]) ||
-                         (ty > 0 && flag[t - sx]) || (ty < sy - 1 && flag[t + sx]) ||
-                         (tz > 0 && flag[t - sx * sy]) || (tz < T.sz[2] - 1 && flag[t + sx * sy]);
-        if (!cov) continue;
-        const uint32_t old = atomicAdd(nodeword + n, NW_CNT_ONE);
-        const int slot = (int)(old >> 24);
-        if (slot < kp.cap) ids[(long long)slot * kp.ld + n] = i;
-        else atomicOr(err, ERR_CAPACITY);
-    }
+    const int per = gridDim.x / 8;
+    const int blk = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    return blk * units_per_block;
 }
 
-// ---- S4: interpolation onto each cell (Eqs. 16-21) ------------------------------------------
 template <typename RT>
 __device__ __forceinline__ RT block_sum(RT v, RT* red)
 {
@@ -252,100 +212,158 @@ __device__ __forceinline__ RT block_sum(RT v, RT* red)
     __syncthreads();
     if (lane == 0) red[wv] = v;
     __syncthreads();
-    RT r = red[0] + red[1] + red[2] + red[3];
-    return r;
+    return red[0] + red[1] + red[2] + red[3];
 }
 
+// ---- S3 + S4: coverage map and interpolation, one block per cell ------------------------
+// Pass 1 over the support tile: exact FP64 support test and the unnormalised kernel raw(x)
+// on fluid nodes; S = sum raw. Pass 2: every covered node (fluid, and inside or next to an
+// inside node) takes a coverage slot and stores (cell id; raw, grad raw by central
+// differences), which the per-node spreading reads; every inside node adds to
+// u~ = sum dhat u, w~ = sum dhat curl u, T^S = alpha sum dhat (sigma . n^) x (x - R),
+// with dhat = raw / S and n^ = grad dhat / |grad dhat| (Eqs. 16-21).
 template <typename RT>
-__device__ __forceinline__ RT u_node(const RT* __restrict__ u, const uint32_t* __restrict__ nw,
-                                     const KParams& kp, int X, int Y, int Z, int a)
-{
-    int xw, yw, zw;
-    const long long n = tile_node(kp, X, Y, Z, xw, yw, zw);
-    if (n < 0 || !(nw[n] & NW_FLUID)) return RT(0);
-    return u[(long long)a * kp.ld + n];
-}
-
-template <typename RT>
-__global__ __launch_bounds__(256) void k_couple(const RbcState* __restrict__ st,
-                                                RbcCouple* __restrict__ cp,
-                                                const uint32_t* __restrict__ nodeword,
-                                                const RT* __restrict__ u, const RT* __restrict__ sig,
-                                                KParams kp, unsigned* err)
+__global__ __launch_bounds__(256) void k_map_couple(const RbcState* __restrict__ st,
+                                                    RbcCouple* __restrict__ cp,
+                                                    uint32_t* __restrict__ nodeword,
+                                                    int* __restrict__ ids, RT* __restrict__ vals,
+                                                    const int* __restrict__ order,
+                                                    const RT* __restrict__ u,
+                                                    const RT* __restrict__ sig, KParams kp,
+                                                    unsigned* __restrict__ err)
 {
     extern __shared__ unsigned char smem[];
+    const int tm = kp.tile_max;
     RT* raw = reinterpret_cast<RT*>(smem);
+    unsigned char* flag = smem + (size_t)tm * tm * tm * sizeof(RT);  // 1 inside, 2 fluid
     __shared__ Tile T;
     __shared__ RT red[4];
-    const int i = blockIdx.x;
+    const int k = xcd_chunk_index(1);
+    if (k >= kp.nrbc) return;
+    const int i = order[k];
     const RbcState& s = st[i];
     if (threadIdx.x == 0) support_tile(s, kp, T);
     __syncthreads();
-    if (T.sz[0] > kp.tile_max || T.sz[1] > kp.tile_max || T.sz[2] > kp.tile_max) {
+    if (T.sz[0] > tm || T.sz[1] > tm || T.sz[2] > tm) {
         if (threadIdx.x == 0) atomicOr(err, ERR_CAPACITY);
         return;
     }
-    const int sx = T.sz[0], sy = T.sz[1], sxy = sx * sy, total = sxy * T.sz[2];
+    const int sx = T.sz[0], sy = T.sz[1], sz = T.sz[2], sxy = sx * sy;
+    const int tx0 = threadIdx.x & 15, ty0 = threadIdx.x >> 4;
     const RT s0 = RT(2.0 / kp.xi[0]), s1 = RT(2.0 / kp.xi[1]), s2 = RT(2.0 / kp.xi[2]);
     RT part = RT(0);
-    for (int t = threadIdx.x; t < total; t += blockDim.x) {
-        const int tx = t % sx, ty = (t / sx) % sy, tz = t / sxy;
-        int xw, yw, zw;
-        const long long n = tile_node(kp, T.lo[0] + tx, T.lo[1] + ty, T.lo[2] + tz, xw, yw, zw);
-        RT r = RT(0);
-        if (n >= 0 && (nodeword[n] & NW_FLUID)) {
-            double y[3];
-            body_of_node(s, kp, xw, yw, zw, y);
-            r = peskin((RT)y[0] * s0) * peskin((RT)y[1] * s1) * peskin((RT)y[2] * s2);
+    for (int tz = 0; tz < sz; ++tz) {
+        int Z = T.lo[2] + tz;
+        const bool okz = wrap_coord(Z, kp.nz, kp.per[2]);
+        for (int ty = ty0; ty < sy; ty += 16) {
+            int Y = T.lo[1] + ty;
+            const bool oky = okz && wrap_coord(Y, kp.ny, kp.per[1]);
+            for (int tx = tx0; tx < sx; tx += 16) {
+                int X = T.lo[0] + tx;
+                const bool ok = oky && wrap_coord(X, kp.nx, kp.per[0]);
+                const int t = tx + sx * (ty + sy * tz);
+                unsigned char fl = 0;
+                RT r = RT(0);
+                if (ok && (nodeword[node_of(kp, X, Y, Z)] & NW_FLUID)) {
+                    fl = 2;
+                    double y[3];
+                    const double d0 = min_img((double)X - s.R[0], (double)kp.nx, kp.per[0]);
+                    const double d1 = min_img((double)Y - s.R[1], (double)kp.ny, kp.per[1]);
+                    const double d2 = min_img((double)Z - s.R[2], (double)kp.nz, kp.per[2]);
+                    body_coords_exact(s.Q, d0, d1, d2, y);
+                    if (fabs(y[0]) < kp.xi[0] && fabs(y[1]) < kp.xi[1] && fabs(y[2]) < kp.xi[2]) {
+                        fl = 3;
+                        r = peskin((RT)y[0] * s0) * peskin((RT)y[1] * s1) * peskin((RT)y[2] * s2);
+                    }
+                }
+                raw[t] = r;
+                flag[t] = fl;
+                part += r;
+            }
         }
-        raw[t] = r;
-        part += r;
     }
     const RT S = block_sum(part, red);
     __syncthreads();
     const RT invS = S > RT(0) ? RT(1) / S : RT(0);
     RT acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int t = threadIdx.x; t < total; t += blockDim.x) {
-        const RT r = raw[t];
-        if (!(r > RT(0))) continue;
-        const int tx = t % sx, ty = (t / sx) % sy, tz = t / sxy;
-        const int X = T.lo[0] + tx, Y = T.lo[1] + ty, Z = T.lo[2] + tz;
-        int xw, yw, zw;
-        const long long n = tile_node(kp, X, Y, Z, xw, yw, zw);
-        const RT dh = r * invS;
-        // nodes with r > 0 are inside the support, so their tile neighbours exist
-        const RT gx = RT(0.5) * (raw[t + 1] - raw[t - 1]) * invS;
-        const RT gy = RT(0.5) * (raw[t + sx] - raw[t - sx]) * invS;
-        const RT gz = RT(0.5) * (raw[t + sxy] - raw[t - sxy]) * invS;
-        acc[0] += dh * u[n];
-        acc[1] += dh * u[kp.ld + n];
-        acc[2] += dh * u[2 * kp.ld + n];
-        // vorticity: curl of u by central differences, u = 0 on solid nodes
-        const RT wx = RT(0.5) * (u_node(u, nodeword, kp, X, Y + 1, Z, 2) - u_node(u, nodeword, kp, X, Y - 1, Z, 2)) -
-                      RT(0.5) * (u_node(u, nodeword, kp, X, Y, Z + 1, 1) - u_node(u, nodeword, kp, X, Y, Z - 1, 1));
-        const RT wy = RT(0.5) * (u_node(u, nodeword, kp, X, Y, Z + 1, 0) - u_node(u, nodeword, kp, X, Y, Z - 1, 0)) -
-                      RT(0.5) * (u_node(u, nodeword, kp, X + 1, Y, Z, 2) - u_node(u, nodeword, kp, X - 1, Y, Z, 2));
-        const RT wz = RT(0.5) * (u_node(u, nodeword, kp, X + 1, Y, Z, 1) - u_node(u, nodeword, kp, X - 1, Y, Z, 1)) -
-                      RT(0.5) * (u_node(u, nodeword, kp, X, Y + 1, Z, 0) - u_node(u, nodeword, kp, X, Y - 1, Z, 0));
-        acc[3] += dh * wx;
-        acc[4] += dh * wy;
-        acc[5] += dh * wz;
-        // elongational torque: alpha dhat (sigma . n^) x (x - R), n^ = grad/|grad|
-        const RT gl = sqrt(gx * gx + gy * gy + gz * gz);
-        const RT nx_ = gl > RT(0) ? gx / gl : RT(0), ny_ = gl > RT(0) ? gy / gl : RT(0),
-                 nz_ = gl > RT(0) ? gz / gl : RT(0);
-        const RT sxx = sig[n], syy = sig[kp.ld + n], szz = sig[2 * kp.ld + n];
-        const RT sxy_ = sig[3 * kp.ld + n], sxz = sig[4 * kp.ld + n], syz = sig[5 * kp.ld + n];
-        const RT t0 = sxx * nx_ + sxy_ * ny_ + sxz * nz_;
-        const RT t1 = sxy_ * nx_ + syy * ny_ + syz * nz_;
-        const RT t2 = sxz * nx_ + syz * ny_ + szz * nz_;
-        const RT d0 = (RT)min_img((double)xw - s.R[0], (double)kp.nx, kp.per[0]);
-        const RT d1 = (RT)min_img((double)yw - s.R[1], (double)kp.ny, kp.per[1]);
-        const RT d2 = (RT)min_img((double)zw - s.R[2], (double)kp.nz, kp.per[2]);
-        const RT al = (RT)kp.alpha * dh;
-        acc[6] += al * (t1 * d2 - t2 * d1);
-        acc[7] += al * (t2 * d0 - t0 * d2);
-        acc[8] += al * (t0 * d1 - t1 * d0);
+    const long long ld = kp.ld;
+    for (int tz = 0; tz < sz; ++tz) {
+        int Z = T.lo[2] + tz;
+        if (!wrap_coord(Z, kp.nz, kp.per[2])) continue;
+        for (int ty = ty0; ty < sy; ty += 16) {
+            int Y = T.lo[1] + ty;
+            if (!wrap_coord(Y, kp.ny, kp.per[1])) continue;
+            for (int tx = tx0; tx < sx; tx += 16) {
+                const int t = tx + sx * (ty + sy * tz);
+                const unsigned char fl = flag[t];
+                if (!(fl & 2)) continue;
+                const bool in = fl & 1;
+                const bool xm = tx > 0, xp = tx < sx - 1, ym = ty > 0, yp = ty < sy - 1,
+                           zm = tz > 0, zp = tz < sz - 1;
+                const bool cov = in || (xm && (flag[t - 1] & 1)) || (xp && (flag[t + 1] & 1)) ||
+                                 (ym && (flag[t - sx] & 1)) || (yp && (flag[t + sx] & 1)) ||
+                                 (zm && (flag[t - sxy] & 1)) || (zp && (flag[t + sxy] & 1));
+                if (!cov) continue;
+                int X = T.lo[0] + tx;
+                wrap_coord(X, kp.nx, kp.per[0]);
+                const unsigned n = node_of(kp, X, Y, Z);
+                const RT gx = RT(0.5) * ((xp ? raw[t + 1] : RT(0)) - (xm ? raw[t - 1] : RT(0)));
+                const RT gy = RT(0.5) * ((yp ? raw[t + sx] : RT(0)) - (ym ? raw[t - sx] : RT(0)));
+                const RT gz = RT(0.5) * ((zp ? raw[t + sxy] : RT(0)) - (zm ? raw[t - sxy] : RT(0)));
+                const uint32_t old = atomicAdd(nodeword + n, NW_CNT_ONE);
+                const int slot = (int)(old >> 24);
+                if (slot < kp.cap) {
+                    const long long e = (long long)slot * ld + n;
+                    ids[e] = i;
+                    RT* v = vals + 4 * e;
+                    v[0] = raw[t];
+                    v[1] = gx;
+                    v[2] = gy;
+                    v[3] = gz;
+                } else {
+                    atomicOr(err, ERR_CAPACITY);
+                }
+                if (!in) continue;
+                // interpolation at an inside node (its tile neighbours exist)
+                const RT dh = raw[t] * invS;
+                acc[0] += dh * u[n];
+                acc[1] += dh * u[ld + n];
+                acc[2] += dh * u[2 * ld + n];
+                auto un = [&](int dt, int ddx, int ddy, int ddz, int a) -> RT {
+                    if (!(flag[t + dt] & 2)) return RT(0);
+                    int Xn = X + ddx, Yn = Y + ddy, Zn = Z + ddz;
+                    wrap_coord(Xn, kp.nx, kp.per[0]);
+                    wrap_coord(Yn, kp.ny, kp.per[1]);
+                    wrap_coord(Zn, kp.nz, kp.per[2]);
+                    return u[(long long)a * ld + node_of(kp, Xn, Yn, Zn)];
+                };
+                const RT wx = RT(0.5) * (un(sx, 0, 1, 0, 2) - un(-sx, 0, -1, 0, 2)) -
+                              RT(0.5) * (un(sxy, 0, 0, 1, 1) - un(-sxy, 0, 0, -1, 1));
+                const RT wy = RT(0.5) * (un(sxy, 0, 0, 1, 0) - un(-sxy, 0, 0, -1, 0)) -
+                              RT(0.5) * (un(1, 1, 0, 0, 2) - un(-1, -1, 0, 0, 2));
+                const RT wz = RT(0.5) * (un(1, 1, 0, 0, 1) - un(-1, -1, 0, 0, 1)) -
+                              RT(0.5) * (un(sx, 0, 1, 0, 0) - un(-sx, 0, -1, 0, 0));
+                acc[3] += dh * wx;
+                acc[4] += dh * wy;
+                acc[5] += dh * wz;
+                const RT hx = gx * invS, hy = gy * invS, hz = gz * invS;
+                const RT gl = sqrt(hx * hx + hy * hy + hz * hz);
+                const RT il = gl > RT(0) ? RT(1) / gl : RT(0);
+                const RT nx_ = hx * il, ny_ = hy * il, nz_ = hz * il;
+                const RT sxx = sig[n], syy = sig[ld + n], szz = sig[2 * ld + n];
+                const RT sxy_ = sig[3 * ld + n], sxz = sig[4 * ld + n], syz = sig[5 * ld + n];
+                const RT t0 = sxx * nx_ + sxy_ * ny_ + sxz * nz_;
+                const RT t1 = sxy_ * nx_ + syy * ny_ + syz * nz_;
+                const RT t2 = sxz * nx_ + syz * ny_ + szz * nz_;
+                const RT d0 = (RT)min_img((double)X - s.R[0], (double)kp.nx, kp.per[0]);
+                const RT d1 = (RT)min_img((double)Y - s.R[1], (double)kp.ny, kp.per[1]);
+                const RT d2 = (RT)min_img((double)Z - s.R[2], (double)kp.nz, kp.per[2]);
+                const RT al = (RT)kp.alpha * dh;
+                acc[6] += al * (t1 * d2 - t2 * d1);
+                acc[7] += al * (t2 * d0 - t0 * d2);
+                acc[8] += al * (t0 * d1 - t1 * d0);
+            }
+        }
     }
     RT tot[9];
     for (int a = 0; a < 9; ++a) {
@@ -364,36 +382,26 @@ __global__ __launch_bounds__(256) void k_couple(const RbcState* __restrict__ st,
 }
 
 // ---- S5: Gay-Berne forces and torques (Sec. II E, Eqs. 24-28; App. B) -----------------------
-// F on i = -du/dR |R^ - (1/R^2) du/dphi [k - (k.R^) R^], k = H^-1 R_ij, H = A_i + A_j;
+// F on i = -du/dR R^ - (1/R^2) du/dphi [k - (k.R^) R^], k = H^-1 R_ij, H = A_i + A_j;
 // torques tau_i = (1/R) R_ci x f_k, R_ci = -A_i k, f_k = -(1/R) du/dphi k (lab frame).
-__device__ int gb_pair(const KParams& kp, const double* rij, const double* Qi, const double* Qj,
-                       int wall, double* F, double* ti)
+__device__ int gb_pair(const KParams& kp, const double* rij, const double* Ai, const double* Aj,
+                       double smin, double* F, double* ti)
 {
-    double Ai[9], H[9];
-    for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 3; ++c) {
-            double a = 0.0, b = 0.0;
-            for (int k = 0; k < 3; ++k) {
-                const double ax2 = kp.axes[k] * kp.axes[k];
-                a += Qi[3 * r + k] * ax2 * Qi[3 * c + k];
-                if (!wall) b += Qj[3 * r + k] * ax2 * Qj[3 * c + k];
-            }
-            if (wall) b = (r == c) ? kp.a_wall * kp.a_wall : 0.0;
-            Ai[3 * r + c] = a;
-            H[3 * r + c] = a + b;
-        }
+    double H[9];
+    for (int a = 0; a < 9; ++a) H[a] = Ai[a] + Aj[a];
     const double det = H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
                        H[2] * (H[3] * H[7] - H[4] * H[6]);
+    const double id = 1.0 / det;
     double Hi[9];
-    Hi[0] = (H[4] * H[8] - H[5] * H[7]) / det;
-    Hi[1] = (H[2] * H[7] - H[1] * H[8]) / det;
-    Hi[2] = (H[1] * H[5] - H[2] * H[4]) / det;
-    Hi[3] = (H[5] * H[6] - H[3] * H[8]) / det;
-    Hi[4] = (H[0] * H[8] - H[2] * H[6]) / det;
-    Hi[5] = (H[2] * H[3] - H[0] * H[5]) / det;
-    Hi[6] = (H[3] * H[7] - H[4] * H[6]) / det;
-    Hi[7] = (H[1] * H[6] - H[0] * H[7]) / det;
-    Hi[8] = (H[0] * H[4] - H[1] * H[3]) / det;
+    Hi[0] = (H[4] * H[8] - H[5] * H[7]) * id;
+    Hi[1] = (H[2] * H[7] - H[1] * H[8]) * id;
+    Hi[2] = (H[1] * H[5] - H[2] * H[4]) * id;
+    Hi[3] = (H[5] * H[6] - H[3] * H[8]) * id;
+    Hi[4] = (H[0] * H[8] - H[2] * H[6]) * id;
+    Hi[5] = (H[2] * H[3] - H[0] * H[5]) * id;
+    Hi[6] = (H[3] * H[7] - H[4] * H[6]) * id;
+    Hi[7] = (H[1] * H[6] - H[0] * H[7]) * id;
+    Hi[8] = (H[0] * H[4] - H[1] * H[3]) * id;
     const double R = sqrt(rij[0] * rij[0] + rij[1] * rij[1] + rij[2] * rij[2]);
     if (!(R > 0.0)) return 1;
     double rh[3], kap[3];
@@ -401,8 +409,6 @@ __device__ int gb_pair(const KParams& kp, const double* rij, const double* Qi, c
     mat_vec(Hi, rij, kap);
     const double phi = 0.5 * (rh[0] * kap[0] + rh[1] * kap[1] + rh[2] * kap[2]) / R;
     const double sigma = 1.0 / sqrt(phi);
-    const double amin = fmin(kp.axes[0], fmin(kp.axes[1], kp.axes[2]));
-    const double smin = wall ? kp.sigmin_wall : sqrt(4.0 * amin * amin);
     const double rho = (R - sigma + smin) / smin;
     if (!(rho > 0.0)) return 1;
     const double r2 = rho * rho, r6 = r2 * r2 * r2;
@@ -424,8 +430,21 @@ __device__ int gb_pair(const KParams& kp, const double* rij, const double* Qi, c
     return 0;
 }
 
-__global__ __launch_bounds__(128) void k_gay_berne(const RbcState* __restrict__ st,
+__device__ __forceinline__ void shape_matrix(const KParams& kp, const double* Q, double* A)
+{
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double a = 0.0;
+            for (int k = 0; k < 3; ++k) a += Q[3 * r + k] * kp.axes[k] * kp.axes[k] * Q[3 * c + k];
+            A[3 * r + c] = a;
+        }
+}
+
+// one wavefront per cell: lanes stride over the candidates of the 27 neighbour cells (cells
+// and wall points), then a fixed-order shuffle reduction (bitwise repeatable)
+__global__ __launch_bounds__(256) void k_gay_berne(const RbcState* __restrict__ st,
                                                    RbcCouple* __restrict__ cp,
+                                                   const int* __restrict__ order,
                                                    const int* __restrict__ cell_off,
                                                    const int* __restrict__ cell_ids,
                                                    const int* __restrict__ wall_xyz,
@@ -433,22 +452,28 @@ __global__ __launch_bounds__(128) void k_gay_berne(const RbcState* __restrict__ 
                                                    const int* __restrict__ wcell_ids, KParams kp,
                                                    unsigned* err)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= kp.nrbc) return;
+    const int lane = threadIdx.x & 63;
+    const int k = xcd_chunk_index(4) + (threadIdx.x >> 6);
+    if (k >= kp.nrbc) return;
+    const int i = order[k];
     const double* Ri = st[i].R;
     const double* Qi = st[i].Q;
+    double Ai[9], Aw[9];
+    shape_matrix(kp, Qi, Ai);
+    for (int a = 0; a < 9; ++a) Aw[a] = (a % 4 == 0) ? kp.a_wall * kp.a_wall : 0.0;
+    const double amin = fmin(kp.axes[0], fmin(kp.axes[1], kp.axes[2]));
+    const double smin_cc = sqrt(4.0 * amin * amin);
     double F[3] = {0, 0, 0}, tl[3] = {0, 0, 0};
     int lst[3][3], cnt[3];
-    int cc[3];
     for (int a = 0; a < 3; ++a) {
-        cc[a] = cell_coord(kp, a, Ri[a]);
+        const int cc = cell_coord(kp, a, Ri[a]);
         const int m = kp.ncell[a];
         cnt[a] = 0;
         if (m < 3) {
             for (int q = 0; q < m; ++q) lst[a][cnt[a]++] = q;
         } else {
             for (int d = -1; d <= 1; ++d) {
-                int v = cc[a] + d;
+                int v = cc + d;
                 if (v < 0 || v >= m) {
                     if (!kp.per[a]) continue;
                     v = (v + m) % m;
@@ -457,37 +482,48 @@ __global__ __launch_bounds__(128) void k_gay_berne(const RbcState* __restrict__ 
             }
         }
     }
-    const double rc2 = kp.rc * kp.rc;
-    bool bad = false;
+    const double rcc2 = kp.rc_pair * kp.rc_pair, rcw2 = kp.rc_wall * kp.rc_wall;
+    int bad = 0;
     for (int kz = 0; kz < cnt[2]; ++kz)
         for (int ky = 0; ky < cnt[1]; ++ky)
             for (int kx = 0; kx < cnt[0]; ++kx) {
                 const int c = lst[0][kx] + kp.ncell[0] * (lst[1][ky] + kp.ncell[1] * lst[2][kz]);
-                for (int e = cell_off[c]; e < cell_off[c + 1]; ++e) {
+                for (int e = cell_off[c] + lane; e < cell_off[c + 1]; e += 64) {
                     const int j = cell_ids[e];
                     if (j == i) continue;
                     double r[3];
                     for (int a = 0; a < 3; ++a)
                         r[a] = min_img(Ri[a] - st[j].R[a], box_len(kp, a), kp.per[a]);
-                    if (r[0] * r[0] + r[1] * r[1] + r[2] * r[2] > rc2) continue;
-                    bad |= gb_pair(kp, r, Qi, st[j].Q, 0, F, tl) != 0;
+                    if (r[0] * r[0] + r[1] * r[1] + r[2] * r[2] > rcc2) continue;
+                    double Aj[9];
+                    shape_matrix(kp, st[j].Q, Aj);
+                    bad |= gb_pair(kp, r, Ai, Aj, smin_cc, F, tl);
                 }
                 if (!kp.wall_particles) continue;
-                for (int e = wcell_off[c]; e < wcell_off[c + 1]; ++e) {
+                for (int e = wcell_off[c] + lane; e < wcell_off[c + 1]; e += 64) {
                     const int wq = wcell_ids[e];
                     double r[3];
                     for (int a = 0; a < 3; ++a)
                         r[a] = min_img(Ri[a] - (double)wall_xyz[3 * wq + a], box_len(kp, a), kp.per[a]);
-                    if (r[0] * r[0] + r[1] * r[1] + r[2] * r[2] > rc2) continue;
-                    bad |= gb_pair(kp, r, Qi, nullptr, 1, F, tl) != 0;
+                    if (r[0] * r[0] + r[1] * r[1] + r[2] * r[2] > rcw2) continue;
+                    bad |= gb_pair(kp, r, Ai, Aw, kp.sigmin_wall, F, tl);
                 }
             }
-    if (bad) atomicOr(err, ERR_OVERLAP);
-    double tb[3];
-    matT_vec(Qi, tl, tb);
-    for (int a = 0; a < 3; ++a) {
-        cp[i].Fm[a] = F[a];
-        cp[i].Tm[a] = tb[a];
+    for (int o = 32; o > 0; o >>= 1) {
+        for (int a = 0; a < 3; ++a) {
+            F[a] += __shfl_down(F[a], o, 64);
+            tl[a] += __shfl_down(tl[a], o, 64);
+        }
+        bad |= __shfl_down(bad, o, 64);
+    }
+    if (lane == 0) {
+        if (bad) atomicOr(err, ERR_OVERLAP);
+        double tb[3];
+        matT_vec(Qi, tl, tb);
+        for (int a = 0; a < 3; ++a) {
+            cp[i].Fm[a] = F[a];
+            cp[i].Tm[a] = tb[a];
+        }
     }
 }
 
@@ -533,11 +569,9 @@ __global__ __launch_bounds__(128) void k_rb_second_half(RbcState* __restrict__ s
     }
     Gather<RT> G;
     for (int a = 0; a < 3; ++a) {
-        G.R[a] = s.R[a];
         G.F[a] = (RT)c.Fh[a];
         G.T[a] = (RT)c.Th[a];
     }
-    for (int a = 0; a < 9; ++a) G.Q[a] = (RT)s.Q[a];
     G.invS = c.S > 0.0 ? (RT)(1.0 / c.S) : RT(0);
     G.pad = RT(0);
     gat[i] = G;
@@ -587,25 +621,27 @@ void launch_cell_list(const CellBuffers& b, const KParams& kp, hipStream_t st)
     launch_fill_u32(reinterpret_cast<uint32_t*>(b.cell_cnt), 0u, nc, st);
 }
 
-void launch_map_fill(const CellBuffers& b, const KParams& kp, hipStream_t st)
+static inline unsigned grid8(long long units, int per_block)
 {
-    const size_t lds = (size_t)kp.tile_max * kp.tile_max * kp.tile_max;
-    hipLaunchKernelGGL(k_map_fill, dim3(kp.nrbc), dim3(256), lds, st, b.st, b.nodeword,
-                       b.map_ids, kp, b.err);
+    const long long b = (units + per_block - 1) / per_block;
+    return (unsigned)((b + 7) / 8 * 8);
 }
 
 template <typename RT>
-void launch_couple(const CellBuffers& b, const KParams& kp, hipStream_t st)
+void launch_map_couple(const CellBuffers& b, const KParams& kp, hipStream_t st)
 {
-    const size_t lds = (size_t)kp.tile_max * kp.tile_max * kp.tile_max * sizeof(RT);
-    hipLaunchKernelGGL((k_couple<RT>), dim3(kp.nrbc), dim3(256), lds, st, b.st, b.cp, b.nodeword,
-                       (const RT*)b.u, (const RT*)b.sig, kp, b.err);
+    const size_t t3 = (size_t)kp.tile_max * kp.tile_max * kp.tile_max;
+    const size_t lds = t3 * sizeof(RT) + t3;
+    hipLaunchKernelGGL((k_map_couple<RT>), dim3(grid8(kp.nrbc, 1)), dim3(256), lds, st, b.st, b.cp,
+                       b.nodeword, b.map_ids, (RT*)b.map_vals, b.cell_ids, (const RT*)b.u,
+                       (const RT*)b.sig, kp, b.err);
 }
 
 void launch_gay_berne(const CellBuffers& b, const KParams& kp, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_gay_berne, dim3(nblk(kp.nrbc, 128)), dim3(128), 0, st, b.st, b.cp,
-                       b.cell_off, b.cell_ids, b.wall_xyz, b.wcell_off, b.wcell_ids, kp, b.err);
+    hipLaunchKernelGGL(k_gay_berne, dim3(grid8(kp.nrbc, 4)), dim3(256), 0, st, b.st, b.cp,
+                       b.cell_ids, b.cell_off, b.cell_ids, b.wall_xyz, b.wcell_off, b.wcell_ids,
+                       kp, b.err);
 }
 
 template <typename RT>
@@ -621,8 +657,8 @@ void launch_init_combined(const CellBuffers& b, const KParams& kp, hipStream_t s
                        kp.nrbc);
 }
 
-template void launch_couple<double>(const CellBuffers&, const KParams&, hipStream_t);
-template void launch_couple<float>(const CellBuffers&, const KParams&, hipStream_t);
+template void launch_map_couple<double>(const CellBuffers&, const KParams&, hipStream_t);
+template void launch_map_couple<float>(const CellBuffers&, const KParams&, hipStream_t);
 template void launch_rb_second_half<double>(const CellBuffers&, const KParams&, int, hipStream_t);
 template void launch_rb_second_half<float>(const CellBuffers&, const KParams&, int, hipStream_t);
 

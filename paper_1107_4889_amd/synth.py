@@ -16,11 +16,12 @@ candidate is rejected when
     c = r^T (A_i + A_j)^-1 r / 2, is below s^2 (s = 1: no contact);
   * it meets a wall mesh point: the point lies inside the ellipsoid grown to semi-axes
     sqrt(2 (a^2 + a_wall^2)) (the same contact function with a sphere of radius a_wall).
-Random sequential addition jams below blood hematocrits (about 0.3 in a wide tube, less in
-narrow ones), so when the attempt budget runs out the pair scale s is lowered, to 0.97 at most (a slight
-soft overlap of the kind a small Gay-Berne energy scale permits, keeping the initial pair
-forces well below the plasma's stability bound), and the achieved count and hematocrit are
-returned.
+Random sequential addition jams below blood hematocrits (about 0.24 in a wide tube, less in
+narrow ones), so the cells that do not fit are dropped at random fluid centres and all
+overlaps are then removed geometrically: pairs below the contact threshold, and cells
+meeting wall points, are pushed apart along their centre lines until every pair contact
+is at least 0.97^2 (a slight soft overlap of the kind a small Gay-Berne energy scale
+permits) and no wall point is inside a grown ellipsoid. Orientations stay uniform.
 """
 from __future__ import annotations
 
@@ -185,8 +186,17 @@ class _Packer:
         self.rng = rng
         self.Aw = (a_wall * a_wall) * np.eye(3)
         wall = boundary_points(solid, periodic)
+        # ghost copies across periodic faces, so a plain (non-periodic) tree answers
+        # every query on wrapped centres
+        for a in range(3):
+            if self.per[a] and len(wall):
+                lo = wall[wall[:, a] < self.r_wall + 1].copy()
+                lo[:, a] += self.box[a]
+                hi = wall[wall[:, a] > self.box[a] - self.r_wall - 1].copy()
+                hi[:, a] -= self.box[a]
+                wall = np.concatenate([wall, lo, hi])
         self.wall = wall
-        self.wtree = _tree(wall, self.box, self.per) if len(wall) else None
+        self.wtree = cKDTree(wall) if len(wall) else None
         zf, yf, xf = np.nonzero(self.fluid)
         self.lo = np.array([xf.min(), yf.min(), zf.min()], dtype=np.float64) - 0.5
         self.hi = np.array([xf.max(), yf.max(), zf.max()], dtype=np.float64) + 0.5
@@ -215,19 +225,19 @@ class _Packer:
         idx = np.nonzero(ok)[0]
         if not len(idx):
             return ok
-        d1, _ = self.wtree.query(_tc(c[idx], self.box, self.per), k=1)
+        cw = _wrap(c, self.box, self.per)
+        d1, _ = self.wtree.query(cw[idx], k=1)
         idx = idx[d1 < self.r_wall]
         k = 64
         while len(idx):
-            dist, j = self.wtree.query(_tc(c[idx], self.box, self.per), k=k,
-                                       distance_upper_bound=self.r_wall)
+            dist, j = self.wtree.query(cw[idx], k=k, distance_upper_bound=self.r_wall)
             full = np.isfinite(dist[:, -1])
             if full.any() and k < 1024:
                 k *= 2
                 continue
             rows, cols = np.nonzero(np.isfinite(dist))
             if len(rows):
-                d = _min_image(c[idx[rows]] - self.wall[j[rows, cols]], self.box, self.per)
+                d = cw[idx[rows]] - self.wall[j[rows, cols]]
                 bad = _contact(d, A[idx[rows]], np.broadcast_to(self.Aw, (len(rows), 3, 3))) < 1.0
                 ok[np.unique(idx[rows[bad]])] = False
             break
@@ -272,20 +282,24 @@ class _Packer:
 
 
 def place_cells(solid: np.ndarray, axes, n_target: int, seed: int, periodic=(0, 0, 1),
-                a_wall: float = 0.5, s_start: float = 1.0, s_floor: float = 0.97,
-                batch: int = 8192, rsa_attempts_per_cell: int = 16) -> Placement:
-    """Random sequential addition at pair contact scale s, lowered from s_start in steps
-    of 0.01 down to s_floor each time the attempt budget of a level runs out."""
+                a_wall: float = 0.5, batch: int = 8192, rsa_attempts_per_cell: int = 4,
+                s_accept: float = 0.97, max_iter: int = 200) -> Placement:
+    """Random sequential addition without contact, then, for the cells that did not fit,
+    random valid centres followed by geometric overlap removal: every pair with contact
+    function c < 1 is pushed apart along its centre line by half its deficit
+    |r| (1 - sqrt(c)), every cell meeting a wall point is pushed away from it likewise, and
+    the sweep repeats until no pair is below s_accept^2 and no wall point inside a grown
+    ellipsoid (or max_iter). Orientations stay as drawn. Cells still meeting a wall point at
+    the end are dropped."""
     rng = np.random.default_rng(seed)
     pk = _Packer(solid, axes, periodic, a_wall, rng)
     box, per = pk.box, pk.per
     Rs = np.zeros((0, 3))
     As = np.zeros((0, 3, 3))
     Qs = np.zeros((0, 3, 3))
-    s = s_start
     attempts = 0
     budget = rsa_attempts_per_cell * max(n_target, 1)
-    while len(Rs) < n_target:
+    while len(Rs) < n_target and attempts < budget:
         B = int(min(batch, 4 * (n_target - len(Rs)) + 64))
         c = pk.lo + rng.random((B, 3)) * (pk.hi - pk.lo)
         Qc = random_rotations(rng, B)
@@ -293,7 +307,7 @@ def place_cells(solid: np.ndarray, axes, n_target: int, seed: int, periodic=(0, 
         Ac = pk.shape(Qc)
         ok = pk.centre_ok(c)
         ok = pk.walls_ok(c, Ac, ok)
-        ok = pk.pairs_ok(c, Ac, ok, Rs, As, s * s)
+        ok = pk.pairs_ok(c, Ac, ok, Rs, As, 1.0)
         idx = np.nonzero(ok)[0]
         accepted = []
         if len(idx):
@@ -303,7 +317,7 @@ def place_cells(solid: np.ndarray, axes, n_target: int, seed: int, periodic=(0, 
             if len(prs):
                 a_, b_ = idx[prs[:, 0]], idx[prs[:, 1]]
                 d = _min_image(c[a_] - c[b_], box, per)
-                bad = _contact(d, Ac[a_], Ac[b_]) < s * s
+                bad = _contact(d, Ac[a_], Ac[b_]) < 1.0
                 for x, y in zip(a_[bad], b_[bad]):
                     lo_, hi_ = (x, y) if x < y else (y, x)
                     conflict.setdefault(hi_, []).append(lo_)
@@ -320,14 +334,91 @@ def place_cells(solid: np.ndarray, axes, n_target: int, seed: int, periodic=(0, 
             Rs = np.concatenate([Rs, _wrap(c[acc], box, per)])
             As = np.concatenate([As, Ac[acc]])
             Qs = np.concatenate([Qs, Qc[acc]])
-        if attempts > budget:
-            if s <= s_floor + 1e-12:
-                break
-            s = max(s_floor, round(s - 0.01, 2))
-            budget = attempts + rsa_attempts_per_cell * max(n_target - len(Rs), 1)
+    if len(Rs) < n_target:
+        # remaining cells at random centres whose node is fluid, then overlap removal
+        need = n_target - len(Rs)
+        extra_R, extra_Q = [], []
+        while sum(len(x) for x in extra_R) < need:
+            c = pk.lo + rng.random((4 * need + 64, 3)) * (pk.hi - pk.lo)
+            Qc = random_rotations(rng, len(c))
+            ok = pk.centre_ok(c)
+            extra_R.append(c[ok])
+            extra_Q.append(Qc[ok])
+        eR = np.concatenate(extra_R)[:need]
+        eQ = np.concatenate(extra_Q)[:need]
+        Rs = np.concatenate([Rs, _wrap(eR, box, per)])
+        Qs = np.concatenate([Qs, eQ])
+        As = np.concatenate([As, pk.shape(eQ)])
+        Rs = _relax(pk, Rs, As, s_accept, max_iter)
+    # final state: drop cells meeting a wall point or with a solid centre node, then the
+    # cell of the worst remaining pair until every pair contact is >= s_accept^2
+    okc = pk.centre_ok(Rs)
+    okc = pk.walls_ok(Rs, As, okc)
+    Rs, As, Qs = Rs[okc], As[okc], Qs[okc]
+    while len(Rs) > 1:
+        tree = _tree(Rs, box, per)
+        pr = tree.query_pairs(pk.r_pair, output_type="ndarray")
+        if not len(pr):
+            break
+        d = _min_image(Rs[pr[:, 0]] - Rs[pr[:, 1]], box, per)
+        c = _contact(d, As[pr[:, 0]], As[pr[:, 1]])
+        bad = c < s_accept * s_accept
+        if not bad.any():
+            break
+        # remove, among the cells in violating pairs, those with the most violations
+        cnt = np.bincount(np.concatenate([pr[bad, 0], pr[bad, 1]]), minlength=len(Rs))
+        drop = set()
+        for k in np.argsort(c[bad]):
+            a_, b_ = pr[bad][k]
+            if a_ in drop or b_ in drop:
+                continue
+            drop.add(a_ if cnt[a_] >= cnt[b_] else b_)
+        keep = np.array([k not in drop for k in range(len(Rs))])
+        Rs, As, Qs = Rs[keep], As[keep], Qs[keep]
+    s = min(1.0, math.sqrt(pk.min_pair_contact(Rs, As))) if len(Rs) > 1 else 1.0
     v = 4.0 / 3.0 * math.pi * float(np.prod(pk.axes))
     H = len(Rs) * v / float(pk.fluid.sum())
     return Placement(R=Rs, Q=Qs.reshape(-1, 9), hematocrit=H, s_pair=s, attempts=attempts)
+
+
+def _relax(pk: "_Packer", Rs, As, s_accept, max_iter):
+    box, per = pk.box, pk.per
+    Rs = Rs.copy()
+    for _ in range(max_iter):
+        disp = np.zeros_like(Rs)
+        worst = 1.0
+        tree = _tree(Rs, box, per)
+        pr = tree.query_pairs(pk.r_pair, output_type="ndarray")
+        if len(pr):
+            d = _min_image(Rs[pr[:, 0]] - Rs[pr[:, 1]], box, per)
+            c = _contact(d, As[pr[:, 0]], As[pr[:, 1]])
+            worst = float(c.min())
+            bad = c < 1.0
+            if bad.any():
+                dist = np.linalg.norm(d[bad], axis=1, keepdims=True)
+                push = 0.5 * (1.0 - np.sqrt(c[bad]))[:, None] * d[bad] / np.maximum(dist, 1e-9) * dist
+                np.add.at(disp, pr[bad, 0], push)
+                np.add.at(disp, pr[bad, 1], -push)
+        wall_bad = 0
+        if pk.wtree is not None:
+            d1, _ = pk.wtree.query(Rs, k=1)
+            near = np.nonzero(d1 < pk.r_wall)[0]
+            if len(near):
+                dist, j = pk.wtree.query(Rs[near], k=64, distance_upper_bound=pk.r_wall)
+                rows, cols = np.nonzero(np.isfinite(dist))
+                if len(rows):
+                    ri = near[rows]
+                    d = Rs[ri] - pk.wall[j[rows, cols]]
+                    c = _contact(d, As[ri], np.broadcast_to(pk.Aw, (len(rows), 3, 3)))
+                    bad = c < 1.0
+                    wall_bad = int(bad.sum())
+                    if wall_bad:
+                        push = 1.05 * (1.0 - np.sqrt(c[bad]))[:, None] * d[bad]
+                        np.add.at(disp, ri[bad], push)
+        if worst >= s_accept * s_accept and wall_bad == 0:
+            break
+        Rs = _wrap(Rs + disp, box, per)
+    return Rs
 
 
 def _wrap(c, box, periodic):
@@ -358,6 +449,8 @@ def _tree(pts, box, periodic):
 
 # ---- named workloads -------------------------------------------------------------------------
 AXES = (4.0, 4.0, 1.5)
+# bump when place_cells changes, so that cached placements are regenerated
+PLACEMENT_VERSION = "rsa-relax-v3"
 
 
 def _cache_dir():
@@ -391,7 +484,7 @@ def tube_workload(nx, ny, nz, radius, hematocrit=None, n_cells=None, seed=1107, 
     solid = tube(nx, ny, nz, radius)
     if n_cells is None:
         n_cells = hematocrit_count(solid, AXES, hematocrit or 0.0)
-    key = f"tube:{nx}:{ny}:{nz}:{radius}:{n_cells}:{seed}:{sorted(kw.items())}:v1"
+    key = f"tube:{nx}:{ny}:{nz}:{radius}:{n_cells}:{seed}:{sorted(kw.items())}:{PLACEMENT_VERSION}"
     pl = cached_placement(key, lambda: place_cells(solid, AXES, n_cells, seed,
                                                    periodic=(0, 0, 1), **kw))
     return solid, pl
