@@ -54,6 +54,10 @@ def workload(name: str, storage: str):
     if name == "tube128":
         nx, ny, nz, R, H, T0 = 128, 128, 512, 60.0, 0.35, 0.8
         solid, pl = synth.tube_workload(nx, ny, nz, R, hematocrit=H, seed=1107)
+    elif name == "tube128_h0":
+        # the same tube without cells (the zero-hematocrit twin of the relative viscosity)
+        nx, ny, nz, R, H, T0 = 128, 128, 512, 60.0, 0.0, 0.8
+        solid, pl = synth.tube_workload(nx, ny, nz, R, n_cells=0, seed=1107)
     elif name == "tube32":
         nx, ny, nz, R, H, T0 = 32, 32, 64, 14.0, None, 1.0
         solid, pl = synth.tube_workload(nx, ny, nz, R, n_cells=110, seed=1107)

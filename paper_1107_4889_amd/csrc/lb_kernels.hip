@@ -7,44 +7,57 @@
 
 namespace lbrbc {
 
+template <typename RT>
+static MapPlanes<RT> map_planes(const int* ids, const void* vals, const KParams& kp)
+{
+    MapPlanes<RT> mp;
+    for (int k = 0; k < CAP_MAX; ++k) mp.ids[k] = ids + (k < kp.cap ? (size_t)k * (size_t)kp.ld : 0);
+    mp.vals0 = (const RT*)vals;
+    return mp;
+}
+
 // ---- spreading at one node (Sec. II B back-reaction G; Sec. II D, Eq. 23) -----------------
 // g = g_ext - sum_i [F_i dhat_i - 1/2 T_i x grad(dhat_i)], theta = sum_i [1 - (1 - raw_i)^kappa]
 // over the covering cells in ascending id order (a fixed order: bitwise repeatable). Each
 // coverage slot holds the cell id and (raw, grad raw) written by the per-cell pass; dhat =
 // raw / S_i. The torque term carries the sign that hands the plasma -T_i of angular momentum.
-template <typename RT>
-__device__ __forceinline__ void spread_at(unsigned n, uint32_t w, const int* __restrict__ ids,
-                                          const RT* __restrict__ vals,
-                                          const Gather<RT>* __restrict__ gat, const KParams& kp,
-                                          RT g[3], RT& theta)
+//
+// The slot ids are read with branch-free loads (unused slots read the node word, already in
+// cache) so that all loads are in flight together; the keys (id << 4 | slot) are sorted by a
+// network sized to the wave's largest count (4, 8 or 12 slots).
+template <int CN>
+__device__ __forceinline__ void sort_keys(int* key)
 {
-    g[0] = (RT)kp.gext[0];
-    g[1] = (RT)kp.gext[1];
-    g[2] = (RT)kp.gext[2];
-    theta = RT(0);
-    int cnt = (int)(w >> 24);
-    if (cnt > kp.cap) cnt = kp.cap;
-    if (cnt == 0) return;
-    // sort keys (id << 4 | slot) in registers: odd-even transposition with static indices
-    int key[CAP_MAX];
 #pragma unroll
-    for (int k = 0; k < CAP_MAX; ++k)
-        key[k] = (k < cnt) ? ((ids[(size_t)k * kp.ld + n] << 4) | k) : INT_MAX;
+    for (int r = 0; r < CN; ++r) {
 #pragma unroll
-    for (int r = 0; r < CAP_MAX; ++r) {
-#pragma unroll
-        for (int k = (r & 1); k + 1 < CAP_MAX; k += 2) {
+        for (int k = (r & 1); k + 1 < CN; k += 2) {
             const int a = min(key[k], key[k + 1]), b = max(key[k], key[k + 1]);
             key[k] = a;
             key[k + 1] = b;
         }
     }
+}
+
+template <typename RT, int CN>
+__device__ __forceinline__ void spread_slots(unsigned n, int cnt, const uint32_t* __restrict__ nodeword,
+                                             const MapPlanes<RT>& mp, const Gather<RT>* __restrict__ gat,
+                                             const KParams& kp, RT g[3], RT& theta)
+{
+    int key[CN];
+#pragma unroll
+    for (int k = 0; k < CN; ++k) {
+        const int* a = (k < cnt) ? at32(mp.ids[k], n) : reinterpret_cast<const int*>(at32(nodeword, n));
+        const int v = *a;
+        key[k] = (k < cnt) ? ((v << 4) | k) : INT_MAX;
+    }
+    sort_keys<CN>(key);
     for (int k = 0; k < cnt; ++k) {
         const int kk = key[0];
 #pragma unroll
-        for (int j = 0; j + 1 < CAP_MAX; ++j) key[j] = key[j + 1];
+        for (int j = 0; j + 1 < CN; ++j) key[j] = key[j + 1];
         const int i = kk >> 4, slot = kk & 15;
-        const RT* v = vals + 4 * ((size_t)slot * kp.ld + n);
+        const RT* v = mp.vals0 + 4 * ((size_t)slot * (size_t)kp.ld + n);
         const RT r0 = v[0], gx = v[1], gy = v[2], gz = v[3];
         const Gather<RT>& G = gat[i];
         const RT invS = G.invS;
@@ -56,6 +69,24 @@ __device__ __forceinline__ void spread_at(unsigned n, uint32_t w, const int* __r
         g[2] -= G.F[2] * dh - RT(0.5) * (T0 * gr1 - T1 * gr0);
         theta += RT(1) - ipow_or_pow(RT(1) - r0, kp.kappa, kp.kappa_int);
     }
+}
+
+template <typename RT>
+__device__ __forceinline__ void spread_at(unsigned n, uint32_t w, const uint32_t* __restrict__ nodeword,
+                                          const MapPlanes<RT>& mp, const Gather<RT>* __restrict__ gat,
+                                          const KParams& kp, RT g[3], RT& theta)
+{
+    g[0] = (RT)kp.gext[0];
+    g[1] = (RT)kp.gext[1];
+    g[2] = (RT)kp.gext[2];
+    theta = RT(0);
+    int cnt = (int)(w >> 24);
+    if (cnt > kp.cap) cnt = kp.cap;
+    // wave-uniform choice of the slot network
+    if (!__any(cnt > 0)) return;
+    if (!__any(cnt > 4)) spread_slots<RT, 4>(n, cnt, nodeword, mp, gat, kp, g, theta);
+    else if (!__any(cnt > 8)) spread_slots<RT, 8>(n, cnt, nodeword, mp, gat, kp, g, theta);
+    else spread_slots<RT, CAP_MAX>(n, cnt, nodeword, mp, gat, kp, g, theta);
 }
 
 template <int P>
@@ -92,6 +123,40 @@ __device__ __forceinline__ void pull_all(RT* f, const ST* __restrict__ fin, unsi
     (pull_one<ST, RT, Ps>(f, fin, n, w, x, y, z, xm, xp, ym, yp, zm, zp, kp), ...);
 }
 
+// pull source offset: n - (c_x + nx c_y + nx ny c_z), wrapped by one period at the box
+// faces on every axis, so the address is always inside the lattice (on a non-periodic face
+// the source is a wall: the value read there is replaced by the bounce-back value)
+template <int P>
+__device__ __forceinline__ unsigned pull_off(unsigned n, int x, int y, int z, const KParams& kp,
+                                             unsigned sx, unsigned sy, unsigned sz)
+{
+    // offset change of the source along an axis: -c s normally, -c s (1 - L) across the face
+    unsigned off = n;
+    if (cx_(P)) off -= (unsigned)cx_(P) * ((x == (cx_(P) > 0 ? 0 : kp.nx - 1)) ? sx * (1u - (unsigned)kp.nx) : sx);
+    if (cy_(P)) off -= (unsigned)cy_(P) * ((y == (cy_(P) > 0 ? 0 : kp.ny - 1)) ? sy * (1u - (unsigned)kp.ny) : sy);
+    if (cz_(P)) off -= (unsigned)cz_(P) * ((z == (cz_(P) > 0 ? 0 : kp.nz - 1)) ? sz * (1u - (unsigned)kp.nz) : sz);
+    return off;
+}
+
+// the 19 pull loads depend only on the position, so they issue without waiting for the node
+// word; directions whose source is solid are then replaced by the opposite population at
+// the node itself (halfway bounce-back)
+template <typename ST, typename RT, int... Ps>
+__device__ __forceinline__ void pull_all_fast(RT* f, const Planes<ST, RT>& pl, unsigned n, int x,
+                                              int y, int z, const KParams& kp,
+                                              std::integer_sequence<int, Ps...>)
+{
+    const unsigned sx = 1u, sy = (unsigned)kp.nx, sz = (unsigned)kp.nx * (unsigned)kp.ny;
+    ((f[Ps] = Store<ST, RT>::ld(pl.in[Ps], pull_off<Ps>(n, x, y, z, kp, sx, sy, sz), kp.f16_inv)), ...);
+}
+
+template <typename ST, typename RT, int... Ps>
+__device__ __forceinline__ void bounce_back(RT* f, const Planes<ST, RT>& pl, unsigned n, uint32_t w,
+                                            const KParams& kp, std::integer_sequence<int, Ps...>)
+{
+    ((f[Ps] = (w & (1u << Ps)) ? Store<ST, RT>::ld(pl.in[opp_(Ps)], n, kp.f16_inv) : f[Ps]), ...);
+}
+
 template <typename RT>
 __device__ __forceinline__ RT feq_shift(int p, RT drho, RT rho, RT ux, RT uy, RT uz, RT usq)
 {
@@ -100,15 +165,43 @@ __device__ __forceinline__ RT feq_shift(int p, RT drho, RT rho, RT ux, RT uy, RT
     return RT(w_(p)) * (drho + rho * (RT(3) * uc + RT(4.5) * uc * uc - RT(1.5) * usq));
 }
 
+// BGK with body force for the pair (P, P+1) of opposite speeds: the equilibrium and the
+// force term split into parts even and odd in c, shared by the two directions.
+template <typename ST, typename RT, int P>
+__device__ __forceinline__ void collide_pair(const RT* f, const Planes<ST, RT>& pl, unsigned n,
+                                             RT drho, RT rho, RT ux, RT uy, RT uz, RT usq,
+                                             const RT g[3], RT gu, RT om, RT kf, RT k2, RT k3,
+                                             const KParams& kp)
+{
+    constexpr int Q = P + 1;
+    const RT w = RT(w_(P));
+    const RT uc = RT(cx_(P)) * ux + RT(cy_(P)) * uy + RT(cz_(P)) * uz;
+    const RT gc = RT(cx_(P)) * g[0] + RT(cy_(P)) * g[1] + RT(cz_(P)) * g[2];
+    const RT sym = w * (drho + rho * (RT(4.5) * uc * uc - RT(1.5) * usq));
+    const RT asym = w * rho * RT(3) * uc;
+    const RT fs = kf * w * (k2 * gc * uc - k3 * gu);
+    const RT fa = kf * w * RT(3) * gc;
+    Store<ST, RT>::st(pl.out[P], n, f[P] - om * (f[P] - sym - asym) + fs + fa, kp.f16_scale);
+    Store<ST, RT>::st(pl.out[Q], n, f[Q] - om * (f[Q] - sym + asym) + fs - fa, kp.f16_scale);
+}
+
+template <typename ST, typename RT, int... Ps>
+__device__ __forceinline__ void collide_pairs(const RT* f, const Planes<ST, RT>& pl, unsigned n,
+                                              RT drho, RT rho, RT ux, RT uy, RT uz, RT usq,
+                                              const RT g[3], RT gu, RT om, RT kf, RT k2, RT k3,
+                                              const KParams& kp, std::integer_sequence<int, Ps...>)
+{
+    (collide_pair<ST, RT, 2 * Ps + 1>(f, pl, n, drho, rho, ux, uy, uz, usq, g, gu, om, kf, k2, k3, kp), ...);
+}
+
 // ---- fused spreading + stream + collide (Sec. II A, Eqs. 1-8) -----------------------------
 // One thread per node; SoA planes f[p*ld + n] of the shifted populations f - w.
 // Launch: blocks of 64 x 4 threads (a wavefront spans 64 consecutive x), grid
 // (ceil(nx/64), ceil(ny/4), nz): no integer division, 32-bit node offsets.
 template <typename ST, typename RT>
 __global__ __launch_bounds__(256) void k_stream_collide(
-    const ST* __restrict__ fin, ST* __restrict__ fout, const uint32_t* __restrict__ nodeword,
-    const int* __restrict__ ids, const RT* __restrict__ vals, const Gather<RT>* __restrict__ gat,
-    RT* __restrict__ uout, RT* __restrict__ sout, KParams kp, unsigned* __restrict__ err)
+    const Planes<ST, RT> pl, const uint32_t* __restrict__ nodeword, const MapPlanes<RT> mp,
+    const Gather<RT>* __restrict__ gat, KParams kp, unsigned* __restrict__ err)
 {
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int y = blockIdx.y * 4 + threadIdx.y;
@@ -117,65 +210,65 @@ __global__ __launch_bounds__(256) void k_stream_collide(
     const unsigned n = (unsigned)x + (unsigned)kp.nx * ((unsigned)y + (unsigned)kp.ny * (unsigned)z);
     const uint32_t w = nodeword[n];
     if (!(w & NW_FLUID) || (w & NW_OPEN)) return;
-    const int xm = x == 0 ? kp.nx - 1 : x - 1, xp = x == kp.nx - 1 ? 0 : x + 1;
-    const int ym = y == 0 ? kp.ny - 1 : y - 1, yp = y == kp.ny - 1 ? 0 : y + 1;
-    const int zm = z == 0 ? kp.nz - 1 : z - 1, zp = z == kp.nz - 1 ? 0 : z + 1;
-
     RT f[19];
-    pull_all<ST, RT>(f, fin, n, w, x, y, z, xm, xp, ym, yp, zm, zp, kp,
-                     std::make_integer_sequence<int, 19>{});
+    pull_all_fast<ST, RT>(f, pl, n, x, y, z, kp, std::make_integer_sequence<int, 19>{});
+    if (w & 0x7FFFEu) bounce_back<ST, RT>(f, pl, n, w, kp, std::make_integer_sequence<int, 19>{});
 
     RT g[3], theta;
-    spread_at<RT>(n, w, ids, vals, gat, kp, g, theta);
+    spread_at<RT>(n, w, nodeword, mp, gat, kp, g, theta);
 
+    // moments of the shifted populations: density excess, momentum, second moments
     RT drho = RT(0), mx = RT(0), my = RT(0), mz = RT(0);
+    RT pxx = RT(0), pyy = RT(0), pzz = RT(0), pxy = RT(0), pxz = RT(0), pyz = RT(0);
 #pragma unroll
     for (int p = 0; p < 19; ++p) {
         drho += f[p];
-        mx += RT(cx_(p)) * f[p];
-        my += RT(cy_(p)) * f[p];
-        mz += RT(cz_(p)) * f[p];
+        if (cx_(p)) mx += RT(cx_(p)) * f[p];
+        if (cy_(p)) my += RT(cy_(p)) * f[p];
+        if (cz_(p)) mz += RT(cz_(p)) * f[p];
+        if (cx_(p)) pxx += f[p];
+        if (cy_(p)) pyy += f[p];
+        if (cz_(p)) pzz += f[p];
+        if (cx_(p) * cy_(p)) pxy += RT(cx_(p) * cy_(p)) * f[p];
+        if (cx_(p) * cz_(p)) pxz += RT(cx_(p) * cz_(p)) * f[p];
+        if (cy_(p) * cz_(p)) pyz += RT(cy_(p) * cz_(p)) * f[p];
     }
     const RT rho = RT(1) + drho;
-    const RT irho = RT(1) / rho;
+    const RT irho = recip(rho);
     const RT ux = (mx + RT(0.5) * g[0]) * irho;
     const RT uy = (my + RT(0.5) * g[1]) * irho;
     const RT uz = (mz + RT(0.5) * g[2]) * irho;
     const RT usq = ux * ux + uy * uy + uz * uz;
     const RT T = (RT)kp.tau0 + (RT)kp.delta * theta;
-    const RT om = RT(1) / T;
+    const RT om = recip(T);
     const RT kf = kp.forcing == 1 ? RT(1) : RT(1) - RT(0.5) * om;
     const RT k2 = kp.forcing == 1 ? RT(4.5) : RT(9);      // 1/(2c^4) or 1/c^4
     const RT k3 = kp.forcing == 1 ? RT(1.5) : RT(3);      // c^2/(2c^4) or c^2/c^4
     const RT gu = g[0] * ux + g[1] * uy + g[2] * uz;
-    RT sxx = 0, syy = 0, szz = 0, sxy = 0, sxz = 0, syz = 0;
-#pragma unroll
-    for (int p = 0; p < 19; ++p) {
-        const RT fe = feq_shift<RT>(p, drho, rho, ux, uy, uz, usq);
-        const RT neq = f[p] - fe;
-        const RT gc = RT(cx_(p)) * g[0] + RT(cy_(p)) * g[1] + RT(cz_(p)) * g[2];
-        const RT uc = RT(cx_(p)) * ux + RT(cy_(p)) * uy + RT(cz_(p)) * uz;
-        const RT Fp = kf * RT(w_(p)) * (RT(3) * gc + k2 * gc * uc - k3 * gu);
-        Store<ST, RT>::st(fout + (size_t)p * (size_t)kp.ld, n, f[p] - om * neq + Fp, kp.f16_scale);
-        if (cx_(p) * cx_(p)) sxx += neq;
-        if (cy_(p) * cy_(p)) syy += neq;
-        if (cz_(p) * cz_(p)) szz += neq;
-        if (cx_(p) * cy_(p)) sxy += RT(cx_(p) * cy_(p)) * neq;
-        if (cx_(p) * cz_(p)) sxz += RT(cx_(p) * cz_(p)) * neq;
-        if (cy_(p) * cz_(p)) syz += RT(cy_(p) * cz_(p)) * neq;
+
+    // rest population, then the nine pairs of opposite speeds
+    {
+        const RT w0 = RT(w_(0));
+        const RT fe0 = w0 * (drho - RT(1.5) * rho * usq);
+        const RT F0 = -kf * w0 * k3 * gu;
+        Store<ST, RT>::st(pl.out[0], n, f[0] - om * (f[0] - fe0) + F0, kp.f16_scale);
     }
-    // stress of the non-equilibrium part: sigma = -(1 - 1/(2T)) sum c c (f - f^eq)
+    collide_pairs<ST, RT>(f, pl, n, drho, rho, ux, uy, uz, usq, g, gu, om, kf, k2, k3, kp,
+                          std::make_integer_sequence<int, 9>{});
+
+    // stress of the non-equilibrium part: sigma = -(1 - 1/(2T)) sum c c (f - f^eq), with
+    // sum c c f^eq - w = drho/3 delta + rho u u
     const RT ks = -(RT(1) - RT(0.5) * om);
-    const size_t ld = (size_t)kp.ld;
-    __builtin_nontemporal_store(ux, uout + n);
-    __builtin_nontemporal_store(uy, (uout + ld) + n);
-    __builtin_nontemporal_store(uz, (uout + 2 * ld) + n);
-    __builtin_nontemporal_store(ks * sxx, sout + n);
-    __builtin_nontemporal_store(ks * syy, (sout + ld) + n);
-    __builtin_nontemporal_store(ks * szz, (sout + 2 * ld) + n);
-    __builtin_nontemporal_store(ks * sxy, (sout + 3 * ld) + n);
-    __builtin_nontemporal_store(ks * sxz, (sout + 4 * ld) + n);
-    __builtin_nontemporal_store(ks * syz, (sout + 5 * ld) + n);
+    const RT d3 = drho * RT(1.0 / 3.0);
+    __builtin_nontemporal_store(ux, at32(pl.u[0], n));
+    __builtin_nontemporal_store(uy, at32(pl.u[1], n));
+    __builtin_nontemporal_store(uz, at32(pl.u[2], n));
+    __builtin_nontemporal_store(ks * (pxx - d3 - rho * ux * ux), at32(pl.sig[0], n));
+    __builtin_nontemporal_store(ks * (pyy - d3 - rho * uy * uy), at32(pl.sig[1], n));
+    __builtin_nontemporal_store(ks * (pzz - d3 - rho * uz * uz), at32(pl.sig[2], n));
+    __builtin_nontemporal_store(ks * (pxy - rho * ux * uy), at32(pl.sig[3], n));
+    __builtin_nontemporal_store(ks * (pxz - rho * ux * uz), at32(pl.sig[4], n));
+    __builtin_nontemporal_store(ks * (pyz - rho * uy * uz), at32(pl.sig[5], n));
     if (!(rho > RT(0)) || !(usq <= RT(0.09))) atomicOr(err, ERR_UNSTABLE);
 }
 
@@ -183,9 +276,8 @@ __global__ __launch_bounds__(256) void k_stream_collide(
 template <typename ST, typename RT>
 __global__ __launch_bounds__(256) void k_open_bc(
     const ST* __restrict__ fin, ST* __restrict__ fout, const uint32_t* __restrict__ nodeword,
-    const long long* __restrict__ plane_nodes, int nplane, const int* __restrict__ ids,
-    const RT* __restrict__ vals, const Gather<RT>* __restrict__ gat, RT* __restrict__ uout,
-    RT* __restrict__ sout, KParams kp)
+    const long long* __restrict__ plane_nodes, int nplane, const MapPlanes<RT> mp,
+    const Gather<RT>* __restrict__ gat, RT* __restrict__ uout, RT* __restrict__ sout, KParams kp)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nplane) return;
@@ -200,13 +292,13 @@ __global__ __launch_bounds__(256) void k_open_bc(
     const uint32_t wi = nodeword[ni];
     const RT rb = z == 0 ? (RT)kp.rho_in : (RT)kp.rho_out;
     RT gb[3], thb;
-    spread_at<RT>((unsigned)n, w, ids, vals, gat, kp, gb, thb);
+    spread_at<RT>((unsigned)n, w, nodeword, mp, gat, kp, gb, thb);
     const RT om = RT(1) / ((RT)kp.tau0 + (RT)kp.delta * thb);
 #pragma unroll
     for (int a = 0; a < 6; ++a) sout[(long long)a * kp.ld + n] = RT(0);
     if (!(wi & NW_FLUID)) {
         for (int p = 0; p < 19; ++p)
-            Store<ST, RT>::st(fout, (long long)p * kp.ld + n, RT(w_(p)) * (rb - RT(1)), kp.f16_scale);
+            Store<ST, RT>::st(fout + (size_t)p * (size_t)kp.ld, (unsigned)n, RT(w_(p)) * (rb - RT(1)), kp.f16_scale);
         for (int a = 0; a < 3; ++a) uout[(long long)a * kp.ld + n] = RT(0);
         return;
     }
@@ -217,7 +309,7 @@ __global__ __launch_bounds__(256) void k_open_bc(
     pull_all<ST, RT>(f, fin, (unsigned)ni, wi, x, y, zi, xm, xp, ym, yp, zm, zp, kp,
                      std::make_integer_sequence<int, 19>{});
     RT gi[3], thi;
-    spread_at<RT>((unsigned)ni, wi, ids, vals, gat, kp, gi, thi);
+    spread_at<RT>((unsigned)ni, wi, nodeword, mp, gat, kp, gi, thi);
     RT drho = 0, mx = 0, my = 0, mz = 0;
     for (int p = 0; p < 19; ++p) {
         drho += f[p];
@@ -232,7 +324,7 @@ __global__ __launch_bounds__(256) void k_open_bc(
     for (int p = 0; p < 19; ++p) {
         const RT feb = feq_shift<RT>(p, rb - RT(1), rb, ux, uy, uz, usq);
         const RT fei = feq_shift<RT>(p, drho, rho, ux, uy, uz, usq);
-        Store<ST, RT>::st(fout, (long long)p * kp.ld + n, feb + (RT(1) - om) * (f[p] - fei), kp.f16_scale);
+        Store<ST, RT>::st(fout + (size_t)p * (size_t)kp.ld, (unsigned)n, feb + (RT(1) - om) * (f[p] - fei), kp.f16_scale);
     }
     uout[n] = ux;
     uout[kp.ld + n] = uy;
@@ -242,8 +334,7 @@ __global__ __launch_bounds__(256) void k_open_bc(
 // ---- spread-field probe: g and T per fluid node (same device function as the step) -------
 template <typename RT>
 __global__ __launch_bounds__(256) void k_spread_field(const uint32_t* __restrict__ nodeword,
-                                                      const int* __restrict__ ids,
-                                                      const RT* __restrict__ vals,
+                                                      const MapPlanes<RT> mp,
                                                       const Gather<RT>* __restrict__ gat,
                                                       RT* __restrict__ gout, RT* __restrict__ tout,
                                                       KParams kp)
@@ -257,7 +348,7 @@ __global__ __launch_bounds__(256) void k_spread_field(const uint32_t* __restrict
         return;
     }
     RT g[3], th;
-    spread_at<RT>((unsigned)n, w, ids, vals, gat, kp, g, th);
+    spread_at<RT>((unsigned)n, w, nodeword, mp, gat, kp, g, th);
     gout[n] = g[0];
     gout[kp.ld + n] = g[1];
     gout[2 * kp.ld + n] = g[2];
@@ -287,7 +378,7 @@ __global__ __launch_bounds__(256) void k_observe_partials(const ST* __restrict__
         if (!(nodeword[n] & NW_FLUID)) continue;
         double m = 0, px = 0, py = 0, pz = 0;
         for (int p = 0; p < 19; ++p) {
-            const double v = (double)Store<ST, RT>::ld(f, (long long)p * kp.ld + n, kp.f16_inv);
+            const double v = (double)Store<ST, RT>::ld(f + (size_t)p * (size_t)kp.ld, (unsigned)n, kp.f16_inv);
             m += v;
             px += cx_(p) * v;
             py += cy_(p) * v;
@@ -354,9 +445,16 @@ void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword
                            const KParams& kp, unsigned* err, hipStream_t st)
 {
     const dim3 grid((unsigned)((kp.nx + 63) / 64), (unsigned)((kp.ny + 3) / 4), (unsigned)kp.nz);
-    hipLaunchKernelGGL((k_stream_collide<ST, RT>), grid, dim3(64, 4, 1), 0, st, (const ST*)fin,
-                       (ST*)fout, nodeword, ids, (const RT*)vals, (const Gather<RT>*)gat, (RT*)u,
-                       (RT*)sig, kp, err);
+    Planes<ST, RT> pl;
+    const size_t ld = (size_t)kp.ld;
+    for (int p = 0; p < 19; ++p) {
+        pl.in[p] = (const ST*)fin + p * ld;
+        pl.out[p] = (ST*)fout + p * ld;
+    }
+    for (int a = 0; a < 3; ++a) pl.u[a] = (RT*)u + a * ld;
+    for (int a = 0; a < 6; ++a) pl.sig[a] = (RT*)sig + a * ld;
+    hipLaunchKernelGGL((k_stream_collide<ST, RT>), grid, dim3(64, 4, 1), 0, st, pl, nodeword,
+                       map_planes<RT>(ids, vals, kp), (const Gather<RT>*)gat, kp, err);
 }
 
 template <typename ST, typename RT>
@@ -366,8 +464,8 @@ void launch_open_bc(const void* fin, void* fout, const uint32_t* nodeword, const
 {
     if (nplane <= 0) return;
     hipLaunchKernelGGL((k_open_bc<ST, RT>), dim3((nplane + 255) / 256), dim3(256), 0, st,
-                       (const ST*)fin, (ST*)fout, nodeword, planes, nplane, ids, (const RT*)vals,
-                       (const Gather<RT>*)gat, (RT*)u, (RT*)sig, kp);
+                       (const ST*)fin, (ST*)fout, nodeword, planes, nplane,
+                       map_planes<RT>(ids, vals, kp), (const Gather<RT>*)gat, (RT*)u, (RT*)sig, kp);
 }
 
 template <typename RT>
@@ -375,8 +473,8 @@ void launch_spread_field(const uint32_t* nodeword, const int* ids, const void* v
                          const void* gat, void* g, void* t, const KParams& kp, hipStream_t st)
 {
     const unsigned blocks = (unsigned)((kp.N + 255) / 256);
-    hipLaunchKernelGGL((k_spread_field<RT>), dim3(blocks), dim3(256), 0, st, nodeword, ids,
-                       (const RT*)vals, (const Gather<RT>*)gat, (RT*)g, (RT*)t, kp);
+    hipLaunchKernelGGL((k_spread_field<RT>), dim3(blocks), dim3(256), 0, st, nodeword,
+                       map_planes<RT>(ids, vals, kp), (const Gather<RT>*)gat, (RT*)g, (RT*)t, kp);
 }
 
 void launch_clear_counts(uint32_t* nodeword, long long N, hipStream_t st)

@@ -73,7 +73,12 @@ std::string validate(const lb_config& c, int n_rbc)
 std::string build_geometry(const lb_config& c, const uint8_t* solid, int n_rbc, Geometry& g)
 {
     g.N = (long long)c.nx * c.ny * c.nz;
-    g.ld = (g.N + 255) / 256 * 256;
+    // plane stride: a multiple of 256 B plus an odd number of 256-B blocks, so that planes
+    // read together do not start at power-of-two distances (HBM channel spread)
+    {
+        const long long G = 256 / storage_bytes(c.storage);
+        g.ld = (g.N + 2 * G - 1) / (2 * G) * (2 * G) + G;
+    }
     g.nodeword.assign((size_t)g.N, 0u);
     auto is_fluid = [&](int x, int y, int z) {
         long long m = node_at(c, x, y, z);

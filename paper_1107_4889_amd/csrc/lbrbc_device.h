@@ -91,44 +91,78 @@ struct alignas(16) Gather {
 };
 
 // ---- storage conversions ------------------------------------------------------------------
+// Loads and stores take a per-plane base (scalar registers) and a 32-bit element offset; the
+// byte offset is formed in 32 bits so that the access is base + zero-extended offset (every
+// plane is far below 4 GiB).
 struct bf16_t { uint16_t v; };
+
+template <typename T>
+__device__ __forceinline__ const T* at32(const T* base, unsigned i)
+{
+    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ T* at32(T* base, unsigned i)
+{
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (unsigned)sizeof(T));
+}
 
 template <typename ST, typename RT>
 struct Store;
 template <>
 struct Store<double, double> {
-    __device__ static double ld(const double* p, long long i, float) { return p[i]; }
-    __device__ static void st(double* p, long long i, double v, float) { __builtin_nontemporal_store(v, p + i); }
+    __device__ static double ld(const double* p, unsigned i, float) { return *at32(p, i); }
+    __device__ static void st(double* p, unsigned i, double v, float) { __builtin_nontemporal_store(v, at32(p, i)); }
 };
 template <>
 struct Store<float, float> {
-    __device__ static float ld(const float* p, long long i, float) { return p[i]; }
-    __device__ static void st(float* p, long long i, float v, float) { __builtin_nontemporal_store(v, p + i); }
+    __device__ static float ld(const float* p, unsigned i, float) { return *at32(p, i); }
+    __device__ static void st(float* p, unsigned i, float v, float) { __builtin_nontemporal_store(v, at32(p, i)); }
 };
 template <>
 struct Store<bf16_t, float> {
-    __device__ static float ld(const bf16_t* p, long long i, float)
+    __device__ static float ld(const bf16_t* p, unsigned i, float)
     {
-        uint32_t u = (uint32_t)reinterpret_cast<const uint16_t*>(p)[i] << 16;
+        uint32_t u = (uint32_t)*at32(reinterpret_cast<const uint16_t*>(p), i) << 16;
         return __uint_as_float(u);
     }
-    __device__ static void st(bf16_t* p, long long i, float v, float)
+    __device__ static void st(bf16_t* p, unsigned i, float v, float)
     {
         // round to nearest even on the upper 16 bits
         uint32_t u = __float_as_uint(v);
         uint16_t r;
         if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) r = 0x7fc0;
         else r = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-        __builtin_nontemporal_store(r, reinterpret_cast<uint16_t*>(p) + i);
+        __builtin_nontemporal_store(r, at32(reinterpret_cast<uint16_t*>(p), i));
     }
 };
 template <>
 struct Store<_Float16, float> {
-    __device__ static float ld(const _Float16* p, long long i, float inv) { return (float)p[i] * inv; }
-    __device__ static void st(_Float16* p, long long i, float v, float scale)
+    __device__ static float ld(const _Float16* p, unsigned i, float inv) { return (float)*at32(p, i) * inv; }
+    __device__ static void st(_Float16* p, unsigned i, float v, float scale)
     {
-        __builtin_nontemporal_store((_Float16)(v * scale), p + i);
+        __builtin_nontemporal_store((_Float16)(v * scale), at32(p, i));
     }
+};
+
+// reciprocal in the compute precision: the hardware reciprocal (1 ulp) for float
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+// coverage slots: per-slot id planes and the (raw, grad raw) values, slot-major
+template <typename RT>
+struct MapPlanes {
+    const int* ids[CAP_MAX];
+    const RT* vals0;
+};
+
+// per-plane pointers of one stream-collide launch (kernel argument)
+template <typename ST, typename RT>
+struct Planes {
+    const ST* in[19];
+    ST* out[19];
+    RT* u[3];
+    RT* sig[6];
 };
 
 // ---- Peskin four-point kernel at r = 2|y|/xi (the normalised 1-D profile) ----------------

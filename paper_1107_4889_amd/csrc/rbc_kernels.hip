@@ -203,174 +203,199 @@ __device__ __forceinline__ int xcd_chunk_index(int units_per_block)
     return blk * units_per_block;
 }
 
-template <typename RT>
-__device__ __forceinline__ RT block_sum(RT v, RT* red)
-{
-    // 256 threads, wave64: shuffle inside the wave, then across the four waves
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) red[wv] = v;
-    __syncthreads();
-    return red[0] + red[1] + red[2] + red[3];
-}
+constexpr int MC_THREADS = 256;
+constexpr int TILE_ROWS_MAX = 20 * 20;   // tile_max <= 20
 
 // ---- S3 + S4: coverage map and interpolation, one block per cell ------------------------
 // Pass 1 over the support tile: exact FP64 support test and the unnormalised kernel raw(x)
 // on fluid nodes; S = sum raw. Pass 2: every covered node (fluid, and inside or next to an
 // inside node) takes a coverage slot and stores (cell id; raw, grad raw by central
-// differences), which the per-node spreading reads; every inside node adds to
-// u~ = sum dhat u, w~ = sum dhat curl u, T^S = alpha sum dhat (sigma . n^) x (x - R),
-// with dhat = raw / S and n^ = grad dhat / |grad dhat| (Eqs. 16-21).
+// differences), which the per-node spreading reads, and adds to the interpolation sums
+// (Eqs. 16-21) with dhat = raw / S:
+//   u~  = sum over inside nodes of dhat u,
+//   w~  = sum over inside nodes of dhat (curl u) = sum over covered nodes of u x grad dhat
+//         (summation by parts of the central-difference curl, exact with u = 0 on solid
+//         nodes; it needs u only at the node itself),
+//   T^S = alpha sum over inside nodes of dhat (sigma . n^) x (x - R), n^ = grad/|grad|.
 template <typename RT>
-__global__ __launch_bounds__(256) void k_map_couple(const RbcState* __restrict__ st,
-                                                    RbcCouple* __restrict__ cp,
-                                                    uint32_t* __restrict__ nodeword,
-                                                    int* __restrict__ ids, RT* __restrict__ vals,
-                                                    const int* __restrict__ order,
-                                                    const RT* __restrict__ u,
-                                                    const RT* __restrict__ sig, KParams kp,
-                                                    unsigned* __restrict__ err)
+__global__ __launch_bounds__(MC_THREADS) void k_map_couple(const RbcState* __restrict__ st,
+                                                           RbcCouple* __restrict__ cp,
+                                                           uint32_t* __restrict__ nodeword,
+                                                           int* __restrict__ ids,
+                                                           RT* __restrict__ vals,
+                                                           const int* __restrict__ order,
+                                                           const RT* __restrict__ u,
+                                                           const RT* __restrict__ sig, KParams kp,
+                                                           unsigned* __restrict__ err)
 {
     extern __shared__ unsigned char smem[];
     const int tm = kp.tile_max;
     RT* raw = reinterpret_cast<RT*>(smem);
     unsigned char* flag = smem + (size_t)tm * tm * tm * sizeof(RT);  // 1 inside, 2 fluid
     __shared__ Tile T;
-    __shared__ RT red[4];
+    __shared__ RT red[MC_THREADS / 64][10];
+    __shared__ short rlo[TILE_ROWS_MAX], rhi[TILE_ROWS_MAX], clo[TILE_ROWS_MAX], chi[TILE_ROWS_MAX];
     const int k = xcd_chunk_index(1);
     if (k >= kp.nrbc) return;
     const int i = order[k];
     const RbcState& s = st[i];
-    if (threadIdx.x == 0) support_tile(s, kp, T);
+    const int tid = threadIdx.x;
+    if (tid == 0) support_tile(s, kp, T);
     __syncthreads();
     if (T.sz[0] > tm || T.sz[1] > tm || T.sz[2] > tm) {
-        if (threadIdx.x == 0) atomicOr(err, ERR_CAPACITY);
+        if (tid == 0) atomicOr(err, ERR_CAPACITY);
         return;
     }
-    const int sx = T.sz[0], sy = T.sz[1], sz = T.sz[2], sxy = sx * sy;
-    const int tx0 = threadIdx.x & 15, ty0 = threadIdx.x >> 4;
+    const unsigned sx = T.sz[0], sy = T.sz[1], sz = T.sz[2], sxy = sx * sy, total = sxy * sz;
+    const unsigned rows = sy * sz;
+    // Conservative x-range of the support on each tile row (y, z): the body coordinates are
+    // affine in x, y_a = Q_xa d_x + b_a, and |y_a| < xi_a cuts an interval; the exact test
+    // below decides each node, the range (widened by two nodes) only skips nodes that are
+    // certainly outside.
+    for (unsigned r = tid; r < rows; r += MC_THREADS) {
+        const int ty = (int)(r % sy), tz = (int)(r / sy);
+        const double dy = (double)(T.lo[1] + ty) - s.R[1], dz = (double)(T.lo[2] + tz) - s.R[2];
+        double xa = -1e30, xb = 1e30;
+        for (int a = 0; a < 3; ++a) {
+            const double qa = s.Q[a], b = s.Q[3 + a] * dy + s.Q[6 + a] * dz;
+            if (fabs(qa) > 1e-12) {
+                double u0 = (-kp.xi[a] - b) / qa, u1 = (kp.xi[a] - b) / qa;
+                if (u0 > u1) { const double t_ = u0; u0 = u1; u1 = t_; }
+                xa = fmax(xa, u0);
+                xb = fmin(xb, u1);
+            } else if (fabs(b) >= kp.xi[a] + 1e-9) {
+                xa = 1e30;
+            }
+        }
+        int lo = (int)sx, hi = -1;
+        if (xa <= xb) {
+            const double X0 = s.R[0] - (double)T.lo[0];
+            lo = max(0, (int)floor(X0 + xa) - 2);
+            hi = min((int)sx - 1, (int)ceil(X0 + xb) + 2);
+        }
+        rlo[r] = (short)lo;
+        rhi[r] = (short)hi;
+    }
+    __syncthreads();
+    // covered range of a row: its own support range widened by one and the ranges of the
+    // four neighbouring rows (a node is covered when it or an axis neighbour is inside)
+    for (unsigned r = tid; r < rows; r += MC_THREADS) {
+        const int ty = (int)(r % sy), tz = (int)(r / sy);
+        int lo = rlo[r] - 1, hi = rhi[r] + 1;
+        if (ty > 0) { lo = min(lo, (int)rlo[r - 1]); hi = max(hi, (int)rhi[r - 1]); }
+        if (ty + 1 < (int)sy) { lo = min(lo, (int)rlo[r + 1]); hi = max(hi, (int)rhi[r + 1]); }
+        if (tz > 0) { lo = min(lo, (int)rlo[r - sy]); hi = max(hi, (int)rhi[r - sy]); }
+        if (tz + 1 < (int)sz) { lo = min(lo, (int)rlo[r + sy]); hi = max(hi, (int)rhi[r + sy]); }
+        clo[r] = (short)max(lo, 0);
+        chi[r] = (short)min(hi, (int)sx - 1);
+    }
+    __syncthreads();
     const RT s0 = RT(2.0 / kp.xi[0]), s1 = RT(2.0 / kp.xi[1]), s2 = RT(2.0 / kp.xi[2]);
     RT part = RT(0);
-    for (int tz = 0; tz < sz; ++tz) {
-        int Z = T.lo[2] + tz;
-        const bool okz = wrap_coord(Z, kp.nz, kp.per[2]);
-        for (int ty = ty0; ty < sy; ty += 16) {
-            int Y = T.lo[1] + ty;
-            const bool oky = okz && wrap_coord(Y, kp.ny, kp.per[1]);
-            for (int tx = tx0; tx < sx; tx += 16) {
-                int X = T.lo[0] + tx;
-                const bool ok = oky && wrap_coord(X, kp.nx, kp.per[0]);
-                const int t = tx + sx * (ty + sy * tz);
-                unsigned char fl = 0;
-                RT r = RT(0);
-                if (ok && (nodeword[node_of(kp, X, Y, Z)] & NW_FLUID)) {
-                    fl = 2;
-                    double y[3];
-                    const double d0 = min_img((double)X - s.R[0], (double)kp.nx, kp.per[0]);
-                    const double d1 = min_img((double)Y - s.R[1], (double)kp.ny, kp.per[1]);
-                    const double d2 = min_img((double)Z - s.R[2], (double)kp.nz, kp.per[2]);
-                    body_coords_exact(s.Q, d0, d1, d2, y);
-                    if (fabs(y[0]) < kp.xi[0] && fabs(y[1]) < kp.xi[1] && fabs(y[2]) < kp.xi[2]) {
-                        fl = 3;
-                        r = peskin((RT)y[0] * s0) * peskin((RT)y[1] * s1) * peskin((RT)y[2] * s2);
-                    }
-                }
-                raw[t] = r;
-                flag[t] = fl;
-                part += r;
+#pragma unroll 4
+    for (unsigned t = tid; t < total; t += MC_THREADS) {
+        const unsigned row = t / sx, tx = t - row * sx;
+        const unsigned tz = row / sy, ty = row - tz * sy;
+        int X = T.lo[0] + (int)tx, Y = T.lo[1] + (int)ty, Z = T.lo[2] + (int)tz;
+        const bool ok = (int)tx >= clo[row] && (int)tx <= chi[row] && wrap_coord(X, kp.nx, kp.per[0]) &&
+                        wrap_coord(Y, kp.ny, kp.per[1]) && wrap_coord(Z, kp.nz, kp.per[2]);
+        unsigned char fl = 0;
+        RT r = RT(0);
+        if (ok && (nodeword[node_of(kp, X, Y, Z)] & NW_FLUID)) {
+            fl = 2;
+            double y[3];
+            const double d0 = min_img((double)X - s.R[0], (double)kp.nx, kp.per[0]);
+            const double d1 = min_img((double)Y - s.R[1], (double)kp.ny, kp.per[1]);
+            const double d2 = min_img((double)Z - s.R[2], (double)kp.nz, kp.per[2]);
+            body_coords_exact(s.Q, d0, d1, d2, y);
+            if (fabs(y[0]) < kp.xi[0] && fabs(y[1]) < kp.xi[1] && fabs(y[2]) < kp.xi[2]) {
+                fl = 3;
+                r = peskin((RT)y[0] * s0) * peskin((RT)y[1] * s1) * peskin((RT)y[2] * s2);
             }
         }
+        raw[t] = r;
+        flag[t] = fl;
+        part += r;
     }
-    const RT S = block_sum(part, red);
+    // S: wave shuffles, then the four waves in order
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_down(part, o, 64);
+    if ((tid & 63) == 0) red[tid >> 6][9] = part;
     __syncthreads();
+    RT S = RT(0);
+    for (int w = 0; w < MC_THREADS / 64; ++w) S += red[w][9];
     const RT invS = S > RT(0) ? RT(1) / S : RT(0);
     RT acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    const long long ld = kp.ld;
-    for (int tz = 0; tz < sz; ++tz) {
-        int Z = T.lo[2] + tz;
-        if (!wrap_coord(Z, kp.nz, kp.per[2])) continue;
-        for (int ty = ty0; ty < sy; ty += 16) {
-            int Y = T.lo[1] + ty;
-            if (!wrap_coord(Y, kp.ny, kp.per[1])) continue;
-            for (int tx = tx0; tx < sx; tx += 16) {
-                const int t = tx + sx * (ty + sy * tz);
-                const unsigned char fl = flag[t];
-                if (!(fl & 2)) continue;
-                const bool in = fl & 1;
-                const bool xm = tx > 0, xp = tx < sx - 1, ym = ty > 0, yp = ty < sy - 1,
-                           zm = tz > 0, zp = tz < sz - 1;
-                const bool cov = in || (xm && (flag[t - 1] & 1)) || (xp && (flag[t + 1] & 1)) ||
-                                 (ym && (flag[t - sx] & 1)) || (yp && (flag[t + sx] & 1)) ||
-                                 (zm && (flag[t - sxy] & 1)) || (zp && (flag[t + sxy] & 1));
-                if (!cov) continue;
-                int X = T.lo[0] + tx;
-                wrap_coord(X, kp.nx, kp.per[0]);
-                const unsigned n = node_of(kp, X, Y, Z);
-                const RT gx = RT(0.5) * ((xp ? raw[t + 1] : RT(0)) - (xm ? raw[t - 1] : RT(0)));
-                const RT gy = RT(0.5) * ((yp ? raw[t + sx] : RT(0)) - (ym ? raw[t - sx] : RT(0)));
-                const RT gz = RT(0.5) * ((zp ? raw[t + sxy] : RT(0)) - (zm ? raw[t - sxy] : RT(0)));
-                const uint32_t old = atomicAdd(nodeword + n, NW_CNT_ONE);
-                const int slot = (int)(old >> 24);
-                if (slot < kp.cap) {
-                    const long long e = (long long)slot * ld + n;
-                    ids[e] = i;
-                    RT* v = vals + 4 * e;
-                    v[0] = raw[t];
-                    v[1] = gx;
-                    v[2] = gy;
-                    v[3] = gz;
-                } else {
-                    atomicOr(err, ERR_CAPACITY);
-                }
-                if (!in) continue;
-                // interpolation at an inside node (its tile neighbours exist)
-                const RT dh = raw[t] * invS;
-                acc[0] += dh * u[n];
-                acc[1] += dh * u[ld + n];
-                acc[2] += dh * u[2 * ld + n];
-                auto un = [&](int dt, int ddx, int ddy, int ddz, int a) -> RT {
-                    if (!(flag[t + dt] & 2)) return RT(0);
-                    int Xn = X + ddx, Yn = Y + ddy, Zn = Z + ddz;
-                    wrap_coord(Xn, kp.nx, kp.per[0]);
-                    wrap_coord(Yn, kp.ny, kp.per[1]);
-                    wrap_coord(Zn, kp.nz, kp.per[2]);
-                    return u[(long long)a * ld + node_of(kp, Xn, Yn, Zn)];
-                };
-                const RT wx = RT(0.5) * (un(sx, 0, 1, 0, 2) - un(-sx, 0, -1, 0, 2)) -
-                              RT(0.5) * (un(sxy, 0, 0, 1, 1) - un(-sxy, 0, 0, -1, 1));
-                const RT wy = RT(0.5) * (un(sxy, 0, 0, 1, 0) - un(-sxy, 0, 0, -1, 0)) -
-                              RT(0.5) * (un(1, 1, 0, 0, 2) - un(-1, -1, 0, 0, 2));
-                const RT wz = RT(0.5) * (un(1, 1, 0, 0, 1) - un(-1, -1, 0, 0, 1)) -
-                              RT(0.5) * (un(sx, 0, 1, 0, 0) - un(-sx, 0, -1, 0, 0));
-                acc[3] += dh * wx;
-                acc[4] += dh * wy;
-                acc[5] += dh * wz;
-                const RT hx = gx * invS, hy = gy * invS, hz = gz * invS;
-                const RT gl = sqrt(hx * hx + hy * hy + hz * hz);
-                const RT il = gl > RT(0) ? RT(1) / gl : RT(0);
-                const RT nx_ = hx * il, ny_ = hy * il, nz_ = hz * il;
-                const RT sxx = sig[n], syy = sig[ld + n], szz = sig[2 * ld + n];
-                const RT sxy_ = sig[3 * ld + n], sxz = sig[4 * ld + n], syz = sig[5 * ld + n];
-                const RT t0 = sxx * nx_ + sxy_ * ny_ + sxz * nz_;
-                const RT t1 = sxy_ * nx_ + syy * ny_ + syz * nz_;
-                const RT t2 = sxz * nx_ + syz * ny_ + szz * nz_;
-                const RT d0 = (RT)min_img((double)X - s.R[0], (double)kp.nx, kp.per[0]);
-                const RT d1 = (RT)min_img((double)Y - s.R[1], (double)kp.ny, kp.per[1]);
-                const RT d2 = (RT)min_img((double)Z - s.R[2], (double)kp.nz, kp.per[2]);
-                const RT al = (RT)kp.alpha * dh;
-                acc[6] += al * (t1 * d2 - t2 * d1);
-                acc[7] += al * (t2 * d0 - t0 * d2);
-                acc[8] += al * (t0 * d1 - t1 * d0);
-            }
+    const size_t ld = (size_t)kp.ld;
+    for (unsigned t = tid; t < total; t += MC_THREADS) {
+        const unsigned char fl = flag[t];
+        if (!(fl & 2)) continue;
+        const unsigned tz = t / sxy, rem = t - tz * sxy, ty = rem / sx, tx = rem - ty * sx;
+        const bool in = fl & 1;
+        const bool xm = tx > 0, xp = tx + 1 < sx, ym = ty > 0, yp = ty + 1 < sy, zm = tz > 0,
+                   zp = tz + 1 < sz;
+        const bool cov = in || (xm && (flag[t - 1] & 1)) || (xp && (flag[t + 1] & 1)) ||
+                         (ym && (flag[t - sx] & 1)) || (yp && (flag[t + sx] & 1)) ||
+                         (zm && (flag[t - sxy] & 1)) || (zp && (flag[t + sxy] & 1));
+        if (!cov) continue;
+        int X = T.lo[0] + (int)tx, Y = T.lo[1] + (int)ty, Z = T.lo[2] + (int)tz;
+        wrap_coord(X, kp.nx, kp.per[0]);
+        wrap_coord(Y, kp.ny, kp.per[1]);
+        wrap_coord(Z, kp.nz, kp.per[2]);
+        const unsigned n = node_of(kp, X, Y, Z);
+        const RT r = raw[t];
+        const RT gx = RT(0.5) * ((xp ? raw[t + 1] : RT(0)) - (xm ? raw[t - 1] : RT(0)));
+        const RT gy = RT(0.5) * ((yp ? raw[t + sx] : RT(0)) - (ym ? raw[t - sx] : RT(0)));
+        const RT gz = RT(0.5) * ((zp ? raw[t + sxy] : RT(0)) - (zm ? raw[t - sxy] : RT(0)));
+        const RT ux = u[n], uy = u[ld + n], uz = u[2 * ld + n];
+        const uint32_t old = atomicAdd(nodeword + n, NW_CNT_ONE);
+        const int slot = (int)(old >> 24);
+        if (slot < kp.cap) {
+            const size_t e = (size_t)slot * ld + n;
+            ids[e] = i;
+            RT* v = vals + 4 * e;
+            v[0] = r;
+            v[1] = gx;
+            v[2] = gy;
+            v[3] = gz;
+        } else {
+            atomicOr(err, ERR_CAPACITY);
         }
+        const RT hx = gx * invS, hy = gy * invS, hz = gz * invS;
+        // u x grad dhat (vorticity, summed by parts over covered nodes)
+        acc[3] += uy * hz - uz * hy;
+        acc[4] += uz * hx - ux * hz;
+        acc[5] += ux * hy - uy * hx;
+        if (!in) continue;
+        const RT dh = r * invS;
+        acc[0] += dh * ux;
+        acc[1] += dh * uy;
+        acc[2] += dh * uz;
+        const RT gl = sqrt(hx * hx + hy * hy + hz * hz);
+        const RT il = gl > RT(0) ? RT(1) / gl : RT(0);
+        const RT nx_ = hx * il, ny_ = hy * il, nz_ = hz * il;
+        const RT sxx = sig[n], syy = sig[ld + n], szz = sig[2 * ld + n];
+        const RT sxy_ = sig[3 * ld + n], sxz = sig[4 * ld + n], syz = sig[5 * ld + n];
+        const RT t0 = sxx * nx_ + sxy_ * ny_ + sxz * nz_;
+        const RT t1 = sxy_ * nx_ + syy * ny_ + syz * nz_;
+        const RT t2 = sxz * nx_ + syz * ny_ + szz * nz_;
+        const RT d0 = (RT)min_img((double)X - s.R[0], (double)kp.nx, kp.per[0]);
+        const RT d1 = (RT)min_img((double)Y - s.R[1], (double)kp.ny, kp.per[1]);
+        const RT d2 = (RT)min_img((double)Z - s.R[2], (double)kp.nz, kp.per[2]);
+        const RT al = (RT)kp.alpha * dh;
+        acc[6] += al * (t1 * d2 - t2 * d1);
+        acc[7] += al * (t2 * d0 - t0 * d2);
+        acc[8] += al * (t0 * d1 - t1 * d0);
     }
-    RT tot[9];
-    for (int a = 0; a < 9; ++a) {
-        tot[a] = block_sum(acc[a], red);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
+    for (int a = 0; a < 9; ++a)
+        for (int o = 32; o > 0; o >>= 1) acc[a] += __shfl_down(acc[a], o, 64);
+    __syncthreads();   // every wave has read red[.][9]
+    if ((tid & 63) == 0)
+        for (int a = 0; a < 9; ++a) red[tid >> 6][a] = acc[a];
+    __syncthreads();
+    if (tid == 0) {
+        RT tot[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int w = 0; w < MC_THREADS / 64; ++w)
+            for (int a = 0; a < 9; ++a) tot[a] += red[w][a];
         RbcCouple& c = cp[i];
         c.S = (double)S;
         for (int a = 0; a < 3; ++a) {
@@ -440,8 +465,73 @@ __device__ __forceinline__ void shape_matrix(const KParams& kp, const double* Q,
         }
 }
 
-// one wavefront per cell: lanes stride over the candidates of the 27 neighbour cells (cells
-// and wall points), then a fixed-order shuffle reduction (bitwise repeatable)
+// Neighbour cell `q` (0..26, dx fastest) of cell coordinates cc; -1 when it does not exist
+// (outside a non-periodic face). An axis with fewer than three cells lists each of its
+// cells once (offset index d -> cell d).
+__device__ __forceinline__ int neighbour_cell(const KParams& kp, const int cc[3], int q)
+{
+    const int d[3] = {q % 3, (q / 3) % 3, q / 9};
+    int v[3];
+    for (int a = 0; a < 3; ++a) {
+        const int m = kp.ncell[a];
+        if (m < 3) {
+            if (d[a] >= m) return -1;
+            v[a] = d[a];
+        } else {
+            int x = cc[a] + d[a] - 1;
+            if (x < 0 || x >= m) {
+                if (!kp.per[a]) return -1;
+                x = (x + m) % m;
+            }
+            v[a] = x;
+        }
+    }
+    return v[0] + kp.ncell[0] * (v[1] + kp.ncell[1] * v[2]);
+}
+
+// Flattened candidates of the 27 neighbour cells: lanes 0..26 hold one cell's CSR range, an
+// inclusive wave scan gives the running totals, and candidate e belongs to the first cell
+// whose running total exceeds e (binary search over the 27 totals kept in LDS).
+struct CandidateRanges {
+    int base[27];
+    int pre[27];
+    int total;
+};
+
+__device__ __forceinline__ void gather_ranges(const int* __restrict__ off, const int* cells_of_lane,
+                                              int lane, CandidateRanges& cr)
+{
+    int cnt = 0, base = 0;
+    if (lane < 27 && cells_of_lane[lane] >= 0) {
+        base = off[cells_of_lane[lane]];
+        cnt = off[cells_of_lane[lane] + 1] - base;
+    }
+    int incl = cnt;
+    for (int o = 1; o < 32; o <<= 1) {
+        const int v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    if (lane < 27) {
+        cr.base[lane] = base;
+        cr.pre[lane] = incl;
+    }
+    cr.total = __shfl(incl, 26, 64);
+}
+
+__device__ __forceinline__ int candidate(const CandidateRanges& cr, const int* __restrict__ ids, int e)
+{
+    int lo = 0, hi = 26;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cr.pre[mid] > e) hi = mid;
+        else lo = mid + 1;
+    }
+    const int start = lo ? cr.pre[lo - 1] : 0;
+    return ids[cr.base[lo] + (e - start)];
+}
+
+// one wavefront per cell: lanes stride over the flattened candidates (cells, then wall
+// points), then a fixed-order shuffle reduction (bitwise repeatable)
 __global__ __launch_bounds__(256) void k_gay_berne(const RbcState* __restrict__ st,
                                                    RbcCouple* __restrict__ cp,
                                                    const int* __restrict__ order,
@@ -452,63 +542,51 @@ __global__ __launch_bounds__(256) void k_gay_berne(const RbcState* __restrict__ 
                                                    const int* __restrict__ wcell_ids, KParams kp,
                                                    unsigned* err)
 {
-    const int lane = threadIdx.x & 63;
-    const int k = xcd_chunk_index(4) + (threadIdx.x >> 6);
+    __shared__ CandidateRanges ranges[4][2];
+    __shared__ int cells[4][27];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int k = xcd_chunk_index(4) + wv;
     if (k >= kp.nrbc) return;
     const int i = order[k];
     const double* Ri = st[i].R;
     const double* Qi = st[i].Q;
+    int cc[3];
+    for (int a = 0; a < 3; ++a) cc[a] = cell_coord(kp, a, Ri[a]);
+    if (lane < 27) cells[wv][lane] = neighbour_cell(kp, cc, lane);
+    __builtin_amdgcn_wave_barrier();
+    gather_ranges(cell_off, cells[wv], lane, ranges[wv][0]);
+    if (kp.wall_particles) gather_ranges(wcell_off, cells[wv], lane, ranges[wv][1]);
+    __builtin_amdgcn_wave_barrier();
     double Ai[9], Aw[9];
     shape_matrix(kp, Qi, Ai);
     for (int a = 0; a < 9; ++a) Aw[a] = (a % 4 == 0) ? kp.a_wall * kp.a_wall : 0.0;
     const double amin = fmin(kp.axes[0], fmin(kp.axes[1], kp.axes[2]));
     const double smin_cc = sqrt(4.0 * amin * amin);
     double F[3] = {0, 0, 0}, tl[3] = {0, 0, 0};
-    int lst[3][3], cnt[3];
-    for (int a = 0; a < 3; ++a) {
-        const int cc = cell_coord(kp, a, Ri[a]);
-        const int m = kp.ncell[a];
-        cnt[a] = 0;
-        if (m < 3) {
-            for (int q = 0; q < m; ++q) lst[a][cnt[a]++] = q;
-        } else {
-            for (int d = -1; d <= 1; ++d) {
-                int v = cc + d;
-                if (v < 0 || v >= m) {
-                    if (!kp.per[a]) continue;
-                    v = (v + m) % m;
-                }
-                lst[a][cnt[a]++] = v;
-            }
-        }
-    }
     const double rcc2 = kp.rc_pair * kp.rc_pair, rcw2 = kp.rc_wall * kp.rc_wall;
     int bad = 0;
-    for (int kz = 0; kz < cnt[2]; ++kz)
-        for (int ky = 0; ky < cnt[1]; ++ky)
-            for (int kx = 0; kx < cnt[0]; ++kx) {
-                const int c = lst[0][kx] + kp.ncell[0] * (lst[1][ky] + kp.ncell[1] * lst[2][kz]);
-                for (int e = cell_off[c] + lane; e < cell_off[c + 1]; e += 64) {
-                    const int j = cell_ids[e];
-                    if (j == i) continue;
-                    double r[3];
-                    for (int a = 0; a < 3; ++a)
-                        r[a] = min_img(Ri[a] - st[j].R[a], box_len(kp, a), kp.per[a]);
-                    if (r[0] * r[0] + r[1] * r[1] + r[2] * r[2] > rcc2) continue;
-                    double Aj[9];
-                    shape_matrix(kp, st[j].Q, Aj);
-                    bad |= gb_pair(kp, r, Ai, Aj, smin_cc, F, tl);
-                }
-                if (!kp.wall_particles) continue;
-                for (int e = wcell_off[c] + lane; e < wcell_off[c + 1]; e += 64) {
-                    const int wq = wcell_ids[e];
-                    double r[3];
-                    for (int a = 0; a < 3; ++a)
-                        r[a] = min_img(Ri[a] - (double)wall_xyz[3 * wq + a], box_len(kp, a), kp.per[a]);
-                    if (r[0] * r[0] + r[1] * r[1] + r[2] * r[2] > rcw2) continue;
-                    bad |= gb_pair(kp, r, Ai, Aw, kp.sigmin_wall, F, tl);
-                }
-            }
+    const CandidateRanges& rc = ranges[wv][0];
+    for (int e = lane; e < rc.total; e += 64) {
+        const int j = candidate(rc, cell_ids, e);
+        if (j == i) continue;
+        double r[3];
+        for (int a = 0; a < 3; ++a) r[a] = min_img(Ri[a] - st[j].R[a], box_len(kp, a), kp.per[a]);
+        if (r[0] * r[0] + r[1] * r[1] + r[2] * r[2] > rcc2) continue;
+        double Aj[9];
+        shape_matrix(kp, st[j].Q, Aj);
+        bad |= gb_pair(kp, r, Ai, Aj, smin_cc, F, tl);
+    }
+    if (kp.wall_particles) {
+        const CandidateRanges& rw = ranges[wv][1];
+        for (int e = lane; e < rw.total; e += 64) {
+            const int wq = candidate(rw, wcell_ids, e);
+            double r[3];
+            for (int a = 0; a < 3; ++a)
+                r[a] = min_img(Ri[a] - (double)wall_xyz[3 * wq + a], box_len(kp, a), kp.per[a]);
+            if (r[0] * r[0] + r[1] * r[1] + r[2] * r[2] > rcw2) continue;
+            bad |= gb_pair(kp, r, Ai, Aw, kp.sigmin_wall, F, tl);
+        }
+    }
     for (int o = 32; o > 0; o >>= 1) {
         for (int a = 0; a < 3; ++a) {
             F[a] += __shfl_down(F[a], o, 64);
@@ -632,7 +710,7 @@ void launch_map_couple(const CellBuffers& b, const KParams& kp, hipStream_t st)
 {
     const size_t t3 = (size_t)kp.tile_max * kp.tile_max * kp.tile_max;
     const size_t lds = t3 * sizeof(RT) + t3;
-    hipLaunchKernelGGL((k_map_couple<RT>), dim3(grid8(kp.nrbc, 1)), dim3(256), lds, st, b.st, b.cp,
+    hipLaunchKernelGGL((k_map_couple<RT>), dim3(grid8(kp.nrbc, 1)), dim3(MC_THREADS), lds, st, b.st, b.cp,
                        b.nodeword, b.map_ids, (RT*)b.map_vals, b.cell_ids, (const RT*)b.u,
                        (const RT*)b.sig, kp, b.err);
 }

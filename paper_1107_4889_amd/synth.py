@@ -28,6 +28,7 @@ from __future__ import annotations
 import hashlib
 import math
 import os
+import sys
 from dataclasses import dataclass
 
 import numpy as np
@@ -384,7 +385,9 @@ def place_cells(solid: np.ndarray, axes, n_target: int, seed: int, periodic=(0, 
 def _relax(pk: "_Packer", Rs, As, s_accept, max_iter):
     box, per = pk.box, pk.per
     Rs = Rs.copy()
-    for _ in range(max_iter):
+    for it in range(max_iter):
+        if it % 10 == 0:
+            print(f"[synth] overlap removal sweep {it}", file=sys.stderr, flush=True)
         disp = np.zeros_like(Rs)
         worst = 1.0
         tree = _tree(Rs, box, per)
@@ -468,6 +471,8 @@ def cached_placement(key: str, make):
         z = np.load(fn)
         return Placement(R=z["R"], Q=z["Q"], hematocrit=float(z["H"]), s_pair=float(z["s"]),
                          attempts=int(z["att"]))
+    print(f"[synth] generating placement {key} (cached afterwards in {d})", file=sys.stderr,
+          flush=True)
     pl = make()
     try:
         os.makedirs(d, exist_ok=True)
@@ -484,7 +489,7 @@ def tube_workload(nx, ny, nz, radius, hematocrit=None, n_cells=None, seed=1107, 
     solid = tube(nx, ny, nz, radius)
     if n_cells is None:
         n_cells = hematocrit_count(solid, AXES, hematocrit or 0.0)
-    key = f"tube:{nx}:{ny}:{nz}:{radius}:{n_cells}:{seed}:{sorted(kw.items())}:{PLACEMENT_VERSION}"
+    key = f"tube:{nx}:{ny}:{nz}:{float(radius):g}:{n_cells}:{seed}:{sorted(kw.items())}:{PLACEMENT_VERSION}"
     pl = cached_placement(key, lambda: place_cells(solid, AXES, n_cells, seed,
                                                    periodic=(0, 0, 1), **kw))
     return solid, pl
