@@ -191,6 +191,8 @@ class Simulation:
         self.device = torch.device(device)
         self.arena = torch.empty(self.bytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # the arena comes from torch's caching allocator: tie its reuse to this stream's work
+        self.arena.record_stream(self.stream)
         h = _P()
         st = _lib.lb_init(ctypes.byref(self.cfg), self.solid.ctypes.data, cells, n,
                           ctypes.c_void_p(self.arena.data_ptr()), self.bytes,

@@ -1,0 +1,212 @@
+"""Continuous-batching request loop: many vessel simulations resident on one GPU.
+
+Requests (a vessel, a cell count, a number of steps) arrive over time. A request is admitted
+as soon as its HBM footprint fits the budget next to the requests already resident; it then
+gets its own arena, its own HIP stream (default priority) and its own context of the C
+library. Every scheduler tick enqueues the next chunk of steps of every resident request
+with one ``lb_batch_step`` call, which interleaves the requests step by step, so their
+kernels overlap on the device. Optionally each request's chunk is captured once into a HIP
+graph (through PyTorch's graph API on the request's stream) and replayed. A request finishes
+when its last chunk's event has completed; its memory is released and queued requests are
+admitted in the same tick. Latency = completion time - arrival time.
+"""
+from __future__ import annotations
+
+import hashlib
+import heapq
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import lbrbc
+
+_CKPT_HEADER = 56     # bytes of the checkpoint header (holds the host step counter)
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float            # seconds after the start of the run
+    cfg: dict                 # lattice configuration (lbrbc config keys)
+    solid: np.ndarray         # (nz, ny, nx) uint8
+    R: np.ndarray             # (n, 3) cell centres
+    Q: np.ndarray             # (n, 9) orientations
+    steps: int
+
+
+@dataclass
+class Result:
+    rid: int
+    arrival: float
+    admitted: float
+    finished: float
+    steps: int
+    n_fluid: int
+    n_cells: int
+    footprint: int
+    flow_rate: float
+    eta_app: float
+    wss_mean: float
+    mass: float
+    flags: int
+    digest: str = None        # SHA-1 of the final state (populations, fields, cells)
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+@dataclass
+class _Active:
+    req: Request
+    sim: lbrbc.Simulation
+    stream: torch.cuda.Stream
+    admitted: float
+    done_steps: int = 0
+    events: list = field(default_factory=list)
+    graph: object = None
+    graph_steps: int = 0
+
+
+class Server:
+    """Admission by footprint, interleaved batched steps, completion by events."""
+
+    def __init__(self, budget_bytes: int, chunk_steps: int = 50, use_graphs: bool = False,
+                 device: str = "cuda:0", max_inflight_chunks: int = 2, digests: bool = False,
+                 max_active: int = 64, progress=None):
+        if use_graphs and chunk_steps % 2:
+            raise ValueError("graph chunks need an even step count (A/B buffers)")
+        self.budget = int(budget_bytes)
+        self.chunk = int(chunk_steps)
+        self.use_graphs = use_graphs
+        self.device = device
+        self.max_inflight = max_inflight_chunks
+        self.digests = digests
+        self.max_active = int(max_active)
+        self.progress = progress       # called with each Result as it retires
+        self.queue: list = []          # (arrival, rid, Request)
+        self.active: dict = {}
+        self.used = 0
+        self.results: list = []
+        self.t0 = None
+
+    # -- admission ------------------------------------------------------------------------
+    def footprint(self, req: Request) -> int:
+        c = lbrbc.make_config(req.cfg)
+        return lbrbc.lb_query_footprint(c, np.ascontiguousarray(req.solid).reshape(-1), len(req.R))
+
+    def submit(self, req: Request):
+        heapq.heappush(self.queue, (req.arrival, req.rid, req))
+
+    def _now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def _admit(self):
+        while self.queue:
+            arrival, rid, req = self.queue[0]
+            if arrival > self._now():
+                break
+            fp = self.footprint(req)
+            if fp > self.budget:
+                raise ValueError(f"request {rid} needs {fp} B, more than the whole budget")
+            if self.used + fp > self.budget or len(self.active) >= self.max_active:
+                break                                   # first come, first served
+            heapq.heappop(self.queue)
+            stream = torch.cuda.Stream(device=self.device)
+            sim = lbrbc.Simulation(req.cfg, req.solid, R=req.R if len(req.R) else None,
+                                   Q=req.Q if len(req.R) else None, device=self.device,
+                                   stream=stream)
+            self.used += fp
+            self.active[rid] = _Active(req, sim, stream, self._now())
+            self.active[rid].footprint = fp
+
+    # -- stepping -------------------------------------------------------------------------
+    def _graph_for(self, a: _Active):
+        """Capture `chunk` steps of this request once (even count: the A/B parity returns)."""
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(a.stream):
+            with torch.cuda.graph(g, stream=a.stream):
+                a.sim.lb_step(self.chunk)
+        a.graph = g
+        a.graph_steps = self.chunk
+
+    def _enqueue(self):
+        eager, counts = [], []
+        for a in self.active.values():
+            left = a.req.steps - a.done_steps
+            if left <= 0 or len(a.events) >= self.max_inflight:
+                continue
+            n = min(self.chunk, left)
+            a.done_steps += n
+            if self.use_graphs and n == self.chunk:
+                if a.graph is None:
+                    self._graph_for(a)
+                with torch.cuda.stream(a.stream):
+                    a.graph.replay()
+                ev = torch.cuda.Event()
+                ev.record(a.stream)
+                a.events.append(ev)
+            else:
+                eager.append(a)
+                counts.append(n)
+        if eager:
+            lbrbc.lb_batch_step([a.sim for a in eager], counts)
+            for a in eager:
+                ev = torch.cuda.Event()
+                ev.record(a.stream)
+                a.events.append(ev)
+
+    def _retire(self):
+        for rid in list(self.active):
+            a = self.active[rid]
+            while a.events and a.events[0].query():
+                a.events.pop(0)
+            if a.done_steps >= a.req.steps and not a.events:
+                a.stream.synchronize()
+                o = a.sim.lb_observe()
+                digest = hashlib.sha1(a.sim.lb_save()[_CKPT_HEADER:]).hexdigest() if self.digests else None
+                res = Result(
+                    rid=rid, arrival=a.req.arrival, admitted=a.admitted, finished=self._now(),
+                    steps=a.req.steps, n_fluid=int(o.n_fluid), n_cells=int(o.n_rbc),
+                    footprint=a.footprint, flow_rate=o.flow_rate, eta_app=o.eta_app,
+                    wss_mean=o.wss_mean, mass=o.mass, flags=int(o.flags), digest=digest)
+                self.results.append(res)
+                if self.progress:
+                    self.progress(res)
+                self.used -= a.footprint
+                a.graph = None
+                del a.sim
+                del self.active[rid]
+
+    def run(self, requests, realtime: bool = True):
+        """Replay the requests' arrivals in wall-clock time and serve them to completion."""
+        for r in requests:
+            self.submit(r if realtime else Request(**{**r.__dict__, "arrival": 0.0}))
+        self.t0 = time.perf_counter()
+        while self.queue or self.active:
+            self._admit()
+            if self.active:
+                self._enqueue()
+                self._retire()
+            elif self.queue:
+                wait = self.queue[0][0] - self._now()
+                if wait > 0:
+                    time.sleep(min(wait, 0.01))
+            time.sleep(0)
+        makespan = self._now()
+        return sorted(self.results, key=lambda r: r.rid), makespan
+
+
+def summary(results, makespan: float) -> dict:
+    lat = np.array([r.latency for r in results])
+    work = sum(r.n_fluid * r.steps for r in results)
+    return {
+        "requests": len(results),
+        "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else None,
+        "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else None,
+        "aggregate_mlups": work / makespan / 1e6 if makespan > 0 else None,
+        "makespan_s": makespan,
+        "failed": int(sum(1 for r in results if r.flags)),
+    }

@@ -284,7 +284,7 @@ class _Packer:
 
 def place_cells(solid: np.ndarray, axes, n_target: int, seed: int, periodic=(0, 0, 1),
                 a_wall: float = 0.5, batch: int = 8192, rsa_attempts_per_cell: int = 4,
-                s_accept: float = 0.97, max_iter: int = 200) -> Placement:
+                s_accept: float = 0.97, max_iter: int = 200, fill: bool = True) -> Placement:
     """Random sequential addition without contact, then, for the cells that did not fit,
     random valid centres followed by geometric overlap removal: every pair with contact
     function c < 1 is pushed apart along its centre line by half its deficit
@@ -335,7 +335,7 @@ def place_cells(solid: np.ndarray, axes, n_target: int, seed: int, periodic=(0, 
             Rs = np.concatenate([Rs, _wrap(c[acc], box, per)])
             As = np.concatenate([As, Ac[acc]])
             Qs = np.concatenate([Qs, Qc[acc]])
-    if len(Rs) < n_target:
+    if len(Rs) < n_target and fill:
         # remaining cells at random centres whose node is fluid, then overlap removal
         need = n_target - len(Rs)
         extra_R, extra_Q = [], []
@@ -493,3 +493,71 @@ def tube_workload(nx, ny, nz, radius, hematocrit=None, n_cells=None, seed=1107, 
     pl = cached_placement(key, lambda: place_cells(solid, AXES, n_cells, seed,
                                                    periodic=(0, 0, 1), **kw))
     return solid, pl
+
+
+def chevron(nx: int, ny: int, nz: int, radius: float, offset: float) -> np.ndarray:
+    """Tube periodic along z with one bend per period: the centre line runs straight from
+    (x0, cy, 0) to (x0 + offset, cy, nz/2) and back to (x0, cy, nz), x0 = radius + 2 (union
+    of capsules, with the periodic images of both segments)."""
+    cy = (ny - 1) / 2.0
+    x0 = radius + 2.0
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    P = np.stack([xx, yy, zz], -1).astype(np.float64)
+    h = nz / 2.0
+    fl = np.zeros((nz, ny, nx), dtype=bool)
+    for z0 in (-nz, 0.0, nz):
+        fl |= _capsule_fluid(P, (x0, cy, z0), (x0 + offset, cy, z0 + h), radius)
+        fl |= _capsule_fluid(P, (x0 + offset, cy, z0 + h), (x0, cy, z0 + nz), radius)
+    return (~fl).astype(np.uint8)
+
+
+def _trace_request(args):
+    k, seed, R, L, H, steps, bent, fill = args
+    n = int(2 * math.ceil(R) + 4)
+    nz = max(L, 24)
+    if bent:
+        off = float(np.round(0.5 * nz * math.tan(math.radians(10.0))))
+        nx = n + int(off)
+        solid = chevron(nx, n, nz, R, off)
+    else:
+        nx = n
+        solid = tube(n, n, nz, R)
+    n_cells = hematocrit_count(solid, AXES, H)
+    key = (f"serve:{seed}:{k}:{nx}:{n}:{nz}:{R:.6f}:{int(bent)}:{n_cells}:{fill}:"
+           f"{PLACEMENT_VERSION}")
+    pl = cached_placement(key, lambda: place_cells(solid, AXES, n_cells, seed * 1000 + k,
+                                                   periodic=(0, 0, 1), fill=fill))
+    return dict(nx=nx, ny=n, nz=nz, radius=R, bent=bent, solid=solid, R=pl.R, Q=pl.Q,
+                hematocrit=pl.hematocrit, target_hematocrit=H)
+
+
+def serving_trace(n_requests: int, rate_hz: float, seed: int = 2011, r_range=(8.0, 32.0),
+                  k_range=(4.0, 16.0), h_range=(0.20, 0.50), steps_range=(500, 5000),
+                  bent_fraction: float = 0.0, fill: bool = False, workers: int = 1):
+    """A seeded stream of vessel requests: Poisson arrivals (exponential gaps at `rate_hz`),
+    periodic tubes of radius R ~ U(r_range) and length k R with k ~ U(k_range), straight or,
+    with probability `bent_fraction`, a chevron with a 20-degree bend; target hematocrit
+    ~ U(h_range) (random sequential addition only unless `fill`: the achieved value is
+    returned); steps ~ U{steps_range}. Returns a list of dicts in arrival order."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    jobs, arrivals = [], []
+    for k in range(n_requests):
+        t += rng.exponential(1.0 / rate_hz)
+        R = float(rng.uniform(*r_range))
+        L = int(round(float(rng.uniform(*k_range)) * R))
+        H = float(rng.uniform(*h_range))
+        steps = int(rng.integers(steps_range[0], steps_range[1] + 1))
+        bent = bool(rng.uniform() < bent_fraction)
+        jobs.append((k, seed, R, L, H, steps, bent, fill))
+        arrivals.append(t)
+    if workers > 1 and n_requests > 1:
+        from concurrent.futures import ProcessPoolExecutor
+
+        with ProcessPoolExecutor(max_workers=workers) as ex:
+            done = list(ex.map(_trace_request, jobs, chunksize=1))
+    else:
+        done = [_trace_request(j) for j in jobs]
+    for j, d, a in zip(jobs, done, arrivals):
+        d.update(rid=j[0], arrival=a, steps=j[5])
+    return done
