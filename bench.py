@@ -167,6 +167,90 @@ def serve(args):
     print(json.dumps(line), flush=True)
 
 
+def precision(args):
+    """Reduced-precision storage against FP64 on the same GPU: a 64x64x256 tube of radius
+    30 lu at target hematocrit 0.40 (the subsample of the 256x256x1024 study), run for
+    --steps steps in each storage; velocity and wall-shear-stress errors against the FP64
+    run, with and without cells (the FP64 path itself is held to the oracle by the parity
+    tests, also at this size)."""
+    import numpy as np
+    import torch
+
+    from paper_1107_4889_amd import lbrbc, synth
+
+    nx, ny, nz, R, H = 64, 64, 256, 30.0, 0.40
+    solid, pl = synth.tube_workload(nx, ny, nz, R, hematocrit=H, seed=1107)
+    fluid = (solid.reshape(-1) == 0)
+    n_fluid = int(fluid.sum())
+    print(f"[precision] tube {nx}x{ny}x{nz} R={R:g}, {len(pl.R)} cells (H={pl.hematocrit:.3f})",
+          file=sys.stderr, flush=True)
+
+    def cfg(st):
+        return dict(nx=nx, ny=ny, nz=nz, periodic=(0, 0, 1), tau0=0.8, g_ext=(0.0, 0.0, 1e-6),
+                    storage=st, f16_scale=2.0 ** 21)
+
+    def run(st, cells):
+        sim = lbrbc.Simulation(cfg(st), solid, R=pl.R if cells else None,
+                               Q=pl.Q if cells else None)
+        half = args.steps // 2
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.lb_step(half)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        sim.lb_wss_accumulate(True)
+        t0 = time.perf_counter()
+        sim.lb_step(args.steps - half)
+        torch.cuda.synchronize()
+        dt += time.perf_counter() - t0
+        obs = sim.lb_observe()
+        u = sim.lb_get_fields(f=False, u=True, sigma=False)["u"][fluid]
+        _, wss = sim.lb_wall_shear_stress(False)
+        _, wss_t = sim.lb_wall_shear_stress(True)
+        Rc = sim.rbc_get_state()[0] if cells else None
+        print(f"[precision] {st} {'cells' if cells else 'plasma'}: {args.steps} steps in {dt:.2f} s, "
+              f"flags {obs.flags}", file=sys.stderr, flush=True)
+        return dict(u=u, wss=wss, wss_t=wss_t, eta=obs.eta_app, Q=obs.flow_rate, R=Rc,
+                    mlups=n_fluid * args.steps / dt / 1e6, flags=int(obs.flags))
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+    out = {}
+    for cells in (False, True):
+        key = "cells" if cells else "plasma_only"
+        ref = run("f64", cells)
+        rows = {"f64": {"mlups": round(ref["mlups"], 1), "flags": ref["flags"]}}
+        for st in ("f32", "bf16", "f16"):
+            r = run(st, cells)
+            row = {
+                "mlups": round(r["mlups"], 1),
+                "speedup_vs_f64": round(r["mlups"] / ref["mlups"], 3),
+                "u_rel_l2": rel(r["u"], ref["u"]),
+                "u_max_abs_over_umax": float(np.abs(r["u"] - ref["u"]).max() / np.abs(ref["u"]).max()),
+                "wss_rel_l2": rel(r["wss"], ref["wss"]),
+                "wss_time_avg_rel_l2": rel(r["wss_t"], ref["wss_t"]),
+                "eta_app_rel": abs(r["eta"] - ref["eta"]) / abs(ref["eta"]),
+                "flags": r["flags"],
+            }
+            if cells:
+                d = r["R"] - ref["R"]
+                d[:, 2] -= nz * np.round(d[:, 2] / nz)
+                row["cell_pos_rms_lu"] = float(np.sqrt((d ** 2).sum(1).mean()))
+            rows[st] = row
+        out[key] = rows
+
+    line = {
+        "metric": "velocity / wall-shear-stress error of reduced-precision storage vs FP64, and MLUPS",
+        "config": {"workload": (f"tube {nx}x{ny}x{nz} R={R:g} periodic z, {len(pl.R)} cells "
+                                f"(H={pl.hematocrit:.3f}, target {H}), T0=0.8, g=1e-6, "
+                                f"{args.steps} steps; WSS time average over the second half"),
+                   "n_fluid": n_fluid},
+        "results": out,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,6 +270,8 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--max-active", type=int, default=64)
     ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--precision", action="store_true",
+                    help="reduced-precision storage study against FP64 on the same GPU")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the hot path runs "
@@ -207,6 +293,9 @@ def main():
 
     if args.serve:
         serve(args)
+        return
+    if args.precision:
+        precision(args)
         return
 
     from paper_1107_4889_amd import lbrbc

@@ -166,12 +166,13 @@ __device__ __forceinline__ RT feq_shift(int p, RT drho, RT rho, RT ux, RT uy, RT
 }
 
 // BGK with body force for the pair (P, P+1) of opposite speeds: the equilibrium and the
-// force term split into parts even and odd in c, shared by the two directions.
+// force term split into parts even and odd in c, shared by the two directions. Lanes that
+// do not hold a fluid node (live == false) store zero.
 template <typename ST, typename RT, int P>
 __device__ __forceinline__ void collide_pair(const RT* f, const Planes<ST, RT>& pl, unsigned n,
                                              RT drho, RT rho, RT ux, RT uy, RT uz, RT usq,
                                              const RT g[3], RT gu, RT om, RT kf, RT k2, RT k3,
-                                             const KParams& kp)
+                                             const KParams& kp, bool live)
 {
     constexpr int Q = P + 1;
     const RT w = RT(w_(P));
@@ -181,23 +182,29 @@ __device__ __forceinline__ void collide_pair(const RT* f, const Planes<ST, RT>& 
     const RT asym = w * rho * RT(3) * uc;
     const RT fs = kf * w * (k2 * gc * uc - k3 * gu);
     const RT fa = kf * w * RT(3) * gc;
-    Store<ST, RT>::st(pl.out[P], n, f[P] - om * (f[P] - sym - asym) + fs + fa, kp.f16_scale);
-    Store<ST, RT>::st(pl.out[Q], n, f[Q] - om * (f[Q] - sym + asym) + fs - fa, kp.f16_scale);
+    Store<ST, RT>::st(pl.out[P], n, live ? f[P] - om * (f[P] - sym - asym) + fs + fa : RT(0), kp.f16_scale);
+    Store<ST, RT>::st(pl.out[Q], n, live ? f[Q] - om * (f[Q] - sym + asym) + fs - fa : RT(0), kp.f16_scale);
 }
 
 template <typename ST, typename RT, int... Ps>
 __device__ __forceinline__ void collide_pairs(const RT* f, const Planes<ST, RT>& pl, unsigned n,
                                               RT drho, RT rho, RT ux, RT uy, RT uz, RT usq,
                                               const RT g[3], RT gu, RT om, RT kf, RT k2, RT k3,
-                                              const KParams& kp, std::integer_sequence<int, Ps...>)
+                                              const KParams& kp, bool live,
+                                              std::integer_sequence<int, Ps...>)
 {
-    (collide_pair<ST, RT, 2 * Ps + 1>(f, pl, n, drho, rho, ux, uy, uz, usq, g, gu, om, kf, k2, k3, kp), ...);
+    (collide_pair<ST, RT, 2 * Ps + 1>(f, pl, n, drho, rho, ux, uy, uz, usq, g, gu, om, kf, k2, k3, kp, live), ...);
 }
 
 // ---- fused spreading + stream + collide (Sec. II A, Eqs. 1-8) -----------------------------
 // One thread per node; SoA planes f[p*ld + n] of the shifted populations f - w.
 // Launch: blocks of 64 x 4 threads (a wavefront spans 64 consecutive x), grid
 // (ceil(nx/64), ceil(ny/4), nz): no integer division, 32-bit node offsets.
+// A wavefront with no fluid node exits. In a wavefront that has one, every lane stores all
+// 28 outputs (zero at solid and open-plane nodes, whose values are never read: pulls from
+// solid sources are replaced by bounce-back, open planes are rewritten by the boundary
+// kernel), so that each store writes whole cache lines: stores that leave part of a line
+// unwritten, as at every wall crossing of a lattice row, measured markedly slower in HBM.
 template <typename ST, typename RT>
 __global__ __launch_bounds__(256) void k_stream_collide(
     const Planes<ST, RT> pl, const uint32_t* __restrict__ nodeword, const MapPlanes<RT> mp,
@@ -209,10 +216,16 @@ __global__ __launch_bounds__(256) void k_stream_collide(
     if (x >= kp.nx || y >= kp.ny) return;
     const unsigned n = (unsigned)x + (unsigned)kp.nx * ((unsigned)y + (unsigned)kp.ny * (unsigned)z);
     const uint32_t w = nodeword[n];
-    if (!(w & NW_FLUID) || (w & NW_OPEN)) return;
+    const bool live = (w & NW_FLUID) && !(w & NW_OPEN);
+    if (!__any(live)) return;
     RT f[19];
-    pull_all_fast<ST, RT>(f, pl, n, x, y, z, kp, std::make_integer_sequence<int, 19>{});
-    if (w & 0x7FFFEu) bounce_back<ST, RT>(f, pl, n, w, kp, std::make_integer_sequence<int, 19>{});
+    if (live) {
+        pull_all_fast<ST, RT>(f, pl, n, x, y, z, kp, std::make_integer_sequence<int, 19>{});
+        if (w & 0x7FFFEu) bounce_back<ST, RT>(f, pl, n, w, kp, std::make_integer_sequence<int, 19>{});
+    } else {
+#pragma unroll
+        for (int p = 0; p < 19; ++p) f[p] = RT(0);
+    }
 
     RT g[3], theta;
     spread_at<RT>(n, w, nodeword, mp, gat, kp, g, theta);
@@ -251,25 +264,26 @@ __global__ __launch_bounds__(256) void k_stream_collide(
         const RT w0 = RT(w_(0));
         const RT fe0 = w0 * (drho - RT(1.5) * rho * usq);
         const RT F0 = -kf * w0 * k3 * gu;
-        Store<ST, RT>::st(pl.out[0], n, f[0] - om * (f[0] - fe0) + F0, kp.f16_scale);
+        Store<ST, RT>::st(pl.out[0], n, live ? f[0] - om * (f[0] - fe0) + F0 : RT(0), kp.f16_scale);
     }
-    collide_pairs<ST, RT>(f, pl, n, drho, rho, ux, uy, uz, usq, g, gu, om, kf, k2, k3, kp,
+    collide_pairs<ST, RT>(f, pl, n, drho, rho, ux, uy, uz, usq, g, gu, om, kf, k2, k3, kp, live,
                           std::make_integer_sequence<int, 9>{});
 
     // stress of the non-equilibrium part: sigma = -(1 - 1/(2T)) sum c c (f - f^eq), with
     // sum c c f^eq - w = drho/3 delta + rho u u
     const RT ks = -(RT(1) - RT(0.5) * om);
     const RT d3 = drho * RT(1.0 / 3.0);
-    __builtin_nontemporal_store(ux, at32(pl.u[0], n));
-    __builtin_nontemporal_store(uy, at32(pl.u[1], n));
-    __builtin_nontemporal_store(uz, at32(pl.u[2], n));
-    __builtin_nontemporal_store(ks * (pxx - d3 - rho * ux * ux), at32(pl.sig[0], n));
-    __builtin_nontemporal_store(ks * (pyy - d3 - rho * uy * uy), at32(pl.sig[1], n));
-    __builtin_nontemporal_store(ks * (pzz - d3 - rho * uz * uz), at32(pl.sig[2], n));
-    __builtin_nontemporal_store(ks * (pxy - rho * ux * uy), at32(pl.sig[3], n));
-    __builtin_nontemporal_store(ks * (pxz - rho * ux * uz), at32(pl.sig[4], n));
-    __builtin_nontemporal_store(ks * (pyz - rho * uy * uz), at32(pl.sig[5], n));
-    if (!(rho > RT(0)) || !(usq <= RT(0.09))) atomicOr(err, ERR_UNSTABLE);
+    const RT z0 = RT(0);
+    __builtin_nontemporal_store(live ? ux : z0, at32(pl.u[0], n));
+    __builtin_nontemporal_store(live ? uy : z0, at32(pl.u[1], n));
+    __builtin_nontemporal_store(live ? uz : z0, at32(pl.u[2], n));
+    __builtin_nontemporal_store(live ? ks * (pxx - d3 - rho * ux * ux) : z0, at32(pl.sig[0], n));
+    __builtin_nontemporal_store(live ? ks * (pyy - d3 - rho * uy * uy) : z0, at32(pl.sig[1], n));
+    __builtin_nontemporal_store(live ? ks * (pzz - d3 - rho * uz * uz) : z0, at32(pl.sig[2], n));
+    __builtin_nontemporal_store(live ? ks * (pxy - rho * ux * uy) : z0, at32(pl.sig[3], n));
+    __builtin_nontemporal_store(live ? ks * (pxz - rho * ux * uz) : z0, at32(pl.sig[4], n));
+    __builtin_nontemporal_store(live ? ks * (pyz - rho * uy * uz) : z0, at32(pl.sig[5], n));
+    if (live && (!(rho > RT(0)) || !(usq <= RT(0.09)))) atomicOr(err, ERR_UNSTABLE);
 }
 
 // ---- open z faces: non-equilibrium extrapolation (Guo, Zheng & Shi 2002) ------------------
