@@ -369,10 +369,13 @@ __global__ __launch_bounds__(256) void k_spread_field(const uint32_t* __restrict
     tout[n] = (RT)kp.tau0 + (RT)kp.delta * th;
 }
 
-// ---- coverage counters: clear the count byte, keep the static bits ------------------------
-__global__ __launch_bounds__(256) void k_clear_counts(uint32_t* __restrict__ nodeword, long long N)
+// ---- coverage counters: clear the count byte, keep the static bits; clear the count of
+// the map pass's overflow list ------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_clear_counts(uint32_t* __restrict__ nodeword, long long N,
+                                                      int* __restrict__ ovf)
 {
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n == 0 && ovf) ovf[0] = 0;
     if (n < N) {
         const uint32_t w = nodeword[n];
         if (w >> 24) nodeword[n] = w & NW_STATIC;
@@ -491,10 +494,10 @@ void launch_spread_field(const uint32_t* nodeword, const int* ids, const void* v
                        map_planes<RT>(ids, vals, kp), (const Gather<RT>*)gat, (RT*)g, (RT*)t, kp);
 }
 
-void launch_clear_counts(uint32_t* nodeword, long long N, hipStream_t st)
+void launch_clear_counts(uint32_t* nodeword, long long N, int* ovf, hipStream_t st)
 {
     hipLaunchKernelGGL(k_clear_counts, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
-                       nodeword, N);
+                       nodeword, N, ovf);
 }
 
 template <typename ST, typename RT>

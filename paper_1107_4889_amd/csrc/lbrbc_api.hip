@@ -37,7 +37,87 @@ struct Geometry {
     double rc = 0;
     std::vector<int> wcell_off, wcell_ids;
     int tile_max = 0;
+    int cand_cap = 0;
 };
+
+// Capacity of the one-wavefront map pass: the largest number of candidate nodes (the
+// covered x-range of every support-tile row, computed as the kernel does) over 4096
+// orientations and sub-node offsets from a fixed generator, with 20% and 64 nodes of margin;
+// at least tile_max^2 (the pass also keeps two row tables there) and at most tile_max^3 (the
+// tile). A cell that still has more takes the full-tile pass, so the bound needs no proof.
+int candidate_capacity(const double* xi, int tm)
+{
+    uint64_t x = 0x9E3779B97F4A7C15ull;
+    auto next = [&]() {   // xorshift64*, uniform in (0, 1)
+        x ^= x >> 12;
+        x ^= x << 25;
+        x ^= x >> 27;
+        return ((double)((x * 0x2545F4914F6CDD1Dull) >> 11) + 0.5) / 9007199254740992.0;
+    };
+    int most = 0;
+    std::vector<int> lo_r, hi_r;
+    for (int k = 0; k < 4096; ++k) {
+        // uniform rotation from a unit quaternion (normal deviates by Box-Muller)
+        double q[4];
+        for (int a = 0; a < 4; a += 2) {
+            const double r1 = std::sqrt(-2.0 * std::log(next())), t = 6.283185307179586 * next();
+            q[a] = r1 * std::cos(t);
+            q[a + 1] = r1 * std::sin(t);
+        }
+        const double qn = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        const double w = q[0] / qn, i = q[1] / qn, j = q[2] / qn, l = q[3] / qn;
+        const double Q[9] = {1 - 2 * (j * j + l * l), 2 * (i * j - w * l), 2 * (i * l + w * j),
+                             2 * (i * j + w * l), 1 - 2 * (i * i + l * l), 2 * (j * l - w * i),
+                             2 * (i * l - w * j), 2 * (j * l + w * i), 1 - 2 * (i * i + j * j)};
+        double R[3];
+        for (int a = 0; a < 3; ++a) R[a] = 64.0 + next();
+        int lo[3], sz[3];
+        for (int a = 0; a < 3; ++a) {
+            const double ext = std::fabs(Q[3 * a]) * xi[0] + std::fabs(Q[3 * a + 1]) * xi[1] +
+                               std::fabs(Q[3 * a + 2]) * xi[2];
+            lo[a] = (int)std::floor(R[a] - ext) - 1;
+            sz[a] = (int)std::ceil(R[a] + ext) + 1 - lo[a] + 1;
+        }
+        if (sz[0] > tm || sz[1] > tm || sz[2] > tm) continue;
+        const int rows = sz[1] * sz[2];
+        lo_r.assign(rows, 0);
+        hi_r.assign(rows, 0);
+        const double X0 = R[0] - lo[0];
+        for (int r = 0; r < rows; ++r) {
+            const double dy = lo[1] + r % sz[1] - R[1], dz = lo[2] + r / sz[1] - R[2];
+            double xa = -1e30, xb = 1e30;
+            for (int a = 0; a < 3; ++a) {
+                const double qa = Q[a], b = Q[3 + a] * dy + Q[6 + a] * dz;
+                if (std::fabs(qa) > 1e-12) {
+                    const double u0 = (-xi[a] - b) / qa, u1 = (xi[a] - b) / qa;
+                    xa = std::max(xa, std::min(u0, u1));
+                    xb = std::min(xb, std::max(u0, u1));
+                } else if (std::fabs(b) >= xi[a] + 1e-9) {
+                    xa = 1e30;
+                }
+            }
+            lo_r[r] = sz[0];
+            hi_r[r] = -1;
+            if (xa <= xb) {
+                lo_r[r] = std::max(0, (int)std::floor(X0 + xa) - 1);
+                hi_r[r] = std::min(sz[0] - 1, (int)std::ceil(X0 + xb) + 1);
+            }
+        }
+        int tot = 0;
+        for (int r = 0; r < rows; ++r) {
+            const int ty = r % sz[1], tz = r / sz[1];
+            int a = lo_r[r] - 1, b = hi_r[r] + 1;
+            if (ty > 0) { a = std::min(a, lo_r[r - 1]); b = std::max(b, hi_r[r - 1]); }
+            if (ty + 1 < sz[1]) { a = std::min(a, lo_r[r + 1]); b = std::max(b, hi_r[r + 1]); }
+            if (tz > 0) { a = std::min(a, lo_r[r - sz[1]]); b = std::max(b, hi_r[r - sz[1]]); }
+            if (tz + 1 < sz[2]) { a = std::min(a, lo_r[r + sz[1]]); b = std::max(b, hi_r[r + sz[1]]); }
+            tot += std::max(0, std::min(b, sz[0] - 1) - std::max(a, 0) + 1);
+        }
+        most = std::max(most, tot);
+    }
+    const int cap = ((int)(1.2 * most) + 64 + 63) / 64 * 64;
+    return std::min(std::max(cap, tm * tm), tm * tm * tm);
+}
 
 long long node_at(const lb_config& c, int x, int y, int z)
 {
@@ -161,8 +241,14 @@ std::string build_geometry(const lb_config& c, const uint8_t* solid, int n_rbc, 
     const double r = std::sqrt(c.xi[0] * c.xi[0] + c.xi[1] * c.xi[1] + c.xi[2] * c.xi[2]);
     g.tile_max = 2 * (int)std::ceil(r) + 5;
     if (n_rbc > 0) {
-        // the double-precision interpolation tile (tile_max^3 values) must fit 64 KiB of LDS
-        if (g.tile_max > 20) return "shape-function support too large for the LDS tile";
+        // The full-tile map pass keeps tile_max^3 kernel values, a flag byte each and a
+        // 2-byte position list in LDS, next to about 3.5 KiB of fixed arrays; the
+        // one-wavefront pass keeps cand_cap candidates. Both within 64 KiB per workgroup.
+        g.cand_cap = candidate_capacity(c.xi, g.tile_max);
+        const int rb = real_bytes(c.storage);
+        if (g.tile_max > 20 || map_couple_tile_lds(g.tile_max, rb) + 4096 > 65536 ||
+            map_couple_lds(g.tile_max, g.cand_cap, rb) > 65536)
+            return "shape-function support too large for the LDS tile";
         for (int a = 0; a < 3; ++a)
             if (c.periodic[a] && L[a] < g.tile_max + 2) return "periodic axis shorter than a support tile";
         for (int a = 0; a < 3; ++a)
@@ -173,7 +259,7 @@ std::string build_geometry(const lb_config& c, const uint8_t* solid, int n_rbc, 
 
 // ---- arena layout --------------------------------------------------------------------------
 struct Layout {
-    size_t fA, fB, u, sig, gdbg, tdbg, nodeword, map_ids, map_vals, st, cp, gat, cellid, cell_cnt, cell_off,
+    size_t fA, fB, u, sig, gdbg, tdbg, nodeword, map_ids, map_vals, ovf, st, cp, gat, cellid, cell_cnt, cell_off,
         cell_ids, wall_xyz, wcell_off, wcell_ids, wn_node, wn_nrm, wss, wss_acc, planes, partials,
         obs_out, err, total;
 };
@@ -201,6 +287,7 @@ Layout layout(const lb_config& c, const Geometry& g, int n_rbc)
     L.nodeword = take(ld * 4);
     L.map_ids = take(n_rbc > 0 ? (size_t)cap * ld * 4 : 4);
     L.map_vals = take(n_rbc > 0 ? (size_t)cap * ld * 4 * rs : 4);
+    L.ovf = take(((size_t)n_rbc + 1) * 4);
     L.st = take(n_rbc * sizeof(RbcState));
     L.cp = take(n_rbc * sizeof(RbcCouple));
     L.gat = take(n_rbc * (rs == 8 ? sizeof(Gather<double>) : sizeof(Gather<float>)));
@@ -357,7 +444,7 @@ void enqueue_cells_map_couple(lb_ctx c)
 {
     hipStream_t s = c->stream;
     launch_cell_list(c->cb, c->kp, s);
-    launch_clear_counts(c->cb.nodeword, c->kp.N, s);
+    launch_clear_counts(c->cb.nodeword, c->kp.N, c->cb.ovf, s);
     launch_map_couple<RT>(c->cb, c->kp, s);
 }
 
@@ -475,6 +562,7 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
         kp.rc_wall = std::sqrt(2.0 * (amax * amax + C.a_wall * C.a_wall)) + shift * C.sigmin_wall;
     }
     kp.tile_max = g.tile_max;
+    kp.cand_cap = g.cand_cap;
 
     const Layout& L = c->lay;
     c->fA = c->at<void>(L.fA);
@@ -493,6 +581,7 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
     b.nodeword = c->at<uint32_t>(L.nodeword);
     b.map_ids = c->at<int>(L.map_ids);
     b.map_vals = c->at<void>(L.map_vals);
+    b.ovf = c->at<int>(L.ovf);
     b.u = c->at<void>(L.u);
     b.sig = c->at<void>(L.sig);
     b.err = c->at<unsigned>(L.err);

@@ -67,6 +67,7 @@ struct KParams {
     double rc_pair;   // cell-cell Gay-Berne cut-off bound
     double rc_wall;   // cell-wall Gay-Berne cut-off bound
     int tile_max;     // LDS tile edge bound
+    int cand_cap;     // candidate nodes per cell held in LDS by the one-wavefront map pass
 };
 
 // ---- per-cell records ---------------------------------------------------------------------

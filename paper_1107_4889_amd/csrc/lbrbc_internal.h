@@ -22,7 +22,7 @@ void launch_open_bc(const void* fin, void* fout, const uint32_t* nodeword, const
 template <typename RT>
 void launch_spread_field(const uint32_t* nodeword, const int* ids, const void* vals,
                          const void* gat, void* g, void* t, const KParams& kp, hipStream_t st);
-void launch_clear_counts(uint32_t* nodeword, long long N, hipStream_t st);
+void launch_clear_counts(uint32_t* nodeword, long long N, int* ovf, hipStream_t st);
 template <typename ST, typename RT>
 void launch_observe(const void* f, const uint32_t* nodeword, const void* u, const KParams& kp,
                     double* partials, int nblk, double* out, hipStream_t st);
@@ -48,12 +48,15 @@ struct CellBuffers {
     const void* u;        // [3 * ld] RT
     const void* sig;      // [6 * ld] RT
     unsigned* err;
+    int* ovf;             // [1 + nrbc] overflow count, then cells for the full-tile map pass
 };
 
 void launch_rb_first_half(const CellBuffers& b, const KParams& kp, hipStream_t st);
 void launch_cell_list(const CellBuffers& b, const KParams& kp, hipStream_t st);
 template <typename RT>
 void launch_map_couple(const CellBuffers& b, const KParams& kp, hipStream_t st);
+size_t map_couple_lds(int tile_max, int cand_cap, int real_bytes);   // dynamic LDS, bytes
+size_t map_couple_tile_lds(int tile_max, int real_bytes);
 void launch_gay_berne(const CellBuffers& b, const KParams& kp, hipStream_t st);
 template <typename RT>
 void launch_rb_second_half(const CellBuffers& b, const KParams& kp, int integrate, hipStream_t st);

@@ -218,26 +218,21 @@ constexpr int TILE_ROWS_MAX = 20 * 20;   // tile_max <= 20
 //         nodes; it needs u only at the node itself),
 //   T^S = alpha sum over inside nodes of dhat (sigma . n^) x (x - R), n^ = grad/|grad|.
 template <typename RT>
-__global__ __launch_bounds__(MC_THREADS) void k_map_couple(const RbcState* __restrict__ st,
-                                                           RbcCouple* __restrict__ cp,
-                                                           uint32_t* __restrict__ nodeword,
-                                                           int* __restrict__ ids,
-                                                           RT* __restrict__ vals,
-                                                           const int* __restrict__ order,
-                                                           const RT* __restrict__ u,
-                                                           const RT* __restrict__ sig, KParams kp,
-                                                           unsigned* __restrict__ err)
+__device__ void map_couple_tile(int i, unsigned char* smem, const RbcState* __restrict__ st,
+                                RbcCouple* __restrict__ cp, uint32_t* __restrict__ nodeword,
+                                int* __restrict__ ids, RT* __restrict__ vals,
+                                const RT* __restrict__ u, const RT* __restrict__ sig,
+                                const KParams& kp, unsigned* __restrict__ err)
 {
-    extern __shared__ unsigned char smem[];
     const int tm = kp.tile_max;
+    const unsigned t3 = (unsigned)(tm * tm * tm);
     RT* raw = reinterpret_cast<RT*>(smem);
-    unsigned char* flag = smem + (size_t)tm * tm * tm * sizeof(RT);  // 1 inside, 2 fluid
+    unsigned char* flag = smem + (size_t)t3 * sizeof(RT);  // 1 inside, 2 fluid
+    unsigned short* list = reinterpret_cast<unsigned short*>(smem + (((size_t)t3 * (sizeof(RT) + 1) + 1) & ~(size_t)1));
     __shared__ Tile T;
     __shared__ RT red[MC_THREADS / 64][10];
+    __shared__ int wcnt[MC_THREADS / 64];
     __shared__ short rlo[TILE_ROWS_MAX], rhi[TILE_ROWS_MAX], clo[TILE_ROWS_MAX], chi[TILE_ROWS_MAX];
-    const int k = xcd_chunk_index(1);
-    if (k >= kp.nrbc) return;
-    const int i = order[k];
     const RbcState& s = st[i];
     const int tid = threadIdx.x;
     if (tid == 0) support_tile(s, kp, T);
@@ -250,7 +245,7 @@ __global__ __launch_bounds__(MC_THREADS) void k_map_couple(const RbcState* __res
     const unsigned rows = sy * sz;
     // Conservative x-range of the support on each tile row (y, z): the body coordinates are
     // affine in x, y_a = Q_xa d_x + b_a, and |y_a| < xi_a cuts an interval; the exact test
-    // below decides each node, the range (widened by two nodes) only skips nodes that are
+    // below decides each node, the range (widened by one node) only skips nodes that are
     // certainly outside.
     for (unsigned r = tid; r < rows; r += MC_THREADS) {
         const int ty = (int)(r % sy), tz = (int)(r / sy);
@@ -270,8 +265,8 @@ __global__ __launch_bounds__(MC_THREADS) void k_map_couple(const RbcState* __res
         int lo = (int)sx, hi = -1;
         if (xa <= xb) {
             const double X0 = s.R[0] - (double)T.lo[0];
-            lo = max(0, (int)floor(X0 + xa) - 2);
-            hi = min((int)sx - 1, (int)ceil(X0 + xb) + 2);
+            lo = max(0, (int)floor(X0 + xa) - 1);
+            hi = min((int)sx - 1, (int)ceil(X0 + xb) + 1);
         }
         rlo[r] = (short)lo;
         rhi[r] = (short)hi;
@@ -324,19 +319,46 @@ __global__ __launch_bounds__(MC_THREADS) void k_map_couple(const RbcState* __res
     RT S = RT(0);
     for (int w = 0; w < MC_THREADS / 64; ++w) S += red[w][9];
     const RT invS = S > RT(0) ? RT(1) / S : RT(0);
+    // Covered nodes (fluid, and inside or next to an inside node), compacted in position
+    // order: wavefront w scans the positions [w per, (w + 1) per) sixty-four at a time and
+    // appends to its own part of the list, so the order, and the sums below, are fixed.
+    constexpr int NW = MC_THREADS / 64;
+    const int lane = tid & 63, wv = tid >> 6;
+    const unsigned per = ((total + NW - 1) / NW + 63u) & ~63u;
+    {
+        unsigned cnt = 0;
+        const unsigned end = min(total, (unsigned)(wv + 1) * per);
+        for (unsigned b = (unsigned)wv * per; b < end; b += 64) {
+            const unsigned t = b + (unsigned)lane;
+            bool cov = false;
+            if (t < end) {
+                const unsigned char fl = flag[t];
+                if (fl & 2) {
+                    const unsigned tz = t / sxy, rem = t - tz * sxy, ty = rem / sx, tx = rem - ty * sx;
+                    cov = (fl & 1) || (tx > 0 && (flag[t - 1] & 1)) || (tx + 1 < sx && (flag[t + 1] & 1)) ||
+                          (ty > 0 && (flag[t - sx] & 1)) || (ty + 1 < sy && (flag[t + sx] & 1)) ||
+                          (tz > 0 && (flag[t - sxy] & 1)) || (tz + 1 < sz && (flag[t + sxy] & 1));
+                }
+            }
+            const unsigned long long m = __ballot(cov);
+            if (cov) list[(unsigned)wv * per + cnt + (unsigned)__popcll(m & ((1ull << lane) - 1ull))] = (unsigned short)t;
+            cnt += (unsigned)__popcll(m);
+        }
+        if (lane == 0) wcnt[wv] = (int)cnt;
+    }
+    __syncthreads();
+    int ncov = 0;
+    for (int w = 0; w < NW; ++w) ncov += wcnt[w];
     RT acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const size_t ld = (size_t)kp.ld;
-    for (unsigned t = tid; t < total; t += MC_THREADS) {
-        const unsigned char fl = flag[t];
-        if (!(fl & 2)) continue;
+    for (int j = tid; j < ncov; j += MC_THREADS) {
+        int q = j, w = 0;
+        while (w + 1 < NW && q >= wcnt[w]) q -= wcnt[w++];
+        const unsigned t = list[(unsigned)w * per + (unsigned)q];
         const unsigned tz = t / sxy, rem = t - tz * sxy, ty = rem / sx, tx = rem - ty * sx;
-        const bool in = fl & 1;
+        const bool in = flag[t] & 1;
         const bool xm = tx > 0, xp = tx + 1 < sx, ym = ty > 0, yp = ty + 1 < sy, zm = tz > 0,
                    zp = tz + 1 < sz;
-        const bool cov = in || (xm && (flag[t - 1] & 1)) || (xp && (flag[t + 1] & 1)) ||
-                         (ym && (flag[t - sx] & 1)) || (yp && (flag[t + sx] & 1)) ||
-                         (zm && (flag[t - sxy] & 1)) || (zp && (flag[t + sxy] & 1));
-        if (!cov) continue;
         int X = T.lo[0] + (int)tx, Y = T.lo[1] + (int)ty, Z = T.lo[2] + (int)tz;
         wrap_coord(X, kp.nx, kp.per[0]);
         wrap_coord(Y, kp.ny, kp.per[1]);
@@ -402,6 +424,247 @@ __global__ __launch_bounds__(MC_THREADS) void k_map_couple(const RbcState* __res
             c.ut[a] = (double)tot[a];
             c.wt[a] = (double)tot[3 + a];
             c.TS[a] = (double)tot[6 + a];
+        }
+    }
+}
+
+// Cells whose row-compressed tile exceeds the capacity of the one-wavefront pass below take
+// the full-tile pass, one block of MC_THREADS per cell, over the list the first pass left.
+template <typename RT>
+__global__ __launch_bounds__(MC_THREADS) void k_map_couple_tile(const RbcState* __restrict__ st,
+                                                                RbcCouple* __restrict__ cp,
+                                                                uint32_t* __restrict__ nodeword,
+                                                                int* __restrict__ ids,
+                                                                RT* __restrict__ vals,
+                                                                const int* __restrict__ ovf,
+                                                                const RT* __restrict__ u,
+                                                                const RT* __restrict__ sig,
+                                                                KParams kp,
+                                                                unsigned* __restrict__ err)
+{
+    extern __shared__ unsigned char smem[];
+    const int n = ovf[0];
+    for (int b = blockIdx.x; b < n; b += gridDim.x)
+        map_couple_tile<RT>(ovf[1 + b], smem, st, cp, nodeword, ids, vals, u, sig, kp, err);
+}
+
+// ---- S3 + S4, one wavefront per cell on the row-compressed support tile -----------------------
+// The same computation as map_couple_tile, organised for occupancy: a block is one wavefront
+// and one cell, and LDS holds only the candidate nodes of each tile row (the covered x-range
+// of the row), row after row:
+//   clo[r]   first candidate x of row r,  off[r] its first candidate index (off[rows] = total),
+//   val[c]   the kernel value raw >= 0 at an inside node, -1 at a fluid node outside the
+//            support, -2 at a solid node or outside a non-periodic face,
+//   rowof[c] the row of candidate c.
+// Neighbours outside a row's candidate range are outside the support (raw = 0, not inside):
+// the covered range of every row contains the support range of the row and of its four
+// neighbouring rows. More candidates than kp.cand_cap: the cell goes to the overflow list
+// ovf[1 + k] (count ovf[0]) for k_map_couple_tile.
+template <typename RT>
+__global__ __launch_bounds__(64) void k_map_couple(const RbcState* __restrict__ st,
+                                                   RbcCouple* __restrict__ cp,
+                                                   uint32_t* __restrict__ nodeword,
+                                                   int* __restrict__ ids, RT* __restrict__ vals,
+                                                   const int* __restrict__ order,
+                                                   const RT* __restrict__ u,
+                                                   const RT* __restrict__ sig, KParams kp,
+                                                   unsigned* __restrict__ err,
+                                                   int* __restrict__ ovf)
+{
+    extern __shared__ unsigned char smem[];
+    const int k = xcd_chunk_index(1);
+    if (k >= kp.nrbc) return;
+    const int i = order[k];
+    const RbcState& s = st[i];
+    const int lane = threadIdx.x;
+    const int tm = kp.tile_max, cap = kp.cand_cap;
+    short* clo = reinterpret_cast<short*>(smem);
+    short* off = clo + tm * tm;
+    RT* val = reinterpret_cast<RT*>(smem + (((size_t)4 * tm * tm + 2 + 15) & ~(size_t)15));
+    unsigned short* rowof = reinterpret_cast<unsigned short*>(val + cap);
+    short* tlo = reinterpret_cast<short*>(val);          // support ranges (before val is used)
+    short* thi = tlo + tm * tm;
+
+    Tile T;
+    support_tile(s, kp, T);
+    if (T.sz[0] > tm || T.sz[1] > tm || T.sz[2] > tm) {
+        if (lane == 0) atomicOr(err, ERR_CAPACITY);
+        return;
+    }
+    const int sx = T.sz[0], sy = T.sz[1], sz = T.sz[2];
+    const int rows = sy * sz;
+    // support x-range of each row, widened by one node (see map_couple_tile)
+    const double X0 = s.R[0] - (double)T.lo[0];
+    for (int r = lane; r < rows; r += 64) {
+        const int ty = r % sy, tz = r / sy;
+        const double dy = (double)(T.lo[1] + ty) - s.R[1], dz = (double)(T.lo[2] + tz) - s.R[2];
+        double xa = -1e30, xb = 1e30;
+        for (int a = 0; a < 3; ++a) {
+            const double qa = s.Q[a], b = s.Q[3 + a] * dy + s.Q[6 + a] * dz;
+            if (fabs(qa) > 1e-12) {
+                double u0 = (-kp.xi[a] - b) / qa, u1 = (kp.xi[a] - b) / qa;
+                if (u0 > u1) { const double t_ = u0; u0 = u1; u1 = t_; }
+                xa = fmax(xa, u0);
+                xb = fmin(xb, u1);
+            } else if (fabs(b) >= kp.xi[a] + 1e-9) {
+                xa = 1e30;
+            }
+        }
+        int lo = sx, hi = -1;
+        if (xa <= xb) {
+            lo = max(0, (int)floor(X0 + xa) - 1);
+            hi = min(sx - 1, (int)ceil(X0 + xb) + 1);
+        }
+        tlo[r] = (short)lo;
+        thi[r] = (short)hi;
+    }
+    __syncthreads();
+    // covered range of each row and its length (kept in off[] until the scan)
+    for (int r = lane; r < rows; r += 64) {
+        const int ty = r % sy, tz = r / sy;
+        int lo = tlo[r] - 1, hi = thi[r] + 1;
+        if (ty > 0) { lo = min(lo, (int)tlo[r - 1]); hi = max(hi, (int)thi[r - 1]); }
+        if (ty + 1 < sy) { lo = min(lo, (int)tlo[r + 1]); hi = max(hi, (int)thi[r + 1]); }
+        if (tz > 0) { lo = min(lo, (int)tlo[r - sy]); hi = max(hi, (int)thi[r - sy]); }
+        if (tz + 1 < sz) { lo = min(lo, (int)tlo[r + sy]); hi = max(hi, (int)thi[r + sy]); }
+        lo = max(lo, 0);
+        hi = min(hi, sx - 1);
+        clo[r] = (short)lo;
+        off[r] = (short)max(0, hi - lo + 1);
+    }
+    __syncthreads();
+    // exclusive scan of the lengths: each lane a run of consecutive rows, then the lanes
+    const int per = (rows + 63) / 64, r0 = min(rows, lane * per), r1 = min(rows, r0 + per);
+    int run = 0;
+    for (int r = r0; r < r1; ++r) run += off[r];
+    int incl = run;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    const int total = __shfl(incl, 63, 64);
+    int base = incl - run;
+    __syncthreads();
+    for (int r = r0; r < r1; ++r) {
+        const int len = off[r];
+        off[r] = (short)base;
+        base += len;
+    }
+    if (lane == 63) off[rows] = (short)total;
+    if (total > cap) {
+        if (lane == 0) ovf[1 + atomicAdd(ovf, 1)] = i;
+        return;
+    }
+    __syncthreads();
+    for (int r = r0; r < r1; ++r)
+        for (int c = off[r], e = off[r + 1]; c < e; ++c) rowof[c] = (unsigned short)r;
+    __syncthreads();
+
+    // pass 1: exact support test and raw kernel value at every candidate; S = sum raw
+    const RT s0 = RT(2.0 / kp.xi[0]), s1 = RT(2.0 / kp.xi[1]), s2 = RT(2.0 / kp.xi[2]);
+    RT part = RT(0);
+    for (int c = lane; c < total; c += 64) {
+        const int r = rowof[c];
+        const int ty = r % sy, tz = r / sy, tx = clo[r] + (c - off[r]);
+        int X = T.lo[0] + tx, Y = T.lo[1] + ty, Z = T.lo[2] + tz;
+        RT v = RT(-2);
+        if (wrap_coord(X, kp.nx, kp.per[0]) && wrap_coord(Y, kp.ny, kp.per[1]) &&
+            wrap_coord(Z, kp.nz, kp.per[2]) && (nodeword[node_of(kp, X, Y, Z)] & NW_FLUID)) {
+            v = RT(-1);
+            double y[3];
+            const double d0 = min_img((double)X - s.R[0], (double)kp.nx, kp.per[0]);
+            const double d1 = min_img((double)Y - s.R[1], (double)kp.ny, kp.per[1]);
+            const double d2 = min_img((double)Z - s.R[2], (double)kp.nz, kp.per[2]);
+            body_coords_exact(s.Q, d0, d1, d2, y);
+            if (fabs(y[0]) < kp.xi[0] && fabs(y[1]) < kp.xi[1] && fabs(y[2]) < kp.xi[2]) {
+                v = peskin((RT)y[0] * s0) * peskin((RT)y[1] * s1) * peskin((RT)y[2] * s2);
+                part += v;
+            }
+        }
+        val[c] = v;
+    }
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_down(part, o, 64);
+    const RT S = __shfl(part, 0, 64);
+    const RT invS = S > RT(0) ? RT(1) / S : RT(0);
+    __syncthreads();
+
+    // pass 2: covered candidates (fluid, and inside or next to an inside node)
+    auto at = [&](int r, int x) -> RT {
+        const int d = x - clo[r], b = off[r];
+        return (d >= 0 && d < off[r + 1] - b) ? val[b + d] : RT(-2);
+    };
+    RT acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const size_t ld = (size_t)kp.ld;
+    for (int c = lane; c < total; c += 64) {
+        const RT v = val[c];
+        if (v < RT(-1.5)) continue;
+        const int r = rowof[c];
+        const int ty = r % sy, tz = r / sy, tx = clo[r] + (c - off[r]);
+        const RT vxm = at(r, tx - 1), vxp = at(r, tx + 1);
+        const RT vym = ty > 0 ? at(r - 1, tx) : RT(-2), vyp = ty + 1 < sy ? at(r + 1, tx) : RT(-2);
+        const RT vzm = tz > 0 ? at(r - sy, tx) : RT(-2), vzp = tz + 1 < sz ? at(r + sy, tx) : RT(-2);
+        const bool in = v >= RT(0);
+        const bool cov = in || vxm >= RT(0) || vxp >= RT(0) || vym >= RT(0) || vyp >= RT(0) ||
+                         vzm >= RT(0) || vzp >= RT(0);
+        if (!cov) continue;
+        int X = T.lo[0] + tx, Y = T.lo[1] + ty, Z = T.lo[2] + tz;
+        wrap_coord(X, kp.nx, kp.per[0]);
+        wrap_coord(Y, kp.ny, kp.per[1]);
+        wrap_coord(Z, kp.nz, kp.per[2]);
+        const unsigned n = node_of(kp, X, Y, Z);
+        const RT z0 = RT(0);
+        const RT rr = in ? v : z0;
+        const RT gx = RT(0.5) * (max(vxp, z0) - max(vxm, z0));
+        const RT gy = RT(0.5) * (max(vyp, z0) - max(vym, z0));
+        const RT gz = RT(0.5) * (max(vzp, z0) - max(vzm, z0));
+        const RT ux = u[n], uy = u[ld + n], uz = u[2 * ld + n];
+        const uint32_t old = atomicAdd(nodeword + n, NW_CNT_ONE);
+        const int slot = (int)(old >> 24);
+        if (slot < kp.cap) {
+            const size_t e = (size_t)slot * ld + n;
+            ids[e] = i;
+            RT* w4 = vals + 4 * e;
+            w4[0] = rr;
+            w4[1] = gx;
+            w4[2] = gy;
+            w4[3] = gz;
+        } else {
+            atomicOr(err, ERR_CAPACITY);
+        }
+        const RT hx = gx * invS, hy = gy * invS, hz = gz * invS;
+        acc[3] += uy * hz - uz * hy;
+        acc[4] += uz * hx - ux * hz;
+        acc[5] += ux * hy - uy * hx;
+        if (!in) continue;
+        const RT dh = rr * invS;
+        acc[0] += dh * ux;
+        acc[1] += dh * uy;
+        acc[2] += dh * uz;
+        const RT gl = sqrt(hx * hx + hy * hy + hz * hz);
+        const RT il = gl > RT(0) ? RT(1) / gl : RT(0);
+        const RT nx_ = hx * il, ny_ = hy * il, nz_ = hz * il;
+        const RT sxx = sig[n], syy = sig[ld + n], szz = sig[2 * ld + n];
+        const RT sxy_ = sig[3 * ld + n], sxz = sig[4 * ld + n], syz = sig[5 * ld + n];
+        const RT t0 = sxx * nx_ + sxy_ * ny_ + sxz * nz_;
+        const RT t1 = sxy_ * nx_ + syy * ny_ + syz * nz_;
+        const RT t2 = sxz * nx_ + syz * ny_ + szz * nz_;
+        const RT d0 = (RT)min_img((double)X - s.R[0], (double)kp.nx, kp.per[0]);
+        const RT d1 = (RT)min_img((double)Y - s.R[1], (double)kp.ny, kp.per[1]);
+        const RT d2 = (RT)min_img((double)Z - s.R[2], (double)kp.nz, kp.per[2]);
+        const RT al = (RT)kp.alpha * dh;
+        acc[6] += al * (t1 * d2 - t2 * d1);
+        acc[7] += al * (t2 * d0 - t0 * d2);
+        acc[8] += al * (t0 * d1 - t1 * d0);
+    }
+    for (int a = 0; a < 9; ++a)
+        for (int o = 32; o > 0; o >>= 1) acc[a] += __shfl_down(acc[a], o, 64);
+    if (lane == 0) {
+        RbcCouple& c = cp[i];
+        c.S = (double)S;
+        for (int a = 0; a < 3; ++a) {
+            c.ut[a] = (double)acc[a];
+            c.wt[a] = (double)acc[3 + a];
+            c.TS[a] = (double)acc[6 + a];
         }
     }
 }
@@ -705,13 +968,30 @@ static inline unsigned grid8(long long units, int per_block)
     return (unsigned)((b + 7) / 8 * 8);
 }
 
+size_t map_couple_lds(int tile_max, int cand_cap, int real_bytes)
+{
+    return (((size_t)4 * tile_max * tile_max + 2 + 15) & ~(size_t)15) + (size_t)cand_cap * (real_bytes + 2);
+}
+
+size_t map_couple_tile_lds(int tile_max, int real_bytes)
+{
+    // raw kernel values, flags, then the covered-position list (2 bytes per entry; the
+    // per-wavefront parts are rounded up to 64 entries)
+    const size_t t3 = (size_t)tile_max * tile_max * tile_max;
+    return ((t3 * (real_bytes + 1) + 1) & ~(size_t)1) + 2 * (t3 + MC_THREADS);
+}
+
 template <typename RT>
 void launch_map_couple(const CellBuffers& b, const KParams& kp, hipStream_t st)
 {
-    const size_t t3 = (size_t)kp.tile_max * kp.tile_max * kp.tile_max;
-    const size_t lds = t3 * sizeof(RT) + t3;
-    hipLaunchKernelGGL((k_map_couple<RT>), dim3(grid8(kp.nrbc, 1)), dim3(MC_THREADS), lds, st, b.st, b.cp,
+    hipLaunchKernelGGL((k_map_couple<RT>), dim3(grid8(kp.nrbc, 1)), dim3(64),
+                       map_couple_lds(kp.tile_max, kp.cand_cap, (int)sizeof(RT)), st, b.st, b.cp,
                        b.nodeword, b.map_ids, (RT*)b.map_vals, b.cell_ids, (const RT*)b.u,
+                       (const RT*)b.sig, kp, b.err, b.ovf);
+    // the overflow list is short (normally empty): a small grid loops over it
+    hipLaunchKernelGGL((k_map_couple_tile<RT>), dim3(64), dim3(MC_THREADS),
+                       map_couple_tile_lds(kp.tile_max, (int)sizeof(RT)), st, b.st, b.cp,
+                       b.nodeword, b.map_ids, (RT*)b.map_vals, b.ovf, (const RT*)b.u,
                        (const RT*)b.sig, kp, b.err);
 }
 
