@@ -318,6 +318,11 @@ struct lb_ctx_s {
     Geometry geo;
     Layout lay;
     hipStream_t stream = nullptr;
+    // Side stream (default priority) for the work of a step that does not depend on the
+    // per-cell map pass: clearing the coverage counts and the Gay-Berne forces run there,
+    // forked from and joined back into `stream` by events, for large cell counts.
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_cells = nullptr, ev_clear = nullptr, ev_gb = nullptr;
     char* base = nullptr;
     void *fA = nullptr, *fB = nullptr;
     CellBuffers cb{};
@@ -341,6 +346,21 @@ struct lb_ctx_s {
 };
 
 namespace {
+
+// cell count from which a context forks the map-independent work onto a side stream
+constexpr int SIDE_STREAM_MIN_CELLS = 2048;
+
+void release_side(lb_ctx c)
+{
+    if (c->side) (void)hipStreamSynchronize(c->side);
+    for (hipEvent_t* ev : {&c->ev_fork, &c->ev_cells, &c->ev_clear, &c->ev_gb})
+        if (*ev) {
+            (void)hipEventDestroy(*ev);
+            *ev = nullptr;
+        }
+    if (c->side) (void)hipStreamDestroy(c->side);
+    c->side = nullptr;
+}
 
 // message of the last lb_init / lb_query_footprint failure (no context exists then)
 std::string g_init_error;
@@ -457,7 +477,24 @@ void enqueue_step(lb_ctx c)
     with_types(c->cfg.storage, [&](auto* sp, auto* rp) {
         using ST = std::remove_pointer_t<decltype(sp)>;
         using RT = std::remove_pointer_t<decltype(rp)>;
-        if (c->nrbc > 0) {
+        if (c->nrbc > 0 && c->side) {
+            // rb1 -> cell list -> map -> rb2 on `stream`; count clearing (after rb1, before
+            // the map) and Gay-Berne (after the cell list, before rb2) on `side`
+            launch_rb_first_half(c->cb, kp, s);
+            (void)hipEventRecord(c->ev_fork, s);
+            (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
+            launch_clear_counts(c->cb.nodeword, kp.N, c->cb.ovf, c->side);
+            (void)hipEventRecord(c->ev_clear, c->side);
+            launch_cell_list(c->cb, kp, s);
+            (void)hipEventRecord(c->ev_cells, s);
+            (void)hipStreamWaitEvent(c->side, c->ev_cells, 0);
+            launch_gay_berne(c->cb, kp, c->side);
+            (void)hipEventRecord(c->ev_gb, c->side);
+            (void)hipStreamWaitEvent(s, c->ev_clear, 0);
+            launch_map_couple<RT>(c->cb, kp, s);
+            (void)hipStreamWaitEvent(s, c->ev_gb, 0);
+            launch_rb_second_half<RT>(c->cb, kp, 1, s);
+        } else if (c->nrbc > 0) {
             launch_rb_first_half(c->cb, kp, s);
             enqueue_cells_map_couple<RT>(c);
             launch_gay_berne(c->cb, kp, s);
@@ -635,6 +672,15 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
     e = hipMemcpy(&err, b.err, 4, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return init_fail(c, LB_EHIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
     if (err & ERR_OVERLAP) return init_fail(c, LB_EOVERLAP, "Gay-Berne pair at rho <= 0 in the initial state");
+    if (n_rbc >= SIDE_STREAM_MIN_CELLS) {
+        e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+        for (hipEvent_t* ev : {&c->ev_fork, &c->ev_cells, &c->ev_clear, &c->ev_gb})
+            if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            release_side(c);
+            return init_fail(c, LB_EHIP, std::string("side stream: ") + hipGetErrorString(e));
+        }
+    }
     *out = c;
     return LB_OK;
 }
@@ -1102,6 +1148,7 @@ void lb_destroy(lb_ctx c)
 {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    release_side(c);
     for (auto& pr : c->sc_pairs) {
         (void)hipEventDestroy(pr.first);
         (void)hipEventDestroy(pr.second);

@@ -102,31 +102,51 @@ __global__ __launch_bounds__(256) void k_cells_bin(const RbcState* __restrict__ 
     atomicAdd(cnt + c, 1);
 }
 
-// exclusive scan of n ints in one block of 1024 threads; also clears `cnt`
+// exclusive scan of n ints in one block of 1024 threads, 4096 values per round (each thread
+// four consecutive values, so the loads are coalesced); also clears `cnt`
 __global__ __launch_bounds__(1024) void k_scan_clear(int* cnt, int* off, int n)
 {
-    __shared__ int part[1024];
-    const int t = threadIdx.x;
-    const int chunk = (n + 1023) / 1024;
-    const int b = t * chunk, e = min(n, b + chunk);
-    int s = 0;
-    for (int k = b; k < e; ++k) s += cnt[k];
-    part[t] = s;
-    __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-        const int v = t >= d ? part[t - d] : 0;
+    __shared__ int wsum[16];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    int carry = 0;
+    for (int base = 0; base < n; base += 4096) {
+        const int i0 = base + 4 * t;
+        int v[4];
+        if (i0 + 3 < n) {
+            const int4 q = *reinterpret_cast<const int4*>(cnt + i0);
+            v[0] = q.x;
+            v[1] = q.y;
+            v[2] = q.z;
+            v[3] = q.w;
+        } else {
+            for (int j = 0; j < 4; ++j) v[j] = i0 + j < n ? cnt[i0 + j] : 0;
+        }
+        const int sum = v[0] + v[1] + v[2] + v[3];
+        int incl = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += y;
+        }
+        if (lane == 63) wsum[w] = incl;
         __syncthreads();
-        part[t] += v;
+        int before = 0, round = 0;
+        for (int k = 0; k < 16; ++k) {
+            const int x = wsum[k];
+            before += k < w ? x : 0;
+            round += x;
+        }
+        int ex = carry + before + incl - sum;
+        for (int j = 0; j < 4; ++j) {
+            if (i0 + j < n) {
+                off[i0 + j] = ex;
+                cnt[i0 + j] = 0;
+            }
+            ex += v[j];
+        }
+        carry += round;
         __syncthreads();
     }
-    int run = part[t] - s;
-    for (int k = b; k < e; ++k) {
-        const int c = cnt[k];
-        off[k] = run;
-        run += c;
-        cnt[k] = 0;
-    }
-    if (t == 1023) off[n] = part[1023];
+    if (t == 0) off[n] = carry;
 }
 
 __global__ __launch_bounds__(256) void k_cells_scatter(const int* __restrict__ cellid,
