@@ -19,12 +19,13 @@ static MapPlanes<RT> map_planes(const int* ids, const void* vals, const KParams&
 // ---- spreading at one node (Sec. II B back-reaction G; Sec. II D, Eq. 23) -----------------
 // g = g_ext - sum_i [F_i dhat_i - 1/2 T_i x grad(dhat_i)], theta = sum_i [1 - (1 - raw_i)^kappa]
 // over the covering cells in ascending id order (a fixed order: bitwise repeatable). Each
-// coverage slot holds the cell id and (raw, grad raw) written by the per-cell pass; dhat =
-// raw / S_i. The torque term carries the sign that hands the plasma -T_i of angular momentum.
+// coverage slot holds an entry index e = (cell << ent_shift) | j, and entry e the (raw,
+// grad raw) of that cell's j-th covered node, written by the per-cell pass; dhat = raw / S_i.
+// The torque term carries the sign that hands the plasma -T_i of angular momentum.
 //
-// The slot ids are read with branch-free loads (unused slots read the node word, already in
-// cache) so that all loads are in flight together; the keys (id << 4 | slot) are sorted by a
-// network sized to the wave's largest count (4, 8 or 12 slots).
+// The slot words are read with branch-free loads (unused slots read the node word, already in
+// cache) so that all loads are in flight together; the entry indices, ascending in the cell,
+// are sorted by a network sized to the wave's largest count (4, 8 or 12 slots).
 template <int CN>
 __device__ __forceinline__ void sort_keys(int* key)
 {
@@ -49,15 +50,15 @@ __device__ __forceinline__ void spread_slots(unsigned n, int cnt, const uint32_t
     for (int k = 0; k < CN; ++k) {
         const int* a = (k < cnt) ? at32(mp.ids[k], n) : reinterpret_cast<const int*>(at32(nodeword, n));
         const int v = *a;
-        key[k] = (k < cnt) ? ((v << 4) | k) : INT_MAX;
+        key[k] = (k < cnt) ? v : INT_MAX;
     }
     sort_keys<CN>(key);
     for (int k = 0; k < cnt; ++k) {
-        const int kk = key[0];
+        const int e = key[0];
 #pragma unroll
         for (int j = 0; j + 1 < CN; ++j) key[j] = key[j + 1];
-        const int i = kk >> 4, slot = kk & 15;
-        const RT* v = mp.vals0 + 4 * ((size_t)slot * (size_t)kp.ld + n);
+        const int i = e >> kp.ent_shift;
+        const RT* v = mp.vals0 + 4 * (size_t)e;
         const RT r0 = v[0], gx = v[1], gy = v[2], gz = v[3];
         const Gather<RT>& G = gat[i];
         const RT invS = G.invS;

@@ -38,6 +38,7 @@ struct Geometry {
     std::vector<int> wcell_off, wcell_ids;
     int tile_max = 0;
     int cand_cap = 0;
+    int ent_shift = 0;
 };
 
 // Capacity of the one-wavefront map pass: the largest number of candidate nodes (the
@@ -245,6 +246,19 @@ std::string build_geometry(const lb_config& c, const uint8_t* solid, int n_rbc, 
         // 2-byte position list in LDS, next to about 3.5 KiB of fixed arrays; the
         // one-wavefront pass keeps cand_cap candidates. Both within 64 KiB per workgroup.
         g.cand_cap = candidate_capacity(c.xi, g.tile_max);
+        // Coverage entries per cell: covered nodes lie within one node (on each axis) of the
+        // support box 2 xi; each such lattice node's unit cube lies in the box grown by 1.5 on
+        // each axis, which lies in the box grown by the ball of radius 1.5 sqrt(3). Steiner's
+        // formula bounds that volume, hence the count; the power of two above it is reserved.
+        {
+            const double a = 2 * c.xi[0], b = 2 * c.xi[1], d = 2 * c.xi[2], rr = 1.5 * std::sqrt(3.0);
+            const double vol = a * b * d + 2 * (a * b + b * d + d * a) * rr + M_PI * (a + b + d) * rr * rr +
+                               4.0 / 3.0 * M_PI * rr * rr * rr;
+            g.ent_shift = 0;
+            while ((double)(1 << g.ent_shift) < vol) ++g.ent_shift;
+            if (((long long)n_rbc << g.ent_shift) >= (1ll << 31))
+                return "too many cells for 32-bit coverage entries at this support size";
+        }
         const int rb = real_bytes(c.storage);
         if (g.tile_max > 20 || map_couple_tile_lds(g.tile_max, rb) + 4096 > 65536 ||
             map_couple_lds(g.tile_max, g.cand_cap, rb) > 65536)
@@ -286,7 +300,7 @@ Layout layout(const lb_config& c, const Geometry& g, int n_rbc)
     L.tdbg = take(ld * rs);
     L.nodeword = take(ld * 4);
     L.map_ids = take(n_rbc > 0 ? (size_t)cap * ld * 4 : 4);
-    L.map_vals = take(n_rbc > 0 ? (size_t)cap * ld * 4 * rs : 4);
+    L.map_vals = take(n_rbc > 0 ? ((size_t)n_rbc << g.ent_shift) * 4 * rs : 4);
     L.ovf = take(((size_t)n_rbc + 1) * 4);
     L.st = take(n_rbc * sizeof(RbcState));
     L.cp = take(n_rbc * sizeof(RbcCouple));
@@ -600,6 +614,7 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
     }
     kp.tile_max = g.tile_max;
     kp.cand_cap = g.cand_cap;
+    kp.ent_shift = g.ent_shift;
 
     const Layout& L = c->lay;
     c->fA = c->at<void>(L.fA);
@@ -1012,7 +1027,7 @@ lb_status rbc_get_map(lb_ctx c, int* off, int* ids, long long* len)
     for (size_t n = 0; n < N; ++n) {
         const int cnt = std::min<int>(nw[n] >> 24, c->kp.cap);
         const long long b = k;
-        for (int s = 0; s < cnt; ++s) ids[k++] = slots[(size_t)s * ld + n];
+        for (int s = 0; s < cnt; ++s) ids[k++] = slots[(size_t)s * ld + n] >> c->kp.ent_shift;
         std::sort(ids + b, ids + k);
         if (off) off[n + 1] = (int)k;
     }

@@ -68,6 +68,7 @@ struct KParams {
     double rc_wall;   // cell-wall Gay-Berne cut-off bound
     int tile_max;     // LDS tile edge bound
     int cand_cap;     // candidate nodes per cell held in LDS by the one-wavefront map pass
+    int ent_shift;    // log2 of the coverage entries reserved per cell
 };
 
 // ---- per-cell records ---------------------------------------------------------------------
@@ -150,7 +151,8 @@ struct Store<_Float16, float> {
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
-// coverage slots: per-slot id planes and the (raw, grad raw) values, slot-major
+// Coverage: per node, up to `cap` slot planes hold entry indices e = (cell << ent_shift) | j;
+// entry e holds (raw, grad raw) of the j-th covered node of that cell, cell-major.
 template <typename RT>
 struct MapPlanes {
     const int* ids[CAP_MAX];

@@ -391,10 +391,10 @@ __device__ void map_couple_tile(int i, unsigned char* smem, const RbcState* __re
         const RT ux = u[n], uy = u[ld + n], uz = u[2 * ld + n];
         const uint32_t old = atomicAdd(nodeword + n, NW_CNT_ONE);
         const int slot = (int)(old >> 24);
-        if (slot < kp.cap) {
-            const size_t e = (size_t)slot * ld + n;
-            ids[e] = i;
-            RT* v = vals + 4 * e;
+        const int e = (i << kp.ent_shift) | j;
+        if (slot < kp.cap && j < (1 << kp.ent_shift)) {
+            ids[(size_t)slot * ld + n] = e;
+            RT* v = vals + 4 * (size_t)e;
             v[0] = r;
             v[1] = gx;
             v[2] = gy;
@@ -613,20 +613,36 @@ __global__ __launch_bounds__(64) void k_map_couple(const RbcState* __restrict__ 
         const int d = x - clo[r], b = off[r];
         return (d >= 0 && d < off[r + 1] - b) ? val[b + d] : RT(-2);
     };
+    // the j-th covered node in candidate order fills the cell's entry j
     RT acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const size_t ld = (size_t)kp.ld;
-    for (int c = lane; c < total; c += 64) {
-        const RT v = val[c];
-        if (v < RT(-1.5)) continue;
-        const int r = rowof[c];
-        const int ty = r % sy, tz = r / sy, tx = clo[r] + (c - off[r]);
-        const RT vxm = at(r, tx - 1), vxp = at(r, tx + 1);
-        const RT vym = ty > 0 ? at(r - 1, tx) : RT(-2), vyp = ty + 1 < sy ? at(r + 1, tx) : RT(-2);
-        const RT vzm = tz > 0 ? at(r - sy, tx) : RT(-2), vzp = tz + 1 < sz ? at(r + sy, tx) : RT(-2);
-        const bool in = v >= RT(0);
-        const bool cov = in || vxm >= RT(0) || vxp >= RT(0) || vym >= RT(0) || vyp >= RT(0) ||
-                         vzm >= RT(0) || vzp >= RT(0);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int jbase = 0;
+    for (int c0 = 0; c0 < total; c0 += 64) {
+        const int c = c0 + lane;
+        const RT v = c < total ? val[c] : RT(-2);
+        int r = 0, ty = 0, tz = 0, tx = 0;
+        RT vxm = RT(-2), vxp = RT(-2), vym = RT(-2), vyp = RT(-2), vzm = RT(-2), vzp = RT(-2);
+        bool cov = false;
+        if (v > RT(-1.5)) {
+            r = rowof[c];
+            ty = r % sy;
+            tz = r / sy;
+            tx = clo[r] + (c - off[r]);
+            vxm = at(r, tx - 1);
+            vxp = at(r, tx + 1);
+            if (ty > 0) vym = at(r - 1, tx);
+            if (ty + 1 < sy) vyp = at(r + 1, tx);
+            if (tz > 0) vzm = at(r - sy, tx);
+            if (tz + 1 < sz) vzp = at(r + sy, tx);
+            cov = v >= RT(0) || vxm >= RT(0) || vxp >= RT(0) || vym >= RT(0) || vyp >= RT(0) ||
+                  vzm >= RT(0) || vzp >= RT(0);
+        }
+        const unsigned long long m = __ballot(cov);
+        const int j = jbase + (int)__popcll(m & below);
+        jbase += (int)__popcll(m);
         if (!cov) continue;
+        const bool in = v >= RT(0);
         int X = T.lo[0] + tx, Y = T.lo[1] + ty, Z = T.lo[2] + tz;
         wrap_coord(X, kp.nx, kp.per[0]);
         wrap_coord(Y, kp.ny, kp.per[1]);
@@ -640,10 +656,10 @@ __global__ __launch_bounds__(64) void k_map_couple(const RbcState* __restrict__ 
         const RT ux = u[n], uy = u[ld + n], uz = u[2 * ld + n];
         const uint32_t old = atomicAdd(nodeword + n, NW_CNT_ONE);
         const int slot = (int)(old >> 24);
-        if (slot < kp.cap) {
-            const size_t e = (size_t)slot * ld + n;
-            ids[e] = i;
-            RT* w4 = vals + 4 * e;
+        const int e = (i << kp.ent_shift) | j;
+        if (slot < kp.cap && j < (1 << kp.ent_shift)) {
+            ids[(size_t)slot * ld + n] = e;
+            RT* w4 = vals + 4 * (size_t)e;
             w4[0] = rr;
             w4[1] = gx;
             w4[2] = gy;
