@@ -491,9 +491,12 @@ void enqueue_step(lb_ctx c)
     with_types(c->cfg.storage, [&](auto* sp, auto* rp) {
         using ST = std::remove_pointer_t<decltype(sp)>;
         using RT = std::remove_pointer_t<decltype(rp)>;
-        if (c->nrbc > 0 && c->side) {
-            // rb1 -> cell list -> map -> rb2 on `stream`; count clearing (after rb1, before
-            // the map) and Gay-Berne (after the cell list, before rb2) on `side`
+        const bool forked = c->nrbc > 0 && c->side;
+        if (forked) {
+            // On `stream`: rb1, cell list, map, hydrodynamic half of rb2, stream-collide, and
+            // (after the join) the kick of rb2. On `side`: count clearing (after rb1, before
+            // the map) and Gay-Berne (after the cell list), which overlaps the map pass and
+            // the memory-bound stream-collide.
             launch_rb_first_half(c->cb, kp, s);
             (void)hipEventRecord(c->ev_fork, s);
             (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
@@ -506,13 +509,12 @@ void enqueue_step(lb_ctx c)
             (void)hipEventRecord(c->ev_gb, c->side);
             (void)hipStreamWaitEvent(s, c->ev_clear, 0);
             launch_map_couple<RT>(c->cb, kp, s);
-            (void)hipStreamWaitEvent(s, c->ev_gb, 0);
-            launch_rb_second_half<RT>(c->cb, kp, 1, s);
+            launch_rb_second_half<RT>(c->cb, kp, RB2_HYDRO, s);
         } else if (c->nrbc > 0) {
             launch_rb_first_half(c->cb, kp, s);
             enqueue_cells_map_couple<RT>(c);
             launch_gay_berne(c->cb, kp, s);
-            launch_rb_second_half<RT>(c->cb, kp, 1, s);
+            launch_rb_second_half<RT>(c->cb, kp, RB2_ALL, s);
         }
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (c->timing && (int)c->sc_pairs.size() < MAX_TIMED && c->ev_pool.size() >= 2) {
@@ -537,6 +539,10 @@ void enqueue_step(lb_ctx c)
             launch_wss<RT>(c->at<void>(c->lay.sig), c->at<long long>(c->lay.wn_node),
                            c->at<double>(c->lay.wn_nrm), (int)c->geo.wn_node.size(), kp, nullptr,
                            c->at<double>(c->lay.wss_acc), 1, s);
+        if (forked) {
+            (void)hipStreamWaitEvent(s, c->ev_gb, 0);
+            launch_rb_second_half<RT>(c->cb, kp, RB2_KICK, s);
+        }
     });
     if (c->wss_on) c->wss_count++;
     std::swap(c->fA, c->fB);
@@ -740,7 +746,7 @@ lb_status rbc_couple(lb_ctx c)
         using RT = std::remove_pointer_t<decltype(rp)>;
         if (c->nrbc > 0) {
             enqueue_cells_map_couple<RT>(c);
-            launch_rb_second_half<RT>(c->cb, c->kp, 0, c->stream);
+            launch_rb_second_half<RT>(c->cb, c->kp, RB2_NOW, c->stream);
         }
         launch_spread_field<RT>(c->cb.nodeword, c->cb.map_ids, c->cb.map_vals, c->cb.gat,
                                 c->at<void>(c->lay.gdbg), c->at<void>(c->lay.tdbg), c->kp, c->stream);

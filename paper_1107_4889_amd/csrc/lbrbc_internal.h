@@ -58,8 +58,9 @@ void launch_map_couple(const CellBuffers& b, const KParams& kp, hipStream_t st);
 size_t map_couple_lds(int tile_max, int cand_cap, int real_bytes);   // dynamic LDS, bytes
 size_t map_couple_tile_lds(int tile_max, int real_bytes);
 void launch_gay_berne(const CellBuffers& b, const KParams& kp, hipStream_t st);
+enum { RB2_NOW = 0, RB2_ALL = 1, RB2_HYDRO = 2, RB2_KICK = 3 };
 template <typename RT>
-void launch_rb_second_half(const CellBuffers& b, const KParams& kp, int integrate, hipStream_t st);
+void launch_rb_second_half(const CellBuffers& b, const KParams& kp, int mode, hipStream_t st);
 void launch_init_combined(const CellBuffers& b, const KParams& kp, hipStream_t st);
 void launch_fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t st);
 

@@ -907,11 +907,15 @@ __global__ __launch_bounds__(256) void k_gay_berne(const RbcState* __restrict__ 
 // ---- S6: combined force/torque, hydrodynamic force/torque, second half --------------------
 // F^comb = F^mech + gT M u~; tau^comb = tau^mech + Q^T T^S + gR I (s Q^T w~);
 // F^hyd = -M gT (V^1/2 - u~); T^hyd = Q [-gR I (Omega^1/2 - s Q^T w~)] + T^S (lab).
+// mode RB2_NOW: F^hyd, T^hyd and the gather record from the current V, Omega (coupling
+// without a time step); RB2_HYDRO: the same from the half-step V, Omega; RB2_KICK: combined
+// force and torque, half-step friction and half kick (needs the Gay-Berne forces);
+// RB2_ALL: RB2_HYDRO and RB2_KICK.
 template <typename RT>
 __global__ __launch_bounds__(128) void k_rb_second_half(RbcState* __restrict__ st,
                                                         RbcCouple* __restrict__ cp,
                                                         Gather<RT>* __restrict__ gat, KParams kp,
-                                                        int integrate)
+                                                        int mode)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= kp.nrbc) return;
@@ -920,15 +924,16 @@ __global__ __launch_bounds__(128) void k_rb_second_half(RbcState* __restrict__ s
     double wb[3], tsb[3], tb[3], tl[3];
     matT_vec(s.Q, c.wt, wb);
     matT_vec(s.Q, c.TS, tsb);
-    const double* Vh = integrate ? s.Vh : s.V;
-    const double* Oh = integrate ? s.Omh : s.Om;
+    const bool half = mode != RB2_NOW;
+    const double* Vh = half ? s.Vh : s.V;
+    const double* Oh = half ? s.Omh : s.Om;
     for (int a = 0; a < 3; ++a) {
         c.Fh[a] = -kp.mass * kp.gammaT * (Vh[a] - c.ut[a]);
         tb[a] = -kp.gammaR * kp.inertia[a] * (Oh[a] - kp.vort_scale * wb[a]);
     }
     mat_vec(s.Q, tb, tl);
     for (int a = 0; a < 3; ++a) c.Th[a] = tl[a] + c.TS[a];
-    if (integrate) {
+    if (mode == RB2_KICK || mode == RB2_ALL) {
         const double eT = exp(-kp.gammaT * 0.5), eR = exp(-kp.gammaR * 0.5);
         for (int a = 0; a < 3; ++a) {
             s.Fc[a] = c.Fm[a] + kp.gammaT * kp.mass * c.ut[a];
@@ -940,6 +945,7 @@ __global__ __launch_bounds__(128) void k_rb_second_half(RbcState* __restrict__ s
         }
         st[i] = s;
     }
+    if (mode == RB2_KICK) return;
     for (int a = 0; a < 3; ++a) {
         cp[i].Fh[a] = c.Fh[a];
         cp[i].Th[a] = c.Th[a];
@@ -1039,10 +1045,10 @@ void launch_gay_berne(const CellBuffers& b, const KParams& kp, hipStream_t st)
 }
 
 template <typename RT>
-void launch_rb_second_half(const CellBuffers& b, const KParams& kp, int integrate, hipStream_t st)
+void launch_rb_second_half(const CellBuffers& b, const KParams& kp, int mode, hipStream_t st)
 {
     hipLaunchKernelGGL((k_rb_second_half<RT>), dim3(nblk(kp.nrbc, 128)), dim3(128), 0, st, b.st,
-                       b.cp, (Gather<RT>*)b.gat, kp, integrate);
+                       b.cp, (Gather<RT>*)b.gat, kp, mode);
 }
 
 void launch_init_combined(const CellBuffers& b, const KParams& kp, hipStream_t st)
