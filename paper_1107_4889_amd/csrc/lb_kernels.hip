@@ -142,20 +142,19 @@ __device__ __forceinline__ unsigned pull_off(unsigned n, int x, int y, int z, co
 // the 19 pull loads depend only on the position, so they issue without waiting for the node
 // word; directions whose source is solid are then replaced by the opposite population at
 // the node itself (halfway bounce-back)
-template <typename ST, typename RT, int... Ps>
-__device__ __forceinline__ void pull_all_fast(RT* f, const Planes<ST, RT>& pl, unsigned n, int x,
-                                              int y, int z, const KParams& kp,
-                                              std::integer_sequence<int, Ps...>)
+template <typename ST, typename RT, typename PL, int... Ps>
+__device__ __forceinline__ void pull_all_fast(RT* f, const PL& pl, unsigned n, int x, int y, int z,
+                                              const KParams& kp, std::integer_sequence<int, Ps...>)
 {
     const unsigned sx = 1u, sy = (unsigned)kp.nx, sz = (unsigned)kp.nx * (unsigned)kp.ny;
-    ((f[Ps] = Store<ST, RT>::ld(pl.in[Ps], pull_off<Ps>(n, x, y, z, kp, sx, sy, sz), kp.f16_inv)), ...);
+    ((f[Ps] = Store<ST, RT>::ld(pl.src(Ps), pull_off<Ps>(n, x, y, z, kp, sx, sy, sz), kp.f16_inv)), ...);
 }
 
-template <typename ST, typename RT, int... Ps>
-__device__ __forceinline__ void bounce_back(RT* f, const Planes<ST, RT>& pl, unsigned n, uint32_t w,
+template <typename ST, typename RT, typename PL, int... Ps>
+__device__ __forceinline__ void bounce_back(RT* f, const PL& pl, unsigned n, uint32_t w,
                                             const KParams& kp, std::integer_sequence<int, Ps...>)
 {
-    ((f[Ps] = (w & (1u << Ps)) ? Store<ST, RT>::ld(pl.in[opp_(Ps)], n, kp.f16_inv) : f[Ps]), ...);
+    ((f[Ps] = (w & (1u << Ps)) ? Store<ST, RT>::ld(pl.src(opp_(Ps)), n, kp.f16_inv) : f[Ps]), ...);
 }
 
 template <typename RT>
@@ -169,8 +168,8 @@ __device__ __forceinline__ RT feq_shift(int p, RT drho, RT rho, RT ux, RT uy, RT
 // BGK with body force for the pair (P, P+1) of opposite speeds: the equilibrium and the
 // force term split into parts even and odd in c, shared by the two directions. Lanes that
 // do not hold a fluid node (live == false) store zero.
-template <typename ST, typename RT, int P>
-__device__ __forceinline__ void collide_pair(const RT* f, const Planes<ST, RT>& pl, unsigned n,
+template <typename ST, typename RT, typename PL, int P>
+__device__ __forceinline__ void collide_pair(const RT* f, const PL& pl, unsigned n,
                                              RT drho, RT rho, RT ux, RT uy, RT uz, RT usq,
                                              const RT g[3], RT gu, RT om, RT kf, RT k2, RT k3,
                                              const KParams& kp, bool live)
@@ -183,18 +182,18 @@ __device__ __forceinline__ void collide_pair(const RT* f, const Planes<ST, RT>& 
     const RT asym = w * rho * RT(3) * uc;
     const RT fs = kf * w * (k2 * gc * uc - k3 * gu);
     const RT fa = kf * w * RT(3) * gc;
-    Store<ST, RT>::st(pl.out[P], n, live ? f[P] - om * (f[P] - sym - asym) + fs + fa : RT(0), kp.f16_scale);
-    Store<ST, RT>::st(pl.out[Q], n, live ? f[Q] - om * (f[Q] - sym + asym) + fs - fa : RT(0), kp.f16_scale);
+    Store<ST, RT>::st(pl.dst(P), n, live ? f[P] - om * (f[P] - sym - asym) + fs + fa : RT(0), kp.f16_scale);
+    Store<ST, RT>::st(pl.dst(Q), n, live ? f[Q] - om * (f[Q] - sym + asym) + fs - fa : RT(0), kp.f16_scale);
 }
 
-template <typename ST, typename RT, int... Ps>
-__device__ __forceinline__ void collide_pairs(const RT* f, const Planes<ST, RT>& pl, unsigned n,
+template <typename ST, typename RT, typename PL, int... Ps>
+__device__ __forceinline__ void collide_pairs(const RT* f, const PL& pl, unsigned n,
                                               RT drho, RT rho, RT ux, RT uy, RT uz, RT usq,
                                               const RT g[3], RT gu, RT om, RT kf, RT k2, RT k3,
                                               const KParams& kp, bool live,
                                               std::integer_sequence<int, Ps...>)
 {
-    (collide_pair<ST, RT, 2 * Ps + 1>(f, pl, n, drho, rho, ux, uy, uz, usq, g, gu, om, kf, k2, k3, kp, live), ...);
+    (collide_pair<ST, RT, PL, 2 * Ps + 1>(f, pl, n, drho, rho, ux, uy, uz, usq, g, gu, om, kf, k2, k3, kp, live), ...);
 }
 
 // ---- fused spreading + stream + collide (Sec. II A, Eqs. 1-8) -----------------------------
@@ -206,15 +205,13 @@ __device__ __forceinline__ void collide_pairs(const RT* f, const Planes<ST, RT>&
 // solid sources are replaced by bounce-back, open planes are rewritten by the boundary
 // kernel), so that each store writes whole cache lines: stores that leave part of a line
 // unwritten, as at every wall crossing of a lattice row, measured markedly slower in HBM.
-template <typename ST, typename RT>
-__global__ __launch_bounds__(256) void k_stream_collide(
-    const Planes<ST, RT> pl, const uint32_t* __restrict__ nodeword, const MapPlanes<RT> mp,
-    const Gather<RT>* __restrict__ gat, KParams kp, unsigned* __restrict__ err)
+template <typename ST, typename RT, typename PL>
+__device__ __forceinline__ void stream_collide_node(const PL& pl, const uint32_t* __restrict__ nodeword,
+                                                    const MapPlanes<RT>& mp,
+                                                    const Gather<RT>* __restrict__ gat,
+                                                    const KParams& kp, unsigned* __restrict__ err,
+                                                    int x, int y, int z)
 {
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= kp.nx || y >= kp.ny) return;
     const unsigned n = (unsigned)x + (unsigned)kp.nx * ((unsigned)y + (unsigned)kp.ny * (unsigned)z);
     const uint32_t w = nodeword[n];
     const bool live = (w & NW_FLUID) && !(w & NW_OPEN);
@@ -265,7 +262,7 @@ __global__ __launch_bounds__(256) void k_stream_collide(
         const RT w0 = RT(w_(0));
         const RT fe0 = w0 * (drho - RT(1.5) * rho * usq);
         const RT F0 = -kf * w0 * k3 * gu;
-        Store<ST, RT>::st(pl.out[0], n, live ? f[0] - om * (f[0] - fe0) + F0 : RT(0), kp.f16_scale);
+        Store<ST, RT>::st(pl.dst(0), n, live ? f[0] - om * (f[0] - fe0) + F0 : RT(0), kp.f16_scale);
     }
     collide_pairs<ST, RT>(f, pl, n, drho, rho, ux, uy, uz, usq, g, gu, om, kf, k2, k3, kp, live,
                           std::make_integer_sequence<int, 9>{});
@@ -275,16 +272,27 @@ __global__ __launch_bounds__(256) void k_stream_collide(
     const RT ks = -(RT(1) - RT(0.5) * om);
     const RT d3 = drho * RT(1.0 / 3.0);
     const RT z0 = RT(0);
-    __builtin_nontemporal_store(live ? ux : z0, at32(pl.u[0], n));
-    __builtin_nontemporal_store(live ? uy : z0, at32(pl.u[1], n));
-    __builtin_nontemporal_store(live ? uz : z0, at32(pl.u[2], n));
-    __builtin_nontemporal_store(live ? ks * (pxx - d3 - rho * ux * ux) : z0, at32(pl.sig[0], n));
-    __builtin_nontemporal_store(live ? ks * (pyy - d3 - rho * uy * uy) : z0, at32(pl.sig[1], n));
-    __builtin_nontemporal_store(live ? ks * (pzz - d3 - rho * uz * uz) : z0, at32(pl.sig[2], n));
-    __builtin_nontemporal_store(live ? ks * (pxy - rho * ux * uy) : z0, at32(pl.sig[3], n));
-    __builtin_nontemporal_store(live ? ks * (pxz - rho * ux * uz) : z0, at32(pl.sig[4], n));
-    __builtin_nontemporal_store(live ? ks * (pyz - rho * uy * uz) : z0, at32(pl.sig[5], n));
+    __builtin_nontemporal_store(live ? ux : z0, at32(pl.vel(0), n));
+    __builtin_nontemporal_store(live ? uy : z0, at32(pl.vel(1), n));
+    __builtin_nontemporal_store(live ? uz : z0, at32(pl.vel(2), n));
+    __builtin_nontemporal_store(live ? ks * (pxx - d3 - rho * ux * ux) : z0, at32(pl.str(0), n));
+    __builtin_nontemporal_store(live ? ks * (pyy - d3 - rho * uy * uy) : z0, at32(pl.str(1), n));
+    __builtin_nontemporal_store(live ? ks * (pzz - d3 - rho * uz * uz) : z0, at32(pl.str(2), n));
+    __builtin_nontemporal_store(live ? ks * (pxy - rho * ux * uy) : z0, at32(pl.str(3), n));
+    __builtin_nontemporal_store(live ? ks * (pxz - rho * ux * uz) : z0, at32(pl.str(4), n));
+    __builtin_nontemporal_store(live ? ks * (pyz - rho * uy * uz) : z0, at32(pl.str(5), n));
     if (live && (!(rho > RT(0)) || !(usq <= RT(0.09)))) atomicOr(err, ERR_UNSTABLE);
+}
+
+template <typename ST, typename RT>
+__global__ __launch_bounds__(256) void k_stream_collide(
+    const Planes<ST, RT> pl, const uint32_t* __restrict__ nodeword, const MapPlanes<RT> mp,
+    const Gather<RT>* __restrict__ gat, KParams kp, unsigned* __restrict__ err)
+{
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    if (x < kp.nx && y < kp.ny)
+        stream_collide_node<ST, RT>(pl, nodeword, mp, gat, kp, err, x, y, (int)blockIdx.z);
 }
 
 // ---- open z faces: non-equilibrium extrapolation (Guo, Zheng & Shi 2002) ------------------
@@ -456,6 +464,47 @@ __global__ __launch_bounds__(256) void k_wss(const RT* __restrict__ sig,
     if (accumulate) acc[k] += v;
 }
 
+// ---- fused multi-lattice versions of the per-node stages -------------------------------------
+template <typename RT>
+__device__ __forceinline__ MapPlanes<RT> map_planes_dev(const int* ids, const void* vals, const KParams& kp)
+{
+    MapPlanes<RT> mp;
+#pragma unroll
+    for (int k = 0; k < CAP_MAX; ++k) mp.ids[k] = ids + (k < kp.cap ? (size_t)k * (size_t)kp.ld : 0);
+    mp.vals0 = (const RT*)vals;
+    return mp;
+}
+
+__global__ __launch_bounds__(256) void kf_clear(const FusedArgs fa)
+{
+    int lb;
+    const SlotDesc& d = *fa.slot[fused_slot(fa, lb)];
+    const long long n = (long long)lb * 256 + threadIdx.x;
+    if (n == 0) d.b.ovf[0] = 0;
+    if (n < d.kp.N) {
+        const uint32_t w = d.b.nodeword[n];
+        if (w >> 24) d.b.nodeword[n] = w & NW_STATIC;
+    }
+}
+
+template <typename ST, typename RT>
+__global__ __launch_bounds__(256) void kf_stream(const FusedArgs fa)
+{
+    int lb;
+    const int sl = fused_slot(fa, lb);
+    const SlotDesc& d = *fa.slot[sl];
+    const KParams kp = d.kp;
+    const int nbx = (kp.nx + 63) >> 6, nby = (kp.ny + 3) >> 2;
+    const int bx = lb % nbx, rr = lb / nbx, by = rr % nby, z = rr / nby;
+    const int x = bx * 64 + (int)threadIdx.x, y = by * 4 + (int)threadIdx.y;
+    if (x >= kp.nx || y >= kp.ny) return;
+    const bool odd = (fa.parity >> sl) & 1ull;
+    const PlanesLd<ST, RT> pl{(const ST*)(odd ? d.fB : d.fA), (ST*)(odd ? d.fA : d.fB), (RT*)d.b.u,
+                              (RT*)d.b.sig, (unsigned long long)kp.ld};
+    const MapPlanes<RT> mp = map_planes_dev<RT>(d.b.map_ids, d.b.map_vals, kp);
+    stream_collide_node<ST, RT>(pl, d.b.nodeword, mp, (const Gather<RT>*)d.b.gat, kp, d.b.err, x, y, z);
+}
+
 // ---- launchers ---------------------------------------------------------------------------------
 template <typename ST, typename RT>
 void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword, const int* ids,
@@ -519,7 +568,17 @@ void launch_wss(const void* sig, const long long* wn_node, const double* wn_nrm,
                        wn_node, wn_nrm, nwn, kp, wss, acc, accumulate);
 }
 
+template <typename ST, typename RT>
+void launch_fused_lattice(const FusedArgs& fa, int stage, hipStream_t st)
+{
+    const unsigned g = (unsigned)fa.start[fa.n];
+    if (g == 0) return;
+    if (stage == FS_CLEAR) hipLaunchKernelGGL(kf_clear, dim3(g), dim3(256), 0, st, fa);
+    if (stage == FS_STREAM) hipLaunchKernelGGL((kf_stream<ST, RT>), dim3(g), dim3(64, 4, 1), 0, st, fa);
+}
+
 #define INST_ST(ST, RT)                                                                           \
+    template void launch_fused_lattice<ST, RT>(const FusedArgs&, int, hipStream_t);               \
     template void launch_stream_collide<ST, RT>(const void*, void*, const uint32_t*, const int*,  \
                                                 const void*, const void*, void*, void*,           \
                                                 const KParams&, unsigned*, hipStream_t);          \

@@ -275,7 +275,7 @@ std::string build_geometry(const lb_config& c, const uint8_t* solid, int n_rbc, 
 struct Layout {
     size_t fA, fB, u, sig, gdbg, tdbg, nodeword, map_ids, map_vals, ovf, st, cp, gat, cellid, cell_cnt, cell_off,
         cell_ids, wall_xyz, wcell_off, wcell_ids, wn_node, wn_nrm, wss, wss_acc, planes, partials,
-        obs_out, err, total;
+        obs_out, err, slot, total;
 };
 
 Layout layout(const lb_config& c, const Geometry& g, int n_rbc)
@@ -320,6 +320,7 @@ Layout layout(const lb_config& c, const Geometry& g, int n_rbc)
     L.partials = take(6 * OBS_BLOCKS * 8);
     L.obs_out = take(8 * 8);
     L.err = take(4);
+    L.slot = take(sizeof(SlotDesc));
     L.total = o;
     return L;
 }
@@ -549,6 +550,68 @@ void enqueue_step(lb_ctx c)
     c->step++;
 }
 
+// Contexts whose steps one fused launch per stage can carry together: the same stream and
+// storage type, no open boundary, no WSS accumulation, no kernel timing.
+bool fusable(lb_ctx c, lb_ctx first)
+{
+    return c->stream == first->stream && c->cfg.storage == first->cfg.storage && c->geo.planes.empty() &&
+           !c->wss_on && !c->timing;
+}
+
+// one step of n contexts (n <= FUSE_MAX): rb1 + binning, scan, scatter, sort, count clearing,
+// map + interpolation (and the overflow pass), Gay-Berne, second half, stream-collide; each
+// stage is one launch over all contexts
+void enqueue_fused_step(lb_ctx* cs, int n)
+{
+    hipStream_t s = cs[0]->stream;
+    FusedArgs fa;
+    fa.n = n;
+    fa.parity = 0;
+    size_t lds_map = 0, lds_tile = 0;
+    for (int i = 0; i < n; ++i) {
+        lb_ctx c = cs[i];
+        fa.slot[i] = c->at<SlotDesc>(c->lay.slot);
+        if (c->fA != c->at<void>(c->lay.fA)) fa.parity |= 1ull << i;
+        const int rb = real_bytes(c->cfg.storage);
+        if (c->nrbc > 0) {
+            lds_map = std::max(lds_map, map_couple_lds(c->kp.tile_max, c->kp.cand_cap, rb));
+            lds_tile = std::max(lds_tile, map_couple_tile_lds(c->kp.tile_max, rb));
+        }
+    }
+    auto starts = [&](int stage) {
+        int tot = 0;
+        for (int i = 0; i < n; ++i) {
+            fa.start[i] = tot;
+            tot += fused_blocks(cs[i]->kp, stage);
+        }
+        fa.start[n] = tot;
+    };
+    with_types(cs[0]->cfg.storage, [&](auto* sp, auto* rp) {
+        using ST = std::remove_pointer_t<decltype(sp)>;
+        using RT = std::remove_pointer_t<decltype(rp)>;
+        for (int stage : {FS_CELLS_A, FS_SCAN, FS_SCATTER, FS_SORT}) {
+            starts(stage);
+            launch_fused_cells<RT>(fa, stage, 0, s);
+        }
+        starts(FS_CLEAR);
+        launch_fused_lattice<ST, RT>(fa, FS_CLEAR, s);
+        starts(FS_MAP);
+        launch_fused_cells<RT>(fa, FS_MAP, lds_map, s);
+        starts(FS_MAP_TILE);
+        launch_fused_cells<RT>(fa, FS_MAP_TILE, lds_tile, s);
+        starts(FS_GB);
+        launch_fused_cells<RT>(fa, FS_GB, 0, s);
+        starts(FS_RB2);
+        launch_fused_cells<RT>(fa, FS_RB2, 0, s);
+        starts(FS_STREAM);
+        launch_fused_lattice<ST, RT>(fa, FS_STREAM, s);
+    });
+    for (int i = 0; i < n; ++i) {
+        std::swap(cs[i]->fA, cs[i]->fB);
+        cs[i]->step++;
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -678,6 +741,14 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
         for (int a = 0; a < 9; ++a) r.Q[a] = cells[i].Q[a];
     }
     e = e ? e : h2d(L.st, hs.data(), hs.size() * sizeof(RbcState));
+    // the context's record for fused multi-lattice launches
+    SlotDesc sd;
+    std::memset(&sd, 0, sizeof sd);
+    sd.kp = kp;
+    sd.b = b;
+    sd.fA = c->fA;
+    sd.fB = c->fB;
+    e = e ? e : h2d(L.slot, &sd, sizeof sd);
     if (e != hipSuccess) return init_fail(c, LB_EHIP, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
     if (n_rbc > 0) {
         // start-up: F^comb(0) = F^mech(0), tau^comb(0) = tau^mech(0) (fluid at rest)
@@ -727,14 +798,27 @@ lb_status lb_batch_step(lb_ctx* ctxs, const int* nsteps, int n)
 {
     if (!ctxs || !nsteps || n < 0) return LB_EINVAL;
     int most = 0;
+    bool fuse = n > 1;
     for (int i = 0; i < n; ++i) {
         if (!ctxs[i] || nsteps[i] < 0) return LB_EINVAL;
         if (ctxs[i]->poisoned) return LB_ESTATE;
         most = std::max(most, nsteps[i]);
+        fuse = fuse && fusable(ctxs[i], ctxs[0]);
     }
-    for (int k = 0; k < most; ++k)
-        for (int i = 0; i < n; ++i)
-            if (k < nsteps[i]) enqueue_step(ctxs[i]);
+    if (fuse) {
+        std::vector<lb_ctx> act;
+        for (int k = 0; k < most; ++k) {
+            act.clear();
+            for (int i = 0; i < n; ++i)
+                if (k < nsteps[i]) act.push_back(ctxs[i]);
+            for (size_t g = 0; g < act.size(); g += FUSE_MAX)
+                enqueue_fused_step(act.data() + g, (int)std::min<size_t>(FUSE_MAX, act.size() - g));
+        }
+    } else {
+        for (int k = 0; k < most; ++k)
+            for (int i = 0; i < n; ++i)
+                if (k < nsteps[i]) enqueue_step(ctxs[i]);
+    }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? LB_OK : LB_EHIP;
 }

@@ -166,6 +166,23 @@ struct Planes {
     ST* out[19];
     RT* u[3];
     RT* sig[6];
+    __device__ const ST* src(int p) const { return in[p]; }
+    __device__ ST* dst(int p) const { return out[p]; }
+    __device__ RT* vel(int a) const { return u[a]; }
+    __device__ RT* str(int a) const { return sig[a]; }
+};
+// the same planes from the buffer bases and the plane stride (fused multi-lattice launches)
+template <typename ST, typename RT>
+struct PlanesLd {
+    const ST* fin;
+    ST* fout;
+    RT* u;
+    RT* sig;
+    unsigned long long ld;
+    __device__ const ST* src(int p) const { return fin + (unsigned long long)p * ld; }
+    __device__ ST* dst(int p) const { return fout + (unsigned long long)p * ld; }
+    __device__ RT* vel(int a) const { return u + (unsigned long long)a * ld; }
+    __device__ RT* str(int a) const { return sig + (unsigned long long)a * ld; }
 };
 
 // ---- Peskin four-point kernel at r = 2|y|/xi (the normalised 1-D profile) ----------------

@@ -51,6 +51,50 @@ struct CellBuffers {
     int* ovf;             // [1 + nrbc] overflow count, then cells for the full-tile map pass
 };
 
+// ---- fused multi-lattice launches -----------------------------------------------------------
+// Everything a fused launch needs about one context; kept in the context's arena.
+struct SlotDesc {
+    KParams kp;
+    CellBuffers b;
+    void* fA;            // population buffers A and B of the arena
+    void* fB;
+};
+// Kernel argument of a fused launch over up to FUSE_MAX contexts: block b belongs to the slot
+// s with start[s] <= b < start[s + 1]; parity bit s: slot s reads B and writes A this step.
+constexpr int FUSE_MAX = 64;
+struct FusedArgs {
+    const SlotDesc* slot[FUSE_MAX];
+    int start[FUSE_MAX + 1];
+    int n;
+    unsigned long long parity;
+};
+// one step of every slot; every slot has the same storage type ST/RT, no open boundary and
+// no WSS accumulation
+enum FusedStage { FS_CELLS_A, FS_SCAN, FS_SCATTER, FS_SORT, FS_CLEAR, FS_MAP, FS_MAP_TILE, FS_GB,
+                  FS_RB2, FS_STREAM, FS_NSTAGES };
+int fused_blocks(const KParams& kp, int stage);    // blocks of one slot in a stage
+// per-cell stages (FS_CELLS_A .. FS_RB2 except FS_CLEAR); lds: dynamic LDS of FS_MAP and
+// FS_MAP_TILE (the largest over the slots)
+template <typename RT>
+void launch_fused_cells(const FusedArgs& fa, int stage, size_t lds, hipStream_t st);
+// per-node stages (FS_CLEAR, FS_STREAM)
+template <typename ST, typename RT>
+void launch_fused_lattice(const FusedArgs& fa, int stage, hipStream_t st);
+
+// slot of this block in a fused launch, and the block's index within the slot
+__device__ __forceinline__ int fused_slot(const FusedArgs& fa, int& lb)
+{
+    const int b = (int)blockIdx.x;
+    int lo = 0, hi = fa.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (fa.start[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    lb = b - fa.start[lo];
+    return lo;
+}
+
 void launch_rb_first_half(const CellBuffers& b, const KParams& kp, hipStream_t st);
 void launch_cell_list(const CellBuffers& b, const KParams& kp, hipStream_t st);
 template <typename RT>

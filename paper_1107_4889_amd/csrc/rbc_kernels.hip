@@ -31,10 +31,8 @@ __device__ __forceinline__ double box_len(const KParams& kp, int a)
 // half kick, half-step friction, drift (wrapped on periodic axes), five free sub-rotations
 // n/2, t/2, g, t/2, n/2 about the body axes: Rot = Rot_k(-f h Omega_k), pi <- Rot pi,
 // Q <- Q Rot^T (Q' = Q hat(Omega)).
-__global__ __launch_bounds__(128) void k_rb_first_half(RbcState* __restrict__ st, KParams kp)
+__device__ __forceinline__ void rb1_cell(RbcState* __restrict__ st, const KParams& kp, int i)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= kp.nrbc) return;
     RbcState s = st[i];
     const double eT = exp(-kp.gammaT * 0.5), eR = exp(-kp.gammaR * 0.5);
     for (int a = 0; a < 3; ++a) {
@@ -81,6 +79,12 @@ __global__ __launch_bounds__(128) void k_rb_first_half(RbcState* __restrict__ st
     st[i] = s;
 }
 
+__global__ __launch_bounds__(128) void k_rb_first_half(RbcState* __restrict__ st, KParams kp)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kp.nrbc) rb1_cell(st, kp, i);
+}
+
 // ---- S2: cell list (counting sort, ids ascending per cell) --------------------------------
 __device__ __forceinline__ int cell_coord(const KParams& kp, int a, double x)
 {
@@ -90,11 +94,9 @@ __device__ __forceinline__ int cell_coord(const KParams& kp, int a, double x)
     return c;
 }
 
-__global__ __launch_bounds__(256) void k_cells_bin(const RbcState* __restrict__ st, int* cellid,
-                                                   int* cnt, KParams kp)
+__device__ __forceinline__ void bin_cell(const RbcState* __restrict__ st, int* cellid, int* cnt,
+                                         const KParams& kp, int i)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= kp.nrbc) return;
     const double* R = st[i].R;
     const int c = cell_coord(kp, 0, R[0]) +
                   kp.ncell[0] * (cell_coord(kp, 1, R[1]) + kp.ncell[1] * cell_coord(kp, 2, R[2]));
@@ -102,9 +104,16 @@ __global__ __launch_bounds__(256) void k_cells_bin(const RbcState* __restrict__ 
     atomicAdd(cnt + c, 1);
 }
 
+__global__ __launch_bounds__(256) void k_cells_bin(const RbcState* __restrict__ st, int* cellid,
+                                                   int* cnt, KParams kp)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kp.nrbc) bin_cell(st, cellid, cnt, kp, i);
+}
+
 // exclusive scan of n ints in one block of 1024 threads, 4096 values per round (each thread
 // four consecutive values, so the loads are coalesced); also clears `cnt`
-__global__ __launch_bounds__(1024) void k_scan_clear(int* cnt, int* off, int n)
+__device__ __forceinline__ void scan_clear_block(int* cnt, int* off, int n)
 {
     __shared__ int wsum[16];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -149,20 +158,31 @@ __global__ __launch_bounds__(1024) void k_scan_clear(int* cnt, int* off, int n)
     if (t == 0) off[n] = carry;
 }
 
+__global__ __launch_bounds__(1024) void k_scan_clear(int* cnt, int* off, int n)
+{
+    scan_clear_block(cnt, off, n);
+}
+
+__device__ __forceinline__ void scatter_cell(const int* __restrict__ cellid,
+                                             const int* __restrict__ off, int* fill, int* ids, int i)
+{
+    const int c = cellid[i];
+    ids[off[c] + atomicAdd(fill + c, 1)] = i;
+}
+
 __global__ __launch_bounds__(256) void k_cells_scatter(const int* __restrict__ cellid,
                                                        const int* __restrict__ off, int* fill,
                                                        int* ids, int nrbc)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nrbc) return;
-    const int c = cellid[i];
-    ids[off[c] + atomicAdd(fill + c, 1)] = i;
+    if (i < nrbc) scatter_cell(cellid, off, fill, ids, i);
 }
 
-__global__ __launch_bounds__(256) void k_cells_sort(const int* __restrict__ off, int* ids, int ncells)
+// ids of grid cell c in ascending order (insertion sort of the short list); the fill
+// counter of the cell is cleared for the next build
+__device__ __forceinline__ void sort_cell(const int* __restrict__ off, int* ids, int* fill, int c)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncells) return;
+    fill[c] = 0;
     const int b = off[c], e = off[c + 1];
     for (int k = b + 1; k < e; ++k) {
         const int v = ids[k];
@@ -173,6 +193,13 @@ __global__ __launch_bounds__(256) void k_cells_sort(const int* __restrict__ off,
         }
         ids[j + 1] = v;
     }
+}
+
+__global__ __launch_bounds__(256) void k_cells_sort(const int* __restrict__ off, int* ids, int* fill,
+                                                    int ncells)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncells) sort_cell(off, ids, fill, c);
 }
 
 // ---- support tile of one cell --------------------------------------------------------------
@@ -481,19 +508,16 @@ __global__ __launch_bounds__(MC_THREADS) void k_map_couple_tile(const RbcState* 
 // neighbouring rows. More candidates than kp.cand_cap: the cell goes to the overflow list
 // ovf[1 + k] (count ovf[0]) for k_map_couple_tile.
 template <typename RT>
-__global__ __launch_bounds__(64) void k_map_couple(const RbcState* __restrict__ st,
-                                                   RbcCouple* __restrict__ cp,
-                                                   uint32_t* __restrict__ nodeword,
-                                                   int* __restrict__ ids, RT* __restrict__ vals,
-                                                   const int* __restrict__ order,
-                                                   const RT* __restrict__ u,
-                                                   const RT* __restrict__ sig, KParams kp,
-                                                   unsigned* __restrict__ err,
-                                                   int* __restrict__ ovf)
+__device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
+                                                const RbcState* __restrict__ st,
+                                                RbcCouple* __restrict__ cp,
+                                                uint32_t* __restrict__ nodeword,
+                                                int* __restrict__ ids, RT* __restrict__ vals,
+                                                const int* __restrict__ order,
+                                                const RT* __restrict__ u,
+                                                const RT* __restrict__ sig, const KParams& kp,
+                                                unsigned* __restrict__ err, int* __restrict__ ovf)
 {
-    extern __shared__ unsigned char smem[];
-    const int k = xcd_chunk_index(1);
-    if (k >= kp.nrbc) return;
     const int i = order[k];
     const RbcState& s = st[i];
     const int lane = threadIdx.x;
@@ -705,6 +729,23 @@ __global__ __launch_bounds__(64) void k_map_couple(const RbcState* __restrict__ 
     }
 }
 
+template <typename RT>
+__global__ __launch_bounds__(64) void k_map_couple(const RbcState* __restrict__ st,
+                                                   RbcCouple* __restrict__ cp,
+                                                   uint32_t* __restrict__ nodeword,
+                                                   int* __restrict__ ids, RT* __restrict__ vals,
+                                                   const int* __restrict__ order,
+                                                   const RT* __restrict__ u,
+                                                   const RT* __restrict__ sig, KParams kp,
+                                                   unsigned* __restrict__ err,
+                                                   int* __restrict__ ovf)
+{
+    extern __shared__ unsigned char smem[];
+    const int k = xcd_chunk_index(1);
+    if (k < kp.nrbc)
+        map_couple_cell<RT>(k, smem, st, cp, nodeword, ids, vals, order, u, sig, kp, err, ovf);
+}
+
 // ---- S5: Gay-Berne forces and torques (Sec. II E, Eqs. 24-28; App. B) -----------------------
 // F on i = -du/dR R^ - (1/R^2) du/dphi [k - (k.R^) R^], k = H^-1 R_ij, H = A_i + A_j;
 // torques tau_i = (1/R) R_ci x f_k, R_ci = -A_i k, f_k = -(1/R) du/dphi k (lab frame).
@@ -831,21 +872,20 @@ __device__ __forceinline__ int candidate(const CandidateRanges& cr, const int* _
 
 // one wavefront per cell: lanes stride over the flattened candidates (cells, then wall
 // points), then a fixed-order shuffle reduction (bitwise repeatable)
-__global__ __launch_bounds__(256) void k_gay_berne(const RbcState* __restrict__ st,
-                                                   RbcCouple* __restrict__ cp,
-                                                   const int* __restrict__ order,
-                                                   const int* __restrict__ cell_off,
-                                                   const int* __restrict__ cell_ids,
-                                                   const int* __restrict__ wall_xyz,
-                                                   const int* __restrict__ wcell_off,
-                                                   const int* __restrict__ wcell_ids, KParams kp,
-                                                   unsigned* err)
+// one wavefront per cell k of the sorted order (wavefront wv of its block)
+__device__ __forceinline__ void gay_berne_cell(int k, const RbcState* __restrict__ st,
+                                               RbcCouple* __restrict__ cp,
+                                               const int* __restrict__ order,
+                                               const int* __restrict__ cell_off,
+                                               const int* __restrict__ cell_ids,
+                                               const int* __restrict__ wall_xyz,
+                                               const int* __restrict__ wcell_off,
+                                               const int* __restrict__ wcell_ids,
+                                               const KParams& kp, unsigned* err)
 {
     __shared__ CandidateRanges ranges[4][2];
     __shared__ int cells[4][27];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int k = xcd_chunk_index(4) + wv;
-    if (k >= kp.nrbc) return;
     const int i = order[k];
     const double* Ri = st[i].R;
     const double* Qi = st[i].Q;
@@ -904,6 +944,21 @@ __global__ __launch_bounds__(256) void k_gay_berne(const RbcState* __restrict__ 
     }
 }
 
+__global__ __launch_bounds__(256) void k_gay_berne(const RbcState* __restrict__ st,
+                                                   RbcCouple* __restrict__ cp,
+                                                   const int* __restrict__ order,
+                                                   const int* __restrict__ cell_off,
+                                                   const int* __restrict__ cell_ids,
+                                                   const int* __restrict__ wall_xyz,
+                                                   const int* __restrict__ wcell_off,
+                                                   const int* __restrict__ wcell_ids, KParams kp,
+                                                   unsigned* err)
+{
+    const int k = xcd_chunk_index(4) + (int)(threadIdx.x >> 6);
+    if (k < kp.nrbc)
+        gay_berne_cell(k, st, cp, order, cell_off, cell_ids, wall_xyz, wcell_off, wcell_ids, kp, err);
+}
+
 // ---- S6: combined force/torque, hydrodynamic force/torque, second half --------------------
 // F^comb = F^mech + gT M u~; tau^comb = tau^mech + Q^T T^S + gR I (s Q^T w~);
 // F^hyd = -M gT (V^1/2 - u~); T^hyd = Q [-gR I (Omega^1/2 - s Q^T w~)] + T^S (lab).
@@ -912,13 +967,10 @@ __global__ __launch_bounds__(256) void k_gay_berne(const RbcState* __restrict__ 
 // force and torque, half-step friction and half kick (needs the Gay-Berne forces);
 // RB2_ALL: RB2_HYDRO and RB2_KICK.
 template <typename RT>
-__global__ __launch_bounds__(128) void k_rb_second_half(RbcState* __restrict__ st,
-                                                        RbcCouple* __restrict__ cp,
-                                                        Gather<RT>* __restrict__ gat, KParams kp,
-                                                        int mode)
+__device__ __forceinline__ void rb2_cell(RbcState* __restrict__ st, RbcCouple* __restrict__ cp,
+                                         Gather<RT>* __restrict__ gat, const KParams& kp, int mode,
+                                         int i)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= kp.nrbc) return;
     RbcState s = st[i];
     RbcCouple c = cp[i];
     double wb[3], tsb[3], tb[3], tl[3];
@@ -960,6 +1012,16 @@ __global__ __launch_bounds__(128) void k_rb_second_half(RbcState* __restrict__ s
     gat[i] = G;
 }
 
+template <typename RT>
+__global__ __launch_bounds__(128) void k_rb_second_half(RbcState* __restrict__ st,
+                                                        RbcCouple* __restrict__ cp,
+                                                        Gather<RT>* __restrict__ gat, KParams kp,
+                                                        int mode)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kp.nrbc) rb2_cell<RT>(st, cp, gat, kp, mode, i);
+}
+
 __global__ void k_init_combined(RbcState* __restrict__ st, const RbcCouple* __restrict__ cp, int nrbc)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -974,6 +1036,89 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, long long n)
 {
     const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n) p[k] = v;
+}
+
+// ---- fused multi-lattice versions of the per-cell stages (one launch for many contexts) -----
+constexpr int FUSED_TILE_BLOCKS = 4;   // blocks per slot of the full-tile overflow pass
+
+__global__ __launch_bounds__(256) void kf_cells_a(const FusedArgs fa)
+{
+    int lb;
+    const SlotDesc& d = *fa.slot[fused_slot(fa, lb)];
+    const KParams kp = d.kp;
+    const int i = lb * 256 + (int)threadIdx.x;
+    if (i >= kp.nrbc) return;
+    rb1_cell(d.b.st, kp, i);
+    bin_cell(d.b.st, d.b.cellid, d.b.cell_cnt, kp, i);
+}
+
+__global__ __launch_bounds__(1024) void kf_scan(const FusedArgs fa)
+{
+    int lb;
+    const SlotDesc& d = *fa.slot[fused_slot(fa, lb)];
+    scan_clear_block(d.b.cell_cnt, d.b.cell_off, d.kp.ncell[0] * d.kp.ncell[1] * d.kp.ncell[2]);
+}
+
+__global__ __launch_bounds__(256) void kf_scatter(const FusedArgs fa)
+{
+    int lb;
+    const SlotDesc& d = *fa.slot[fused_slot(fa, lb)];
+    const int i = lb * 256 + (int)threadIdx.x;
+    if (i < d.kp.nrbc) scatter_cell(d.b.cellid, d.b.cell_off, d.b.cell_cnt, d.b.cell_ids, i);
+}
+
+__global__ __launch_bounds__(256) void kf_sort(const FusedArgs fa)
+{
+    int lb;
+    const SlotDesc& d = *fa.slot[fused_slot(fa, lb)];
+    const int c = lb * 256 + (int)threadIdx.x;
+    if (c < d.kp.ncell[0] * d.kp.ncell[1] * d.kp.ncell[2]) sort_cell(d.b.cell_off, d.b.cell_ids, d.b.cell_cnt, c);
+}
+
+template <typename RT>
+__global__ __launch_bounds__(64) void kf_map(const FusedArgs fa)
+{
+    extern __shared__ unsigned char smem[];
+    int lb;
+    const SlotDesc& d = *fa.slot[fused_slot(fa, lb)];
+    const KParams kp = d.kp;
+    if (lb < kp.nrbc)
+        map_couple_cell<RT>(lb, smem, d.b.st, d.b.cp, d.b.nodeword, d.b.map_ids, (RT*)d.b.map_vals,
+                            d.b.cell_ids, (const RT*)d.b.u, (const RT*)d.b.sig, kp, d.b.err, d.b.ovf);
+}
+
+template <typename RT>
+__global__ __launch_bounds__(MC_THREADS) void kf_map_tile(const FusedArgs fa)
+{
+    extern __shared__ unsigned char smem[];
+    int lb;
+    const SlotDesc& d = *fa.slot[fused_slot(fa, lb)];
+    const KParams kp = d.kp;
+    const int n = d.b.ovf[0];
+    for (int b = lb; b < n; b += FUSED_TILE_BLOCKS)
+        map_couple_tile<RT>(d.b.ovf[1 + b], smem, d.b.st, d.b.cp, d.b.nodeword, d.b.map_ids,
+                            (RT*)d.b.map_vals, (const RT*)d.b.u, (const RT*)d.b.sig, kp, d.b.err);
+}
+
+__global__ __launch_bounds__(256) void kf_gb(const FusedArgs fa)
+{
+    int lb;
+    const SlotDesc& d = *fa.slot[fused_slot(fa, lb)];
+    const KParams kp = d.kp;
+    const int k = lb * 4 + (int)(threadIdx.x >> 6);
+    if (k < kp.nrbc)
+        gay_berne_cell(k, d.b.st, d.b.cp, d.b.cell_ids, d.b.cell_off, d.b.cell_ids, d.b.wall_xyz,
+                       d.b.wcell_off, d.b.wcell_ids, kp, d.b.err);
+}
+
+template <typename RT>
+__global__ __launch_bounds__(128) void kf_rb2(const FusedArgs fa)
+{
+    int lb;
+    const SlotDesc& d = *fa.slot[fused_slot(fa, lb)];
+    const KParams kp = d.kp;
+    const int i = lb * 128 + (int)threadIdx.x;
+    if (i < kp.nrbc) rb2_cell<RT>(d.b.st, d.b.cp, (Gather<RT>*)d.b.gat, kp, RB2_ALL, i);
 }
 
 // ---- launchers ---------------------------------------------------------------------------------
@@ -998,10 +1143,9 @@ void launch_cell_list(const CellBuffers& b, const KParams& kp, hipStream_t st)
     hipLaunchKernelGGL(k_scan_clear, dim3(1), dim3(1024), 0, st, b.cell_cnt, b.cell_off, nc);
     hipLaunchKernelGGL(k_cells_scatter, dim3(nblk(kp.nrbc, 256)), dim3(256), 0, st, b.cellid,
                        b.cell_off, b.cell_cnt, b.cell_ids, kp.nrbc);
+    // the sort leaves the fill counters at zero for the next call
     hipLaunchKernelGGL(k_cells_sort, dim3(nblk(nc, 256)), dim3(256), 0, st, b.cell_off,
-                       b.cell_ids, nc);
-    // leave the fill counters at zero for the next call
-    launch_fill_u32(reinterpret_cast<uint32_t*>(b.cell_cnt), 0u, nc, st);
+                       b.cell_ids, b.cell_cnt, nc);
 }
 
 static inline unsigned grid8(long long units, int per_block)
@@ -1057,6 +1201,45 @@ void launch_init_combined(const CellBuffers& b, const KParams& kp, hipStream_t s
                        kp.nrbc);
 }
 
+int fused_blocks(const KParams& kp, int stage)
+{
+    const long long nc = (long long)kp.ncell[0] * kp.ncell[1] * kp.ncell[2];
+    const int cells = kp.nrbc;
+    switch (stage) {
+    case FS_CELLS_A: return (int)nblk(cells, 256);
+    case FS_SCAN: return cells > 0 ? 1 : 0;
+    case FS_SCATTER: return (int)nblk(cells, 256);
+    case FS_SORT: return cells > 0 ? (int)nblk(nc, 256) : 0;
+    case FS_CLEAR: return cells > 0 ? (int)nblk(kp.N, 256) : 0;
+    case FS_MAP: return cells;
+    case FS_MAP_TILE: return cells > 0 ? FUSED_TILE_BLOCKS : 0;
+    case FS_GB: return (int)nblk(cells, 4);
+    case FS_RB2: return (int)nblk(cells, 128);
+    case FS_STREAM: return (int)((kp.nx + 63) / 64) * ((kp.ny + 3) / 4) * kp.nz;
+    default: return 0;
+    }
+}
+
+template <typename RT>
+void launch_fused_cells(const FusedArgs& fa, int stage, size_t lds, hipStream_t st)
+{
+    const unsigned g = (unsigned)fa.start[fa.n];
+    if (g == 0) return;
+    switch (stage) {
+    case FS_CELLS_A: hipLaunchKernelGGL(kf_cells_a, dim3(g), dim3(256), 0, st, fa); break;
+    case FS_SCAN: hipLaunchKernelGGL(kf_scan, dim3(g), dim3(1024), 0, st, fa); break;
+    case FS_SCATTER: hipLaunchKernelGGL(kf_scatter, dim3(g), dim3(256), 0, st, fa); break;
+    case FS_SORT: hipLaunchKernelGGL(kf_sort, dim3(g), dim3(256), 0, st, fa); break;
+    case FS_MAP: hipLaunchKernelGGL((kf_map<RT>), dim3(g), dim3(64), lds, st, fa); break;
+    case FS_MAP_TILE: hipLaunchKernelGGL((kf_map_tile<RT>), dim3(g), dim3(MC_THREADS), lds, st, fa); break;
+    case FS_GB: hipLaunchKernelGGL(kf_gb, dim3(g), dim3(256), 0, st, fa); break;
+    case FS_RB2: hipLaunchKernelGGL((kf_rb2<RT>), dim3(g), dim3(128), 0, st, fa); break;
+    default: break;
+    }
+}
+
+template void launch_fused_cells<double>(const FusedArgs&, int, size_t, hipStream_t);
+template void launch_fused_cells<float>(const FusedArgs&, int, size_t, hipStream_t);
 template void launch_map_couple<double>(const CellBuffers&, const KParams&, hipStream_t);
 template void launch_map_couple<float>(const CellBuffers&, const KParams&, hipStream_t);
 template void launch_rb_second_half<double>(const CellBuffers&, const KParams&, int, hipStream_t);

@@ -6,7 +6,9 @@ gets its own arena, its own HIP stream (default priority) and its own context of
 library. Every scheduler tick enqueues the next chunk of steps of every resident request
 with one ``lb_batch_step`` call, which interleaves the requests step by step, so their
 kernels overlap on the device. Optionally each request's chunk is captured once into a HIP
-graph (through PyTorch's graph API on the request's stream) and replayed. A request finishes
+graph (through PyTorch's graph API on the request's stream) and replayed. In the fused mode all
+requests share one stream and ``lb_batch_step`` runs each stage of a step as one launch over
+every resident request (batching at the kernel level). A request finishes
 when its last chunk's event has completed; its memory is released and queued requests are
 admitted in the same tick. Latency = completion time - arrival time.
 """
@@ -75,9 +77,13 @@ class Server:
 
     def __init__(self, budget_bytes: int, chunk_steps: int = 50, use_graphs: bool = False,
                  device: str = "cuda:0", max_inflight_chunks: int = 2, digests: bool = False,
-                 max_active: int = 64, progress=None):
+                 max_active: int = 64, progress=None, fused: bool = False):
         if use_graphs and chunk_steps % 2:
             raise ValueError("graph chunks need an even step count (A/B buffers)")
+        if use_graphs and fused:
+            raise ValueError("the fused mode launches per step over the resident set: no graphs")
+        self.fused = fused
+        self.shared_stream = torch.cuda.Stream(device=device) if fused else None
         self.budget = int(budget_bytes)
         self.chunk = int(chunk_steps)
         self.use_graphs = use_graphs
@@ -114,7 +120,7 @@ class Server:
             if self.used + fp > self.budget or len(self.active) >= self.max_active:
                 break                                   # first come, first served
             heapq.heappop(self.queue)
-            stream = torch.cuda.Stream(device=self.device)
+            stream = self.shared_stream if self.fused else torch.cuda.Stream(device=self.device)
             sim = lbrbc.Simulation(req.cfg, req.solid, R=req.R if len(req.R) else None,
                                    Q=req.Q if len(req.R) else None, device=self.device,
                                    stream=stream)
@@ -133,6 +139,8 @@ class Server:
         a.graph_steps = self.chunk
 
     def _enqueue(self):
+        if self.fused:
+            return self._enqueue_fused()
         eager, counts = [], []
         for a in self.active.values():
             left = a.req.steps - a.done_steps
@@ -157,6 +165,20 @@ class Server:
                 ev = torch.cuda.Event()
                 ev.record(a.stream)
                 a.events.append(ev)
+
+    def _enqueue_fused(self):
+        """One chunk of every resident request with steps left, as one fused batch."""
+        todo = [a for a in self.active.values()
+                if a.req.steps - a.done_steps > 0 and len(a.events) < self.max_inflight]
+        if not todo:
+            return
+        counts = [min(self.chunk, a.req.steps - a.done_steps) for a in todo]
+        lbrbc.lb_batch_step([a.sim for a in todo], counts)
+        ev = torch.cuda.Event()
+        ev.record(self.shared_stream)
+        for a, n in zip(todo, counts):
+            a.done_steps += n
+            a.events.append(ev)
 
     def _retire(self):
         for rid in list(self.active):

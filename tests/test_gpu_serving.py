@@ -87,3 +87,55 @@ def test_graph_every_replay_matches_eager():
         d_g = hashlib.sha1(graph.lb_save()[56:]).hexdigest()
         assert d_e == d_g, rep
         assert o_e.mass == o_g.mass and o_e.flow_rate == o_g.flow_rate
+
+
+def test_fused_batch_equals_each_alone():
+    """lb_batch_step over contexts on one stream runs each stage as one launch for all of them
+    (fused); each context ends bitwise where it ends when stepped alone. The mix has different
+    step counts, a context without cells and one large enough to fork onto a side stream when
+    stepped alone."""
+    import hashlib
+
+    import torch
+
+    from paper_1107_4889_amd import lbrbc
+
+    reqs = _requests(2, seed=80, steps=(40, 40))
+    big_solid, big = synth.tube_workload(64, 64, 256, 30.0, hematocrit=0.40, seed=1107)
+    bigcfg = dict(nx=64, ny=64, nz=256, periodic=(0, 0, 1), tau0=0.8, g_ext=(0, 0, 1e-6),
+                  storage="f32")
+    cases = [(r.cfg, r.solid, r.R, r.Q) for r in reqs]
+    cases.append((reqs[0].cfg, reqs[0].solid, None, None))          # plasma only
+    cases.append((bigcfg, big_solid, big.R, big.Q))                    # >= 2048 cells
+    nsteps = [30, 50, 40, 20]
+
+    def digest(sim):
+        return hashlib.sha1(sim.lb_save()[56:]).hexdigest()
+
+    alone = []
+    for (cfg, solid, R, Q), n in zip(cases, nsteps):
+        sim = lbrbc.Simulation(cfg, solid, R=R, Q=Q)
+        sim.lb_step(n)
+        sim.lb_sync()
+        alone.append(digest(sim))
+        del sim
+    shared = torch.cuda.Stream()
+    sims = [lbrbc.Simulation(cfg, solid, R=R, Q=Q, stream=shared) for cfg, solid, R, Q in cases]
+    lbrbc.lb_batch_step(sims, nsteps)
+    torch.cuda.synchronize()
+    for k, (sim, d) in enumerate(zip(sims, alone)):
+        assert sim.lb_observe().flags == 0
+        assert digest(sim) == d, k
+
+
+def test_fused_server_matches_alone():
+    from paper_1107_4889_amd.serving import Server
+
+    reqs = _requests(4, seed=81)
+    alone = {}
+    for r in reqs:
+        res, _ = Server(budget_bytes=8 << 30, chunk_steps=16, digests=True).run([r])
+        alone[r.rid] = res[0].digest
+    mixed, _ = Server(budget_bytes=8 << 30, chunk_steps=16, digests=True, fused=True).run(reqs)
+    for m in mixed:
+        assert m.digest == alone[m.rid] and m.flags == 0
