@@ -169,7 +169,6 @@ def serve(args):
             "fused_launches": bool(args.fused),
             "budget_gib": args.budget_gib,
             "max_active": args.max_active,
-            "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
             "mean_queue_wait_s": round(float(np.mean([r.admitted - r.arrival for r in results])), 4),
         },
     }
@@ -281,9 +280,6 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--max-active", type=int, default=64)
     ap.add_argument("--workers", type=int, default=8)
-    ap.add_argument("--hw-queues", type=int, default=16,
-                    help="serving mode: HIP hardware queues per process (GPU_MAX_HW_QUEUES, 1..32), "
-                         "so that more resident requests' kernels run concurrently")
     ap.add_argument("--precision", action="store_true",
                     help="reduced-precision storage study against FP64 on the same GPU")
     args = ap.parse_args()
@@ -292,10 +288,6 @@ def main():
               "on a single MI355X; a multi-GPU run would shard the lattice in z-slabs)",
               file=sys.stderr, flush=True)
         sys.exit(2)
-
-    if args.serve and "GPU_MAX_HW_QUEUES" not in os.environ:
-        # read when the HIP runtime starts, so it is set before torch is imported
-        os.environ["GPU_MAX_HW_QUEUES"] = str(max(1, min(32, args.hw_queues)))
 
     import torch
 

@@ -165,10 +165,25 @@ lb_status rbc_get_map(lb_ctx ctx, int* off, int* ids, long long* len);
 lb_status lb_save(lb_ctx ctx, void* buf, size_t* bytes);
 lb_status lb_load(lb_ctx ctx, const void* buf, size_t bytes);
 
-/* Serving: enqueue nsteps[i] steps for each of n contexts, interleaved step by step so
- * the contexts' kernels overlap on the device. Contexts may use different streams. */
+/* Serving: enqueue nsteps[i] steps for each of n contexts (asynchronous).
+ * - When all contexts share one stream and one storage type, and none has open boundaries,
+ *   WSS accumulation or kernel timing on, each stage of a step is ONE launch over all the
+ *   contexts still stepping (fused multi-lattice kernels, up to 64 contexts per launch);
+ *   the results are bitwise those of stepping each context alone.
+ * - Otherwise the contexts' steps are interleaved step by step on their own streams, so
+ *   their kernels can overlap on the device.
+ * nsteps[i] < 0 or a NULL context: LB_EINVAL; a poisoned context: LB_ESTATE (nothing is
+ * enqueued in either case). */
 lb_status lb_batch_step(lb_ctx* ctxs, const int* nsteps, int n);
 
+/* Move the context's later work to another HIP stream (not NULL). The caller orders it after
+ * the work already enqueued (e.g. an event recorded on the old stream and waited on by the
+ * new one); the library does not. Used to put contexts on one stream for fused batches and
+ * to take a finished one off it. NULL context or stream: LB_EINVAL. */
+lb_status lb_set_stream(lb_ctx ctx, void* hip_stream);
+
+/* Wait for the context's stream and report device faults (LB_EUNSTABLE, LB_EOVERLAP,
+ * LB_ECAPACITY) raised since the last check; after a fault the context is poisoned. */
 lb_status lb_sync(lb_ctx ctx);
 const char* lb_last_error(lb_ctx ctx);
 void lb_destroy(lb_ctx ctx);

@@ -494,10 +494,12 @@ __global__ __launch_bounds__(256) void kf_stream(const FusedArgs fa)
     const int sl = fused_slot(fa, lb);
     const SlotDesc& d = *fa.slot[sl];
     const KParams kp = d.kp;
-    const int nbx = (kp.nx + 63) >> 6, nby = (kp.ny + 3) >> 2;
-    const int bx = lb % nbx, rr = lb / nbx, by = rr % nby, z = rr / nby;
-    const int x = bx * 64 + (int)threadIdx.x, y = by * 4 + (int)threadIdx.y;
-    if (x >= kp.nx || y >= kp.ny) return;
+    // flat node order (no idle lanes on lattices narrower than, or not a multiple of, 64)
+    const unsigned n = (unsigned)lb * 256u + threadIdx.y * 64u + threadIdx.x;
+    if (n >= (unsigned)kp.N) return;
+    const unsigned nxy = (unsigned)kp.nx * (unsigned)kp.ny;
+    const int z = (int)(n / nxy), rem = (int)(n - (unsigned)z * nxy);
+    const int y = rem / kp.nx, x = rem - y * kp.nx;
     const bool odd = (fa.parity >> sl) & 1ull;
     const PlanesLd<ST, RT> pl{(const ST*)(odd ? d.fB : d.fA), (ST*)(odd ? d.fA : d.fB), (RT*)d.b.u,
                               (RT*)d.b.sig, (unsigned long long)kp.ld};

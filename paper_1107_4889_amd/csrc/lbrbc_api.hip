@@ -856,6 +856,13 @@ lb_status rbc_collide(lb_ctx c, double* F, double* T)
     return st;
 }
 
+lb_status lb_set_stream(lb_ctx c, void* hip_stream)
+{
+    if (!c || !hip_stream) return LB_EINVAL;
+    c->stream = (hipStream_t)hip_stream;
+    return LB_OK;
+}
+
 lb_status lb_sync(lb_ctx c)
 {
     if (!c) return LB_EINVAL;

@@ -1215,7 +1215,7 @@ int fused_blocks(const KParams& kp, int stage)
     case FS_MAP_TILE: return cells > 0 ? FUSED_TILE_BLOCKS : 0;
     case FS_GB: return (int)nblk(cells, 4);
     case FS_RB2: return (int)nblk(cells, 128);
-    case FS_STREAM: return (int)((kp.nx + 63) / 64) * ((kp.ny + 3) / 4) * kp.nz;
+    case FS_STREAM: return (int)nblk(kp.N, 256);
     default: return 0;
     }
 }

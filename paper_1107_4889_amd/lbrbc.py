@@ -28,7 +28,8 @@ STORAGE = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
 SYMBOLS = ["lb_query_footprint", "lb_init", "lb_step", "rbc_couple", "rbc_collide", "lb_observe",
            "lb_wall_shear_stress", "lb_apparent_viscosity", "lb_wss_accumulate", "lb_get_fields",
            "lb_set_fields", "rbc_get_state", "rbc_set_state", "rbc_get_coupling", "rbc_get_cells",
-           "rbc_get_map", "lb_save", "lb_load", "lb_batch_step", "lb_sync", "lb_last_error",
+           "rbc_get_map", "lb_save", "lb_load", "lb_batch_step", "lb_set_stream", "lb_sync",
+           "lb_last_error",
            "lb_destroy", "lb_set_timing", "lb_kernel_time"]
 
 
@@ -78,6 +79,7 @@ _sig = {
     "lb_init": [ctypes.POINTER(lb_config), _P, ctypes.POINTER(lb_rbc), ctypes.c_int, _P,
                 ctypes.c_size_t, _P, ctypes.POINTER(_P)],
     "lb_step": [_P, ctypes.c_int],
+    "lb_set_stream": [_P, _P],
     "rbc_couple": [_P],
     "rbc_collide": [_P, _D, _D],
     "lb_observe": [_P, ctypes.POINTER(lb_observables)],
@@ -211,6 +213,13 @@ class Simulation:
         if st:
             msg = _lib.lb_last_error(self.h)
             raise LbError(st, f"{what} ({msg.decode() if msg else ''})")
+
+    def lb_set_stream(self, stream):
+        """Later work of this context goes to `stream` (a torch stream); the caller orders it
+        after the work already enqueued."""
+        self.stream = stream
+        self.arena.record_stream(stream)
+        self._chk(_lib.lb_set_stream(self.h, ctypes.c_void_p(stream.cuda_stream)), "lb_set_stream")
 
     # -- stepping
     def lb_step(self, n: int = 1):

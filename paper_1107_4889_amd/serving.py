@@ -120,10 +120,14 @@ class Server:
             if self.used + fp > self.budget or len(self.active) >= self.max_active:
                 break                                   # first come, first served
             heapq.heappop(self.queue)
-            stream = self.shared_stream if self.fused else torch.cuda.Stream(device=self.device)
+            # set-up runs on the request's own stream (lb_init waits for it); in the fused
+            # mode the context then moves to the shared stream, so set-up does not drain it
+            stream = torch.cuda.Stream(device=self.device)
             sim = lbrbc.Simulation(req.cfg, req.solid, R=req.R if len(req.R) else None,
                                    Q=req.Q if len(req.R) else None, device=self.device,
                                    stream=stream)
+            if self.fused:
+                sim.lb_set_stream(self.shared_stream)
             self.used += fp
             self.active[rid] = _Active(req, sim, stream, self._now())
             self.active[rid].footprint = fp
@@ -186,6 +190,9 @@ class Server:
             while a.events and a.events[0].query():
                 a.events.pop(0)
             if a.done_steps >= a.req.steps and not a.events:
+                if self.fused:
+                    # its last chunk is complete: read it back off the shared stream
+                    a.sim.lb_set_stream(a.stream)
                 a.stream.synchronize()
                 o = a.sim.lb_observe()
                 digest = hashlib.sha1(a.sim.lb_save()[_CKPT_HEADER:]).hexdigest() if self.digests else None
