@@ -205,8 +205,10 @@ __device__ __forceinline__ void collide_pairs(const RT* f, const PL& pl, unsigne
 // solid sources are replaced by bounce-back, open planes are rewritten by the boundary
 // kernel), so that each store writes whole cache lines: stores that leave part of a line
 // unwritten, as at every wall crossing of a lattice row, measured markedly slower in HBM.
-template <typename ST, typename RT, typename PL>
-__device__ __forceinline__ void stream_collide_node(const PL& pl, const uint32_t* __restrict__ nodeword,
+// CLEAR: also write the node word back with the coverage count cleared (every lane of the
+// wavefront, whole lines), for the next step's map pass (fused launches, no open planes)
+template <typename ST, typename RT, typename PL, bool CLEAR = false>
+__device__ __forceinline__ void stream_collide_node(const PL& pl, uint32_t* __restrict__ nodeword,
                                                     const MapPlanes<RT>& mp,
                                                     const Gather<RT>* __restrict__ gat,
                                                     const KParams& kp, unsigned* __restrict__ err,
@@ -281,12 +283,13 @@ __device__ __forceinline__ void stream_collide_node(const PL& pl, const uint32_t
     __builtin_nontemporal_store(live ? ks * (pxy - rho * ux * uy) : z0, at32(pl.str(3), n));
     __builtin_nontemporal_store(live ? ks * (pxz - rho * ux * uz) : z0, at32(pl.str(4), n));
     __builtin_nontemporal_store(live ? ks * (pyz - rho * uy * uz) : z0, at32(pl.str(5), n));
+    if (CLEAR) __builtin_nontemporal_store(w & NW_STATIC, at32(nodeword, n));
     if (live && (!(rho > RT(0)) || !(usq <= RT(0.09)))) atomicOr(err, ERR_UNSTABLE);
 }
 
 template <typename ST, typename RT>
 __global__ __launch_bounds__(256) void k_stream_collide(
-    const Planes<ST, RT> pl, const uint32_t* __restrict__ nodeword, const MapPlanes<RT> mp,
+    const Planes<ST, RT> pl, uint32_t* __restrict__ nodeword, const MapPlanes<RT> mp,
     const Gather<RT>* __restrict__ gat, KParams kp, unsigned* __restrict__ err)
 {
     const int x = blockIdx.x * 64 + threadIdx.x;
@@ -504,7 +507,8 @@ __global__ __launch_bounds__(256) void kf_stream(const FusedArgs fa)
     const PlanesLd<ST, RT> pl{(const ST*)(odd ? d.fB : d.fA), (ST*)(odd ? d.fA : d.fB), (RT*)d.b.u,
                               (RT*)d.b.sig, (unsigned long long)kp.ld};
     const MapPlanes<RT> mp = map_planes_dev<RT>(d.b.map_ids, d.b.map_vals, kp);
-    stream_collide_node<ST, RT>(pl, d.b.nodeword, mp, (const Gather<RT>*)d.b.gat, kp, d.b.err, x, y, z);
+    stream_collide_node<ST, RT, PlanesLd<ST, RT>, true>(pl, d.b.nodeword, mp, (const Gather<RT>*)d.b.gat,
+                                                        kp, d.b.err, x, y, z);
 }
 
 // ---- launchers ---------------------------------------------------------------------------------
@@ -522,8 +526,9 @@ void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword
     }
     for (int a = 0; a < 3; ++a) pl.u[a] = (RT*)u + a * ld;
     for (int a = 0; a < 6; ++a) pl.sig[a] = (RT*)sig + a * ld;
-    hipLaunchKernelGGL((k_stream_collide<ST, RT>), grid, dim3(64, 4, 1), 0, st, pl, nodeword,
-                       map_planes<RT>(ids, vals, kp), (const Gather<RT>*)gat, kp, err);
+    hipLaunchKernelGGL((k_stream_collide<ST, RT>), grid, dim3(64, 4, 1), 0, st, pl,
+                       const_cast<uint32_t*>(nodeword), map_planes<RT>(ids, vals, kp),
+                       (const Gather<RT>*)gat, kp, err);
 }
 
 template <typename ST, typename RT>

@@ -340,6 +340,9 @@ struct lb_ctx_s {
     hipEvent_t ev_fork = nullptr, ev_cells = nullptr, ev_clear = nullptr, ev_gb = nullptr;
     char* base = nullptr;
     void *fA = nullptr, *fB = nullptr;
+    // coverage counts all zero (after init and after a fused step, whose stream-collide clears
+    // them); a single-context step or rbc_couple leaves them set
+    bool counts_clean = true;
     CellBuffers cb{};
     long long step = 0;
     int nrbc = 0;
@@ -546,6 +549,7 @@ void enqueue_step(lb_ctx c)
         }
     });
     if (c->wss_on) c->wss_count++;
+    if (c->nrbc > 0) c->counts_clean = false;
     std::swap(c->fA, c->fB);
     c->step++;
 }
@@ -593,8 +597,17 @@ void enqueue_fused_step(lb_ctx* cs, int n)
             starts(stage);
             launch_fused_cells<RT>(fa, stage, 0, s);
         }
-        starts(FS_CLEAR);
-        launch_fused_lattice<ST, RT>(fa, FS_CLEAR, s);
+        // counts left by a single-context step are cleared here; otherwise the previous fused
+        // stream-collide has cleared them
+        {
+            int tot = 0;
+            for (int i = 0; i < n; ++i) {
+                fa.start[i] = tot;
+                tot += cs[i]->counts_clean ? 0 : fused_blocks(cs[i]->kp, FS_CLEAR);
+            }
+            fa.start[n] = tot;
+            launch_fused_lattice<ST, RT>(fa, FS_CLEAR, s);
+        }
         starts(FS_MAP);
         launch_fused_cells<RT>(fa, FS_MAP, lds_map, s);
         starts(FS_MAP_TILE);
@@ -609,6 +622,7 @@ void enqueue_fused_step(lb_ctx* cs, int n)
     for (int i = 0; i < n; ++i) {
         std::swap(cs[i]->fA, cs[i]->fB);
         cs[i]->step++;
+        cs[i]->counts_clean = true;
     }
 }
 
@@ -830,6 +844,7 @@ lb_status rbc_couple(lb_ctx c)
         using RT = std::remove_pointer_t<decltype(rp)>;
         if (c->nrbc > 0) {
             enqueue_cells_map_couple<RT>(c);
+            c->counts_clean = false;
             launch_rb_second_half<RT>(c->cb, c->kp, RB2_NOW, c->stream);
         }
         launch_spread_field<RT>(c->cb.nodeword, c->cb.map_ids, c->cb.map_vals, c->cb.gat,

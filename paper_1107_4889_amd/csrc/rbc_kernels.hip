@@ -1047,6 +1047,7 @@ __global__ __launch_bounds__(256) void kf_cells_a(const FusedArgs fa)
     const SlotDesc& d = *fa.slot[fused_slot(fa, lb)];
     const KParams kp = d.kp;
     const int i = lb * 256 + (int)threadIdx.x;
+    if (i == 0) d.b.ovf[0] = 0;   // overflow list of this step's map pass
     if (i >= kp.nrbc) return;
     rb1_cell(d.b.st, kp, i);
     bin_cell(d.b.st, d.b.cellid, d.b.cell_cnt, kp, i);
