@@ -97,11 +97,17 @@ class Server:
         self.used = 0
         self.results: list = []
         self.t0 = None
+        self._fp: dict = {}
 
     # -- admission ------------------------------------------------------------------------
     def footprint(self, req: Request) -> int:
-        c = lbrbc.make_config(req.cfg)
-        return lbrbc.lb_query_footprint(c, np.ascontiguousarray(req.solid).reshape(-1), len(req.R))
+        """HBM bytes of the request (computed once per request: it builds the geometry)."""
+        fp = self._fp.get(req.rid)
+        if fp is None:
+            c = lbrbc.make_config(req.cfg)
+            fp = lbrbc.lb_query_footprint(c, np.ascontiguousarray(req.solid).reshape(-1), len(req.R))
+            self._fp[req.rid] = fp
+        return fp
 
     def submit(self, req: Request):
         heapq.heappush(self.queue, (req.arrival, req.rid, req))
