@@ -172,7 +172,7 @@ template <typename ST, typename RT, typename PL, int P>
 __device__ __forceinline__ void collide_pair(const RT* f, const PL& pl, unsigned n,
                                              RT drho, RT rho, RT ux, RT uy, RT uz, RT usq,
                                              const RT g[3], RT gu, RT om, RT kf, RT k2, RT k3,
-                                             const KParams& kp, bool live)
+                                             const KParams& kp, bool live, bool put)
 {
     constexpr int Q = P + 1;
     const RT w = RT(w_(P));
@@ -182,18 +182,20 @@ __device__ __forceinline__ void collide_pair(const RT* f, const PL& pl, unsigned
     const RT asym = w * rho * RT(3) * uc;
     const RT fs = kf * w * (k2 * gc * uc - k3 * gu);
     const RT fa = kf * w * RT(3) * gc;
-    Store<ST, RT>::st(pl.dst(P), n, live ? f[P] - om * (f[P] - sym - asym) + fs + fa : RT(0), kp.f16_scale);
-    Store<ST, RT>::st(pl.dst(Q), n, live ? f[Q] - om * (f[Q] - sym + asym) + fs - fa : RT(0), kp.f16_scale);
+    if (put) {
+        Store<ST, RT>::st(pl.dst(P), n, live ? f[P] - om * (f[P] - sym - asym) + fs + fa : RT(0), kp.f16_scale);
+        Store<ST, RT>::st(pl.dst(Q), n, live ? f[Q] - om * (f[Q] - sym + asym) + fs - fa : RT(0), kp.f16_scale);
+    }
 }
 
 template <typename ST, typename RT, typename PL, int... Ps>
 __device__ __forceinline__ void collide_pairs(const RT* f, const PL& pl, unsigned n,
                                               RT drho, RT rho, RT ux, RT uy, RT uz, RT usq,
                                               const RT g[3], RT gu, RT om, RT kf, RT k2, RT k3,
-                                              const KParams& kp, bool live,
+                                              const KParams& kp, bool live, bool put,
                                               std::integer_sequence<int, Ps...>)
 {
-    (collide_pair<ST, RT, PL, 2 * Ps + 1>(f, pl, n, drho, rho, ux, uy, uz, usq, g, gu, om, kf, k2, k3, kp, live), ...);
+    (collide_pair<ST, RT, PL, 2 * Ps + 1>(f, pl, n, drho, rho, ux, uy, uz, usq, g, gu, om, kf, k2, k3, kp, live, put), ...);
 }
 
 // ---- fused spreading + stream + collide (Sec. II A, Eqs. 1-8) -----------------------------
@@ -217,7 +219,18 @@ __device__ __forceinline__ void stream_collide_node(const PL& pl, uint32_t* __re
     const unsigned n = (unsigned)x + (unsigned)kp.nx * ((unsigned)y + (unsigned)kp.ny * (unsigned)z);
     const uint32_t w = nodeword[n];
     const bool live = (w & NW_FLUID) && !(w & NW_OPEN);
-    if (!__any(live)) return;
+    const unsigned long long lv = __ballot(live);
+    if (!lv) return;
+    // A lane stores when its 128-B line (of S-byte elements) holds a fluid node of this
+    // wavefront; the 64 lanes hold consecutive nodes.
+    const int lane = (int)__lane_id();
+    auto line_has_fluid = [&](unsigned S) {
+        const int first = lane - (int)((n * S & 127u) / S);
+        const int lo = max(first, 0), hi = min(first + (int)(128u / S) - 1, 63);
+        const unsigned long long m = (hi == 63 ? ~0ull : (2ull << hi) - 1ull) & ~((1ull << lo) - 1ull);
+        return (lv & m) != 0ull;
+    };
+    const bool put_f = line_has_fluid((unsigned)sizeof(ST)), put_u = line_has_fluid((unsigned)sizeof(RT));
     RT f[19];
     if (live) {
         pull_all_fast<ST, RT>(f, pl, n, x, y, z, kp, std::make_integer_sequence<int, 19>{});
@@ -264,9 +277,9 @@ __device__ __forceinline__ void stream_collide_node(const PL& pl, uint32_t* __re
         const RT w0 = RT(w_(0));
         const RT fe0 = w0 * (drho - RT(1.5) * rho * usq);
         const RT F0 = -kf * w0 * k3 * gu;
-        Store<ST, RT>::st(pl.dst(0), n, live ? f[0] - om * (f[0] - fe0) + F0 : RT(0), kp.f16_scale);
+        if (put_f) Store<ST, RT>::st(pl.dst(0), n, live ? f[0] - om * (f[0] - fe0) + F0 : RT(0), kp.f16_scale);
     }
-    collide_pairs<ST, RT>(f, pl, n, drho, rho, ux, uy, uz, usq, g, gu, om, kf, k2, k3, kp, live,
+    collide_pairs<ST, RT>(f, pl, n, drho, rho, ux, uy, uz, usq, g, gu, om, kf, k2, k3, kp, live, put_f,
                           std::make_integer_sequence<int, 9>{});
 
     // stress of the non-equilibrium part: sigma = -(1 - 1/(2T)) sum c c (f - f^eq), with
@@ -274,16 +287,18 @@ __device__ __forceinline__ void stream_collide_node(const PL& pl, uint32_t* __re
     const RT ks = -(RT(1) - RT(0.5) * om);
     const RT d3 = drho * RT(1.0 / 3.0);
     const RT z0 = RT(0);
-    __builtin_nontemporal_store(live ? ux : z0, at32(pl.vel(0), n));
-    __builtin_nontemporal_store(live ? uy : z0, at32(pl.vel(1), n));
-    __builtin_nontemporal_store(live ? uz : z0, at32(pl.vel(2), n));
-    __builtin_nontemporal_store(live ? ks * (pxx - d3 - rho * ux * ux) : z0, at32(pl.str(0), n));
-    __builtin_nontemporal_store(live ? ks * (pyy - d3 - rho * uy * uy) : z0, at32(pl.str(1), n));
-    __builtin_nontemporal_store(live ? ks * (pzz - d3 - rho * uz * uz) : z0, at32(pl.str(2), n));
-    __builtin_nontemporal_store(live ? ks * (pxy - rho * ux * uy) : z0, at32(pl.str(3), n));
-    __builtin_nontemporal_store(live ? ks * (pxz - rho * ux * uz) : z0, at32(pl.str(4), n));
-    __builtin_nontemporal_store(live ? ks * (pyz - rho * uy * uz) : z0, at32(pl.str(5), n));
-    if (CLEAR) __builtin_nontemporal_store(w & NW_STATIC, at32(nodeword, n));
+    if (put_u) {
+        __builtin_nontemporal_store(live ? ux : z0, at32(pl.vel(0), n));
+        __builtin_nontemporal_store(live ? uy : z0, at32(pl.vel(1), n));
+        __builtin_nontemporal_store(live ? uz : z0, at32(pl.vel(2), n));
+        __builtin_nontemporal_store(live ? ks * (pxx - d3 - rho * ux * ux) : z0, at32(pl.str(0), n));
+        __builtin_nontemporal_store(live ? ks * (pyy - d3 - rho * uy * uy) : z0, at32(pl.str(1), n));
+        __builtin_nontemporal_store(live ? ks * (pzz - d3 - rho * uz * uz) : z0, at32(pl.str(2), n));
+        __builtin_nontemporal_store(live ? ks * (pxy - rho * ux * uy) : z0, at32(pl.str(3), n));
+        __builtin_nontemporal_store(live ? ks * (pxz - rho * ux * uz) : z0, at32(pl.str(4), n));
+        __builtin_nontemporal_store(live ? ks * (pyz - rho * uy * uz) : z0, at32(pl.str(5), n));
+    }
+    if (CLEAR && line_has_fluid(4u)) __builtin_nontemporal_store(w & NW_STATIC, at32(nodeword, n));
     if (live && (!(rho > RT(0)) || !(usq <= RT(0.09)))) atomicOr(err, ERR_UNSTABLE);
 }
 
