@@ -302,7 +302,7 @@ __device__ __forceinline__ void stream_collide_node(const PL& pl, uint32_t* __re
     if (live && (!(rho > RT(0)) || !(usq <= RT(0.09)))) atomicOr(err, ERR_UNSTABLE);
 }
 
-template <typename ST, typename RT>
+template <typename ST, typename RT, bool CLEAR>
 __global__ __launch_bounds__(256) void k_stream_collide(
     const Planes<ST, RT> pl, uint32_t* __restrict__ nodeword, const MapPlanes<RT> mp,
     const Gather<RT>* __restrict__ gat, KParams kp, unsigned* __restrict__ err)
@@ -310,7 +310,8 @@ __global__ __launch_bounds__(256) void k_stream_collide(
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int y = blockIdx.y * 4 + threadIdx.y;
     if (x < kp.nx && y < kp.ny)
-        stream_collide_node<ST, RT>(pl, nodeword, mp, gat, kp, err, x, y, (int)blockIdx.z);
+        stream_collide_node<ST, RT, Planes<ST, RT>, CLEAR>(pl, nodeword, mp, gat, kp, err, x, y,
+                                                           (int)blockIdx.z);
 }
 
 // ---- open z faces: non-equilibrium extrapolation (Guo, Zheng & Shi 2002) ------------------
@@ -530,7 +531,7 @@ __global__ __launch_bounds__(256) void kf_stream(const FusedArgs fa)
 template <typename ST, typename RT>
 void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword, const int* ids,
                            const void* vals, const void* gat, void* u, void* sig,
-                           const KParams& kp, unsigned* err, hipStream_t st)
+                           const KParams& kp, unsigned* err, bool clear_counts, hipStream_t st)
 {
     const dim3 grid((unsigned)((kp.nx + 63) / 64), (unsigned)((kp.ny + 3) / 4), (unsigned)kp.nz);
     Planes<ST, RT> pl;
@@ -541,9 +542,13 @@ void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword
     }
     for (int a = 0; a < 3; ++a) pl.u[a] = (RT*)u + a * ld;
     for (int a = 0; a < 6; ++a) pl.sig[a] = (RT*)sig + a * ld;
-    hipLaunchKernelGGL((k_stream_collide<ST, RT>), grid, dim3(64, 4, 1), 0, st, pl,
-                       const_cast<uint32_t*>(nodeword), map_planes<RT>(ids, vals, kp),
-                       (const Gather<RT>*)gat, kp, err);
+    uint32_t* nw = const_cast<uint32_t*>(nodeword);
+    if (clear_counts)
+        hipLaunchKernelGGL((k_stream_collide<ST, RT, true>), grid, dim3(64, 4, 1), 0, st, pl, nw,
+                           map_planes<RT>(ids, vals, kp), (const Gather<RT>*)gat, kp, err);
+    else
+        hipLaunchKernelGGL((k_stream_collide<ST, RT, false>), grid, dim3(64, 4, 1), 0, st, pl, nw,
+                           map_planes<RT>(ids, vals, kp), (const Gather<RT>*)gat, kp, err);
 }
 
 template <typename ST, typename RT>
@@ -603,7 +608,7 @@ void launch_fused_lattice(const FusedArgs& fa, int stage, hipStream_t st)
     template void launch_fused_lattice<ST, RT>(const FusedArgs&, int, hipStream_t);               \
     template void launch_stream_collide<ST, RT>(const void*, void*, const uint32_t*, const int*,  \
                                                 const void*, const void*, void*, void*,           \
-                                                const KParams&, unsigned*, hipStream_t);          \
+                                                const KParams&, unsigned*, bool, hipStream_t);    \
     template void launch_open_bc<ST, RT>(const void*, void*, const uint32_t*, const long long*,   \
                                          int, const int*, const void*, const void*, void*, void*, \
                                          const KParams&, hipStream_t);                            \

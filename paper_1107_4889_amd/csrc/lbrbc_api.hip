@@ -333,11 +333,11 @@ struct lb_ctx_s {
     Geometry geo;
     Layout lay;
     hipStream_t stream = nullptr;
-    // Side stream (default priority) for the work of a step that does not depend on the
-    // per-cell map pass: clearing the coverage counts and the Gay-Berne forces run there,
-    // forked from and joined back into `stream` by events, for large cell counts.
+    // Side stream (default priority) for the Gay-Berne forces, which do not depend on the
+    // per-cell map pass: forked from `stream` after the cell list and joined back before the
+    // kick by events, for large cell counts.
     hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_cells = nullptr, ev_clear = nullptr, ev_gb = nullptr;
+    hipEvent_t ev_cells = nullptr, ev_gb = nullptr;
     char* base = nullptr;
     void *fA = nullptr, *fB = nullptr;
     // coverage counts all zero (after init and after a fused step, whose stream-collide clears
@@ -371,7 +371,7 @@ constexpr int SIDE_STREAM_MIN_CELLS = 2048;
 void release_side(lb_ctx c)
 {
     if (c->side) (void)hipStreamSynchronize(c->side);
-    for (hipEvent_t* ev : {&c->ev_fork, &c->ev_cells, &c->ev_clear, &c->ev_gb})
+    for (hipEvent_t* ev : {&c->ev_cells, &c->ev_gb})
         if (*ev) {
             (void)hipEventDestroy(*ev);
             *ev = nullptr;
@@ -492,33 +492,31 @@ void enqueue_step(lb_ctx c)
     const KParams& kp = c->kp;
     c->cb.u = c->at<void>(c->lay.u);
     c->cb.sig = c->at<void>(c->lay.sig);
+    // Without open planes the stream-collide clears the coverage counts for the next step;
+    // with them the boundary kernel still needs the counts after it, so they are cleared
+    // before the map pass instead (and once after rbc_couple, which leaves them set).
+    const bool sc_clears = c->geo.planes.empty();
     with_types(c->cfg.storage, [&](auto* sp, auto* rp) {
         using ST = std::remove_pointer_t<decltype(sp)>;
         using RT = std::remove_pointer_t<decltype(rp)>;
         const bool forked = c->nrbc > 0 && c->side;
-        if (forked) {
-            // On `stream`: rb1, cell list, map, hydrodynamic half of rb2, stream-collide, and
-            // (after the join) the kick of rb2. On `side`: count clearing (after rb1, before
-            // the map) and Gay-Berne (after the cell list), which overlaps the map pass and
-            // the memory-bound stream-collide.
-            launch_rb_first_half(c->cb, kp, s);
-            (void)hipEventRecord(c->ev_fork, s);
-            (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
-            launch_clear_counts(c->cb.nodeword, kp.N, c->cb.ovf, c->side);
-            (void)hipEventRecord(c->ev_clear, c->side);
-            launch_cell_list(c->cb, kp, s);
-            (void)hipEventRecord(c->ev_cells, s);
-            (void)hipStreamWaitEvent(c->side, c->ev_cells, 0);
-            launch_gay_berne(c->cb, kp, c->side);
-            (void)hipEventRecord(c->ev_gb, c->side);
-            (void)hipStreamWaitEvent(s, c->ev_clear, 0);
+        if (c->nrbc > 0) {
+            // rb1 + cell list, map + interpolation (which writes F^hyd, T^hyd and the gather
+            // records), Gay-Berne, kick. Forked: Gay-Berne on `side` after the cell list,
+            // overlapping the map pass and stream-collide; the kick waits for it.
+            launch_rb1_cell_list(c->cb, kp, s);
+            if (forked) {
+                (void)hipEventRecord(c->ev_cells, s);
+                (void)hipStreamWaitEvent(c->side, c->ev_cells, 0);
+                launch_gay_berne(c->cb, kp, c->side);
+                (void)hipEventRecord(c->ev_gb, c->side);
+            }
+            if (!sc_clears || !c->counts_clean) launch_clear_counts(c->cb.nodeword, kp.N, c->cb.ovf, s);
             launch_map_couple<RT>(c->cb, kp, s);
-            launch_rb_second_half<RT>(c->cb, kp, RB2_HYDRO, s);
-        } else if (c->nrbc > 0) {
-            launch_rb_first_half(c->cb, kp, s);
-            enqueue_cells_map_couple<RT>(c);
-            launch_gay_berne(c->cb, kp, s);
-            launch_rb_second_half<RT>(c->cb, kp, RB2_ALL, s);
+            if (!forked) {
+                launch_gay_berne(c->cb, kp, s);
+                launch_rb_second_half(c->cb, kp, s);
+            }
         }
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (c->timing && (int)c->sc_pairs.size() < MAX_TIMED && c->ev_pool.size() >= 2) {
@@ -530,7 +528,7 @@ void enqueue_step(lb_ctx c)
         }
         launch_stream_collide<ST, RT>(c->fA, c->fB, c->cb.nodeword, c->cb.map_ids, c->cb.map_vals,
                                       c->cb.gat, c->at<void>(c->lay.u), c->at<void>(c->lay.sig), kp,
-                                      c->cb.err, s);
+                                      c->cb.err, sc_clears && c->nrbc > 0, s);
         if (e0) {
             (void)hipEventRecord(e1, s);
             c->sc_pairs.emplace_back(e0, e1);
@@ -545,11 +543,11 @@ void enqueue_step(lb_ctx c)
                            c->at<double>(c->lay.wss_acc), 1, s);
         if (forked) {
             (void)hipStreamWaitEvent(s, c->ev_gb, 0);
-            launch_rb_second_half<RT>(c->cb, kp, RB2_KICK, s);
+            launch_rb_second_half(c->cb, kp, s);
         }
     });
     if (c->wss_on) c->wss_count++;
-    if (c->nrbc > 0) c->counts_clean = false;
+    c->counts_clean = sc_clears;
     std::swap(c->fA, c->fB);
     c->step++;
 }
@@ -780,7 +778,7 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
     if (err & ERR_OVERLAP) return init_fail(c, LB_EOVERLAP, "Gay-Berne pair at rho <= 0 in the initial state");
     if (n_rbc >= SIDE_STREAM_MIN_CELLS) {
         e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
-        for (hipEvent_t* ev : {&c->ev_fork, &c->ev_cells, &c->ev_clear, &c->ev_gb})
+        for (hipEvent_t* ev : {&c->ev_cells, &c->ev_gb})
             if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
         if (e != hipSuccess) {
             release_side(c);
@@ -845,7 +843,6 @@ lb_status rbc_couple(lb_ctx c)
         if (c->nrbc > 0) {
             enqueue_cells_map_couple<RT>(c);
             c->counts_clean = false;
-            launch_rb_second_half<RT>(c->cb, c->kp, RB2_NOW, c->stream);
         }
         launch_spread_field<RT>(c->cb.nodeword, c->cb.map_ids, c->cb.map_vals, c->cb.gat,
                                 c->at<void>(c->lay.gdbg), c->at<void>(c->lay.tdbg), c->kp, c->stream);

@@ -11,10 +11,11 @@
 namespace lbrbc {
 
 // per-node kernels (lb_kernels.hip)
+// clear_counts: also clear the coverage counts for the next step (no open planes)
 template <typename ST, typename RT>
 void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword, const int* ids,
                            const void* vals, const void* gat, void* u, void* sig,
-                           const KParams& kp, unsigned* err, hipStream_t st);
+                           const KParams& kp, unsigned* err, bool clear_counts, hipStream_t st);
 template <typename ST, typename RT>
 void launch_open_bc(const void* fin, void* fout, const uint32_t* nodeword, const long long* planes,
                     int nplane, const int* ids, const void* vals, const void* gat, void* u,
@@ -97,14 +98,16 @@ __device__ __forceinline__ int fused_slot(const FusedArgs& fa, int& lb)
 
 void launch_rb_first_half(const CellBuffers& b, const KParams& kp, hipStream_t st);
 void launch_cell_list(const CellBuffers& b, const KParams& kp, hipStream_t st);
+// first rigid-body half fused with the binning, then the rest of the cell list
+void launch_rb1_cell_list(const CellBuffers& b, const KParams& kp, hipStream_t st);
 template <typename RT>
 void launch_map_couple(const CellBuffers& b, const KParams& kp, hipStream_t st);
 size_t map_couple_lds(int tile_max, int cand_cap, int real_bytes);   // dynamic LDS, bytes
 size_t map_couple_tile_lds(int tile_max, int real_bytes);
 void launch_gay_berne(const CellBuffers& b, const KParams& kp, hipStream_t st);
-enum { RB2_NOW = 0, RB2_ALL = 1, RB2_HYDRO = 2, RB2_KICK = 3 };
-template <typename RT>
-void launch_rb_second_half(const CellBuffers& b, const KParams& kp, int mode, hipStream_t st);
+// combined force and torque, friction and half kick (the map pass has written F^hyd, T^hyd
+// and the gather records)
+void launch_rb_second_half(const CellBuffers& b, const KParams& kp, hipStream_t st);
 void launch_init_combined(const CellBuffers& b, const KParams& kp, hipStream_t st);
 void launch_fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t st);
 

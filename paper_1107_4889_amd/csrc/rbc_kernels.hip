@@ -111,6 +111,18 @@ __global__ __launch_bounds__(256) void k_cells_bin(const RbcState* __restrict__ 
     if (i < kp.nrbc) bin_cell(st, cellid, cnt, kp, i);
 }
 
+// first half of the rigid-body step and binning of the moved centre, per cell; also clears
+// the overflow count of this step's map pass
+__global__ __launch_bounds__(256) void k_rb1_bin(RbcState* __restrict__ st, int* cellid, int* cnt,
+                                                 int* ovf, KParams kp)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) ovf[0] = 0;
+    if (i >= kp.nrbc) return;
+    rb1_cell(st, kp, i);
+    bin_cell(st, cellid, cnt, kp, i);
+}
+
 // exclusive scan of n ints in one block of 1024 threads, 4096 values per round (each thread
 // four consecutive values, so the loads are coalesced); also clears `cnt`
 __device__ __forceinline__ void scan_clear_block(int* cnt, int* off, int n)
@@ -266,7 +278,8 @@ constexpr int TILE_ROWS_MAX = 20 * 20;   // tile_max <= 20
 //   T^S = alpha sum over inside nodes of dhat (sigma . n^) x (x - R), n^ = grad/|grad|.
 template <typename RT>
 __device__ void map_couple_tile(int i, unsigned char* smem, const RbcState* __restrict__ st,
-                                RbcCouple* __restrict__ cp, uint32_t* __restrict__ nodeword,
+                                RbcCouple* __restrict__ cp, Gather<RT>* __restrict__ gat,
+                                uint32_t* __restrict__ nodeword,
                                 int* __restrict__ ids, RT* __restrict__ vals,
                                 const RT* __restrict__ u, const RT* __restrict__ sig,
                                 const KParams& kp, unsigned* __restrict__ err)
@@ -472,6 +485,7 @@ __device__ void map_couple_tile(int i, unsigned char* smem, const RbcState* __re
             c.wt[a] = (double)tot[3 + a];
             c.TS[a] = (double)tot[6 + a];
         }
+        hydro_cell<RT>(s, c, kp, gat + i);
     }
 }
 
@@ -480,6 +494,7 @@ __device__ void map_couple_tile(int i, unsigned char* smem, const RbcState* __re
 template <typename RT>
 __global__ __launch_bounds__(MC_THREADS) void k_map_couple_tile(const RbcState* __restrict__ st,
                                                                 RbcCouple* __restrict__ cp,
+                                                                Gather<RT>* __restrict__ gat,
                                                                 uint32_t* __restrict__ nodeword,
                                                                 int* __restrict__ ids,
                                                                 RT* __restrict__ vals,
@@ -492,7 +507,7 @@ __global__ __launch_bounds__(MC_THREADS) void k_map_couple_tile(const RbcState* 
     extern __shared__ unsigned char smem[];
     const int n = ovf[0];
     for (int b = blockIdx.x; b < n; b += gridDim.x)
-        map_couple_tile<RT>(ovf[1 + b], smem, st, cp, nodeword, ids, vals, u, sig, kp, err);
+        map_couple_tile<RT>(ovf[1 + b], smem, st, cp, gat, nodeword, ids, vals, u, sig, kp, err);
 }
 
 // ---- S3 + S4, one wavefront per cell on the row-compressed support tile -----------------------
@@ -511,6 +526,7 @@ template <typename RT>
 __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
                                                 const RbcState* __restrict__ st,
                                                 RbcCouple* __restrict__ cp,
+                                                Gather<RT>* __restrict__ gat,
                                                 uint32_t* __restrict__ nodeword,
                                                 int* __restrict__ ids, RT* __restrict__ vals,
                                                 const int* __restrict__ order,
@@ -726,12 +742,14 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
             c.wt[a] = (double)acc[3 + a];
             c.TS[a] = (double)acc[6 + a];
         }
+        hydro_cell<RT>(s, c, kp, gat + i);
     }
 }
 
 template <typename RT>
 __global__ __launch_bounds__(64) void k_map_couple(const RbcState* __restrict__ st,
                                                    RbcCouple* __restrict__ cp,
+                                                   Gather<RT>* __restrict__ gat,
                                                    uint32_t* __restrict__ nodeword,
                                                    int* __restrict__ ids, RT* __restrict__ vals,
                                                    const int* __restrict__ order,
@@ -743,7 +761,7 @@ __global__ __launch_bounds__(64) void k_map_couple(const RbcState* __restrict__ 
     extern __shared__ unsigned char smem[];
     const int k = xcd_chunk_index(1);
     if (k < kp.nrbc)
-        map_couple_cell<RT>(k, smem, st, cp, nodeword, ids, vals, order, u, sig, kp, err, ovf);
+        map_couple_cell<RT>(k, smem, st, cp, gat, nodeword, ids, vals, order, u, sig, kp, err, ovf);
 }
 
 // ---- S5: Gay-Berne forces and torques (Sec. II E, Eqs. 24-28; App. B) -----------------------
@@ -961,65 +979,61 @@ __global__ __launch_bounds__(256) void k_gay_berne(const RbcState* __restrict__ 
 
 // ---- S6: combined force/torque, hydrodynamic force/torque, second half --------------------
 // F^comb = F^mech + gT M u~; tau^comb = tau^mech + Q^T T^S + gR I (s Q^T w~);
-// F^hyd = -M gT (V^1/2 - u~); T^hyd = Q [-gR I (Omega^1/2 - s Q^T w~)] + T^S (lab).
-// mode RB2_NOW: F^hyd, T^hyd and the gather record from the current V, Omega (coupling
-// without a time step); RB2_HYDRO: the same from the half-step V, Omega; RB2_KICK: combined
-// force and torque, half-step friction and half kick (needs the Gay-Berne forces);
-// RB2_ALL: RB2_HYDRO and RB2_KICK.
+// F^hyd = -M gT (V - u~); T^hyd = Q [-gR I (Omega - s Q^T w~)] + T^S (lab), with the velocities
+// after the first half (which equal the half-step values within a step).
+// hydro_cell: F^hyd, T^hyd and the gather record of cell i from its interpolation sums in c
+// (S, u~, w~, T^S, just written by the same thread); run at the end of the map pass.
 template <typename RT>
-__device__ __forceinline__ void rb2_cell(RbcState* __restrict__ st, RbcCouple* __restrict__ cp,
-                                         Gather<RT>* __restrict__ gat, const KParams& kp, int mode,
-                                         int i)
+__device__ __forceinline__ void hydro_cell(const RbcState& s, RbcCouple& c, const KParams& kp,
+                                           Gather<RT>* __restrict__ gi)
 {
-    RbcState s = st[i];
-    RbcCouple c = cp[i];
-    double wb[3], tsb[3], tb[3], tl[3];
+    double wb[3], tb[3], tl[3], Fh[3], Th[3];
     matT_vec(s.Q, c.wt, wb);
-    matT_vec(s.Q, c.TS, tsb);
-    const bool half = mode != RB2_NOW;
-    const double* Vh = half ? s.Vh : s.V;
-    const double* Oh = half ? s.Omh : s.Om;
     for (int a = 0; a < 3; ++a) {
-        c.Fh[a] = -kp.mass * kp.gammaT * (Vh[a] - c.ut[a]);
-        tb[a] = -kp.gammaR * kp.inertia[a] * (Oh[a] - kp.vort_scale * wb[a]);
+        Fh[a] = -kp.mass * kp.gammaT * (s.V[a] - c.ut[a]);
+        tb[a] = -kp.gammaR * kp.inertia[a] * (s.Om[a] - kp.vort_scale * wb[a]);
     }
     mat_vec(s.Q, tb, tl);
-    for (int a = 0; a < 3; ++a) c.Th[a] = tl[a] + c.TS[a];
-    if (mode == RB2_KICK || mode == RB2_ALL) {
-        const double eT = exp(-kp.gammaT * 0.5), eR = exp(-kp.gammaR * 0.5);
-        for (int a = 0; a < 3; ++a) {
-            s.Fc[a] = c.Fm[a] + kp.gammaT * kp.mass * c.ut[a];
-            s.Tc[a] = c.Tm[a] + tsb[a] + kp.gammaR * kp.inertia[a] * kp.vort_scale * wb[a];
-            s.V[a] *= eT;
-            s.Om[a] *= eR;
-            s.V[a] += 0.5 / kp.mass * s.Fc[a];
-            s.Om[a] += 0.5 * s.Tc[a] / kp.inertia[a];
-        }
-        st[i] = s;
-    }
-    if (mode == RB2_KICK) return;
-    for (int a = 0; a < 3; ++a) {
-        cp[i].Fh[a] = c.Fh[a];
-        cp[i].Th[a] = c.Th[a];
-    }
+    for (int a = 0; a < 3; ++a) Th[a] = tl[a] + c.TS[a];
     Gather<RT> G;
     for (int a = 0; a < 3; ++a) {
-        G.F[a] = (RT)c.Fh[a];
-        G.T[a] = (RT)c.Th[a];
+        c.Fh[a] = Fh[a];
+        c.Th[a] = Th[a];
+        G.F[a] = (RT)Fh[a];
+        G.T[a] = (RT)Th[a];
     }
     G.invS = c.S > 0.0 ? (RT)(1.0 / c.S) : RT(0);
     G.pad = RT(0);
-    gat[i] = G;
+    *gi = G;
 }
 
-template <typename RT>
+// kick_cell: combined force and torque (needs the Gay-Berne forces), half-step friction and
+// half kick
+__device__ __forceinline__ void kick_cell(RbcState* __restrict__ st, const RbcCouple* __restrict__ cp,
+                                          const KParams& kp, int i)
+{
+    RbcState s = st[i];
+    const RbcCouple& c = cp[i];
+    double wb[3], tsb[3];
+    matT_vec(s.Q, c.wt, wb);
+    matT_vec(s.Q, c.TS, tsb);
+    const double eT = exp(-kp.gammaT * 0.5), eR = exp(-kp.gammaR * 0.5);
+    for (int a = 0; a < 3; ++a) {
+        s.Fc[a] = c.Fm[a] + kp.gammaT * kp.mass * c.ut[a];
+        s.Tc[a] = c.Tm[a] + tsb[a] + kp.gammaR * kp.inertia[a] * kp.vort_scale * wb[a];
+        s.V[a] *= eT;
+        s.Om[a] *= eR;
+        s.V[a] += 0.5 / kp.mass * s.Fc[a];
+        s.Om[a] += 0.5 * s.Tc[a] / kp.inertia[a];
+    }
+    st[i] = s;
+}
+
 __global__ __launch_bounds__(128) void k_rb_second_half(RbcState* __restrict__ st,
-                                                        RbcCouple* __restrict__ cp,
-                                                        Gather<RT>* __restrict__ gat, KParams kp,
-                                                        int mode)
+                                                        const RbcCouple* __restrict__ cp, KParams kp)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < kp.nrbc) rb2_cell<RT>(st, cp, gat, kp, mode, i);
+    if (i < kp.nrbc) kick_cell(st, cp, kp, i);
 }
 
 __global__ void k_init_combined(RbcState* __restrict__ st, const RbcCouple* __restrict__ cp, int nrbc)
@@ -1084,7 +1098,8 @@ __global__ __launch_bounds__(64) void kf_map(const FusedArgs fa)
     const SlotDesc& d = *fa.slot[fused_slot(fa, lb)];
     const KParams kp = d.kp;
     if (lb < kp.nrbc)
-        map_couple_cell<RT>(lb, smem, d.b.st, d.b.cp, d.b.nodeword, d.b.map_ids, (RT*)d.b.map_vals,
+        map_couple_cell<RT>(lb, smem, d.b.st, d.b.cp, (Gather<RT>*)d.b.gat, d.b.nodeword, d.b.map_ids,
+                            (RT*)d.b.map_vals,
                             d.b.cell_ids, (const RT*)d.b.u, (const RT*)d.b.sig, kp, d.b.err, d.b.ovf);
 }
 
@@ -1097,7 +1112,8 @@ __global__ __launch_bounds__(MC_THREADS) void kf_map_tile(const FusedArgs fa)
     const KParams kp = d.kp;
     const int n = d.b.ovf[0];
     for (int b = lb; b < n; b += FUSED_TILE_BLOCKS)
-        map_couple_tile<RT>(d.b.ovf[1 + b], smem, d.b.st, d.b.cp, d.b.nodeword, d.b.map_ids,
+        map_couple_tile<RT>(d.b.ovf[1 + b], smem, d.b.st, d.b.cp, (Gather<RT>*)d.b.gat, d.b.nodeword,
+                            d.b.map_ids,
                             (RT*)d.b.map_vals, (const RT*)d.b.u, (const RT*)d.b.sig, kp, d.b.err);
 }
 
@@ -1112,14 +1128,13 @@ __global__ __launch_bounds__(256) void kf_gb(const FusedArgs fa)
                        d.b.wcell_off, d.b.wcell_ids, kp, d.b.err);
 }
 
-template <typename RT>
-__global__ __launch_bounds__(128) void kf_rb2(const FusedArgs fa)
+__global__ __launch_bounds__(128) void kf_kick(const FusedArgs fa)
 {
     int lb;
     const SlotDesc& d = *fa.slot[fused_slot(fa, lb)];
     const KParams kp = d.kp;
     const int i = lb * 128 + (int)threadIdx.x;
-    if (i < kp.nrbc) rb2_cell<RT>(d.b.st, d.b.cp, (Gather<RT>*)d.b.gat, kp, RB2_ALL, i);
+    if (i < kp.nrbc) kick_cell(d.b.st, d.b.cp, kp, i);
 }
 
 // ---- launchers ---------------------------------------------------------------------------------
@@ -1133,6 +1148,18 @@ void launch_fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t st)
 void launch_rb_first_half(const CellBuffers& b, const KParams& kp, hipStream_t st)
 {
     hipLaunchKernelGGL(k_rb_first_half, dim3(nblk(kp.nrbc, 128)), dim3(128), 0, st, b.st, kp);
+}
+
+void launch_rb1_cell_list(const CellBuffers& b, const KParams& kp, hipStream_t st)
+{
+    const int nc = kp.ncell[0] * kp.ncell[1] * kp.ncell[2];
+    hipLaunchKernelGGL(k_rb1_bin, dim3(nblk(kp.nrbc, 256)), dim3(256), 0, st, b.st, b.cellid,
+                       b.cell_cnt, b.ovf, kp);
+    hipLaunchKernelGGL(k_scan_clear, dim3(1), dim3(1024), 0, st, b.cell_cnt, b.cell_off, nc);
+    hipLaunchKernelGGL(k_cells_scatter, dim3(nblk(kp.nrbc, 256)), dim3(256), 0, st, b.cellid,
+                       b.cell_off, b.cell_cnt, b.cell_ids, kp.nrbc);
+    hipLaunchKernelGGL(k_cells_sort, dim3(nblk(nc, 256)), dim3(256), 0, st, b.cell_off,
+                       b.cell_ids, b.cell_cnt, nc);
 }
 
 void launch_cell_list(const CellBuffers& b, const KParams& kp, hipStream_t st)
@@ -1173,12 +1200,12 @@ void launch_map_couple(const CellBuffers& b, const KParams& kp, hipStream_t st)
 {
     hipLaunchKernelGGL((k_map_couple<RT>), dim3(grid8(kp.nrbc, 1)), dim3(64),
                        map_couple_lds(kp.tile_max, kp.cand_cap, (int)sizeof(RT)), st, b.st, b.cp,
-                       b.nodeword, b.map_ids, (RT*)b.map_vals, b.cell_ids, (const RT*)b.u,
+                       (Gather<RT>*)b.gat, b.nodeword, b.map_ids, (RT*)b.map_vals, b.cell_ids, (const RT*)b.u,
                        (const RT*)b.sig, kp, b.err, b.ovf);
     // the overflow list is short (normally empty): a small grid loops over it
     hipLaunchKernelGGL((k_map_couple_tile<RT>), dim3(64), dim3(MC_THREADS),
                        map_couple_tile_lds(kp.tile_max, (int)sizeof(RT)), st, b.st, b.cp,
-                       b.nodeword, b.map_ids, (RT*)b.map_vals, b.ovf, (const RT*)b.u,
+                       (Gather<RT>*)b.gat, b.nodeword, b.map_ids, (RT*)b.map_vals, b.ovf, (const RT*)b.u,
                        (const RT*)b.sig, kp, b.err);
 }
 
@@ -1189,11 +1216,9 @@ void launch_gay_berne(const CellBuffers& b, const KParams& kp, hipStream_t st)
                        kp, b.err);
 }
 
-template <typename RT>
-void launch_rb_second_half(const CellBuffers& b, const KParams& kp, int mode, hipStream_t st)
+void launch_rb_second_half(const CellBuffers& b, const KParams& kp, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_rb_second_half<RT>), dim3(nblk(kp.nrbc, 128)), dim3(128), 0, st, b.st,
-                       b.cp, (Gather<RT>*)b.gat, kp, mode);
+    hipLaunchKernelGGL(k_rb_second_half, dim3(nblk(kp.nrbc, 128)), dim3(128), 0, st, b.st, b.cp, kp);
 }
 
 void launch_init_combined(const CellBuffers& b, const KParams& kp, hipStream_t st)
@@ -1234,7 +1259,7 @@ void launch_fused_cells(const FusedArgs& fa, int stage, size_t lds, hipStream_t 
     case FS_MAP: hipLaunchKernelGGL((kf_map<RT>), dim3(g), dim3(64), lds, st, fa); break;
     case FS_MAP_TILE: hipLaunchKernelGGL((kf_map_tile<RT>), dim3(g), dim3(MC_THREADS), lds, st, fa); break;
     case FS_GB: hipLaunchKernelGGL(kf_gb, dim3(g), dim3(256), 0, st, fa); break;
-    case FS_RB2: hipLaunchKernelGGL((kf_rb2<RT>), dim3(g), dim3(128), 0, st, fa); break;
+    case FS_RB2: hipLaunchKernelGGL(kf_kick, dim3(g), dim3(128), 0, st, fa); break;
     default: break;
     }
 }
@@ -1243,7 +1268,6 @@ template void launch_fused_cells<double>(const FusedArgs&, int, size_t, hipStrea
 template void launch_fused_cells<float>(const FusedArgs&, int, size_t, hipStream_t);
 template void launch_map_couple<double>(const CellBuffers&, const KParams&, hipStream_t);
 template void launch_map_couple<float>(const CellBuffers&, const KParams&, hipStream_t);
-template void launch_rb_second_half<double>(const CellBuffers&, const KParams&, int, hipStream_t);
-template void launch_rb_second_half<float>(const CellBuffers&, const KParams&, int, hipStream_t);
+
 
 }  // namespace lbrbc
