@@ -517,7 +517,7 @@ __global__ __launch_bounds__(MC_THREADS) void k_map_couple_tile(const RbcState* 
 //   clo[r]   first candidate x of row r,  off[r] its first candidate index (off[rows] = total),
 //   val[c]   the kernel value raw >= 0 at an inside node, -1 at a fluid node outside the
 //            support, -2 at a solid node or outside a non-periodic face,
-//   rowof[c] the row of candidate c.
+//   rowof[c] the row of candidate c as ty | tz << 8 (row r = ty + tz sy).
 // Neighbours outside a row's candidate range are outside the support (raw = 0, not inside):
 // the covered range of every row contains the support range of the row and of its four
 // neighbouring rows. More candidates than kp.cand_cap: the cell goes to the overflow list
@@ -555,6 +555,8 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
     const int rows = sy * sz;
     // support x-range of each row, widened by one node (see map_couple_tile)
     const double X0 = s.R[0] - (double)T.lo[0];
+    double iq[3];
+    for (int a = 0; a < 3; ++a) iq[a] = fabs(s.Q[a]) > 1e-12 ? 1.0 / s.Q[a] : 0.0;
     for (int r = lane; r < rows; r += 64) {
         const int ty = r % sy, tz = r / sy;
         const double dy = (double)(T.lo[1] + ty) - s.R[1], dz = (double)(T.lo[2] + tz) - s.R[2];
@@ -562,7 +564,7 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
         for (int a = 0; a < 3; ++a) {
             const double qa = s.Q[a], b = s.Q[3 + a] * dy + s.Q[6 + a] * dz;
             if (fabs(qa) > 1e-12) {
-                double u0 = (-kp.xi[a] - b) / qa, u1 = (kp.xi[a] - b) / qa;
+                double u0 = (-kp.xi[a] - b) * iq[a], u1 = (kp.xi[a] - b) * iq[a];
                 if (u0 > u1) { const double t_ = u0; u0 = u1; u1 = t_; }
                 xa = fmax(xa, u0);
                 xb = fmin(xb, u1);
@@ -617,15 +619,16 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
     }
     __syncthreads();
     for (int r = r0; r < r1; ++r)
-        for (int c = off[r], e = off[r + 1]; c < e; ++c) rowof[c] = (unsigned short)r;
+        for (int c = off[r], e = off[r + 1]; c < e; ++c)
+            rowof[c] = (unsigned short)((r % sy) | (r / sy) << 8);
     __syncthreads();
 
     // pass 1: exact support test and raw kernel value at every candidate; S = sum raw
     const RT s0 = RT(2.0 / kp.xi[0]), s1 = RT(2.0 / kp.xi[1]), s2 = RT(2.0 / kp.xi[2]);
     RT part = RT(0);
     for (int c = lane; c < total; c += 64) {
-        const int r = rowof[c];
-        const int ty = r % sy, tz = r / sy, tx = clo[r] + (c - off[r]);
+        const int yz = rowof[c];
+        const int ty = yz & 255, tz = yz >> 8, r = ty + tz * sy, tx = clo[r] + (c - off[r]);
         int X = T.lo[0] + tx, Y = T.lo[1] + ty, Z = T.lo[2] + tz;
         RT v = RT(-2);
         if (wrap_coord(X, kp.nx, kp.per[0]) && wrap_coord(Y, kp.ny, kp.per[1]) &&
@@ -665,9 +668,10 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
         RT vxm = RT(-2), vxp = RT(-2), vym = RT(-2), vyp = RT(-2), vzm = RT(-2), vzp = RT(-2);
         bool cov = false;
         if (v > RT(-1.5)) {
-            r = rowof[c];
-            ty = r % sy;
-            tz = r / sy;
+            const int yz = rowof[c];
+            ty = yz & 255;
+            tz = yz >> 8;
+            r = ty + tz * sy;
             tx = clo[r] + (c - off[r]);
             vxm = at(r, tx - 1);
             vxp = at(r, tx + 1);
@@ -693,7 +697,7 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
         const RT gx = RT(0.5) * (max(vxp, z0) - max(vxm, z0));
         const RT gy = RT(0.5) * (max(vyp, z0) - max(vym, z0));
         const RT gz = RT(0.5) * (max(vzp, z0) - max(vzm, z0));
-        const RT ux = u[n], uy = u[ld + n], uz = u[2 * ld + n];
+        const RT ux = *at32(u, n), uy = *at32(u + ld, n), uz = *at32(u + 2 * ld, n);
         const uint32_t old = atomicAdd(nodeword + n, NW_CNT_ONE);
         const int slot = (int)(old >> 24);
         const int e = (i << kp.ent_shift) | j;
@@ -719,8 +723,8 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
         const RT gl = sqrt(hx * hx + hy * hy + hz * hz);
         const RT il = gl > RT(0) ? RT(1) / gl : RT(0);
         const RT nx_ = hx * il, ny_ = hy * il, nz_ = hz * il;
-        const RT sxx = sig[n], syy = sig[ld + n], szz = sig[2 * ld + n];
-        const RT sxy_ = sig[3 * ld + n], sxz = sig[4 * ld + n], syz = sig[5 * ld + n];
+        const RT sxx = *at32(sig, n), syy = *at32(sig + ld, n), szz = *at32(sig + 2 * ld, n);
+        const RT sxy_ = *at32(sig + 3 * ld, n), sxz = *at32(sig + 4 * ld, n), syz = *at32(sig + 5 * ld, n);
         const RT t0 = sxx * nx_ + sxy_ * ny_ + sxz * nz_;
         const RT t1 = sxy_ * nx_ + syy * ny_ + syz * nz_;
         const RT t2 = sxz * nx_ + syz * ny_ + szz * nz_;
