@@ -1,7 +1,9 @@
 // lbrbc_api.hip -- C ABI of the MI355X library: arena layout, host-side geometry tables,
 // step orchestration on the caller's stream, getters/setters, checkpoints, timing.
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <mutex>
 #include <cstring>
 #include <string>
 #include <type_traits>
@@ -46,7 +48,23 @@ struct Geometry {
 // orientations and sub-node offsets from a fixed generator, with 20% and 64 nodes of margin;
 // at least tile_max^2 (the pass also keeps two row tables there) and at most tile_max^3 (the
 // tile). A cell that still has more takes the full-tile pass, so the bound needs no proof.
+int candidate_capacity_sampled(const double* xi, int tm);
+
+// the sampled bound depends on xi and tile_max only: kept per process
 int candidate_capacity(const double* xi, int tm)
+{
+    static std::mutex mu;
+    static std::vector<std::pair<std::array<double, 4>, int>> memo;
+    const std::array<double, 4> key = {xi[0], xi[1], xi[2], (double)tm};
+    std::lock_guard<std::mutex> lock(mu);
+    for (const auto& kv : memo)
+        if (kv.first == key) return kv.second;
+    const int cap = candidate_capacity_sampled(xi, tm);
+    memo.emplace_back(key, cap);
+    return cap;
+}
+
+int candidate_capacity_sampled(const double* xi, int tm)
 {
     uint64_t x = 0x9E3779B97F4A7C15ull;
     auto next = [&]() {   // xorshift64*, uniform in (0, 1)

@@ -17,6 +17,7 @@ from __future__ import annotations
 import hashlib
 import heapq
 import time
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -88,7 +89,9 @@ class Server:
         self.chunk = int(chunk_steps)
         self.use_graphs = use_graphs
         self.device = device
-        self.max_inflight = max_inflight_chunks
+        # the fused mode keeps more chunks queued, so set-up and read-back on the host never
+        # leave the device idle
+        self.max_inflight = max(max_inflight_chunks, 4) if fused else max_inflight_chunks
         self.digests = digests
         self.max_active = int(max_active)
         self.progress = progress       # called with each Result as it retires
@@ -98,6 +101,8 @@ class Server:
         self.results: list = []
         self.t0 = None
         self._fp: dict = {}
+        self.pending: list = []      # (request, footprint, future of its set-up)
+        self.pool = ThreadPoolExecutor(max_workers=1)
 
     # -- admission ------------------------------------------------------------------------
     def footprint(self, req: Request) -> int:
@@ -115,7 +120,18 @@ class Server:
     def _now(self) -> float:
         return time.perf_counter() - self.t0
 
+    def _setup(self, req: Request):
+        """Context of a request on its own stream (lb_init waits for that stream only)."""
+        stream = torch.cuda.Stream(device=self.device)
+        sim = lbrbc.Simulation(req.cfg, req.solid, R=req.R if len(req.R) else None,
+                               Q=req.Q if len(req.R) else None, device=self.device,
+                               stream=stream)
+        return sim, stream
+
     def _admit(self):
+        """Admit arrived requests in order while the budget and the slot count allow. The
+        memory is reserved at once; the set-up (host geometry build and the context's first
+        kernels) runs on a worker thread, so the loop keeps the device fed meanwhile."""
         while self.queue:
             arrival, rid, req = self.queue[0]
             if arrival > self._now():
@@ -123,20 +139,21 @@ class Server:
             fp = self.footprint(req)
             if fp > self.budget:
                 raise ValueError(f"request {rid} needs {fp} B, more than the whole budget")
-            if self.used + fp > self.budget or len(self.active) >= self.max_active:
+            if (self.used + fp > self.budget or
+                    len(self.active) + len(self.pending) >= self.max_active):
                 break                                   # first come, first served
             heapq.heappop(self.queue)
-            # set-up runs on the request's own stream (lb_init waits for it); in the fused
-            # mode the context then moves to the shared stream, so set-up does not drain it
-            stream = torch.cuda.Stream(device=self.device)
-            sim = lbrbc.Simulation(req.cfg, req.solid, R=req.R if len(req.R) else None,
-                                   Q=req.Q if len(req.R) else None, device=self.device,
-                                   stream=stream)
-            if self.fused:
-                sim.lb_set_stream(self.shared_stream)
             self.used += fp
-            self.active[rid] = _Active(req, sim, stream, self._now())
-            self.active[rid].footprint = fp
+            self.pending.append((req, fp, self.pool.submit(self._setup, req)))
+        # contexts whose set-up has finished join the resident set (in admission order)
+        while self.pending and self.pending[0][2].done():
+            req, fp, fut = self.pending.pop(0)
+            sim, stream = fut.result()
+            if self.fused:
+                # steps go to the shared stream; set-up and read-back stay on `stream`
+                sim.lb_set_stream(self.shared_stream)
+            self.active[req.rid] = _Active(req, sim, stream, self._now())
+            self.active[req.rid].footprint = fp
 
     # -- stepping -------------------------------------------------------------------------
     def _graph_for(self, a: _Active):
@@ -220,16 +237,19 @@ class Server:
         for r in requests:
             self.submit(r if realtime else Request(**{**r.__dict__, "arrival": 0.0}))
         self.t0 = time.perf_counter()
-        while self.queue or self.active:
-            self._admit()
-            if self.active:
-                self._enqueue()
-                self._retire()
-            elif self.queue:
-                wait = self.queue[0][0] - self._now()
-                if wait > 0:
-                    time.sleep(min(wait, 0.01))
-            time.sleep(0)
+        try:
+            while self.queue or self.active or self.pending:
+                if self.active:
+                    self._enqueue()
+                    self._retire()
+                self._admit()
+                if not self.active and not self.pending and self.queue:
+                    wait = self.queue[0][0] - self._now()
+                    if wait > 0:
+                        time.sleep(min(wait, 0.01))
+                time.sleep(0)
+        finally:
+            self.pool.shutdown(wait=True)
         makespan = self._now()
         return sorted(self.results, key=lambda r: r.rid), makespan
 
