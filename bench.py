@@ -10,8 +10,13 @@ fused spreading + stream-collide.
 
 Prints one JSON line: MLUPS of the whole step (fluid-node updates per second), the
 stream-collide kernel's roofline against HBM (algorithmic bytes per launch over its mean
-HIP-event duration on the library's stream), and the FP64 CPU oracle timed on a bounded
-sample of the same workload.
+HIP-event duration on the library's stream), the request-latency part of the metric (p50/p99
+latency and aggregate MLUPS of a seeded stream of 256 vessel requests served with fused
+launches; --no-serving skips it), and the FP64 CPU oracle timed on a bounded sample of the
+same workload.
+
+Other modes: --serve (a serving line of its own), --precision (reduced-precision storage
+against FP64 on the same GPU), --copy-calibration (HBM counter calibration).
 """
 from __future__ import annotations
 
@@ -92,9 +97,10 @@ def cpu_baseline(cfg, solid, pl, n_fluid: int):
                       f"{len(pl.R)} cells) after set-up; {dt:.1f} s"}
 
 
-def serve(args):
+def run_serving(args):
     """Continuous batching of a seeded request stream (Poisson arrivals in wall-clock time):
-    p50/p99 request latency beside the aggregate MLUPS over the makespan."""
+    p50/p99 request latency beside the aggregate MLUPS over the makespan. Returns
+    (aggregate MLUPS, serving record, workload description, total steps)."""
     import numpy as np
     import torch
 
@@ -133,12 +139,40 @@ def serve(args):
     results, makespan = srv.run([req(d) for d in tr])
     sm = summary(results, makespan)
     lu = sum(r.n_fluid * r.steps for r in results)
+    desc = (f"serving: {len(tr)} requests, Poisson arrivals at {args.rate:g}/s, "
+            "straight tubes and 20-degree chevrons (1:1), R ~ U(8, 32), length "
+            "~ U(4, 16) R, target hematocrit ~ U(0.2, 0.5) (random sequential "
+            "addition: achieved values reported), steps ~ U{500..5000}, "
+            f"{args.storage} storage")
+    record = {
+        "aggregate_mlups": round(sm["aggregate_mlups"], 2),
+        "p50_latency_s": round(sm["p50_latency_s"], 4),
+        "p99_latency_s": round(sm["p99_latency_s"], 4),
+        "makespan_s": round(makespan, 3),
+        "requests": sm["requests"],
+        "failed": sm["failed"],
+        "lattice_updates": int(lu),
+        "mean_hematocrit": round(float(np.mean([d["hematocrit"] for d in tr])), 4),
+        "chunk_steps": args.chunk,
+        "hip_graphs": bool(args.graphs),
+        "fused_launches": bool(args.fused),
+        "budget_gib": args.budget_gib,
+        "max_active": args.max_active,
+        "mean_queue_wait_s": round(float(np.mean([r.admitted - r.arrival for r in results])), 4),
+        "workload": desc,
+    }
+    return sm["aggregate_mlups"], record, desc, int(sum(r.steps for r in results))
+
+
+def serve(args):
+    """Serving mode: the JSON line's value is the aggregate MLUPS of the request stream."""
+    agg, record, desc, steps = run_serving(args)
     line = {
         "metric": "MLUPS & achieved HBM GB/s (LBM+RBC step); p50/p99 request latency",
-        "value": round(sm["aggregate_mlups"], 2),
+        "value": round(agg, 2),
         "unit": "MLUPS",
         "n_gpus": 1,
-        "steps": int(sum(r.steps for r in results)),
+        "steps": steps,
         "warmup": 1,
         "ms_per_step": None,
         "higher_is_better": True,
@@ -147,30 +181,12 @@ def serve(args):
         "dtype": "f64" if args.storage == "f64" else "f32",
         "data": "synthetic",
         "config": {
-            "workload": (f"serving: {len(tr)} requests, Poisson arrivals at {args.rate:g}/s, "
-                         "straight tubes and 20-degree chevrons (1:1), R ~ U(8, 32), length "
-                         "~ U(4, 16) R, target hematocrit ~ U(0.2, 0.5) (random sequential "
-                         "addition: achieved values reported), steps ~ U{500..5000}, "
-                         f"{args.storage} storage"),
+            "workload": desc,
             "storage": args.storage,
             "parallelism": ("single GPU, one launch per stage over all resident requests" if args.fused
                             else "single GPU, one HIP stream per resident request"),
         },
-        "serving": {
-            "p50_latency_s": round(sm["p50_latency_s"], 4),
-            "p99_latency_s": round(sm["p99_latency_s"], 4),
-            "makespan_s": round(makespan, 3),
-            "requests": sm["requests"],
-            "failed": sm["failed"],
-            "lattice_updates": int(lu),
-            "mean_hematocrit": round(float(np.mean([d["hematocrit"] for d in tr])), 4),
-            "chunk_steps": args.chunk,
-            "hip_graphs": bool(args.graphs),
-            "fused_launches": bool(args.fused),
-            "budget_gib": args.budget_gib,
-            "max_active": args.max_active,
-            "mean_queue_wait_s": round(float(np.mean([r.admitted - r.arrival for r in results])), 4),
-        },
+        "serving": record,
     }
     print(json.dumps(line), flush=True)
 
@@ -277,6 +293,8 @@ def main():
     ap.add_argument("--graphs", action="store_true", help="replay captured HIP graphs per chunk")
     ap.add_argument("--fused", action="store_true",
                     help="serving mode: one stream, each stage one launch over all resident requests")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="default run: skip the request-stream leg (p50/p99 latency)")
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--max-active", type=int, default=64)
     ap.add_argument("--workers", type=int, default=8)
@@ -374,6 +392,15 @@ def main():
         "observables": {"flow_rate": obs.flow_rate, "eta_app": obs.eta_app,
                         "wss_mean": obs.wss_mean, "mass": obs.mass},
     }
+    del sim
+    if not args.no_serving and args.workload == "tube128":
+        # the metric's request-latency part: the seeded request stream, fused launches
+        print("[bench] serving the seeded request stream (fused launches)", file=sys.stderr,
+              flush=True)
+        sargs = argparse.Namespace(**{**vars(args), "fused": True, "graphs": False,
+                                      "storage": "f32"})
+        _, record, _, _ = run_serving(sargs)
+        line["serving"] = record
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on one step of the same workload", file=sys.stderr,
               flush=True)
