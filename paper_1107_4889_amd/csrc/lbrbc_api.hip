@@ -827,6 +827,7 @@ lb_status lb_step(lb_ctx c, int nsteps)
 lb_status lb_batch_step(lb_ctx* ctxs, const int* nsteps, int n)
 {
     if (!ctxs || !nsteps || n < 0) return LB_EINVAL;
+    if (n == 0) return LB_OK;
     int most = 0;
     bool fuse = n > 1;
     for (int i = 0; i < n; ++i) {

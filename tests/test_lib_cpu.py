@@ -57,3 +57,21 @@ def test_null_arguments_are_rejected():
     assert L.lb_sync(None) == lbrbc.LB_EINVAL
     assert L.rbc_couple(None) == lbrbc.LB_EINVAL
     assert L.lb_query_footprint(None, None, 0, None) == lbrbc.LB_EINVAL
+    assert L.lb_set_stream(None, None) == lbrbc.LB_EINVAL
+    arr = (lbrbc._P * 1)(None)
+    ns = (ctypes.c_int * 1)(3)
+    assert L.lb_batch_step(arr, ns, 1) == lbrbc.LB_EINVAL          # a NULL context
+    assert L.lb_batch_step(None, ns, 1) == lbrbc.LB_EINVAL
+    assert L.lb_batch_step(arr, ns, 0) == lbrbc.LB_OK              # nothing to do
+
+
+def test_too_many_cells_for_coverage_entries():
+    # entries are cell << shift | j in 32 bits: the shift for xi = (4, 4, 1.5) is 11, so at
+    # most 2^20 cells fit
+    from paper_1107_4889_amd import lbrbc, synth
+
+    solid = synth.tube(16, 16, 32, 6.0)
+    assert lbrbc.lb_query_footprint(_cfg(), solid, (1 << 20) - 1) > 0
+    with pytest.raises(lbrbc.LbError) as e:
+        lbrbc.lb_query_footprint(_cfg(), solid, 1 << 20)
+    assert e.value.status == lbrbc.LB_EINVAL
