@@ -156,8 +156,10 @@ lb_status rbc_set_state(lb_ctx ctx, const lb_rbc* in, int n);
 lb_status rbc_get_coupling(lb_ctx ctx, double* out22, int n);
 /* Cell grid and list: ncell[3]; off[ncells + 1]; ids[n_rbc] ascending per cell. */
 lb_status rbc_get_cells(lb_ctx ctx, int* ncell, int* off, int* ids);
-/* Coverage map as CSR over all nodes, ids ascending per node: off[N + 1] (may be NULL),
- * ids[*len] (NULL to query *len). */
+/* Coverage map (the cells covering each node) as CSR over all nodes, ids ascending per
+ * node: off[N + 1] (may be NULL), ids[*len] (NULL to query *len). It is the map of the last
+ * rbc_couple call: call rbc_couple first to read the map of the current state (a time step
+ * consumes the per-node counts of its own map). */
 lb_status rbc_get_map(lb_ctx ctx, int* off, int* ids, long long* len);
 
 /* Checkpoint of the full dynamic state (populations in storage precision, fields, cells,
