@@ -210,8 +210,10 @@ def precision(args):
           file=sys.stderr, flush=True)
 
     def cfg(st):
+        # "bf16": stochastic rounding (the default); "bf16rne": round to nearest even
         return dict(nx=nx, ny=ny, nz=nz, periodic=(0, 0, 1), tau0=0.8, g_ext=(0.0, 0.0, 1e-6),
-                    storage=st, f16_scale=2.0 ** 21)
+                    storage="bf16" if st.startswith("bf16") else st, f16_scale=2.0 ** 21,
+                    bf16_nearest=1 if st == "bf16rne" else 0)
 
     def run(st, cells):
         sim = lbrbc.Simulation(cfg(st), solid, R=pl.R if cells else None,
@@ -245,7 +247,7 @@ def precision(args):
         key = "cells" if cells else "plasma_only"
         ref = run("f64", cells)
         rows = {"f64": {"mlups": round(ref["mlups"], 1), "flags": ref["flags"]}}
-        for st in ("f32", "bf16", "f16"):
+        for st in ("f32", "bf16", "bf16rne", "f16"):
             r = run(st, cells)
             row = {
                 "mlups": round(r["mlups"], 1),

@@ -83,6 +83,9 @@ typedef struct lb_config {
     int open_z;           /* 1: z faces are pressure boundaries (inlet z = 0, outlet top) */
     double rho_in, rho_out;
     int map_cap;          /* coverage slots per node, 1..12 (0 = 12) */
+    int bf16_nearest;     /* BF16 storage rounding: 0 = stochastic (unbiased; the random bits are
+                             a hash of node, direction and value, so results stay deterministic);
+                             1 = round to nearest even, which loses the increments of slow flows */
 } lb_config;
 
 typedef struct lb_rbc {

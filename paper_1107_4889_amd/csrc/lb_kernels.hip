@@ -183,8 +183,8 @@ __device__ __forceinline__ void collide_pair(const RT* f, const PL& pl, unsigned
     const RT fs = kf * w * (k2 * gc * uc - k3 * gu);
     const RT fa = kf * w * RT(3) * gc;
     if (put) {
-        Store<ST, RT>::st(pl.dst(P), n, live ? f[P] - om * (f[P] - sym - asym) + fs + fa : RT(0), kp.f16_scale);
-        Store<ST, RT>::st(pl.dst(Q), n, live ? f[Q] - om * (f[Q] - sym + asym) + fs - fa : RT(0), kp.f16_scale);
+        store_pop<ST, RT>(pl.dst(P), n, live ? f[P] - om * (f[P] - sym - asym) + fs + fa : RT(0), kp, P);
+        store_pop<ST, RT>(pl.dst(Q), n, live ? f[Q] - om * (f[Q] - sym + asym) + fs - fa : RT(0), kp, Q);
     }
 }
 
@@ -277,7 +277,7 @@ __device__ __forceinline__ void stream_collide_node(const PL& pl, uint32_t* __re
         const RT w0 = RT(w_(0));
         const RT fe0 = w0 * (drho - RT(1.5) * rho * usq);
         const RT F0 = -kf * w0 * k3 * gu;
-        if (put_f) Store<ST, RT>::st(pl.dst(0), n, live ? f[0] - om * (f[0] - fe0) + F0 : RT(0), kp.f16_scale);
+        if (put_f) store_pop<ST, RT>(pl.dst(0), n, live ? f[0] - om * (f[0] - fe0) + F0 : RT(0), kp, 0u);
     }
     collide_pairs<ST, RT>(f, pl, n, drho, rho, ux, uy, uz, usq, g, gu, om, kf, k2, k3, kp, live, put_f,
                           std::make_integer_sequence<int, 9>{});
@@ -340,7 +340,7 @@ __global__ __launch_bounds__(256) void k_open_bc(
     for (int a = 0; a < 6; ++a) sout[(long long)a * kp.ld + n] = RT(0);
     if (!(wi & NW_FLUID)) {
         for (int p = 0; p < 19; ++p)
-            Store<ST, RT>::st(fout + (size_t)p * (size_t)kp.ld, (unsigned)n, RT(w_(p)) * (rb - RT(1)), kp.f16_scale);
+            store_pop<ST, RT>(fout + (size_t)p * (size_t)kp.ld, (unsigned)n, RT(w_(p)) * (rb - RT(1)), kp, (unsigned)p);
         for (int a = 0; a < 3; ++a) uout[(long long)a * kp.ld + n] = RT(0);
         return;
     }
@@ -366,7 +366,7 @@ __global__ __launch_bounds__(256) void k_open_bc(
     for (int p = 0; p < 19; ++p) {
         const RT feb = feq_shift<RT>(p, rb - RT(1), rb, ux, uy, uz, usq);
         const RT fei = feq_shift<RT>(p, drho, rho, ux, uy, uz, usq);
-        Store<ST, RT>::st(fout + (size_t)p * (size_t)kp.ld, (unsigned)n, feb + (RT(1) - om) * (f[p] - fei), kp.f16_scale);
+        store_pop<ST, RT>(fout + (size_t)p * (size_t)kp.ld, (unsigned)n, feb + (RT(1) - om) * (f[p] - fei), kp, (unsigned)p);
     }
     uout[n] = ux;
     uout[kp.ld + n] = uy;

@@ -153,6 +153,7 @@ std::string validate(const lb_config& c, int n_rbc)
     if (!(c.tau0 > 0.5)) return "tau0 must exceed 1/2";
     if (c.forcing != 0 && c.forcing != 1) return "forcing must be 0 or 1";
     if (c.map_cap < 0 || c.map_cap > CAP_MAX) return "map_cap must be in 0..12";
+    if (c.bf16_nearest != 0 && c.bf16_nearest != 1) return "bf16_nearest must be 0 or 1";
     if (c.storage == LB_F16 && !(c.f16_scale > 0)) return "f16_scale must be positive";
     if (c.open_z && c.periodic[2]) return "open z faces need a non-periodic z axis";
     if (c.open_z && c.nz < 3) return "open z faces need nz >= 3";
@@ -713,6 +714,7 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
     }
     kp.tile_max = g.tile_max;
     kp.cand_cap = g.cand_cap;
+    kp.bf16_sr = C.storage == LB_BF16 && !C.bf16_nearest ? 1 : 0;
     kp.ent_shift = g.ent_shift;
 
     const Layout& L = c->lay;

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace lbrbc {
 
 // ---- D3Q19 (Sec. II A) -------------------------------------------------------------------
@@ -69,6 +71,7 @@ struct KParams {
     int tile_max;     // LDS tile edge bound
     int cand_cap;     // candidate nodes per cell held in LDS by the one-wavefront map pass
     int ent_shift;    // log2 of the coverage entries reserved per cell
+    int bf16_sr;      // BF16 storage with stochastic rounding
 };
 
 // ---- per-cell records ---------------------------------------------------------------------
@@ -138,6 +141,40 @@ struct Store<bf16_t, float> {
         __builtin_nontemporal_store(r, at32(reinterpret_cast<uint16_t*>(p), i));
     }
 };
+// Stochastic rounding of FP32 to BF16: add 16 random bits below the kept mantissa, then
+// truncate (rounds up with probability equal to the dropped fraction: unbiased). The bits
+// are the MurmurHash3 32-bit finalizer of the node, the direction and the value.
+__device__ __forceinline__ uint32_t fmix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+__device__ __forceinline__ void store_bf16_sr(bf16_t* p, unsigned i, float v, unsigned dir)
+{
+    const uint32_t u = __float_as_uint(v);
+    uint16_t r;
+    if ((u & 0x7f800000u) == 0x7f800000u) r = (u & 0x007fffffu) ? 0x7fc0 : (uint16_t)(u >> 16);
+    else r = (uint16_t)((u + (fmix32(i * 0x9e3779b1u ^ dir * 0x85ebca77u ^ u) & 0xffffu)) >> 16);
+    __builtin_nontemporal_store(r, at32(reinterpret_cast<uint16_t*>(p), i));
+}
+
+// store of population `dir` at node i: the storage's own rounding, or stochastic for BF16
+template <typename ST, typename RT>
+__device__ __forceinline__ void store_pop(ST* p, unsigned i, RT v, const KParams& kp, unsigned dir)
+{
+    if constexpr (std::is_same<ST, bf16_t>::value) {
+        if (kp.bf16_sr) {
+            store_bf16_sr(p, i, v, dir);
+            return;
+        }
+    }
+    Store<ST, RT>::st(p, i, v, kp.f16_scale);
+}
+
 template <>
 struct Store<_Float16, float> {
     __device__ static float ld(const _Float16* p, unsigned i, float inv) { return (float)*at32(p, i) * inv; }

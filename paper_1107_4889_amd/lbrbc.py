@@ -51,6 +51,7 @@ class lb_config(ctypes.Structure):
         ("a_wall", ctypes.c_double), ("sigmin_wall", ctypes.c_double),
         ("wall_particles", ctypes.c_int), ("open_z", ctypes.c_int),
         ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double), ("map_cap", ctypes.c_int),
+        ("bf16_nearest", ctypes.c_int),
     ]
 
 
@@ -118,7 +119,8 @@ DEFAULTS = dict(periodic=(0, 0, 1), storage="f32", f16_scale=2.0 ** 21, forcing=
                 delta_visc=2.0, kappa=20.0, g_ext=(0.0, 0.0, 0.0), gammaT=0.1, gammaR=0.1,
                 alpha=0.04, mass=10.0, inertia=(1000.0, 1000.0, 1000.0), vort_scale=1.0,
                 xi=(4.0, 4.0, 1.5), axes=(4.0, 4.0, 1.5), eps0=1e-3, a_wall=0.5, sigmin_wall=0.5,
-                wall_particles=1, open_z=0, rho_in=1.0, rho_out=1.0, map_cap=12)
+                wall_particles=1, open_z=0, rho_in=1.0, rho_out=1.0, map_cap=12,
+                bf16_nearest=0)
 
 
 def make_config(cfg: dict) -> lb_config:

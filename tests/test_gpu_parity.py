@@ -150,13 +150,21 @@ def test_coupled_100_steps_f32_and_16bit(lb, small, ref100):
     fl = solid.reshape(-1) == 0
     ur = ref100.u()[fl]
     errs = {}
-    for storage, tol in (("f32", 1e-4), ("f16", 5e-3), ("bf16", 3e-2)):
-        sim = lb.Simulation(dict(cfg, storage=storage, f16_scale=2.0 ** 24), solid, R=pl.R, Q=pl.Q)
+    # bf16: stochastic rounding (the default); bf16rne: round to nearest even
+    for storage, tol in (("f32", 1e-4), ("f16", 5e-3), ("bf16", 3e-2), ("bf16rne", 3e-2)):
+        c = dict(cfg, storage=storage[:4] if storage.startswith("bf16") else storage,
+                 f16_scale=2.0 ** 24, bf16_nearest=int(storage == "bf16rne"))
+        sim = lb.Simulation(c, solid, R=pl.R, Q=pl.Q)
         sim.lb_step(100)
         sim.lb_sync()
         u = sim.lb_get_fields(f=False, sigma=False)["u"][fl]
         errs[storage] = rel_l2(u, ur)
         assert errs[storage] < tol, (storage, errs[storage])
+        if storage == "bf16":
+            # the rounding bits hash node, direction and value: a rerun is bitwise identical
+            again = lb.Simulation(c, solid, R=pl.R, Q=pl.Q)
+            again.lb_step(100)
+            assert again.lb_save()[56:] == sim.lb_save()[56:]
     print("velocity rel-L2 vs FP64 oracle after 100 coupled steps:", errs)
 
 
