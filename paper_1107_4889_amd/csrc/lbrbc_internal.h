@@ -96,7 +96,6 @@ __device__ __forceinline__ int fused_slot(const FusedArgs& fa, int& lb)
     return lo;
 }
 
-void launch_rb_first_half(const CellBuffers& b, const KParams& kp, hipStream_t st);
 void launch_cell_list(const CellBuffers& b, const KParams& kp, hipStream_t st);
 // first rigid-body half fused with the binning, then the rest of the cell list
 void launch_rb1_cell_list(const CellBuffers& b, const KParams& kp, hipStream_t st);
@@ -109,6 +108,5 @@ void launch_gay_berne(const CellBuffers& b, const KParams& kp, hipStream_t st);
 // and the gather records)
 void launch_rb_second_half(const CellBuffers& b, const KParams& kp, hipStream_t st);
 void launch_init_combined(const CellBuffers& b, const KParams& kp, hipStream_t st);
-void launch_fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t st);
 
 }  // namespace lbrbc

@@ -79,11 +79,6 @@ __device__ __forceinline__ void rb1_cell(RbcState* __restrict__ st, const KParam
     st[i] = s;
 }
 
-__global__ __launch_bounds__(128) void k_rb_first_half(RbcState* __restrict__ st, KParams kp)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < kp.nrbc) rb1_cell(st, kp, i);
-}
 
 // ---- S2: cell list (counting sort, ids ascending per cell) --------------------------------
 __device__ __forceinline__ int cell_coord(const KParams& kp, int a, double x)
@@ -1050,11 +1045,6 @@ __global__ void k_init_combined(RbcState* __restrict__ st, const RbcCouple* __re
     }
 }
 
-__global__ void k_fill_u32(uint32_t* p, uint32_t v, long long n)
-{
-    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) p[k] = v;
-}
 
 // ---- fused multi-lattice versions of the per-cell stages (one launch for many contexts) -----
 constexpr int FUSED_TILE_BLOCKS = 4;   // blocks per slot of the full-tile overflow pass
@@ -1144,15 +1134,7 @@ __global__ __launch_bounds__(128) void kf_kick(const FusedArgs fa)
 // ---- launchers ---------------------------------------------------------------------------------
 static inline unsigned nblk(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
-void launch_fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t st)
-{
-    if (n > 0) hipLaunchKernelGGL(k_fill_u32, dim3(nblk(n, 256)), dim3(256), 0, st, p, v, n);
-}
 
-void launch_rb_first_half(const CellBuffers& b, const KParams& kp, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_rb_first_half, dim3(nblk(kp.nrbc, 128)), dim3(128), 0, st, b.st, kp);
-}
 
 void launch_rb1_cell_list(const CellBuffers& b, const KParams& kp, hipStream_t st)
 {
