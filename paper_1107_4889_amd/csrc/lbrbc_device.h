@@ -234,10 +234,9 @@ __device__ __forceinline__ RT peskin(RT r)
 
 __device__ __forceinline__ double min_img(double d, double L, int per)
 {
-    if (per) {
-        if (d > 0.5 * L) d -= L;
-        else if (d < -0.5 * L) d += L;
-    }
+    // one period at most (selects, no branches)
+    d = (per && d > 0.5 * L) ? d - L : d;
+    d = (per && d < -0.5 * L) ? d + L : d;
     return d;
 }
 

@@ -232,14 +232,9 @@ __device__ __forceinline__ void support_tile(const RbcState& s, const KParams& k
 // returns false outside a non-periodic face
 __device__ __forceinline__ bool wrap_coord(int& X, int L, int per)
 {
-    if (X < 0) {
-        if (!per) return false;
-        X += L;
-    } else if (X >= L) {
-        if (!per) return false;
-        X -= L;
-    }
-    return true;
+    const bool lo = X < 0, hi = X >= L;
+    X = (per && lo) ? X + L : ((per && hi) ? X - L : X);
+    return per || !(lo || hi);
 }
 
 __device__ __forceinline__ unsigned node_of(const KParams& kp, int X, int Y, int Z)
@@ -626,8 +621,9 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
         const int ty = yz & 255, tz = yz >> 8, r = ty + tz * sy, tx = clo[r] + (c - off[r]);
         int X = T.lo[0] + tx, Y = T.lo[1] + ty, Z = T.lo[2] + tz;
         RT v = RT(-2);
-        if (wrap_coord(X, kp.nx, kp.per[0]) && wrap_coord(Y, kp.ny, kp.per[1]) &&
-            wrap_coord(Z, kp.nz, kp.per[2]) && (nodeword[node_of(kp, X, Y, Z)] & NW_FLUID)) {
+        const bool inbox = wrap_coord(X, kp.nx, kp.per[0]) & wrap_coord(Y, kp.ny, kp.per[1]) &
+                           wrap_coord(Z, kp.nz, kp.per[2]);
+        if (inbox && (nodeword[node_of(kp, X, Y, Z)] & NW_FLUID)) {
             v = RT(-1);
             double y[3];
             const double d0 = min_img((double)X - s.R[0], (double)kp.nx, kp.per[0]);
