@@ -184,9 +184,14 @@ struct Store<_Float16, float> {
     }
 };
 
-// reciprocal in the compute precision: the hardware reciprocal (1 ulp) for float
+// reciprocal and square roots in the compute precision: the hardware instructions (1 ulp)
+// for float, correctly rounded for double
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fast_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float fast_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double fast_rsqrt(double x) { return 1.0 / sqrt(x); }
 
 // Coverage: per node, up to `cap` slot planes hold entry indices e = (cell << ent_shift) | j;
 // entry e holds (raw, grad raw) of the j-th covered node of that cell, cell-major.
@@ -226,10 +231,14 @@ struct PlanesLd {
 template <typename RT>
 __device__ __forceinline__ RT peskin(RT r)
 {
+    // both pieces with one square root (selects): (3 - 2r + sqrt(1 + 4r - 4r^2)) / 8 on
+    // [0, 1], (5 - 2r - sqrt(-7 + 12r - 4r^2)) / 8 on (1, 2), 0 beyond
     r = fabs(r);
-    if (r <= RT(1)) return (RT(3) - RT(2) * r + sqrt(RT(1) + RT(4) * r - RT(4) * r * r)) * RT(0.125);
-    if (r < RT(2)) return (RT(5) - RT(2) * r - sqrt(RT(-7) + RT(12) * r - RT(4) * r * r)) * RT(0.125);
-    return RT(0);
+    const bool in1 = r <= RT(1);
+    const RT q = in1 ? RT(1) + RT(4) * r - RT(4) * r * r : RT(-7) + RT(12) * r - RT(4) * r * r;
+    const RT sq = fast_sqrt(q > RT(0) ? q : RT(0));
+    const RT v = (in1 ? RT(3) - RT(2) * r + sq : RT(5) - RT(2) * r - sq) * RT(0.125);
+    return r < RT(2) ? v : RT(0);
 }
 
 __device__ __forceinline__ double min_img(double d, double L, int per)

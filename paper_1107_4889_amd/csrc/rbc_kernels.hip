@@ -442,8 +442,8 @@ __device__ void map_couple_tile(int i, unsigned char* smem, const RbcState* __re
         acc[0] += dh * ux;
         acc[1] += dh * uy;
         acc[2] += dh * uz;
-        const RT gl = sqrt(hx * hx + hy * hy + hz * hz);
-        const RT il = gl > RT(0) ? RT(1) / gl : RT(0);
+        const RT g2 = hx * hx + hy * hy + hz * hz;
+        const RT il = g2 > RT(0) ? fast_rsqrt(g2) : RT(0);
         const RT nx_ = hx * il, ny_ = hy * il, nz_ = hz * il;
         const RT sxx = sig[n], syy = sig[ld + n], szz = sig[2 * ld + n];
         const RT sxy_ = sig[3 * ld + n], sxz = sig[4 * ld + n], syz = sig[5 * ld + n];
@@ -711,8 +711,8 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
         acc[0] += dh * ux;
         acc[1] += dh * uy;
         acc[2] += dh * uz;
-        const RT gl = sqrt(hx * hx + hy * hy + hz * hz);
-        const RT il = gl > RT(0) ? RT(1) / gl : RT(0);
+        const RT g2 = hx * hx + hy * hy + hz * hz;
+        const RT il = g2 > RT(0) ? fast_rsqrt(g2) : RT(0);
         const RT nx_ = hx * il, ny_ = hy * il, nz_ = hz * il;
         const RT sxx = *at32(sig, n), syy = *at32(sig + ld, n), szz = *at32(sig + 2 * ld, n);
         const RT sxy_ = *at32(sig + 3 * ld, n), sxz = *at32(sig + 4 * ld, n), syz = *at32(sig + 5 * ld, n);
