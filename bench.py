@@ -277,6 +277,64 @@ def precision(args):
     print(json.dumps(line), flush=True)
 
 
+def observables(args):
+    """The tube's observables near steady state: the cell-laden tube and its H = 0 twin run
+    for --obs-steps steps; flow rate, apparent and relative viscosity (eta_rel = Q_0 / Q_H),
+    the radial profile of u_z (1-lu bins, averaged over z and angle), the time-averaged wall
+    shear stress (mean and spread) over the last quarter, and the radial distribution of the
+    cell centres."""
+    import numpy as np
+    import torch
+
+    from paper_1107_4889_amd import lbrbc
+
+    out = {}
+    prof = {}
+    for name in ("tube128_h0", "tube128"):
+        cfg, solid, pl, desc = workload(name, "f32")
+        sim = lbrbc.Simulation(cfg, solid, R=pl.R if len(pl.R) else None, Q=pl.Q if len(pl.R) else None)
+        n = args.obs_steps
+        t0 = time.perf_counter()
+        sim.lb_step(n - n // 4)
+        sim.lb_wss_accumulate(True)
+        for k in range(4):
+            sim.lb_step(n // 16)
+            torch.cuda.synchronize()
+            print(f"[observables] {name}: {n - n // 4 + (k + 1) * (n // 16)}/{n} steps", file=sys.stderr,
+                  flush=True)
+        dt = time.perf_counter() - t0
+        o = sim.lb_observe()
+        u = sim.lb_get_fields(f=False, u=True, sigma=False)["u"]
+        nx, ny, nz = cfg["nx"], cfg["ny"], cfg["nz"]
+        uz = u[:, 2].reshape(nz, ny, nx).mean(axis=0)
+        yy, xx = np.mgrid[0:ny, 0:nx]
+        r = np.hypot(xx - (nx - 1) / 2.0, yy - (ny - 1) / 2.0)
+        fl2 = solid.reshape(nz, ny, nx)[0] == 0
+        bins = np.floor(r[fl2]).astype(int)
+        prof[name] = (np.bincount(bins, weights=uz[fl2]) / np.maximum(np.bincount(bins), 1)).tolist()
+        _, wss_t = sim.lb_wall_shear_stress(True)
+        rec = {"steps": n, "seconds": round(dt, 2), "flow_rate": o.flow_rate, "eta_app": o.eta_app,
+               "wss_time_avg_mean": float(wss_t.mean()), "wss_time_avg_std": float(wss_t.std()),
+               "flags": int(o.flags)}
+        if len(pl.R):
+            Rc = sim.rbc_get_state()[0]
+            rc = np.hypot(Rc[:, 0] - (nx - 1) / 2.0, Rc[:, 1] - (ny - 1) / 2.0)
+            rec["cell_centre_radial_histogram"] = np.bincount(np.floor(rc).astype(int),
+                                                              minlength=int(np.ceil(rc.max())) + 1).tolist()
+            rec["cell_centre_r_max"] = float(rc.max())
+        out[name] = rec
+        del sim
+    line = {
+        "metric": "tube observables near steady state (FP32)",
+        "config": {"workload": "tube 128x128x512 R=60, 19,241 cells (H=0.334) and its H=0 twin, "
+                               "T0=0.8, g=1e-6"},
+        "results": out,
+        "eta_rel": out["tube128_h0"]["flow_rate"] / out["tube128"]["flow_rate"],
+        "u_z_radial_profile": prof,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -295,6 +353,9 @@ def main():
     ap.add_argument("--graphs", action="store_true", help="replay captured HIP graphs per chunk")
     ap.add_argument("--fused", action="store_true",
                     help="serving mode: one stream, each stage one launch over all resident requests")
+    ap.add_argument("--observables", action="store_true",
+                    help="flow rate, eta_app, eta_rel, u_z profile, WSS near steady state")
+    ap.add_argument("--obs-steps", type=int, default=40000)
     ap.add_argument("--no-serving", action="store_true",
                     help="default run: skip the request-stream leg (p50/p99 latency)")
     ap.add_argument("--budget-gib", type=float, default=64.0)
@@ -326,6 +387,9 @@ def main():
         return
     if args.precision:
         precision(args)
+        return
+    if args.observables:
+        observables(args)
         return
 
     from paper_1107_4889_amd import lbrbc
