@@ -298,7 +298,10 @@ __device__ __forceinline__ void stream_collide_node(const PL& pl, uint32_t* __re
         __builtin_nontemporal_store(live ? ks * (pxz - rho * ux * uz) : z0, at32(pl.str(4), n));
         __builtin_nontemporal_store(live ? ks * (pyz - rho * uy * uz) : z0, at32(pl.str(5), n));
     }
-    if (CLEAR && line_has_fluid(4u)) __builtin_nontemporal_store(w & NW_STATIC, at32(nodeword, n));
+    // (the boundary kernel still reads, and then clears, the counts at the open planes and
+    // at the nodes it extrapolates from)
+    if (CLEAR && line_has_fluid(4u))
+        __builtin_nontemporal_store((w & NW_OPEN_INNER) ? w : (w & NW_STATIC), at32(nodeword, n));
     if (live && (!(rho > RT(0)) || !(usq <= RT(0.09)))) atomicOr(err, ERR_UNSTABLE);
 }
 
@@ -314,12 +317,30 @@ __global__ __launch_bounds__(256) void k_stream_collide(
                                                            (int)blockIdx.z);
 }
 
+// The same update over a list of 64-node row segments (x0, y, z) that hold a fluid node, one
+// wavefront each, four per block: sparse geometries skip the all-solid segments, whose
+// wavefronts would only read their node words and exit.
+template <typename ST, typename RT, bool CLEAR>
+__global__ __launch_bounds__(256) void k_stream_collide_seg(
+    const Planes<ST, RT> pl, uint32_t* __restrict__ nodeword, const MapPlanes<RT> mp,
+    const Gather<RT>* __restrict__ gat, KParams kp, unsigned* __restrict__ err,
+    const int4* __restrict__ segs, int nseg)
+{
+    const int k = (int)blockIdx.x * 4 + (int)threadIdx.y;
+    if (k >= nseg) return;
+    const int4 sg = segs[k];
+    const int x = sg.x + (int)threadIdx.x;
+    if (x < kp.nx)
+        stream_collide_node<ST, RT, Planes<ST, RT>, CLEAR>(pl, nodeword, mp, gat, kp, err, x, sg.y, sg.z);
+}
+
 // ---- open z faces: non-equilibrium extrapolation (Guo, Zheng & Shi 2002) ------------------
 template <typename ST, typename RT>
 __global__ __launch_bounds__(256) void k_open_bc(
-    const ST* __restrict__ fin, ST* __restrict__ fout, const uint32_t* __restrict__ nodeword,
+    const ST* __restrict__ fin, ST* __restrict__ fout, uint32_t* __restrict__ nodeword,
     const long long* __restrict__ plane_nodes, int nplane, const MapPlanes<RT> mp,
-    const Gather<RT>* __restrict__ gat, RT* __restrict__ uout, RT* __restrict__ sout, KParams kp)
+    const Gather<RT>* __restrict__ gat, RT* __restrict__ uout, RT* __restrict__ sout, KParams kp,
+    int clear_counts)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nplane) return;
@@ -338,6 +359,9 @@ __global__ __launch_bounds__(256) void k_open_bc(
     const RT om = RT(1) / ((RT)kp.tau0 + (RT)kp.delta * thb);
 #pragma unroll
     for (int a = 0; a < 6; ++a) sout[(long long)a * kp.ld + n] = RT(0);
+    // with clear_counts this thread is the only reader of the counts at n and ni (the inner
+    // node of one plane node): it clears them for the next step's map pass once read
+    if (clear_counts && (w >> 24)) nodeword[n] = w & NW_STATIC;
     if (!(wi & NW_FLUID)) {
         for (int p = 0; p < 19; ++p)
             store_pop<ST, RT>(fout + (size_t)p * (size_t)kp.ld, (unsigned)n, RT(w_(p)) * (rb - RT(1)), kp, (unsigned)p);
@@ -352,6 +376,7 @@ __global__ __launch_bounds__(256) void k_open_bc(
                      std::make_integer_sequence<int, 19>{});
     RT gi[3], thi;
     spread_at<RT>((unsigned)ni, wi, nodeword, mp, gat, kp, gi, thi);
+    if (clear_counts && (wi >> 24)) nodeword[ni] = wi & NW_STATIC;
     RT drho = 0, mx = 0, my = 0, mz = 0;
     for (int p = 0; p < 19; ++p) {
         drho += f[p];
@@ -408,6 +433,24 @@ __global__ __launch_bounds__(256) void k_clear_counts(uint32_t* __restrict__ nod
         const uint32_t w = nodeword[n];
         if (w >> 24) nodeword[n] = w & NW_STATIC;
     }
+}
+
+// the same over the row segments that hold a fluid node (counts are only ever set at fluid
+// nodes); blocks of 64 x 4, one segment per wavefront. A segment with a count is written
+// whole (scattered single-word stores measured several times slower).
+__global__ __launch_bounds__(256) void k_clear_counts_seg(uint32_t* __restrict__ nodeword,
+                                                          const int4* __restrict__ segs, int nseg,
+                                                          int nx, int ny, int* __restrict__ ovf)
+{
+    const int k = (int)blockIdx.x * 4 + (int)threadIdx.y;
+    if (k == 0 && threadIdx.x == 0 && ovf) ovf[0] = 0;
+    if (k >= nseg) return;
+    const int4 sg = segs[k];
+    const int x = sg.x + (int)threadIdx.x;
+    const bool in = x < nx;
+    const size_t n = (size_t)x + (size_t)nx * ((size_t)sg.y + (size_t)ny * (size_t)sg.z);
+    const uint32_t w = in ? nodeword[n] : 0u;
+    if (__ballot(w >> 24) != 0ull && in) nodeword[n] = w & NW_STATIC;
 }
 
 // ---- FP64 reductions: mass, momentum, summed u_z (two passes, fixed order) --------------
@@ -531,7 +574,8 @@ __global__ __launch_bounds__(256) void kf_stream(const FusedArgs fa)
 template <typename ST, typename RT>
 void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword, const int* ids,
                            const void* vals, const void* gat, void* u, void* sig,
-                           const KParams& kp, unsigned* err, bool clear_counts, hipStream_t st)
+                           const KParams& kp, unsigned* err, bool clear_counts, const int4* segs,
+                           int nseg, hipStream_t st)
 {
     const dim3 grid((unsigned)((kp.nx + 63) / 64), (unsigned)((kp.ny + 3) / 4), (unsigned)kp.nz);
     Planes<ST, RT> pl;
@@ -543,6 +587,16 @@ void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword
     for (int a = 0; a < 3; ++a) pl.u[a] = (RT*)u + a * ld;
     for (int a = 0; a < 6; ++a) pl.sig[a] = (RT*)sig + a * ld;
     uint32_t* nw = const_cast<uint32_t*>(nodeword);
+    if (segs && nseg > 0) {
+        const dim3 sgrid((unsigned)((nseg + 3) / 4));
+        if (clear_counts)
+            hipLaunchKernelGGL((k_stream_collide_seg<ST, RT, true>), sgrid, dim3(64, 4, 1), 0, st, pl, nw,
+                               map_planes<RT>(ids, vals, kp), (const Gather<RT>*)gat, kp, err, segs, nseg);
+        else
+            hipLaunchKernelGGL((k_stream_collide_seg<ST, RT, false>), sgrid, dim3(64, 4, 1), 0, st, pl, nw,
+                               map_planes<RT>(ids, vals, kp), (const Gather<RT>*)gat, kp, err, segs, nseg);
+        return;
+    }
     if (clear_counts)
         hipLaunchKernelGGL((k_stream_collide<ST, RT, true>), grid, dim3(64, 4, 1), 0, st, pl, nw,
                            map_planes<RT>(ids, vals, kp), (const Gather<RT>*)gat, kp, err);
@@ -552,14 +606,15 @@ void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword
 }
 
 template <typename ST, typename RT>
-void launch_open_bc(const void* fin, void* fout, const uint32_t* nodeword, const long long* planes,
+void launch_open_bc(const void* fin, void* fout, uint32_t* nodeword, const long long* planes,
                     int nplane, const int* ids, const void* vals, const void* gat, void* u,
-                    void* sig, const KParams& kp, hipStream_t st)
+                    void* sig, const KParams& kp, bool clear_counts, hipStream_t st)
 {
     if (nplane <= 0) return;
     hipLaunchKernelGGL((k_open_bc<ST, RT>), dim3((nplane + 255) / 256), dim3(256), 0, st,
                        (const ST*)fin, (ST*)fout, nodeword, planes, nplane,
-                       map_planes<RT>(ids, vals, kp), (const Gather<RT>*)gat, (RT*)u, (RT*)sig, kp);
+                       map_planes<RT>(ids, vals, kp), (const Gather<RT>*)gat, (RT*)u, (RT*)sig, kp,
+                       clear_counts ? 1 : 0);
 }
 
 template <typename RT>
@@ -571,8 +626,14 @@ void launch_spread_field(const uint32_t* nodeword, const int* ids, const void* v
                        map_planes<RT>(ids, vals, kp), (const Gather<RT>*)gat, (RT*)g, (RT*)t, kp);
 }
 
-void launch_clear_counts(uint32_t* nodeword, long long N, int* ovf, hipStream_t st)
+void launch_clear_counts(uint32_t* nodeword, long long N, int* ovf, const int4* segs, int nseg,
+                         int nx, int ny, hipStream_t st)
 {
+    if (segs && nseg > 0) {
+        hipLaunchKernelGGL(k_clear_counts_seg, dim3((unsigned)((nseg + 3) / 4)), dim3(64, 4, 1), 0, st,
+                           nodeword, segs, nseg, nx, ny, ovf);
+        return;
+    }
     hipLaunchKernelGGL(k_clear_counts, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
                        nodeword, N, ovf);
 }
@@ -608,10 +669,11 @@ void launch_fused_lattice(const FusedArgs& fa, int stage, hipStream_t st)
     template void launch_fused_lattice<ST, RT>(const FusedArgs&, int, hipStream_t);               \
     template void launch_stream_collide<ST, RT>(const void*, void*, const uint32_t*, const int*,  \
                                                 const void*, const void*, void*, void*,           \
-                                                const KParams&, unsigned*, bool, hipStream_t);    \
-    template void launch_open_bc<ST, RT>(const void*, void*, const uint32_t*, const long long*,   \
+                                                const KParams&, unsigned*, bool, const int4*,     \
+                                                int, hipStream_t);                                \
+    template void launch_open_bc<ST, RT>(const void*, void*, uint32_t*, const long long*,         \
                                          int, const int*, const void*, const void*, void*, void*, \
-                                         const KParams&, hipStream_t);                            \
+                                         const KParams&, bool, hipStream_t);                      \
     template void launch_observe<ST, RT>(const void*, const uint32_t*, const void*,               \
                                          const KParams&, double*, int, double*, hipStream_t);
 INST_ST(double, double)

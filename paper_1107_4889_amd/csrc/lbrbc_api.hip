@@ -23,6 +23,10 @@ constexpr int MAX_TIMED = 4096;
 
 size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
+// a segment list replaces the dense launch grid when fewer than this fraction of the 64-node
+// row segments hold fluid (the benchmark tube: 94%; the Y-bifurcation: a few per cent)
+constexpr double SEG_LIST_MAX_FRACTION = 0.6;
+
 int storage_bytes(int s) { return s == LB_F64 ? 8 : (s == LB_F32 ? 4 : 2); }
 int real_bytes(int s) { return s == LB_F64 ? 8 : 4; }
 
@@ -34,6 +38,8 @@ struct Geometry {
     std::vector<long long> wn_node;  // wall-adjacent fluid nodes
     std::vector<double> wn_nrm;
     std::vector<long long> planes;   // open-boundary plane nodes
+    std::vector<int> segs;           // (x0, y, z, 0) of the 64-node row segments holding fluid,
+                                     // kept only when under SEG_LIST_MAX_FRACTION of all segments
     int ncell[3] = {1, 1, 1};
     double cedge[3] = {1, 1, 1};
     double rc = 0;
@@ -157,6 +163,8 @@ std::string validate(const lb_config& c, int n_rbc)
     if (c.storage == LB_F16 && !(c.f16_scale > 0)) return "f16_scale must be positive";
     if (c.open_z && c.periodic[2]) return "open z faces need a non-periodic z axis";
     if (c.open_z && c.nz < 3) return "open z faces need nz >= 3";
+    if ((long long)c.nx * c.ny * c.nz >= (1LL << 32) - (1LL << 20))
+        return "at most 2^32 - 2^20 nodes (32-bit node offsets in a plane)";
     if (n_rbc < 0) return "negative cell count";
     if (n_rbc >= (1 << 27)) return "at most 2^27 - 1 cells (coverage sort keys)";
     if (n_rbc > 0) {
@@ -222,9 +230,34 @@ std::string build_geometry(const lb_config& c, const uint8_t* solid, int n_rbc, 
                     w |= NW_OPEN;
                     g.planes.push_back(n);
                 }
+                // inner neighbour of an open-plane node (z = 1 above the inlet, z = nz - 2
+                // below the outlet)
+                if (c.open_z && ((z == 1 && !solid[n - (long long)c.nx * c.ny]) ||
+                                 (z == c.nz - 2 && !solid[n + (long long)c.nx * c.ny])))
+                    w |= NW_OPEN_INNER;
                 g.nodeword[n] = w;
                 g.n_fluid++;
             }
+    // row segments of 64 nodes that hold a fluid node: sparse geometries launch the
+    // stream-collide and the count clearing over these only
+    {
+        const int nb = (c.nx + 63) / 64;
+        long long active = 0;
+        std::vector<int> segs;
+        for (int z = 0; z < c.nz; ++z)
+            for (int y = 0; y < c.ny; ++y)
+                for (int b = 0; b < nb; ++b) {
+                    const long long n0 = (long long)c.nx * ((long long)y + (long long)c.ny * z);
+                    bool any = false;
+                    for (int x = 64 * b; x < std::min(c.nx, 64 * b + 64) && !any; ++x)
+                        any = (g.nodeword[n0 + x] & NW_FLUID) != 0;
+                    if (!any) continue;
+                    ++active;
+                    segs.insert(segs.end(), {64 * b, y, z, 0});
+                }
+        const long long total = (long long)nb * c.ny * c.nz;
+        if (active > 0 && (double)active < SEG_LIST_MAX_FRACTION * (double)total) g.segs.swap(segs);
+    }
     // cell grid: r_c bounds every Gay-Berne cut-off (cell-cell and cell-wall)
     const double amax = std::max(c.axes[0], std::max(c.axes[1], c.axes[2]));
     const double amin = std::min(c.axes[0], std::min(c.axes[1], c.axes[2]));
@@ -293,7 +326,7 @@ std::string build_geometry(const lb_config& c, const uint8_t* solid, int n_rbc, 
 // ---- arena layout --------------------------------------------------------------------------
 struct Layout {
     size_t fA, fB, u, sig, gdbg, tdbg, nodeword, map_ids, map_vals, ovf, st, cp, gat, cellid, cell_cnt, cell_off,
-        cell_ids, wall_xyz, wcell_off, wcell_ids, wn_node, wn_nrm, wss, wss_acc, planes, partials,
+        cell_part, cell_ids, wall_xyz, wcell_off, wcell_ids, wn_node, wn_nrm, wss, wss_acc, planes, segs, partials,
         obs_out, err, slot, total;
 };
 
@@ -327,6 +360,7 @@ Layout layout(const lb_config& c, const Geometry& g, int n_rbc)
     L.cellid = take(n_rbc * 4);
     L.cell_cnt = take(nc * 4);
     L.cell_off = take((nc + 1) * 4);
+    L.cell_part = take((nc + 4095) / 4096 * 4);
     L.cell_ids = take(n_rbc * 4);
     L.wall_xyz = take(nwall * 3 * 4);
     L.wcell_off = take((nc + 1) * 4);
@@ -336,6 +370,7 @@ Layout layout(const lb_config& c, const Geometry& g, int n_rbc)
     L.wss = take(nwn * 8);
     L.wss_acc = take(nwn * 8);
     L.planes = take(g.planes.size() * 8);
+    L.segs = take(g.segs.size() * 4);
     L.partials = take(6 * OBS_BLOCKS * 8);
     L.obs_out = take(8 * 8);
     L.err = take(4);
@@ -380,6 +415,9 @@ struct lb_ctx_s {
 
     template <typename T>
     T* at(size_t off) { return reinterpret_cast<T*>(base + off); }
+    // the row-segment list of a sparse geometry (null and 0: the dense launch grid)
+    const int4* segs() { return geo.segs.empty() ? nullptr : at<int4>(lay.segs); }
+    int nseg() const { return (int)(geo.segs.size() / 4); }
 };
 
 namespace {
@@ -501,7 +539,7 @@ void enqueue_cells_map_couple(lb_ctx c)
 {
     hipStream_t s = c->stream;
     launch_cell_list(c->cb, c->kp, s);
-    launch_clear_counts(c->cb.nodeword, c->kp.N, c->cb.ovf, s);
+    launch_clear_counts(c->cb.nodeword, c->kp.N, c->cb.ovf, c->segs(), c->nseg(), c->kp.nx, c->kp.ny, s);
     launch_map_couple<RT>(c->cb, c->kp, s);
 }
 
@@ -511,10 +549,12 @@ void enqueue_step(lb_ctx c)
     const KParams& kp = c->kp;
     c->cb.u = c->at<void>(c->lay.u);
     c->cb.sig = c->at<void>(c->lay.sig);
-    // Without open planes the stream-collide clears the coverage counts for the next step;
-    // with them the boundary kernel still needs the counts after it, so they are cleared
-    // before the map pass instead (and once after rbc_couple, which leaves them set).
-    const bool sc_clears = c->geo.planes.empty();
+    // The stream-collide clears the coverage counts for the next step, except at the open
+    // planes and their inner neighbours, whose counts the boundary kernel reads after it and
+    // then clears. With nz = 3 both planes extrapolate from the same layer (two readers), so
+    // the counts are cleared before the map pass instead; likewise once after rbc_couple,
+    // which leaves them set.
+    const bool sc_clears = c->geo.planes.empty() || c->cfg.nz > 3;
     with_types(c->cfg.storage, [&](auto* sp, auto* rp) {
         using ST = std::remove_pointer_t<decltype(sp)>;
         using RT = std::remove_pointer_t<decltype(rp)>;
@@ -530,7 +570,8 @@ void enqueue_step(lb_ctx c)
                 launch_gay_berne(c->cb, kp, c->side);
                 (void)hipEventRecord(c->ev_gb, c->side);
             }
-            if (!sc_clears || !c->counts_clean) launch_clear_counts(c->cb.nodeword, kp.N, c->cb.ovf, s);
+            if (!sc_clears || !c->counts_clean)
+                launch_clear_counts(c->cb.nodeword, kp.N, c->cb.ovf, c->segs(), c->nseg(), kp.nx, kp.ny, s);
             launch_map_couple<RT>(c->cb, kp, s);
             if (!forked) {
                 launch_gay_berne(c->cb, kp, s);
@@ -547,7 +588,7 @@ void enqueue_step(lb_ctx c)
         }
         launch_stream_collide<ST, RT>(c->fA, c->fB, c->cb.nodeword, c->cb.map_ids, c->cb.map_vals,
                                       c->cb.gat, c->at<void>(c->lay.u), c->at<void>(c->lay.sig), kp,
-                                      c->cb.err, sc_clears && c->nrbc > 0, s);
+                                      c->cb.err, sc_clears && c->nrbc > 0, c->segs(), c->nseg(), s);
         if (e0) {
             (void)hipEventRecord(e1, s);
             c->sc_pairs.emplace_back(e0, e1);
@@ -555,7 +596,8 @@ void enqueue_step(lb_ctx c)
         if (!c->geo.planes.empty())
             launch_open_bc<ST, RT>(c->fA, c->fB, c->cb.nodeword, c->at<long long>(c->lay.planes),
                                    (int)c->geo.planes.size(), c->cb.map_ids, c->cb.map_vals, c->cb.gat,
-                                   c->at<void>(c->lay.u), c->at<void>(c->lay.sig), kp, s);
+                                   c->at<void>(c->lay.u), c->at<void>(c->lay.sig), kp,
+                                   sc_clears && c->nrbc > 0, s);
         if (c->wss_on)
             launch_wss<RT>(c->at<void>(c->lay.sig), c->at<long long>(c->lay.wn_node),
                            c->at<double>(c->lay.wn_nrm), (int)c->geo.wn_node.size(), kp, nullptr,
@@ -727,6 +769,7 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
     b.cellid = c->at<int>(L.cellid);
     b.cell_cnt = c->at<int>(L.cell_cnt);
     b.cell_off = c->at<int>(L.cell_off);
+    b.cell_part = c->at<int>(L.cell_part);
     b.cell_ids = c->at<int>(L.cell_ids);
     b.wall_xyz = c->at<int>(L.wall_xyz);
     b.wcell_off = c->at<int>(L.wcell_off);
@@ -755,6 +798,7 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
     e = e ? e : h2d(L.wn_node, g.wn_node.data(), g.wn_node.size() * 8);
     e = e ? e : h2d(L.wn_nrm, g.wn_nrm.data(), g.wn_nrm.size() * 8);
     e = e ? e : h2d(L.planes, g.planes.data(), g.planes.size() * 8);
+    e = e ? e : h2d(L.segs, g.segs.data(), g.segs.size() * 4);
     std::vector<RbcState> hs(n_rbc);
     for (int i = 0; i < n_rbc; ++i) {
         RbcState& r = hs[i];

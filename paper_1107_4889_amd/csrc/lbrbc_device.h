@@ -34,10 +34,12 @@ __host__ __device__ constexpr double w_(int p)
 // ---- node word ---------------------------------------------------------------------------
 // bits 0-18: bit p set <=> the pull source x - c_p is solid or outside a wall face
 // bit 19: fluid node; bit 20: has an in-box solid neighbour (wall-adjacent);
-// bit 21: open-boundary plane node; bits 24-31: number of covering cells this step.
+// bit 21: open-boundary plane node; bit 22: fluid node next to an open-plane node along z
+// (the boundary kernel extrapolates from it); bits 24-31: number of covering cells this step.
 constexpr uint32_t NW_FLUID = 1u << 19;
 constexpr uint32_t NW_WALLADJ = 1u << 20;
 constexpr uint32_t NW_OPEN = 1u << 21;
+constexpr uint32_t NW_OPEN_INNER = 1u << 22;
 constexpr uint32_t NW_CNT_ONE = 1u << 24;
 constexpr uint32_t NW_STATIC = 0x00FFFFFFu;
 constexpr int CAP_MAX = 12;

@@ -15,15 +15,17 @@ namespace lbrbc {
 template <typename ST, typename RT>
 void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword, const int* ids,
                            const void* vals, const void* gat, void* u, void* sig,
-                           const KParams& kp, unsigned* err, bool clear_counts, hipStream_t st);
+                           const KParams& kp, unsigned* err, bool clear_counts, const int4* segs,
+                           int nseg, hipStream_t st);
 template <typename ST, typename RT>
-void launch_open_bc(const void* fin, void* fout, const uint32_t* nodeword, const long long* planes,
+void launch_open_bc(const void* fin, void* fout, uint32_t* nodeword, const long long* planes,
                     int nplane, const int* ids, const void* vals, const void* gat, void* u,
-                    void* sig, const KParams& kp, hipStream_t st);
+                    void* sig, const KParams& kp, bool clear_counts, hipStream_t st);
 template <typename RT>
 void launch_spread_field(const uint32_t* nodeword, const int* ids, const void* vals,
                          const void* gat, void* g, void* t, const KParams& kp, hipStream_t st);
-void launch_clear_counts(uint32_t* nodeword, long long N, int* ovf, hipStream_t st);
+void launch_clear_counts(uint32_t* nodeword, long long N, int* ovf, const int4* segs, int nseg,
+                         int nx, int ny, hipStream_t st);
 template <typename ST, typename RT>
 void launch_observe(const void* f, const uint32_t* nodeword, const void* u, const KParams& kp,
                     double* partials, int nblk, double* out, hipStream_t st);
@@ -39,6 +41,7 @@ struct CellBuffers {
     int* cellid;          // [nrbc]
     int* cell_cnt;        // [ncells]
     int* cell_off;        // [ncells + 1]
+    int* cell_part;       // [ceil(ncells / 4096)] chunk totals of the multi-block scan
     int* cell_ids;        // [nrbc]
     const int* wall_xyz;  // [3 * nwall]
     const int* wcell_off; // [ncells + 1]

@@ -120,54 +120,104 @@ __global__ __launch_bounds__(256) void k_rb1_bin(RbcState* __restrict__ st, int*
 
 // exclusive scan of n ints in one block of 1024 threads, 4096 values per round (each thread
 // four consecutive values, so the loads are coalesced); also clears `cnt`
+// One round of the exclusive scan of the cell counts over SCAN_CHUNK entries from `base`
+// (1024 threads, four consecutive entries each), offset by `carry`; writes the offsets,
+// clears the counts and returns the round's total.
+constexpr int SCAN_CHUNK = 4096;
+constexpr int SCAN_SINGLE_BLOCK_CHUNKS = 2;
+
+__device__ __forceinline__ int scan_round(int* cnt, int* off, int base, int n, int carry,
+                                          int* wsum)
+{
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int i0 = base + 4 * t;
+    int v[4];
+    if (i0 + 3 < n) {
+        const int4 q = *reinterpret_cast<const int4*>(cnt + i0);
+        v[0] = q.x;
+        v[1] = q.y;
+        v[2] = q.z;
+        v[3] = q.w;
+    } else {
+        for (int j = 0; j < 4; ++j) v[j] = i0 + j < n ? cnt[i0 + j] : 0;
+    }
+    const int sum = v[0] + v[1] + v[2] + v[3];
+    int incl = sum;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int before = 0, round = 0;
+    for (int k = 0; k < 16; ++k) {
+        const int x = wsum[k];
+        before += k < w ? x : 0;
+        round += x;
+    }
+    int ex = carry + before + incl - sum;
+    for (int j = 0; j < 4; ++j) {
+        if (i0 + j < n) {
+            off[i0 + j] = ex;
+            cnt[i0 + j] = 0;
+        }
+        ex += v[j];
+    }
+    __syncthreads();   // wsum is reused by the next round
+    return round;
+}
+
+// the whole scan in one block, round after round (small cell grids and the fused launches)
 __device__ __forceinline__ void scan_clear_block(int* cnt, int* off, int n)
 {
     __shared__ int wsum[16];
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     int carry = 0;
-    for (int base = 0; base < n; base += 4096) {
-        const int i0 = base + 4 * t;
-        int v[4];
-        if (i0 + 3 < n) {
-            const int4 q = *reinterpret_cast<const int4*>(cnt + i0);
-            v[0] = q.x;
-            v[1] = q.y;
-            v[2] = q.z;
-            v[3] = q.w;
-        } else {
-            for (int j = 0; j < 4; ++j) v[j] = i0 + j < n ? cnt[i0 + j] : 0;
-        }
-        const int sum = v[0] + v[1] + v[2] + v[3];
-        int incl = sum;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += y;
-        }
-        if (lane == 63) wsum[w] = incl;
-        __syncthreads();
-        int before = 0, round = 0;
-        for (int k = 0; k < 16; ++k) {
-            const int x = wsum[k];
-            before += k < w ? x : 0;
-            round += x;
-        }
-        int ex = carry + before + incl - sum;
-        for (int j = 0; j < 4; ++j) {
-            if (i0 + j < n) {
-                off[i0 + j] = ex;
-                cnt[i0 + j] = 0;
-            }
-            ex += v[j];
-        }
-        carry += round;
-        __syncthreads();
-    }
-    if (t == 0) off[n] = carry;
+    for (int base = 0; base < n; base += SCAN_CHUNK) carry += scan_round(cnt, off, base, n, carry, wsum);
+    if (threadIdx.x == 0) off[n] = carry;
 }
 
 __global__ __launch_bounds__(1024) void k_scan_clear(int* cnt, int* off, int n)
 {
     scan_clear_block(cnt, off, n);
+}
+
+// Large cell grids: one block per chunk of SCAN_CHUNK counts. First the chunk totals ...
+__global__ __launch_bounds__(1024) void k_scan_partials(const int* __restrict__ cnt,
+                                                        int* __restrict__ part, int n)
+{
+    __shared__ int wsum[16];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int i0 = (int)blockIdx.x * SCAN_CHUNK + 4 * t;
+    int v = 0;
+    for (int j = 0; j < 4; ++j) v += i0 + j < n ? cnt[i0 + j] : 0;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if (lane == 0) wsum[w] = v;
+    __syncthreads();
+    if (t == 0) {
+        int tot = 0;
+        for (int k = 0; k < 16; ++k) tot += wsum[k];
+        part[blockIdx.x] = tot;
+    }
+}
+
+// ... then each chunk's scan, offset by the totals of the chunks before it (the last block
+// writes off[n])
+__global__ __launch_bounds__(1024) void k_scan_chunks(int* cnt, int* off, const int* __restrict__ part,
+                                                      int n)
+{
+    __shared__ int wsum[16];
+    __shared__ int carry_s;
+    const int b = (int)blockIdx.x, t = threadIdx.x;
+    if (t < 64) {
+        int c = 0;
+        for (int k = t; k < b; k += 64) c += part[k];
+        for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
+        if (t == 0) carry_s = c;
+    }
+    __syncthreads();
+    const int carry = carry_s;
+    const int round = scan_round(cnt, off, b * SCAN_CHUNK, n, carry, wsum);
+    if (t == 0 && b == (int)gridDim.x - 1) off[n] = carry + round;
 }
 
 __device__ __forceinline__ void scatter_cell(const int* __restrict__ cellid,
@@ -1130,6 +1180,19 @@ __global__ __launch_bounds__(128) void kf_kick(const FusedArgs fa)
 // ---- launchers ---------------------------------------------------------------------------------
 static inline unsigned nblk(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// cell offsets from the counts: one block for a few chunks, else one block per chunk
+static void launch_scan_clear(const CellBuffers& b, int nc, hipStream_t st)
+{
+    const int nchunk = (nc + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    if (nchunk <= SCAN_SINGLE_BLOCK_CHUNKS) {
+        hipLaunchKernelGGL(k_scan_clear, dim3(1), dim3(1024), 0, st, b.cell_cnt, b.cell_off, nc);
+        return;
+    }
+    hipLaunchKernelGGL(k_scan_partials, dim3(nchunk), dim3(1024), 0, st, b.cell_cnt, b.cell_part, nc);
+    hipLaunchKernelGGL(k_scan_chunks, dim3(nchunk), dim3(1024), 0, st, b.cell_cnt, b.cell_off,
+                       b.cell_part, nc);
+}
+
 
 
 void launch_rb1_cell_list(const CellBuffers& b, const KParams& kp, hipStream_t st)
@@ -1137,7 +1200,7 @@ void launch_rb1_cell_list(const CellBuffers& b, const KParams& kp, hipStream_t s
     const int nc = kp.ncell[0] * kp.ncell[1] * kp.ncell[2];
     hipLaunchKernelGGL(k_rb1_bin, dim3(nblk(kp.nrbc, 256)), dim3(256), 0, st, b.st, b.cellid,
                        b.cell_cnt, b.ovf, kp);
-    hipLaunchKernelGGL(k_scan_clear, dim3(1), dim3(1024), 0, st, b.cell_cnt, b.cell_off, nc);
+    launch_scan_clear(b, nc, st);
     hipLaunchKernelGGL(k_cells_scatter, dim3(nblk(kp.nrbc, 256)), dim3(256), 0, st, b.cellid,
                        b.cell_off, b.cell_cnt, b.cell_ids, kp.nrbc);
     hipLaunchKernelGGL(k_cells_sort, dim3(nblk(nc, 256)), dim3(256), 0, st, b.cell_off,
@@ -1150,7 +1213,7 @@ void launch_cell_list(const CellBuffers& b, const KParams& kp, hipStream_t st)
     // cell_cnt is all zero here: k_scan_clear leaves it so, and init clears it once
     hipLaunchKernelGGL(k_cells_bin, dim3(nblk(kp.nrbc, 256)), dim3(256), 0, st, b.st, b.cellid,
                        b.cell_cnt, kp);
-    hipLaunchKernelGGL(k_scan_clear, dim3(1), dim3(1024), 0, st, b.cell_cnt, b.cell_off, nc);
+    launch_scan_clear(b, nc, st);
     hipLaunchKernelGGL(k_cells_scatter, dim3(nblk(kp.nrbc, 256)), dim3(256), 0, st, b.cellid,
                        b.cell_off, b.cell_cnt, b.cell_ids, kp.nrbc);
     // the sort leaves the fill counters at zero for the next call

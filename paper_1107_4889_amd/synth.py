@@ -66,18 +66,23 @@ def _capsule_fluid(P, a, b, radius):
 def y_bifurcation(nx: int, ny: int, nz: int, r_parent: float, r_daughter: float,
                   z_branch: float, angle_deg: float = 30.0) -> np.ndarray:
     """Parent tube along z from z = 0 to z_branch, two daughters leaving the branch point at
-    +/- angle to +z in the x-z plane up to the top face (union of capsules)."""
+    +/- angle to +z in the x-z plane up to the top face (union of capsules). Voxelised in
+    z-slabs, so memory stays bounded at large sizes."""
     cx, cy = (nx - 1) / 2.0, (ny - 1) / 2.0
-    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-    P = np.stack([xx, yy, zz], -1).astype(np.float64)
-    # parent, extended below the inlet face so the inlet plane is a full disc
-    fl = _capsule_fluid(P, (cx, cy, -r_parent - 2.0), (cx, cy, z_branch), r_parent)
     th = math.radians(angle_deg)
     L = (nz - 1 - z_branch) / math.cos(th) + r_daughter + 2.0
-    for sgn in (-1.0, 1.0):
-        end = (cx + sgn * L * math.sin(th), cy, z_branch + L * math.cos(th))
-        fl |= _capsule_fluid(P, (cx, cy, z_branch), end, r_daughter)
-    solid = (~fl).astype(np.uint8)
+    solid = np.empty((nz, ny, nx), dtype=np.uint8)
+    slab_z = max(1, (1 << 22) // max(1, nx * ny))
+    for z0 in range(0, nz, slab_z):
+        z1 = min(nz, z0 + slab_z)
+        zz, yy, xx = np.meshgrid(np.arange(z0, z1), np.arange(ny), np.arange(nx), indexing="ij")
+        P = np.stack([xx, yy, zz], -1).astype(np.float64)
+        # parent, extended below the inlet face so the inlet plane is a full disc
+        fl = _capsule_fluid(P, (cx, cy, -r_parent - 2.0), (cx, cy, z_branch), r_parent)
+        for sgn in (-1.0, 1.0):
+            end = (cx + sgn * L * math.sin(th), cy, z_branch + L * math.cos(th))
+            fl |= _capsule_fluid(P, (cx, cy, z_branch), end, r_daughter)
+        solid[z0:z1] = ~fl
     return solid
 
 
@@ -493,6 +498,44 @@ def tube_workload(nx, ny, nz, radius, hematocrit=None, n_cells=None, seed=1107, 
     pl = cached_placement(key, lambda: place_cells(solid, AXES, n_cells, seed,
                                                    periodic=(0, 0, 1), **kw))
     return solid, pl
+
+
+def bifurcation_workload(nx, ny, nz, r_parent, r_daughter, z_branch, hematocrit, seed=1107,
+                         margin=16, **kw):
+    """Y-bifurcation with open z faces plus seeded cells kept `margin` nodes away from the
+    inlet and outlet planes. The voxelised geometry is memoised beside the placement.
+    Returns (solid, Placement)."""
+    d = _cache_dir()
+    gkey = f"ybif:{nx}:{ny}:{nz}:{float(r_parent):g}:{float(r_daughter):g}:{float(z_branch):g}"
+    gfn = os.path.join(d, hashlib.sha1(gkey.encode()).hexdigest()[:16] + ".geom.npz")
+    solid = None
+    if os.path.exists(gfn):
+        z = np.load(gfn)
+        solid = np.unpackbits(z["bits"], count=nx * ny * nz).reshape(nz, ny, nx)
+    if solid is None:
+        solid = y_bifurcation(nx, ny, nz, r_parent, r_daughter, z_branch)
+        try:
+            os.makedirs(d, exist_ok=True)
+            tmp = gfn + f".{os.getpid()}.tmp.npz"
+            np.savez_compressed(tmp, bits=np.packbits(solid.ravel()))
+            os.replace(tmp, gfn)
+        except OSError:
+            pass
+    n_cells = hematocrit_count(solid, AXES, hematocrit)
+    key = f"{gkey}:{n_cells}:{seed}:lid{margin}:{sorted(kw.items())}:{PLACEMENT_VERSION}"
+
+    def make():
+        # placed in the vessel closed by solid lids `margin` nodes thick at both z faces: the
+        # lids keep cells off the open planes, and every real wall point stays in the test
+        closed = solid.copy()
+        closed[:margin] = 1
+        closed[nz - margin:] = 1
+        pl = place_cells(closed, AXES, n_cells, seed, periodic=(0, 0, 0), **kw)
+        v = 4.0 / 3.0 * math.pi * float(np.prod(AXES))
+        return Placement(R=pl.R, Q=pl.Q, hematocrit=len(pl.R) * v / float((solid == 0).sum()),
+                         s_pair=pl.s_pair, attempts=pl.attempts)
+
+    return solid, cached_placement(key, make)
 
 
 def chevron(nx: int, ny: int, nz: int, radius: float, offset: float) -> np.ndarray:

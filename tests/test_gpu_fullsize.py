@@ -35,6 +35,9 @@ def test_fullsize_fp64_step_matches_oracle(tube):
     Rg, Qg, Vg, Og = sim.rbc_get_state()
     sim.rbc_couple()                     # the map of the state after the step
     moff, mids = sim.rbc_get_map()
+    # the 15x15x61 cell grid spans four scan chunks: the multi-block offsets scan
+    ncell, coff, cids = sim.rbc_get_cells()
+    assert int(np.prod(ncell)) > 2 * 4096
     del sim
     ref = orc.Oracle(_cfg(), solid, R=pl.R, Q=pl.Q)
     assert ref.step(1) == 0
@@ -51,6 +54,8 @@ def test_fullsize_fp64_step_matches_oracle(tube):
     ref.couple()
     roff, rids = ref.node_map()
     assert np.array_equal(moff, roff) and np.array_equal(mids, rids)
+    rcoff, rcids = ref.cells()
+    assert np.array_equal(coff, rcoff) and np.array_equal(cids, rcids)
 
 
 def test_fullsize_fp32_bench_config_properties(tube):

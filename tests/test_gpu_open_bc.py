@@ -38,6 +38,11 @@ def test_bifurcation_with_cells_f64_and_f32():
 
     nx, ny, nz = 48, 40, 64
     solid = synth.y_bifurcation(nx, ny, nz, r_parent=10.0, r_daughter=8.0, z_branch=36.0)
+    # 46% of the 64-node row segments hold fluid: the stream-collide and the count clearing
+    # run over the segment list (the tube tests take the dense launch grid)
+    segs = np.zeros((nz, ny, 64), dtype=bool)
+    segs[:, :, :nx] = solid == 0
+    assert segs.any(-1).mean() < 0.6
     # cells away from the open planes (16 lu margin), no periodic axis
     pl = synth.place_cells(solid[16:nz - 16], synth.AXES, 12, seed=5, periodic=(0, 0, 0))
     R = pl.R + np.array([0.0, 0.0, 16.0])
@@ -57,3 +62,34 @@ def test_bifurcation_with_cells_f64_and_f32():
     sim32.lb_step(40)
     u32 = sim32.lb_get_fields(f=False, sigma=False)["u"][fl]
     assert np.linalg.norm(u32 - ref.u()[fl]) / np.linalg.norm(ref.u()[fl]) < 1e-4
+
+
+def test_cells_covering_the_open_planes_f64():
+    """Cells whose supports cover the inlet and outlet planes and the layers the boundary
+    extrapolates from: the boundary kernel reads the coverage counts there after the
+    stream-collide and then clears them. Any count left over would double the cells' forcing
+    in the next step."""
+    from paper_1107_4889_amd import lbrbc
+
+    nx, ny, nz = 24, 24, 40
+    solid = synth.tube(nx, ny, nz, 10.0)
+    Q = synth.random_rotations(np.random.default_rng(17), 3).reshape(3, 9)
+    R = np.array([[11.5, 11.5, 2.0], [11.5, 11.5, 37.2], [11.0, 12.0, 20.0]])
+    cfg = dict(nx=nx, ny=ny, nz=nz, periodic=(0, 0, 0), tau0=0.8, open_z=1, rho_in=1.002,
+               rho_out=0.998)
+    ref = orc.Oracle(cfg, solid, R=R, Q=Q)
+    sim = lbrbc.Simulation(dict(cfg, storage="f64"), solid, R=R, Q=Q)
+    fl = solid.reshape(-1) == 0
+    for _ in range(3):
+        assert ref.step(10) == 0
+        sim.lb_step(10)
+        d = sim.lb_get_fields()
+        assert rel(d["u"][fl], ref.u()[fl]) < 1e-10
+        assert rel(d["f"][:, fl], ref.f()[:, fl]) < 1e-10
+        Rg = sim.rbc_get_state()[0]
+        assert np.abs(Rg - ref.rbc()[0]).max() < 1e-10
+    # the map of the final state covers nodes of both open planes and both inner layers
+    sim.rbc_couple()
+    moff = sim.rbc_get_map()[0]
+    cnt = np.diff(moff).reshape(nz, ny, nx)
+    assert cnt[0].any() and cnt[1].any() and cnt[nz - 2].any() and cnt[nz - 1].any()
