@@ -665,28 +665,55 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
 
     // pass 1: exact support test and raw kernel value at every candidate; S = sum raw
     const RT s0 = RT(2.0 / kp.xi[0]), s1 = RT(2.0 / kp.xi[1]), s2 = RT(2.0 / kp.xi[2]);
-    RT part = RT(0);
-    for (int c = lane; c < total; c += 64) {
-        const int yz = rowof[c];
-        const int ty = yz & 255, tz = yz >> 8, r = ty + tz * sy, tx = clo[r] + (c - off[r]);
-        int X = T.lo[0] + tx, Y = T.lo[1] + ty, Z = T.lo[2] + tz;
-        RT v = RT(-2);
-        const bool inbox = wrap_coord(X, kp.nx, kp.per[0]) & wrap_coord(Y, kp.ny, kp.per[1]) &
-                           wrap_coord(Z, kp.nz, kp.per[2]);
-        if (inbox && (nodeword[node_of(kp, X, Y, Z)] & NW_FLUID)) {
-            v = RT(-1);
-            double y[3];
-            const double d0 = min_img((double)X - s.R[0], (double)kp.nx, kp.per[0]);
-            const double d1 = min_img((double)Y - s.R[1], (double)kp.ny, kp.per[1]);
-            const double d2 = min_img((double)Z - s.R[2], (double)kp.nz, kp.per[2]);
-            body_coords_exact(s.Q, d0, d1, d2, y);
-            if (fabs(y[0]) < kp.xi[0] && fabs(y[1]) < kp.xi[1] && fabs(y[2]) < kp.xi[2]) {
-                v = peskin((RT)y[0] * s0) * peskin((RT)y[1] * s1) * peskin((RT)y[2] * s2);
-                part += v;
-            }
+    // A tile inside the box on every axis, whose nodes all lie within half a period of the
+    // centre on the periodic axes, needs no coordinate wrapping, and its minimum images are
+    // the plain differences (min_img is the identity there): the passes below are
+    // instantiated for that case (most cells) and for the general one.
+    bool interior = true;
+    {
+        const int Lx[3] = {kp.nx, kp.ny, kp.nz};
+        for (int a = 0; a < 3; ++a) {
+            interior = interior && T.lo[a] >= 0 && T.lo[a] + T.sz[a] <= Lx[a];
+            if (kp.per[a])
+                interior = interior && s.R[a] - (double)T.lo[a] <= 0.5 * (double)Lx[a] &&
+                           (double)(T.lo[a] + T.sz[a] - 1) - s.R[a] <= 0.5 * (double)Lx[a];
         }
-        val[c] = v;
     }
+    auto wrap3 = [&](auto inner, int& X, int& Y, int& Z) -> bool {
+        if constexpr (decltype(inner)::value) return true;
+        else
+            return wrap_coord(X, kp.nx, kp.per[0]) & wrap_coord(Y, kp.ny, kp.per[1]) &
+                   wrap_coord(Z, kp.nz, kp.per[2]);
+    };
+    auto mimg = [&](auto inner, double d, double L, int per) -> double {
+        if constexpr (decltype(inner)::value) return d;
+        else return min_img(d, L, per);
+    };
+    RT part = RT(0);
+    auto pass1 = [&](auto inner) {
+        for (int c = lane; c < total; c += 64) {
+            const int yz = rowof[c];
+            const int ty = yz & 255, tz = yz >> 8, r = ty + tz * sy, tx = clo[r] + (c - off[r]);
+            int X = T.lo[0] + tx, Y = T.lo[1] + ty, Z = T.lo[2] + tz;
+            RT v = RT(-2);
+            const bool inbox = wrap3(inner, X, Y, Z);
+            if (inbox && (nodeword[node_of(kp, X, Y, Z)] & NW_FLUID)) {
+                v = RT(-1);
+                double y[3];
+                const double d0 = mimg(inner, (double)X - s.R[0], (double)kp.nx, kp.per[0]);
+                const double d1 = mimg(inner, (double)Y - s.R[1], (double)kp.ny, kp.per[1]);
+                const double d2 = mimg(inner, (double)Z - s.R[2], (double)kp.nz, kp.per[2]);
+                body_coords_exact(s.Q, d0, d1, d2, y);
+                if (fabs(y[0]) < kp.xi[0] && fabs(y[1]) < kp.xi[1] && fabs(y[2]) < kp.xi[2]) {
+                    v = peskin((RT)y[0] * s0) * peskin((RT)y[1] * s1) * peskin((RT)y[2] * s2);
+                    part += v;
+                }
+            }
+            val[c] = v;
+        }
+    };
+    if (interior) pass1(std::true_type{});
+    else pass1(std::false_type{});
     for (int o = 32; o > 0; o >>= 1) part += __shfl_down(part, o, 64);
     const RT S = __shfl(part, 0, 64);
     const RT invS = S > RT(0) ? RT(1) / S : RT(0);
@@ -702,81 +729,83 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
     const size_t ld = (size_t)kp.ld;
     const unsigned long long below = (1ull << lane) - 1ull;
     int jbase = 0;
-    for (int c0 = 0; c0 < total; c0 += 64) {
-        const int c = c0 + lane;
-        const RT v = c < total ? val[c] : RT(-2);
-        int r = 0, ty = 0, tz = 0, tx = 0;
-        RT vxm = RT(-2), vxp = RT(-2), vym = RT(-2), vyp = RT(-2), vzm = RT(-2), vzp = RT(-2);
-        bool cov = false;
-        if (v > RT(-1.5)) {
-            const int yz = rowof[c];
-            ty = yz & 255;
-            tz = yz >> 8;
-            r = ty + tz * sy;
-            tx = clo[r] + (c - off[r]);
-            vxm = at(r, tx - 1);
-            vxp = at(r, tx + 1);
-            if (ty > 0) vym = at(r - 1, tx);
-            if (ty + 1 < sy) vyp = at(r + 1, tx);
-            if (tz > 0) vzm = at(r - sy, tx);
-            if (tz + 1 < sz) vzp = at(r + sy, tx);
-            cov = v >= RT(0) || vxm >= RT(0) || vxp >= RT(0) || vym >= RT(0) || vyp >= RT(0) ||
-                  vzm >= RT(0) || vzp >= RT(0);
+    auto pass2 = [&](auto inner) {
+        for (int c0 = 0; c0 < total; c0 += 64) {
+            const int c = c0 + lane;
+            const RT v = c < total ? val[c] : RT(-2);
+            int r = 0, ty = 0, tz = 0, tx = 0;
+            RT vxm = RT(-2), vxp = RT(-2), vym = RT(-2), vyp = RT(-2), vzm = RT(-2), vzp = RT(-2);
+            bool cov = false;
+            if (v > RT(-1.5)) {
+                const int yz = rowof[c];
+                ty = yz & 255;
+                tz = yz >> 8;
+                r = ty + tz * sy;
+                tx = clo[r] + (c - off[r]);
+                vxm = at(r, tx - 1);
+                vxp = at(r, tx + 1);
+                if (ty > 0) vym = at(r - 1, tx);
+                if (ty + 1 < sy) vyp = at(r + 1, tx);
+                if (tz > 0) vzm = at(r - sy, tx);
+                if (tz + 1 < sz) vzp = at(r + sy, tx);
+                cov = v >= RT(0) || vxm >= RT(0) || vxp >= RT(0) || vym >= RT(0) || vyp >= RT(0) ||
+                      vzm >= RT(0) || vzp >= RT(0);
+            }
+            const unsigned long long m = __ballot(cov);
+            const int j = jbase + (int)__popcll(m & below);
+            jbase += (int)__popcll(m);
+            if (!cov) continue;
+            const bool in = v >= RT(0);
+            int X = T.lo[0] + tx, Y = T.lo[1] + ty, Z = T.lo[2] + tz;
+            wrap3(inner, X, Y, Z);
+            const unsigned n = node_of(kp, X, Y, Z);
+            const RT z0 = RT(0);
+            const RT rr = in ? v : z0;
+            const RT gx = RT(0.5) * (max(vxp, z0) - max(vxm, z0));
+            const RT gy = RT(0.5) * (max(vyp, z0) - max(vym, z0));
+            const RT gz = RT(0.5) * (max(vzp, z0) - max(vzm, z0));
+            const RT ux = *at32(u, n), uy = *at32(u + ld, n), uz = *at32(u + 2 * ld, n);
+            const uint32_t old = atomicAdd(nodeword + n, NW_CNT_ONE);
+            const int slot = (int)(old >> 24);
+            const int e = (i << kp.ent_shift) | j;
+            if (slot < kp.cap && j < (1 << kp.ent_shift)) {
+                ids[(size_t)slot * ld + n] = e;
+                RT* w4 = vals + 4 * (size_t)e;
+                w4[0] = rr;
+                w4[1] = gx;
+                w4[2] = gy;
+                w4[3] = gz;
+            } else {
+                atomicOr(err, ERR_CAPACITY);
+            }
+            const RT hx = gx * invS, hy = gy * invS, hz = gz * invS;
+            acc[3] += uy * hz - uz * hy;
+            acc[4] += uz * hx - ux * hz;
+            acc[5] += ux * hy - uy * hx;
+            if (!in) continue;
+            const RT dh = rr * invS;
+            acc[0] += dh * ux;
+            acc[1] += dh * uy;
+            acc[2] += dh * uz;
+            const RT g2 = hx * hx + hy * hy + hz * hz;
+            const RT il = g2 > RT(0) ? fast_rsqrt(g2) : RT(0);
+            const RT nx_ = hx * il, ny_ = hy * il, nz_ = hz * il;
+            const RT sxx = *at32(sig, n), syy = *at32(sig + ld, n), szz = *at32(sig + 2 * ld, n);
+            const RT sxy_ = *at32(sig + 3 * ld, n), sxz = *at32(sig + 4 * ld, n), syz = *at32(sig + 5 * ld, n);
+            const RT t0 = sxx * nx_ + sxy_ * ny_ + sxz * nz_;
+            const RT t1 = sxy_ * nx_ + syy * ny_ + syz * nz_;
+            const RT t2 = sxz * nx_ + syz * ny_ + szz * nz_;
+            const RT d0 = (RT)mimg(inner, (double)X - s.R[0], (double)kp.nx, kp.per[0]);
+            const RT d1 = (RT)mimg(inner, (double)Y - s.R[1], (double)kp.ny, kp.per[1]);
+            const RT d2 = (RT)mimg(inner, (double)Z - s.R[2], (double)kp.nz, kp.per[2]);
+            const RT al = (RT)kp.alpha * dh;
+            acc[6] += al * (t1 * d2 - t2 * d1);
+            acc[7] += al * (t2 * d0 - t0 * d2);
+            acc[8] += al * (t0 * d1 - t1 * d0);
         }
-        const unsigned long long m = __ballot(cov);
-        const int j = jbase + (int)__popcll(m & below);
-        jbase += (int)__popcll(m);
-        if (!cov) continue;
-        const bool in = v >= RT(0);
-        int X = T.lo[0] + tx, Y = T.lo[1] + ty, Z = T.lo[2] + tz;
-        wrap_coord(X, kp.nx, kp.per[0]);
-        wrap_coord(Y, kp.ny, kp.per[1]);
-        wrap_coord(Z, kp.nz, kp.per[2]);
-        const unsigned n = node_of(kp, X, Y, Z);
-        const RT z0 = RT(0);
-        const RT rr = in ? v : z0;
-        const RT gx = RT(0.5) * (max(vxp, z0) - max(vxm, z0));
-        const RT gy = RT(0.5) * (max(vyp, z0) - max(vym, z0));
-        const RT gz = RT(0.5) * (max(vzp, z0) - max(vzm, z0));
-        const RT ux = *at32(u, n), uy = *at32(u + ld, n), uz = *at32(u + 2 * ld, n);
-        const uint32_t old = atomicAdd(nodeword + n, NW_CNT_ONE);
-        const int slot = (int)(old >> 24);
-        const int e = (i << kp.ent_shift) | j;
-        if (slot < kp.cap && j < (1 << kp.ent_shift)) {
-            ids[(size_t)slot * ld + n] = e;
-            RT* w4 = vals + 4 * (size_t)e;
-            w4[0] = rr;
-            w4[1] = gx;
-            w4[2] = gy;
-            w4[3] = gz;
-        } else {
-            atomicOr(err, ERR_CAPACITY);
-        }
-        const RT hx = gx * invS, hy = gy * invS, hz = gz * invS;
-        acc[3] += uy * hz - uz * hy;
-        acc[4] += uz * hx - ux * hz;
-        acc[5] += ux * hy - uy * hx;
-        if (!in) continue;
-        const RT dh = rr * invS;
-        acc[0] += dh * ux;
-        acc[1] += dh * uy;
-        acc[2] += dh * uz;
-        const RT g2 = hx * hx + hy * hy + hz * hz;
-        const RT il = g2 > RT(0) ? fast_rsqrt(g2) : RT(0);
-        const RT nx_ = hx * il, ny_ = hy * il, nz_ = hz * il;
-        const RT sxx = *at32(sig, n), syy = *at32(sig + ld, n), szz = *at32(sig + 2 * ld, n);
-        const RT sxy_ = *at32(sig + 3 * ld, n), sxz = *at32(sig + 4 * ld, n), syz = *at32(sig + 5 * ld, n);
-        const RT t0 = sxx * nx_ + sxy_ * ny_ + sxz * nz_;
-        const RT t1 = sxy_ * nx_ + syy * ny_ + syz * nz_;
-        const RT t2 = sxz * nx_ + syz * ny_ + szz * nz_;
-        const RT d0 = (RT)min_img((double)X - s.R[0], (double)kp.nx, kp.per[0]);
-        const RT d1 = (RT)min_img((double)Y - s.R[1], (double)kp.ny, kp.per[1]);
-        const RT d2 = (RT)min_img((double)Z - s.R[2], (double)kp.nz, kp.per[2]);
-        const RT al = (RT)kp.alpha * dh;
-        acc[6] += al * (t1 * d2 - t2 * d1);
-        acc[7] += al * (t2 * d0 - t0 * d2);
-        acc[8] += al * (t0 * d1 - t1 * d0);
-    }
+    };
+    if (interior) pass2(std::true_type{});
+    else pass2(std::false_type{});
     for (int a = 0; a < 9; ++a)
         for (int o = 32; o > 0; o >>= 1) acc[a] += __shfl_down(acc[a], o, 64);
     if (lane == 0) {
