@@ -724,37 +724,40 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
         const int d = x - clo[r], b = off[r];
         return (d >= 0 && d < off[r + 1] - b) ? val[b + d] : RT(-2);
     };
-    // the j-th covered node in candidate order fills the cell's entry j
+    // the covered candidates, in candidate order, listed over the consumed front of rowof as
+    // ty | tz << 5 | d << 10 (d: position in the row; tiles are at most 20 nodes long): the
+    // j-th fills the cell's entry j. The write index never passes the candidate being read.
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int ncov = 0;
+    for (int c0 = 0; c0 < total; c0 += 64) {
+        const int c = c0 + lane;
+        const RT v = c < total ? val[c] : RT(-2);
+        bool cov = false;
+        unsigned short code = 0;
+        if (v > RT(-1.5)) {
+            const int yz = rowof[c];
+            const int ty = yz & 255, tz = yz >> 8, r = ty + tz * sy, d = c - off[r], tx = clo[r] + d;
+            cov = v >= RT(0) || at(r, tx - 1) >= RT(0) || at(r, tx + 1) >= RT(0) ||
+                  (ty > 0 && at(r - 1, tx) >= RT(0)) || (ty + 1 < sy && at(r + 1, tx) >= RT(0)) ||
+                  (tz > 0 && at(r - sy, tx) >= RT(0)) || (tz + 1 < sz && at(r + sy, tx) >= RT(0));
+            code = (unsigned short)(ty | tz << 5 | d << 10);
+        }
+        const unsigned long long m = __ballot(cov);
+        if (cov) rowof[ncov + (int)__popcll(m & below)] = code;
+        ncov += (int)__popcll(m);
+    }
+    __syncthreads();
     RT acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const size_t ld = (size_t)kp.ld;
-    const unsigned long long below = (1ull << lane) - 1ull;
-    int jbase = 0;
     auto pass2 = [&](auto inner) {
-        for (int c0 = 0; c0 < total; c0 += 64) {
-            const int c = c0 + lane;
-            const RT v = c < total ? val[c] : RT(-2);
-            int r = 0, ty = 0, tz = 0, tx = 0;
-            RT vxm = RT(-2), vxp = RT(-2), vym = RT(-2), vyp = RT(-2), vzm = RT(-2), vzp = RT(-2);
-            bool cov = false;
-            if (v > RT(-1.5)) {
-                const int yz = rowof[c];
-                ty = yz & 255;
-                tz = yz >> 8;
-                r = ty + tz * sy;
-                tx = clo[r] + (c - off[r]);
-                vxm = at(r, tx - 1);
-                vxp = at(r, tx + 1);
-                if (ty > 0) vym = at(r - 1, tx);
-                if (ty + 1 < sy) vyp = at(r + 1, tx);
-                if (tz > 0) vzm = at(r - sy, tx);
-                if (tz + 1 < sz) vzp = at(r + sy, tx);
-                cov = v >= RT(0) || vxm >= RT(0) || vxp >= RT(0) || vym >= RT(0) || vyp >= RT(0) ||
-                      vzm >= RT(0) || vzp >= RT(0);
-            }
-            const unsigned long long m = __ballot(cov);
-            const int j = jbase + (int)__popcll(m & below);
-            jbase += (int)__popcll(m);
-            if (!cov) continue;
+        for (int j = lane; j < ncov; j += 64) {
+            const int q = rowof[j];
+            const int ty = q & 31, tz = (q >> 5) & 31, d = q >> 10, r = ty + tz * sy;
+            const int tx = clo[r] + d;
+            const RT v = val[off[r] + d];
+            const RT vxm = at(r, tx - 1), vxp = at(r, tx + 1);
+            const RT vym = ty > 0 ? at(r - 1, tx) : RT(-2), vyp = ty + 1 < sy ? at(r + 1, tx) : RT(-2);
+            const RT vzm = tz > 0 ? at(r - sy, tx) : RT(-2), vzp = tz + 1 < sz ? at(r + sy, tx) : RT(-2);
             const bool in = v >= RT(0);
             int X = T.lo[0] + tx, Y = T.lo[1] + ty, Z = T.lo[2] + tz;
             wrap3(inner, X, Y, Z);
