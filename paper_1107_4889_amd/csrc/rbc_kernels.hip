@@ -844,15 +844,14 @@ __global__ __launch_bounds__(64) void k_map_couple(const RbcState* __restrict__ 
 // ---- S5: Gay-Berne forces and torques (Sec. II E, Eqs. 24-28; App. B) -----------------------
 // F on i = -du/dR R^ - (1/R^2) du/dphi [k - (k.R^) R^], k = H^-1 R_ij, H = A_i + A_j;
 // torques tau_i = (1/R) R_ci x f_k, R_ci = -A_i k, f_k = -(1/R) du/dphi k (lab frame).
-__device__ int gb_pair(const KParams& kp, const double* rij, const double* Ai, const double* Aj,
-                       double smin, double* F, double* ti)
+// (A_i + A_j)^-1 by cofactors
+__device__ __forceinline__ void gb_inverse(const double* Ai, const double* Aj, double* Hi)
 {
     double H[9];
     for (int a = 0; a < 9; ++a) H[a] = Ai[a] + Aj[a];
     const double det = H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
                        H[2] * (H[3] * H[7] - H[4] * H[6]);
     const double id = 1.0 / det;
-    double Hi[9];
     Hi[0] = (H[4] * H[8] - H[5] * H[7]) * id;
     Hi[1] = (H[2] * H[7] - H[1] * H[8]) * id;
     Hi[2] = (H[1] * H[5] - H[2] * H[4]) * id;
@@ -862,6 +861,12 @@ __device__ int gb_pair(const KParams& kp, const double* rij, const double* Ai, c
     Hi[6] = (H[3] * H[7] - H[4] * H[6]) * id;
     Hi[7] = (H[1] * H[6] - H[0] * H[7]) * id;
     Hi[8] = (H[0] * H[4] - H[1] * H[3]) * id;
+}
+
+// one pair given Hi = (A_i + A_j)^-1; returns 1 at rho <= 0 (or coincident centres)
+__device__ int gb_pair(const KParams& kp, const double* rij, const double* Ai, const double* Hi,
+                       double smin, double* F, double* ti)
+{
     const double R = sqrt(rij[0] * rij[0] + rij[1] * rij[1] + rij[2] * rij[2]);
     if (!(R > 0.0)) return 1;
     double rh[3], kap[3];
@@ -1006,11 +1011,15 @@ __device__ __forceinline__ void gay_berne_cell(int k, const RbcState* __restrict
         double r[3];
         for (int a = 0; a < 3; ++a) r[a] = min_img(Ri[a] - st[j].R[a], box_len(kp, a), kp.per[a]);
         if (r[0] * r[0] + r[1] * r[1] + r[2] * r[2] > rcc2) continue;
-        double Aj[9];
+        double Aj[9], Hi[9];
         shape_matrix(kp, st[j].Q, Aj);
-        bad |= gb_pair(kp, r, Ai, Aj, smin_cc, F, tl);
+        gb_inverse(Ai, Aj, Hi);
+        bad |= gb_pair(kp, r, Ai, Hi, smin_cc, F, tl);
     }
     if (kp.wall_particles) {
+        // H^-1 = (A_i + a_w^2 1)^-1 is the same for every wall point
+        double Hw[9];
+        gb_inverse(Ai, Aw, Hw);
         const CandidateRanges& rw = ranges[wv][1];
         for (int e = lane; e < rw.total; e += 64) {
             const int wq = candidate(rw, wcell_ids, e);
@@ -1018,7 +1027,7 @@ __device__ __forceinline__ void gay_berne_cell(int k, const RbcState* __restrict
             for (int a = 0; a < 3; ++a)
                 r[a] = min_img(Ri[a] - (double)wall_xyz[3 * wq + a], box_len(kp, a), kp.per[a]);
             if (r[0] * r[0] + r[1] * r[1] + r[2] * r[2] > rcw2) continue;
-            bad |= gb_pair(kp, r, Ai, Aw, kp.sigmin_wall, F, tl);
+            bad |= gb_pair(kp, r, Ai, Hw, kp.sigmin_wall, F, tl);
         }
     }
     for (int o = 32; o > 0; o >>= 1) {
