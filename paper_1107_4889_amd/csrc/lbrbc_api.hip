@@ -387,11 +387,14 @@ struct lb_ctx_s {
     Geometry geo;
     Layout lay;
     hipStream_t stream = nullptr;
-    // Side stream (default priority) for the Gay-Berne forces, which do not depend on the
-    // per-cell map pass: forked from `stream` after the cell list and joined back before the
-    // kick by events, for large cell counts.
+    // Side stream (default priority) for the cells' own work, for large cell counts: the
+    // Gay-Berne forces (independent of the map pass), then, once the map pass is done, the
+    // kick and, within one lb_step call, the next step's first half and cell list, all
+    // overlapping the stream-collide. Events order the two streams.
     hipStream_t side = nullptr;
-    hipEvent_t ev_cells = nullptr, ev_gb = nullptr;
+    hipEvent_t ev_cells = nullptr, ev_gb = nullptr, ev_map = nullptr;
+    // the current step's first half, cell list and Gay-Berne are already on the side stream
+    bool cells_ahead = false;
     char* base = nullptr;
     void *fA = nullptr, *fB = nullptr;
     // coverage counts all zero (after init and after a fused step, whose stream-collide clears
@@ -428,7 +431,7 @@ constexpr int SIDE_STREAM_MIN_CELLS = 2048;
 void release_side(lb_ctx c)
 {
     if (c->side) (void)hipStreamSynchronize(c->side);
-    for (hipEvent_t* ev : {&c->ev_cells, &c->ev_gb})
+    for (hipEvent_t* ev : {&c->ev_cells, &c->ev_gb, &c->ev_map})
         if (*ev) {
             (void)hipEventDestroy(*ev);
             *ev = nullptr;
@@ -543,7 +546,11 @@ void enqueue_cells_map_couple(lb_ctx c)
     launch_map_couple<RT>(c->cb, c->kp, s);
 }
 
-void enqueue_step(lb_ctx c)
+// One step. With a side stream the cells' work runs there: after the map pass, the kick and,
+// unless this is the last step of the call (`last`), the next step's first half, cell list
+// and Gay-Berne forces, all while the stream-collide runs; the map pass waits for the cell
+// list. The last step joins the side stream back, so a call leaves whole steps behind.
+void enqueue_step(lb_ctx c, bool last)
 {
     hipStream_t s = c->stream;
     const KParams& kp = c->kp;
@@ -561,14 +568,16 @@ void enqueue_step(lb_ctx c)
         const bool forked = c->nrbc > 0 && c->side;
         if (c->nrbc > 0) {
             // rb1 + cell list, map + interpolation (which writes F^hyd, T^hyd and the gather
-            // records), Gay-Berne, kick. Forked: Gay-Berne on `side` after the cell list,
-            // overlapping the map pass and stream-collide; the kick waits for it.
-            launch_rb1_cell_list(c->cb, kp, s);
-            if (forked) {
+            // records), Gay-Berne, kick
+            if (!forked) {
+                launch_rb1_cell_list(c->cb, kp, s);
+            } else if (!c->cells_ahead) {
+                launch_rb1_cell_list(c->cb, kp, s);
                 (void)hipEventRecord(c->ev_cells, s);
                 (void)hipStreamWaitEvent(c->side, c->ev_cells, 0);
                 launch_gay_berne(c->cb, kp, c->side);
-                (void)hipEventRecord(c->ev_gb, c->side);
+            } else {
+                (void)hipStreamWaitEvent(s, c->ev_cells, 0);
             }
             if (!sc_clears || !c->counts_clean)
                 launch_clear_counts(c->cb.nodeword, kp.N, c->cb.ovf, c->segs(), c->nseg(), kp.nx, kp.ny, s);
@@ -576,6 +585,18 @@ void enqueue_step(lb_ctx c)
             if (!forked) {
                 launch_gay_berne(c->cb, kp, s);
                 launch_rb_second_half(c->cb, kp, s);
+            } else {
+                (void)hipEventRecord(c->ev_map, s);
+                (void)hipStreamWaitEvent(c->side, c->ev_map, 0);
+                launch_rb_second_half(c->cb, kp, c->side);
+                c->cells_ahead = !last;
+                if (!last) {
+                    launch_rb1_cell_list(c->cb, kp, c->side);
+                    (void)hipEventRecord(c->ev_cells, c->side);
+                    launch_gay_berne(c->cb, kp, c->side);
+                } else {
+                    (void)hipEventRecord(c->ev_gb, c->side);
+                }
             }
         }
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -602,10 +623,7 @@ void enqueue_step(lb_ctx c)
             launch_wss<RT>(c->at<void>(c->lay.sig), c->at<long long>(c->lay.wn_node),
                            c->at<double>(c->lay.wn_nrm), (int)c->geo.wn_node.size(), kp, nullptr,
                            c->at<double>(c->lay.wss_acc), 1, s);
-        if (forked) {
-            (void)hipStreamWaitEvent(s, c->ev_gb, 0);
-            launch_rb_second_half(c->cb, kp, s);
-        }
+        if (forked && last) (void)hipStreamWaitEvent(s, c->ev_gb, 0);
     });
     if (c->wss_on) c->wss_count++;
     c->counts_clean = sc_clears;
@@ -842,7 +860,7 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
     if (err & ERR_OVERLAP) return init_fail(c, LB_EOVERLAP, "Gay-Berne pair at rho <= 0 in the initial state");
     if (n_rbc >= SIDE_STREAM_MIN_CELLS) {
         e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
-        for (hipEvent_t* ev : {&c->ev_cells, &c->ev_gb})
+        for (hipEvent_t* ev : {&c->ev_cells, &c->ev_gb, &c->ev_map})
             if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
         if (e != hipSuccess) {
             release_side(c);
@@ -861,7 +879,7 @@ lb_status lb_step(lb_ctx c, int nsteps)
         (void)hipEventRecord(c->step_t0, c->stream);
         c->step_t0_set = true;
     }
-    for (int k = 0; k < nsteps; ++k) enqueue_step(c);
+    for (int k = 0; k < nsteps; ++k) enqueue_step(c, k + 1 == nsteps);
     if (c->timing && nsteps > 0) {
         (void)hipEventRecord(c->step_t1, c->stream);
         c->timed_steps += nsteps;
@@ -894,7 +912,7 @@ lb_status lb_batch_step(lb_ctx* ctxs, const int* nsteps, int n)
     } else {
         for (int k = 0; k < most; ++k)
             for (int i = 0; i < n; ++i)
-                if (k < nsteps[i]) enqueue_step(ctxs[i]);
+                if (k < nsteps[i]) enqueue_step(ctxs[i], k + 1 == nsteps[i]);
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? LB_OK : LB_EHIP;
