@@ -42,6 +42,8 @@ struct Geometry {
                                      // kept only when under SEG_LIST_MAX_FRACTION of all segments
     int ncell[3] = {1, 1, 1};
     double cedge[3] = {1, 1, 1};
+    int wncell[3] = {1, 1, 1};        // grid of the wall points, edge >= the cell-wall cut-off
+    double wcedge[3] = {1, 1, 1};
     double rc = 0;
     std::vector<int> wcell_off, wcell_ids;
     int tile_max = 0;
@@ -273,16 +275,25 @@ std::string build_geometry(const lb_config& c, const uint8_t* solid, int n_rbc, 
         g.ncell[a] = m;
         g.cedge[a] = (double)L[a] / m;
     }
-    const int nc = g.ncell[0] * g.ncell[1] * g.ncell[2];
+    // wall points in a grid of their own: its edge bounds only the cell-wall cut-off, so the
+    // 27 neighbour cells of a cell centre hold about three times fewer points than the cell
+    // grid's would
+    for (int a = 0; a < 3; ++a) {
+        int m = (int)std::floor(L[a] / rc_cw);
+        if (m < 1) m = 1;
+        g.wncell[a] = m;
+        g.wcedge[a] = (double)L[a] / m;
+    }
+    const int nc = g.wncell[0] * g.wncell[1] * g.wncell[2];
     const int nwall = (int)g.wall_xyz.size() / 3;
     std::vector<int> cnt(nc, 0), wc(nwall);
     auto cell_of = [&](double v, int a) {
-        int q = (int)std::floor(v / g.cedge[a]);
-        return std::min(std::max(q, 0), g.ncell[a] - 1);
+        int q = (int)std::floor(v / g.wcedge[a]);
+        return std::min(std::max(q, 0), g.wncell[a] - 1);
     };
     for (int k = 0; k < nwall; ++k) {
         wc[k] = cell_of(g.wall_xyz[3 * k], 0) +
-                g.ncell[0] * (cell_of(g.wall_xyz[3 * k + 1], 1) + g.ncell[1] * cell_of(g.wall_xyz[3 * k + 2], 2));
+                g.wncell[0] * (cell_of(g.wall_xyz[3 * k + 1], 1) + g.wncell[1] * cell_of(g.wall_xyz[3 * k + 2], 2));
         cnt[wc[k]]++;
     }
     g.wcell_off.assign(nc + 1, 0);
@@ -363,7 +374,7 @@ Layout layout(const lb_config& c, const Geometry& g, int n_rbc)
     L.cell_part = take((nc + 4095) / 4096 * 4);
     L.cell_ids = take(n_rbc * 4);
     L.wall_xyz = take(nwall * 3 * 4);
-    L.wcell_off = take((nc + 1) * 4);
+    L.wcell_off = take(((size_t)g.wncell[0] * g.wncell[1] * g.wncell[2] + 1) * 4);
     L.wcell_ids = take(std::max<size_t>(nwall, 1) * 4);
     L.wn_node = take(nwn * 8);
     L.wn_nrm = take(nwn * 3 * 8);
@@ -755,6 +766,8 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
         kp.axes[a] = C.axes[a];
         kp.ncell[a] = g.ncell[a];
         kp.cedge[a] = g.cedge[a];
+        kp.wncell[a] = g.wncell[a];
+        kp.wcedge[a] = g.wcedge[a];
     }
     kp.gammaT = C.gammaT; kp.gammaR = C.gammaR; kp.alpha = C.alpha; kp.mass = C.mass;
     kp.vort_scale = C.vort_scale;

@@ -67,6 +67,8 @@ struct KParams {
     int nrbc;
     int ncell[3];
     double cedge[3];
+    int wncell[3];    // grid of the wall points (edge >= rc_wall)
+    double wcedge[3];
     double rc;        // cell-list cut-off (bounds every pair kind)
     double rc_pair;   // cell-cell Gay-Berne cut-off bound
     double rc_wall;   // cell-wall Gay-Berne cut-off bound

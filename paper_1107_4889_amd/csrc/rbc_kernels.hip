@@ -724,40 +724,37 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
         const int d = x - clo[r], b = off[r];
         return (d >= 0 && d < off[r + 1] - b) ? val[b + d] : RT(-2);
     };
-    // the covered candidates, in candidate order, listed over the consumed front of rowof as
-    // ty | tz << 5 | d << 10 (d: position in the row; tiles are at most 20 nodes long): the
-    // j-th fills the cell's entry j. The write index never passes the candidate being read.
-    const unsigned long long below = (1ull << lane) - 1ull;
-    int ncov = 0;
-    for (int c0 = 0; c0 < total; c0 += 64) {
-        const int c = c0 + lane;
-        const RT v = c < total ? val[c] : RT(-2);
-        bool cov = false;
-        unsigned short code = 0;
-        if (v > RT(-1.5)) {
-            const int yz = rowof[c];
-            const int ty = yz & 255, tz = yz >> 8, r = ty + tz * sy, d = c - off[r], tx = clo[r] + d;
-            cov = v >= RT(0) || at(r, tx - 1) >= RT(0) || at(r, tx + 1) >= RT(0) ||
-                  (ty > 0 && at(r - 1, tx) >= RT(0)) || (ty + 1 < sy && at(r + 1, tx) >= RT(0)) ||
-                  (tz > 0 && at(r - sy, tx) >= RT(0)) || (tz + 1 < sz && at(r + sy, tx) >= RT(0));
-            code = (unsigned short)(ty | tz << 5 | d << 10);
-        }
-        const unsigned long long m = __ballot(cov);
-        if (cov) rowof[ncov + (int)__popcll(m & below)] = code;
-        ncov += (int)__popcll(m);
-    }
-    __syncthreads();
+    // the j-th covered node in candidate order fills the cell's entry j
     RT acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const size_t ld = (size_t)kp.ld;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int jbase = 0;
     auto pass2 = [&](auto inner) {
-        for (int j = lane; j < ncov; j += 64) {
-            const int q = rowof[j];
-            const int ty = q & 31, tz = (q >> 5) & 31, d = q >> 10, r = ty + tz * sy;
-            const int tx = clo[r] + d;
-            const RT v = val[off[r] + d];
-            const RT vxm = at(r, tx - 1), vxp = at(r, tx + 1);
-            const RT vym = ty > 0 ? at(r - 1, tx) : RT(-2), vyp = ty + 1 < sy ? at(r + 1, tx) : RT(-2);
-            const RT vzm = tz > 0 ? at(r - sy, tx) : RT(-2), vzp = tz + 1 < sz ? at(r + sy, tx) : RT(-2);
+        for (int c0 = 0; c0 < total; c0 += 64) {
+            const int c = c0 + lane;
+            const RT v = c < total ? val[c] : RT(-2);
+            int r = 0, ty = 0, tz = 0, tx = 0;
+            RT vxm = RT(-2), vxp = RT(-2), vym = RT(-2), vyp = RT(-2), vzm = RT(-2), vzp = RT(-2);
+            bool cov = false;
+            if (v > RT(-1.5)) {
+                const int yz = rowof[c];
+                ty = yz & 255;
+                tz = yz >> 8;
+                r = ty + tz * sy;
+                tx = clo[r] + (c - off[r]);
+                vxm = at(r, tx - 1);
+                vxp = at(r, tx + 1);
+                if (ty > 0) vym = at(r - 1, tx);
+                if (ty + 1 < sy) vyp = at(r + 1, tx);
+                if (tz > 0) vzm = at(r - sy, tx);
+                if (tz + 1 < sz) vzp = at(r + sy, tx);
+                cov = v >= RT(0) || vxm >= RT(0) || vxp >= RT(0) || vym >= RT(0) || vyp >= RT(0) ||
+                      vzm >= RT(0) || vzp >= RT(0);
+            }
+            const unsigned long long m = __ballot(cov);
+            const int j = jbase + (int)__popcll(m & below);
+            jbase += (int)__popcll(m);
+            if (!cov) continue;
             const bool in = v >= RT(0);
             int X = T.lo[0] + tx, Y = T.lo[1] + ty, Z = T.lo[2] + tz;
             wrap3(inner, X, Y, Z);
@@ -908,12 +905,12 @@ __device__ __forceinline__ void shape_matrix(const KParams& kp, const double* Q,
 // Neighbour cell `q` (0..26, dx fastest) of cell coordinates cc; -1 when it does not exist
 // (outside a non-periodic face). An axis with fewer than three cells lists each of its
 // cells once (offset index d -> cell d).
-__device__ __forceinline__ int neighbour_cell(const KParams& kp, const int cc[3], int q)
+__device__ __forceinline__ int neighbour_cell(const KParams& kp, const int* ncell, const int cc[3], int q)
 {
     const int d[3] = {q % 3, (q / 3) % 3, q / 9};
     int v[3];
     for (int a = 0; a < 3; ++a) {
-        const int m = kp.ncell[a];
+        const int m = ncell[a];
         if (m < 3) {
             if (d[a] >= m) return -1;
             v[a] = d[a];
@@ -926,7 +923,7 @@ __device__ __forceinline__ int neighbour_cell(const KParams& kp, const int cc[3]
             v[a] = x;
         }
     }
-    return v[0] + kp.ncell[0] * (v[1] + kp.ncell[1] * v[2]);
+    return v[0] + ncell[0] * (v[1] + ncell[1] * v[2]);
 }
 
 // Flattened candidates of the 27 neighbour cells: lanes 0..26 hold one cell's CSR range, an
@@ -938,13 +935,13 @@ struct CandidateRanges {
     int total;
 };
 
-__device__ __forceinline__ void gather_ranges(const int* __restrict__ off, const int* cells_of_lane,
-                                              int lane, CandidateRanges& cr)
+__device__ __forceinline__ void gather_ranges(const int* __restrict__ off, int cell_of_lane, int lane,
+                                              CandidateRanges& cr)
 {
     int cnt = 0, base = 0;
-    if (lane < 27 && cells_of_lane[lane] >= 0) {
-        base = off[cells_of_lane[lane]];
-        cnt = off[cells_of_lane[lane] + 1] - base;
+    if (lane < 27 && cell_of_lane >= 0) {
+        base = off[cell_of_lane];
+        cnt = off[cell_of_lane + 1] - base;
     }
     int incl = cnt;
     for (int o = 1; o < 32; o <<= 1) {
@@ -984,17 +981,23 @@ __device__ __forceinline__ void gay_berne_cell(int k, const RbcState* __restrict
                                                const KParams& kp, unsigned* err)
 {
     __shared__ CandidateRanges ranges[4][2];
-    __shared__ int cells[4][27];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int i = order[k];
     const double* Ri = st[i].R;
     const double* Qi = st[i].Q;
     int cc[3];
     for (int a = 0; a < 3; ++a) cc[a] = cell_coord(kp, a, Ri[a]);
-    if (lane < 27) cells[wv][lane] = neighbour_cell(kp, cc, lane);
-    __builtin_amdgcn_wave_barrier();
-    gather_ranges(cell_off, cells[wv], lane, ranges[wv][0]);
-    if (kp.wall_particles) gather_ranges(wcell_off, cells[wv], lane, ranges[wv][1]);
+    gather_ranges(cell_off, lane < 27 ? neighbour_cell(kp, kp.ncell, cc, lane) : -1, lane, ranges[wv][0]);
+    if (kp.wall_particles) {
+        // wall points are binned in their own grid, of edge at least the cell-wall cut-off
+        int wc[3];
+        for (int a = 0; a < 3; ++a) {
+            wc[a] = (int)floor(Ri[a] / kp.wcedge[a]);
+            wc[a] = wc[a] < 0 ? 0 : (wc[a] >= kp.wncell[a] ? kp.wncell[a] - 1 : wc[a]);
+        }
+        gather_ranges(wcell_off, lane < 27 ? neighbour_cell(kp, kp.wncell, wc, lane) : -1, lane,
+                      ranges[wv][1]);
+    }
     __builtin_amdgcn_wave_barrier();
     double Ai[9], Aw[9];
     shape_matrix(kp, Qi, Ai);
@@ -1048,7 +1051,9 @@ __device__ __forceinline__ void gay_berne_cell(int k, const RbcState* __restrict
     }
 }
 
-__global__ __launch_bounds__(256) void k_gay_berne(const RbcState* __restrict__ st,
+// blocks of one wavefront: on the side stream they fit into whatever slots the concurrent
+// map pass and stream-collide leave
+__global__ __launch_bounds__(64) void k_gay_berne(const RbcState* __restrict__ st,
                                                    RbcCouple* __restrict__ cp,
                                                    const int* __restrict__ order,
                                                    const int* __restrict__ cell_off,
@@ -1058,7 +1063,7 @@ __global__ __launch_bounds__(256) void k_gay_berne(const RbcState* __restrict__ 
                                                    const int* __restrict__ wcell_ids, KParams kp,
                                                    unsigned* err)
 {
-    const int k = xcd_chunk_index(4) + (int)(threadIdx.x >> 6);
+    const int k = xcd_chunk_index(1);
     if (k < kp.nrbc)
         gay_berne_cell(k, st, cp, order, cell_off, cell_ids, wall_xyz, wcell_off, wcell_ids, kp, err);
 }
@@ -1297,7 +1302,7 @@ void launch_map_couple(const CellBuffers& b, const KParams& kp, hipStream_t st)
 
 void launch_gay_berne(const CellBuffers& b, const KParams& kp, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_gay_berne, dim3(grid8(kp.nrbc, 4)), dim3(256), 0, st, b.st, b.cp,
+    hipLaunchKernelGGL(k_gay_berne, dim3(grid8(kp.nrbc, 1)), dim3(64), 0, st, b.st, b.cp,
                        b.cell_ids, b.cell_off, b.cell_ids, b.wall_xyz, b.wcell_off, b.wcell_ids,
                        kp, b.err);
 }
