@@ -371,7 +371,7 @@ Layout layout(const lb_config& c, const Geometry& g, int n_rbc)
     L.cellid = take(n_rbc * 4);
     L.cell_cnt = take(nc * 4);
     L.cell_off = take((nc + 1) * 4);
-    L.cell_part = take((nc + 4095) / 4096 * 4);
+    L.cell_part = take((nc + CELL_SCAN_CHUNK - 1) / CELL_SCAN_CHUNK * 4);
     L.cell_ids = take(n_rbc * 4);
     L.wall_xyz = take(nwall * 3 * 4);
     L.wcell_off = take(((size_t)g.wncell[0] * g.wncell[1] * g.wncell[2] + 1) * 4);

@@ -34,6 +34,9 @@ void launch_wss(const void* sig, const long long* wn_node, const double* wn_nrm,
                 const KParams& kp, double* wss, double* acc, int accumulate, hipStream_t st);
 
 // per-cell kernels (rbc_kernels.hip)
+// cell counts per block of the multi-block cell-list scan (256 threads, four counts each)
+constexpr int CELL_SCAN_CHUNK = 1024;
+
 struct CellBuffers {
     RbcState* st;
     RbcCouple* cp;
@@ -41,7 +44,7 @@ struct CellBuffers {
     int* cellid;          // [nrbc]
     int* cell_cnt;        // [ncells]
     int* cell_off;        // [ncells + 1]
-    int* cell_part;       // [ceil(ncells / 4096)] chunk totals of the multi-block scan
+    int* cell_part;       // [ceil(ncells / CELL_SCAN_CHUNK)] chunk totals of the multi-block scan
     int* cell_ids;        // [nrbc]
     const int* wall_xyz;  // [3 * nwall]
     const int* wcell_off; // [ncells + 1]

@@ -118,12 +118,14 @@ __global__ __launch_bounds__(256) void k_rb1_bin(RbcState* __restrict__ st, int*
     bin_cell(st, cellid, cnt, kp, i);
 }
 
-// exclusive scan of n ints in one block of 1024 threads, 4096 values per round (each thread
-// four consecutive values, so the loads are coalesced); also clears `cnt`
-// One round of the exclusive scan of the cell counts over SCAN_CHUNK entries from `base`
-// (1024 threads, four consecutive entries each), offset by `carry`; writes the offsets,
-// clears the counts and returns the round's total.
-constexpr int SCAN_CHUNK = 4096;
+// Exclusive scan of the cell counts (also clears them). One round covers SCAN_CHUNK entries
+// from `base` (SCAN_THREADS threads, four consecutive entries each, so the loads are
+// coalesced), offset by `carry`; it writes the offsets, clears the counts and returns the
+// round's total. Blocks of 256 threads find room beside the concurrent stream-collide.
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_WAVES = SCAN_THREADS / 64;
+constexpr int SCAN_CHUNK = 4 * SCAN_THREADS;
+static_assert(SCAN_CHUNK == CELL_SCAN_CHUNK, "the arena sizes the chunk totals by CELL_SCAN_CHUNK");
 constexpr int SCAN_SINGLE_BLOCK_CHUNKS = 2;
 
 __device__ __forceinline__ int scan_round(int* cnt, int* off, int base, int n, int carry,
@@ -150,7 +152,7 @@ __device__ __forceinline__ int scan_round(int* cnt, int* off, int base, int n, i
     if (lane == 63) wsum[w] = incl;
     __syncthreads();
     int before = 0, round = 0;
-    for (int k = 0; k < 16; ++k) {
+    for (int k = 0; k < SCAN_WAVES; ++k) {
         const int x = wsum[k];
         before += k < w ? x : 0;
         round += x;
@@ -170,22 +172,22 @@ __device__ __forceinline__ int scan_round(int* cnt, int* off, int base, int n, i
 // the whole scan in one block, round after round (small cell grids and the fused launches)
 __device__ __forceinline__ void scan_clear_block(int* cnt, int* off, int n)
 {
-    __shared__ int wsum[16];
+    __shared__ int wsum[SCAN_WAVES];
     int carry = 0;
     for (int base = 0; base < n; base += SCAN_CHUNK) carry += scan_round(cnt, off, base, n, carry, wsum);
     if (threadIdx.x == 0) off[n] = carry;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_clear(int* cnt, int* off, int n)
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_clear(int* cnt, int* off, int n)
 {
     scan_clear_block(cnt, off, n);
 }
 
 // Large cell grids: one block per chunk of SCAN_CHUNK counts. First the chunk totals ...
-__global__ __launch_bounds__(1024) void k_scan_partials(const int* __restrict__ cnt,
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_partials(const int* __restrict__ cnt,
                                                         int* __restrict__ part, int n)
 {
-    __shared__ int wsum[16];
+    __shared__ int wsum[SCAN_WAVES];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int i0 = (int)blockIdx.x * SCAN_CHUNK + 4 * t;
     int v = 0;
@@ -195,17 +197,17 @@ __global__ __launch_bounds__(1024) void k_scan_partials(const int* __restrict__ 
     __syncthreads();
     if (t == 0) {
         int tot = 0;
-        for (int k = 0; k < 16; ++k) tot += wsum[k];
+        for (int k = 0; k < SCAN_WAVES; ++k) tot += wsum[k];
         part[blockIdx.x] = tot;
     }
 }
 
 // ... then each chunk's scan, offset by the totals of the chunks before it (the last block
 // writes off[n])
-__global__ __launch_bounds__(1024) void k_scan_chunks(int* cnt, int* off, const int* __restrict__ part,
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_chunks(int* cnt, int* off, const int* __restrict__ part,
                                                       int n)
 {
-    __shared__ int wsum[16];
+    __shared__ int wsum[SCAN_WAVES];
     __shared__ int carry_s;
     const int b = (int)blockIdx.x, t = threadIdx.x;
     if (t < 64) {
@@ -1153,7 +1155,7 @@ __global__ __launch_bounds__(256) void kf_cells_a(const FusedArgs fa)
     bin_cell(d.b.st, d.b.cellid, d.b.cell_cnt, kp, i);
 }
 
-__global__ __launch_bounds__(1024) void kf_scan(const FusedArgs fa)
+__global__ __launch_bounds__(SCAN_THREADS) void kf_scan(const FusedArgs fa)
 {
     int lb;
     const SlotDesc& d = *fa.slot[fused_slot(fa, lb)];
@@ -1231,11 +1233,11 @@ static void launch_scan_clear(const CellBuffers& b, int nc, hipStream_t st)
 {
     const int nchunk = (nc + SCAN_CHUNK - 1) / SCAN_CHUNK;
     if (nchunk <= SCAN_SINGLE_BLOCK_CHUNKS) {
-        hipLaunchKernelGGL(k_scan_clear, dim3(1), dim3(1024), 0, st, b.cell_cnt, b.cell_off, nc);
+        hipLaunchKernelGGL(k_scan_clear, dim3(1), dim3(SCAN_THREADS), 0, st, b.cell_cnt, b.cell_off, nc);
         return;
     }
-    hipLaunchKernelGGL(k_scan_partials, dim3(nchunk), dim3(1024), 0, st, b.cell_cnt, b.cell_part, nc);
-    hipLaunchKernelGGL(k_scan_chunks, dim3(nchunk), dim3(1024), 0, st, b.cell_cnt, b.cell_off,
+    hipLaunchKernelGGL(k_scan_partials, dim3(nchunk), dim3(SCAN_THREADS), 0, st, b.cell_cnt, b.cell_part, nc);
+    hipLaunchKernelGGL(k_scan_chunks, dim3(nchunk), dim3(SCAN_THREADS), 0, st, b.cell_cnt, b.cell_off,
                        b.cell_part, nc);
 }
 
@@ -1244,12 +1246,12 @@ static void launch_scan_clear(const CellBuffers& b, int nc, hipStream_t st)
 void launch_rb1_cell_list(const CellBuffers& b, const KParams& kp, hipStream_t st)
 {
     const int nc = kp.ncell[0] * kp.ncell[1] * kp.ncell[2];
-    hipLaunchKernelGGL(k_rb1_bin, dim3(nblk(kp.nrbc, 256)), dim3(256), 0, st, b.st, b.cellid,
+    hipLaunchKernelGGL(k_rb1_bin, dim3(nblk(kp.nrbc, 64)), dim3(64), 0, st, b.st, b.cellid,
                        b.cell_cnt, b.ovf, kp);
     launch_scan_clear(b, nc, st);
-    hipLaunchKernelGGL(k_cells_scatter, dim3(nblk(kp.nrbc, 256)), dim3(256), 0, st, b.cellid,
+    hipLaunchKernelGGL(k_cells_scatter, dim3(nblk(kp.nrbc, 64)), dim3(64), 0, st, b.cellid,
                        b.cell_off, b.cell_cnt, b.cell_ids, kp.nrbc);
-    hipLaunchKernelGGL(k_cells_sort, dim3(nblk(nc, 256)), dim3(256), 0, st, b.cell_off,
+    hipLaunchKernelGGL(k_cells_sort, dim3(nblk(nc, 64)), dim3(64), 0, st, b.cell_off,
                        b.cell_ids, b.cell_cnt, nc);
 }
 
@@ -1260,10 +1262,10 @@ void launch_cell_list(const CellBuffers& b, const KParams& kp, hipStream_t st)
     hipLaunchKernelGGL(k_cells_bin, dim3(nblk(kp.nrbc, 256)), dim3(256), 0, st, b.st, b.cellid,
                        b.cell_cnt, kp);
     launch_scan_clear(b, nc, st);
-    hipLaunchKernelGGL(k_cells_scatter, dim3(nblk(kp.nrbc, 256)), dim3(256), 0, st, b.cellid,
+    hipLaunchKernelGGL(k_cells_scatter, dim3(nblk(kp.nrbc, 64)), dim3(64), 0, st, b.cellid,
                        b.cell_off, b.cell_cnt, b.cell_ids, kp.nrbc);
     // the sort leaves the fill counters at zero for the next call
-    hipLaunchKernelGGL(k_cells_sort, dim3(nblk(nc, 256)), dim3(256), 0, st, b.cell_off,
+    hipLaunchKernelGGL(k_cells_sort, dim3(nblk(nc, 64)), dim3(64), 0, st, b.cell_off,
                        b.cell_ids, b.cell_cnt, nc);
 }
 
@@ -1309,7 +1311,7 @@ void launch_gay_berne(const CellBuffers& b, const KParams& kp, hipStream_t st)
 
 void launch_rb_second_half(const CellBuffers& b, const KParams& kp, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_rb_second_half, dim3(nblk(kp.nrbc, 128)), dim3(128), 0, st, b.st, b.cp, kp);
+    hipLaunchKernelGGL(k_rb_second_half, dim3(nblk(kp.nrbc, 64)), dim3(64), 0, st, b.st, b.cp, kp);
 }
 
 void launch_init_combined(const CellBuffers& b, const KParams& kp, hipStream_t st)
@@ -1344,7 +1346,7 @@ void launch_fused_cells(const FusedArgs& fa, int stage, size_t lds, hipStream_t 
     if (g == 0) return;
     switch (stage) {
     case FS_CELLS_A: hipLaunchKernelGGL(kf_cells_a, dim3(g), dim3(256), 0, st, fa); break;
-    case FS_SCAN: hipLaunchKernelGGL(kf_scan, dim3(g), dim3(1024), 0, st, fa); break;
+    case FS_SCAN: hipLaunchKernelGGL(kf_scan, dim3(g), dim3(SCAN_THREADS), 0, st, fa); break;
     case FS_SCATTER: hipLaunchKernelGGL(kf_scatter, dim3(g), dim3(256), 0, st, fa); break;
     case FS_SORT: hipLaunchKernelGGL(kf_sort, dim3(g), dim3(256), 0, st, fa); break;
     case FS_MAP: hipLaunchKernelGGL((kf_map<RT>), dim3(g), dim3(64), lds, st, fa); break;
