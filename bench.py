@@ -348,6 +348,94 @@ def observables(args):
     print(json.dumps(line), flush=True)
 
 
+def mobility(args):
+    """Single-cell mobilities (Sec. IV): a lone cell in a periodic 60^3 box of quiescent plasma
+    (no viscosity contrast, M = 10, I = 1000, shape-function radii 2, 2, 1 with the short one
+    on the symmetry axis), driven by a constant external force along the symmetry axis
+    (frontal) or along a long axis (side-wise), or spun by a constant torque about the same
+    two axes. A uniform body force of the opposite total acts on the plasma, so the total
+    momentum stays zero. The steady mobilities, relative to the mean plasma velocity, are
+    fitted as linear in 1/(M gT) (1/(I gR)): the intercepts are the mobilities the coupling
+    keeps at infinite friction, mu_T = 1/(M gT^mesh) and 1/(I gR^mesh)."""
+    import numpy as np
+    import torch
+
+    from paper_1107_4889_amd import lbrbc
+
+    n = 60
+    solid = np.zeros((n, n, n), dtype=np.uint8)
+    R0 = np.array([[n / 2.0, n / 2.0, n / 2.0]])
+    Q0 = np.eye(3).reshape(1, 9)
+    base = dict(nx=n, ny=n, nz=n, periodic=(1, 1, 1), tau0=1.0, wall_particles=0, delta_visc=0.0,
+                xi=(2.0, 2.0, 1.0), mass=10.0, inertia=(1000.0, 1000.0, 1000.0), storage="f64")
+    # translation: gT swept at gR = 0.01; rotation: gR swept at gT = 0.01 (the explicit
+    # rotational exchange, I gR against the plasma inside a support one node thick across the
+    # disc, is the first to lose stability)
+    sweeps = {"frontal": [0.01, 0.02, 0.05, 0.1], "side-wise": [0.01, 0.02, 0.05, 0.1],
+              "spin_short_axis": [0.005, 0.01, 0.02, 0.05], "spin_long_axis": [0.005, 0.01, 0.02, 0.05]}
+    F, T = 1e-4, 1e-2
+    steps = args.mob_steps
+    out = {}
+    for kind, axis in (("frontal", 2), ("side-wise", 0), ("spin_short_axis", 2), ("spin_long_axis", 0)):
+        rows = []
+        spin = kind.startswith("spin")
+        for g in sweeps[kind]:
+            cfg = dict(base, gammaT=0.01 if spin else g, gammaR=g if spin else 0.01)
+            e = np.zeros(3)
+            e[axis] = 1.0
+            if spin:
+                cfg["ext_torque"] = tuple(T * e)
+            else:
+                cfg["ext_force"] = tuple(F * e)
+                cfg["g_ext"] = tuple(-F * e / n ** 3)
+            sim = lbrbc.Simulation(cfg, solid, R=R0, Q=Q0)
+            t0 = time.perf_counter()
+            vals = []
+            try:
+                for part in (steps // 2, steps - steps // 2):
+                    sim.lb_step(part)
+                    o = sim.lb_observe()
+                    Rg, Qg, Vg, Og = sim.rbc_get_state()
+                    if spin:
+                        vals.append(float(Og[0][axis]) / T)
+                    else:
+                        ubar = np.array(o.momentum) / o.mass
+                        vals.append(float(Vg[0][axis] - ubar[axis]) / F)
+            except lbrbc.LbError as err:
+                print(f"[mobility] {kind} gamma={g}: {err}", file=sys.stderr, flush=True)
+                rows.append({"gamma": g, "unstable": True})
+                del sim
+                continue
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            x = 1.0 / (1000.0 * g) if spin else 1.0 / (10.0 * g)
+            rows.append({"gamma": g, "x": x, "mobility": vals[-1], "mobility_half_steps": vals[0],
+                         "seconds": round(dt, 2)})
+            print(f"[mobility] {kind} gamma={g}: {vals[0]:.5g} -> {vals[-1]:.5g} ({dt:.1f} s)",
+                  file=sys.stderr, flush=True)
+            del sim
+        rows_ok = [r for r in rows if not r.get("unstable")]
+        rec = {"runs": rows}
+        if len(rows_ok) >= 2:
+            xs = np.array([r["x"] for r in rows_ok])
+            ys = np.array([r["mobility"] for r in rows_ok])
+            slope, icpt = np.polyfit(xs, ys, 1)
+            rec.update(fit_slope=float(slope), intercept=float(icpt))
+            if spin:
+                rec["gammaR_mesh"] = float(1.0 / (1000.0 * icpt)) if icpt > 0 else None
+        out[kind] = rec
+    line = {
+        "metric": "single-cell mobilities at infinite coupling (Sec. IV)",
+        "config": {"workload": f"lone cell, periodic {n}^3 plasma at rest, T0=1.0 (nu=1/6), Delta=0, "
+                               f"xi=(2,2,1), M=10, I=1000; force {F} (gR=0.01), torque {T} (gT=0.01); "
+                               f"{steps} steps per run; FP64 storage"},
+        "paper_printed": {"frontal": 6.6, "side-wise": 10.3, "gammaR_mesh_short_axis": 1 / 44.0,
+                          "gammaR_mesh_long_axis": 1 / 38.0},
+        "results": out,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -369,6 +457,9 @@ def main():
     ap.add_argument("--observables", action="store_true",
                     help="flow rate, eta_app, eta_rel, u_z profile, WSS near steady state")
     ap.add_argument("--obs-steps", type=int, default=40000)
+    ap.add_argument("--mobility", action="store_true",
+                    help="single-cell translational and rotational mobilities vs the coupling rates")
+    ap.add_argument("--mob-steps", type=int, default=20000)
     ap.add_argument("--no-serving", action="store_true",
                     help="default run: skip the request-stream leg (p50/p99 latency)")
     ap.add_argument("--budget-gib", type=float, default=64.0)
@@ -403,6 +494,9 @@ def main():
         return
     if args.observables:
         observables(args)
+        return
+    if args.mobility:
+        mobility(args)
         return
 
     from paper_1107_4889_amd import lbrbc

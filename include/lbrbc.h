@@ -86,6 +86,10 @@ typedef struct lb_config {
     int bf16_nearest;     /* BF16 storage rounding: 0 = stochastic (unbiased; the random bits are
                              a hash of node, direction and value, so results stay deterministic);
                              1 = round to nearest even, which loses the increments of slow flows */
+    double ext_force[3];  /* constant external force on every cell, lab frame, added to the
+                             combined force (drag experiments of Sec. IV; 0 = none) */
+    double ext_torque[3]; /* constant external torque on every cell, body frame, added to the
+                             combined torque (spin experiments of Sec. IV; 0 = none) */
 } lb_config;
 
 typedef struct lb_rbc {

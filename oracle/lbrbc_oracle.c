@@ -838,7 +838,9 @@ static int collide_all(orc_sim* s, int brute)
  * translational/rotational friction carries the mass and inertia (F = -M gT (V - u~),
  * T^A = -gR I (Omega - Q^T w~)), as the integrator's M gT u~ and I gR w~ terms require;
  * and tau^comb includes the elongational torque Q^T T^S, without which alpha would have
- * no effect on the cell. */
+ * no effect on the cell. A constant external force (lab) and torque (body) on every cell,
+ * as a drag experiment applies (Sec. IV, single-cell mobilities), add to the mechanical
+ * ones. */
 static void combined(const orc_sim* s, int i, double Fc[3], double Tc[3])
 {
     const orc_params* P = &s->P;
@@ -847,8 +849,9 @@ static void combined(const orc_sim* s, int i, double Fc[3], double Tc[3])
     matT_vec(s->Q + 9 * i, s->wt + 3 * i, wb);
     matT_vec(s->Q + 9 * i, s->TS + 3 * i, tsb);
     for (a = 0; a < 3; ++a) {
-        Fc[a] = s->Fmech[3 * i + a] + P->gammaT * P->mass * s->ut[3 * i + a];
-        Tc[a] = s->Tmech[3 * i + a] + tsb[a] + P->gammaR * P->inertia[a] * P->vort_scale * wb[a];
+        Fc[a] = s->Fmech[3 * i + a] + P->ext_force[a] + P->gammaT * P->mass * s->ut[3 * i + a];
+        Tc[a] = s->Tmech[3 * i + a] + P->ext_torque[a] + tsb[a] +
+                P->gammaR * P->inertia[a] * P->vort_scale * wb[a];
     }
 }
 
@@ -1174,8 +1177,11 @@ orc_sim* orc_create(const orc_params* prm, const uint8_t* solid, int n_rbc, cons
             *status = st;
             return NULL;
         }
-        memcpy(s->Fcomb, s->Fmech, sizeof(double) * 3 * (size_t)n_rbc);
-        memcpy(s->Tcomb, s->Tmech, sizeof(double) * 3 * (size_t)n_rbc);
+        for (int i = 0; i < n_rbc; ++i)
+            for (int a = 0; a < 3; ++a) {
+                s->Fcomb[3 * i + a] = s->Fmech[3 * i + a] + s->P.ext_force[a];
+                s->Tcomb[3 * i + a] = s->Tmech[3 * i + a] + s->P.ext_torque[a];
+            }
     }
     *status = ORC_OK;
     return s;

@@ -44,6 +44,8 @@ typedef struct orc_params {
     int wall_particles;   /* 1: wall mesh points repel the cells */
     int open_z;           /* 1: z faces are pressure boundaries (inlet z=0, outlet z=nz-1) */
     double rho_in, rho_out;
+    double ext_force[3];  /* external force on every cell, lab frame (drag experiments) */
+    double ext_torque[3]; /* external torque on every cell, body frame */
 } orc_params;
 
 typedef struct orc_sim orc_sim;

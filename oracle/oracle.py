@@ -41,6 +41,7 @@ class Params(ctypes.Structure):
         ("a_wall", ctypes.c_double), ("sigmin_wall", ctypes.c_double),
         ("wall_particles", ctypes.c_int),
         ("open_z", ctypes.c_int), ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double),
+        ("ext_force", ctypes.c_double * 3), ("ext_torque", ctypes.c_double * 3),
     ]
 
 
@@ -106,7 +107,8 @@ def make_params(cfg: dict) -> Params:
                     g_ext=(0.0, 0.0, 0.0), gammaT=0.1, gammaR=0.1, alpha=0.04, mass=10.0,
                     inertia=(1000.0, 1000.0, 1000.0), vort_scale=1.0, xi=(4.0, 4.0, 1.5),
                     axes=(4.0, 4.0, 1.5), eps0=1e-3, a_wall=0.5, sigmin_wall=0.5,
-                    wall_particles=1, open_z=0, rho_in=1.0, rho_out=1.0)
+                    wall_particles=1, open_z=0, rho_in=1.0, rho_out=1.0,
+                    ext_force=(0.0, 0.0, 0.0), ext_torque=(0.0, 0.0, 0.0))
     d = dict(defaults)
     d.update(cfg)
     for k, v in d.items():

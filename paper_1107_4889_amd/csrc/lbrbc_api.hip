@@ -162,6 +162,9 @@ std::string validate(const lb_config& c, int n_rbc)
     if (c.forcing != 0 && c.forcing != 1) return "forcing must be 0 or 1";
     if (c.map_cap < 0 || c.map_cap > CAP_MAX) return "map_cap must be in 0..12";
     if (c.bf16_nearest != 0 && c.bf16_nearest != 1) return "bf16_nearest must be 0 or 1";
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(c.ext_force[a]) || !std::isfinite(c.ext_torque[a]))
+            return "ext_force and ext_torque must be finite";
     if (c.storage == LB_F16 && !(c.f16_scale > 0)) return "f16_scale must be positive";
     if (c.open_z && c.periodic[2]) return "open z faces need a non-periodic z axis";
     if (c.open_z && c.nz < 3) return "open z faces need nz >= 3";
@@ -771,6 +774,10 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
     }
     kp.gammaT = C.gammaT; kp.gammaR = C.gammaR; kp.alpha = C.alpha; kp.mass = C.mass;
     kp.vort_scale = C.vort_scale;
+    for (int a = 0; a < 3; ++a) {
+        kp.ext_force[a] = C.ext_force[a];
+        kp.ext_torque[a] = C.ext_torque[a];
+    }
     kp.eps0 = C.eps0; kp.a_wall = C.a_wall; kp.sigmin_wall = C.sigmin_wall;
     kp.wall_particles = C.wall_particles;
     kp.open_z = C.open_z; kp.rho_in = C.rho_in; kp.rho_out = C.rho_out;

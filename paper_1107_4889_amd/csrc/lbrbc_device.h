@@ -59,6 +59,7 @@ struct KParams {
     int kappa_int;    // kappa if it is an integer in [0, 64], else -1
     double gext[3];
     double gammaT, gammaR, alpha, mass, inertia[3], vort_scale;
+    double ext_force[3], ext_torque[3];   // on every cell: lab force, body torque
     double xi[3], axes[3], eps0, a_wall, sigmin_wall;
     int wall_particles;
     int open_z;

@@ -1071,7 +1071,8 @@ __global__ __launch_bounds__(64) void k_gay_berne(const RbcState* __restrict__ s
 }
 
 // ---- S6: combined force/torque, hydrodynamic force/torque, second half --------------------
-// F^comb = F^mech + gT M u~; tau^comb = tau^mech + Q^T T^S + gR I (s Q^T w~);
+// F^comb = F^mech + F^ext + gT M u~; tau^comb = tau^mech + tau^ext + Q^T T^S + gR I (s Q^T w~)
+// (F^ext lab, tau^ext body: the constant drive of the single-cell drag and spin experiments);
 // F^hyd = -M gT (V - u~); T^hyd = Q [-gR I (Omega - s Q^T w~)] + T^S (lab), with the velocities
 // after the first half (which equal the half-step values within a step).
 // hydro_cell: F^hyd, T^hyd and the gather record of cell i from its interpolation sums in c
@@ -1112,8 +1113,8 @@ __device__ __forceinline__ void kick_cell(RbcState* __restrict__ st, const RbcCo
     matT_vec(s.Q, c.TS, tsb);
     const double eT = exp(-kp.gammaT * 0.5), eR = exp(-kp.gammaR * 0.5);
     for (int a = 0; a < 3; ++a) {
-        s.Fc[a] = c.Fm[a] + kp.gammaT * kp.mass * c.ut[a];
-        s.Tc[a] = c.Tm[a] + tsb[a] + kp.gammaR * kp.inertia[a] * kp.vort_scale * wb[a];
+        s.Fc[a] = c.Fm[a] + kp.ext_force[a] + kp.gammaT * kp.mass * c.ut[a];
+        s.Tc[a] = c.Tm[a] + kp.ext_torque[a] + tsb[a] + kp.gammaR * kp.inertia[a] * kp.vort_scale * wb[a];
         s.V[a] *= eT;
         s.Om[a] *= eR;
         s.V[a] += 0.5 / kp.mass * s.Fc[a];
@@ -1129,13 +1130,13 @@ __global__ __launch_bounds__(128) void k_rb_second_half(RbcState* __restrict__ s
     if (i < kp.nrbc) kick_cell(st, cp, kp, i);
 }
 
-__global__ void k_init_combined(RbcState* __restrict__ st, const RbcCouple* __restrict__ cp, int nrbc)
+__global__ void k_init_combined(RbcState* __restrict__ st, const RbcCouple* __restrict__ cp, KParams kp)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nrbc) return;
+    if (i >= kp.nrbc) return;
     for (int a = 0; a < 3; ++a) {
-        st[i].Fc[a] = cp[i].Fm[a];
-        st[i].Tc[a] = cp[i].Tm[a];
+        st[i].Fc[a] = cp[i].Fm[a] + kp.ext_force[a];
+        st[i].Tc[a] = cp[i].Tm[a] + kp.ext_torque[a];
     }
 }
 
@@ -1316,8 +1317,7 @@ void launch_rb_second_half(const CellBuffers& b, const KParams& kp, hipStream_t 
 
 void launch_init_combined(const CellBuffers& b, const KParams& kp, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_init_combined, dim3(nblk(kp.nrbc, 128)), dim3(128), 0, st, b.st, b.cp,
-                       kp.nrbc);
+    hipLaunchKernelGGL(k_init_combined, dim3(nblk(kp.nrbc, 128)), dim3(128), 0, st, b.st, b.cp, kp);
 }
 
 int fused_blocks(const KParams& kp, int stage)

@@ -394,3 +394,30 @@ def test_integrator_matches_rigid_rotation_and_euler_equation():
     rate = np.unwrap(phis)
     rate = (rate[-1] - rate[0]) / (len(rate) - 1)
     assert rate == pytest.approx((1500 - 1000) / 1000 * 0.01, rel=1e-3)
+
+
+def test_external_force_and_torque_drive_a_free_cell_exactly():
+    # A lone cell without coupling (gT = gR = 0, alpha = 0) and without walls or neighbours:
+    # the combined force and torque are the external ones, applied whole once per step, so
+    # the velocity Verlet steps are exact for the uniform drive (the printed drag and spin
+    # experiments of Sec. IV apply such a constant force or torque).
+    n = 24
+    solid = np.zeros((n, n, n), dtype=np.uint8)
+    F = np.array([1e-3, -2e-3, 5e-4])
+    tau = 0.4                                  # about body axis 3, inertia 1000
+    cfg = dict(nx=n, ny=n, nz=n, periodic=(1, 1, 1), wall_particles=0, gammaT=0.0, gammaR=0.0,
+               alpha=0.0, delta_visc=0.0, xi=(2.0, 2.0, 1.0), ext_force=tuple(F),
+               ext_torque=(0.0, 0.0, tau))
+    R0 = np.array([[11.3, 12.1, 10.7]])
+    o = orc.Oracle(cfg, solid, R=R0, Q=np.eye(3).reshape(1, 9))
+    t = 40
+    assert o.step(t) == 0
+    R, Q, V, Om = o.rbc()
+    assert np.allclose(V[0], F / 10.0 * t, rtol=1e-12)
+    assert np.allclose(R[0], R0[0] + F / (2 * 10.0) * t * t, rtol=1e-12)
+    assert np.allclose(Om[0], [0.0, 0.0, tau / 1000.0 * t], rtol=1e-12, atol=1e-18)
+    ang = tau / (2 * 1000.0) * t * t            # Q' = Q hat(Omega), Omega growing linearly
+    ref = np.array([[math.cos(ang), -math.sin(ang), 0], [math.sin(ang), math.cos(ang), 0], [0, 0, 1]])
+    assert np.allclose(Q[0].reshape(3, 3), ref, atol=1e-12)
+    # the plasma is left at rest: no coupling, no spreading
+    assert np.abs(o.u()).max() < 1e-15
