@@ -290,6 +290,32 @@ def precision(args):
     print(json.dumps(line), flush=True)
 
 
+def cell_free_layer(state, cfg, R_vessel, dz=8.0, sectors=16):
+    """Cell-free layer of a tube from the cell state: each cell's outermost radius is its centre
+    radius plus its ellipsoid's extent along the radial direction, sqrt(n^T Q diag(a^2) Q^T n);
+    the layer is the vessel radius minus the outermost radius of the cells in each slab of
+    `dz` along the axis and each of `sectors` angular sectors. Returns the mean and the
+    minimum over the occupied (slab, sector) bins."""
+    import numpy as np
+
+    Rc, Qc = state[0], state[1].reshape(-1, 3, 3)
+    cx, cy = (cfg["nx"] - 1) / 2.0, (cfg["ny"] - 1) / 2.0
+    d = np.stack([Rc[:, 0] - cx, Rc[:, 1] - cy, np.zeros(len(Rc))], axis=1)
+    r = np.linalg.norm(d, axis=1)
+    nrm = d / np.maximum(r, 1e-12)[:, None]
+    a2 = np.array([4.0, 4.0, 1.5]) ** 2
+    nb = np.einsum("nji,nj->ni", Qc, nrm)                 # radial direction in the body frame
+    outer = r + np.sqrt((nb * nb * a2).sum(axis=1))
+    sl = np.floor(Rc[:, 2] / dz).astype(int)
+    sec = np.floor((np.arctan2(d[:, 1], d[:, 0]) + np.pi) / (2 * np.pi) * sectors).astype(int) % sectors
+    key = sl * sectors + sec
+    top = {}
+    for k, o in zip(key, outer):
+        top[k] = max(top.get(k, 0.0), o)
+    gaps = R_vessel - np.array(list(top.values()))
+    return {"mean": float(gaps.mean()), "min": float(gaps.min())}
+
+
 def observables(args):
     """The tube's observables near steady state: the cell-laden tube and its H = 0 twin run
     for --obs-steps steps; flow rate, apparent and relative viscosity (eta_rel = Q_0 / Q_H),
@@ -310,9 +336,12 @@ def observables(args):
         t0 = time.perf_counter()
         sim.lb_step(n - n // 4)
         sim.lb_wss_accumulate(True)
+        cfl = []
         for k in range(4):
             sim.lb_step(n // 16)
             torch.cuda.synchronize()
+            if len(pl.R):
+                cfl.append(cell_free_layer(sim.rbc_get_state(), cfg, R_vessel=60.0))
             print(f"[observables] {name}: {n - n // 4 + (k + 1) * (n // 16)}/{n} steps", file=sys.stderr,
                   flush=True)
         dt = time.perf_counter() - t0
@@ -335,6 +364,7 @@ def observables(args):
             rec["cell_centre_radial_histogram"] = np.bincount(np.floor(rc).astype(int),
                                                               minlength=int(np.ceil(rc.max())) + 1).tolist()
             rec["cell_centre_r_max"] = float(rc.max())
+            rec["cell_free_layer"] = {k: float(np.mean([c[k] for c in cfl])) for k in cfl[0]}
         out[name] = rec
         del sim
     line = {

@@ -692,26 +692,48 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
         else return min_img(d, L, per);
     };
     RT part = RT(0);
+    // the node words of P1_GROUP candidates are loaded together, then the candidates are
+    // tested one after another (in the same order, so S sums identically)
+    constexpr int P1_GROUP = 4;
     auto pass1 = [&](auto inner) {
-        for (int c = lane; c < total; c += 64) {
-            const int yz = rowof[c];
-            const int ty = yz & 255, tz = yz >> 8, r = ty + tz * sy, tx = clo[r] + (c - off[r]);
-            int X = T.lo[0] + tx, Y = T.lo[1] + ty, Z = T.lo[2] + tz;
-            RT v = RT(-2);
-            const bool inbox = wrap3(inner, X, Y, Z);
-            if (inbox && (nodeword[node_of(kp, X, Y, Z)] & NW_FLUID)) {
-                v = RT(-1);
-                double y[3];
-                const double d0 = mimg(inner, (double)X - s.R[0], (double)kp.nx, kp.per[0]);
-                const double d1 = mimg(inner, (double)Y - s.R[1], (double)kp.ny, kp.per[1]);
-                const double d2 = mimg(inner, (double)Z - s.R[2], (double)kp.nz, kp.per[2]);
-                body_coords_exact(s.Q, d0, d1, d2, y);
-                if (fabs(y[0]) < kp.xi[0] && fabs(y[1]) < kp.xi[1] && fabs(y[2]) < kp.xi[2]) {
-                    v = peskin((RT)y[0] * s0) * peskin((RT)y[1] * s1) * peskin((RT)y[2] * s2);
-                    part += v;
+        for (int c0 = lane; c0 < total; c0 += 64 * P1_GROUP) {
+            int Xg[P1_GROUP], Yg[P1_GROUP], Zg[P1_GROUP];
+            uint32_t wg[P1_GROUP];
+#pragma unroll
+            for (int g = 0; g < P1_GROUP; ++g) {
+                const int c = c0 + 64 * g;
+                wg[g] = 0u;
+                Xg[g] = Yg[g] = Zg[g] = 0;
+                if (c < total) {
+                    const int yz = rowof[c];
+                    const int ty = yz & 255, tz = yz >> 8, r = ty + tz * sy, tx = clo[r] + (c - off[r]);
+                    int X = T.lo[0] + tx, Y = T.lo[1] + ty, Z = T.lo[2] + tz;
+                    if (wrap3(inner, X, Y, Z)) wg[g] = nodeword[node_of(kp, X, Y, Z)];
+                    Xg[g] = X;
+                    Yg[g] = Y;
+                    Zg[g] = Z;
                 }
             }
-            val[c] = v;
+#pragma unroll
+            for (int g = 0; g < P1_GROUP; ++g) {
+                const int c = c0 + 64 * g;
+                if (c >= total) break;
+                const int X = Xg[g], Y = Yg[g], Z = Zg[g];
+                RT v = RT(-2);
+                if (wg[g] & NW_FLUID) {
+                    v = RT(-1);
+                    double y[3];
+                    const double d0 = mimg(inner, (double)X - s.R[0], (double)kp.nx, kp.per[0]);
+                    const double d1 = mimg(inner, (double)Y - s.R[1], (double)kp.ny, kp.per[1]);
+                    const double d2 = mimg(inner, (double)Z - s.R[2], (double)kp.nz, kp.per[2]);
+                    body_coords_exact(s.Q, d0, d1, d2, y);
+                    if (fabs(y[0]) < kp.xi[0] && fabs(y[1]) < kp.xi[1] && fabs(y[2]) < kp.xi[2]) {
+                        v = peskin((RT)y[0] * s0) * peskin((RT)y[1] * s1) * peskin((RT)y[2] * s2);
+                        part += v;
+                    }
+                }
+                val[c] = v;
+            }
         }
     };
     if (interior) pass1(std::true_type{});
