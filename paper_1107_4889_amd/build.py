@@ -10,8 +10,11 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbrbc.so")
 SOURCES = ["lb_kernels.hip", "rbc_kernels.hip", "lbrbc_api.hip"]
 
-# Packed FP32 instructions are disabled for every HIP translation unit.
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+# Packed FP32 instructions are disabled for every HIP translation unit. Multiply-adds are
+# contracted only within one source expression (-ffp-contract=on), so a device function
+# rounds identically wherever it is inlined: the per-context and the fused multi-context
+# kernels of a step give bitwise-equal results.
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument"]
 

@@ -8,11 +8,12 @@
 namespace lbrbc {
 
 template <typename RT>
-static MapPlanes<RT> map_planes(const int* ids, const void* vals, const KParams& kp)
+static MapPlanes<RT> map_planes(const int* ids, const void* vals, uint32_t* cnt, const KParams& kp)
 {
     MapPlanes<RT> mp;
     for (int k = 0; k < CAP_MAX; ++k) mp.ids[k] = ids + (k < kp.cap ? (size_t)k * (size_t)kp.ld : 0);
     mp.vals0 = (const RT*)vals;
+    mp.cnt = cnt;
     return mp;
 }
 
@@ -23,8 +24,8 @@ static MapPlanes<RT> map_planes(const int* ids, const void* vals, const KParams&
 // grad raw) of that cell's j-th covered node, written by the per-cell pass; dhat = raw / S_i.
 // The torque term carries the sign that hands the plasma -T_i of angular momentum.
 //
-// The slot words are read with branch-free loads (unused slots read the node word, already in
-// cache) so that all loads are in flight together; the entry indices, ascending in the cell,
+// The slot words are read with branch-free loads (unused slots read the node's count, already
+// in cache) so that all loads are in flight together; the entry indices, ascending in the cell,
 // are sorted by a network sized to the wave's largest count (4, 8 or 12 slots).
 template <int CN>
 __device__ __forceinline__ void sort_keys(int* key)
@@ -41,14 +42,14 @@ __device__ __forceinline__ void sort_keys(int* key)
 }
 
 template <typename RT, int CN>
-__device__ __forceinline__ void spread_slots(unsigned n, int cnt, const uint32_t* __restrict__ nodeword,
-                                             const MapPlanes<RT>& mp, const Gather<RT>* __restrict__ gat,
-                                             const KParams& kp, RT g[3], RT& theta)
+__device__ __forceinline__ void spread_slots(unsigned n, int cnt, const MapPlanes<RT>& mp,
+                                             const Gather<RT>* __restrict__ gat, const KParams& kp,
+                                             RT g[3], RT& theta)
 {
     int key[CN];
 #pragma unroll
     for (int k = 0; k < CN; ++k) {
-        const int* a = (k < cnt) ? at32(mp.ids[k], n) : reinterpret_cast<const int*>(at32(nodeword, n));
+        const int* a = (k < cnt) ? at32(mp.ids[k], n) : reinterpret_cast<const int*>(at32(mp.cnt, n));
         const int v = *a;
         key[k] = (k < cnt) ? v : INT_MAX;
     }
@@ -73,21 +74,20 @@ __device__ __forceinline__ void spread_slots(unsigned n, int cnt, const uint32_t
 }
 
 template <typename RT>
-__device__ __forceinline__ void spread_at(unsigned n, uint32_t w, const uint32_t* __restrict__ nodeword,
-                                          const MapPlanes<RT>& mp, const Gather<RT>* __restrict__ gat,
-                                          const KParams& kp, RT g[3], RT& theta)
+__device__ __forceinline__ void spread_at(unsigned n, uint32_t count, const MapPlanes<RT>& mp,
+                                          const Gather<RT>* __restrict__ gat, const KParams& kp,
+                                          RT g[3], RT& theta)
 {
     g[0] = (RT)kp.gext[0];
     g[1] = (RT)kp.gext[1];
     g[2] = (RT)kp.gext[2];
     theta = RT(0);
-    int cnt = (int)(w >> 24);
-    if (cnt > kp.cap) cnt = kp.cap;
+    int cnt = (int)min(count, (uint32_t)kp.cap);
     // wave-uniform choice of the slot network
     if (!__any(cnt > 0)) return;
-    if (!__any(cnt > 4)) spread_slots<RT, 4>(n, cnt, nodeword, mp, gat, kp, g, theta);
-    else if (!__any(cnt > 8)) spread_slots<RT, 8>(n, cnt, nodeword, mp, gat, kp, g, theta);
-    else spread_slots<RT, CAP_MAX>(n, cnt, nodeword, mp, gat, kp, g, theta);
+    if (!__any(cnt > 4)) spread_slots<RT, 4>(n, cnt, mp, gat, kp, g, theta);
+    else if (!__any(cnt > 8)) spread_slots<RT, 8>(n, cnt, mp, gat, kp, g, theta);
+    else spread_slots<RT, CAP_MAX>(n, cnt, mp, gat, kp, g, theta);
 }
 
 template <int P>
@@ -207,10 +207,10 @@ __device__ __forceinline__ void collide_pairs(const RT* f, const PL& pl, unsigne
 // solid sources are replaced by bounce-back, open planes are rewritten by the boundary
 // kernel), so that each store writes whole cache lines: stores that leave part of a line
 // unwritten, as at every wall crossing of a lattice row, measured markedly slower in HBM.
-// CLEAR: also write the node word back with the coverage count cleared (every lane of the
-// wavefront, whole lines), for the next step's map pass (fused launches, no open planes)
+// CLEAR: also clear the coverage counts read here (every lane of the wavefront, whole lines),
+// for the map pass that next uses this set of counts
 template <typename ST, typename RT, typename PL, bool CLEAR = false>
-__device__ __forceinline__ void stream_collide_node(const PL& pl, uint32_t* __restrict__ nodeword,
+__device__ __forceinline__ void stream_collide_node(const PL& pl, const uint32_t* __restrict__ nodeword,
                                                     const MapPlanes<RT>& mp,
                                                     const Gather<RT>* __restrict__ gat,
                                                     const KParams& kp, unsigned* __restrict__ err,
@@ -221,6 +221,7 @@ __device__ __forceinline__ void stream_collide_node(const PL& pl, uint32_t* __re
     const bool live = (w & NW_FLUID) && !(w & NW_OPEN);
     const unsigned long long lv = __ballot(live);
     if (!lv) return;
+    const uint32_t cnum = *at32(mp.cnt, n);
     // A lane stores when its 128-B line (of S-byte elements) holds a fluid node of this
     // wavefront; the 64 lanes hold consecutive nodes.
     const int lane = (int)__lane_id();
@@ -241,7 +242,7 @@ __device__ __forceinline__ void stream_collide_node(const PL& pl, uint32_t* __re
     }
 
     RT g[3], theta;
-    spread_at<RT>(n, w, nodeword, mp, gat, kp, g, theta);
+    spread_at<RT>(n, cnum, mp, gat, kp, g, theta);
 
     // moments of the shifted populations: density excess, momentum, second moments
     RT drho = RT(0), mx = RT(0), my = RT(0), mz = RT(0);
@@ -301,13 +302,13 @@ __device__ __forceinline__ void stream_collide_node(const PL& pl, uint32_t* __re
     // (the boundary kernel still reads, and then clears, the counts at the open planes and
     // at the nodes it extrapolates from)
     if (CLEAR && line_has_fluid(4u))
-        __builtin_nontemporal_store((w & NW_OPEN_INNER) ? w : (w & NW_STATIC), at32(nodeword, n));
+        __builtin_nontemporal_store((w & NW_OPEN_INNER) ? cnum : 0u, at32(mp.cnt, n));
     if (live && (!(rho > RT(0)) || !(usq <= RT(0.09)))) atomicOr(err, ERR_UNSTABLE);
 }
 
 template <typename ST, typename RT, bool CLEAR>
 __global__ __launch_bounds__(256) void k_stream_collide(
-    const Planes<ST, RT> pl, uint32_t* __restrict__ nodeword, const MapPlanes<RT> mp,
+    const Planes<ST, RT> pl, const uint32_t* __restrict__ nodeword, const MapPlanes<RT> mp,
     const Gather<RT>* __restrict__ gat, KParams kp, unsigned* __restrict__ err)
 {
     const int x = blockIdx.x * 64 + threadIdx.x;
@@ -322,7 +323,7 @@ __global__ __launch_bounds__(256) void k_stream_collide(
 // wavefronts would only read their node words and exit.
 template <typename ST, typename RT, bool CLEAR>
 __global__ __launch_bounds__(256) void k_stream_collide_seg(
-    const Planes<ST, RT> pl, uint32_t* __restrict__ nodeword, const MapPlanes<RT> mp,
+    const Planes<ST, RT> pl, const uint32_t* __restrict__ nodeword, const MapPlanes<RT> mp,
     const Gather<RT>* __restrict__ gat, KParams kp, unsigned* __restrict__ err,
     const int4* __restrict__ segs, int nseg)
 {
@@ -337,7 +338,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_seg(
 // ---- open z faces: non-equilibrium extrapolation (Guo, Zheng & Shi 2002) ------------------
 template <typename ST, typename RT>
 __global__ __launch_bounds__(256) void k_open_bc(
-    const ST* __restrict__ fin, ST* __restrict__ fout, uint32_t* __restrict__ nodeword,
+    const ST* __restrict__ fin, ST* __restrict__ fout, const uint32_t* __restrict__ nodeword,
     const long long* __restrict__ plane_nodes, int nplane, const MapPlanes<RT> mp,
     const Gather<RT>* __restrict__ gat, RT* __restrict__ uout, RT* __restrict__ sout, KParams kp,
     int clear_counts)
@@ -355,13 +356,14 @@ __global__ __launch_bounds__(256) void k_open_bc(
     const uint32_t wi = nodeword[ni];
     const RT rb = z == 0 ? (RT)kp.rho_in : (RT)kp.rho_out;
     RT gb[3], thb;
-    spread_at<RT>((unsigned)n, w, nodeword, mp, gat, kp, gb, thb);
+    const uint32_t cn = mp.cnt[n], cni = mp.cnt[ni];
+    spread_at<RT>((unsigned)n, cn, mp, gat, kp, gb, thb);
     const RT om = RT(1) / ((RT)kp.tau0 + (RT)kp.delta * thb);
 #pragma unroll
     for (int a = 0; a < 6; ++a) sout[(long long)a * kp.ld + n] = RT(0);
     // with clear_counts this thread is the only reader of the counts at n and ni (the inner
     // node of one plane node): it clears them for the next step's map pass once read
-    if (clear_counts && (w >> 24)) nodeword[n] = w & NW_STATIC;
+    if (clear_counts && cn) mp.cnt[n] = 0u;
     if (!(wi & NW_FLUID)) {
         for (int p = 0; p < 19; ++p)
             store_pop<ST, RT>(fout + (size_t)p * (size_t)kp.ld, (unsigned)n, RT(w_(p)) * (rb - RT(1)), kp, (unsigned)p);
@@ -375,8 +377,8 @@ __global__ __launch_bounds__(256) void k_open_bc(
     pull_all<ST, RT>(f, fin, (unsigned)ni, wi, x, y, zi, xm, xp, ym, yp, zm, zp, kp,
                      std::make_integer_sequence<int, 19>{});
     RT gi[3], thi;
-    spread_at<RT>((unsigned)ni, wi, nodeword, mp, gat, kp, gi, thi);
-    if (clear_counts && (wi >> 24)) nodeword[ni] = wi & NW_STATIC;
+    spread_at<RT>((unsigned)ni, cni, mp, gat, kp, gi, thi);
+    if (clear_counts && cni) mp.cnt[ni] = 0u;
     RT drho = 0, mx = 0, my = 0, mz = 0;
     for (int p = 0; p < 19; ++p) {
         drho += f[p];
@@ -415,30 +417,26 @@ __global__ __launch_bounds__(256) void k_spread_field(const uint32_t* __restrict
         return;
     }
     RT g[3], th;
-    spread_at<RT>((unsigned)n, w, nodeword, mp, gat, kp, g, th);
+    spread_at<RT>((unsigned)n, mp.cnt[n], mp, gat, kp, g, th);
     gout[n] = g[0];
     gout[kp.ld + n] = g[1];
     gout[2 * kp.ld + n] = g[2];
     tout[n] = (RT)kp.tau0 + (RT)kp.delta * th;
 }
 
-// ---- coverage counters: clear the count byte, keep the static bits; clear the count of
-// the map pass's overflow list ------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_clear_counts(uint32_t* __restrict__ nodeword, long long N,
+// ---- coverage counts: clear one set, and the count of the map pass's overflow list ----------
+__global__ __launch_bounds__(256) void k_clear_counts(uint32_t* __restrict__ cnt, long long N,
                                                       int* __restrict__ ovf)
 {
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (n == 0 && ovf) ovf[0] = 0;
-    if (n < N) {
-        const uint32_t w = nodeword[n];
-        if (w >> 24) nodeword[n] = w & NW_STATIC;
-    }
+    if (n < N && cnt[n]) cnt[n] = 0u;
 }
 
 // the same over the row segments that hold a fluid node (counts are only ever set at fluid
 // nodes); blocks of 64 x 4, one segment per wavefront. A segment with a count is written
 // whole (scattered single-word stores measured several times slower).
-__global__ __launch_bounds__(256) void k_clear_counts_seg(uint32_t* __restrict__ nodeword,
+__global__ __launch_bounds__(256) void k_clear_counts_seg(uint32_t* __restrict__ cnt,
                                                           const int4* __restrict__ segs, int nseg,
                                                           int nx, int ny, int* __restrict__ ovf)
 {
@@ -449,8 +447,8 @@ __global__ __launch_bounds__(256) void k_clear_counts_seg(uint32_t* __restrict__
     const int x = sg.x + (int)threadIdx.x;
     const bool in = x < nx;
     const size_t n = (size_t)x + (size_t)nx * ((size_t)sg.y + (size_t)ny * (size_t)sg.z);
-    const uint32_t w = in ? nodeword[n] : 0u;
-    if (__ballot(w >> 24) != 0ull && in) nodeword[n] = w & NW_STATIC;
+    const uint32_t c = in ? cnt[n] : 0u;
+    if (__ballot(c != 0u) != 0ull && in) cnt[n] = 0u;
 }
 
 // ---- FP64 reductions: mass, momentum, summed u_z (two passes, fixed order) --------------
@@ -528,12 +526,14 @@ __global__ __launch_bounds__(256) void k_wss(const RT* __restrict__ sig,
 
 // ---- fused multi-lattice versions of the per-node stages -------------------------------------
 template <typename RT>
-__device__ __forceinline__ MapPlanes<RT> map_planes_dev(const int* ids, const void* vals, const KParams& kp)
+__device__ __forceinline__ MapPlanes<RT> map_planes_dev(const int* ids, const void* vals, uint32_t* cnt,
+                                                        const KParams& kp)
 {
     MapPlanes<RT> mp;
 #pragma unroll
     for (int k = 0; k < CAP_MAX; ++k) mp.ids[k] = ids + (k < kp.cap ? (size_t)k * (size_t)kp.ld : 0);
     mp.vals0 = (const RT*)vals;
+    mp.cnt = cnt;
     return mp;
 }
 
@@ -543,10 +543,7 @@ __global__ __launch_bounds__(256) void kf_clear(const FusedArgs fa)
     const SlotDesc& d = *fa.slot[fused_slot(fa, lb)];
     const long long n = (long long)lb * 256 + threadIdx.x;
     if (n == 0) d.b.ovf[0] = 0;
-    if (n < d.kp.N) {
-        const uint32_t w = d.b.nodeword[n];
-        if (w >> 24) d.b.nodeword[n] = w & NW_STATIC;
-    }
+    if (n < d.kp.N && d.b.cnt[n]) d.b.cnt[n] = 0u;
 }
 
 template <typename ST, typename RT>
@@ -565,7 +562,7 @@ __global__ __launch_bounds__(256) void kf_stream(const FusedArgs fa)
     const bool odd = (fa.parity >> sl) & 1ull;
     const PlanesLd<ST, RT> pl{(const ST*)(odd ? d.fB : d.fA), (ST*)(odd ? d.fA : d.fB), (RT*)d.b.u,
                               (RT*)d.b.sig, (unsigned long long)kp.ld};
-    const MapPlanes<RT> mp = map_planes_dev<RT>(d.b.map_ids, d.b.map_vals, kp);
+    const MapPlanes<RT> mp = map_planes_dev<RT>(d.b.map_ids, d.b.map_vals, d.b.cnt, kp);
     stream_collide_node<ST, RT, PlanesLd<ST, RT>, true>(pl, d.b.nodeword, mp, (const Gather<RT>*)d.b.gat,
                                                         kp, d.b.err, x, y, z);
 }
@@ -573,7 +570,7 @@ __global__ __launch_bounds__(256) void kf_stream(const FusedArgs fa)
 // ---- launchers ---------------------------------------------------------------------------------
 template <typename ST, typename RT>
 void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword, const int* ids,
-                           const void* vals, const void* gat, void* u, void* sig,
+                           const void* vals, uint32_t* cnt, const void* gat, void* u, void* sig,
                            const KParams& kp, unsigned* err, bool clear_counts, const int4* segs,
                            int nseg, hipStream_t st)
 {
@@ -586,56 +583,56 @@ void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword
     }
     for (int a = 0; a < 3; ++a) pl.u[a] = (RT*)u + a * ld;
     for (int a = 0; a < 6; ++a) pl.sig[a] = (RT*)sig + a * ld;
-    uint32_t* nw = const_cast<uint32_t*>(nodeword);
+    const uint32_t* nw = nodeword;
     if (segs && nseg > 0) {
         const dim3 sgrid((unsigned)((nseg + 3) / 4));
         if (clear_counts)
             hipLaunchKernelGGL((k_stream_collide_seg<ST, RT, true>), sgrid, dim3(64, 4, 1), 0, st, pl, nw,
-                               map_planes<RT>(ids, vals, kp), (const Gather<RT>*)gat, kp, err, segs, nseg);
+                               map_planes<RT>(ids, vals, cnt, kp), (const Gather<RT>*)gat, kp, err, segs, nseg);
         else
             hipLaunchKernelGGL((k_stream_collide_seg<ST, RT, false>), sgrid, dim3(64, 4, 1), 0, st, pl, nw,
-                               map_planes<RT>(ids, vals, kp), (const Gather<RT>*)gat, kp, err, segs, nseg);
+                               map_planes<RT>(ids, vals, cnt, kp), (const Gather<RT>*)gat, kp, err, segs, nseg);
         return;
     }
     if (clear_counts)
         hipLaunchKernelGGL((k_stream_collide<ST, RT, true>), grid, dim3(64, 4, 1), 0, st, pl, nw,
-                           map_planes<RT>(ids, vals, kp), (const Gather<RT>*)gat, kp, err);
+                           map_planes<RT>(ids, vals, cnt, kp), (const Gather<RT>*)gat, kp, err);
     else
         hipLaunchKernelGGL((k_stream_collide<ST, RT, false>), grid, dim3(64, 4, 1), 0, st, pl, nw,
-                           map_planes<RT>(ids, vals, kp), (const Gather<RT>*)gat, kp, err);
+                           map_planes<RT>(ids, vals, cnt, kp), (const Gather<RT>*)gat, kp, err);
 }
 
 template <typename ST, typename RT>
-void launch_open_bc(const void* fin, void* fout, uint32_t* nodeword, const long long* planes,
-                    int nplane, const int* ids, const void* vals, const void* gat, void* u,
+void launch_open_bc(const void* fin, void* fout, const uint32_t* nodeword, const long long* planes,
+                    int nplane, const int* ids, const void* vals, uint32_t* cnt, const void* gat, void* u,
                     void* sig, const KParams& kp, bool clear_counts, hipStream_t st)
 {
     if (nplane <= 0) return;
     hipLaunchKernelGGL((k_open_bc<ST, RT>), dim3((nplane + 255) / 256), dim3(256), 0, st,
                        (const ST*)fin, (ST*)fout, nodeword, planes, nplane,
-                       map_planes<RT>(ids, vals, kp), (const Gather<RT>*)gat, (RT*)u, (RT*)sig, kp,
+                       map_planes<RT>(ids, vals, cnt, kp), (const Gather<RT>*)gat, (RT*)u, (RT*)sig, kp,
                        clear_counts ? 1 : 0);
 }
 
 template <typename RT>
-void launch_spread_field(const uint32_t* nodeword, const int* ids, const void* vals,
+void launch_spread_field(const uint32_t* nodeword, const int* ids, const void* vals, uint32_t* cnt,
                          const void* gat, void* g, void* t, const KParams& kp, hipStream_t st)
 {
     const unsigned blocks = (unsigned)((kp.N + 255) / 256);
     hipLaunchKernelGGL((k_spread_field<RT>), dim3(blocks), dim3(256), 0, st, nodeword,
-                       map_planes<RT>(ids, vals, kp), (const Gather<RT>*)gat, (RT*)g, (RT*)t, kp);
+                       map_planes<RT>(ids, vals, cnt, kp), (const Gather<RT>*)gat, (RT*)g, (RT*)t, kp);
 }
 
-void launch_clear_counts(uint32_t* nodeword, long long N, int* ovf, const int4* segs, int nseg,
+void launch_clear_counts(uint32_t* cnt, long long N, int* ovf, const int4* segs, int nseg,
                          int nx, int ny, hipStream_t st)
 {
     if (segs && nseg > 0) {
         hipLaunchKernelGGL(k_clear_counts_seg, dim3((unsigned)((nseg + 3) / 4)), dim3(64, 4, 1), 0, st,
-                           nodeword, segs, nseg, nx, ny, ovf);
+                           cnt, segs, nseg, nx, ny, ovf);
         return;
     }
     hipLaunchKernelGGL(k_clear_counts, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
-                       nodeword, N, ovf);
+                       cnt, N, ovf);
 }
 
 template <typename ST, typename RT>
@@ -668,11 +665,12 @@ void launch_fused_lattice(const FusedArgs& fa, int stage, hipStream_t st)
 #define INST_ST(ST, RT)                                                                           \
     template void launch_fused_lattice<ST, RT>(const FusedArgs&, int, hipStream_t);               \
     template void launch_stream_collide<ST, RT>(const void*, void*, const uint32_t*, const int*,  \
-                                                const void*, const void*, void*, void*,           \
+                                                const void*, uint32_t*, const void*, void*, void*, \
                                                 const KParams&, unsigned*, bool, const int4*,     \
                                                 int, hipStream_t);                                \
-    template void launch_open_bc<ST, RT>(const void*, void*, uint32_t*, const long long*,         \
-                                         int, const int*, const void*, const void*, void*, void*, \
+    template void launch_open_bc<ST, RT>(const void*, void*, const uint32_t*, const long long*,   \
+                                         int, const int*, const void*, uint32_t*, const void*,    \
+                                         void*, void*,                                            \
                                          const KParams&, bool, hipStream_t);                      \
     template void launch_observe<ST, RT>(const void*, const uint32_t*, const void*,               \
                                          const KParams&, double*, int, double*, hipStream_t);
@@ -680,10 +678,10 @@ INST_ST(double, double)
 INST_ST(float, float)
 INST_ST(bf16_t, float)
 INST_ST(_Float16, float)
-template void launch_spread_field<double>(const uint32_t*, const int*, const void*, const void*,
-                                          void*, void*, const KParams&, hipStream_t);
-template void launch_spread_field<float>(const uint32_t*, const int*, const void*, const void*,
-                                         void*, void*, const KParams&, hipStream_t);
+template void launch_spread_field<double>(const uint32_t*, const int*, const void*, uint32_t*,
+                                          const void*, void*, void*, const KParams&, hipStream_t);
+template void launch_spread_field<float>(const uint32_t*, const int*, const void*, uint32_t*,
+                                         const void*, void*, void*, const KParams&, hipStream_t);
 template void launch_wss<double>(const void*, const long long*, const double*, int,
                                  const KParams&, double*, double*, int, hipStream_t);
 template void launch_wss<float>(const void*, const long long*, const double*, int,

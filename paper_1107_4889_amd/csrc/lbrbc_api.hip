@@ -339,7 +339,7 @@ std::string build_geometry(const lb_config& c, const uint8_t* solid, int n_rbc, 
 
 // ---- arena layout --------------------------------------------------------------------------
 struct Layout {
-    size_t fA, fB, u, sig, gdbg, tdbg, nodeword, map_ids, map_vals, ovf, st, cp, gat, cellid, cell_cnt, cell_off,
+    size_t fA, fB, u, sig, gdbg, tdbg, nodeword, map_ids[2], map_vals[2], cnt[2], ovf, st, cp, gat, cellid, cell_cnt, cell_off,
         cell_part, cell_ids, wall_xyz, wcell_off, wcell_ids, wn_node, wn_nrm, wss, wss_acc, planes, segs, partials,
         obs_out, err, slot, total;
 };
@@ -365,8 +365,12 @@ Layout layout(const lb_config& c, const Geometry& g, int n_rbc)
     L.gdbg = take(3 * ld * rs);
     L.tdbg = take(ld * rs);
     L.nodeword = take(ld * 4);
-    L.map_ids = take(n_rbc > 0 ? (size_t)cap * ld * 4 : 4);
-    L.map_vals = take(n_rbc > 0 ? ((size_t)n_rbc << g.ent_shift) * 4 * rs : 4);
+    // two coverage sets, alternating with the step's parity
+    for (int p = 0; p < 2; ++p) {
+        L.map_ids[p] = take(n_rbc > 0 ? (size_t)cap * ld * 4 : 4);
+        L.map_vals[p] = take(n_rbc > 0 ? ((size_t)n_rbc << g.ent_shift) * 4 * rs : 4);
+        L.cnt[p] = take(ld * 4);   // read at every fluid node, with or without cells
+    }
     L.ovf = take(((size_t)n_rbc + 1) * 4);
     L.st = take(n_rbc * sizeof(RbcState));
     L.cp = take(n_rbc * sizeof(RbcCouple));
@@ -411,9 +415,11 @@ struct lb_ctx_s {
     bool cells_ahead = false;
     char* base = nullptr;
     void *fA = nullptr, *fB = nullptr;
-    // coverage counts all zero (after init and after a fused step, whose stream-collide clears
-    // them); a single-context step or rbc_couple leaves them set
-    bool counts_clean = true;
+    // per coverage set: counts possibly nonzero (left by rbc_couple, or by a step whose
+    // stream-collide could not clear them); cleared before that set's next map pass
+    bool dirty[2] = {false, false};
+    // the set the last map pass filled (rbc_get_map and the spread probe read it)
+    int map_parity = 0;
     CellBuffers cb{};
     long long step = 0;
     int nrbc = 0;
@@ -432,6 +438,15 @@ struct lb_ctx_s {
 
     template <typename T>
     T* at(size_t off) { return reinterpret_cast<T*>(base + off); }
+    // the cell buffers with coverage set p (the fused launches use set 0, written at init)
+    CellBuffers par(int p)
+    {
+        CellBuffers b = cb;
+        b.map_ids = at<int>(lay.map_ids[p]);
+        b.map_vals = at<void>(lay.map_vals[p]);
+        b.cnt = at<uint32_t>(lay.cnt[p]);
+        return b;
+    }
     // the row-segment list of a sparse geometry (null and 0: the dense launch grid)
     const int4* segs() { return geo.segs.empty() ? nullptr : at<int4>(lay.segs); }
     int nseg() const { return (int)(geo.segs.size() / 4); }
@@ -550,14 +565,19 @@ lb_status check_fault(lb_ctx c)
     return LB_OK;
 }
 
-// cell list, coverage map and interpolation onto the cells (one pass per cell)
+// cell list, coverage map and interpolation onto the cells (one pass per cell), into the
+// coverage set of the next step
 template <typename RT>
 void enqueue_cells_map_couple(lb_ctx c)
 {
     hipStream_t s = c->stream;
-    launch_cell_list(c->cb, c->kp, s);
-    launch_clear_counts(c->cb.nodeword, c->kp.N, c->cb.ovf, c->segs(), c->nseg(), c->kp.nx, c->kp.ny, s);
-    launch_map_couple<RT>(c->cb, c->kp, s);
+    const int p = (int)(c->step & 1);
+    const CellBuffers b = c->par(p);
+    launch_cell_list(b, c->kp, s);
+    launch_clear_counts(b.cnt, c->kp.N, b.ovf, c->segs(), c->nseg(), c->kp.nx, c->kp.ny, s);
+    launch_map_couple<RT>(b, c->kp, s);
+    c->dirty[p] = true;
+    c->map_parity = p;
 }
 
 // One step. With a side stream the cells' work runs there: after the map pass, the kick and,
@@ -570,11 +590,13 @@ void enqueue_step(lb_ctx c, bool last)
     const KParams& kp = c->kp;
     c->cb.u = c->at<void>(c->lay.u);
     c->cb.sig = c->at<void>(c->lay.sig);
-    // The stream-collide clears the coverage counts for the next step, except at the open
-    // planes and their inner neighbours, whose counts the boundary kernel reads after it and
-    // then clears. With nz = 3 both planes extrapolate from the same layer (two readers), so
-    // the counts are cleared before the map pass instead; likewise once after rbc_couple,
-    // which leaves them set.
+    // this step's coverage set
+    const int p = (int)(c->step & 1);
+    const CellBuffers b = c->par(p);
+    // The stream-collide clears the counts of the set it reads, except at the open planes and
+    // their inner neighbours, whose counts the boundary kernel reads after it and then
+    // clears. With nz = 3 both planes extrapolate from the same layer (two readers), so the
+    // counts stay and are cleared before that set's next map pass, as after rbc_couple.
     const bool sc_clears = c->geo.planes.empty() || c->cfg.nz > 3;
     with_types(c->cfg.storage, [&](auto* sp, auto* rp) {
         using ST = std::remove_pointer_t<decltype(sp)>;
@@ -593,9 +615,10 @@ void enqueue_step(lb_ctx c, bool last)
             } else {
                 (void)hipStreamWaitEvent(s, c->ev_cells, 0);
             }
-            if (!sc_clears || !c->counts_clean)
-                launch_clear_counts(c->cb.nodeword, kp.N, c->cb.ovf, c->segs(), c->nseg(), kp.nx, kp.ny, s);
-            launch_map_couple<RT>(c->cb, kp, s);
+            if (c->dirty[p])
+                launch_clear_counts(b.cnt, kp.N, b.ovf, c->segs(), c->nseg(), kp.nx, kp.ny, s);
+            launch_map_couple<RT>(b, kp, s);
+            c->map_parity = p;
             if (!forked) {
                 launch_gay_berne(c->cb, kp, s);
                 launch_rb_second_half(c->cb, kp, s);
@@ -621,7 +644,7 @@ void enqueue_step(lb_ctx c, bool last)
             c->ev_pool.pop_back();
             (void)hipEventRecord(e0, s);
         }
-        launch_stream_collide<ST, RT>(c->fA, c->fB, c->cb.nodeword, c->cb.map_ids, c->cb.map_vals,
+        launch_stream_collide<ST, RT>(c->fA, c->fB, b.nodeword, b.map_ids, b.map_vals, b.cnt,
                                       c->cb.gat, c->at<void>(c->lay.u), c->at<void>(c->lay.sig), kp,
                                       c->cb.err, sc_clears && c->nrbc > 0, c->segs(), c->nseg(), s);
         if (e0) {
@@ -629,8 +652,8 @@ void enqueue_step(lb_ctx c, bool last)
             c->sc_pairs.emplace_back(e0, e1);
         }
         if (!c->geo.planes.empty())
-            launch_open_bc<ST, RT>(c->fA, c->fB, c->cb.nodeword, c->at<long long>(c->lay.planes),
-                                   (int)c->geo.planes.size(), c->cb.map_ids, c->cb.map_vals, c->cb.gat,
+            launch_open_bc<ST, RT>(c->fA, c->fB, b.nodeword, c->at<long long>(c->lay.planes),
+                                   (int)c->geo.planes.size(), b.map_ids, b.map_vals, b.cnt, c->cb.gat,
                                    c->at<void>(c->lay.u), c->at<void>(c->lay.sig), kp,
                                    sc_clears && c->nrbc > 0, s);
         if (c->wss_on)
@@ -640,7 +663,8 @@ void enqueue_step(lb_ctx c, bool last)
         if (forked && last) (void)hipStreamWaitEvent(s, c->ev_gb, 0);
     });
     if (c->wss_on) c->wss_count++;
-    c->counts_clean = sc_clears;
+    // the stream-collide (and the boundary kernel) cleared the counts of this step's set
+    c->dirty[p] = c->nrbc > 0 && !sc_clears;
     std::swap(c->fA, c->fB);
     c->step++;
 }
@@ -694,7 +718,7 @@ void enqueue_fused_step(lb_ctx* cs, int n)
             int tot = 0;
             for (int i = 0; i < n; ++i) {
                 fa.start[i] = tot;
-                tot += cs[i]->counts_clean ? 0 : fused_blocks(cs[i]->kp, FS_CLEAR);
+                tot += cs[i]->dirty[0] ? fused_blocks(cs[i]->kp, FS_CLEAR) : 0;
             }
             fa.start[n] = tot;
             launch_fused_lattice<ST, RT>(fa, FS_CLEAR, s);
@@ -713,7 +737,8 @@ void enqueue_fused_step(lb_ctx* cs, int n)
     for (int i = 0; i < n; ++i) {
         std::swap(cs[i]->fA, cs[i]->fB);
         cs[i]->step++;
-        cs[i]->counts_clean = true;
+        cs[i]->dirty[0] = false;
+        cs[i]->map_parity = 0;
     }
 }
 
@@ -813,8 +838,9 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
     b.wcell_off = c->at<int>(L.wcell_off);
     b.wcell_ids = c->at<int>(L.wcell_ids);
     b.nodeword = c->at<uint32_t>(L.nodeword);
-    b.map_ids = c->at<int>(L.map_ids);
-    b.map_vals = c->at<void>(L.map_vals);
+    b.map_ids = c->at<int>(L.map_ids[0]);
+    b.map_vals = c->at<void>(L.map_vals[0]);
+    b.cnt = c->at<uint32_t>(L.cnt[0]);
     b.ovf = c->at<int>(L.ovf);
     b.u = c->at<void>(L.u);
     b.sig = c->at<void>(L.sig);
@@ -943,11 +969,9 @@ lb_status rbc_couple(lb_ctx c)
     if (!c) return LB_EINVAL;
     with_types(c->cfg.storage, [&](auto*, auto* rp) {
         using RT = std::remove_pointer_t<decltype(rp)>;
-        if (c->nrbc > 0) {
-            enqueue_cells_map_couple<RT>(c);
-            c->counts_clean = false;
-        }
-        launch_spread_field<RT>(c->cb.nodeword, c->cb.map_ids, c->cb.map_vals, c->cb.gat,
+        if (c->nrbc > 0) enqueue_cells_map_couple<RT>(c);
+        const CellBuffers b = c->par(c->map_parity);
+        launch_spread_field<RT>(b.nodeword, b.map_ids, b.map_vals, b.cnt, c->cb.gat,
                                 c->at<void>(c->lay.gdbg), c->at<void>(c->lay.tdbg), c->kp, c->stream);
     });
     HIPCHK(c, hipGetLastError());
@@ -1216,15 +1240,16 @@ lb_status rbc_get_map(lb_ctx c, int* off, int* ids, long long* len)
     if (!c || !len) return LB_EINVAL;
     lb_status st = check_fault(c);
     const size_t N = (size_t)c->kp.N, ld = (size_t)c->kp.ld;
-    std::vector<uint32_t> nw(N);
-    HIPCHK(c, hipMemcpy(nw.data(), c->cb.nodeword, N * 4, hipMemcpyDeviceToHost));
+    const CellBuffers b = c->par(c->map_parity);
+    std::vector<uint32_t> cn(N, 0u);
+    if (c->nrbc) HIPCHK(c, hipMemcpy(cn.data(), b.cnt, N * 4, hipMemcpyDeviceToHost));
     long long tot = 0;
-    for (size_t n = 0; n < N; ++n) tot += std::min<int>(nw[n] >> 24, c->kp.cap);
+    for (size_t n = 0; n < N; ++n) tot += std::min<int>((int)cn[n], c->kp.cap);
     if (!ids) {
         *len = tot;
         if (off) {
             off[0] = 0;
-            for (size_t n = 0; n < N; ++n) off[n + 1] = off[n] + std::min<int>(nw[n] >> 24, c->kp.cap);
+            for (size_t n = 0; n < N; ++n) off[n + 1] = off[n] + std::min<int>((int)cn[n], c->kp.cap);
         }
         return st;
     }
@@ -1232,15 +1257,15 @@ lb_status rbc_get_map(lb_ctx c, int* off, int* ids, long long* len)
     std::vector<int> slots;
     if (c->nrbc) {
         slots.resize((size_t)c->kp.cap * ld);
-        HIPCHK(c, hipMemcpy(slots.data(), c->cb.map_ids, slots.size() * 4, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(slots.data(), b.map_ids, slots.size() * 4, hipMemcpyDeviceToHost));
     }
     long long k = 0;
     if (off) off[0] = 0;
     for (size_t n = 0; n < N; ++n) {
-        const int cnt = std::min<int>(nw[n] >> 24, c->kp.cap);
-        const long long b = k;
-        for (int s = 0; s < cnt; ++s) ids[k++] = slots[(size_t)s * ld + n] >> c->kp.ent_shift;
-        std::sort(ids + b, ids + k);
+        const int cnt = std::min<int>((int)cn[n], c->kp.cap);
+        const long long k0 = k;
+        for (int q = 0; q < cnt; ++q) ids[k++] = slots[(size_t)q * ld + n] >> c->kp.ent_shift;
+        std::sort(ids + k0, ids + k);
         if (off) off[n + 1] = (int)k;
     }
     *len = tot;

@@ -35,13 +35,11 @@ __host__ __device__ constexpr double w_(int p)
 // bits 0-18: bit p set <=> the pull source x - c_p is solid or outside a wall face
 // bit 19: fluid node; bit 20: has an in-box solid neighbour (wall-adjacent);
 // bit 21: open-boundary plane node; bit 22: fluid node next to an open-plane node along z
-// (the boundary kernel extrapolates from it); bits 24-31: number of covering cells this step.
+// (the boundary kernel extrapolates from it). The coverage counts live in arrays of their own.
 constexpr uint32_t NW_FLUID = 1u << 19;
 constexpr uint32_t NW_WALLADJ = 1u << 20;
 constexpr uint32_t NW_OPEN = 1u << 21;
 constexpr uint32_t NW_OPEN_INNER = 1u << 22;
-constexpr uint32_t NW_CNT_ONE = 1u << 24;
-constexpr uint32_t NW_STATIC = 0x00FFFFFFu;
 constexpr int CAP_MAX = 12;
 
 // device fault bits
@@ -198,12 +196,15 @@ __device__ __forceinline__ double fast_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float fast_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double fast_rsqrt(double x) { return 1.0 / sqrt(x); }
 
-// Coverage: per node, up to `cap` slot planes hold entry indices e = (cell << ent_shift) | j;
-// entry e holds (raw, grad raw) of the j-th covered node of that cell, cell-major.
+// Coverage: per node, a count and up to `cap` slot planes of entry indices
+// e = (cell << ent_shift) | j; entry e holds (raw, grad raw) of the j-th covered node of that
+// cell, cell-major. Two such sets alternate with the step's parity, so the next step's map
+// pass can fill one while the stream-collide reads the other.
 template <typename RT>
 struct MapPlanes {
     const int* ids[CAP_MAX];
     const RT* vals0;
+    uint32_t* cnt;
 };
 
 // per-plane pointers of one stream-collide launch (kernel argument)

@@ -14,17 +14,17 @@ namespace lbrbc {
 // clear_counts: also clear the coverage counts for the next step (no open planes)
 template <typename ST, typename RT>
 void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword, const int* ids,
-                           const void* vals, const void* gat, void* u, void* sig,
+                           const void* vals, uint32_t* cnt, const void* gat, void* u, void* sig,
                            const KParams& kp, unsigned* err, bool clear_counts, const int4* segs,
                            int nseg, hipStream_t st);
 template <typename ST, typename RT>
-void launch_open_bc(const void* fin, void* fout, uint32_t* nodeword, const long long* planes,
-                    int nplane, const int* ids, const void* vals, const void* gat, void* u,
+void launch_open_bc(const void* fin, void* fout, const uint32_t* nodeword, const long long* planes,
+                    int nplane, const int* ids, const void* vals, uint32_t* cnt, const void* gat, void* u,
                     void* sig, const KParams& kp, bool clear_counts, hipStream_t st);
 template <typename RT>
-void launch_spread_field(const uint32_t* nodeword, const int* ids, const void* vals,
+void launch_spread_field(const uint32_t* nodeword, const int* ids, const void* vals, uint32_t* cnt,
                          const void* gat, void* g, void* t, const KParams& kp, hipStream_t st);
-void launch_clear_counts(uint32_t* nodeword, long long N, int* ovf, const int4* segs, int nseg,
+void launch_clear_counts(uint32_t* cnt, long long N, int* ovf, const int4* segs, int nseg,
                          int nx, int ny, hipStream_t st);
 template <typename ST, typename RT>
 void launch_observe(const void* f, const uint32_t* nodeword, const void* u, const KParams& kp,
@@ -49,9 +49,11 @@ struct CellBuffers {
     const int* wall_xyz;  // [3 * nwall]
     const int* wcell_off; // [ncells + 1]
     const int* wcell_ids; // [nwall]
-    uint32_t* nodeword;
-    int* map_ids;         // [cap * ld] cell id per coverage slot
-    void* map_vals;       // [cap * ld * 4] RT: raw kernel and its gradient per slot
+    uint32_t* nodeword;   // static bits per node (fluid, bounce-back, wall, open planes)
+    // one of the two coverage sets (chosen by the step's parity)
+    int* map_ids;         // [cap * ld] entry index per coverage slot
+    void* map_vals;       // [entries * 4] RT: raw kernel and its gradient per entry
+    uint32_t* cnt;        // [ld] coverage count per node
     const void* u;        // [3 * ld] RT
     const void* sig;      // [6 * ld] RT
     unsigned* err;

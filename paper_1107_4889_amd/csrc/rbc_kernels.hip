@@ -321,7 +321,7 @@ constexpr int TILE_ROWS_MAX = 20 * 20;   // tile_max <= 20
 template <typename RT>
 __device__ void map_couple_tile(int i, unsigned char* smem, const RbcState* __restrict__ st,
                                 RbcCouple* __restrict__ cp, Gather<RT>* __restrict__ gat,
-                                uint32_t* __restrict__ nodeword,
+                                const uint32_t* __restrict__ nodeword, uint32_t* __restrict__ cnt,
                                 int* __restrict__ ids, RT* __restrict__ vals,
                                 const RT* __restrict__ u, const RT* __restrict__ sig,
                                 const KParams& kp, unsigned* __restrict__ err)
@@ -471,8 +471,8 @@ __device__ void map_couple_tile(int i, unsigned char* smem, const RbcState* __re
         const RT gy = RT(0.5) * ((yp ? raw[t + sx] : RT(0)) - (ym ? raw[t - sx] : RT(0)));
         const RT gz = RT(0.5) * ((zp ? raw[t + sxy] : RT(0)) - (zm ? raw[t - sxy] : RT(0)));
         const RT ux = u[n], uy = u[ld + n], uz = u[2 * ld + n];
-        const uint32_t old = atomicAdd(nodeword + n, NW_CNT_ONE);
-        const int slot = (int)(old >> 24);
+        const uint32_t old = atomicAdd(cnt + n, 1u);
+        const int slot = (int)old;
         const int e = (i << kp.ent_shift) | j;
         if (slot < kp.cap && j < (1 << kp.ent_shift)) {
             ids[(size_t)slot * ld + n] = e;
@@ -537,7 +537,7 @@ template <typename RT>
 __global__ __launch_bounds__(MC_THREADS) void k_map_couple_tile(const RbcState* __restrict__ st,
                                                                 RbcCouple* __restrict__ cp,
                                                                 Gather<RT>* __restrict__ gat,
-                                                                uint32_t* __restrict__ nodeword,
+                                                                const uint32_t* __restrict__ nodeword, uint32_t* __restrict__ cnt,
                                                                 int* __restrict__ ids,
                                                                 RT* __restrict__ vals,
                                                                 const int* __restrict__ ovf,
@@ -549,7 +549,7 @@ __global__ __launch_bounds__(MC_THREADS) void k_map_couple_tile(const RbcState* 
     extern __shared__ unsigned char smem[];
     const int n = ovf[0];
     for (int b = blockIdx.x; b < n; b += gridDim.x)
-        map_couple_tile<RT>(ovf[1 + b], smem, st, cp, gat, nodeword, ids, vals, u, sig, kp, err);
+        map_couple_tile<RT>(ovf[1 + b], smem, st, cp, gat, nodeword, cnt, ids, vals, u, sig, kp, err);
 }
 
 // ---- S3 + S4, one wavefront per cell on the row-compressed support tile -----------------------
@@ -569,7 +569,7 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
                                                 const RbcState* __restrict__ st,
                                                 RbcCouple* __restrict__ cp,
                                                 Gather<RT>* __restrict__ gat,
-                                                uint32_t* __restrict__ nodeword,
+                                                const uint32_t* __restrict__ nodeword, uint32_t* __restrict__ cnt,
                                                 int* __restrict__ ids, RT* __restrict__ vals,
                                                 const int* __restrict__ order,
                                                 const RT* __restrict__ u,
@@ -789,8 +789,8 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
             const RT gy = RT(0.5) * (max(vyp, z0) - max(vym, z0));
             const RT gz = RT(0.5) * (max(vzp, z0) - max(vzm, z0));
             const RT ux = *at32(u, n), uy = *at32(u + ld, n), uz = *at32(u + 2 * ld, n);
-            const uint32_t old = atomicAdd(nodeword + n, NW_CNT_ONE);
-            const int slot = (int)(old >> 24);
+            const uint32_t old = atomicAdd(cnt + n, 1u);
+            const int slot = (int)old;
             const int e = (i << kp.ent_shift) | j;
             if (slot < kp.cap && j < (1 << kp.ent_shift)) {
                 ids[(size_t)slot * ld + n] = e;
@@ -848,7 +848,7 @@ template <typename RT>
 __global__ __launch_bounds__(64) void k_map_couple(const RbcState* __restrict__ st,
                                                    RbcCouple* __restrict__ cp,
                                                    Gather<RT>* __restrict__ gat,
-                                                   uint32_t* __restrict__ nodeword,
+                                                   const uint32_t* __restrict__ nodeword, uint32_t* __restrict__ cnt,
                                                    int* __restrict__ ids, RT* __restrict__ vals,
                                                    const int* __restrict__ order,
                                                    const RT* __restrict__ u,
@@ -859,7 +859,7 @@ __global__ __launch_bounds__(64) void k_map_couple(const RbcState* __restrict__ 
     extern __shared__ unsigned char smem[];
     const int k = xcd_chunk_index(1);
     if (k < kp.nrbc)
-        map_couple_cell<RT>(k, smem, st, cp, gat, nodeword, ids, vals, order, u, sig, kp, err, ovf);
+        map_couple_cell<RT>(k, smem, st, cp, gat, nodeword, cnt, ids, vals, order, u, sig, kp, err, ovf);
 }
 
 // ---- S5: Gay-Berne forces and torques (Sec. II E, Eqs. 24-28; App. B) -----------------------
@@ -1209,7 +1209,7 @@ __global__ __launch_bounds__(64) void kf_map(const FusedArgs fa)
     const SlotDesc& d = *fa.slot[fused_slot(fa, lb)];
     const KParams kp = d.kp;
     if (lb < kp.nrbc)
-        map_couple_cell<RT>(lb, smem, d.b.st, d.b.cp, (Gather<RT>*)d.b.gat, d.b.nodeword, d.b.map_ids,
+        map_couple_cell<RT>(lb, smem, d.b.st, d.b.cp, (Gather<RT>*)d.b.gat, d.b.nodeword, d.b.cnt, d.b.map_ids,
                             (RT*)d.b.map_vals,
                             d.b.cell_ids, (const RT*)d.b.u, (const RT*)d.b.sig, kp, d.b.err, d.b.ovf);
 }
@@ -1223,7 +1223,7 @@ __global__ __launch_bounds__(MC_THREADS) void kf_map_tile(const FusedArgs fa)
     const KParams kp = d.kp;
     const int n = d.b.ovf[0];
     for (int b = lb; b < n; b += FUSED_TILE_BLOCKS)
-        map_couple_tile<RT>(d.b.ovf[1 + b], smem, d.b.st, d.b.cp, (Gather<RT>*)d.b.gat, d.b.nodeword,
+        map_couple_tile<RT>(d.b.ovf[1 + b], smem, d.b.st, d.b.cp, (Gather<RT>*)d.b.gat, d.b.nodeword, d.b.cnt,
                             d.b.map_ids,
                             (RT*)d.b.map_vals, (const RT*)d.b.u, (const RT*)d.b.sig, kp, d.b.err);
 }
@@ -1316,12 +1316,12 @@ void launch_map_couple(const CellBuffers& b, const KParams& kp, hipStream_t st)
 {
     hipLaunchKernelGGL((k_map_couple<RT>), dim3(grid8(kp.nrbc, 1)), dim3(64),
                        map_couple_lds(kp.tile_max, kp.cand_cap, (int)sizeof(RT)), st, b.st, b.cp,
-                       (Gather<RT>*)b.gat, b.nodeword, b.map_ids, (RT*)b.map_vals, b.cell_ids, (const RT*)b.u,
+                       (Gather<RT>*)b.gat, b.nodeword, b.cnt, b.map_ids, (RT*)b.map_vals, b.cell_ids, (const RT*)b.u,
                        (const RT*)b.sig, kp, b.err, b.ovf);
     // the overflow list is short (normally empty): a small grid loops over it
     hipLaunchKernelGGL((k_map_couple_tile<RT>), dim3(64), dim3(MC_THREADS),
                        map_couple_tile_lds(kp.tile_max, (int)sizeof(RT)), st, b.st, b.cp,
-                       (Gather<RT>*)b.gat, b.nodeword, b.map_ids, (RT*)b.map_vals, b.ovf, (const RT*)b.u,
+                       (Gather<RT>*)b.gat, b.nodeword, b.cnt, b.map_ids, (RT*)b.map_vals, b.ovf, (const RT*)b.u,
                        (const RT*)b.sig, kp, b.err);
 }
 
