@@ -305,6 +305,11 @@ __device__ __forceinline__ int xcd_chunk_index(int units_per_block)
 }
 
 constexpr int MC_THREADS = 256;
+
+// F^hyd, T^hyd and the gather record of a cell from its interpolation sums (defined with S6)
+template <typename RT>
+__device__ __forceinline__ void hydro_cell(const RbcState& s, RbcCouple& c, const KParams& kp,
+                                           Gather<RT>* __restrict__ gi);
 constexpr int TILE_ROWS_MAX = 20 * 20;   // tile_max <= 20
 
 // ---- S3 + S4: coverage map and interpolation, one block per cell ------------------------
