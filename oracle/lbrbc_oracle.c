@@ -29,6 +29,12 @@
 #include <omp.h>
 #endif
 
+/* Loops over fewer nodes or cells than these run on one thread: a parallel region per step
+ * costs more than such loops, and far more when several processes share the cores. Every
+ * iteration is independent, so the thread count changes no result. */
+#define ORC_PAR_NODES 16384
+#define ORC_PAR_CELLS 64
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
@@ -825,7 +831,7 @@ static int collide_one(orc_sim* s, int i, int brute, double F[3], double T[3])
 static int collide_all(orc_sim* s, int brute)
 {
     int i, err = ORC_OK;
-#pragma omp parallel for schedule(dynamic, 16) reduction(max : err)
+#pragma omp parallel for schedule(dynamic, 16) reduction(max : err) if (s->nrbc >= ORC_PAR_CELLS)
     for (i = 0; i < s->nrbc; ++i) {
         int st = collide_one(s, i, brute, s->Fmech + 3 * i, s->Tmech + 3 * i);
         if (st > err) err = st;
@@ -886,7 +892,7 @@ static void hydrodynamic(orc_sim* s, int i, const double* V, const double* Om)
 static void spread(orc_sim* s)
 {
     long n;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (s->N >= ORC_PAR_NODES)
     for (n = 0; n < s->N; ++n) {
         int x, y, z, a;
         long e;
@@ -939,7 +945,7 @@ static int stream_collide(orc_sim* s)
 {
     long n;
     int bad = 0;
-#pragma omp parallel for schedule(static) reduction(| : bad)
+#pragma omp parallel for schedule(static) reduction(| : bad) if (s->N >= ORC_PAR_NODES)
     for (n = 0; n < s->N; ++n) {
         int x, y, z, p, a;
         double f[19], rho, m[3], u[3], T, Pn[6] = {0, 0, 0, 0, 0, 0}, k;
@@ -1032,7 +1038,7 @@ static int couple_cells(orc_sim* s)
     int i;
     build_cell_list(s);
     build_map(s);
-#pragma omp parallel for schedule(dynamic, 4)
+#pragma omp parallel for schedule(dynamic, 4) if (s->nrbc >= ORC_PAR_CELLS)
     for (i = 0; i < s->nrbc; ++i) interpolate_cell(s, i);
     return ORC_OK;
 }
