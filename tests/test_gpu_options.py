@@ -71,3 +71,42 @@ def test_coverage_capacity_error_is_reported(lb, small):
     with pytest.raises(lb.LbError) as e:
         sim.lb_step(1)
     assert e.value.status == lb.LB_ESTATE
+
+
+def test_observables_and_time_averaged_wss_match_oracle_f64(lb, small):
+    # Sec. III observables: flow rate, apparent viscosity and the wall shear stress, the last
+    # also averaged over time from the step lb_wss_accumulate(1) is called; the oracle's
+    # average is the plain mean of its per-step values over the same steps
+    solid, pl = small
+    cfg = dict(nx=32, ny=32, nz=64, periodic=(0, 0, 1), tau0=1.0, g_ext=(0, 0, 1e-6))
+    warm, steps = 10, 20
+    print(f"[options] observables: {len(pl.R)} cells, {warm} + {steps} steps", flush=True)
+    ref = orc.Oracle(cfg, solid, R=pl.R, Q=pl.Q)
+    assert ref.step(warm) == 0
+    acc = None
+    for _ in range(steps):
+        assert ref.step(1) == 0
+        node_o, w = ref.wall_shear_stress()
+        acc = w.copy() if acc is None else acc + w
+    wss_avg = acc / steps
+    sim = lb.Simulation(dict(cfg, storage="f64"), solid, R=pl.R, Q=pl.Q)
+    sim.lb_step(warm)
+    sim.lb_wss_accumulate(True)
+    sim.lb_step(steps)
+    sim.lb_sync()
+    node_g, wss_g = sim.lb_wall_shear_stress(True)
+    assert np.array_equal(node_g, node_o)
+    assert rel(wss_g, wss_avg) < 1e-9
+    node_g, wss_now = sim.lb_wall_shear_stress(False)
+    assert rel(wss_now, ref.wall_shear_stress()[1]) < 1e-9
+    o, ro = sim.lb_observe(), ref.observe()
+    assert o.n_wall_nodes == ro["n_wall_nodes"] == len(node_o)
+    assert o.mass == pytest.approx(ro["mass"], rel=1e-12)
+    assert np.abs(o.momentum - ro["momentum"]).max() < 1e-9 * abs(ro["momentum"][2])
+    assert o.flow_rate == pytest.approx(ro["flow_rate"], rel=1e-10)
+    assert o.eta_app == pytest.approx(ro["eta_app"], rel=1e-10)
+    assert sim.lb_apparent_viscosity() == pytest.approx(o.eta_app, rel=1e-14)
+    assert o.wss_mean == pytest.approx(ro["wss_mean"], rel=1e-9)
+    assert o.wss_max == pytest.approx(ro["wss_max"], rel=1e-9)
+    assert o.wss_time_mean == pytest.approx(float(wss_avg.mean()), rel=1e-9)
+    sim.lb_wss_accumulate(False)
