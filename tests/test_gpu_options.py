@@ -110,3 +110,34 @@ def test_observables_and_time_averaged_wss_match_oracle_f64(lb, small):
     assert o.wss_max == pytest.approx(ro["wss_max"], rel=1e-9)
     assert o.wss_time_mean == pytest.approx(float(wss_avg.mean()), rel=1e-9)
     sim.lb_wss_accumulate(False)
+
+
+def test_degenerate_lattices(lb):
+    # one periodic node under a uniform body force: every population streams back onto the
+    # node, so after n steps the momentum is n g and the velocity (m + g/2)/rho = (n - 1/2) g
+    g = np.array([1e-5, -2e-5, 3e-5])
+    n = 20
+    cfg = dict(nx=1, ny=1, nz=1, periodic=(1, 1, 1), tau0=0.8, g_ext=tuple(g))
+    solid = np.zeros((1, 1, 1), np.uint8)
+    print("[options] single periodic node, all-solid box", flush=True)
+    ref = orc.Oracle(cfg, solid)
+    assert ref.step(n) == 0
+    assert np.allclose(ref.u()[0], (n - 0.5) * g, rtol=1e-12, atol=0)
+    for storage, tol in (("f64", 1e-12), ("f32", 1e-5)):
+        sim = lb.Simulation(dict(cfg, storage=storage), solid)
+        sim.lb_step(n)
+        sim.lb_sync()
+        d = sim.lb_get_fields()
+        assert rel(d["u"], ref.u()) < tol, storage
+        assert rel(d["f"], ref.f()) < tol, storage
+        o = sim.lb_observe()
+        assert o.n_fluid == 1 and o.n_wall_nodes == 0
+        assert np.allclose(o.momentum, n * g, rtol=tol, atol=0), storage
+    # a box with no fluid node: the steps run and every observable is zero
+    box = dict(nx=8, ny=8, nz=8, periodic=(0, 0, 0), tau0=0.8, storage="f32")
+    sim = lb.Simulation(box, np.ones((8, 8, 8), np.uint8))
+    sim.lb_step(5)
+    sim.lb_sync()
+    o = sim.lb_observe()
+    assert o.n_fluid == 0 and o.mass == 0.0 and o.n_wall_nodes == 0
+    assert not np.any(o.momentum)

@@ -179,6 +179,22 @@ def test_mass_conserved_tube_and_momentum_gain_periodic():
     assert np.allclose(p1 - p0, n ** 3 * np.array([1e-5, -2e-5, 3e-5]), rtol=1e-11)
 
 
+def test_single_periodic_node_velocity_is_half_force_shifted():
+    # one periodic node: every population streams back onto it, so after n steps of a uniform
+    # force density g the momentum is n g, and the velocity, defined with half the force of the
+    # step (Sec. II A), is (n g - g/2) / rho with rho = 1
+    g = np.array([1e-5, -2e-5, 3e-5])
+    o = orc.Oracle(dict(nx=1, ny=1, nz=1, periodic=(1, 1, 1), tau0=0.8, g_ext=tuple(g)),
+                   np.zeros((1, 1, 1), np.uint8))
+    done = 0
+    for n in (1, 7, 20):
+        o.step(n - done)
+        done = n
+        assert np.allclose(o.u()[0], (n - 0.5) * g, rtol=1e-12, atol=0)
+        assert np.allclose(o.observe()["momentum"], n * g, rtol=1e-12, atol=0)
+        assert o.observe()["mass"] == pytest.approx(1.0, rel=1e-14)
+
+
 def test_taylor_green_decay_rate():
     # 2-D Taylor-Green vortex: kinetic energy decays as exp(-4 nu k^2 t), nu = c^2 (T - 1/2)
     n, nzz, T = 32, 2, 0.8
