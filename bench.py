@@ -68,12 +68,6 @@ def workload(name: str, storage: str):
         # hematocrit is below the 0.40 target and is reported)
         nx, ny, nz, R, H, T0 = 256, 256, 1024, 120.0, 0.40, 0.8
         solid, pl = synth.tube_workload(nx, ny, nz, R, hematocrit=H, seed=1107, fill=False)
-    elif name == "tube256_full":
-        # the same tube filled towards H = 0.40 by random centres and overlap removal, as the
-        # benchmark tube (generating the placement takes most of an hour on 8 host cores the
-        # first time; it is cached afterwards)
-        nx, ny, nz, R, H, T0 = 256, 256, 1024, 120.0, 0.40, 0.8
-        solid, pl = synth.tube_workload(nx, ny, nz, R, hematocrit=H, seed=1107)
     elif name == "bif384":
         # Y-bifurcation 384x384x768, parent R = 48 on the axis up to z = 512, daughters R = 36
         # at +/-30 degrees to the top face; pressure-driven (open z faces, rho 1 +/- 1e-3);
