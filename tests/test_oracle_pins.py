@@ -144,6 +144,45 @@ def test_exchange_conserves_momentum_and_angular_momentum(seed):
     assert np.abs(g2.sum(0)).max() < 1e-12 * np.abs(Th2).max()
 
 
+@pytest.mark.parametrize("seed", [4, 5])
+def test_interpolated_velocity_and_vorticity_of_linear_fields(seed):
+    # Eqs. 16-21: the normalised kernel sums to one over the support, so a uniform flow u0
+    # interpolates to u0 with no vorticity; the central-difference curl is exact on a linear
+    # field, so a rigid rotation u = W x (x - R) gives the smeared vorticity 2 W and the
+    # interpolated velocity W x (first moment of the kernel). The vorticity scale s enters
+    # where the vorticity drives the cell: at rest, with isotropic inertia I and no stress,
+    # the hydrodynamic torque is gamma_R I s (2 W).
+    n = 28
+    rng = np.random.default_rng(seed)
+    R = np.array([[14.0, 14.0, 14.0]]) + rng.random(3)
+    Q = _rot(seed).reshape(1, 9)
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    X = np.stack([x.ravel(), y.ravel(), z.ravel()], 1).astype(float)
+    u0 = np.array([1e-3, -2e-3, 5e-4])
+    W = np.array([2e-4, -1e-4, 3e-4])
+    for scale in (1.0, 0.5):
+        cfg = _periodic_cfg(n, vort_scale=scale, gammaR=0.1, inertia=(1000.0, 1000.0, 1000.0))
+        o = orc.Oracle(cfg, np.zeros((n, n, n), np.uint8), R=R, Q=Q)
+        o.set_fields(u=np.broadcast_to(u0, (n ** 3, 3)).copy())
+        o.couple()
+        cp = o.coupling()[0]
+        assert np.allclose(cp[1:4], u0, rtol=1e-13, atol=0)
+        assert np.abs(cp[4:7]).max() < 1e-16
+        o = orc.Oracle(cfg, np.zeros((n, n, n), np.uint8), R=R, Q=Q)
+        o.set_fields(u=np.cross(W, X - R[0]))
+        o.couple()
+        cp = o.coupling()[0]
+        assert np.allclose(cp[4:7], 2 * W, rtol=1e-12, atol=0)
+        assert np.allclose(cp[13:16], 0.1 * 1000.0 * scale * 2 * W, rtol=1e-12, atol=0)
+        # first moment of the normalised kernel, from the kernel weights the oracle spreads
+        o1 = orc.Oracle(_periodic_cfg(n, delta_visc=1.0, kappa=1.0), np.zeros((n, n, n), np.uint8),
+                        R=R, Q=Q)
+        o1.couple()
+        raw = o1.relax() - 1.0                 # kappa = Delta = 1: T - T0 = raw kernel
+        m1 = (raw[:, None] * (X - R[0])).sum(0) / raw.sum()
+        assert np.allclose(cp[1:4], np.cross(W, m1), rtol=1e-10, atol=1e-20)
+
+
 def test_viscosity_contrast_closed_form():
     # Eq. 23 with nu = c^2 (T - 1/2): nu0 = 1/6 (T0 = 1), Delta = 2, theta -> 1 gives ratio 5
     g = GOLD["viscosity_ratio"]
@@ -229,6 +268,27 @@ def test_plane_poiseuille_curvature():
     prof = ux[1:ny - 1]
     d2 = prof[2:] - 2 * prof[1:-1] + prof[:-2]
     assert np.allclose(d2, -g / nu, rtol=1e-6)
+    assert np.allclose(prof, prof[::-1], rtol=1e-10)
+
+
+def test_pressure_driven_channel_open_planes():
+    # open z planes (the inlet/outlet of Sec. III) held at rho_in and rho_out drive a plane
+    # channel: at steady state the mid-channel profile is Poiseuille's with the pressure
+    # gradient c^2 (rho_in - rho_out) / (nz - 1), walls halfway between the wall and fluid nodes
+    ny, nz, T = 18, 25, 1.0
+    rin, rout = 1.001, 0.999
+    cfg = dict(nx=1, ny=ny, nz=nz, periodic=(1, 0, 0), tau0=T, open_z=1, rho_in=rin, rho_out=rout)
+    o = orc.Oracle(cfg, synth.slab(1, ny, nz))
+    o.step(4000)
+    rho = o.f().reshape(19, nz, ny).sum(0)
+    assert np.allclose(rho[0, 1:ny - 1], rin, rtol=1e-13)
+    assert np.allclose(rho[nz - 1, 1:ny - 1], rout, rtol=1e-13)
+    prof = o.u().reshape(nz, ny, 3)[nz // 2, 1:ny - 1, 2]
+    y = np.arange(1, ny - 1)
+    nu = CS2 * (T - 0.5)
+    G = CS2 * (rin - rout) / (nz - 1)
+    ana = G / (2 * nu) * (y - 0.5) * (ny - 1.5 - y)
+    assert np.abs(prof - ana).max() < 0.01 * ana.max()
     assert np.allclose(prof, prof[::-1], rtol=1e-10)
 
 
