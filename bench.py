@@ -68,13 +68,15 @@ def workload(name: str, storage: str):
         # hematocrit is below the 0.40 target and is reported)
         nx, ny, nz, R, H, T0 = 256, 256, 1024, 120.0, 0.40, 0.8
         solid, pl = synth.tube_workload(nx, ny, nz, R, hematocrit=H, seed=1107, fill=False)
-    elif name == "bif384":
+    elif name in ("bif384", "bif384_full"):
         # Y-bifurcation 384x384x768, parent R = 48 on the axis up to z = 512, daughters R = 36
         # at +/-30 degrees to the top face; pressure-driven (open z faces, rho 1 +/- 1e-3);
-        # cells by random sequential addition only, 16 nodes clear of the open planes
+        # cells 16 nodes clear of the open planes. bif384: random sequential addition only;
+        # bif384_full: filled towards H = 0.45 by random centres and overlap removal, as the
+        # benchmark tube
         nx, ny, nz, H, T0 = 384, 384, 768, 0.45, 0.8
-        solid, pl = synth.bifurcation_workload(nx, ny, nz, 48.0, 36.0, 512.0, H, seed=1107,
-                                               fill=False, rsa_attempts_per_cell=40)
+        kw = {} if name == "bif384_full" else dict(fill=False, rsa_attempts_per_cell=40)
+        solid, pl = synth.bifurcation_workload(nx, ny, nz, 48.0, 36.0, 512.0, H, seed=1107, **kw)
         cfg = dict(nx=nx, ny=ny, nz=nz, periodic=(0, 0, 0), tau0=T0, g_ext=(0.0, 0.0, 0.0),
                    open_z=1, rho_in=1.001, rho_out=0.999, storage=storage, f16_scale=2.0 ** 21)
         desc = (f"Y-bifurcation {nx}x{ny}x{nz} (parent R=48 to z=512, daughters R=36 at "
