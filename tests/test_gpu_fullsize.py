@@ -1,6 +1,7 @@
 """Parity at the benchmark's full size (128x128x512 tube, R = 60, 19,241 cells): the FP64 path
 against the oracle over one coupled step (fields, cells, the node->cell map bit for bit), and
-the FP32 configuration the benchmark times checked by properties that hold at any size."""
+the FP32 configuration the benchmark times checked by properties that hold at any size; the
+256x256x1024 study tube by the same properties in the reduced storages."""
 import numpy as np
 import pytest
 
@@ -76,3 +77,31 @@ def test_fullsize_fp32_bench_config_properties(tube):
     assert r.max() < R
     node, wss = sim.lb_wall_shear_stress(False)
     assert len(node) > 0 and np.all(np.isfinite(wss)) and wss.mean() > 0
+
+
+def test_study_tube_256_properties_in_each_storage():
+    """The largest configuration, the 256x256x1024 study tube (R = 120, 80,451 cells by random
+    sequential addition), in the three reduced storages over 100 steps: no device fault, mass
+    conserved to the storage's round-off, cells inside the tube, a positive flow rate and
+    finite wall shear stress."""
+    from paper_1107_4889_amd import lbrbc
+
+    nx, ny, nz, Rt = 256, 256, 1024, 120.0
+    solid, pl = synth.tube_workload(nx, ny, nz, Rt, hematocrit=0.40, seed=1107, fill=False)
+    cfg = dict(nx=nx, ny=ny, nz=nz, periodic=(0, 0, 1), tau0=0.8, g_ext=(0.0, 0.0, 1e-6),
+               f16_scale=2.0 ** 21)
+    for storage, tol in (("f32", 1e-6), ("bf16", 1e-4), ("f16", 1e-4)):
+        print(f"study tube {nx}x{ny}x{nz}, {len(pl.R)} cells, {storage}, 100 steps", flush=True)
+        sim = lbrbc.Simulation(dict(cfg, storage=storage), solid, R=pl.R, Q=pl.Q)
+        m0 = sim.lb_observe().mass
+        sim.lb_step(100)
+        o = sim.lb_observe()
+        assert o.flags == 0, storage
+        assert abs(o.mass - m0) <= tol * m0, (storage, o.mass, m0)
+        assert o.flow_rate > 0, storage
+        Rc = sim.rbc_get_state()[0]
+        r = np.hypot(Rc[:, 0] - (nx - 1) / 2, Rc[:, 1] - (ny - 1) / 2)
+        assert r.max() < Rt, storage
+        node, wss = sim.lb_wall_shear_stress(False)
+        assert len(node) > 0 and np.all(np.isfinite(wss)), storage
+        del sim
