@@ -75,3 +75,22 @@ def test_too_many_cells_for_coverage_entries():
     with pytest.raises(lbrbc.LbError) as e:
         lbrbc.lb_query_footprint(_cfg(), solid, 1 << 20)
     assert e.value.status == lbrbc.LB_EINVAL
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    # the binding has no fallback: imported from a package folder without liblbrbc.so it
+    # raises ImportError naming the missing library
+    import shutil
+    import subprocess
+    import sys
+
+    pkg = tmp_path / "nolib_pkg"
+    pkg.mkdir()
+    (pkg / "__init__.py").write_text("")
+    src = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_1107_4889_amd", "lbrbc.py")
+    shutil.copy(src, pkg / "lbrbc.py")
+    r = subprocess.run([sys.executable, "-c", "import nolib_pkg.lbrbc"], cwd=tmp_path,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "liblbrbc.so is not built" in r.stderr
