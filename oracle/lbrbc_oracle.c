@@ -20,9 +20,9 @@
  *   8. pull stream + BGK collision with body force (Eqs. 1-8), halfway bounce-back
  * Steps 4 uses the velocity and stress stored by step 8 of the previous step.
  *
- * Parity unpinned: the stress torque T^S of step 4 (Eq. 16). No closed form or invariant
- * fixes it, so the tests check every other stage against the mathematics but this one only
- * against the GPU path.
+ * Parity partly unpinned: the stress torque T^S of step 4 (Eq. 16). Its symmetries, its sign
+ * and its linearity in alpha are pinned; no closed form fixes its magnitude, which the tests
+ * check only against the GPU path.
  */
 #include "lbrbc_oracle.h"
 

@@ -183,6 +183,36 @@ def test_interpolated_velocity_and_vorticity_of_linear_fields(seed):
         assert np.allclose(cp[1:4], np.cross(W, m1), rtol=1e-10, atol=1e-20)
 
 
+def test_stress_torque_symmetries_and_sign():
+    # T^S of Eq. 16 on the benchmark's oblate cell (semi-axes 4, 4, 1.5, short axis along z),
+    # axis-aligned and centred on a node, in a uniform stress. By the cell's symmetries an
+    # isotropic stress and a shear stress in the plane of the two long axes give no torque.
+    # A shear stress sigma_xz = s > 0 stretches along (1, 0, 1): the elongational torque turns
+    # the long axis x towards it, a rotation about -y, so T_y < 0 with T_x = T_z = 0.
+    # sigma_yz gives the same torque turned by 90 degrees about z, and T^S is linear in alpha.
+    n, s = 24, 1e-3
+    R, Q = np.array([[12.0, 12.0, 12.0]]), np.eye(3).reshape(1, 9)
+
+    def ts(alpha, stress):
+        o = orc.Oracle(_periodic_cfg(n, alpha=alpha), np.zeros((n, n, n), np.uint8), R=R, Q=Q)
+        sig = np.zeros((n ** 3, 6))           # xx yy zz xy xz yz
+        for k, v in stress.items():
+            sig[:, k] = v
+        o.set_fields(sigma=sig)
+        o.couple()
+        return o.coupling()[0, 7:10]
+
+    t_xz = ts(0.04, {4: s})
+    ref = abs(t_xz[1])
+    assert t_xz[1] < 0 and ref > 1e-8
+    assert abs(t_xz[0]) < 1e-12 * ref and abs(t_xz[2]) < 1e-12 * ref
+    assert np.abs(ts(0.04, {3: s})).max() < 1e-12 * ref
+    assert np.abs(ts(0.04, {0: s, 1: s, 2: s})).max() < 1e-12 * ref
+    t_yz = ts(0.04, {5: s})
+    assert np.allclose(t_yz, [-t_xz[1], 0.0, 0.0], rtol=1e-12, atol=1e-12 * ref)
+    assert np.allclose(ts(0.08, {4: s}), 2 * t_xz, rtol=1e-12, atol=1e-12 * ref)
+
+
 def test_viscosity_contrast_closed_form():
     # Eq. 23 with nu = c^2 (T - 1/2): nu0 = 1/6 (T0 = 1), Delta = 2, theta -> 1 gives ratio 5
     g = GOLD["viscosity_ratio"]
