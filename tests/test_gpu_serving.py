@@ -142,3 +142,46 @@ def test_fused_server_matches_alone():
     mixed, _ = Server(budget_bytes=8 << 30, chunk_steps=16, digests=True, fused=True).run(reqs)
     for m in mixed:
         assert m.digest == alone[m.rid] and m.flags == 0
+
+
+def test_interleaved_batch_with_open_boundaries_equals_each_alone():
+    """A context with open z faces cannot join a fused launch, so lb_batch_step interleaves the
+    contexts step by step on their own streams instead; each still ends bitwise where it ends
+    when stepped alone, also when the contexts share one stream."""
+    import hashlib
+
+    import torch
+
+    from paper_1107_4889_amd import lbrbc
+
+    reqs = _requests(1, seed=81, steps=(30, 30))
+    solid = synth.tube(24, 24, 40, 10.0)
+    Q = synth.random_rotations(np.random.default_rng(17), 3).reshape(3, 9)
+    R = np.array([[11.5, 11.5, 2.0], [11.5, 11.5, 37.2], [11.0, 12.0, 20.0]])
+    open_cfg = dict(nx=24, ny=24, nz=40, periodic=(0, 0, 0), tau0=0.8, open_z=1, rho_in=1.002,
+                    rho_out=0.998, storage="f32")
+    cases = [(open_cfg, solid, R, Q), (reqs[0].cfg, reqs[0].solid, reqs[0].R, reqs[0].Q)]
+    nsteps = [25, 35]
+    print("interleaved batch: open-boundary tube with 3 cells beside a periodic request",
+          flush=True)
+
+    def digest(sim):
+        return hashlib.sha1(sim.lb_save()[56:]).hexdigest()
+
+    alone = []
+    for (cfg, sd, Rc, Qc), n in zip(cases, nsteps):
+        sim = lbrbc.Simulation(cfg, sd, R=Rc, Q=Qc)
+        sim.lb_step(n)
+        sim.lb_sync()
+        alone.append(digest(sim))
+        del sim
+    for shared in (False, True):
+        one = torch.cuda.Stream()
+        sims = [lbrbc.Simulation(cfg, sd, R=Rc, Q=Qc, stream=one if shared else torch.cuda.Stream())
+                for cfg, sd, Rc, Qc in cases]
+        lbrbc.lb_batch_step(sims, nsteps)
+        torch.cuda.synchronize()
+        for k, (sim, d) in enumerate(zip(sims, alone)):
+            assert sim.lb_observe().flags == 0
+            assert digest(sim) == d, (shared, k)
+        del sims
