@@ -299,6 +299,15 @@ def test_plane_poiseuille_curvature():
     d2 = prof[2:] - 2 * prof[1:-1] + prof[:-2]
     assert np.allclose(d2, -g / nu, rtol=1e-6)
     assert np.allclose(prof, prof[::-1], rtol=1e-10)
+    # the momentum balance d(sigma_xy)/dy = -g fixes the viscous stress, rho nu du/dy, exactly:
+    # sigma_xy(y) = g ((ny - 1)/2 - y) at the fluid nodes, and the wall shear stress at the two
+    # wall-adjacent nodes is g (ny - 3)/2
+    y = np.arange(1, ny - 1)
+    sxy = o.sigma()[1:ny - 1, 3]
+    assert np.allclose(sxy, g * ((ny - 1) / 2 - y), rtol=1e-9, atol=1e-9 * g)
+    node, wss = o.wall_shear_stress()
+    assert list(node) == [1, ny - 2]
+    assert np.allclose(wss, g * (ny - 3) / 2, rtol=1e-9)
 
 
 def test_pressure_driven_channel_open_planes():
