@@ -63,7 +63,20 @@ def test_plane_poiseuille_single_column(lb):
     ref.step(3000)
     sim = lb.Simulation(dict(cfg, storage="f64"), solid)
     sim.lb_step(3000)
-    assert rel(sim.lb_get_fields()["u"], ref.u()) < 1e-11
+    d = sim.lb_get_fields()
+    assert rel(d["u"], ref.u()) < 1e-11
+    assert rel(d["sigma"], ref.sigma()) < 1e-10
+    node, wss = sim.lb_wall_shear_stress(False)
+    node_o, wss_o = ref.wall_shear_stress()
+    assert np.array_equal(node, node_o) and rel(wss, wss_o) < 1e-10
+    # at steady state the stress is the momentum balance's exact one: sigma_xy = g ((ny-1)/2 - y),
+    # wall shear stress g (ny - 3)/2 at both wall-adjacent nodes
+    g = cfg["g_ext"][0]
+    sim.lb_step(27000)
+    y = np.arange(1, ny - 1)
+    sxy = sim.lb_get_fields(f=False, u=False)["sigma"][1:ny - 1, 3]
+    assert np.allclose(sxy, g * ((ny - 1) / 2 - y), rtol=1e-9, atol=1e-9 * g)
+    assert np.allclose(sim.lb_wall_shear_stress(False)[1], g * (ny - 3) / 2, rtol=1e-9)
 
 
 def test_cell_list_and_map_bit_exact(lb, small):
