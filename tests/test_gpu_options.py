@@ -164,3 +164,21 @@ def test_bf16_stochastic_rounding_keeps_slow_flow(lb):
     # measured on the MI355X: 0.0010 with stochastic rounding, 0.083 with rounding to nearest
     assert err["sr"] < 0.01, err
     assert err["rne"] > 10 * err["sr"], err
+
+
+def test_fp16_scale_too_large_is_reported(lb):
+    # FP16 storage keeps scale * (f - w): a scale far too large for the flow overflows the
+    # stored populations to infinity, the next update finds a non-finite velocity, and the
+    # fault is reported and poisons the context like any other instability
+    nx = ny = nz = 16
+    cfg = dict(nx=nx, ny=ny, nz=nz, periodic=(0, 0, 1), tau0=0.8, g_ext=(0, 0, 1e-5),
+               storage="f16", f16_scale=2.0 ** 40)
+    print("[options] f16 scale 2^40 on a driven tube", flush=True)
+    sim = lb.Simulation(cfg, synth.tube(nx, ny, nz, 6.0))
+    sim.lb_step(3)
+    with pytest.raises(lb.LbError) as e:
+        sim.lb_sync()
+    assert e.value.status == lb.LB_EUNSTABLE
+    with pytest.raises(lb.LbError) as e:
+        sim.lb_step(1)
+    assert e.value.status == lb.LB_ESTATE
