@@ -63,7 +63,8 @@ typedef struct lb_config {
     int periodic[3];      /* 1: periodic axis; 0: box faces are walls (outside = solid) */
     int storage;          /* lb_storage of the shifted populations f - w; F64 computes in
                              double, the others in float */
-    double f16_scale;     /* LB_F16: stored value = scale * (f - w); a power of two */
+    double f16_scale;     /* LB_F16: stored value = scale * (f - w); a power of two in
+                             [2^-100, 2^100], else LB_EINVAL */
     int forcing;          /* 0: second-order (Guo) body-force term; 1: Eq. 4 as printed */
     double tau0;          /* plasma relaxation time T0 > 1/2 (nu = (T0 - 1/2)/3) */
     double delta_visc;    /* viscosity enhancement Delta (Eq. 23) */

@@ -165,7 +165,13 @@ std::string validate(const lb_config& c, int n_rbc)
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(c.ext_force[a]) || !std::isfinite(c.ext_torque[a]))
             return "ext_force and ext_torque must be finite";
-    if (c.storage == LB_F16 && !(c.f16_scale > 0)) return "f16_scale must be positive";
+    if (c.storage == LB_F16) {
+        // a power of two between 2^-100 and 2^100: scaling and unscaling are then exact in float
+        int e = 0;
+        if (!(c.f16_scale > 0) || !std::isfinite(c.f16_scale) || std::frexp(c.f16_scale, &e) != 0.5 ||
+            e < -99 || e > 101)
+            return "f16_scale must be a power of two between 2^-100 and 2^100";
+    }
     if (c.open_z && c.periodic[2]) return "open z faces need a non-periodic z axis";
     if (c.open_z && c.nz < 3) return "open z faces need nz >= 3";
     if ((long long)c.nx * c.ny * c.nz >= (1LL << 32) - (1LL << 20))

@@ -39,8 +39,11 @@ def test_footprint_and_validation_on_host():
     b16 = lbrbc.lb_query_footprint(_cfg(storage="bf16"), solid, 10)
     N = 16 * 16 * 32
     assert b64 > b32 > b16 >= 2 * 19 * N * 2
+    for ok in (2.0 ** 21, 2.0 ** -100, 2.0 ** 100, 1.0):
+        assert lbrbc.lb_query_footprint(_cfg(storage="f16", f16_scale=ok), solid, 10) > 0
     for bad in (dict(tau0=0.5), dict(map_cap=13), dict(storage=7), dict(open_z=1),
-                dict(nx=0), dict(xi=(0, 1, 1))):
+                dict(nx=0), dict(xi=(0, 1, 1)), dict(storage="f16", f16_scale=3.0),
+                dict(storage="f16", f16_scale=0.0), dict(storage="f16", f16_scale=2.0 ** 101)):
         with pytest.raises(lbrbc.LbError) as e:
             lbrbc.lb_query_footprint(_cfg(**bad), solid, 10)
         assert e.value.status == lbrbc.LB_EINVAL
