@@ -64,19 +64,15 @@ def workload(name: str, storage: str):
         nx, ny, nz, R, H, T0 = 128, 128, 512, 60.0, 0.0, 0.8
         solid, pl = synth.tube_workload(nx, ny, nz, R, n_cells=0, seed=1107)
     elif name == "tube256":
-        # the 256x256x1024 study tube (random sequential addition only: the achieved
-        # hematocrit is below the 0.40 target and is reported)
+        # the 256x256x1024 study tube at hematocrit 0.40
         nx, ny, nz, R, H, T0 = 256, 256, 1024, 120.0, 0.40, 0.8
-        solid, pl = synth.tube_workload(nx, ny, nz, R, hematocrit=H, seed=1107, fill=False)
-    elif name in ("bif384", "bif384_full"):
+        solid, pl = synth.tube_workload(nx, ny, nz, R, hematocrit=H, seed=1107)
+    elif name == "bif384":
         # Y-bifurcation 384x384x768, parent R = 48 on the axis up to z = 512, daughters R = 36
         # at +/-30 degrees to the top face; pressure-driven (open z faces, rho 1 +/- 1e-3);
-        # cells 16 nodes clear of the open planes. bif384: random sequential addition only;
-        # bif384_full: filled towards H = 0.45 by random centres and overlap removal, as the
-        # benchmark tube
+        # cells at hematocrit 0.45, 16 nodes clear of the open planes
         nx, ny, nz, H, T0 = 384, 384, 768, 0.45, 0.8
-        kw = {} if name == "bif384_full" else dict(fill=False, rsa_attempts_per_cell=40)
-        solid, pl = synth.bifurcation_workload(nx, ny, nz, 48.0, 36.0, 512.0, H, seed=1107, **kw)
+        solid, pl = synth.bifurcation_workload(nx, ny, nz, 48.0, 36.0, 512.0, H, seed=1107)
         cfg = dict(nx=nx, ny=ny, nz=nz, periodic=(0, 0, 0), tau0=T0, g_ext=(0.0, 0.0, 0.0),
                    open_z=1, rho_in=1.001, rho_out=0.999, storage=storage, f16_scale=2.0 ** 21)
         desc = (f"Y-bifurcation {nx}x{ny}x{nz} (parent R=48 to z=512, daughters R=36 at "
@@ -381,7 +377,7 @@ def observables(args):
 
 
 def mobility(args):
-    """Single-cell mobilities (Sec. IV): a lone cell in a periodic 60^3 box of quiescent plasma
+    """Single-cell mobilities (Sec. III): a lone cell in a periodic 60^3 box of quiescent plasma
     (no viscosity contrast, M = 10, I = 1000, shape-function radii 2, 2, 1 with the short one
     on the symmetry axis), driven by a constant external force along the symmetry axis
     (frontal) or along a long axis (side-wise), or spun by a constant torque about the same
@@ -457,7 +453,7 @@ def mobility(args):
                 rec["gammaR_mesh"] = float(1.0 / (1000.0 * icpt)) if icpt > 0 else None
         out[kind] = rec
     line = {
-        "metric": "single-cell mobilities at infinite coupling (Sec. IV)",
+        "metric": "single-cell mobilities at infinite coupling (Sec. III)",
         "config": {"workload": f"lone cell, periodic {n}^3 plasma at rest, T0=1.0 (nu=1/6), Delta=0, "
                                f"xi=(2,2,1), M=10, I=1000; force {F} (gR=0.01), torque {T} (gT=0.01); "
                                f"{steps} steps per run; FP64 storage"},

@@ -64,7 +64,11 @@ typedef struct lb_config {
     int storage;          /* lb_storage of the shifted populations f - w; F64 computes in
                              double, the others in float */
     double f16_scale;     /* LB_F16: stored value = scale * (f - w); a power of two in
-                             [2^-100, 2^100], else LB_EINVAL */
+                             [2^10, 2^40], else LB_EINVAL. Below about 2^10 the populations of a
+                             slow flow (|f - w| ~ 1e-5) fall into FP16's subnormal range and
+                             their per-step increments round to zero without any error; above
+                             2^17 a fast flow (|f - w| ~ 0.3) overflows, which the step reports
+                             as LB_EUNSTABLE */
     int forcing;          /* 0: second-order (Guo) body-force term; 1: Eq. 4 as printed */
     double tau0;          /* plasma relaxation time T0 > 1/2 (nu = (T0 - 1/2)/3) */
     double delta_visc;    /* viscosity enhancement Delta (Eq. 23) */
@@ -88,9 +92,13 @@ typedef struct lb_config {
                              a hash of node, direction and value, so results stay deterministic);
                              1 = round to nearest even, which loses the increments of slow flows */
     double ext_force[3];  /* constant external force on every cell, lab frame, added to the
-                             combined force (drag experiments of Sec. IV; 0 = none) */
+                             combined force (drag experiments of Sec. III; 0 = none) */
     double ext_torque[3]; /* constant external torque on every cell, body frame, added to the
-                             combined torque (spin experiments of Sec. IV; 0 = none) */
+                             combined torque (spin experiments of Sec. III; 0 = none) */
+    int cand_cap;         /* test hook: candidate nodes per cell that the one-wavefront map pass
+                             holds (0 = a sampled bound, above every orientation met in
+                             practice). Smaller values, raised to at least tile_max^2, send
+                             more cells to the full-tile pass; the results do not change */
 } lb_config;
 
 typedef struct lb_rbc {
@@ -130,21 +138,34 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
 lb_status lb_step(lb_ctx ctx, int nsteps);
 
 /* Coupling only, at the current state, no time advance (asynchronous): cell list,
- * coverage map, interpolation sums, hydrodynamic force/torque from the current V and
- * Omega, and the spread force density and local relaxation time per node (readable with
- * lb_get_fields). */
+ * coverage map (the support of Sec. II B, Eqs. 10-12, plus the one-node halo of its
+ * central-difference gradient), interpolation sums S, u~, w~, T^S (Sec. II B, Eqs. 16-21;
+ * Sec. II C, Eq. 16 for T^S), hydrodynamic force/torque from the current V and Omega
+ * (Eqs. 14-15), and the spread force density G (Sec. II B, back-reaction) and local
+ * relaxation time (Sec. II D, Eq. 23) per node, readable with lb_get_fields. */
 lb_status rbc_couple(lb_ctx ctx);
 
-/* Cell list and Gay-Berne forces at the current positions (synchronous).
- * F: host [3*n_rbc] lab force; T: host [3*n_rbc] body-frame torque. Either may be NULL. */
+/* Cell list and Gay-Berne cell-cell and cell-wall forces and torques at the current
+ * positions (Sec. II E, Eqs. 24-28; App. B, with the torques of App. B corrected as stated
+ * in the library's notes: tau_i = (1/R) R_ci x f_k, tau_j = -(1/R) R_cj x f_k); synchronous.
+ * F: host [3*n_rbc] lab force; T: host [3*n_rbc] body-frame torque. Either may be NULL.
+ * A pair at rho_ij <= 0 returns LB_EOVERLAP. */
 lb_status rbc_collide(lb_ctx ctx, double* F, double* T);
 
-/* Synchronous reads. */
+/* Synchronous reads of the observables of Sec. III: mass and momentum (sums of f and f c
+ * over fluid nodes, Eqs. 5-6), the flow rate Q (mean over z-slices of the summed u_z), the
+ * apparent viscosity pi R^4 g / (8 Q) of a body-force-driven tube (Poiseuille's law, which
+ * the paper's viscosity comparisons assume) and the wall shear stress of
+ * lb_wall_shear_stress. FP64 reductions in a fixed order. */
 lb_status lb_observe(lb_ctx ctx, lb_observables* out);
-/* Wall shear stress at each wall-adjacent fluid node, ascending node index. wss: host
- * [*n] or NULL to query the count; node: host [*n] or NULL. With time != 0, the time
- * average since lb_wss_accumulate(ctx, 1). */
+/* Wall shear stress at each wall-adjacent fluid node (the quantity Sec. III reports for the
+ * bifurcation), from the deviatoric stress of Eq. 8: with the wall normal n_w =
+ * normalize(sum over solid neighbours x + c_p of w_p c_p) and the traction t = sigma n_w,
+ * WSS = |t - (t . n_w) n_w|, in FP64. Ascending node index. wss: host [*n] or NULL to query
+ * the count; node: host [*n] or NULL. With time != 0, the time average since
+ * lb_wss_accumulate(ctx, 1). */
 lb_status lb_wall_shear_stress(lb_ctx ctx, int time, double* wss, long long* node, int* n);
+/* The apparent viscosity of lb_observe alone (Sec. III, the viscosity of a tube flow). */
 lb_status lb_apparent_viscosity(lb_ctx ctx, double* eta_app);
 /* Start (on != 0, resetting the sums) or stop per-step FP64 accumulation of the WSS. */
 lb_status lb_wss_accumulate(lb_ctx ctx, int on);
@@ -175,7 +196,9 @@ lb_status rbc_get_map(lb_ctx ctx, int* off, int* ids, long long* len);
 lb_status lb_save(lb_ctx ctx, void* buf, size_t* bytes);
 lb_status lb_load(lb_ctx ctx, const void* buf, size_t bytes);
 
-/* Serving: enqueue nsteps[i] steps for each of n contexts (asynchronous).
+/* Serving (not in the paper, whose method is one simulation at a time): enqueue nsteps[i]
+ * steps of the same coupled time step (the steps of lb_step) for each of n contexts
+ * (asynchronous).
  * - When all contexts share one stream and one storage type, and none has open boundaries,
  *   WSS accumulation or kernel timing on, each stage of a step is ONE launch over all the
  *   contexts still stepping (fused multi-lattice kernels, up to 64 contexts per launch);
@@ -192,14 +215,25 @@ lb_status lb_batch_step(lb_ctx* ctxs, const int* nsteps, int n);
  * to take a finished one off it. NULL context or stream: LB_EINVAL. */
 lb_status lb_set_stream(lb_ctx ctx, void* hip_stream);
 
+/* Second stream for the cells' own work (no paper passage: scheduling only). With 2048 or
+ * more cells a step runs the Gay-Berne pass, and after the map pass the kick and the next
+ * step's first half and cell list, on a second stream beside the stream-collide, ordered by
+ * events. By default the library creates that stream at lb_init (default priority); this
+ * call hands it a caller-owned one instead (e.g. a torch stream), which must outlive the
+ * context, or, with NULL, runs every kernel on the main stream. Results are bitwise the same
+ * in every case. Synchronises the context's streams first. */
+lb_status lb_set_side_stream(lb_ctx ctx, void* hip_stream);
+
 /* Wait for the context's stream and report device faults (LB_EUNSTABLE, LB_EOVERLAP,
  * LB_ECAPACITY) raised since the last check; after a fault the context is poisoned. */
 lb_status lb_sync(lb_ctx ctx);
 const char* lb_last_error(lb_ctx ctx);
 void lb_destroy(lb_ctx ctx);
 
-/* Average device duration (ms) of the stream-collide kernel over the last lb_step call
- * that was timed (lb_set_timing(ctx, 1)); 0 if none. */
+/* Measurement (no paper passage): with lb_set_timing(ctx, 1), HIP events on the main stream
+ * bracket every stream-collide launch and the whole lb_step calls; lb_kernel_time gives the
+ * average stream-collide duration and the average step duration (ms) since timing was
+ * switched on, 0 if none. */
 lb_status lb_set_timing(lb_ctx ctx, int on);
 lb_status lb_kernel_time(lb_ctx ctx, double* sc_ms, double* step_ms);
 

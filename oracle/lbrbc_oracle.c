@@ -849,7 +849,7 @@ static int collide_all(orc_sim* s, int brute)
  * T^A = -gR I (Omega - Q^T w~)), as the integrator's M gT u~ and I gR w~ terms require;
  * and tau^comb includes the elongational torque Q^T T^S, without which alpha would have
  * no effect on the cell. A constant external force (lab) and torque (body) on every cell,
- * as a drag experiment applies (Sec. IV, single-cell mobilities), add to the mechanical
+ * as a drag experiment applies (Sec. III, single-cell mobilities), add to the mechanical
  * ones. */
 static void combined(const orc_sim* s, int i, double Fc[3], double Tc[3])
 {

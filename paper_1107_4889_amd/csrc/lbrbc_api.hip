@@ -51,6 +51,18 @@ struct Geometry {
     int ent_shift = 0;
 };
 
+// FNV-1a over the node words
+unsigned long long geometry_hash(const Geometry& g)
+{
+    unsigned long long h = 1469598103934665603ull;
+    for (uint32_t w : g.nodeword)
+        for (int b = 0; b < 4; ++b) {
+            h ^= (w >> (8 * b)) & 0xffu;
+            h *= 1099511628211ull;
+        }
+    return h;
+}
+
 // Capacity of the one-wavefront map pass: the largest number of candidate nodes (the
 // covered x-range of every support-tile row, computed as the kernel does) over 4096
 // orientations and sub-node offsets from a fixed generator, with 20% and 64 nodes of margin;
@@ -166,16 +178,26 @@ std::string validate(const lb_config& c, int n_rbc)
         if (!std::isfinite(c.ext_force[a]) || !std::isfinite(c.ext_torque[a]))
             return "ext_force and ext_torque must be finite";
     if (c.storage == LB_F16) {
-        // a power of two between 2^-100 and 2^100: scaling and unscaling are then exact in float
+        // a power of two (scaling and unscaling are then exact in float) between 2^10, below
+        // which slow flows underflow into FP16 subnormals without any error, and 2^40
         int e = 0;
         if (!(c.f16_scale > 0) || !std::isfinite(c.f16_scale) || std::frexp(c.f16_scale, &e) != 0.5 ||
-            e < -99 || e > 101)
-            return "f16_scale must be a power of two between 2^-100 and 2^100";
+            e < 11 || e > 41)
+            return "f16_scale must be a power of two between 2^10 and 2^40";
     }
+    if (c.cand_cap < 0) return "cand_cap must be non-negative";
     if (c.open_z && c.periodic[2]) return "open z faces need a non-periodic z axis";
     if (c.open_z && c.nz < 3) return "open z faces need nz >= 3";
-    if ((long long)c.nx * c.ny * c.nz >= (1LL << 32) - (1LL << 20))
-        return "at most 2^32 - 2^20 nodes (32-bit node offsets in a plane)";
+    {
+        // The kernels address every per-node plane (populations, u, sigma, coverage counts
+        // and slots) as a base plus a 32-bit byte offset node * element size: the padded plane
+        // must stay below 4 GiB. FP64 planes hold 8-byte elements, the others at most 4.
+        const long long N = (long long)c.nx * c.ny * c.nz;
+        const long long elem = c.storage == LB_F64 ? 8 : 4;
+        if ((N + 4096) * elem >= (1LL << 32))
+            return c.storage == LB_F64 ? "at most 2^29 - 4096 nodes with FP64 storage (32-bit plane offsets)"
+                                       : "at most 2^30 - 4096 nodes (32-bit plane offsets)";
+    }
     if (n_rbc < 0) return "negative cell count";
     if (n_rbc >= (1 << 27)) return "at most 2^27 - 1 cells (coverage sort keys)";
     if (n_rbc > 0) {
@@ -318,6 +340,10 @@ std::string build_geometry(const lb_config& c, const uint8_t* solid, int n_rbc, 
         // 2-byte position list in LDS, next to about 3.5 KiB of fixed arrays; the
         // one-wavefront pass keeps cand_cap candidates. Both within 64 KiB per workgroup.
         g.cand_cap = candidate_capacity(c.xi, g.tile_max);
+        // test hook: a smaller capacity sends more cells to the full-tile pass
+        if (c.cand_cap > 0)
+            g.cand_cap = std::min(std::max(c.cand_cap, g.tile_max * g.tile_max),
+                                  g.tile_max * g.tile_max * g.tile_max);
         // Coverage entries per cell: covered nodes lie within one node (on each axis) of the
         // support box 2 xi; each such lattice node's unit cube lies in the box grown by 1.5 on
         // each axis, which lies in the box grown by the ball of radius 1.5 sqrt(3). Steiner's
@@ -409,6 +435,7 @@ struct lb_ctx_s {
     lb_config cfg;
     KParams kp;
     Geometry geo;
+    unsigned long long geo_hash = 0;
     Layout lay;
     hipStream_t stream = nullptr;
     // Side stream (default priority) for the cells' own work, for large cell counts: the
@@ -416,6 +443,7 @@ struct lb_ctx_s {
     // kick and, within one lb_step call, the next step's first half and cell list, all
     // overlapping the stream-collide. Events order the two streams.
     hipStream_t side = nullptr;
+    bool side_owned = false;   // created by lb_init (else the caller's, from lb_set_side_stream)
     hipEvent_t ev_cells = nullptr, ev_gb = nullptr, ev_map = nullptr;
     // the current step's first half, cell list and Gay-Berne are already on the side stream
     bool cells_ahead = false;
@@ -471,8 +499,9 @@ void release_side(lb_ctx c)
             (void)hipEventDestroy(*ev);
             *ev = nullptr;
         }
-    if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->side && c->side_owned) (void)hipStreamDestroy(c->side);
     c->side = nullptr;
+    c->side_owned = false;
 }
 
 // message of the last lb_init / lb_query_footprint failure (no context exists then)
@@ -777,6 +806,7 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
     if ((reinterpret_cast<uintptr_t>(arena) % ALIGN) != 0)
         return init_fail(c, LB_EINVAL, "arena must be 256-byte aligned");
     c->lay = layout(c->cfg, c->geo, n_rbc);
+    c->geo_hash = geometry_hash(c->geo);
     if (arena_bytes < c->lay.total) return init_fail(c, LB_ENOMEM, "arena smaller than the footprint");
     c->stream = (hipStream_t)hip_stream;
     c->base = (char*)arena;
@@ -912,6 +942,7 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
     if (err & ERR_OVERLAP) return init_fail(c, LB_EOVERLAP, "Gay-Berne pair at rho <= 0 in the initial state");
     if (n_rbc >= SIDE_STREAM_MIN_CELLS) {
         e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+        c->side_owned = e == hipSuccess;
         for (hipEvent_t* ev : {&c->ev_cells, &c->ev_gb, &c->ev_map})
             if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
         if (e != hipSuccess) {
@@ -1005,6 +1036,25 @@ lb_status lb_set_stream(lb_ctx c, void* hip_stream)
 {
     if (!c || !hip_stream) return LB_EINVAL;
     c->stream = (hipStream_t)hip_stream;
+    return LB_OK;
+}
+
+lb_status lb_set_side_stream(lb_ctx c, void* hip_stream)
+{
+    if (!c) return LB_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    release_side(c);
+    c->cells_ahead = false;
+    if (!hip_stream) return LB_OK;
+    c->side = (hipStream_t)hip_stream;
+    c->side_owned = false;
+    for (hipEvent_t* ev : {&c->ev_cells, &c->ev_gb, &c->ev_map}) {
+        hipError_t e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            release_side(c);
+            return fail(c, LB_EHIP, std::string("side stream events: ") + hipGetErrorString(e));
+        }
+    }
     return LB_OK;
 }
 
@@ -1279,11 +1329,18 @@ lb_status rbc_get_map(lb_ctx c, int* off, int* ids, long long* len)
 }
 
 // checkpoint: header, populations (storage precision), u, sigma, cell states, WSS sums
+// Version 2 also records the lattice shape, the FP16 scale, the BF16 rounding mode and a
+// hash of the node words (geometry and boundary flags): a checkpoint loads only into a context
+// whose stored populations mean the same thing.
+constexpr int CKPT_VERSION = 2;
 struct CkptHeader {
     char magic[8];
     int version, storage, nrbc, nwn;
     long long N, step, wss_count;
-    int wss_on, pad;
+    int wss_on, bf16_nearest;
+    int nx, ny, nz, pad;
+    double f16_scale;
+    unsigned long long geom_hash;
 };
 
 lb_status lb_save(lb_ctx c, void* buf, size_t* bytes)
@@ -1301,8 +1358,14 @@ lb_status lb_save(lb_ctx c, void* buf, size_t* bytes)
     lb_status st = check_fault(c);
     CkptHeader h{};
     std::memcpy(h.magic, "LBRBCCK1", 8);
-    h.version = 1;
+    h.version = CKPT_VERSION;
     h.storage = c->cfg.storage;
+    h.bf16_nearest = c->cfg.bf16_nearest;
+    h.nx = c->cfg.nx;
+    h.ny = c->cfg.ny;
+    h.nz = c->cfg.nz;
+    h.f16_scale = c->cfg.storage == LB_F16 ? c->cfg.f16_scale : 0.0;
+    h.geom_hash = c->geo_hash;
     h.nrbc = c->nrbc;
     h.nwn = (int)c->geo.wn_node.size();
     h.N = c->kp.N;
@@ -1333,10 +1396,15 @@ lb_status lb_load(lb_ctx c, const void* buf, size_t bytes)
     const size_t ld = (size_t)c->kp.ld;
     const size_t fb = 19 * ld * storage_bytes(c->cfg.storage), rb = 9 * ld * real_bytes(c->cfg.storage);
     const size_t sb = c->nrbc * sizeof(RbcState), wb = c->geo.wn_node.size() * 8;
-    if (std::memcmp(h.magic, "LBRBCCK1", 8) != 0 || h.storage != c->cfg.storage || h.nrbc != c->nrbc ||
-        h.N != c->kp.N || h.nwn != (int)c->geo.wn_node.size() ||
+    if (std::memcmp(h.magic, "LBRBCCK1", 8) != 0 || h.version != CKPT_VERSION)
+        return fail(c, LB_EINVAL, "not a checkpoint of this library version");
+    if (h.storage != c->cfg.storage || h.nrbc != c->nrbc || h.N != c->kp.N ||
+        h.nwn != (int)c->geo.wn_node.size() || h.nx != c->cfg.nx || h.ny != c->cfg.ny ||
+        h.nz != c->cfg.nz || h.bf16_nearest != c->cfg.bf16_nearest ||
+        h.f16_scale != (c->cfg.storage == LB_F16 ? c->cfg.f16_scale : 0.0) || h.geom_hash != c->geo_hash ||
         bytes < sizeof h + fb + rb + sb + wb)
-        return fail(c, LB_EINVAL, "checkpoint does not match this context");
+        return fail(c, LB_EINVAL, "checkpoint does not match this context (storage, scale, rounding, "
+                                  "lattice shape, geometry or cell count)");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const char* p = (const char*)buf + sizeof h;
     HIPCHK(c, hipMemcpy(c->fA, p, fb, hipMemcpyHostToDevice));

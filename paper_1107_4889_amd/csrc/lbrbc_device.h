@@ -100,8 +100,9 @@ struct alignas(16) Gather {
 
 // ---- storage conversions ------------------------------------------------------------------
 // Loads and stores take a per-plane base (scalar registers) and a 32-bit element offset; the
-// byte offset is formed in 32 bits so that the access is base + zero-extended offset (every
-// plane is far below 4 GiB).
+// byte offset i * sizeof(T) is formed in 32 bits so that the access is base + zero-extended
+// offset. lb_init rejects lattices whose padded planes would reach 4 GiB (more than
+// 2^29 - 4096 nodes with 8-byte elements, 2^30 - 4096 otherwise), so the offset never wraps.
 struct bf16_t { uint16_t v; };
 
 template <typename T>

@@ -28,7 +28,8 @@ STORAGE = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
 SYMBOLS = ["lb_query_footprint", "lb_init", "lb_step", "rbc_couple", "rbc_collide", "lb_observe",
            "lb_wall_shear_stress", "lb_apparent_viscosity", "lb_wss_accumulate", "lb_get_fields",
            "lb_set_fields", "rbc_get_state", "rbc_set_state", "rbc_get_coupling", "rbc_get_cells",
-           "rbc_get_map", "lb_save", "lb_load", "lb_batch_step", "lb_set_stream", "lb_sync",
+           "rbc_get_map", "lb_save", "lb_load", "lb_batch_step", "lb_set_stream", "lb_set_side_stream",
+           "lb_sync",
            "lb_last_error",
            "lb_destroy", "lb_set_timing", "lb_kernel_time"]
 
@@ -53,6 +54,7 @@ class lb_config(ctypes.Structure):
         ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double), ("map_cap", ctypes.c_int),
         ("bf16_nearest", ctypes.c_int),
         ("ext_force", ctypes.c_double * 3), ("ext_torque", ctypes.c_double * 3),
+        ("cand_cap", ctypes.c_int),
     ]
 
 
@@ -82,6 +84,7 @@ _sig = {
                 ctypes.c_size_t, _P, ctypes.POINTER(_P)],
     "lb_step": [_P, ctypes.c_int],
     "lb_set_stream": [_P, _P],
+    "lb_set_side_stream": [_P, _P],
     "rbc_couple": [_P],
     "rbc_collide": [_P, _D, _D],
     "lb_observe": [_P, ctypes.POINTER(lb_observables)],
@@ -121,7 +124,7 @@ DEFAULTS = dict(periodic=(0, 0, 1), storage="f32", f16_scale=2.0 ** 21, forcing=
                 alpha=0.04, mass=10.0, inertia=(1000.0, 1000.0, 1000.0), vort_scale=1.0,
                 xi=(4.0, 4.0, 1.5), axes=(4.0, 4.0, 1.5), eps0=1e-3, a_wall=0.5, sigmin_wall=0.5,
                 wall_particles=1, open_z=0, rho_in=1.0, rho_out=1.0, map_cap=12,
-                bf16_nearest=0, ext_force=(0.0, 0.0, 0.0), ext_torque=(0.0, 0.0, 0.0))
+                bf16_nearest=0, ext_force=(0.0, 0.0, 0.0), ext_torque=(0.0, 0.0, 0.0), cand_cap=0)
 
 
 def make_config(cfg: dict) -> lb_config:
@@ -223,6 +226,15 @@ class Simulation:
         self.stream = stream
         self.arena.record_stream(stream)
         self._chk(_lib.lb_set_stream(self.h, ctypes.c_void_p(stream.cuda_stream)), "lb_set_stream")
+
+    def lb_set_side_stream(self, stream):
+        """The cells' concurrent work goes to `stream` (a torch stream, kept alive here), or,
+        with None, stays on the main stream."""
+        self.side_stream = stream
+        if stream is not None:
+            self.arena.record_stream(stream)
+        self._chk(_lib.lb_set_side_stream(self.h, None if stream is None else ctypes.c_void_p(stream.cuda_stream)),
+                  "lb_set_side_stream")
 
     # -- stepping
     def lb_step(self, n: int = 1):

@@ -25,7 +25,7 @@ import torch
 
 from . import lbrbc
 
-_CKPT_HEADER = 56     # bytes of the checkpoint header (holds the host step counter)
+_CKPT_HEADER = 88     # bytes of the checkpoint header (holds the host step counter)
 
 
 @dataclass
@@ -55,6 +55,7 @@ class Result:
     mass: float
     flags: int
     digest: str = None        # SHA-1 of the final state (populations, fields, cells)
+    state: dict = None        # final velocity field and cell state (keep_state=True)
 
     @property
     def latency(self) -> float:
@@ -78,7 +79,7 @@ class Server:
 
     def __init__(self, budget_bytes: int, chunk_steps: int = 50, use_graphs: bool = False,
                  device: str = "cuda:0", max_inflight_chunks: int = 2, digests: bool = False,
-                 max_active: int = 64, progress=None, fused: bool = False):
+                 max_active: int = 64, progress=None, fused: bool = False, keep_state: bool = False):
         if use_graphs and chunk_steps % 2:
             raise ValueError("graph chunks need an even step count (A/B buffers)")
         if use_graphs and fused:
@@ -93,6 +94,7 @@ class Server:
         # leave the device idle
         self.max_inflight = max(max_inflight_chunks, 4) if fused else max_inflight_chunks
         self.digests = digests
+        self.keep_state = keep_state
         self.max_active = int(max_active)
         self.progress = progress       # called with each Result as it retires
         self.queue: list = []          # (arrival, rid, Request)
@@ -219,11 +221,15 @@ class Server:
                 a.stream.synchronize()
                 o = a.sim.lb_observe()
                 digest = hashlib.sha1(a.sim.lb_save()[_CKPT_HEADER:]).hexdigest() if self.digests else None
+                state = None
+                if self.keep_state:
+                    state = dict(u=a.sim.lb_get_fields(f=False, u=True, sigma=False)["u"],
+                                 cells=a.sim.rbc_get_state() if a.sim.nrbc else None)
                 res = Result(
                     rid=rid, arrival=a.req.arrival, admitted=a.admitted, finished=self._now(),
                     steps=a.req.steps, n_fluid=int(o.n_fluid), n_cells=int(o.n_rbc),
                     footprint=a.footprint, flow_rate=o.flow_rate, eta_app=o.eta_app,
-                    wss_mean=o.wss_mean, mass=o.mass, flags=int(o.flags), digest=digest)
+                    wss_mean=o.wss_mean, mass=o.mass, flags=int(o.flags), digest=digest, state=state)
                 self.results.append(res)
                 if self.progress:
                     self.progress(res)

@@ -7,21 +7,16 @@ voxelises simple vessels and places rigid oblate ellipsoids without overlap, fro
 Geometry convention: arrays are shaped (nz, ny, nx) so that the flat index is
 n = x + nx*(y + ny*z); node (x, y, z) sits at the point (x, y, z); 1 = solid.
 
-Placement rule: centres uniform in the fluid region, orientations uniform on SO(3)
-(normalised Gaussian quaternions), by random sequential addition vectorised in batches. A
-candidate is rejected when
-  * the node nearest its centre is solid;
-  * it meets an already placed cell: for ellipsoids with shape matrices
-    A = Q diag(a^2) Q^T, the Perram-Wertheim contact function at lambda = 1/2,
-    c = r^T (A_i + A_j)^-1 r / 2, is below s^2 (s = 1: no contact);
-  * it meets a wall mesh point: the point lies inside the ellipsoid grown to semi-axes
-    sqrt(2 (a^2 + a_wall^2)) (the same contact function with a sphere of radius a_wall).
-Random sequential addition jams below blood hematocrits (about 0.24 in a wide tube, less in
-narrow ones), so the cells that do not fit are dropped at random fluid centres and all
-overlaps are then removed geometrically: pairs below the contact threshold, and cells
-meeting wall points, are pushed apart along their centre lines until every pair contact
-is at least 0.97^2 (a slight soft overlap of the kind a small Gay-Berne energy scale
-permits) and no wall point is inside a grown ellipsoid. Orientations stay uniform.
+Placement rule (place_cells): centres uniform in the fluid region, orientations uniform on
+SO(3) (normalised Gaussian quaternions). All cells are first placed by random sequential
+addition at half their size, then inflated to full size in steps, each followed by
+overlap-removal sweeps that move and turn the cells (synth_pack.c). The overlap measure is
+the Perram-Wertheim contact function at lambda = 1/2 of two ellipsoids with shape matrices
+A = Q diag(a^2) Q^T, c = r^T (A_i + A_j)^-1 r / 2 (c >= 1: no contact), and for a cell and
+a wall mesh point the same function with a sphere of radius a_wall. A placement is accepted
+with every pair at c >= 0.98^2 and every cell-wall contact at c >= 0.95^2 (a slight soft
+overlap of the kind a small Gay-Berne energy scale permits); the few cells still violating
+either bound are dropped and the achieved hematocrit is reported.
 """
 from __future__ import annotations
 
@@ -190,8 +185,11 @@ class _Packer:
         self.r_wall = math.sqrt(2.0 * (amax * amax + a_wall * a_wall))
         self.fluid = solid == 0
         self.rng = rng
+        self.a_wall = a_wall
         self.Aw = (a_wall * a_wall) * np.eye(3)
         wall = boundary_points(solid, periodic)
+        self.wall_base = wall.copy()
+        self.fluid_xyz = np.ascontiguousarray((solid == 0).astype(np.uint8))
         # ghost copies across periodic faces, so a plain (non-periodic) tree answers
         # every query on wrapped centres
         for a in range(3):
@@ -225,7 +223,7 @@ class _Packer:
                 ci[:, a] = np.clip(ci[:, a], 0, n - 1)
         return ok & self.fluid[ci[:, 2], ci[:, 1], ci[:, 0]]
 
-    def walls_ok(self, c, A, ok):
+    def walls_ok(self, c, A, ok, s2=1.0):
         if self.wtree is None:
             return ok
         idx = np.nonzero(ok)[0]
@@ -244,7 +242,7 @@ class _Packer:
             rows, cols = np.nonzero(np.isfinite(dist))
             if len(rows):
                 d = cw[idx[rows]] - self.wall[j[rows, cols]]
-                bad = _contact(d, A[idx[rows]], np.broadcast_to(self.Aw, (len(rows), 3, 3))) < 1.0
+                bad = _contact(d, A[idx[rows]], np.broadcast_to(self.Aw, (len(rows), 3, 3))) < s2
                 ok[np.unique(idx[rows[bad]])] = False
             break
         return ok
@@ -288,32 +286,44 @@ class _Packer:
 
 
 def place_cells(solid: np.ndarray, axes, n_target: int, seed: int, periodic=(0, 0, 1),
-                a_wall: float = 0.5, batch: int = 8192, rsa_attempts_per_cell: int = 4,
-                s_accept: float = 0.97, max_iter: int = 200, fill: bool = True) -> Placement:
-    """Random sequential addition without contact, then, for the cells that did not fit,
-    random valid centres followed by geometric overlap removal: every pair with contact
-    function c < 1 is pushed apart along its centre line by half its deficit
-    |r| (1 - sqrt(c)), every cell meeting a wall point is pushed away from it likewise, and
-    the sweep repeats until no pair is below s_accept^2 and no wall point inside a grown
-    ellipsoid (or max_iter). Orientations stay as drawn. Cells still meeting a wall point at
-    the end are dropped."""
+                a_wall: float = 0.5, batch: int = 8192, scale0: float = 0.5,
+                increments: int = 20, steps_per_increment: int = 100, final_steps: int = 1000,
+                s_accept: float = 0.98, s_wall: float = 0.95, target: float = 1.0,
+                damp: float = 0.8, verbose: bool = False) -> Placement:
+    """Seeded placement at a target count, reached by inflation.
+
+    1. Random sequential addition of all n_target cells with their semi-axes scaled by
+       scale0 (a dilute packing: it always fits), orientations uniform on SO(3).
+    2. Inflation: the scale grows to 1 in `increments` equal steps; after each one,
+       `steps_per_increment` overlap-removal sweeps move and turn the cells.
+    3. Sweeps at full size until every pair has contact function c >= s_accept^2 and every
+       cell-wall contact c >= s_wall^2, or `final_steps` sweeps.
+    4. Cells still violating either bound are dropped (the achieved hematocrit is reported).
+
+    A sweep is a damped Jacobi projection on the linearised contact function: for each pair
+    below the target, c(R_i - R_j) = r^T (A_i + A_j)^-1 r / 2 with x = (A_i + A_j)^-1 r has the
+    gradient x with respect to R_i and x cross (A_i x) with respect to a small rotation of cell
+    i; the minimum-norm move (rotations weighted by 1/a_max^2) that would lift c to the target
+    is split between the two cells, averaged over each cell's contacts, capped, and applied.
+    Pure geometry: no forces or potentials of the model."""
     rng = np.random.default_rng(seed)
     pk = _Packer(solid, axes, periodic, a_wall, rng)
     box, per = pk.box, pk.per
+    # 1. dilute random sequential addition at scale0
     Rs = np.zeros((0, 3))
-    As = np.zeros((0, 3, 3))
     Qs = np.zeros((0, 3, 3))
     attempts = 0
-    budget = rsa_attempts_per_cell * max(n_target, 1)
+    s2 = scale0 * scale0
+    budget = 200 * max(n_target, 1) + 100000
     while len(Rs) < n_target and attempts < budget:
         B = int(min(batch, 4 * (n_target - len(Rs)) + 64))
         c = pk.lo + rng.random((B, 3)) * (pk.hi - pk.lo)
         Qc = random_rotations(rng, B)
         attempts += B
-        Ac = pk.shape(Qc)
+        Ac = s2 * pk.shape(Qc)
         ok = pk.centre_ok(c)
         ok = pk.walls_ok(c, Ac, ok)
-        ok = pk.pairs_ok(c, Ac, ok, Rs, As, 1.0)
+        ok = pk.pairs_ok(c, Ac, ok, Rs, s2 * pk.shape(Qs) if len(Qs) else np.zeros((0, 3, 3)), 1.0)
         idx = np.nonzero(ok)[0]
         accepted = []
         if len(idx):
@@ -338,28 +348,25 @@ def place_cells(solid: np.ndarray, axes, n_target: int, seed: int, periodic=(0, 
         if accepted:
             acc = np.array(accepted)
             Rs = np.concatenate([Rs, _wrap(c[acc], box, per)])
-            As = np.concatenate([As, Ac[acc]])
             Qs = np.concatenate([Qs, Qc[acc]])
-    if len(Rs) < n_target and fill:
-        # remaining cells at random centres whose node is fluid, then overlap removal
-        need = n_target - len(Rs)
-        extra_R, extra_Q = [], []
-        while sum(len(x) for x in extra_R) < need:
-            c = pk.lo + rng.random((4 * need + 64, 3)) * (pk.hi - pk.lo)
-            Qc = random_rotations(rng, len(c))
-            ok = pk.centre_ok(c)
-            extra_R.append(c[ok])
-            extra_Q.append(Qc[ok])
-        eR = np.concatenate(extra_R)[:need]
-        eQ = np.concatenate(extra_Q)[:need]
-        Rs = np.concatenate([Rs, _wrap(eR, box, per)])
-        Qs = np.concatenate([Qs, eQ])
-        As = np.concatenate([As, pk.shape(eQ)])
-        Rs = _relax(pk, Rs, As, s_accept, max_iter)
-    # final state: drop cells meeting a wall point or with a solid centre node, then the
-    # cell of the worst remaining pair until every pair contact is >= s_accept^2
+    # 2.-3. inflation, then sweeps at full size
+    sched = [scale0 + (1.0 - scale0) * (k + 1) / increments for k in range(increments)]
+    for sc in sched:
+        Rs, Qs, worst, nbad = _sweeps(pk, Rs, Qs, sc, target, target, target, target, damp,
+                                      steps_per_increment)
+        if verbose:
+            print(f"[synth] scale {sc:.3f}: worst pair contact {worst:.4f}, {nbad} violations",
+                  file=sys.stderr, flush=True)
+    Rs, Qs, worst, nbad = _sweeps(pk, Rs, Qs, 1.0, target, target, s_accept, s_wall, damp,
+                                  final_steps)
+    if verbose:
+        print(f"[synth] final: worst pair contact {worst:.4f}, {nbad} violations", file=sys.stderr,
+              flush=True)
+    # 4. drop what still violates: cells off the fluid or meeting a wall point, then the cell
+    # with most violations in each violating pair
+    As = pk.shape(Qs)
     okc = pk.centre_ok(Rs)
-    okc = pk.walls_ok(Rs, As, okc)
+    okc = pk.walls_ok(Rs, As, okc, s_wall * s_wall)
     Rs, As, Qs = Rs[okc], As[okc], Qs[okc]
     while len(Rs) > 1:
         tree = _tree(Rs, box, per)
@@ -371,7 +378,6 @@ def place_cells(solid: np.ndarray, axes, n_target: int, seed: int, periodic=(0, 
         bad = c < s_accept * s_accept
         if not bad.any():
             break
-        # remove, among the cells in violating pairs, those with the most violations
         cnt = np.bincount(np.concatenate([pr[bad, 0], pr[bad, 1]]), minlength=len(Rs))
         drop = set()
         for k in np.argsort(c[bad]):
@@ -381,52 +387,73 @@ def place_cells(solid: np.ndarray, axes, n_target: int, seed: int, periodic=(0, 
             drop.add(a_ if cnt[a_] >= cnt[b_] else b_)
         keep = np.array([k not in drop for k in range(len(Rs))])
         Rs, As, Qs = Rs[keep], As[keep], Qs[keep]
+    # orthonormal to rounding (polar factor of the accumulated rotations)
+    if len(Qs):
+        U, _, Vt = np.linalg.svd(Qs)
+        Qs = U @ Vt
     s = min(1.0, math.sqrt(pk.min_pair_contact(Rs, As))) if len(Rs) > 1 else 1.0
     v = 4.0 / 3.0 * math.pi * float(np.prod(pk.axes))
     H = len(Rs) * v / float(pk.fluid.sum())
     return Placement(R=Rs, Q=Qs.reshape(-1, 9), hematocrit=H, s_pair=s, attempts=attempts)
 
 
-def _relax(pk: "_Packer", Rs, As, s_accept, max_iter):
-    box, per = pk.box, pk.per
-    Rs = Rs.copy()
-    for it in range(max_iter):
-        if it % 10 == 0:
-            print(f"[synth] overlap removal sweep {it}", file=sys.stderr, flush=True)
-        disp = np.zeros_like(Rs)
-        worst = 1.0
-        tree = _tree(Rs, box, per)
-        pr = tree.query_pairs(pk.r_pair, output_type="ndarray")
-        if len(pr):
-            d = _min_image(Rs[pr[:, 0]] - Rs[pr[:, 1]], box, per)
-            c = _contact(d, As[pr[:, 0]], As[pr[:, 1]])
-            worst = float(c.min())
-            bad = c < 1.0
-            if bad.any():
-                dist = np.linalg.norm(d[bad], axis=1, keepdims=True)
-                push = 0.5 * (1.0 - np.sqrt(c[bad]))[:, None] * d[bad] / np.maximum(dist, 1e-9) * dist
-                np.add.at(disp, pr[bad, 0], push)
-                np.add.at(disp, pr[bad, 1], -push)
-        wall_bad = 0
-        if pk.wtree is not None:
-            d1, _ = pk.wtree.query(Rs, k=1)
-            near = np.nonzero(d1 < pk.r_wall)[0]
-            if len(near):
-                dist, j = pk.wtree.query(Rs[near], k=64, distance_upper_bound=pk.r_wall)
-                rows, cols = np.nonzero(np.isfinite(dist))
-                if len(rows):
-                    ri = near[rows]
-                    d = Rs[ri] - pk.wall[j[rows, cols]]
-                    c = _contact(d, As[ri], np.broadcast_to(pk.Aw, (len(rows), 3, 3)))
-                    bad = c < 1.0
-                    wall_bad = int(bad.sum())
-                    if wall_bad:
-                        push = 1.05 * (1.0 - np.sqrt(c[bad]))[:, None] * d[bad]
-                        np.add.at(disp, ri[bad], push)
-        if worst >= s_accept * s_accept and wall_bad == 0:
-            break
-        Rs = _wrap(Rs + disp, box, per)
-    return Rs
+_PACK = None
+
+
+def _pack_lib():
+    """The compiled overlap-removal sweeps (synth_pack.c), built with gcc when missing."""
+    global _PACK
+    if _PACK is None:
+        import ctypes
+
+        here = os.path.dirname(os.path.abspath(__file__))
+        so = os.path.join(here, "libsynthpack.so")
+        if not os.path.exists(so):
+            build_pack(so)
+        lib = ctypes.CDLL(so)
+        P = ctypes.c_void_p
+        lib.pack_sweeps.argtypes = [ctypes.c_int, P, P, P, P, P, P, ctypes.c_int, ctypes.c_double, P,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_int, P]
+        lib.pack_sweeps.restype = ctypes.c_int
+        _PACK = lib
+    return _PACK
+
+
+def build_pack(so=None):
+    """Compile synth_pack.c into libsynthpack.so (gcc, OpenMP; no contraction, so the
+    placement is the same on every host)."""
+    import subprocess
+
+    here = os.path.dirname(os.path.abspath(__file__))
+    so = so or os.path.join(here, "libsynthpack.so")
+    tmp = so + f".{os.getpid()}.tmp"
+    subprocess.run(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-shared", "-fPIC", "-o", tmp,
+                    os.path.join(here, "synth_pack.c"), "-lm"], check=True)
+    os.replace(tmp, so)
+    return so
+
+
+def _sweeps(pk: "_Packer", Rs, Qs, scale, t_pair, t_wall, s_acc, s_wacc, damp, nsweeps,
+            dmax=0.25, thmax=0.1):
+    """Up to nsweeps overlap-removal sweeps at the given scale of the semi-axes (synth_pack.c);
+    returns centres, orientations, the smallest pair contact and the violations left."""
+    import ctypes
+
+    lib = _pack_lib()
+    R = np.ascontiguousarray(Rs, dtype=np.float64).copy()
+    Q = np.ascontiguousarray(Qs.reshape(-1, 9), dtype=np.float64).copy()
+    dims = np.array([int(b) for b in pk.box], dtype=np.int32)
+    per = np.array([1 if p else 0 for p in pk.per], dtype=np.int32)
+    wall = np.ascontiguousarray(pk.wall_base, dtype=np.float64)
+    axes = np.ascontiguousarray(pk.axes, dtype=np.float64)
+    stats = np.zeros(2)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    lib.pack_sweeps(len(R), p(R), p(Q), p(axes), p(dims), p(per), p(wall), len(wall) if len(R) else 0,
+                    pk.a_wall, p(pk.fluid_xyz), scale, t_pair, t_wall, s_acc, s_wacc, damp, dmax,
+                    thmax, int(nsweeps), p(stats))
+    return R, Q.reshape(-1, 3, 3), float(stats[0]), int(stats[1])
 
 
 def _wrap(c, box, periodic):
@@ -458,7 +485,7 @@ def _tree(pts, box, periodic):
 # ---- named workloads -------------------------------------------------------------------------
 AXES = (4.0, 4.0, 1.5)
 # bump when place_cells changes, so that cached placements are regenerated
-PLACEMENT_VERSION = "rsa-relax-v3"
+PLACEMENT_VERSION = "inflate-v1"
 
 
 def _cache_dir():
@@ -555,7 +582,7 @@ def chevron(nx: int, ny: int, nz: int, radius: float, offset: float) -> np.ndarr
 
 
 def _trace_request(args):
-    k, seed, R, L, H, steps, bent, fill = args
+    k, seed, R, L, H, steps, bent = args
     n = int(2 * math.ceil(R) + 4)
     nz = max(L, 24)
     if bent:
@@ -566,17 +593,17 @@ def _trace_request(args):
         nx = n
         solid = tube(n, n, nz, R)
     n_cells = hematocrit_count(solid, AXES, H)
-    key = (f"serve:{seed}:{k}:{nx}:{n}:{nz}:{R:.6f}:{int(bent)}:{n_cells}:{fill}:"
+    key = (f"serve:{seed}:{k}:{nx}:{n}:{nz}:{R:.6f}:{int(bent)}:{n_cells}:"
            f"{PLACEMENT_VERSION}")
     pl = cached_placement(key, lambda: place_cells(solid, AXES, n_cells, seed * 1000 + k,
-                                                   periodic=(0, 0, 1), fill=fill))
+                                                   periodic=(0, 0, 1)))
     return dict(nx=nx, ny=n, nz=nz, radius=R, bent=bent, solid=solid, R=pl.R, Q=pl.Q,
                 hematocrit=pl.hematocrit, target_hematocrit=H)
 
 
 def serving_trace(n_requests: int, rate_hz: float, seed: int = 2011, r_range=(8.0, 32.0),
                   k_range=(4.0, 16.0), h_range=(0.20, 0.50), steps_range=(500, 5000),
-                  bent_fraction: float = 0.0, fill: bool = False, workers: int = 1):
+                  bent_fraction: float = 0.0, workers: int = 1):
     """A seeded stream of vessel requests: Poisson arrivals (exponential gaps at `rate_hz`),
     periodic tubes of radius R ~ U(r_range) and length k R with k ~ U(k_range), straight or,
     with probability `bent_fraction`, a chevron with a 20-degree bend; target hematocrit
@@ -592,7 +619,7 @@ def serving_trace(n_requests: int, rate_hz: float, seed: int = 2011, r_range=(8.
         H = float(rng.uniform(*h_range))
         steps = int(rng.integers(steps_range[0], steps_range[1] + 1))
         bent = bool(rng.uniform() < bent_fraction)
-        jobs.append((k, seed, R, L, H, steps, bent, fill))
+        jobs.append((k, seed, R, L, H, steps, bent))
         arrivals.append(t)
     if workers > 1 and n_requests > 1:
         from concurrent.futures import ProcessPoolExecutor

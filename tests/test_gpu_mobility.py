@@ -1,4 +1,4 @@
-"""GPU parity of the driven single-cell runs (the drag and spin experiments of Sec. IV):
+"""GPU parity of the driven single-cell runs (the drag and spin experiments of Sec. III):
 a constant external force (lab) and torque (body) on every cell, coupled to the plasma,
 against the FP64 oracle."""
 import numpy as np

@@ -1,6 +1,9 @@
-"""FP64 GPU path against the oracle at the size of the precision-study subsample
-(64x64x256 tube, R = 30, target hematocrit 0.40): the reduced-precision errors that the
-benchmark's precision mode reports are measured against this FP64 path."""
+"""Every storage against the FP64 oracle at the size of the precision-study subsample (64x64x256
+tube, R = 30, hematocrit 0.40, 2,881 cells), over 20 coupled steps from rest: the FP64 path to
+round-off growth, FP32 within the velocity target 1e-4 and the wall-shear-stress target 1e-3
+(relative L2 over the fluid and the wall-adjacent nodes), BF16 with stochastic rounding within
+1e-2 and FP16 (scale 2^21) within 2e-3 in velocity, with their wall shear stress reported
+against bounds set from the measured errors."""
 import numpy as np
 import pytest
 
@@ -8,30 +11,47 @@ from paper_1107_4889_amd import synth
 
 pytestmark = pytest.mark.gpu
 
+NX, NY, NZ, STEPS = 64, 64, 256, 20
+CFG = dict(nx=NX, ny=NY, nz=NZ, periodic=(0, 0, 1), tau0=0.8, g_ext=(0.0, 0.0, 1e-6),
+           f16_scale=2.0 ** 21)
 
-def test_fp64_matches_oracle_at_study_size():
+
+@pytest.fixture(scope="module")
+def subsample():
     from oracle import oracle as orc
+
+    solid, pl = synth.tube_workload(NX, NY, NZ, 30.0, hematocrit=0.40, seed=1107)
+    print(f"oracle: {NX}x{NY}x{NZ} tube, {len(pl.R)} cells, {STEPS} steps", flush=True)
+    o = orc.Oracle({k: v for k, v in CFG.items() if k != "f16_scale"}, solid, R=pl.R, Q=pl.Q)
+    assert o.step(STEPS) == 0
+    return solid, pl, dict(u=o.u(), rbc=o.rbc(), wss=o.wall_shear_stress())
+
+
+# storage: (velocity, wall shear stress, cell position) bounds, relative L2 / absolute lu
+BOUNDS = {"f64": (1e-10, 1e-9, 1e-10), "f32": (1e-4, 1e-3, 1e-7),
+          "bf16": (1e-2, 5e-2, 1e-6), "f16": (2e-3, 1e-2, 1e-6)}
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16", "f16"])
+def test_storage_matches_oracle_at_study_size(subsample, storage):
     from paper_1107_4889_amd import lbrbc
 
-    nx, ny, nz = 64, 64, 256
-    solid, pl = synth.tube_workload(nx, ny, nz, 30.0, hematocrit=0.40, seed=1107)
-    cfg = dict(nx=nx, ny=ny, nz=nz, periodic=(0, 0, 1), tau0=0.8, g_ext=(0.0, 0.0, 1e-6))
-    steps = 3
-    o = orc.Oracle(cfg, solid, R=pl.R, Q=pl.Q)
-    assert o.step(steps) == 0
-    sim = lbrbc.Simulation({**cfg, "storage": "f64"}, solid, R=pl.R, Q=pl.Q)
-    sim.lb_step(steps)
+    solid, pl, ref = subsample
+    print(f"{storage} against the oracle: {NX}x{NY}x{NZ}, {len(pl.R)} cells, {STEPS} steps", flush=True)
+    sim = lbrbc.Simulation({**CFG, "storage": storage}, solid, R=pl.R, Q=pl.Q)
+    sim.lb_step(STEPS)
     fl = solid.reshape(-1) == 0
     ug = sim.lb_get_fields(f=False, u=True, sigma=False)["u"][fl]
-    uo = o.u()[fl]
-    assert np.linalg.norm(ug - uo) <= 1e-10 * np.linalg.norm(uo)
-    Rg = sim.rbc_get_state()[0]
-    Ro = o.rbc()[0]
-    assert np.abs(Rg - Ro).max() < 1e-10
+    uo = ref["u"][fl]
+    bu, bw, br = BOUNDS[storage]
+    eu = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
     node_g, wss_g = sim.lb_wall_shear_stress(False)
-    node_o, wss_o = o.wall_shear_stress()
+    node_o, wss_o = ref["wss"]
     assert np.array_equal(node_g, node_o)
-    assert np.linalg.norm(wss_g - wss_o) <= 1e-9 * np.linalg.norm(wss_o)
+    ew = np.linalg.norm(wss_g - wss_o) / np.linalg.norm(wss_o)
+    er = np.abs(sim.rbc_get_state()[0] - ref["rbc"][0]).max()
+    print(f"{storage}: u rel L2 {eu:.3e}, WSS rel L2 {ew:.3e}, max |dR| {er:.3e}", flush=True)
+    assert eu <= bu and ew <= bw and er <= br
 
 
 def test_pipelined_steps_bitwise_equal_to_single_steps():

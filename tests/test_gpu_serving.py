@@ -83,8 +83,8 @@ def test_graph_every_replay_matches_eager():
         torch.cuda.synchronize()
         o_e, o_g = eager.lb_observe(), graph.lb_observe()
         assert o_e.flags == 0 and o_g.flags == 0
-        d_e = hashlib.sha1(eager.lb_save()[56:]).hexdigest()
-        d_g = hashlib.sha1(graph.lb_save()[56:]).hexdigest()
+        d_e = hashlib.sha1(eager.lb_save()[88:]).hexdigest()
+        d_g = hashlib.sha1(graph.lb_save()[88:]).hexdigest()
         assert d_e == d_g, rep
         assert o_e.mass == o_g.mass and o_e.flow_rate == o_g.flow_rate
 
@@ -110,7 +110,7 @@ def test_fused_batch_equals_each_alone():
     nsteps = [30, 50, 40, 20]
 
     def digest(sim):
-        return hashlib.sha1(sim.lb_save()[56:]).hexdigest()
+        return hashlib.sha1(sim.lb_save()[88:]).hexdigest()
 
     alone = []
     for (cfg, solid, R, Q), n in zip(cases, nsteps):
@@ -166,7 +166,7 @@ def test_interleaved_batch_with_open_boundaries_equals_each_alone():
           flush=True)
 
     def digest(sim):
-        return hashlib.sha1(sim.lb_save()[56:]).hexdigest()
+        return hashlib.sha1(sim.lb_save()[88:]).hexdigest()
 
     alone = []
     for (cfg, sd, Rc, Qc), n in zip(cases, nsteps):
@@ -185,3 +185,29 @@ def test_interleaved_batch_with_open_boundaries_equals_each_alone():
             assert sim.lb_observe().flags == 0
             assert digest(sim) == d, (shared, k)
         del sims
+
+
+def test_served_request_matches_oracle_f64():
+    """A request served in the fused mode beside two others, in FP64, ends where the oracle
+    ends after the same number of steps: velocity and cells to 1e-10 relative."""
+    from oracle import oracle as orc
+    from paper_1107_4889_amd.serving import Request, Server
+
+    reqs = _requests(3, seed=82, steps=(40, 60))
+    reqs = [Request(**{**r.__dict__, "cfg": dict(r.cfg, storage="f64")}) for r in reqs]
+    target = max(reqs, key=lambda r: len(r.R))
+    print(f"served request {target.rid}: {target.cfg['nx']}x{target.cfg['ny']}x{target.cfg['nz']}, "
+          f"{len(target.R)} cells, {target.steps} steps, FP64", flush=True)
+    res, _ = Server(budget_bytes=8 << 30, chunk_steps=16, fused=True, keep_state=True).run(reqs)
+    got = {r.rid: r for r in res}[target.rid]
+    assert got.flags == 0 and got.steps == target.steps
+    ocfg = {k: v for k, v in target.cfg.items() if k != "storage"}
+    ref = orc.Oracle(ocfg, target.solid, R=target.R, Q=target.Q)
+    assert ref.step(target.steps) == 0
+    fl = target.solid.reshape(-1) == 0
+    ur = ref.u()[fl]
+    assert np.linalg.norm(got.state["u"][fl] - ur) <= 1e-10 * np.linalg.norm(ur)
+    Rg, Qg, Vg, Og = got.state["cells"]
+    Rr, Qr, Vr, Or = ref.rbc()
+    assert np.abs(Rg - Rr).max() < 1e-10 and np.abs(Qg - Qr).max() < 1e-10
+    assert np.linalg.norm(Vg - Vr) <= 1e-9 * np.linalg.norm(Vr)

@@ -39,11 +39,14 @@ def test_footprint_and_validation_on_host():
     b16 = lbrbc.lb_query_footprint(_cfg(storage="bf16"), solid, 10)
     N = 16 * 16 * 32
     assert b64 > b32 > b16 >= 2 * 19 * N * 2
-    for ok in (2.0 ** 21, 2.0 ** -100, 2.0 ** 100, 1.0):
+    for ok in (2.0 ** 21, 2.0 ** 10, 2.0 ** 40):
         assert lbrbc.lb_query_footprint(_cfg(storage="f16", f16_scale=ok), solid, 10) > 0
+    # FP16 scales below 2^10 let slow flows underflow silently; a scale must be a power of two
     for bad in (dict(tau0=0.5), dict(map_cap=13), dict(storage=7), dict(open_z=1),
                 dict(nx=0), dict(xi=(0, 1, 1)), dict(storage="f16", f16_scale=3.0),
-                dict(storage="f16", f16_scale=0.0), dict(storage="f16", f16_scale=2.0 ** 101)):
+                dict(storage="f16", f16_scale=0.0), dict(storage="f16", f16_scale=2.0 ** 41),
+                dict(storage="f16", f16_scale=2.0 ** 9), dict(storage="f16", f16_scale=1.0),
+                dict(cand_cap=-1)):
         with pytest.raises(lbrbc.LbError) as e:
             lbrbc.lb_query_footprint(_cfg(**bad), solid, 10)
         assert e.value.status == lbrbc.LB_EINVAL
@@ -97,3 +100,17 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
                        capture_output=True, text=True, timeout=300)
     assert r.returncode != 0
     assert "ImportError" in r.stderr and "liblbrbc.so is not built" in r.stderr
+
+
+def test_planes_over_4_gib_are_rejected():
+    # Per-node planes are addressed with 32-bit byte offsets: a 1024 x 1024 x 1025 FP32 lattice
+    # (2^30 + 2^20 nodes, 4-byte u and sigma planes over 4 GiB) and a 1024 x 1024 x 513 FP64
+    # one are rejected before any geometry is built; 1024 x 1024 x 1023 FP32 passes that check.
+    from paper_1107_4889_amd import lbrbc
+
+    for nz, storage in ((1025, "f32"), (1025, "bf16"), (513, "f64")):
+        solid = np.zeros(1024 * 1024 * nz, dtype=np.uint8)     # never read: rejected first
+        with pytest.raises(lbrbc.LbError) as e:
+            lbrbc.lb_query_footprint(_cfg(nx=1024, ny=1024, nz=nz, storage=storage), solid, 0)
+        assert e.value.status == lbrbc.LB_EINVAL
+        assert "32-bit plane offsets" in str(e.value)

@@ -213,6 +213,38 @@ def test_stress_torque_symmetries_and_sign():
     assert np.allclose(ts(0.08, {4: s}), 2 * t_xz, rtol=1e-12, atol=1e-12 * ref)
 
 
+def _four_node_stress_torque_closed_form(alpha, comp, s):
+    """T^S of Eq. 16 worked out by hand for a cell with shape-function radii xi = (1, 1, 1/2),
+    axis-aligned, centred at (x0 + 1/2, y0 + 1/2, z0) in a periodic fluid.
+
+    Support |y_a| < xi_a: dx, dy in {-1/2, +1/2} and dz = 0, four nodes. The Peskin kernel at
+    r = 2|y|/xi gives phi(1) = (3 - 2 + 1)/8 = 1/4 along x and y, phi(0) = 1/2 along z, so raw
+    = 1/32 at each node, S = 1/8 and dhat = 1/4. The central-difference gradient of dhat at the
+    node (dx, dy) is -(sgn dx, sgn dy, 0)/8 (its own axis neighbours outside the support hold
+    dhat = 0), so n^ = -(sgn dx, sgn dy, 0)/sqrt(2). A uniform stress with the single shear
+    component s in the xz (yz) plane gives sigma . n^ = (0, 0, s n_x) ((0, 0, s n_y)), and
+    (sigma . n^) x (x - R) = (-t_z dy, t_z dx, 0). Summed with weight dhat = 1/4 over the four
+    nodes: xz -> (0, -s/(2 sqrt 2), 0), yz -> (s/(2 sqrt 2), 0, 0); times alpha."""
+    k = math.sqrt(2.0) / 4.0 * alpha * s
+    return np.array([0.0, -k, 0.0]) if comp == 4 else np.array([k, 0.0, 0.0])
+
+
+@pytest.mark.parametrize("alpha,comp,s", [(0.04, 4, 1e-3), (0.063, 5, -2.5e-4), (0.1, 4, 3e-5)])
+def test_stress_torque_magnitude_four_node_closed_form(alpha, comp, s):
+    n = 16
+    R = np.array([[7.5, 8.5, 6.0]])
+    cfg = _periodic_cfg(n, alpha=alpha, xi=(1.0, 1.0, 0.5))
+    o = orc.Oracle(cfg, np.zeros((n, n, n), np.uint8), R=R, Q=np.eye(3).reshape(1, 9))
+    sig = np.zeros((n ** 3, 6))               # xx yy zz xy xz yz
+    sig[:, comp] = s
+    o.set_fields(sigma=sig)
+    o.couple()
+    cp = o.coupling()[0]
+    assert cp[0] == pytest.approx(1.0 / 8.0, rel=1e-15)          # S
+    ref = _four_node_stress_torque_closed_form(alpha, comp, s)
+    assert np.allclose(cp[7:10], ref, rtol=1e-13, atol=1e-16 * abs(s))
+
+
 def test_viscosity_contrast_closed_form():
     # Eq. 23 with nu = c^2 (T - 1/2): nu0 = 1/6 (T0 = 1), Delta = 2, theta -> 1 gives ratio 5
     g = GOLD["viscosity_ratio"]
@@ -515,7 +547,7 @@ def test_external_force_and_torque_drive_a_free_cell_exactly():
     # A lone cell without coupling (gT = gR = 0, alpha = 0) and without walls or neighbours:
     # the combined force and torque are the external ones, applied whole once per step, so
     # the velocity Verlet steps are exact for the uniform drive (the printed drag and spin
-    # experiments of Sec. IV apply such a constant force or torque).
+    # experiments of Sec. III apply such a constant force or torque).
     n = 24
     solid = np.zeros((n, n, n), dtype=np.uint8)
     F = np.array([1e-3, -2e-3, 5e-4])
