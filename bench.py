@@ -1,12 +1,13 @@
 #!/usr/bin/env python
 """Benchmark of the coupled plasma / rigid-RBC time step on one MI355X.
 
-Workload (default): a straight tube of radius 60 lu along z in a 128x128x512 box (periodic
-in z, body-force driven g = 1e-6, T0 = 0.8), cells of semi-axes (4, 4, 1.5) placed from
-seed 1107 at the target hematocrit 0.35 (the achieved count is reported), FP32 shifted
-populations with FP32 arithmetic. One step = every stage of the hot path: rigid-body first
-half, cell list, coverage map, interpolation, Gay-Berne forces, rigid-body second half,
-fused spreading + stream-collide.
+Workload (default): the largest single-GPU configuration, a straight tube of radius 120 lu
+along z in a 256x256x1024 box (periodic in z, body-force driven g = 1e-6, T0 = 0.8), with
+184,341 cells of semi-axes (4, 4, 1.5) placed from seed 1107 at hematocrit 0.40 (the achieved
+count is reported), FP32 shifted populations with FP32 arithmetic. One step = every stage of
+the hot path: rigid-body first half, cell list, coverage map, interpolation, Gay-Berne forces,
+rigid-body second half, fused spreading + stream-collide. --workload tube128 times the
+128x128x512 tube (R = 60, hematocrit 0.35), bif384 the Y-bifurcation.
 
 Prints one JSON line: MLUPS of the whole step (fluid-node updates per second), the
 stream-collide kernel's roofline against HBM (algorithmic bytes per launch over its mean
@@ -91,21 +92,41 @@ def workload(name: str, storage: str):
     return cfg, solid, pl, desc
 
 
-def cpu_baseline(cfg, solid, pl, n_fluid: int):
-    """The FP64 oracle, as it stands, on one coupled step of the same workload."""
+def cpu_baseline(cfg, solid, pl, n_fluid: int, hematocrit=None, steps: int = 1):
+    """The FP64 oracle, as it stands, on a bounded sample of the timed workload, with all host
+    threads and with one. A tube workload is sampled as the 64x64x256 tube of radius 30 at the
+    same hematocrit (the subsample of the precision study); other workloads run one step of
+    themselves."""
     from oracle import oracle as orc
+    from paper_1107_4889_amd import synth
 
     ocfg = {k: v for k, v in cfg.items() if k not in ("storage", "f16_scale")}
-    o = orc.Oracle(ocfg, solid, R=pl.R, Q=pl.Q)
-    t0 = time.perf_counter()
-    st = o.step(1)
-    dt = time.perf_counter() - t0
-    if st != 0:
-        return None
-    return {"value": round(n_fluid / dt / 1e6, 4), "unit": "MLUPS", "cores": orc.num_threads(),
-            "kind": "oracle",
-            "sample": f"1 coupled step of the same workload (all stages, {n_fluid} fluid nodes, "
-                      f"{len(pl.R)} cells) after set-up; {dt:.1f} s"}
+    if hematocrit is not None:
+        solid, pl = synth.tube_workload(64, 64, 256, 30.0, hematocrit=hematocrit, seed=1107)
+        ocfg = dict(ocfg, nx=64, ny=64, nz=256)
+        n_fluid = int((solid == 0).sum())
+        what = (f"{steps} coupled step(s) of the 64x64x256 tube of radius 30 at the workload's "
+                f"hematocrit {hematocrit} ({n_fluid} fluid nodes, {len(pl.R)} cells), after set-up")
+    else:
+        what = f"{steps} coupled step(s) of the workload itself ({n_fluid} fluid nodes, {len(pl.R)} cells)"
+    nthr = orc.num_threads()
+    rates = {}
+    for threads in (nthr, 1):
+        orc.set_num_threads(threads)
+        o = orc.Oracle(ocfg, solid, R=pl.R, Q=pl.Q)
+        t0 = time.perf_counter()
+        st = o.step(steps)
+        dt = time.perf_counter() - t0
+        del o
+        if st != 0:
+            return None
+        rates[threads] = (n_fluid * steps / dt / 1e6, dt)
+        print(f"[bench] oracle on {threads} thread(s): {rates[threads][0]:.4f} MLUPS ({dt:.1f} s)",
+              file=sys.stderr, flush=True)
+    orc.set_num_threads(nthr)
+    return {"value": round(rates[nthr][0], 4), "unit": "MLUPS", "cores": nthr, "kind": "oracle",
+            "sample": f"{what}; {rates[nthr][1]:.1f} s on {nthr} threads, {rates[1][1]:.1f} s on one",
+            "value_one_thread": round(rates[1][0], 4)}
 
 
 def run_serving(args):
@@ -189,7 +210,8 @@ def serve(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.storage == "f64" else "f32",
+        "dtype": args.storage,
+        "compute_dtype": "f64" if args.storage == "f64" else "f32",
         "data": "synthetic",
         "config": {
             "workload": desc,
@@ -470,7 +492,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--storage", default="f32", choices=list(STORAGE_BYTES))
-    ap.add_argument("--workload", default="tube128")
+    ap.add_argument("--workload", default="tube256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 1 GiB (HBM counter calibration)")
@@ -565,7 +587,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.storage == "f64" else "f32",
+        "dtype": args.storage,
+        "compute_dtype": "f64" if args.storage == "f64" else "f32",
         "data": "synthetic",
         "config": {
             "workload": desc,
@@ -594,7 +617,7 @@ def main():
                         "wss_mean": obs.wss_mean, "mass": obs.mass},
     }
     del sim
-    if not args.no_serving and args.workload == "tube128":
+    if not args.no_serving and args.workload in ("tube256", "tube128"):
         # the metric's request-latency part: the seeded request stream, fused launches
         print("[bench] serving the seeded request stream (fused launches)", file=sys.stderr,
               flush=True)
@@ -603,9 +626,10 @@ def main():
         _, record, _, _ = run_serving(sargs)
         line["serving"] = record
     if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle on one step of the same workload", file=sys.stderr,
+        print("[bench] timing the CPU oracle on a sample of the same workload", file=sys.stderr,
               flush=True)
-        line["cpu_baseline"] = cpu_baseline(cfg, solid, pl, n_fluid)
+        H = {"tube256": 0.40, "tube128": 0.35}.get(args.workload)
+        line["cpu_baseline"] = cpu_baseline(cfg, solid, pl, n_fluid, hematocrit=H)
     print(json.dumps(line), flush=True)
 
 

@@ -48,6 +48,16 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Threads of the OpenMP loops from here on (the timing of the oracle on 1 and on N cores). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ---------------------------------------------------------------------------------- */
 /* D3Q19 lattice (Sec. II A): c0 = 0 (w = 1/3), six first neighbours (w = 1/18), twelve
  * second neighbours (w = 1/36). The paper leaves the order inside each group open; the

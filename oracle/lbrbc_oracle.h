@@ -102,6 +102,7 @@ void orc_wall_momentum(const orc_sim* s, double out3[3]);
 
 /* Threads the oracle's parallel loops use (OpenMP; 1 without it). */
 int orc_num_threads(void);
+void orc_set_num_threads(int n);
 
 /* Primitives exposed for closed-form tests. */
 void   orc_lattice(int c[19][3], double w[19]);

@@ -83,6 +83,8 @@ def lib():
         L.orc_lattice.argtypes = [_I, _D]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_num_threads.argtypes = []
+        L.orc_set_num_threads.restype = None
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
         L.orc_peskin.restype = ctypes.c_double
         L.orc_peskin.argtypes = [ctypes.c_double]
         L.orc_feq.restype = ctypes.c_double
@@ -257,6 +259,10 @@ def lattice():
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    lib().orc_set_num_threads(int(n))
 
 
 def peskin(r: float) -> float:
