@@ -44,6 +44,7 @@ extern "C" {
 #endif
 
 typedef struct lb_ctx_s* lb_ctx;
+typedef struct lb_graph_s* lb_graph;
 
 typedef enum {
     LB_OK = 0,
@@ -208,6 +209,19 @@ lb_status lb_load(lb_ctx ctx, const void* buf, size_t bytes);
  * nsteps[i] < 0 or a NULL context: LB_EINVAL; a poisoned context: LB_ESTATE (nothing is
  * enqueued in either case). */
 lb_status lb_batch_step(lb_ctx* ctxs, const int* nsteps, int n);
+
+/* Serving with captured HIP graphs (scheduling only, no paper passage): record nsteps (even,
+ * >= 2) fused steps of the n contexts, the same launches lb_batch_step issues for a fused
+ * batch, into a HIP graph on their common stream; nothing runs and no context changes. The
+ * contexts must share one stream and one storage, without open boundaries, WSS accumulation
+ * or timing (else LB_EINVAL), and stay alive and on that stream while the graph exists.
+ * Every replay first clears the contexts' coverage counts, so it is valid whatever ran before.
+ * lb_graph_launch enqueues one replay (asynchronous; LB_ESTATE if a context is poisoned) and
+ * advances the contexts' step counters; lb_graph_destroy waits for the graph's last replay to
+ * finish (that replay only, not the rest of the stream) and frees it. */
+lb_status lb_batch_capture(lb_ctx* ctxs, int n, int nsteps, lb_graph* out);
+lb_status lb_graph_launch(lb_graph graph);
+void lb_graph_destroy(lb_graph graph);
 
 /* Move the context's later work to another HIP stream (not NULL). The caller orders it after
  * the work already enqueued (e.g. an event recorded on the old stream and waited on by the

@@ -306,16 +306,31 @@ __device__ __forceinline__ void stream_collide_node(const PL& pl, const uint32_t
     if (live && (!(rho > RT(0)) || !(usq <= RT(0.09)))) atomicOr(err, ERR_UNSTABLE);
 }
 
+// Block -> tile: the hardware deals consecutive blocks to the eight XCDs in turn, so block
+// k + 8 t of a grid padded to a multiple of 8 is tile t of XCD k's contiguous share. Each XCD then
+// sweeps one range of tiles in order (x fastest, then y, then z), and the cache lines that
+// neighbouring tiles share (the pulls across a tile's x faces) are fetched into one L2.
+__device__ __forceinline__ unsigned xcd_tile()
+{
+    const unsigned per = gridDim.x / 8u;
+    return (blockIdx.x % 8u) * per + blockIdx.x / 8u;
+}
+
 template <typename ST, typename RT, bool CLEAR>
 __global__ __launch_bounds__(256) void k_stream_collide(
     const Planes<ST, RT> pl, const uint32_t* __restrict__ nodeword, const MapPlanes<RT> mp,
-    const Gather<RT>* __restrict__ gat, KParams kp, unsigned* __restrict__ err)
+    const Gather<RT>* __restrict__ gat, KParams kp, unsigned* __restrict__ err, unsigned nbx,
+    unsigned nby, unsigned ntiles)
 {
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y;
+    // tiles of 64 x 4 nodes (a wavefront spans 64 consecutive x)
+    const unsigned t = xcd_tile();
+    if (t >= ntiles) return;
+    const unsigned r = t / nbx;
+    const int x = (int)(t - r * nbx) * 64 + threadIdx.x;
+    const int y = (int)(r % nby) * 4 + threadIdx.y;
     if (x < kp.nx && y < kp.ny)
         stream_collide_node<ST, RT, Planes<ST, RT>, CLEAR>(pl, nodeword, mp, gat, kp, err, x, y,
-                                                           (int)blockIdx.z);
+                                                           (int)(r / nby));
 }
 
 // The same update over a list of 64-node row segments (x0, y, z) that hold a fluid node, one
@@ -327,7 +342,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_seg(
     const Gather<RT>* __restrict__ gat, KParams kp, unsigned* __restrict__ err,
     const int4* __restrict__ segs, int nseg)
 {
-    const int k = (int)blockIdx.x * 4 + (int)threadIdx.y;
+    const int k = (int)xcd_tile() * 4 + (int)threadIdx.y;
     if (k >= nseg) return;
     const int4 sg = segs[k];
     const int x = sg.x + (int)threadIdx.x;
@@ -549,8 +564,11 @@ __global__ __launch_bounds__(256) void kf_clear(const FusedArgs fa)
 template <typename ST, typename RT>
 __global__ __launch_bounds__(256) void kf_stream(const FusedArgs fa)
 {
+    // XCD-contiguous shares of the blocks, as in k_stream_collide (the grid is padded to 8)
+    const unsigned t = xcd_tile();
+    if (t >= (unsigned)fa.start[fa.n]) return;
     int lb;
-    const int sl = fused_slot(fa, lb);
+    const int sl = fused_slot_at(fa, (int)t, lb);
     const SlotDesc& d = *fa.slot[sl];
     const KParams kp = d.kp;
     // flat node order (no idle lanes on lattices narrower than, or not a multiple of, 64)
@@ -574,7 +592,9 @@ void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword
                            const KParams& kp, unsigned* err, bool clear_counts, const int4* segs,
                            int nseg, hipStream_t st)
 {
-    const dim3 grid((unsigned)((kp.nx + 63) / 64), (unsigned)((kp.ny + 3) / 4), (unsigned)kp.nz);
+    const unsigned nbx = (unsigned)((kp.nx + 63) / 64), nby = (unsigned)((kp.ny + 3) / 4);
+    const unsigned ntiles = nbx * nby * (unsigned)kp.nz;
+    const dim3 grid((ntiles + 7u) / 8u * 8u);
     Planes<ST, RT> pl;
     const size_t ld = (size_t)kp.ld;
     for (int p = 0; p < 19; ++p) {
@@ -585,7 +605,7 @@ void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword
     for (int a = 0; a < 6; ++a) pl.sig[a] = (RT*)sig + a * ld;
     const uint32_t* nw = nodeword;
     if (segs && nseg > 0) {
-        const dim3 sgrid((unsigned)((nseg + 3) / 4));
+        const dim3 sgrid(((unsigned)((nseg + 3) / 4) + 7u) / 8u * 8u);
         if (clear_counts)
             hipLaunchKernelGGL((k_stream_collide_seg<ST, RT, true>), sgrid, dim3(64, 4, 1), 0, st, pl, nw,
                                map_planes<RT>(ids, vals, cnt, kp), (const Gather<RT>*)gat, kp, err, segs, nseg);
@@ -596,10 +616,12 @@ void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword
     }
     if (clear_counts)
         hipLaunchKernelGGL((k_stream_collide<ST, RT, true>), grid, dim3(64, 4, 1), 0, st, pl, nw,
-                           map_planes<RT>(ids, vals, cnt, kp), (const Gather<RT>*)gat, kp, err);
+                           map_planes<RT>(ids, vals, cnt, kp), (const Gather<RT>*)gat, kp, err, nbx, nby,
+                           ntiles);
     else
         hipLaunchKernelGGL((k_stream_collide<ST, RT, false>), grid, dim3(64, 4, 1), 0, st, pl, nw,
-                           map_planes<RT>(ids, vals, cnt, kp), (const Gather<RT>*)gat, kp, err);
+                           map_planes<RT>(ids, vals, cnt, kp), (const Gather<RT>*)gat, kp, err, nbx, nby,
+                           ntiles);
 }
 
 template <typename ST, typename RT>
@@ -659,7 +681,7 @@ void launch_fused_lattice(const FusedArgs& fa, int stage, hipStream_t st)
     const unsigned g = (unsigned)fa.start[fa.n];
     if (g == 0) return;
     if (stage == FS_CLEAR) hipLaunchKernelGGL(kf_clear, dim3(g), dim3(256), 0, st, fa);
-    if (stage == FS_STREAM) hipLaunchKernelGGL((kf_stream<ST, RT>), dim3(g), dim3(64, 4, 1), 0, st, fa);
+    if (stage == FS_STREAM) hipLaunchKernelGGL((kf_stream<ST, RT>), dim3((g + 7u) / 8u * 8u), dim3(64, 4, 1), 0, st, fa);
 }
 
 #define INST_ST(ST, RT)                                                                           \

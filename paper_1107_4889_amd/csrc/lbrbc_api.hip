@@ -1001,6 +1001,123 @@ lb_status lb_batch_step(lb_ctx* ctxs, const int* nsteps, int n)
     return e == hipSuccess ? LB_OK : LB_EHIP;
 }
 
+}  // extern "C"
+
+// A captured sequence of fused steps over a fixed set of contexts (serving).
+struct lb_graph_s {
+    std::vector<lb_ctx> ctxs;
+    int nsteps = 0;
+    hipStream_t stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;   // recorded after every replay; destruction waits for it
+};
+
+extern "C" {
+
+lb_status lb_batch_capture(lb_ctx* ctxs, int n, int nsteps, lb_graph* out)
+{
+    if (!ctxs || !out || n < 1 || nsteps < 2 || (nsteps & 1)) return LB_EINVAL;
+    *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i]) return LB_EINVAL;
+        if (ctxs[i]->poisoned) return fail(ctxs[i], LB_ESTATE, "context poisoned by a device fault");
+        if (!fusable(ctxs[i], ctxs[0]))
+            return fail(ctxs[i], LB_EINVAL, "lb_batch_capture: the contexts must share one stream and "
+                                            "one storage, without open boundaries, WSS accumulation or timing");
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return fail(ctxs[i], LB_EINVAL, "lb_batch_capture: a context twice");
+    }
+    hipStream_t s = ctxs[0]->stream;
+    struct Saved {
+        void *fA, *fB;
+        long long step;
+        bool dirty0;
+        int map_parity;
+    };
+    std::vector<Saved> sv(n);
+    for (int i = 0; i < n; ++i) {
+        lb_ctx c = ctxs[i];
+        sv[i] = {c->fA, c->fB, c->step, c->dirty[0], c->map_parity};
+        // every replay first clears the coverage counts of every context, whatever the host
+        // did in between (e.g. rbc_couple): counts left clean are read and left as they are
+        c->dirty[0] = true;
+    }
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        for (int i = 0; i < n; ++i) ctxs[i]->dirty[0] = sv[i].dirty0;
+        return fail(ctxs[0], LB_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    }
+    for (int k = 0; k < nsteps; ++k)
+        for (int g = 0; g < n; g += FUSE_MAX) enqueue_fused_step(ctxs + g, std::min(FUSE_MAX, n - g));
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(s, &graph);
+    // nothing ran: the host state is what it was (an even step count returns the buffers)
+    for (int i = 0; i < n; ++i) {
+        lb_ctx c = ctxs[i];
+        c->fA = sv[i].fA;
+        c->fB = sv[i].fB;
+        c->step = sv[i].step;
+        c->dirty[0] = sv[i].dirty0;
+        c->map_parity = sv[i].map_parity;
+    }
+    if (e != hipSuccess || !graph)
+        return fail(ctxs[0], LB_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(ctxs[0], LB_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    hipEvent_t done = nullptr;
+    e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return fail(ctxs[0], LB_EHIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
+    }
+    lb_graph g = new lb_graph_s();
+    g->done = done;
+    g->ctxs.assign(ctxs, ctxs + n);
+    g->nsteps = nsteps;
+    g->stream = s;
+    g->graph = graph;
+    g->exec = exec;
+    *out = g;
+    return LB_OK;
+}
+
+lb_status lb_graph_launch(lb_graph g)
+{
+    if (!g) return LB_EINVAL;
+    for (lb_ctx c : g->ctxs) {
+        if (c->poisoned) return fail(c, LB_ESTATE, "context poisoned by a device fault");
+        if (c->stream != g->stream) return fail(c, LB_EINVAL, "context moved off the captured stream");
+    }
+    hipError_t e = hipGraphLaunch(g->exec, g->stream);
+    if (e == hipSuccess) e = hipEventRecord(g->done, g->stream);
+    if (e != hipSuccess) return fail(g->ctxs[0], LB_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+    for (lb_ctx c : g->ctxs) {
+        c->step += g->nsteps;
+        c->dirty[0] = false;
+        c->map_parity = 0;
+    }
+    return LB_OK;
+}
+
+void lb_graph_destroy(lb_graph g)
+{
+    if (!g) return;
+    // the last replay must have finished before its executable goes
+    if (g->done) {
+        (void)hipEventSynchronize(g->done);
+        (void)hipEventDestroy(g->done);
+    }
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
 lb_status rbc_couple(lb_ctx c)
 {
     if (!c) return LB_EINVAL;

@@ -88,6 +88,10 @@ struct RbcCouple {       // interpolation results and forces
     double Fm[3], Tm[3];     // Gay-Berne force (lab), torque (body)
     double Fh[3], Th[3];     // hydrodynamic force / torque (lab)
 };
+// doubles between consecutive cells' records (the Gay-Berne pass writes Fm and Tm with it)
+constexpr int COUPLE_STRIDE = (int)(sizeof(RbcCouple) / sizeof(double));
+static_assert(sizeof(RbcCouple) % sizeof(double) == 0, "RbcCouple holds doubles only");
+
 // Record read by the per-node spreading: hydrodynamic force and torque (lab) and 1/S in
 // the compute precision (32 B for float, 64 B for double).
 template <typename RT>
@@ -239,13 +243,16 @@ template <typename RT>
 __device__ __forceinline__ RT peskin(RT r)
 {
     // both pieces with one square root (selects): (3 - 2r + sqrt(1 + 4r - 4r^2)) / 8 on
-    // [0, 1], (5 - 2r - sqrt(-7 + 12r - 4r^2)) / 8 on (1, 2), 0 beyond
+    // [0, 1], (5 - 2r - sqrt(-7 + 12r - 4r^2)) / 8 on (1, 2), 0 beyond. The second piece
+    // falls to exactly 0 at r = 2, where the rounded square root can exceed 5 - 2r by an ulp:
+    // the kernel is clamped at its true lower bound 0, so a value is never negative (the map
+    // pass reads a negative value as "outside the support")
     r = fabs(r);
     const bool in1 = r <= RT(1);
     const RT q = in1 ? RT(1) + RT(4) * r - RT(4) * r * r : RT(-7) + RT(12) * r - RT(4) * r * r;
     const RT sq = fast_sqrt(q > RT(0) ? q : RT(0));
     const RT v = (in1 ? RT(3) - RT(2) * r + sq : RT(5) - RT(2) * r - sq) * RT(0.125);
-    return r < RT(2) ? v : RT(0);
+    return r < RT(2) && v > RT(0) ? v : RT(0);
 }
 
 __device__ __forceinline__ double min_img(double d, double L, int per)

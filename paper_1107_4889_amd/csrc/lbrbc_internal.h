@@ -90,10 +90,9 @@ void launch_fused_cells(const FusedArgs& fa, int stage, size_t lds, hipStream_t 
 template <typename ST, typename RT>
 void launch_fused_lattice(const FusedArgs& fa, int stage, hipStream_t st);
 
-// slot of this block in a fused launch, and the block's index within the slot
-__device__ __forceinline__ int fused_slot(const FusedArgs& fa, int& lb)
+// slot of block b of a fused launch, and the block's index within the slot
+__device__ __forceinline__ int fused_slot_at(const FusedArgs& fa, int b, int& lb)
 {
-    const int b = (int)blockIdx.x;
     int lo = 0, hi = fa.n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -102,6 +101,10 @@ __device__ __forceinline__ int fused_slot(const FusedArgs& fa, int& lb)
     }
     lb = b - fa.start[lo];
     return lo;
+}
+__device__ __forceinline__ int fused_slot(const FusedArgs& fa, int& lb)
+{
+    return fused_slot_at(fa, (int)blockIdx.x, lb);
 }
 
 void launch_cell_list(const CellBuffers& b, const KParams& kp, hipStream_t st);
@@ -112,6 +115,9 @@ void launch_map_couple(const CellBuffers& b, const KParams& kp, hipStream_t st);
 size_t map_couple_lds(int tile_max, int cand_cap, int real_bytes);   // dynamic LDS, bytes
 size_t map_couple_tile_lds(int tile_max, int real_bytes);
 void launch_gay_berne(const CellBuffers& b, const KParams& kp, hipStream_t st);
+// the same forces and torques into F[stride i + a] (lab) and T[stride i + a] (body)
+void launch_gay_berne_out(const CellBuffers& b, const KParams& kp, double* F, double* T, int stride,
+                          hipStream_t st);
 // combined force and torque, friction and half kick (the map pass has written F^hyd, T^hyd
 // and the gather records)
 void launch_rb_second_half(const CellBuffers& b, const KParams& kp, hipStream_t st);

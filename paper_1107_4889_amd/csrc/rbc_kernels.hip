@@ -998,9 +998,12 @@ __device__ __forceinline__ int candidate(const CandidateRanges& cr, const int* _
 
 // one wavefront per cell: lanes stride over the flattened candidates (cells, then wall
 // points), then a fixed-order shuffle reduction (bitwise repeatable)
-// one wavefront per cell k of the sorted order (wavefront wv of its block)
+// one wavefront per cell k of the sorted order (wavefront wv of its block); the lab force and
+// body torque of cell i go to outF[stride i + a], outT[stride i + a] (the cell's coupling
+// record, or caller arrays with stride 3)
 __device__ __forceinline__ void gay_berne_cell(int k, const RbcState* __restrict__ st,
-                                               RbcCouple* __restrict__ cp,
+                                               double* __restrict__ outF, double* __restrict__ outT,
+                                               int ostride,
                                                const int* __restrict__ order,
                                                const int* __restrict__ cell_off,
                                                const int* __restrict__ cell_ids,
@@ -1074,8 +1077,8 @@ __device__ __forceinline__ void gay_berne_cell(int k, const RbcState* __restrict
         double tb[3];
         matT_vec(Qi, tl, tb);
         for (int a = 0; a < 3; ++a) {
-            cp[i].Fm[a] = F[a];
-            cp[i].Tm[a] = tb[a];
+            outF[(size_t)ostride * i + a] = F[a];
+            outT[(size_t)ostride * i + a] = tb[a];
         }
     }
 }
@@ -1083,7 +1086,8 @@ __device__ __forceinline__ void gay_berne_cell(int k, const RbcState* __restrict
 // blocks of one wavefront: on the side stream they fit into whatever slots the concurrent
 // map pass and stream-collide leave
 __global__ __launch_bounds__(64) void k_gay_berne(const RbcState* __restrict__ st,
-                                                   RbcCouple* __restrict__ cp,
+                                                   double* __restrict__ outF,
+                                                   double* __restrict__ outT, int ostride,
                                                    const int* __restrict__ order,
                                                    const int* __restrict__ cell_off,
                                                    const int* __restrict__ cell_ids,
@@ -1094,7 +1098,8 @@ __global__ __launch_bounds__(64) void k_gay_berne(const RbcState* __restrict__ s
 {
     const int k = xcd_chunk_index(1);
     if (k < kp.nrbc)
-        gay_berne_cell(k, st, cp, order, cell_off, cell_ids, wall_xyz, wcell_off, wcell_ids, kp, err);
+        gay_berne_cell(k, st, outF, outT, ostride, order, cell_off, cell_ids, wall_xyz, wcell_off,
+                       wcell_ids, kp, err);
 }
 
 // ---- S6: combined force/torque, hydrodynamic force/torque, second half --------------------
@@ -1240,8 +1245,8 @@ __global__ __launch_bounds__(256) void kf_gb(const FusedArgs fa)
     const KParams kp = d.kp;
     const int k = lb * 4 + (int)(threadIdx.x >> 6);
     if (k < kp.nrbc)
-        gay_berne_cell(k, d.b.st, d.b.cp, d.b.cell_ids, d.b.cell_off, d.b.cell_ids, d.b.wall_xyz,
-                       d.b.wcell_off, d.b.wcell_ids, kp, d.b.err);
+        gay_berne_cell(k, d.b.st, d.b.cp[0].Fm, d.b.cp[0].Tm, COUPLE_STRIDE, d.b.cell_ids, d.b.cell_off,
+                       d.b.cell_ids, d.b.wall_xyz, d.b.wcell_off, d.b.wcell_ids, kp, d.b.err);
 }
 
 __global__ __launch_bounds__(128) void kf_kick(const FusedArgs fa)
@@ -1330,11 +1335,17 @@ void launch_map_couple(const CellBuffers& b, const KParams& kp, hipStream_t st)
                        (const RT*)b.sig, kp, b.err);
 }
 
-void launch_gay_berne(const CellBuffers& b, const KParams& kp, hipStream_t st)
+void launch_gay_berne_out(const CellBuffers& b, const KParams& kp, double* F, double* T, int stride,
+                          hipStream_t st)
 {
-    hipLaunchKernelGGL(k_gay_berne, dim3(grid8(kp.nrbc, 1)), dim3(64), 0, st, b.st, b.cp,
+    hipLaunchKernelGGL(k_gay_berne, dim3(grid8(kp.nrbc, 1)), dim3(64), 0, st, b.st, F, T, stride,
                        b.cell_ids, b.cell_off, b.cell_ids, b.wall_xyz, b.wcell_off, b.wcell_ids,
                        kp, b.err);
+}
+
+void launch_gay_berne(const CellBuffers& b, const KParams& kp, hipStream_t st)
+{
+    launch_gay_berne_out(b, kp, b.cp[0].Fm, b.cp[0].Tm, COUPLE_STRIDE, st);
 }
 
 void launch_rb_second_half(const CellBuffers& b, const KParams& kp, hipStream_t st)

@@ -29,6 +29,7 @@ SYMBOLS = ["lb_query_footprint", "lb_init", "lb_step", "rbc_couple", "rbc_collid
            "lb_wall_shear_stress", "lb_apparent_viscosity", "lb_wss_accumulate", "lb_get_fields",
            "lb_set_fields", "rbc_get_state", "rbc_set_state", "rbc_get_coupling", "rbc_get_cells",
            "rbc_get_map", "lb_save", "lb_load", "lb_batch_step", "lb_set_stream", "lb_set_side_stream",
+           "lb_batch_capture", "lb_graph_launch", "lb_graph_destroy",
            "lb_sync",
            "lb_last_error",
            "lb_destroy", "lb_set_timing", "lb_kernel_time"]
@@ -101,6 +102,9 @@ _sig = {
     "lb_save": [_P, _P, _SZ],
     "lb_load": [_P, _P, ctypes.c_size_t],
     "lb_batch_step": [ctypes.POINTER(_P), _I, ctypes.c_int],
+    "lb_batch_capture": [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_int, ctypes.POINTER(_P)],
+    "lb_graph_launch": [_P],
+    "lb_graph_destroy": [_P],
     "lb_sync": [_P],
     "lb_destroy": [_P],
     "lb_set_timing": [_P, ctypes.c_int],
@@ -109,7 +113,7 @@ _sig = {
 for _n, _a in _sig.items():
     _f = getattr(_lib, _n)
     _f.argtypes = _a
-    _f.restype = None if _n == "lb_destroy" else ctypes.c_int
+    _f.restype = None if _n in ("lb_destroy", "lb_graph_destroy") else ctypes.c_int
 _lib.lb_last_error.argtypes = [_P]
 _lib.lb_last_error.restype = ctypes.c_char_p
 
@@ -362,3 +366,29 @@ def lb_batch_step(sims, nsteps):
     st = _lib.lb_batch_step(arr, ns, len(sims))
     if st:
         raise LbError(st, "lb_batch_step")
+
+
+class BatchGraph:
+    """A captured sequence of `nsteps` fused steps over fixed contexts (lb_batch_capture);
+    launch() enqueues one replay. Keeps the Simulations alive while it exists."""
+
+    def __init__(self, sims, nsteps: int):
+        self.sims = list(sims)
+        arr = (_P * len(self.sims))(*[x.h for x in self.sims])
+        h = _P()
+        st = _lib.lb_batch_capture(arr, len(self.sims), int(nsteps), ctypes.byref(h))
+        if st:
+            msg = _lib.lb_last_error(self.sims[0].h)
+            raise LbError(st, f"lb_batch_capture ({msg.decode() if msg else ''})")
+        self.h = h
+        self.nsteps = int(nsteps)
+
+    def launch(self):
+        st = _lib.lb_graph_launch(self.h)
+        if st:
+            raise LbError(st, "lb_graph_launch")
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _lib.lb_graph_destroy(self.h)
+            self.h = None

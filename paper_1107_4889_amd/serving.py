@@ -8,7 +8,9 @@ with one ``lb_batch_step`` call, which interleaves the requests step by step, so
 kernels overlap on the device. Optionally each request's chunk is captured once into a HIP
 graph (through PyTorch's graph API on the request's stream) and replayed. In the fused mode all
 requests share one stream and ``lb_batch_step`` runs each stage of a step as one launch over
-every resident request (batching at the kernel level). A request finishes
+every resident request (batching at the kernel level); with graphs, the fused chunk of the
+current resident set is captured once (``lb_batch_capture``) and replayed with one launch per
+chunk until a request joins or leaves. A request finishes
 when its last chunk's event has completed; its memory is released and queued requests are
 admitted in the same tick. Latency = completion time - arrival time.
 """
@@ -82,9 +84,14 @@ class Server:
                  max_active: int = 64, progress=None, fused: bool = False, keep_state: bool = False):
         if use_graphs and chunk_steps % 2:
             raise ValueError("graph chunks need an even step count (A/B buffers)")
-        if use_graphs and fused:
-            raise ValueError("the fused mode launches per step over the resident set: no graphs")
         self.fused = fused
+        # fused mode with graphs: one captured chunk per composition of the resident set
+        self._bgraph = None
+        self._bkey = None
+        self._old_graphs: list = []    # (graph, event after its last replay): freed once done
+        self.captures = 0
+        self.graph_launches = 0
+        self.eager_chunks = 0
         self.shared_stream = torch.cuda.Stream(device=device) if fused else None
         self.budget = int(budget_bytes)
         self.chunk = int(chunk_steps)
@@ -196,18 +203,42 @@ class Server:
                 a.events.append(ev)
 
     def _enqueue_fused(self):
-        """One chunk of every resident request with steps left, as one fused batch."""
+        """One chunk of every resident request with steps left, as one fused batch: with graphs,
+        a replay of the chunk captured for this composition of the resident set (captured anew
+        when the composition changes), else the launches themselves."""
         todo = [a for a in self.active.values()
                 if a.req.steps - a.done_steps > 0 and len(a.events) < self.max_inflight]
         if not todo:
             return
         counts = [min(self.chunk, a.req.steps - a.done_steps) for a in todo]
-        lbrbc.lb_batch_step([a.sim for a in todo], counts)
+        if self.use_graphs and all(n == self.chunk for n in counts):
+            key = tuple(a.req.rid for a in todo)
+            if key != self._bkey:
+                self._drop_graph()
+                self._bgraph = lbrbc.BatchGraph([a.sim for a in todo], self.chunk)
+                self._bkey = key
+                self.captures += 1
+            self._bgraph.launch()
+            self.graph_launches += 1
+        else:
+            lbrbc.lb_batch_step([a.sim for a in todo], counts)
+            self.eager_chunks += 1
         ev = torch.cuda.Event()
         ev.record(self.shared_stream)
         for a, n in zip(todo, counts):
             a.done_steps += n
             a.events.append(ev)
+
+    def _drop_graph(self):
+        """Retire the current batch graph; it is freed once its last replay has finished
+        (its contexts stay alive until then)."""
+        if self._bgraph is not None:
+            ev = torch.cuda.Event()
+            ev.record(self.shared_stream)
+            self._old_graphs.append((self._bgraph, ev))
+        self._bgraph = None
+        self._bkey = None
+        self._old_graphs = [(g, e) for g, e in self._old_graphs if not e.query()]
 
     def _retire(self):
         for rid in list(self.active):
@@ -235,6 +266,8 @@ class Server:
                     self.progress(res)
                 self.used -= a.footprint
                 a.graph = None
+                if self._bkey is not None and rid in self._bkey:
+                    self._drop_graph()           # it refers to this context
                 del a.sim
                 del self.active[rid]
 
@@ -257,6 +290,9 @@ class Server:
         finally:
             self.pool.shutdown(wait=True)
         makespan = self._now()
+        self._drop_graph()
+        torch.cuda.synchronize()
+        self._old_graphs = []
         return sorted(self.results, key=lambda r: r.rid), makespan
 
 

@@ -24,6 +24,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Fewer cells than this sweep on one thread: a parallel region per sweep costs more, and far
+ * more when several placements run in parallel processes. */
+#define PAR_MIN_CELLS 4096
+
 typedef struct {
     int n[3];
     double edge[3];
@@ -175,7 +179,7 @@ int pack_sweeps(int n, double *R, double *Q, const double *axes, const int *dims
         grid_build(&cg, box, rpair, R, n);
         worst = INFINITY;
         nbad = 0;
-#pragma omp parallel for schedule(dynamic, 256) reduction(min : worst) reduction(+ : nbad)
+#pragma omp parallel for schedule(dynamic, 256) reduction(min : worst) reduction(+ : nbad) if (n >= PAR_MIN_CELLS)
         for (int i = 0; i < n; ++i) {
             const double *Ri = R + 3 * i, *Ai = A + 9 * i;
             double acc[3] = {0, 0, 0}, rot[3] = {0, 0, 0};
@@ -266,7 +270,7 @@ int pack_sweeps(int n, double *R, double *Q, const double *axes, const int *dims
         }
         grid_free(&cg);
         done = sw + 1;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= PAR_MIN_CELLS)
         for (int i = 0; i < n; ++i) {
             if (!hits[i]) continue;
             double c[3];

@@ -211,3 +211,55 @@ def test_served_request_matches_oracle_f64():
     Rr, Qr, Vr, Or = ref.rbc()
     assert np.abs(Rg - Rr).max() < 1e-10 and np.abs(Qg - Qr).max() < 1e-10
     assert np.linalg.norm(Vg - Vr) <= 1e-9 * np.linalg.norm(Vr)
+
+
+def test_batch_graph_every_replay_matches_eager_fused():
+    """lb_batch_capture records 8 fused steps of three contexts on one stream; each of four
+    replays, with eager work (observables, a coupling probe that leaves coverage counts set)
+    between them, leaves every context bitwise where eager fused batches of 8 steps leave a
+    twin, and advances the step counters."""
+    import hashlib
+
+    import torch
+
+    from paper_1107_4889_amd import lbrbc
+
+    reqs = _requests(3, seed=83, steps=(64, 64))
+    s_g, s_e = torch.cuda.Stream(), torch.cuda.Stream()
+    graph_sims = [lbrbc.Simulation(r.cfg, r.solid, R=r.R, Q=r.Q, stream=s_g) for r in reqs]
+    eager_sims = [lbrbc.Simulation(r.cfg, r.solid, R=r.R, Q=r.Q, stream=s_e) for r in reqs]
+    torch.cuda.synchronize()
+    g = lbrbc.BatchGraph(graph_sims, 8)
+    assert all(s.lb_observe().step == 0 for s in graph_sims)     # capturing runs nothing
+
+    def digest(sim):
+        return hashlib.sha1(sim.lb_save()[88:]).hexdigest()
+
+    for rep in range(4):
+        print(f"batch graph replay {rep}", flush=True)
+        g.launch()
+        lbrbc.lb_batch_step(eager_sims, [8, 8, 8])
+        torch.cuda.synchronize()
+        for a, b in zip(graph_sims, eager_sims):
+            o = a.lb_observe()
+            assert o.flags == 0 and o.step == 8 * (rep + 1)
+            assert digest(a) == digest(b), rep
+        # eager work between replays: a coupling probe leaves the coverage counts set
+        graph_sims[rep % 3].rbc_couple()
+        eager_sims[rep % 3].rbc_couple()
+    del g
+
+
+def test_fused_server_with_graphs_matches_alone():
+    from paper_1107_4889_amd.serving import Server
+
+    reqs = _requests(4, seed=84, steps=(48, 96))
+    alone = {}
+    for r in reqs:
+        res, _ = Server(budget_bytes=8 << 30, chunk_steps=16, digests=True).run([r])
+        alone[r.rid] = res[0].digest
+    srv = Server(budget_bytes=8 << 30, chunk_steps=16, digests=True, fused=True, use_graphs=True)
+    mixed, _ = srv.run(reqs)
+    assert srv.graph_launches > 0 and srv.captures > 0
+    for m in mixed:
+        assert m.digest == alone[m.rid] and m.flags == 0
