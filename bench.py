@@ -310,42 +310,19 @@ def precision(args):
     print(json.dumps(line), flush=True)
 
 
-def cell_free_layer(state, cfg, R_vessel, dz=8.0, sectors=16):
-    """Cell-free layer of a tube from the cell state: each cell's outermost radius is its centre
-    radius plus its ellipsoid's extent along the radial direction, sqrt(n^T Q diag(a^2) Q^T n);
-    the layer is the vessel radius minus the outermost radius of the cells in each slab of
-    `dz` along the axis and each of `sectors` angular sectors. Returns the mean and the
-    minimum over the occupied (slab, sector) bins."""
-    import numpy as np
-
-    Rc, Qc = state[0], state[1].reshape(-1, 3, 3)
-    cx, cy = (cfg["nx"] - 1) / 2.0, (cfg["ny"] - 1) / 2.0
-    d = np.stack([Rc[:, 0] - cx, Rc[:, 1] - cy, np.zeros(len(Rc))], axis=1)
-    r = np.linalg.norm(d, axis=1)
-    nrm = d / np.maximum(r, 1e-12)[:, None]
-    a2 = np.array([4.0, 4.0, 1.5]) ** 2
-    nb = np.einsum("nji,nj->ni", Qc, nrm)                 # radial direction in the body frame
-    outer = r + np.sqrt((nb * nb * a2).sum(axis=1))
-    sl = np.floor(Rc[:, 2] / dz).astype(int)
-    sec = np.floor((np.arctan2(d[:, 1], d[:, 0]) + np.pi) / (2 * np.pi) * sectors).astype(int) % sectors
-    key = sl * sectors + sec
-    top = {}
-    for k, o in zip(key, outer):
-        top[k] = max(top.get(k, 0.0), o)
-    gaps = R_vessel - np.array(list(top.values()))
-    return {"mean": float(gaps.mean()), "min": float(gaps.min())}
-
-
 def observables(args):
-    """The tube's observables near steady state: the cell-laden tube and its H = 0 twin run
-    for --obs-steps steps; flow rate, apparent and relative viscosity (eta_rel = Q_0 / Q_H),
-    the radial profile of u_z (1-lu bins, averaged over z and angle), the time-averaged wall
-    shear stress (mean and spread) over the last quarter, and the radial distribution of the
-    cell centres."""
+    """The tube's observables near steady state (Sec. III): the cell-laden 128x128x512 tube and
+    its H = 0 twin run for --obs-steps steps; flow rate, apparent and relative viscosity
+    (eta_rel = Q_0 / Q_H), the radial profile of u_z (1-lu bins, averaged over z and angle), the
+    time-averaged wall shear stress (mean and spread) over the last quarter, the radial density of
+    the cell centres, the cell-free layer and the rouleaux cluster-size histogram, the last two
+    averaged over four snapshots of the last quarter."""
     import numpy as np
     import torch
 
     from paper_1107_4889_amd import lbrbc
+    from paper_1107_4889_amd import observables as ob
+    from paper_1107_4889_amd.synth import AXES
 
     out = {}
     prof = {}
@@ -353,43 +330,42 @@ def observables(args):
         cfg, solid, pl, desc = workload(name, "f32")
         sim = lbrbc.Simulation(cfg, solid, R=pl.R if len(pl.R) else None, Q=pl.Q if len(pl.R) else None)
         n = args.obs_steps
+        nx, ny, nz = cfg["nx"], cfg["ny"], cfg["nz"]
         t0 = time.perf_counter()
         sim.lb_step(n - n // 4)
         sim.lb_wss_accumulate(True)
-        cfl = []
+        cfl, hist = [], []
         for k in range(4):
             sim.lb_step(n // 16)
             torch.cuda.synchronize()
             if len(pl.R):
-                cfl.append(cell_free_layer(sim.rbc_get_state(), cfg, R_vessel=60.0))
+                Rc, Qc = sim.rbc_get_state()[:2]
+                cfl.append(ob.cell_free_layer(Rc, Qc, AXES, nx, ny, R_vessel=60.0))
+                hist.append(ob.rouleaux_histogram(Rc, Qc, AXES, box=(nx, ny, nz), periodic=(0, 0, 1)))
             print(f"[observables] {name}: {n - n // 4 + (k + 1) * (n // 16)}/{n} steps", file=sys.stderr,
                   flush=True)
         dt = time.perf_counter() - t0
         o = sim.lb_observe()
         u = sim.lb_get_fields(f=False, u=True, sigma=False)["u"]
-        nx, ny, nz = cfg["nx"], cfg["ny"], cfg["nz"]
-        uz = u[:, 2].reshape(nz, ny, nx).mean(axis=0)
-        yy, xx = np.mgrid[0:ny, 0:nx]
-        r = np.hypot(xx - (nx - 1) / 2.0, yy - (ny - 1) / 2.0)
-        fl2 = solid.reshape(nz, ny, nx)[0] == 0
-        bins = np.floor(r[fl2]).astype(int)
-        prof[name] = (np.bincount(bins, weights=uz[fl2]) / np.maximum(np.bincount(bins), 1)).tolist()
+        prof[name] = ob.radial_velocity_profile(u, solid, nx, ny, nz).tolist()
         _, wss_t = sim.lb_wall_shear_stress(True)
         rec = {"steps": n, "seconds": round(dt, 2), "flow_rate": o.flow_rate, "eta_app": o.eta_app,
                "wss_time_avg_mean": float(wss_t.mean()), "wss_time_avg_std": float(wss_t.std()),
                "flags": int(o.flags)}
         if len(pl.R):
             Rc = sim.rbc_get_state()[0]
-            rc = np.hypot(Rc[:, 0] - (nx - 1) / 2.0, Rc[:, 1] - (ny - 1) / 2.0)
-            rec["cell_centre_radial_histogram"] = np.bincount(np.floor(rc).astype(int),
-                                                              minlength=int(np.ceil(rc.max())) + 1).tolist()
-            rec["cell_centre_r_max"] = float(rc.max())
+            dens, edges = ob.cell_radial_density(Rc, nx, ny, nz, r_max=60.0)
+            rec["cell_centre_radial_density"] = [round(float(x), 7) for x in dens]
+            rec["cell_centre_r_max"] = float(np.hypot(Rc[:, 0] - (nx - 1) / 2, Rc[:, 1] - (ny - 1) / 2).max())
             rec["cell_free_layer"] = {k: float(np.mean([c[k] for c in cfl])) for k in cfl[0]}
+            L = max(len(h) for h in hist)
+            rec["rouleaux_histogram_mean"] = (np.mean([np.pad(h, (0, L - len(h))) for h in hist], axis=0)
+                                              .round(2).tolist())
         out[name] = rec
         del sim
     line = {
         "metric": "tube observables near steady state (FP32)",
-        "config": {"workload": "tube 128x128x512 R=60, 19,241 cells (H=0.334) and its H=0 twin, "
+        "config": {"workload": "tube 128x128x512 R=60, 20,150 cells (H=0.35) and its H=0 twin, "
                                "T0=0.8, g=1e-6"},
         "results": out,
         "eta_rel": out["tube128_h0"]["flow_rate"] / out["tube128"]["flow_rate"],
