@@ -462,6 +462,87 @@ def mobility(args):
     print(json.dumps(line), flush=True)
 
 
+def shear_cell_config(alpha: float, storage: str = "f64", U: float = 0.02, n=(64, 42, 32)):
+    """Wall-bounded shear cell: solid rows y = 0 and y = ny - 1 moving along x with -U and +U
+    (shear rate 2U/(ny - 2)), periodic in x and z, T0 = 1 (nu = 1/6), gammaT = gammaR = 0.1, one
+    cell of semi-axes (4, 4, 1.5) at the centre with its symmetry axis along the gradient y."""
+    import numpy as np
+
+    nx, ny, nz = n
+    cfg = dict(nx=nx, ny=ny, nz=nz, periodic=(1, 0, 1), tau0=1.0, gammaT=0.1, gammaR=0.1,
+               alpha=alpha, wall_u_lo=(-U, 0.0, 0.0), wall_u_hi=(U, 0.0, 0.0), storage=storage)
+    from paper_1107_4889_amd import synth
+
+    solid = synth.slab(nx, ny, nz)
+    R = np.array([[nx / 2.0, (ny - 1) / 2.0, nz / 2.0]])
+    # body axes as columns: n = x, t = -z, g = y (right-handed)
+    Q = np.array([[1.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0, -1.0, 0.0]])
+    return cfg, solid, R, Q
+
+
+def tank_treading(args):
+    """Single cell in shear against the elongational torque factor alpha (Sec. II C; Sec. III,
+    the tank-treading torque figure). The paper uses a Lees-Edwards shear field and reports the
+    transition to a fixed orientation (tank treading) at alpha = 0.063 with an angle of about 40
+    degrees, and 20-35 degrees in a bounded slab; this run uses the bounded slab of
+    shear_cell_config. Per alpha: the orientation psi of the cell's long axis in the shear plane
+    (angle to the flow direction x, from the symmetry axis g as atan2(-g_x, g_y)), unwrapped, and the
+    z component of the elongational torque T^S, sampled every 250 steps after a warm-up that
+    establishes the shear flow; tumbling if psi turns through more than 180 degrees, else the
+    fixed angle (mean over the last quarter)."""
+    import numpy as np
+    import torch
+
+    from paper_1107_4889_amd import lbrbc
+
+    alphas = [0.0, 0.02, 0.04, 0.063, 0.08, 0.1, 0.15]
+    warm, steps, every = args.tt_warmup, args.tt_steps, 250
+    out = {}
+    for alpha in alphas:
+        cfg, solid, R, Q = shear_cell_config(alpha)
+        sim = lbrbc.Simulation(cfg, solid, R=R, Q=Q)
+        t0 = time.perf_counter()
+        sim.lb_step(warm)
+        psi, ts = [], []
+        for k in range(steps // every):
+            sim.lb_step(every)
+            Qc = sim.rbc_get_state()[1][0].reshape(3, 3)
+            g = Qc[:, 2]
+            psi.append(float(np.arctan2(-g[0], g[1])))
+            ts.append(float(sim.rbc_get_coupling()[0, 9]))
+        torch.cuda.synchronize()
+        ps = np.degrees(np.unwrap(np.array(psi)))
+        turned = float(ps.max() - ps.min())
+        q = len(ps) // 4
+        rec = {"psi_deg_samples": [round(x, 2) for x in ps[::4]],
+               "TS_z_samples": [float(f"{x:.4g}") for x in ts[::4]],
+               "turned_deg": round(turned, 1), "seconds": round(time.perf_counter() - t0, 2),
+               "flags": int(sim.lb_observe().flags)}
+        if turned > 180.0:
+            crossings = np.nonzero(np.diff(np.floor(ps / 180.0)) != 0)[0]
+            period = (2 * every * float(np.mean(np.diff(crossings)))) if len(crossings) > 1 else None
+            rec.update(regime="tumbling", period_steps=period)
+        else:
+            rec.update(regime="fixed orientation", psi_deg=round(float(np.mean(ps[-q:]) % 180.0), 2),
+                       psi_spread_deg=round(float(np.ptp(ps[-q:])), 3))
+        out[str(alpha)] = rec
+        print(f"[tank-treading] alpha={alpha}: {rec['regime']}, turned {turned:.0f} deg "
+              f"({rec['seconds']} s)", file=sys.stderr, flush=True)
+        del sim
+    cfg, _, _, _ = shear_cell_config(0.0)
+    line = {
+        "metric": "single-cell orientation in shear against the elongational torque factor alpha",
+        "config": {"workload": (f"wall-bounded shear cell {cfg['nx']}x{cfg['ny']}x{cfg['nz']}, walls moving "
+                                f"+/-{cfg['wall_u_hi'][0]} along x (shear rate "
+                                f"{2 * cfg['wall_u_hi'][0] / (cfg['ny'] - 2):.2e}), T0=1, gammaT=gammaR=0.1, "
+                                f"one cell (4, 4, 1.5) at the centre, FP64; {warm} warm-up + {steps} steps")},
+        "paper_printed": {"transition_alpha": 0.063, "fixed_angle_deg_lees_edwards": 40,
+                          "fixed_angle_deg_bounded_slab": "20-35"},
+        "results": out,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -491,6 +572,10 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--max-active", type=int, default=64)
     ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--tank-treading", action="store_true",
+                    help="single cell in a shear cell: orientation against alpha")
+    ap.add_argument("--tt-warmup", type=int, default=20000)
+    ap.add_argument("--tt-steps", type=int, default=40000)
     ap.add_argument("--precision", action="store_true",
                     help="reduced-precision storage study against FP64 on the same GPU")
     args = ap.parse_args()
@@ -523,6 +608,9 @@ def main():
         return
     if args.mobility:
         mobility(args)
+        return
+    if args.tank_treading:
+        tank_treading(args)
         return
 
     from paper_1107_4889_amd import lbrbc

@@ -935,12 +935,29 @@ static void spread(orc_sim* s)
  * shear stress of the non-equilibrium part (Eq. 8). Eq. 8 as printed has the sign of
  * +sum c c (f - f^eq), opposite to its left-hand side nu rho (du + du^T); the stored
  * stress is sigma = -(1 - 1/(2T)) sum c c (f - f^eq), with nu/(c^2 T) = 1 - 1/(2T). */
+/* Velocity of the wall at a solid (or outside) source row ys: the solid nodes below the box's
+ * mid-plane y = ny/2 move with wall_u_lo, the others with wall_u_hi (both zero: resting walls). */
+static const double* wall_velocity(const orc_sim* s, int ys)
+{
+    return 2 * ys < s->ny ? s->P.wall_u_lo : s->P.wall_u_hi;
+}
+
+/* Halfway bounce-back from a wall moving with velocity u_w (Ladd 1994): the population that
+ * left x towards the wall along -c_p comes back along c_p with the momentum the wall hands it,
+ * f_p(x) = f*_{opp(p)}(x) + 2 w_p rho_w (c_p . u_w) / c^2, with the wall density rho_w = 1. */
+static double bounce_back_term(const orc_sim* s, int p, int ys)
+{
+    const double* uw = wall_velocity(s, ys);
+    return 2.0 * WV[p] * (CV[p][0] * uw[0] + CV[p][1] * uw[1] + CV[p][2] * uw[2]) / CS2;
+}
+
 static void pulled(const orc_sim* s, long n, int x, int y, int z, double f[19])
 {
     int p;
     for (p = 0; p < 19; ++p) {
         long src = node_at(s, x - CV[p][0], y - CV[p][1], z - CV[p][2]);
-        if (src < 0 || s->solid[src]) f[p] = s->f[(long)opposite(p) * s->N + n];
+        if (src < 0 || s->solid[src])
+            f[p] = s->f[(long)opposite(p) * s->N + n] + bounce_back_term(s, p, y - CV[p][1]);
         else f[p] = s->f[(long)p * s->N + src];
     }
 }
@@ -1031,10 +1048,12 @@ static int stream_collide(orc_sim* s)
             for (p = 1; p < 19; ++p) {
                 long src = node_at(s, x - CV[p][0], y - CV[p][1], z - CV[p][2]);
                 if (src < 0 || s->solid[src]) {
-                    double fo = s->f[(long)opposite(p) * s->N + n];
-                    wm[0] -= 2.0 * fo * CV[p][0];
-                    wm[1] -= 2.0 * fo * CV[p][1];
-                    wm[2] -= 2.0 * fo * CV[p][2];
+                    /* the fluid gains c_p (f_back + f_out): the wall takes the opposite */
+                    const double fo = s->f[(long)opposite(p) * s->N + n];
+                    const double fb = fo + bounce_back_term(s, p, y - CV[p][1]);
+                    wm[0] -= (fo + fb) * CV[p][0];
+                    wm[1] -= (fo + fb) * CV[p][1];
+                    wm[2] -= (fo + fb) * CV[p][2];
                 }
             }
         }

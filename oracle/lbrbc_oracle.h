@@ -46,6 +46,8 @@ typedef struct orc_params {
     double rho_in, rho_out;
     double ext_force[3];  /* external force on every cell, lab frame (drag experiments) */
     double ext_torque[3]; /* external torque on every cell, body frame */
+    double wall_u_lo[3];  /* velocity of the solid nodes with y < ny/2 (moving walls) */
+    double wall_u_hi[3];  /* velocity of the solid nodes with y >= ny/2 */
 } orc_params;
 
 typedef struct orc_sim orc_sim;

@@ -42,6 +42,7 @@ class Params(ctypes.Structure):
         ("wall_particles", ctypes.c_int),
         ("open_z", ctypes.c_int), ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double),
         ("ext_force", ctypes.c_double * 3), ("ext_torque", ctypes.c_double * 3),
+        ("wall_u_lo", ctypes.c_double * 3), ("wall_u_hi", ctypes.c_double * 3),
     ]
 
 
@@ -110,7 +111,8 @@ def make_params(cfg: dict) -> Params:
                     inertia=(1000.0, 1000.0, 1000.0), vort_scale=1.0, xi=(4.0, 4.0, 1.5),
                     axes=(4.0, 4.0, 1.5), eps0=1e-3, a_wall=0.5, sigmin_wall=0.5,
                     wall_particles=1, open_z=0, rho_in=1.0, rho_out=1.0,
-                    ext_force=(0.0, 0.0, 0.0), ext_torque=(0.0, 0.0, 0.0))
+                    ext_force=(0.0, 0.0, 0.0), ext_torque=(0.0, 0.0, 0.0),
+                    wall_u_lo=(0.0, 0.0, 0.0), wall_u_hi=(0.0, 0.0, 0.0))
     d = dict(defaults)
     d.update(cfg)
     for k, v in d.items():

@@ -568,3 +568,26 @@ def test_external_force_and_torque_drive_a_free_cell_exactly():
     assert np.allclose(Q[0].reshape(3, 3), ref, atol=1e-12)
     # the plasma is left at rest: no coupling, no spreading
     assert np.abs(o.u()).max() < 1e-15
+
+
+@pytest.mark.parametrize("tau", [0.8, 1.0, 1.7])
+def test_plane_couette_between_moving_walls_is_exact(tau):
+    # Walls moving along x with -U (rows below the mid-plane) and +U (above), halfway
+    # bounce-back with the wall's momentum: the walls sit half a node outside the first fluid
+    # rows, so the steady profile is the straight line through (0.5, -U) and (ny - 1.5, +U),
+    # u_x(y) = U (2 y - ny + 1)/(ny - 2), and the shear stress is nu 2U/(ny - 2) everywhere
+    # (nu = (T - 1/2)/3), whatever tau: the scheme is exact on linear profiles.
+    ny, U = 18, 1e-3
+    cfg = dict(nx=1, ny=ny, nz=1, periodic=(1, 0, 1), tau0=tau, wall_u_lo=(-U, 0, 0), wall_u_hi=(U, 0, 0))
+    o = orc.Oracle(cfg, synth.slab(1, ny, 1))
+    o.step(40000)
+    y = np.arange(1, ny - 1)
+    u = o.u()[1:ny - 1]
+    # (round-off accumulates by about 1e-19 per step at tau = 0.8: bound 1e-11 U)
+    assert np.allclose(u[:, 0], U * (2 * y - ny + 1) / (ny - 2), rtol=0, atol=1e-11 * U)
+    assert np.abs(u[:, 1:]).max() < 1e-11 * U
+    nu = (tau - 0.5) / 3.0
+    sxy = o.sigma()[1:ny - 1, 3]
+    assert np.allclose(sxy, nu * 2 * U / (ny - 2), rtol=1e-9)
+    # the momentum the walls exchange balances: the fluid's total x momentum stays zero
+    assert abs(o.observe()["momentum"][0]) < 1e-14
