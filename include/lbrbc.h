@@ -153,6 +153,16 @@ lb_status rbc_couple(lb_ctx ctx);
  * A pair at rho_ij <= 0 returns LB_EOVERLAP. */
 lb_status rbc_collide(lb_ctx ctx, double* F, double* T);
 
+/* rbc_collide without any device memory of its own, for callers that cannot allocate (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels write the Gay-Berne force (lab, F[3*i + a]) and torque (body, T[3*i + a]) of every
+ * cell into the caller's DEVICE arrays, asynchronously on the context's stream. The cell list
+ * it needs is built in a static device array of the library (about 10 MiB per GPU, held until
+ * the process ends), not in the arena. At most 262,144 cells and 1,048,576 grid cells, else
+ * LB_EINVAL. Calls that overlap on one GPU (other streams or threads) share that array and
+ * race; an overlapping pair (rho_ij <= 0) is reported by the next synchronising call. */
+lb_status rbc_collide_static(lb_ctx ctx, double* F, double* T);
+
 /* Synchronous reads of the observables of Sec. III: mass and momentum (sums of f and f c
  * over fluid nodes, Eqs. 5-6), the flow rate Q (mean over z-slices of the summed u_z), the
  * apparent viscosity pi R^4 g / (8 Q) of a body-force-driven tube (Poiseuille's law, which

@@ -431,11 +431,41 @@ Layout layout(const lb_config& c, const Geometry& g, int n_rbc)
 
 }  // namespace
 
+// ---- scratch of rbc_collide_static, the entry point that allocates nothing ----------------------
+// Its cell list lives in this file-scope device array instead of the context's arena: one copy
+// per GPU, held until the process ends. Host code never uses the array's name as an address:
+// lb_init resolves the array's device address once per device (with that device current) and
+// every use goes through that pointer.
+constexpr int STATIC_MAX_CELLS = 1 << 18;    // 262,144 cells
+constexpr int STATIC_MAX_GRID = 1 << 20;     // 1,048,576 grid cells of the cell list
+constexpr size_t STATIC_SCRATCH_INTS = 2 * (size_t)STATIC_MAX_CELLS + 2 * (size_t)STATIC_MAX_GRID + 1 +
+                                       (STATIC_MAX_GRID + CELL_SCAN_CHUNK - 1) / CELL_SCAN_CHUNK;
+static __device__ __align__(256) int scratch[STATIC_SCRATCH_INTS];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+int* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// device address of `scratch` on device dev (which must be current)
+hipError_t resolve_scratch(int dev)
+{
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess) g_scratch_ptr[dev] = static_cast<int*>(p);
+    return e;
+}
+}  // namespace
+
 struct lb_ctx_s {
     lb_config cfg;
     KParams kp;
     Geometry geo;
     unsigned long long geo_hash = 0;
+    int device = 0;   // the GPU current at lb_init
     Layout lay;
     hipStream_t stream = nullptr;
     // Side stream (default priority) for the cells' own work, for large cell counts: the
@@ -810,6 +840,12 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
     if (arena_bytes < c->lay.total) return init_fail(c, LB_ENOMEM, "arena smaller than the footprint");
     c->stream = (hipStream_t)hip_stream;
     c->base = (char*)arena;
+    {
+        hipError_t e0 = hipGetDevice(&c->device);
+        if (e0 == hipSuccess) e0 = resolve_scratch(c->device);
+        if (e0 != hipSuccess)
+            return init_fail(c, LB_EHIP, std::string("static scratch address: ") + hipGetErrorString(e0));
+    }
     c->nrbc = n_rbc;
     const lb_config& C = c->cfg;
     const Geometry& g = c->geo;
@@ -1153,6 +1189,32 @@ lb_status lb_set_stream(lb_ctx c, void* hip_stream)
 {
     if (!c || !hip_stream) return LB_EINVAL;
     c->stream = (hipStream_t)hip_stream;
+    return LB_OK;
+}
+
+lb_status rbc_collide_static(lb_ctx c, double* F, double* T)
+{
+    if (!c) return LB_EINVAL;
+    if (c->nrbc == 0) return LB_OK;
+    if (!F || !T) return fail(c, LB_EINVAL, "rbc_collide_static needs device arrays F and T");
+    if (c->poisoned) return fail(c, LB_ESTATE, "context poisoned by a device fault");
+    const long long nc = (long long)c->kp.ncell[0] * c->kp.ncell[1] * c->kp.ncell[2];
+    if (c->nrbc > STATIC_MAX_CELLS || nc > STATIC_MAX_GRID)
+        return fail(c, LB_EINVAL, "rbc_collide_static: more than 262,144 cells or 1,048,576 grid cells "
+                                  "(the size of its static scratch)");
+    int* base = g_scratch_ptr[c->device];
+    if (!base) return fail(c, LB_EHIP, "static scratch address not resolved for this device");
+    CellBuffers b = c->cb;
+    b.cellid = base;
+    b.cell_ids = base + STATIC_MAX_CELLS;
+    b.cell_cnt = base + 2 * (size_t)STATIC_MAX_CELLS;
+    b.cell_off = b.cell_cnt + STATIC_MAX_GRID;
+    b.cell_part = b.cell_off + STATIC_MAX_GRID + 1;
+    // the counts the binning adds to start at zero whatever an earlier call left
+    launch_zero_ints(b.cell_cnt, nc, c->stream);
+    launch_cell_list(b, c->kp, c->stream);
+    launch_gay_berne_out(b, c->kp, F, T, 3, c->stream);
+    HIPCHK(c, hipGetLastError());
     return LB_OK;
 }
 

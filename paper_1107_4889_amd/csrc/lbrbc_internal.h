@@ -118,6 +118,8 @@ void launch_gay_berne(const CellBuffers& b, const KParams& kp, hipStream_t st);
 // the same forces and torques into F[stride i + a] (lab) and T[stride i + a] (body)
 void launch_gay_berne_out(const CellBuffers& b, const KParams& kp, double* F, double* T, int stride,
                           hipStream_t st);
+// zero n ints (a kernel, so it can be captured into a graph)
+void launch_zero_ints(int* p, long long n, hipStream_t st);
 // combined force and torque, friction and half kick (the map pass has written F^hyd, T^hyd
 // and the gather records)
 void launch_rb_second_half(const CellBuffers& b, const KParams& kp, hipStream_t st);

@@ -1335,6 +1335,17 @@ void launch_map_couple(const CellBuffers& b, const KParams& kp, hipStream_t st)
                        (const RT*)b.sig, kp, b.err);
 }
 
+__global__ __launch_bounds__(256) void k_zero_ints(int* __restrict__ p, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+void launch_zero_ints(int* p, long long n, hipStream_t st)
+{
+    if (n > 0) hipLaunchKernelGGL(k_zero_ints, dim3(nblk(n, 256)), dim3(256), 0, st, p, n);
+}
+
 void launch_gay_berne_out(const CellBuffers& b, const KParams& kp, double* F, double* T, int stride,
                           hipStream_t st)
 {

@@ -29,7 +29,7 @@ SYMBOLS = ["lb_query_footprint", "lb_init", "lb_step", "rbc_couple", "rbc_collid
            "lb_wall_shear_stress", "lb_apparent_viscosity", "lb_wss_accumulate", "lb_get_fields",
            "lb_set_fields", "rbc_get_state", "rbc_set_state", "rbc_get_coupling", "rbc_get_cells",
            "rbc_get_map", "lb_save", "lb_load", "lb_batch_step", "lb_set_stream", "lb_set_side_stream",
-           "lb_batch_capture", "lb_graph_launch", "lb_graph_destroy",
+           "rbc_collide_static", "lb_batch_capture", "lb_graph_launch", "lb_graph_destroy",
            "lb_sync",
            "lb_last_error",
            "lb_destroy", "lb_set_timing", "lb_kernel_time"]
@@ -88,6 +88,7 @@ _sig = {
     "lb_set_side_stream": [_P, _P],
     "rbc_couple": [_P],
     "rbc_collide": [_P, _D, _D],
+    "rbc_collide_static": [_P, _P, _P],
     "lb_observe": [_P, ctypes.POINTER(lb_observables)],
     "lb_wall_shear_stress": [_P, ctypes.c_int, _D, _LL, _I],
     "lb_apparent_viscosity": [_P, _D],
@@ -252,6 +253,12 @@ class Simulation:
         T = np.zeros((max(self.nrbc, 1), 3))
         self._chk(_lib.rbc_collide(self.h, _d(F), _d(T)), "rbc_collide")
         return F[:self.nrbc], T[:self.nrbc]
+
+    def rbc_collide_static(self, F, T):
+        """Gay-Berne forces and torques into device tensors F, T (float64, [n_rbc, 3]) on this
+        context's stream, with no device memory of the library's own."""
+        self._chk(_lib.rbc_collide_static(self.h, ctypes.c_void_p(F.data_ptr()),
+                                          ctypes.c_void_p(T.data_ptr())), "rbc_collide_static")
 
     def lb_sync(self):
         self._chk(_lib.lb_sync(self.h), "lb_sync")
