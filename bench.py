@@ -392,8 +392,10 @@ def mobility(args):
     solid = np.zeros((n, n, n), dtype=np.uint8)
     R0 = np.array([[n / 2.0, n / 2.0, n / 2.0]])
     Q0 = np.eye(3).reshape(1, 9)
+    xs = args.mob_xi_scale
     base = dict(nx=n, ny=n, nz=n, periodic=(1, 1, 1), tau0=1.0, wall_particles=0, delta_visc=0.0,
-                xi=(2.0, 2.0, 1.0), mass=10.0, inertia=(1000.0, 1000.0, 1000.0), storage="f64")
+                xi=(2.0 * xs, 2.0 * xs, 1.0 * xs), mass=10.0, inertia=(1000.0, 1000.0, 1000.0),
+                storage="f64")
     # translation: gT swept at gR = 0.01; rotation: gR swept at gT = 0.01 (the explicit
     # rotational exchange, I gR against the plasma inside a support one node thick across the
     # disc, is the first to lose stability)
@@ -402,7 +404,9 @@ def mobility(args):
     F, T = 1e-4, 1e-2
     steps = args.mob_steps
     out = {}
-    for kind, axis in (("frontal", 2), ("side-wise", 0), ("spin_short_axis", 2), ("spin_long_axis", 0)):
+    kinds = [k for k in (("frontal", 2), ("side-wise", 0), ("spin_short_axis", 2), ("spin_long_axis", 0))
+             if k[0] in args.mob_kinds.split(",")]
+    for kind, axis in kinds:
         rows = []
         spin = kind.startswith("spin")
         for g in sweeps[kind]:
@@ -453,7 +457,7 @@ def mobility(args):
     line = {
         "metric": "single-cell mobilities at infinite coupling (Sec. III)",
         "config": {"workload": f"lone cell, periodic {n}^3 plasma at rest, T0=1.0 (nu=1/6), Delta=0, "
-                               f"xi=(2,2,1), M=10, I=1000; force {F} (gR=0.01), torque {T} (gT=0.01); "
+                               f"xi={tuple(base['xi'])}, M=10, I=1000; force {F} (gR=0.01), torque {T} (gT=0.01); "
                                f"{steps} steps per run; FP64 storage"},
         "paper_printed": {"frontal": 6.6, "side-wise": 10.3, "gammaR_mesh_short_axis": 1 / 44.0,
                           "gammaR_mesh_long_axis": 1 / 38.0},
@@ -567,6 +571,9 @@ def main():
     ap.add_argument("--mobility", action="store_true",
                     help="single-cell translational and rotational mobilities vs the coupling rates")
     ap.add_argument("--mob-steps", type=int, default=20000)
+    ap.add_argument("--mob-xi-scale", type=float, default=1.0,
+                    help="mobility runs: shape-function radii (2, 2, 1) times this factor")
+    ap.add_argument("--mob-kinds", default="frontal,side-wise,spin_short_axis,spin_long_axis")
     ap.add_argument("--no-serving", action="store_true",
                     help="default run: skip the request-stream leg (p50/p99 latency)")
     ap.add_argument("--budget-gib", type=float, default=64.0)

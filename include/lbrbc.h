@@ -96,6 +96,11 @@ typedef struct lb_config {
                              combined force (drag experiments of Sec. III; 0 = none) */
     double ext_torque[3]; /* constant external torque on every cell, body frame, added to the
                              combined torque (spin experiments of Sec. III; 0 = none) */
+    double wall_u_lo[3];  /* moving walls: velocity of the solid nodes with y < ny/2 (lab) */
+    double wall_u_hi[3];  /* velocity of the solid nodes with y >= ny/2. Nonzero velocities make
+                             the halfway bounce-back hand the fluid the wall's momentum (Ladd's
+                             rule, wall density 1): the wall-bounded shear cell of the
+                             tank-treading experiments (Sec. III). Not with open_z (LB_EINVAL) */
     int cand_cap;         /* test hook: candidate nodes per cell that the one-wavefront map pass
                              holds (0 = a sampled bound, above every orientation met in
                              practice). Smaller values, raised to at least tile_max^2, send

@@ -150,11 +150,23 @@ __device__ __forceinline__ void pull_all_fast(RT* f, const PL& pl, unsigned n, i
     ((f[Ps] = Store<ST, RT>::ld(pl.src(Ps), pull_off<Ps>(n, x, y, z, kp, sx, sy, sz), kp.f16_inv)), ...);
 }
 
+// Momentum a moving wall hands the population it reflects (Ladd's rule with wall density 1):
+// 2 w_P (c_P . u_w) / c^2, u_w the velocity of the solid source row y - c_y (below the mid-plane
+// y = ny/2: wall_u_lo, else wall_u_hi). Zero for resting walls.
+template <typename RT, int P>
+__device__ __forceinline__ RT moving_wall_term(int y, const KParams& kp)
+{
+    if (!kp.moving_walls) return RT(0);
+    const double* uw = 2 * (y - cy_(P)) < kp.ny ? kp.uw_lo : kp.uw_hi;
+    return RT(6.0 * w_(P) * ((double)cx_(P) * uw[0] + (double)cy_(P) * uw[1] + (double)cz_(P) * uw[2]));
+}
+
 template <typename ST, typename RT, typename PL, int... Ps>
-__device__ __forceinline__ void bounce_back(RT* f, const PL& pl, unsigned n, uint32_t w,
+__device__ __forceinline__ void bounce_back(RT* f, const PL& pl, unsigned n, uint32_t w, int y,
                                             const KParams& kp, std::integer_sequence<int, Ps...>)
 {
-    ((f[Ps] = (w & (1u << Ps)) ? Store<ST, RT>::ld(pl.src(opp_(Ps)), n, kp.f16_inv) : f[Ps]), ...);
+    ((f[Ps] = (w & (1u << Ps)) ? Store<ST, RT>::ld(pl.src(opp_(Ps)), n, kp.f16_inv) + moving_wall_term<RT, Ps>(y, kp)
+                               : f[Ps]), ...);
 }
 
 template <typename RT>
@@ -235,7 +247,7 @@ __device__ __forceinline__ void stream_collide_node(const PL& pl, const uint32_t
     RT f[19];
     if (live) {
         pull_all_fast<ST, RT>(f, pl, n, x, y, z, kp, std::make_integer_sequence<int, 19>{});
-        if (w & 0x7FFFEu) bounce_back<ST, RT>(f, pl, n, w, kp, std::make_integer_sequence<int, 19>{});
+        if (w & 0x7FFFEu) bounce_back<ST, RT>(f, pl, n, w, y, kp, std::make_integer_sequence<int, 19>{});
     } else {
 #pragma unroll
         for (int p = 0; p < 19; ++p) f[p] = RT(0);

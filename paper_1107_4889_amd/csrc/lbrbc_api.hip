@@ -187,6 +187,12 @@ std::string validate(const lb_config& c, int n_rbc)
     }
     if (c.cand_cap < 0) return "cand_cap must be non-negative";
     if (c.open_z && c.periodic[2]) return "open z faces need a non-periodic z axis";
+    for (int a = 0; a < 3; ++a) {
+        if (!std::isfinite(c.wall_u_lo[a]) || !std::isfinite(c.wall_u_hi[a]))
+            return "wall velocities must be finite";
+        if (c.open_z && (c.wall_u_lo[a] != 0.0 || c.wall_u_hi[a] != 0.0))
+            return "moving walls and open z faces together are not supported";
+    }
     if (c.open_z && c.nz < 3) return "open z faces need nz >= 3";
     {
         // The kernels address every per-node plane (populations, u, sigma, coverage counts
@@ -892,6 +898,12 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
     kp.tile_max = g.tile_max;
     kp.cand_cap = g.cand_cap;
     kp.bf16_sr = C.storage == LB_BF16 && !C.bf16_nearest ? 1 : 0;
+    kp.moving_walls = 0;
+    for (int a = 0; a < 3; ++a) {
+        kp.uw_lo[a] = C.wall_u_lo[a];
+        kp.uw_hi[a] = C.wall_u_hi[a];
+        if (C.wall_u_lo[a] != 0.0 || C.wall_u_hi[a] != 0.0) kp.moving_walls = 1;
+    }
     kp.ent_shift = g.ent_shift;
 
     const Layout& L = c->lay;

@@ -75,6 +75,8 @@ struct KParams {
     int cand_cap;     // candidate nodes per cell held in LDS by the one-wavefront map pass
     int ent_shift;    // log2 of the coverage entries reserved per cell
     int bf16_sr;      // BF16 storage with stochastic rounding
+    int moving_walls; // wall_u_lo or wall_u_hi nonzero
+    double uw_lo[3], uw_hi[3];   // velocities of the solid nodes below / from the mid-plane y = ny/2
 };
 
 // ---- per-cell records ---------------------------------------------------------------------

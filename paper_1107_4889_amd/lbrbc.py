@@ -55,6 +55,7 @@ class lb_config(ctypes.Structure):
         ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double), ("map_cap", ctypes.c_int),
         ("bf16_nearest", ctypes.c_int),
         ("ext_force", ctypes.c_double * 3), ("ext_torque", ctypes.c_double * 3),
+        ("wall_u_lo", ctypes.c_double * 3), ("wall_u_hi", ctypes.c_double * 3),
         ("cand_cap", ctypes.c_int),
     ]
 
@@ -129,7 +130,8 @@ DEFAULTS = dict(periodic=(0, 0, 1), storage="f32", f16_scale=2.0 ** 21, forcing=
                 alpha=0.04, mass=10.0, inertia=(1000.0, 1000.0, 1000.0), vort_scale=1.0,
                 xi=(4.0, 4.0, 1.5), axes=(4.0, 4.0, 1.5), eps0=1e-3, a_wall=0.5, sigmin_wall=0.5,
                 wall_particles=1, open_z=0, rho_in=1.0, rho_out=1.0, map_cap=12,
-                bf16_nearest=0, ext_force=(0.0, 0.0, 0.0), ext_torque=(0.0, 0.0, 0.0), cand_cap=0)
+                bf16_nearest=0, ext_force=(0.0, 0.0, 0.0), ext_torque=(0.0, 0.0, 0.0), cand_cap=0,
+                wall_u_lo=(0.0, 0.0, 0.0), wall_u_hi=(0.0, 0.0, 0.0))
 
 
 def make_config(cfg: dict) -> lb_config:

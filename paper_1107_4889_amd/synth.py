@@ -14,9 +14,9 @@ overlap-removal sweeps that move and turn the cells (synth_pack.c). The overlap 
 the Perram-Wertheim contact function at lambda = 1/2 of two ellipsoids with shape matrices
 A = Q diag(a^2) Q^T, c = r^T (A_i + A_j)^-1 r / 2 (c >= 1: no contact), and for a cell and
 a wall mesh point the same function with a sphere of radius a_wall. A placement is accepted
-with every pair at c >= 0.98^2 and every cell-wall contact at c >= 0.95^2 (a slight soft
-overlap of the kind a small Gay-Berne energy scale permits); the few cells still violating
-either bound are dropped and the achieved hematocrit is reported.
+with every pair at c >= 0.98^2 (a slight soft overlap of the kind a small Gay-Berne energy
+scale permits) and no cell-wall contact (c >= 1); the few cells still violating either bound
+are dropped and the achieved hematocrit is reported.
 """
 from __future__ import annotations
 
@@ -287,17 +287,20 @@ class _Packer:
 
 def place_cells(solid: np.ndarray, axes, n_target: int, seed: int, periodic=(0, 0, 1),
                 a_wall: float = 0.5, batch: int = 8192, scale0: float = 0.5,
-                increments: int = 20, steps_per_increment: int = 100, final_steps: int = 1000,
-                s_accept: float = 0.98, s_wall: float = 0.95, target: float = 1.0,
-                damp: float = 0.8, verbose: bool = False) -> Placement:
+                increments: int = 20, steps_per_increment: int = 100, final_steps: int = 3000,
+                s_accept: float = 0.98, s_wall: float = 1.0, target: float = 1.0,
+                target_wall: float = 1.02, damp: float = 0.8, verbose: bool = False) -> Placement:
     """Seeded placement at a target count, reached by inflation.
 
     1. Random sequential addition of all n_target cells with their semi-axes scaled by
        scale0 (a dilute packing: it always fits), orientations uniform on SO(3).
     2. Inflation: the scale grows to 1 in `increments` equal steps; after each one,
-       `steps_per_increment` overlap-removal sweeps move and turn the cells.
+       `steps_per_increment` overlap-removal sweeps move and turn the cells, aiming at contact
+       `target` between cells and `target_wall` (a little clear of the wall points).
     3. Sweeps at full size until every pair has contact function c >= s_accept^2 and every
-       cell-wall contact c >= s_wall^2, or `final_steps` sweeps.
+       cell-wall contact c >= s_wall^2 (no wall overlap at all: the cell-wall Gay-Berne pair is
+       the stiffest of the model, and a cell started inside its range would get kicks the time
+       step cannot follow), or `final_steps` sweeps.
     4. Cells still violating either bound are dropped (the achieved hematocrit is reported).
 
     A sweep is a damped Jacobi projection on the linearised contact function: for each pair
@@ -352,12 +355,12 @@ def place_cells(solid: np.ndarray, axes, n_target: int, seed: int, periodic=(0, 
     # 2.-3. inflation, then sweeps at full size
     sched = [scale0 + (1.0 - scale0) * (k + 1) / increments for k in range(increments)]
     for sc in sched:
-        Rs, Qs, worst, nbad = _sweeps(pk, Rs, Qs, sc, target, target, target, target, damp,
+        Rs, Qs, worst, nbad = _sweeps(pk, Rs, Qs, sc, target, target_wall, target, s_wall, damp,
                                       steps_per_increment)
         if verbose:
             print(f"[synth] scale {sc:.3f}: worst pair contact {worst:.4f}, {nbad} violations",
                   file=sys.stderr, flush=True)
-    Rs, Qs, worst, nbad = _sweeps(pk, Rs, Qs, 1.0, target, target, s_accept, s_wall, damp,
+    Rs, Qs, worst, nbad = _sweeps(pk, Rs, Qs, 1.0, target, target_wall, s_accept, s_wall, damp,
                                   final_steps)
     if verbose:
         print(f"[synth] final: worst pair contact {worst:.4f}, {nbad} violations", file=sys.stderr,
@@ -485,7 +488,7 @@ def _tree(pts, box, periodic):
 # ---- named workloads -------------------------------------------------------------------------
 AXES = (4.0, 4.0, 1.5)
 # bump when place_cells changes, so that cached placements are regenerated
-PLACEMENT_VERSION = "inflate-v1"
+PLACEMENT_VERSION = "inflate-v2"
 
 
 def _cache_dir():

@@ -46,7 +46,8 @@ def test_footprint_and_validation_on_host():
                 dict(nx=0), dict(xi=(0, 1, 1)), dict(storage="f16", f16_scale=3.0),
                 dict(storage="f16", f16_scale=0.0), dict(storage="f16", f16_scale=2.0 ** 41),
                 dict(storage="f16", f16_scale=2.0 ** 9), dict(storage="f16", f16_scale=1.0),
-                dict(cand_cap=-1)):
+                dict(cand_cap=-1), dict(wall_u_hi=(float("nan"), 0, 0)),
+                dict(periodic=(0, 0, 0), open_z=1, wall_u_lo=(1e-3, 0, 0))):
         with pytest.raises(lbrbc.LbError) as e:
             lbrbc.lb_query_footprint(_cfg(**bad), solid, 10)
         assert e.value.status == lbrbc.LB_EINVAL
