@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 STORAGE_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
+LAYOUTS = {"auto": 0, "dense": 1, "compact": 2}
 
 
 def kernel_source_hash() -> str:
@@ -42,10 +43,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:12]
 
 
-def measured_traffic(workload: str, storage: str):
+def measured_traffic(workload: str, storage: str, layout: str):
     """HBM bytes per stream-collide launch from the committed rocprofv3 counter summary,
     or None when the kernel source changed since the counters were taken."""
-    fn = os.path.join(ROOT, "profiles", f"traffic_stream_collide_{workload}_{storage}.json")
+    fn = os.path.join(ROOT, "profiles", f"traffic_stream_collide_{workload}_{storage}_{layout}.json")
     if not os.path.exists(fn):
         return None
     d = json.load(open(fn))
@@ -499,7 +500,7 @@ def tank_treading(args):
 
     from paper_1107_4889_amd import lbrbc
 
-    alphas = [0.0, 0.02, 0.04, 0.063, 0.08, 0.1, 0.15]
+    alphas = [a * args.tt_alpha_scale for a in (0.0, 0.02, 0.04, 0.063, 0.08, 0.1, 0.15)]
     warm, steps, every = args.tt_warmup, args.tt_steps, 250
     out = {}
     for alpha in alphas:
@@ -507,19 +508,24 @@ def tank_treading(args):
         sim = lbrbc.Simulation(cfg, solid, R=R, Q=Q)
         t0 = time.perf_counter()
         sim.lb_step(warm)
-        psi, ts = [], []
+        psi, ts, th, om = [], [], [], []
         for k in range(steps // every):
             sim.lb_step(every)
             Qc = sim.rbc_get_state()[1][0].reshape(3, 3)
             g = Qc[:, 2]
             psi.append(float(np.arctan2(-g[0], g[1])))
-            ts.append(float(sim.rbc_get_coupling()[0, 9]))
+            cp = sim.rbc_get_coupling()[0]
+            ts.append(float(cp[9]))
+            th.append(float(cp[15]))
+            om.append(float(cp[6]))
         torch.cuda.synchronize()
         ps = np.degrees(np.unwrap(np.array(psi)))
         turned = float(ps.max() - ps.min())
         q = len(ps) // 4
         rec = {"psi_deg_samples": [round(x, 2) for x in ps[::4]],
                "TS_z_samples": [float(f"{x:.4g}") for x in ts[::4]],
+               "T_hyd_z_samples": [float(f"{x:.4g}") for x in th[::4]],
+               "vorticity_z_samples": [float(f"{x:.4g}") for x in om[::4]],
                "turned_deg": round(turned, 1), "seconds": round(time.perf_counter() - t0, 2),
                "flags": int(sim.lb_observe().flags)}
         if turned > 180.0:
@@ -539,7 +545,8 @@ def tank_treading(args):
         "config": {"workload": (f"wall-bounded shear cell {cfg['nx']}x{cfg['ny']}x{cfg['nz']}, walls moving "
                                 f"+/-{cfg['wall_u_hi'][0]} along x (shear rate "
                                 f"{2 * cfg['wall_u_hi'][0] / (cfg['ny'] - 2):.2e}), T0=1, gammaT=gammaR=0.1, "
-                                f"one cell (4, 4, 1.5) at the centre, FP64; {warm} warm-up + {steps} steps")},
+                                f"one cell (4, 4, 1.5) at the centre, FP64; {warm} warm-up + {steps} steps"),
+                   "alpha_scale": args.tt_alpha_scale},
         "paper_printed": {"transition_alpha": 0.063, "fixed_angle_deg_lees_edwards": 40,
                           "fixed_angle_deg_bounded_slab": "20-35"},
         "results": out,
@@ -583,6 +590,11 @@ def main():
                     help="single cell in a shear cell: orientation against alpha")
     ap.add_argument("--tt-warmup", type=int, default=20000)
     ap.add_argument("--tt-steps", type=int, default=40000)
+    ap.add_argument("--tt-alpha-scale", type=float, default=1.0,
+                    help="multiply the paper's alpha values (the balance of the elongational torque "
+                         "against the rotational friction)")
+    ap.add_argument("--layout", default="auto", choices=["auto", "dense", "compact"],
+                    help="storage layout of the per-node planes (auto: compact for sparse geometries)")
     ap.add_argument("--precision", action="store_true",
                     help="reduced-precision storage study against FP64 on the same GPU")
     args = ap.parse_args()
@@ -623,9 +635,12 @@ def main():
     from paper_1107_4889_amd import lbrbc
 
     cfg, solid, pl, desc = workload(args.workload, args.storage)
+    cfg["layout"] = LAYOUTS[args.layout]
     print(f"[bench] {desc}", file=sys.stderr, flush=True)
     sim = lbrbc.Simulation(cfg, solid, R=pl.R, Q=pl.Q)
+    arena = sim.bytes
     n_fluid = int((solid == 0).sum())
+    layout = "compact" if sim.lb_observe().compact else "dense"
 
     sim.lb_step(args.warmup)
     torch.cuda.synchronize()
@@ -668,6 +683,9 @@ def main():
             "n_cells": int(len(pl.R)),
             "hematocrit": round(pl.hematocrit, 4),
             "storage": args.storage,
+            "layout": layout,
+            "stored_slots": int(obs.n_stored),
+            "arena_gib": round(arena / 2 ** 30, 3),
             "parallelism": "single GPU",
         },
         "stream_collide": {
@@ -682,7 +700,7 @@ def main():
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4),
-            "traffic": measured_traffic(args.workload, args.storage),
+            "traffic": measured_traffic(args.workload, args.storage, layout),
         },
         "observables": {"flow_rate": obs.flow_rate, "eta_app": obs.eta_app,
                         "wss_mean": obs.wss_mean, "mass": obs.mass},

@@ -105,6 +105,13 @@ typedef struct lb_config {
                              holds (0 = a sampled bound, above every orientation met in
                              practice). Smaller values, raised to at least tile_max^2, send
                              more cells to the full-tile pass; the results do not change */
+    int layout;           /* storage of the per-node planes: 0 = automatic, 1 = dense (every node,
+                             index x + nx (y + ny z)), 2 = compact (only the 64-node row segments
+                             that hold a fluid node, with a neighbour table per segment). The
+                             automatic choice is compact when under 60% of the row segments hold
+                             fluid. Field accessors work in lattice order either way;
+                             checkpoints hold the storage order, so one loads only into a
+                             context of the same layout */
 } lb_config;
 
 typedef struct lb_rbc {
@@ -127,6 +134,8 @@ typedef struct lb_observables {
     long long n_fluid;
     int n_wall_nodes;
     int n_rbc;
+    int compact;          /* storage layout in use: 1 compact, 0 dense */
+    long long n_stored;   /* storage slots per plane (nodes, or 64 per stored row segment) */
 } lb_observables;
 
 /* Bytes of device arena needed for this configuration (solid: host, nx*ny*nz bytes). */

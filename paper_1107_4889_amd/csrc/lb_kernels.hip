@@ -90,47 +90,46 @@ __device__ __forceinline__ void spread_at(unsigned n, uint32_t count, const MapP
     else spread_slots<RT, CAP_MAX>(n, cnt, mp, gat, kp, g, theta);
 }
 
+// ---- pull sources in the compact layout -----------------------------------------------------
+// The 27 neighbour segments of one stored segment, held in registers (scalar ones when the
+// segment is wave-uniform). Entry e = (dx + 1) + 3 (dy + 1) + 9 (dz + 1).
+struct SegNb {
+    int e[27];
+};
+__device__ __forceinline__ void load_segnb(const int* __restrict__ nb, int s, SegNb& out)
+{
+#pragma unroll
+    for (int j = 0; j < 27; ++j) out.e[j] = nb[27 * s + j];
+}
+
+// Storage index of the pull source x - c_P of node (x, y, z), storage k, in the segment that
+// starts at x0: the source row is (y - c_y, z - c_z); along x it lies in the left neighbour
+// segment when it falls before x0, in the right one when it passes the segment's last node (x0 + 63
+// or the row's last node), else in the column of the node itself, at lane (x - c_x wrapped) mod 64.
+// A source outside the box or in a segment that is not stored is solid: the node's own index is
+// returned (any valid address: the bounce-back value replaces it).
 template <int P>
-__device__ __forceinline__ unsigned pull_src(int x, int y, int z, int xm, int xp, int ym, int yp,
-                                             int zm, int zp, const KParams& kp)
+__device__ __forceinline__ unsigned pull_src(unsigned k, int x, int x0, const SegNb& nb, const KParams& kp)
 {
-    // source of direction P is x - c_P
-    const int xs = cx_(P) == 1 ? xm : (cx_(P) == -1 ? xp : x);
-    const int ys = cy_(P) == 1 ? ym : (cy_(P) == -1 ? yp : y);
-    const int zs = cz_(P) == 1 ? zm : (cz_(P) == -1 ? zp : z);
-    return (unsigned)xs + (unsigned)kp.nx * ((unsigned)ys + (unsigned)kp.ny * (unsigned)zs);
+    constexpr int eb = 3 * (1 - cy_(P)) + 9 * (1 - cz_(P));
+    int sn;
+    if constexpr (cx_(P) > 0) sn = x == x0 ? nb.e[eb] : nb.e[eb + 1];
+    else if constexpr (cx_(P) < 0) sn = (x == x0 + 63 || x == kp.nx - 1) ? nb.e[eb + 2] : nb.e[eb + 1];
+    else sn = nb.e[eb + 1];
+    int xs = x - cx_(P);
+    xs += xs < 0 ? kp.nx : 0;
+    xs -= xs >= kp.nx ? kp.nx : 0;
+    return sn < 0 ? k : ((unsigned)sn << 6) | ((unsigned)xs & 63u);
 }
 
-// one population: a uniform plane base (scalar registers) plus a 32-bit per-lane offset;
-// the bounce-back source is the opposite population at the node itself
-template <typename ST, typename RT, int P>
-__device__ __forceinline__ void pull_one(RT* f, const ST* __restrict__ fin, unsigned n, uint32_t w,
-                                         int x, int y, int z, int xm, int xp, int ym, int yp,
-                                         int zm, int zp, const KParams& kp)
-{
-    constexpr int O = opp_(P);
-    const bool bb = w & (1u << P);
-    const ST* plane = fin + (size_t)(bb ? O : P) * (size_t)kp.ld;
-    const unsigned off = bb ? n : pull_src<P>(x, y, z, xm, xp, ym, yp, zm, zp, kp);
-    f[P] = Store<ST, RT>::ld(plane, off, kp.f16_inv);
-}
-
-template <typename ST, typename RT, int... Ps>
-__device__ __forceinline__ void pull_all(RT* f, const ST* __restrict__ fin, unsigned n, uint32_t w,
-                                         int x, int y, int z, int xm, int xp, int ym, int yp,
-                                         int zm, int zp, const KParams& kp,
-                                         std::integer_sequence<int, Ps...>)
-{
-    (pull_one<ST, RT, Ps>(f, fin, n, w, x, y, z, xm, xp, ym, yp, zm, zp, kp), ...);
-}
-
-// pull source offset: n - (c_x + nx c_y + nx ny c_z), wrapped by one period at the box
-// faces on every axis, so the address is always inside the lattice (on a non-periodic face
-// the source is a wall: the value read there is replaced by the bounce-back value)
+// Dense layout (storage index n = x + nx (y + ny z)): the pull source offset is
+// n - (c_x + nx c_y + nx ny c_z), wrapped by one period at the box faces on every axis, so the
+// address is always inside the lattice (on a non-periodic face the source is a wall: the value
+// read there is replaced by the bounce-back value)
 template <int P>
-__device__ __forceinline__ unsigned pull_off(unsigned n, int x, int y, int z, const KParams& kp,
-                                             unsigned sx, unsigned sy, unsigned sz)
+__device__ __forceinline__ unsigned pull_off(unsigned n, int x, int y, int z, const KParams& kp)
 {
+    const unsigned sx = 1u, sy = (unsigned)kp.nx, sz = (unsigned)kp.nx * (unsigned)kp.ny;
     // offset change of the source along an axis: -c s normally, -c s (1 - L) across the face
     unsigned off = n;
     if (cx_(P)) off -= (unsigned)cx_(P) * ((x == (cx_(P) > 0 ? 0 : kp.nx - 1)) ? sx * (1u - (unsigned)kp.nx) : sx);
@@ -139,15 +138,49 @@ __device__ __forceinline__ unsigned pull_off(unsigned n, int x, int y, int z, co
     return off;
 }
 
+// Where a node's pull sources are: in the dense layout from its coordinates, in the compact
+// layout from its segment's neighbour table.
+struct NodeAt {
+    unsigned k;       // storage index
+    int x, y, z;      // lattice coordinates
+    int x0;           // compact layout: first x of the node's segment
+};
+
+template <bool CMP, int P>
+__device__ __forceinline__ unsigned source_of(const NodeAt& a, const SegNb& nb, const KParams& kp)
+{
+    if constexpr (CMP) return pull_src<P>(a.k, a.x, a.x0, nb, kp);
+    else return pull_off<P>(a.k, a.x, a.y, a.z, kp);
+}
+
+// one population: a uniform plane base (scalar registers) plus a 32-bit per-lane offset;
+// the bounce-back source is the opposite population at the node itself
+template <typename ST, typename RT, bool CMP, int P>
+__device__ __forceinline__ void pull_one(RT* f, const ST* __restrict__ fin, const NodeAt& a, uint32_t w,
+                                         const SegNb& nb, const KParams& kp)
+{
+    constexpr int O = opp_(P);
+    const bool bb = w & (1u << P);
+    const ST* plane = fin + (size_t)(bb ? O : P) * (size_t)kp.ld;
+    const unsigned off = bb ? a.k : source_of<CMP, P>(a, nb, kp);
+    f[P] = Store<ST, RT>::ld(plane, off, kp.f16_inv);
+}
+
+template <typename ST, typename RT, bool CMP, int... Ps>
+__device__ __forceinline__ void pull_all(RT* f, const ST* __restrict__ fin, const NodeAt& a, uint32_t w,
+                                         const SegNb& nb, const KParams& kp, std::integer_sequence<int, Ps...>)
+{
+    (pull_one<ST, RT, CMP, Ps>(f, fin, a, w, nb, kp), ...);
+}
+
 // the 19 pull loads depend only on the position, so they issue without waiting for the node
 // word; directions whose source is solid are then replaced by the opposite population at
 // the node itself (halfway bounce-back)
-template <typename ST, typename RT, typename PL, int... Ps>
-__device__ __forceinline__ void pull_all_fast(RT* f, const PL& pl, unsigned n, int x, int y, int z,
+template <typename ST, typename RT, bool CMP, typename PL, int... Ps>
+__device__ __forceinline__ void pull_all_fast(RT* f, const PL& pl, const NodeAt& a, const SegNb& nb,
                                               const KParams& kp, std::integer_sequence<int, Ps...>)
 {
-    const unsigned sx = 1u, sy = (unsigned)kp.nx, sz = (unsigned)kp.nx * (unsigned)kp.ny;
-    ((f[Ps] = Store<ST, RT>::ld(pl.src(Ps), pull_off<Ps>(n, x, y, z, kp, sx, sy, sz), kp.f16_inv)), ...);
+    ((f[Ps] = Store<ST, RT>::ld(pl.src(Ps), source_of<CMP, Ps>(a, nb, kp), kp.f16_inv)), ...);
 }
 
 // Momentum a moving wall hands the population it reflects (Ladd's rule with wall density 1):
@@ -211,24 +244,25 @@ __device__ __forceinline__ void collide_pairs(const RT* f, const PL& pl, unsigne
 }
 
 // ---- fused spreading + stream + collide (Sec. II A, Eqs. 1-8) -----------------------------
-// One thread per node; SoA planes f[p*ld + n] of the shifted populations f - w.
-// Launch: blocks of 64 x 4 threads (a wavefront spans 64 consecutive x), grid
-// (ceil(nx/64), ceil(ny/4), nz): no integer division, 32-bit node offsets.
-// A wavefront with no fluid node exits. In a wavefront that has one, every lane stores all
+// One thread per node, a wavefront over 64 consecutive x (a tile row of the dense layout, or one
+// stored row segment of the compact layout); SoA planes f[p*ld + k] of the shifted populations
+// f - w, 32-bit storage offsets. A wavefront with no fluid node exits. In a wavefront that has one, every lane stores all
 // 28 outputs (zero at solid and open-plane nodes, whose values are never read: pulls from
 // solid sources are replaced by bounce-back, open planes are rewritten by the boundary
 // kernel), so that each store writes whole cache lines: stores that leave part of a line
 // unwritten, as at every wall crossing of a lattice row, measured markedly slower in HBM.
 // CLEAR: also clear the coverage counts read here (every lane of the wavefront, whole lines),
 // for the map pass that next uses this set of counts
-template <typename ST, typename RT, typename PL, bool CLEAR = false>
+template <typename ST, typename RT, typename PL, bool CLEAR, bool CMP>
 __device__ __forceinline__ void stream_collide_node(const PL& pl, const uint32_t* __restrict__ nodeword,
                                                     const MapPlanes<RT>& mp,
                                                     const Gather<RT>* __restrict__ gat,
                                                     const KParams& kp, unsigned* __restrict__ err,
-                                                    int x, int y, int z)
+                                                    const NodeAt& at, const SegNb& nb)
 {
-    const unsigned n = (unsigned)x + (unsigned)kp.nx * ((unsigned)y + (unsigned)kp.ny * (unsigned)z);
+    // (compact layout: lanes past the row's end hold node word 0, not live)
+    const unsigned n = at.k;
+    const int y = at.y;
     const uint32_t w = nodeword[n];
     const bool live = (w & NW_FLUID) && !(w & NW_OPEN);
     const unsigned long long lv = __ballot(live);
@@ -246,7 +280,7 @@ __device__ __forceinline__ void stream_collide_node(const PL& pl, const uint32_t
     const bool put_f = line_has_fluid((unsigned)sizeof(ST)), put_u = line_has_fluid((unsigned)sizeof(RT));
     RT f[19];
     if (live) {
-        pull_all_fast<ST, RT>(f, pl, n, x, y, z, kp, std::make_integer_sequence<int, 19>{});
+        pull_all_fast<ST, RT, CMP>(f, pl, at, nb, kp, std::make_integer_sequence<int, 19>{});
         if (w & 0x7FFFEu) bounce_back<ST, RT>(f, pl, n, w, y, kp, std::make_integer_sequence<int, 19>{});
     } else {
 #pragma unroll
@@ -320,71 +354,84 @@ __device__ __forceinline__ void stream_collide_node(const PL& pl, const uint32_t
 
 // Block -> tile: the hardware deals consecutive blocks to the eight XCDs in turn, so block
 // k + 8 t of a grid padded to a multiple of 8 is tile t of XCD k's contiguous share. Each XCD then
-// sweeps one range of tiles in order (x fastest, then y, then z), and the cache lines that
-// neighbouring tiles share (the pulls across a tile's x faces) are fetched into one L2.
+// sweeps one range of tiles (four stored segments each, in x, y, z order), and the cache lines
+// that neighbouring segments share (the pulls across a segment's x faces) are fetched into one L2.
 __device__ __forceinline__ unsigned xcd_tile()
 {
     const unsigned per = gridDim.x / 8u;
     return (blockIdx.x % 8u) * per + blockIdx.x / 8u;
 }
 
+// one stored segment per wavefront, four per block; the segment's neighbour table is loaded
+// once per wavefront into scalar registers
+template <typename ST, typename RT, typename PL, bool CLEAR>
+__device__ __forceinline__ void stream_collide_segment(const PL& pl, const uint32_t* __restrict__ nodeword,
+                                                       const MapPlanes<RT>& mp,
+                                                       const Gather<RT>* __restrict__ gat,
+                                                       const KParams& kp, unsigned* __restrict__ err,
+                                                       const SegTables& tab, int s)
+{
+    s = __builtin_amdgcn_readfirstlane(s);
+    const int4 sg = tab.seg[s];
+    SegNb nb;
+    load_segnb(tab.nb, s, nb);
+    const NodeAt at{((unsigned)s << 6) | threadIdx.x, sg.x + (int)threadIdx.x, sg.y, sg.z, sg.x};
+    stream_collide_node<ST, RT, PL, CLEAR, true>(pl, nodeword, mp, gat, kp, err, at, nb);
+}
+
+// compact layout: one stored segment per wavefront, four per block
+template <typename ST, typename RT, bool CLEAR>
+__global__ __launch_bounds__(256) void k_stream_collide_cmp(
+    const Planes<ST, RT> pl, const uint32_t* __restrict__ nodeword, const MapPlanes<RT> mp,
+    const Gather<RT>* __restrict__ gat, KParams kp, unsigned* __restrict__ err, const SegTables tab,
+    int nseg)
+{
+    const int s = (int)xcd_tile() * 4 + (int)threadIdx.y;
+    if (s < nseg) stream_collide_segment<ST, RT, Planes<ST, RT>, CLEAR>(pl, nodeword, mp, gat, kp, err, tab, s);
+}
+
+// dense layout: tiles of 64 x 4 nodes (a wavefront spans 64 consecutive x)
 template <typename ST, typename RT, bool CLEAR>
 __global__ __launch_bounds__(256) void k_stream_collide(
     const Planes<ST, RT> pl, const uint32_t* __restrict__ nodeword, const MapPlanes<RT> mp,
     const Gather<RT>* __restrict__ gat, KParams kp, unsigned* __restrict__ err, unsigned nbx,
     unsigned nby, unsigned ntiles)
 {
-    // tiles of 64 x 4 nodes (a wavefront spans 64 consecutive x)
     const unsigned t = xcd_tile();
     if (t >= ntiles) return;
     const unsigned r = t / nbx;
     const int x = (int)(t - r * nbx) * 64 + threadIdx.x;
     const int y = (int)(r % nby) * 4 + threadIdx.y;
-    if (x < kp.nx && y < kp.ny)
-        stream_collide_node<ST, RT, Planes<ST, RT>, CLEAR>(pl, nodeword, mp, gat, kp, err, x, y,
-                                                           (int)(r / nby));
-}
-
-// The same update over a list of 64-node row segments (x0, y, z) that hold a fluid node, one
-// wavefront each, four per block: sparse geometries skip the all-solid segments, whose
-// wavefronts would only read their node words and exit.
-template <typename ST, typename RT, bool CLEAR>
-__global__ __launch_bounds__(256) void k_stream_collide_seg(
-    const Planes<ST, RT> pl, const uint32_t* __restrict__ nodeword, const MapPlanes<RT> mp,
-    const Gather<RT>* __restrict__ gat, KParams kp, unsigned* __restrict__ err,
-    const int4* __restrict__ segs, int nseg)
-{
-    const int k = (int)xcd_tile() * 4 + (int)threadIdx.y;
-    if (k >= nseg) return;
-    const int4 sg = segs[k];
-    const int x = sg.x + (int)threadIdx.x;
-    if (x < kp.nx)
-        stream_collide_node<ST, RT, Planes<ST, RT>, CLEAR>(pl, nodeword, mp, gat, kp, err, x, sg.y, sg.z);
+    const int z = (int)(r / nby);
+    if (x < kp.nx && y < kp.ny) {
+        const NodeAt at{(unsigned)x + (unsigned)kp.nx * ((unsigned)y + (unsigned)kp.ny * (unsigned)z), x, y, z, 0};
+        stream_collide_node<ST, RT, Planes<ST, RT>, CLEAR, false>(pl, nodeword, mp, gat, kp, err, at, SegNb{});
+    }
 }
 
 // ---- open z faces: non-equilibrium extrapolation (Guo, Zheng & Shi 2002) ------------------
+// planes[q] = (storage index of the plane node, storage index of its inner neighbour along z
+// or -1 when that node is solid, x | y << 16, z)
 template <typename ST, typename RT>
 __global__ __launch_bounds__(256) void k_open_bc(
     const ST* __restrict__ fin, ST* __restrict__ fout, const uint32_t* __restrict__ nodeword,
-    const long long* __restrict__ plane_nodes, int nplane, const MapPlanes<RT> mp,
+    const int4* __restrict__ planes, int nplane, const MapPlanes<RT> mp,
     const Gather<RT>* __restrict__ gat, RT* __restrict__ uout, RT* __restrict__ sout, KParams kp,
-    int clear_counts)
+    const SegTables tab, int clear_counts)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nplane) return;
-    const long long n = plane_nodes[k];
-    const uint32_t w = nodeword[n];
-    const int x = (int)(n % kp.nx);
-    const long long yz = n / kp.nx;
-    const int y = (int)(yz % kp.ny);
-    const int z = (int)(yz / kp.ny);
-    const int zi = z == 0 ? 1 : kp.nz - 2;
-    const long long ni = (long long)x + (long long)kp.nx * ((long long)y + (long long)kp.ny * zi);
-    const uint32_t wi = nodeword[ni];
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nplane) return;
+    const int4 pq = planes[q];
+    const unsigned n = (unsigned)pq.x;
+    const int x = pq.z & 0xffff;
+    const int z = pq.w;
+    const bool inner_fluid = pq.y >= 0;
+    const unsigned ni = inner_fluid ? (unsigned)pq.y : n;
+    const uint32_t wi = inner_fluid ? nodeword[ni] : 0u;
     const RT rb = z == 0 ? (RT)kp.rho_in : (RT)kp.rho_out;
     RT gb[3], thb;
-    const uint32_t cn = mp.cnt[n], cni = mp.cnt[ni];
-    spread_at<RT>((unsigned)n, cn, mp, gat, kp, gb, thb);
+    const uint32_t cn = mp.cnt[n], cni = inner_fluid ? mp.cnt[ni] : 0u;
+    spread_at<RT>(n, cn, mp, gat, kp, gb, thb);
     const RT om = RT(1) / ((RT)kp.tau0 + (RT)kp.delta * thb);
 #pragma unroll
     for (int a = 0; a < 6; ++a) sout[(long long)a * kp.ld + n] = RT(0);
@@ -397,14 +444,20 @@ __global__ __launch_bounds__(256) void k_open_bc(
         for (int a = 0; a < 3; ++a) uout[(long long)a * kp.ld + n] = RT(0);
         return;
     }
-    const int xm = x == 0 ? kp.nx - 1 : x - 1, xp = x == kp.nx - 1 ? 0 : x + 1;
-    const int ym = y == 0 ? kp.ny - 1 : y - 1, yp = y == kp.ny - 1 ? 0 : y + 1;
-    const int zm = zi - 1, zp = zi + 1;
     RT f[19];
-    pull_all<ST, RT>(f, fin, (unsigned)ni, wi, x, y, zi, xm, xp, ym, yp, zm, zp, kp,
-                     std::make_integer_sequence<int, 19>{});
+    const int y = pq.z >> 16, zi = z == 0 ? 1 : kp.nz - 2;
+    if (kp.compact) {
+        const int si = (int)(ni >> 6);
+        SegNb nb;
+        load_segnb(tab.nb, si, nb);
+        const NodeAt at{ni, x, y, zi, tab.seg[si].x};
+        pull_all<ST, RT, true>(f, fin, at, wi, nb, kp, std::make_integer_sequence<int, 19>{});
+    } else {
+        const NodeAt at{ni, x, y, zi, 0};
+        pull_all<ST, RT, false>(f, fin, at, wi, SegNb{}, kp, std::make_integer_sequence<int, 19>{});
+    }
     RT gi[3], thi;
-    spread_at<RT>((unsigned)ni, cni, mp, gat, kp, gi, thi);
+    spread_at<RT>(ni, cni, mp, gat, kp, gi, thi);
     if (clear_counts && cni) mp.cnt[ni] = 0u;
     RT drho = 0, mx = 0, my = 0, mz = 0;
     for (int p = 0; p < 19; ++p) {
@@ -458,24 +511,6 @@ __global__ __launch_bounds__(256) void k_clear_counts(uint32_t* __restrict__ cnt
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (n == 0 && ovf) ovf[0] = 0;
     if (n < N && cnt[n]) cnt[n] = 0u;
-}
-
-// the same over the row segments that hold a fluid node (counts are only ever set at fluid
-// nodes); blocks of 64 x 4, one segment per wavefront. A segment with a count is written
-// whole (scattered single-word stores measured several times slower).
-__global__ __launch_bounds__(256) void k_clear_counts_seg(uint32_t* __restrict__ cnt,
-                                                          const int4* __restrict__ segs, int nseg,
-                                                          int nx, int ny, int* __restrict__ ovf)
-{
-    const int k = (int)blockIdx.x * 4 + (int)threadIdx.y;
-    if (k == 0 && threadIdx.x == 0 && ovf) ovf[0] = 0;
-    if (k >= nseg) return;
-    const int4 sg = segs[k];
-    const int x = sg.x + (int)threadIdx.x;
-    const bool in = x < nx;
-    const size_t n = (size_t)x + (size_t)nx * ((size_t)sg.y + (size_t)ny * (size_t)sg.z);
-    const uint32_t c = in ? cnt[n] : 0u;
-    if (__ballot(c != 0u) != 0ull && in) cnt[n] = 0u;
 }
 
 // ---- FP64 reductions: mass, momentum, summed u_z (two passes, fixed order) --------------
@@ -583,30 +618,38 @@ __global__ __launch_bounds__(256) void kf_stream(const FusedArgs fa)
     const int sl = fused_slot_at(fa, (int)t, lb);
     const SlotDesc& d = *fa.slot[sl];
     const KParams kp = d.kp;
-    // flat node order (no idle lanes on lattices narrower than, or not a multiple of, 64)
+    const bool odd = (fa.parity >> sl) & 1ull;
+    const PlanesLd<ST, RT> pl{(const ST*)(odd ? d.fB : d.fA), (ST*)(odd ? d.fA : d.fB), (RT*)d.b.u,
+                              (RT*)d.b.sig, (unsigned long long)kp.ld};
+    const MapPlanes<RT> mp = map_planes_dev<RT>(d.b.map_ids, d.b.map_vals, d.b.cnt, kp);
+    if (kp.compact) {
+        // four stored segments per block, one per wavefront
+        const int s = lb * 4 + (int)threadIdx.y;
+        if ((long long)s * 64 < kp.N)
+            stream_collide_segment<ST, RT, PlanesLd<ST, RT>, true>(pl, d.b.nodeword, mp, (const Gather<RT>*)d.b.gat,
+                                                                   kp, d.b.err, d.b.tab, s);
+        return;
+    }
+    // dense layout: flat node order (no idle lanes on lattices narrower than, or not a multiple
+    // of, 64)
     const unsigned n = (unsigned)lb * 256u + threadIdx.y * 64u + threadIdx.x;
     if (n >= (unsigned)kp.N) return;
     const unsigned nxy = (unsigned)kp.nx * (unsigned)kp.ny;
     const int z = (int)(n / nxy), rem = (int)(n - (unsigned)z * nxy);
     const int y = rem / kp.nx, x = rem - y * kp.nx;
-    const bool odd = (fa.parity >> sl) & 1ull;
-    const PlanesLd<ST, RT> pl{(const ST*)(odd ? d.fB : d.fA), (ST*)(odd ? d.fA : d.fB), (RT*)d.b.u,
-                              (RT*)d.b.sig, (unsigned long long)kp.ld};
-    const MapPlanes<RT> mp = map_planes_dev<RT>(d.b.map_ids, d.b.map_vals, d.b.cnt, kp);
-    stream_collide_node<ST, RT, PlanesLd<ST, RT>, true>(pl, d.b.nodeword, mp, (const Gather<RT>*)d.b.gat,
-                                                        kp, d.b.err, x, y, z);
+    const NodeAt at{n, x, y, z, 0};
+    stream_collide_node<ST, RT, PlanesLd<ST, RT>, true, false>(pl, d.b.nodeword, mp, (const Gather<RT>*)d.b.gat,
+                                                               kp, d.b.err, at, SegNb{});
 }
 
 // ---- launchers ---------------------------------------------------------------------------------
 template <typename ST, typename RT>
 void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword, const int* ids,
                            const void* vals, uint32_t* cnt, const void* gat, void* u, void* sig,
-                           const KParams& kp, unsigned* err, bool clear_counts, const int4* segs,
+                           const KParams& kp, unsigned* err, bool clear_counts, const SegTables& tab,
                            int nseg, hipStream_t st)
 {
-    const unsigned nbx = (unsigned)((kp.nx + 63) / 64), nby = (unsigned)((kp.ny + 3) / 4);
-    const unsigned ntiles = nbx * nby * (unsigned)kp.nz;
-    const dim3 grid((ntiles + 7u) / 8u * 8u);
+    if (kp.compact && nseg <= 0) return;
     Planes<ST, RT> pl;
     const size_t ld = (size_t)kp.ld;
     for (int p = 0; p < 19; ++p) {
@@ -615,37 +658,39 @@ void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword
     }
     for (int a = 0; a < 3; ++a) pl.u[a] = (RT*)u + a * ld;
     for (int a = 0; a < 6; ++a) pl.sig[a] = (RT*)sig + a * ld;
-    const uint32_t* nw = nodeword;
-    if (segs && nseg > 0) {
-        const dim3 sgrid(((unsigned)((nseg + 3) / 4) + 7u) / 8u * 8u);
+    const auto mp = map_planes<RT>(ids, vals, cnt, kp);
+    const Gather<RT>* g = (const Gather<RT>*)gat;
+    if (kp.compact) {
+        const dim3 grid(((unsigned)((nseg + 3) / 4) + 7u) / 8u * 8u);
         if (clear_counts)
-            hipLaunchKernelGGL((k_stream_collide_seg<ST, RT, true>), sgrid, dim3(64, 4, 1), 0, st, pl, nw,
-                               map_planes<RT>(ids, vals, cnt, kp), (const Gather<RT>*)gat, kp, err, segs, nseg);
+            hipLaunchKernelGGL((k_stream_collide_cmp<ST, RT, true>), grid, dim3(64, 4, 1), 0, st, pl, nodeword, mp, g,
+                               kp, err, tab, nseg);
         else
-            hipLaunchKernelGGL((k_stream_collide_seg<ST, RT, false>), sgrid, dim3(64, 4, 1), 0, st, pl, nw,
-                               map_planes<RT>(ids, vals, cnt, kp), (const Gather<RT>*)gat, kp, err, segs, nseg);
+            hipLaunchKernelGGL((k_stream_collide_cmp<ST, RT, false>), grid, dim3(64, 4, 1), 0, st, pl, nodeword, mp,
+                               g, kp, err, tab, nseg);
         return;
     }
+    const unsigned nbx = (unsigned)((kp.nx + 63) / 64), nby = (unsigned)((kp.ny + 3) / 4);
+    const unsigned ntiles = nbx * nby * (unsigned)kp.nz;
+    const dim3 grid((ntiles + 7u) / 8u * 8u);
     if (clear_counts)
-        hipLaunchKernelGGL((k_stream_collide<ST, RT, true>), grid, dim3(64, 4, 1), 0, st, pl, nw,
-                           map_planes<RT>(ids, vals, cnt, kp), (const Gather<RT>*)gat, kp, err, nbx, nby,
-                           ntiles);
+        hipLaunchKernelGGL((k_stream_collide<ST, RT, true>), grid, dim3(64, 4, 1), 0, st, pl, nodeword, mp, g, kp,
+                           err, nbx, nby, ntiles);
     else
-        hipLaunchKernelGGL((k_stream_collide<ST, RT, false>), grid, dim3(64, 4, 1), 0, st, pl, nw,
-                           map_planes<RT>(ids, vals, cnt, kp), (const Gather<RT>*)gat, kp, err, nbx, nby,
-                           ntiles);
+        hipLaunchKernelGGL((k_stream_collide<ST, RT, false>), grid, dim3(64, 4, 1), 0, st, pl, nodeword, mp, g, kp,
+                           err, nbx, nby, ntiles);
 }
 
 template <typename ST, typename RT>
-void launch_open_bc(const void* fin, void* fout, const uint32_t* nodeword, const long long* planes,
+void launch_open_bc(const void* fin, void* fout, const uint32_t* nodeword, const int4* planes,
                     int nplane, const int* ids, const void* vals, uint32_t* cnt, const void* gat, void* u,
-                    void* sig, const KParams& kp, bool clear_counts, hipStream_t st)
+                    void* sig, const KParams& kp, const SegTables& tab, bool clear_counts, hipStream_t st)
 {
     if (nplane <= 0) return;
     hipLaunchKernelGGL((k_open_bc<ST, RT>), dim3((nplane + 255) / 256), dim3(256), 0, st,
                        (const ST*)fin, (ST*)fout, nodeword, planes, nplane,
                        map_planes<RT>(ids, vals, cnt, kp), (const Gather<RT>*)gat, (RT*)u, (RT*)sig, kp,
-                       clear_counts ? 1 : 0);
+                       tab, clear_counts ? 1 : 0);
 }
 
 template <typename RT>
@@ -657,14 +702,8 @@ void launch_spread_field(const uint32_t* nodeword, const int* ids, const void* v
                        map_planes<RT>(ids, vals, cnt, kp), (const Gather<RT>*)gat, (RT*)g, (RT*)t, kp);
 }
 
-void launch_clear_counts(uint32_t* cnt, long long N, int* ovf, const int4* segs, int nseg,
-                         int nx, int ny, hipStream_t st)
+void launch_clear_counts(uint32_t* cnt, long long N, int* ovf, hipStream_t st)
 {
-    if (segs && nseg > 0) {
-        hipLaunchKernelGGL(k_clear_counts_seg, dim3((unsigned)((nseg + 3) / 4)), dim3(64, 4, 1), 0, st,
-                           cnt, segs, nseg, nx, ny, ovf);
-        return;
-    }
     hipLaunchKernelGGL(k_clear_counts, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
                        cnt, N, ovf);
 }
@@ -700,12 +739,12 @@ void launch_fused_lattice(const FusedArgs& fa, int stage, hipStream_t st)
     template void launch_fused_lattice<ST, RT>(const FusedArgs&, int, hipStream_t);               \
     template void launch_stream_collide<ST, RT>(const void*, void*, const uint32_t*, const int*,  \
                                                 const void*, uint32_t*, const void*, void*, void*, \
-                                                const KParams&, unsigned*, bool, const int4*,     \
+                                                const KParams&, unsigned*, bool, const SegTables&, \
                                                 int, hipStream_t);                                \
-    template void launch_open_bc<ST, RT>(const void*, void*, const uint32_t*, const long long*,   \
+    template void launch_open_bc<ST, RT>(const void*, void*, const uint32_t*, const int4*,        \
                                          int, const int*, const void*, uint32_t*, const void*,    \
                                          void*, void*,                                            \
-                                         const KParams&, bool, hipStream_t);                      \
+                                         const KParams&, const SegTables&, bool, hipStream_t);    \
     template void launch_observe<ST, RT>(const void*, const uint32_t*, const void*,               \
                                          const KParams&, double*, int, double*, hipStream_t);
 INST_ST(double, double)

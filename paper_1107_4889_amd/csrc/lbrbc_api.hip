@@ -23,23 +23,39 @@ constexpr int MAX_TIMED = 4096;
 
 size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
-// a segment list replaces the dense launch grid when fewer than this fraction of the 64-node
-// row segments hold fluid (the benchmark tube: 94%; the Y-bifurcation: a few per cent)
-constexpr double SEG_LIST_MAX_FRACTION = 0.6;
+// automatic layout choice: the compact layout (only the 64-node row segments holding fluid are
+// stored) when fewer than this fraction of all row segments hold fluid (the straight tubes:
+// 80-94%, dense; the Y-bifurcation in its box: a few per cent, compact)
+constexpr double COMPACT_MAX_FRACTION = 0.6;
 
 int storage_bytes(int s) { return s == LB_F64 ? 8 : (s == LB_F32 ? 4 : 2); }
 int real_bytes(int s) { return s == LB_F64 ? 8 : 4; }
 
 // ---- host geometry tables --------------------------------------------------------------------
 struct Geometry {
-    long long N = 0, ld = 0, n_fluid = 0;
-    std::vector<uint32_t> nodeword;
+    long long nodes = 0;             // lattice nodes nx ny nz
+    long long N = 0, ld = 0, n_fluid = 0;   // storage slots (nodes, or 64 per stored segment)
+    bool compact = false;
+    int nbx = 1;                     // 64-node column segments per row
+    std::vector<uint32_t> nodeword;  // per storage slot
     std::vector<int> wall_xyz;       // solid nodes with a fluid D3Q19 neighbour
-    std::vector<long long> wn_node;  // wall-adjacent fluid nodes
+    std::vector<long long> wn_node;  // wall-adjacent fluid nodes: storage index
+    std::vector<long long> wn_dense; //   and lattice index x + nx (y + ny z)
     std::vector<double> wn_nrm;
-    std::vector<long long> planes;   // open-boundary plane nodes
-    std::vector<int> segs;           // (x0, y, z, 0) of the 64-node row segments holding fluid,
-                                     // kept only when under SEG_LIST_MAX_FRACTION of all segments
+    std::vector<int> planes;         // open-boundary plane nodes: (k, k of the inner neighbour
+                                     // or -1 when solid, x | y << 16, z)
+    std::vector<int> segs;           // compact layout: (x0, y, z, 0) per stored segment,
+    std::vector<int> segnb;          //   27 neighbour segments each,
+    std::vector<int> segmap;         //   stored segment per column segment, or -1
+    // storage index of lattice node n (x + nx (y + ny z)), -1 when not stored
+    long long store_of(long long n, int nx, int ny) const
+    {
+        if (!compact) return n;
+        const long long x = n % nx, row = n / nx;
+        const int sg = segmap[(size_t)((x >> 6) + (long long)nbx * row)];
+        (void)ny;
+        return sg < 0 ? -1 : ((long long)sg << 6) | (x & 63);
+    }
     int ncell[3] = {1, 1, 1};
     double cedge[3] = {1, 1, 1};
     int wncell[3] = {1, 1, 1};        // grid of the wall points, edge >= the cell-wall cut-off
@@ -51,10 +67,12 @@ struct Geometry {
     int ent_shift = 0;
 };
 
-// FNV-1a over the node words
+// FNV-1a over the layout and the node words (in storage order)
 unsigned long long geometry_hash(const Geometry& g)
 {
     unsigned long long h = 1469598103934665603ull;
+    h ^= g.compact ? 1u : 0u;
+    h *= 1099511628211ull;
     for (uint32_t w : g.nodeword)
         for (int b = 0; b < 4; ++b) {
             h ^= (w >> (8 * b)) & 0xffu;
@@ -194,6 +212,8 @@ std::string validate(const lb_config& c, int n_rbc)
             return "moving walls and open z faces together are not supported";
     }
     if (c.open_z && c.nz < 3) return "open z faces need nz >= 3";
+    if (c.open_z && (c.nx > 65535 || c.ny > 32767)) return "open z faces need nx < 65536 and ny < 32768";
+    if (c.layout < 0 || c.layout > 2) return "layout must be 0 (automatic), 1 (dense) or 2 (compact)";
     {
         // The kernels address every per-node plane (populations, u, sigma, coverage counts
         // and slots) as a base plus a 32-bit byte offset node * element size: the padded plane
@@ -219,14 +239,9 @@ std::string validate(const lb_config& c, int n_rbc)
 
 std::string build_geometry(const lb_config& c, const uint8_t* solid, int n_rbc, Geometry& g)
 {
-    g.N = (long long)c.nx * c.ny * c.nz;
-    // plane stride: a multiple of 256 B plus an odd number of 256-B blocks, so that planes
-    // read together do not start at power-of-two distances (HBM channel spread)
-    {
-        const long long G = 256 / storage_bytes(c.storage);
-        g.ld = (g.N + 2 * G - 1) / (2 * G) * (2 * G) + G;
-    }
-    g.nodeword.assign((size_t)g.N, 0u);
+    g.nodes = (long long)c.nx * c.ny * c.nz;
+    std::vector<uint32_t> dense((size_t)g.nodes, 0u);   // node words in lattice order
+    std::vector<long long> plane_nodes;
     auto is_fluid = [&](int x, int y, int z) {
         long long m = node_at(c, x, y, z);
         return m >= 0 && !solid[m];
@@ -262,40 +277,100 @@ std::string build_geometry(const lb_config& c, const uint8_t* solid, int n_rbc, 
                 if (wadj) {
                     w |= NW_WALLADJ;
                     const double len = std::sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
-                    g.wn_node.push_back(n);
+                    g.wn_dense.push_back(n);
                     for (int a = 0; a < 3; ++a) g.wn_nrm.push_back(len > 0 ? nv[a] / len : 0.0);
                 }
                 if (c.open_z && (z == 0 || z == c.nz - 1)) {
                     w |= NW_OPEN;
-                    g.planes.push_back(n);
+                    plane_nodes.push_back(n);
                 }
                 // inner neighbour of an open-plane node (z = 1 above the inlet, z = nz - 2
                 // below the outlet)
                 if (c.open_z && ((z == 1 && !solid[n - (long long)c.nx * c.ny]) ||
                                  (z == c.nz - 2 && !solid[n + (long long)c.nx * c.ny])))
                     w |= NW_OPEN_INNER;
-                g.nodeword[n] = w;
+                dense[n] = w;
                 g.n_fluid++;
             }
-    // row segments of 64 nodes that hold a fluid node: sparse geometries launch the
-    // stream-collide and the count clearing over these only
+    // storage layout: the 64-node row segments that hold a fluid node decide between the dense
+    // layout (every node stored, index x + nx (y + ny z)) and the compact one
     {
-        const int nb = (c.nx + 63) / 64;
-        long long active = 0;
-        std::vector<int> segs;
-        for (int z = 0; z < c.nz; ++z)
-            for (int y = 0; y < c.ny; ++y)
-                for (int b = 0; b < nb; ++b) {
-                    const long long n0 = (long long)c.nx * ((long long)y + (long long)c.ny * z);
-                    bool any = false;
-                    for (int x = 64 * b; x < std::min(c.nx, 64 * b + 64) && !any; ++x)
-                        any = (g.nodeword[n0 + x] & NW_FLUID) != 0;
-                    if (!any) continue;
-                    ++active;
-                    segs.insert(segs.end(), {64 * b, y, z, 0});
+        const int nbx = (c.nx + 63) / 64;
+        g.nbx = nbx;
+        const long long ncol = (long long)nbx * c.ny * c.nz;
+        std::vector<int> smap((size_t)ncol, -1);
+        int active = 0;
+        for (long long col = 0; col < ncol; ++col) {
+            const long long row = col / nbx, x0 = 64 * (col - row * nbx);
+            const long long n0 = row * c.nx;
+            for (long long x = x0; x < std::min<long long>(c.nx, x0 + 64); ++x)
+                if (dense[(size_t)(n0 + x)] & NW_FLUID) {
+                    smap[(size_t)col] = active++;
+                    break;
                 }
-        const long long total = (long long)nb * c.ny * c.nz;
-        if (active > 0 && (double)active < SEG_LIST_MAX_FRACTION * (double)total) g.segs.swap(segs);
+        }
+        g.compact = c.layout == 2 || (c.layout == 0 && active > 0 &&
+                                      (double)active < COMPACT_MAX_FRACTION * (double)ncol);
+        if (g.compact) {
+            g.segmap.swap(smap);
+            g.segs.assign((size_t)active * 4, 0);
+            g.segnb.assign((size_t)active * 27, -1);
+            for (long long col = 0; col < ncol; ++col) {
+                const int sg = g.segmap[(size_t)col];
+                if (sg < 0) continue;
+                const long long row = col / nbx;
+                const int x0 = (int)(64 * (col - row * nbx)), y = (int)(row % c.ny), z = (int)(row / c.ny);
+                g.segs[4 * (size_t)sg + 0] = x0;
+                g.segs[4 * (size_t)sg + 1] = y;
+                g.segs[4 * (size_t)sg + 2] = z;
+                // x of the neighbouring column segments: the node before x0, the first node past
+                // the segment's last node (both wrapped on a periodic x axis, else outside)
+                const int xl = x0 - 1, xr = std::min(x0 + 64, c.nx);
+                const int xs[3] = {xl >= 0 ? xl : (c.periodic[0] ? c.nx - 1 : -1), x0,
+                                   xr < c.nx ? xr : (c.periodic[0] ? 0 : -1)};
+                for (int dz = -1; dz <= 1; ++dz)
+                    for (int dy = -1; dy <= 1; ++dy)
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            int Y = y + dy, Z = z + dz;
+                            const int X = xs[dx + 1];
+                            if (X < 0) continue;
+                            if (Y < 0 || Y >= c.ny) {
+                                if (!c.periodic[1]) continue;
+                                Y = (Y + c.ny) % c.ny;
+                            }
+                            if (Z < 0 || Z >= c.nz) {
+                                if (!c.periodic[2]) continue;
+                                Z = (Z + c.nz) % c.nz;
+                            }
+                            g.segnb[27 * (size_t)sg + (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)] =
+                                g.segmap[(size_t)((X >> 6) + (long long)nbx * (Y + (long long)c.ny * Z))];
+                        }
+            }
+            g.N = 64LL * active;
+            g.nodeword.assign((size_t)g.N, 0u);
+            for (int sg = 0; sg < active; ++sg) {
+                const int x0 = g.segs[4 * (size_t)sg], y = g.segs[4 * (size_t)sg + 1], z = g.segs[4 * (size_t)sg + 2];
+                const long long n0 = (long long)c.nx * ((long long)y + (long long)c.ny * z);
+                for (int x = x0; x < std::min(c.nx, x0 + 64); ++x)
+                    g.nodeword[64 * (size_t)sg + (x - x0)] = dense[(size_t)(n0 + x)];
+            }
+        } else {
+            g.N = g.nodes;
+            g.nodeword.swap(dense);
+        }
+        // plane stride: a multiple of 256 B plus an odd number of 256-B blocks, so that planes
+        // read together do not start at power-of-two distances (HBM channel spread)
+        const long long G = 256 / storage_bytes(c.storage);
+        g.ld = (g.N + 2 * G - 1) / (2 * G) * (2 * G) + G;
+        g.wn_node.resize(g.wn_dense.size());
+        for (size_t k = 0; k < g.wn_dense.size(); ++k) g.wn_node[k] = g.store_of(g.wn_dense[k], c.nx, c.ny);
+        const long long nxy = (long long)c.nx * c.ny;
+        for (long long n : plane_nodes) {
+            const long long z = n / nxy, rem = n - z * nxy, y = rem / c.nx, x = rem - y * c.nx;
+            const long long ni = z == 0 ? n + nxy : n - nxy;
+            const long long ki = solid[ni] ? -1 : g.store_of(ni, c.nx, c.ny);
+            g.planes.insert(g.planes.end(), {(int)g.store_of(n, c.nx, c.ny), (int)ki, (int)(x | (y << 16)), (int)z});
+        }
     }
     // cell grid: r_c bounds every Gay-Berne cut-off (cell-cell and cell-wall)
     const double amax = std::max(c.axes[0], std::max(c.axes[1], c.axes[2]));
@@ -378,8 +453,8 @@ std::string build_geometry(const lb_config& c, const uint8_t* solid, int n_rbc, 
 // ---- arena layout --------------------------------------------------------------------------
 struct Layout {
     size_t fA, fB, u, sig, gdbg, tdbg, nodeword, map_ids[2], map_vals[2], cnt[2], ovf, st, cp, gat, cellid, cell_cnt, cell_off,
-        cell_part, cell_ids, wall_xyz, wcell_off, wcell_ids, wn_node, wn_nrm, wss, wss_acc, planes, segs, partials,
-        obs_out, err, slot, total;
+        cell_part, cell_ids, wall_xyz, wcell_off, wcell_ids, wn_node, wn_nrm, wss, wss_acc, planes, segs, segnb,
+        segmap, partials, obs_out, err, slot, total;
 };
 
 Layout layout(const lb_config& c, const Geometry& g, int n_rbc)
@@ -425,8 +500,10 @@ Layout layout(const lb_config& c, const Geometry& g, int n_rbc)
     L.wn_nrm = take(nwn * 3 * 8);
     L.wss = take(nwn * 8);
     L.wss_acc = take(nwn * 8);
-    L.planes = take(g.planes.size() * 8);
+    L.planes = take(g.planes.size() * 4);
     L.segs = take(g.segs.size() * 4);
+    L.segnb = take(g.segnb.size() * 4);
+    L.segmap = take(g.segmap.size() * 4);
     L.partials = take(6 * OBS_BLOCKS * 8);
     L.obs_out = take(8 * 8);
     L.err = take(4);
@@ -517,8 +594,7 @@ struct lb_ctx_s {
         b.cnt = at<uint32_t>(lay.cnt[p]);
         return b;
     }
-    // the row-segment list of a sparse geometry (null and 0: the dense launch grid)
-    const int4* segs() { return geo.segs.empty() ? nullptr : at<int4>(lay.segs); }
+    // stored segments of the compact layout (0 in the dense one)
     int nseg() const { return (int)(geo.segs.size() / 4); }
 };
 
@@ -645,7 +721,7 @@ void enqueue_cells_map_couple(lb_ctx c)
     const int p = (int)(c->step & 1);
     const CellBuffers b = c->par(p);
     launch_cell_list(b, c->kp, s);
-    launch_clear_counts(b.cnt, c->kp.N, b.ovf, c->segs(), c->nseg(), c->kp.nx, c->kp.ny, s);
+    launch_clear_counts(b.cnt, c->kp.N, b.ovf, s);
     launch_map_couple<RT>(b, c->kp, s);
     c->dirty[p] = true;
     c->map_parity = p;
@@ -687,7 +763,7 @@ void enqueue_step(lb_ctx c, bool last)
                 (void)hipStreamWaitEvent(s, c->ev_cells, 0);
             }
             if (c->dirty[p])
-                launch_clear_counts(b.cnt, kp.N, b.ovf, c->segs(), c->nseg(), kp.nx, kp.ny, s);
+                launch_clear_counts(b.cnt, kp.N, b.ovf, s);
             launch_map_couple<RT>(b, kp, s);
             c->map_parity = p;
             if (!forked) {
@@ -717,15 +793,15 @@ void enqueue_step(lb_ctx c, bool last)
         }
         launch_stream_collide<ST, RT>(c->fA, c->fB, b.nodeword, b.map_ids, b.map_vals, b.cnt,
                                       c->cb.gat, c->at<void>(c->lay.u), c->at<void>(c->lay.sig), kp,
-                                      c->cb.err, sc_clears && c->nrbc > 0, c->segs(), c->nseg(), s);
+                                      c->cb.err, sc_clears && c->nrbc > 0, c->cb.tab, c->nseg(), s);
         if (e0) {
             (void)hipEventRecord(e1, s);
             c->sc_pairs.emplace_back(e0, e1);
         }
         if (!c->geo.planes.empty())
-            launch_open_bc<ST, RT>(c->fA, c->fB, b.nodeword, c->at<long long>(c->lay.planes),
-                                   (int)c->geo.planes.size(), b.map_ids, b.map_vals, b.cnt, c->cb.gat,
-                                   c->at<void>(c->lay.u), c->at<void>(c->lay.sig), kp,
+            launch_open_bc<ST, RT>(c->fA, c->fB, b.nodeword, c->at<int4>(c->lay.planes),
+                                   (int)c->geo.planes.size() / 4, b.map_ids, b.map_vals, b.cnt, c->cb.gat,
+                                   c->at<void>(c->lay.u), c->at<void>(c->lay.sig), kp, c->cb.tab,
                                    sc_clears && c->nrbc > 0, s);
         if (c->wss_on)
             launch_wss<RT>(c->at<void>(c->lay.sig), c->at<long long>(c->lay.wn_node),
@@ -861,6 +937,8 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
     for (int a = 0; a < 3; ++a) kp.per[a] = C.periodic[a] ? 1 : 0;
     kp.N = g.N;
     kp.ld = g.ld;
+    kp.nbx = g.nbx;
+    kp.compact = g.compact ? 1 : 0;
     kp.forcing = C.forcing;
     kp.cap = C.map_cap;
     kp.tau0 = C.tau0; kp.delta = C.delta_visc; kp.kappa = C.kappa;
@@ -929,6 +1007,9 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
     b.u = c->at<void>(L.u);
     b.sig = c->at<void>(L.sig);
     b.err = c->at<unsigned>(L.err);
+    b.tab.seg = c->at<int4>(L.segs);
+    b.tab.nb = c->at<int>(L.segnb);
+    b.tab.map = c->at<int>(L.segmap);
 
     hipStream_t s = c->stream;
     auto h2d = [&](size_t off, const void* src, size_t bytes) {
@@ -945,8 +1026,10 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
     e = e ? e : h2d(L.wcell_ids, g.wcell_ids.data(), g.wcell_ids.size() * 4);
     e = e ? e : h2d(L.wn_node, g.wn_node.data(), g.wn_node.size() * 8);
     e = e ? e : h2d(L.wn_nrm, g.wn_nrm.data(), g.wn_nrm.size() * 8);
-    e = e ? e : h2d(L.planes, g.planes.data(), g.planes.size() * 8);
+    e = e ? e : h2d(L.planes, g.planes.data(), g.planes.size() * 4);
     e = e ? e : h2d(L.segs, g.segs.data(), g.segs.size() * 4);
+    e = e ? e : h2d(L.segnb, g.segnb.data(), g.segnb.size() * 4);
+    e = e ? e : h2d(L.segmap, g.segmap.data(), g.segmap.size() * 4);
     std::vector<RbcState> hs(n_rbc);
     for (int i = 0; i < n_rbc; ++i) {
         RbcState& r = hs[i];
@@ -1300,6 +1383,8 @@ lb_status lb_observe(lb_ctx c, lb_observables* o)
     o->n_fluid = c->geo.n_fluid;
     o->n_wall_nodes = (int)nwn;
     o->n_rbc = c->nrbc;
+    o->compact = c->geo.compact ? 1 : 0;
+    o->n_stored = c->kp.N;
     return st;
 }
 
@@ -1309,7 +1394,7 @@ lb_status lb_wall_shear_stress(lb_ctx c, int time, double* wss, long long* node,
     const int nwn = (int)c->geo.wn_node.size();
     *n = nwn;
     if (node)
-        for (int k = 0; k < nwn; ++k) node[k] = c->geo.wn_node[k];
+        for (int k = 0; k < nwn; ++k) node[k] = c->geo.wn_dense[k];
     if (!wss) return LB_OK;
     if (time) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1355,20 +1440,24 @@ lb_status lb_get_fields(lb_ctx c, double* f, double* u, double* sigma, double* g
     if (!c) return LB_EINVAL;
     lb_status st = check_fault(c);
     const int S = c->cfg.storage;
-    const size_t N = (size_t)c->kp.N, ld = (size_t)c->kp.ld;
+    const size_t N = (size_t)c->geo.nodes, ld = (size_t)c->kp.ld;
     const size_t rs = real_bytes(S);
+    // storage slot of every lattice node (-1: not stored, rest state and zero fields)
+    std::vector<long long> ks(N);
+    for (size_t n = 0; n < N; ++n) ks[n] = c->geo.store_of((long long)n, c->cfg.nx, c->cfg.ny);
     if (f) {
         std::vector<char> h(19 * ld * storage_bytes(S));
         HIPCHK(c, hipMemcpy(h.data(), c->fA, h.size(), hipMemcpyDeviceToHost));
         const double inv = S == LB_F16 ? 1.0 / c->cfg.f16_scale : 1.0;
         for (int p = 0; p < 19; ++p)
-            for (size_t n = 0; n < N; ++n) f[p * N + n] = w_(p) + load_stored(h.data(), p * ld + n, S, inv);
+            for (size_t n = 0; n < N; ++n)
+                f[p * N + n] = w_(p) + (ks[n] < 0 ? 0.0 : load_stored(h.data(), p * ld + ks[n], S, inv));
     }
     auto planes = [&](size_t off, int k, double* out) -> lb_status {
         std::vector<char> h(k * ld * rs);
         HIPCHK(c, hipMemcpy(h.data(), c->base + off, h.size(), hipMemcpyDeviceToHost));
         for (int a = 0; a < k; ++a)
-            for (size_t n = 0; n < N; ++n) out[n * k + a] = load_real(h.data(), a * ld + n, S);
+            for (size_t n = 0; n < N; ++n) out[n * k + a] = ks[n] < 0 ? 0.0 : load_real(h.data(), a * ld + ks[n], S);
         return LB_OK;
     };
     lb_status r;
@@ -1384,19 +1473,24 @@ lb_status lb_set_fields(lb_ctx c, const double* f, const double* u, const double
     if (!c) return LB_EINVAL;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const int S = c->cfg.storage;
-    const size_t N = (size_t)c->kp.N, ld = (size_t)c->kp.ld;
+    const size_t N = (size_t)c->geo.nodes, ld = (size_t)c->kp.ld;
     const size_t rs = real_bytes(S);
+    // nodes that are not stored (compact layout) are solid: their values are dropped
+    std::vector<long long> ks(N);
+    for (size_t n = 0; n < N; ++n) ks[n] = c->geo.store_of((long long)n, c->cfg.nx, c->cfg.ny);
     if (f) {
         std::vector<char> h(19 * ld * storage_bytes(S), 0);
         const double scale = S == LB_F16 ? c->cfg.f16_scale : 1.0;
         for (int p = 0; p < 19; ++p)
-            for (size_t n = 0; n < N; ++n) store_value(h.data(), p * ld + n, S, f[p * N + n] - w_(p), scale);
+            for (size_t n = 0; n < N; ++n)
+                if (ks[n] >= 0) store_value(h.data(), p * ld + ks[n], S, f[p * N + n] - w_(p), scale);
         HIPCHK(c, hipMemcpy(c->fA, h.data(), h.size(), hipMemcpyHostToDevice));
     }
     auto planes = [&](size_t off, int k, const double* in) -> lb_status {
         std::vector<char> h(k * ld * rs, 0);
         for (int a = 0; a < k; ++a)
-            for (size_t n = 0; n < N; ++n) store_real(h.data(), a * ld + n, S, in[n * k + a]);
+            for (size_t n = 0; n < N; ++n)
+                if (ks[n] >= 0) store_real(h.data(), a * ld + ks[n], S, in[n * k + a]);
         HIPCHK(c, hipMemcpy(c->base + off, h.data(), h.size(), hipMemcpyHostToDevice));
         return LB_OK;
     };
@@ -1486,10 +1580,17 @@ lb_status rbc_get_map(lb_ctx c, int* off, int* ids, long long* len)
 {
     if (!c || !len) return LB_EINVAL;
     lb_status st = check_fault(c);
-    const size_t N = (size_t)c->kp.N, ld = (size_t)c->kp.ld;
+    const size_t N = (size_t)c->geo.nodes, NS = (size_t)c->kp.N, ld = (size_t)c->kp.ld;
     const CellBuffers b = c->par(c->map_parity);
+    std::vector<uint32_t> cs(NS, 0u);
+    if (c->nrbc && NS) HIPCHK(c, hipMemcpy(cs.data(), b.cnt, NS * 4, hipMemcpyDeviceToHost));
+    // counts and slot columns in lattice order
     std::vector<uint32_t> cn(N, 0u);
-    if (c->nrbc) HIPCHK(c, hipMemcpy(cn.data(), b.cnt, N * 4, hipMemcpyDeviceToHost));
+    std::vector<long long> ks(N);
+    for (size_t n = 0; n < N; ++n) {
+        ks[n] = c->geo.store_of((long long)n, c->cfg.nx, c->cfg.ny);
+        if (ks[n] >= 0) cn[n] = cs[(size_t)ks[n]];
+    }
     long long tot = 0;
     for (size_t n = 0; n < N; ++n) tot += std::min<int>((int)cn[n], c->kp.cap);
     if (!ids) {
@@ -1511,7 +1612,7 @@ lb_status rbc_get_map(lb_ctx c, int* off, int* ids, long long* len)
     for (size_t n = 0; n < N; ++n) {
         const int cnt = std::min<int>((int)cn[n], c->kp.cap);
         const long long k0 = k;
-        for (int q = 0; q < cnt; ++q) ids[k++] = slots[(size_t)q * ld + n] >> c->kp.ent_shift;
+        for (int q = 0; q < cnt; ++q) ids[k++] = slots[(size_t)q * ld + (size_t)ks[n]] >> c->kp.ent_shift;
         std::sort(ids + k0, ids + k);
         if (off) off[n + 1] = (int)k;
     }

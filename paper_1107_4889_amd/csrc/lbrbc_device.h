@@ -49,8 +49,10 @@ constexpr unsigned ERR_UNSTABLE = 1u, ERR_OVERLAP = 2u, ERR_CAPACITY = 4u;
 struct KParams {
     int nx, ny, nz;
     int per[3];
-    long long N;      // nodes
+    long long N;      // storage slots: 64 per stored row segment (the nodes of the compact layout)
     long long ld;     // plane stride (N rounded up)
+    int nbx;          // 64-node column segments per lattice row, ceil(nx / 64)
+    int compact;      // 1: compact layout (only the row segments holding fluid are stored)
     int forcing;
     int cap;
     double tau0, delta, kappa;
@@ -78,6 +80,30 @@ struct KParams {
     int moving_walls; // wall_u_lo or wall_u_hi nonzero
     double uw_lo[3], uw_hi[3];   // velocities of the solid nodes below / from the mid-plane y = ny/2
 };
+
+// ---- compact layout -------------------------------------------------------------------------
+// Only the 64-node row segments (x0 = 64 b, y, z) that hold a fluid node are stored, one after
+// another: node (x, y, z) of stored segment s has storage index k = 64 s + (x - x0). Tables:
+//   seg[s]           (x0, y, z, 0) of stored segment s;
+//   segnb[27 s + e]  the stored segment holding the neighbouring column segment (dx, dy, dz) in
+//                    {-1, 0, 1}^3, e = (dx + 1) + 3 (dy + 1) + 9 (dz + 1), where dx = -1 is the
+//                    segment of x0 - 1 and dx = +1 that of the first node past the segment
+//                    (wrapped on periodic axes); -1 when it is outside the box or not stored;
+//   segmap[b + nbx (y + ny z)]  stored segment of column segment b of row (y, z), or -1.
+struct SegTables {
+    const int4* seg;
+    const int* nb;
+    const int* map;
+};
+
+// storage index of node (X, Y, Z): x + nx (y + ny z) in the dense layout; in the compact one
+// from the segment map, -1 when the node's row segment is not stored (the node is solid)
+__device__ __forceinline__ int storage_of(const int* __restrict__ segmap, const KParams& kp, int X, int Y, int Z)
+{
+    if (!kp.compact) return X + kp.nx * (Y + kp.ny * Z);
+    const int s = segmap[(X >> 6) + kp.nbx * (Y + kp.ny * Z)];
+    return s < 0 ? -1 : (s << 6) | (X & 63);
+}
 
 // ---- per-cell records ---------------------------------------------------------------------
 struct RbcState {        // FP64, lab frame except Om (body) and Tc (body)

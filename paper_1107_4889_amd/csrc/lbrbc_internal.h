@@ -15,17 +15,17 @@ namespace lbrbc {
 template <typename ST, typename RT>
 void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword, const int* ids,
                            const void* vals, uint32_t* cnt, const void* gat, void* u, void* sig,
-                           const KParams& kp, unsigned* err, bool clear_counts, const int4* segs,
+                           const KParams& kp, unsigned* err, bool clear_counts, const SegTables& tab,
                            int nseg, hipStream_t st);
+// planes: per open-plane node (k, k of its inner neighbour, x | y << 16, z)
 template <typename ST, typename RT>
-void launch_open_bc(const void* fin, void* fout, const uint32_t* nodeword, const long long* planes,
+void launch_open_bc(const void* fin, void* fout, const uint32_t* nodeword, const int4* planes,
                     int nplane, const int* ids, const void* vals, uint32_t* cnt, const void* gat, void* u,
-                    void* sig, const KParams& kp, bool clear_counts, hipStream_t st);
+                    void* sig, const KParams& kp, const SegTables& tab, bool clear_counts, hipStream_t st);
 template <typename RT>
 void launch_spread_field(const uint32_t* nodeword, const int* ids, const void* vals, uint32_t* cnt,
                          const void* gat, void* g, void* t, const KParams& kp, hipStream_t st);
-void launch_clear_counts(uint32_t* cnt, long long N, int* ovf, const int4* segs, int nseg,
-                         int nx, int ny, hipStream_t st);
+void launch_clear_counts(uint32_t* cnt, long long N, int* ovf, hipStream_t st);
 template <typename ST, typename RT>
 void launch_observe(const void* f, const uint32_t* nodeword, const void* u, const KParams& kp,
                     double* partials, int nblk, double* out, hipStream_t st);
@@ -50,6 +50,7 @@ struct CellBuffers {
     const int* wcell_off; // [ncells + 1]
     const int* wcell_ids; // [nwall]
     uint32_t* nodeword;   // static bits per node (fluid, bounce-back, wall, open planes)
+    SegTables tab;        // compact layout: stored segments, their neighbours, the segment map
     // one of the two coverage sets (chosen by the step's parity)
     int* map_ids;         // [cap * ld] entry index per coverage slot
     void* map_vals;       // [entries * 4] RT: raw kernel and its gradient per entry

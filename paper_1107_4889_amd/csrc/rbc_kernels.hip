@@ -289,10 +289,6 @@ __device__ __forceinline__ bool wrap_coord(int& X, int L, int per)
     return per || !(lo || hi);
 }
 
-__device__ __forceinline__ unsigned node_of(const KParams& kp, int X, int Y, int Z)
-{
-    return (unsigned)X + (unsigned)kp.nx * ((unsigned)Y + (unsigned)kp.ny * (unsigned)Z);
-}
 
 // block index -> position in the spatially sorted cell order, so that each XCD (blocks are
 // dealt to the eight XCDs round-robin) works on one contiguous, spatially compact chunk and
@@ -326,7 +322,8 @@ constexpr int TILE_ROWS_MAX = 20 * 20;   // tile_max <= 20
 template <typename RT>
 __device__ void map_couple_tile(int i, unsigned char* smem, const RbcState* __restrict__ st,
                                 RbcCouple* __restrict__ cp, Gather<RT>* __restrict__ gat,
-                                const uint32_t* __restrict__ nodeword, uint32_t* __restrict__ cnt,
+                                const uint32_t* __restrict__ nodeword, const int* __restrict__ segmap,
+                                uint32_t* __restrict__ cnt,
                                 int* __restrict__ ids, RT* __restrict__ vals,
                                 const RT* __restrict__ u, const RT* __restrict__ sig,
                                 const KParams& kp, unsigned* __restrict__ err)
@@ -403,7 +400,8 @@ __device__ void map_couple_tile(int i, unsigned char* smem, const RbcState* __re
                         wrap_coord(Y, kp.ny, kp.per[1]) && wrap_coord(Z, kp.nz, kp.per[2]);
         unsigned char fl = 0;
         RT r = RT(0);
-        if (ok && (nodeword[node_of(kp, X, Y, Z)] & NW_FLUID)) {
+        const int kst = ok ? storage_of(segmap, kp, X, Y, Z) : -1;
+        if (kst >= 0 && (nodeword[kst] & NW_FLUID)) {
             fl = 2;
             double y[3];
             const double d0 = min_img((double)X - s.R[0], (double)kp.nx, kp.per[0]);
@@ -470,7 +468,7 @@ __device__ void map_couple_tile(int i, unsigned char* smem, const RbcState* __re
         wrap_coord(X, kp.nx, kp.per[0]);
         wrap_coord(Y, kp.ny, kp.per[1]);
         wrap_coord(Z, kp.nz, kp.per[2]);
-        const unsigned n = node_of(kp, X, Y, Z);
+        const unsigned n = (unsigned)storage_of(segmap, kp, X, Y, Z);   // covered nodes are fluid
         const RT r = raw[t];
         const RT gx = RT(0.5) * ((xp ? raw[t + 1] : RT(0)) - (xm ? raw[t - 1] : RT(0)));
         const RT gy = RT(0.5) * ((yp ? raw[t + sx] : RT(0)) - (ym ? raw[t - sx] : RT(0)));
@@ -542,7 +540,9 @@ template <typename RT>
 __global__ __launch_bounds__(MC_THREADS) void k_map_couple_tile(const RbcState* __restrict__ st,
                                                                 RbcCouple* __restrict__ cp,
                                                                 Gather<RT>* __restrict__ gat,
-                                                                const uint32_t* __restrict__ nodeword, uint32_t* __restrict__ cnt,
+                                                                const uint32_t* __restrict__ nodeword,
+                                                                const int* __restrict__ segmap,
+                                                                uint32_t* __restrict__ cnt,
                                                                 int* __restrict__ ids,
                                                                 RT* __restrict__ vals,
                                                                 const int* __restrict__ ovf,
@@ -554,7 +554,7 @@ __global__ __launch_bounds__(MC_THREADS) void k_map_couple_tile(const RbcState* 
     extern __shared__ unsigned char smem[];
     const int n = ovf[0];
     for (int b = blockIdx.x; b < n; b += gridDim.x)
-        map_couple_tile<RT>(ovf[1 + b], smem, st, cp, gat, nodeword, cnt, ids, vals, u, sig, kp, err);
+        map_couple_tile<RT>(ovf[1 + b], smem, st, cp, gat, nodeword, segmap, cnt, ids, vals, u, sig, kp, err);
 }
 
 // ---- S3 + S4, one wavefront per cell on the row-compressed support tile -----------------------
@@ -574,7 +574,8 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
                                                 const RbcState* __restrict__ st,
                                                 RbcCouple* __restrict__ cp,
                                                 Gather<RT>* __restrict__ gat,
-                                                const uint32_t* __restrict__ nodeword, uint32_t* __restrict__ cnt,
+                                                const uint32_t* __restrict__ nodeword,
+                                                const int* __restrict__ segmap, uint32_t* __restrict__ cnt,
                                                 int* __restrict__ ids, RT* __restrict__ vals,
                                                 const int* __restrict__ order,
                                                 const RT* __restrict__ u,
@@ -713,7 +714,10 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
                     const int yz = rowof[c];
                     const int ty = yz & 255, tz = yz >> 8, r = ty + tz * sy, tx = clo[r] + (c - off[r]);
                     int X = T.lo[0] + tx, Y = T.lo[1] + ty, Z = T.lo[2] + tz;
-                    if (wrap3(inner, X, Y, Z)) wg[g] = nodeword[node_of(kp, X, Y, Z)];
+                    if (wrap3(inner, X, Y, Z)) {
+                        const int kst = storage_of(segmap, kp, X, Y, Z);
+                        wg[g] = kst >= 0 ? nodeword[kst] : 0u;
+                    }
                     Xg[g] = X;
                     Yg[g] = Y;
                     Zg[g] = Z;
@@ -787,7 +791,7 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
             const bool in = v >= RT(0);
             int X = T.lo[0] + tx, Y = T.lo[1] + ty, Z = T.lo[2] + tz;
             wrap3(inner, X, Y, Z);
-            const unsigned n = node_of(kp, X, Y, Z);
+            const unsigned n = (unsigned)storage_of(segmap, kp, X, Y, Z);   // covered nodes are fluid
             const RT z0 = RT(0);
             const RT rr = in ? v : z0;
             const RT gx = RT(0.5) * (max(vxp, z0) - max(vxm, z0));
@@ -853,7 +857,8 @@ template <typename RT>
 __global__ __launch_bounds__(64) void k_map_couple(const RbcState* __restrict__ st,
                                                    RbcCouple* __restrict__ cp,
                                                    Gather<RT>* __restrict__ gat,
-                                                   const uint32_t* __restrict__ nodeword, uint32_t* __restrict__ cnt,
+                                                   const uint32_t* __restrict__ nodeword,
+                                                   const int* __restrict__ segmap, uint32_t* __restrict__ cnt,
                                                    int* __restrict__ ids, RT* __restrict__ vals,
                                                    const int* __restrict__ order,
                                                    const RT* __restrict__ u,
@@ -864,7 +869,7 @@ __global__ __launch_bounds__(64) void k_map_couple(const RbcState* __restrict__ 
     extern __shared__ unsigned char smem[];
     const int k = xcd_chunk_index(1);
     if (k < kp.nrbc)
-        map_couple_cell<RT>(k, smem, st, cp, gat, nodeword, cnt, ids, vals, order, u, sig, kp, err, ovf);
+        map_couple_cell<RT>(k, smem, st, cp, gat, nodeword, segmap, cnt, ids, vals, order, u, sig, kp, err, ovf);
 }
 
 // ---- S5: Gay-Berne forces and torques (Sec. II E, Eqs. 24-28; App. B) -----------------------
@@ -1219,7 +1224,8 @@ __global__ __launch_bounds__(64) void kf_map(const FusedArgs fa)
     const SlotDesc& d = *fa.slot[fused_slot(fa, lb)];
     const KParams kp = d.kp;
     if (lb < kp.nrbc)
-        map_couple_cell<RT>(lb, smem, d.b.st, d.b.cp, (Gather<RT>*)d.b.gat, d.b.nodeword, d.b.cnt, d.b.map_ids,
+        map_couple_cell<RT>(lb, smem, d.b.st, d.b.cp, (Gather<RT>*)d.b.gat, d.b.nodeword, d.b.tab.map, d.b.cnt,
+                            d.b.map_ids,
                             (RT*)d.b.map_vals,
                             d.b.cell_ids, (const RT*)d.b.u, (const RT*)d.b.sig, kp, d.b.err, d.b.ovf);
 }
@@ -1233,7 +1239,8 @@ __global__ __launch_bounds__(MC_THREADS) void kf_map_tile(const FusedArgs fa)
     const KParams kp = d.kp;
     const int n = d.b.ovf[0];
     for (int b = lb; b < n; b += FUSED_TILE_BLOCKS)
-        map_couple_tile<RT>(d.b.ovf[1 + b], smem, d.b.st, d.b.cp, (Gather<RT>*)d.b.gat, d.b.nodeword, d.b.cnt,
+        map_couple_tile<RT>(d.b.ovf[1 + b], smem, d.b.st, d.b.cp, (Gather<RT>*)d.b.gat, d.b.nodeword, d.b.tab.map,
+                            d.b.cnt,
                             d.b.map_ids,
                             (RT*)d.b.map_vals, (const RT*)d.b.u, (const RT*)d.b.sig, kp, d.b.err);
 }
@@ -1326,12 +1333,14 @@ void launch_map_couple(const CellBuffers& b, const KParams& kp, hipStream_t st)
 {
     hipLaunchKernelGGL((k_map_couple<RT>), dim3(grid8(kp.nrbc, 1)), dim3(64),
                        map_couple_lds(kp.tile_max, kp.cand_cap, (int)sizeof(RT)), st, b.st, b.cp,
-                       (Gather<RT>*)b.gat, b.nodeword, b.cnt, b.map_ids, (RT*)b.map_vals, b.cell_ids, (const RT*)b.u,
+                       (Gather<RT>*)b.gat, b.nodeword, b.tab.map, b.cnt, b.map_ids, (RT*)b.map_vals, b.cell_ids,
+                       (const RT*)b.u,
                        (const RT*)b.sig, kp, b.err, b.ovf);
     // the overflow list is short (normally empty): a small grid loops over it
     hipLaunchKernelGGL((k_map_couple_tile<RT>), dim3(64), dim3(MC_THREADS),
                        map_couple_tile_lds(kp.tile_max, (int)sizeof(RT)), st, b.st, b.cp,
-                       (Gather<RT>*)b.gat, b.nodeword, b.cnt, b.map_ids, (RT*)b.map_vals, b.ovf, (const RT*)b.u,
+                       (Gather<RT>*)b.gat, b.nodeword, b.tab.map, b.cnt, b.map_ids, (RT*)b.map_vals, b.ovf,
+                       (const RT*)b.u,
                        (const RT*)b.sig, kp, b.err);
 }
 

@@ -56,7 +56,7 @@ class lb_config(ctypes.Structure):
         ("bf16_nearest", ctypes.c_int),
         ("ext_force", ctypes.c_double * 3), ("ext_torque", ctypes.c_double * 3),
         ("wall_u_lo", ctypes.c_double * 3), ("wall_u_hi", ctypes.c_double * 3),
-        ("cand_cap", ctypes.c_int),
+        ("cand_cap", ctypes.c_int), ("layout", ctypes.c_int),
     ]
 
 
@@ -71,7 +71,8 @@ class lb_observables(ctypes.Structure):
                 ("wss_mean", ctypes.c_double), ("wss_max", ctypes.c_double),
                 ("wss_time_mean", ctypes.c_double), ("step", ctypes.c_longlong),
                 ("flags", ctypes.c_uint), ("n_fluid", ctypes.c_longlong),
-                ("n_wall_nodes", ctypes.c_int), ("n_rbc", ctypes.c_int)]
+                ("n_wall_nodes", ctypes.c_int), ("n_rbc", ctypes.c_int),
+                ("compact", ctypes.c_int), ("n_stored", ctypes.c_longlong)]
 
 
 _P = ctypes.c_void_p
@@ -131,7 +132,7 @@ DEFAULTS = dict(periodic=(0, 0, 1), storage="f32", f16_scale=2.0 ** 21, forcing=
                 xi=(4.0, 4.0, 1.5), axes=(4.0, 4.0, 1.5), eps0=1e-3, a_wall=0.5, sigmin_wall=0.5,
                 wall_particles=1, open_z=0, rho_in=1.0, rho_out=1.0, map_cap=12,
                 bf16_nearest=0, ext_force=(0.0, 0.0, 0.0), ext_torque=(0.0, 0.0, 0.0), cand_cap=0,
-                wall_u_lo=(0.0, 0.0, 0.0), wall_u_hi=(0.0, 0.0, 0.0))
+                wall_u_lo=(0.0, 0.0, 0.0), wall_u_hi=(0.0, 0.0, 0.0), layout=0)
 
 
 def make_config(cfg: dict) -> lb_config:
@@ -188,6 +189,8 @@ class Observables:
     n_fluid: int
     n_wall_nodes: int
     n_rbc: int
+    compact: int = 0
+    n_stored: int = 0
 
 
 class Simulation:
@@ -271,7 +274,7 @@ class Simulation:
         self._chk(_lib.lb_observe(self.h, ctypes.byref(o)), "lb_observe")
         return Observables(o.mass, np.array(o.momentum[:]), o.flow_rate, o.eta_app, o.wss_mean,
                            o.wss_max, o.wss_time_mean, o.step, o.flags, o.n_fluid,
-                           o.n_wall_nodes, o.n_rbc)
+                           o.n_wall_nodes, o.n_rbc, o.compact, o.n_stored)
 
     def lb_wall_shear_stress(self, time: bool = False):
         n = ctypes.c_int(0)

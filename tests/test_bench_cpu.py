@@ -24,15 +24,18 @@ def test_traffic_is_used_only_for_the_kernel_source_it_was_measured_on(monkeypat
     assert files, "no committed HBM counter summary"
     for f in files:
         rec = json.load(open(os.path.join(d, f)))
-        wl, st = rec["workload"], rec["storage"]
-        assert f == f"traffic_stream_collide_{wl}_{st}.json"
+        wl, st, lay = rec["workload"], rec["storage"], rec["layout"]
+        assert f == f"traffic_stream_collide_{wl}_{st}_{lay}.json"
         # read + written bytes, and the summary beside it names the same source hash
         assert rec["bytes_per_launch"] == rec["bytes_read"] + rec["bytes_written"]
-        md = open(os.path.join(d, f"stream_collide_{wl}_{st}.md")).read()
+        md = open(os.path.join(d, f"stream_collide_{wl}_{st}_{lay}.md")).read()
         assert f"kernel source hash: {rec['kernel_source_hash']}" in md
         monkeypatch.setattr(bench, "kernel_source_hash", lambda h=rec["kernel_source_hash"]: h)
-        assert bench.measured_traffic(wl, st) == rec["bytes_per_launch"]
+        assert bench.measured_traffic(wl, st, lay) == rec["bytes_per_launch"]
+        other = "compact" if lay == "dense" else "dense"
+        if not os.path.exists(os.path.join(d, f"traffic_stream_collide_{wl}_{st}_{other}.json")):
+            assert bench.measured_traffic(wl, st, other) is None
         monkeypatch.setattr(bench, "kernel_source_hash", lambda: "changed")
-        assert bench.measured_traffic(wl, st) is None
-    assert bench.measured_traffic("no_such_workload", "f32") is None
+        assert bench.measured_traffic(wl, st, lay) is None
+    assert bench.measured_traffic("no_such_workload", "f32", "dense") is None
 

@@ -38,8 +38,8 @@ def test_bifurcation_with_cells_f64_and_f32():
 
     nx, ny, nz = 48, 40, 64
     solid = synth.y_bifurcation(nx, ny, nz, r_parent=10.0, r_daughter=8.0, z_branch=36.0)
-    # 46% of the 64-node row segments hold fluid: the stream-collide and the count clearing
-    # run over the segment list (the tube tests take the dense launch grid)
+    # 46% of the 64-node row segments hold fluid: the automatic choice stores the lattice in
+    # the compact layout (the tube tests take the dense one)
     segs = np.zeros((nz, ny, 64), dtype=bool)
     segs[:, :, :nx] = solid == 0
     assert segs.any(-1).mean() < 0.6
@@ -52,6 +52,7 @@ def test_bifurcation_with_cells_f64_and_f32():
     assert ref.step(40) == 0
     fl = solid.reshape(-1) == 0
     sim = lbrbc.Simulation(dict(cfg, storage="f64"), solid, R=R, Q=pl.Q)
+    assert sim.lb_observe().compact == 1
     sim.lb_step(40)
     d = sim.lb_get_fields()
     assert rel(d["u"][fl], ref.u()[fl]) < 1e-10
