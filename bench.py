@@ -505,19 +505,28 @@ def tank_treading(args):
     out = {}
     for alpha in alphas:
         cfg, solid, R, Q = shear_cell_config(alpha)
+        cfg["inertia"] = (args.tt_inertia,) * 3
         sim = lbrbc.Simulation(cfg, solid, R=R, Q=Q)
         t0 = time.perf_counter()
-        sim.lb_step(warm)
         psi, ts, th, om = [], [], [], []
-        for k in range(steps // every):
-            sim.lb_step(every)
-            Qc = sim.rbc_get_state()[1][0].reshape(3, 3)
-            g = Qc[:, 2]
-            psi.append(float(np.arctan2(-g[0], g[1])))
-            cp = sim.rbc_get_coupling()[0]
-            ts.append(float(cp[9]))
-            th.append(float(cp[15]))
-            om.append(float(cp[6]))
+        try:
+            sim.lb_step(warm)
+            for k in range(steps // every):
+                sim.lb_step(every)
+                Qc = sim.rbc_get_state()[1][0].reshape(3, 3)
+                g = Qc[:, 2]
+                psi.append(float(np.arctan2(-g[0], g[1])))
+                cp = sim.rbc_get_coupling()[0]
+                ts.append(float(cp[9]))
+                th.append(float(cp[15]))
+                om.append(float(cp[6]))
+        except lbrbc.LbError as e:
+            # the flow itself went unstable (the torques' back-reaction on the plasma)
+            out[str(alpha)] = {"regime": "unstable", "error": str(e), "samples_before": len(psi)}
+            print(f"[tank-treading] alpha={alpha}: unstable after {len(psi)} samples", file=sys.stderr,
+                  flush=True)
+            del sim
+            continue
         torch.cuda.synchronize()
         ps = np.degrees(np.unwrap(np.array(psi)))
         turned = float(ps.max() - ps.min())
@@ -546,7 +555,7 @@ def tank_treading(args):
                                 f"+/-{cfg['wall_u_hi'][0]} along x (shear rate "
                                 f"{2 * cfg['wall_u_hi'][0] / (cfg['ny'] - 2):.2e}), T0=1, gammaT=gammaR=0.1, "
                                 f"one cell (4, 4, 1.5) at the centre, FP64; {warm} warm-up + {steps} steps"),
-                   "alpha_scale": args.tt_alpha_scale},
+                   "alpha_scale": args.tt_alpha_scale, "inertia": args.tt_inertia},
         "paper_printed": {"transition_alpha": 0.063, "fixed_angle_deg_lees_edwards": 40,
                           "fixed_angle_deg_bounded_slab": "20-35"},
         "results": out,
@@ -590,6 +599,8 @@ def main():
                     help="single cell in a shear cell: orientation against alpha")
     ap.add_argument("--tt-warmup", type=int, default=20000)
     ap.add_argument("--tt-steps", type=int, default=40000)
+    ap.add_argument("--tt-inertia", type=float, default=1000.0,
+                    help="principal moments of inertia of the cell (the paper's 1000 by default)")
     ap.add_argument("--tt-alpha-scale", type=float, default=1.0,
                     help="multiply the paper's alpha values (the balance of the elongational torque "
                          "against the rotational friction)")

@@ -156,14 +156,18 @@ int candidate_capacity_sampled(const double* xi, int tm)
             lo_r[r] = sz[0];
             hi_r[r] = -1;
             if (xa <= xb) {
-                lo_r[r] = std::max(0, (int)std::floor(X0 + xa) - 1);
-                hi_r[r] = std::min(sz[0] - 1, (int)std::ceil(X0 + xb) + 1);
+                lo_r[r] = std::max(0, (int)std::floor(X0 + xa - 1e-7) + 1);
+                hi_r[r] = std::min(sz[0] - 1, (int)std::ceil(X0 + xb + 1e-7) - 1);
             }
         }
         int tot = 0;
         for (int r = 0; r < rows; ++r) {
             const int ty = r % sz[1], tz = r / sz[1];
-            int a = lo_r[r] - 1, b = hi_r[r] + 1;
+            int a = sz[0], b = -1;
+            if (lo_r[r] <= hi_r[r]) {
+                a = lo_r[r] - 1;
+                b = hi_r[r] + 1;
+            }
             if (ty > 0) { a = std::min(a, lo_r[r - 1]); b = std::max(b, hi_r[r - 1]); }
             if (ty + 1 < sz[1]) { a = std::min(a, lo_r[r + 1]); b = std::max(b, hi_r[r + 1]); }
             if (tz > 0) { a = std::min(a, lo_r[r - sz[1]]); b = std::max(b, hi_r[r - sz[1]]); }

@@ -289,6 +289,57 @@ __device__ __forceinline__ bool wrap_coord(int& X, int L, int per)
     return per || !(lo || hi);
 }
 
+// Nodes of tile row (ty, tz) that may lie inside the support. The body coordinates are affine
+// in x along the row, y_a = Q_xa d_x + b_a, and |y_a| < xi_a cuts an open interval (xa, xb) of
+// d_x. Every node that the exact FP64 test can find inside lies strictly within
+// (xa - ROW_EPS, xb + ROW_EPS): ROW_EPS is far above the rounding of either computation (a few
+// ulps of coordinates below 2^11). The range is [lo, hi] in tile coordinates, empty when lo > hi.
+constexpr double ROW_EPS = 1e-7;
+__device__ __forceinline__ void support_row(const RbcState& s, const KParams& kp, const Tile& T, int ty, int tz,
+                                            int& lo, int& hi)
+{
+    const double dy = (double)(T.lo[1] + ty) - s.R[1], dz = (double)(T.lo[2] + tz) - s.R[2];
+    double xa = -1e30, xb = 1e30;
+    for (int a = 0; a < 3; ++a) {
+        const double qa = s.Q[a], b = s.Q[3 + a] * dy + s.Q[6 + a] * dz;
+        if (fabs(qa) > 1e-12) {
+            double u0 = (-kp.xi[a] - b) / qa, u1 = (kp.xi[a] - b) / qa;
+            if (u0 > u1) { const double t_ = u0; u0 = u1; u1 = t_; }
+            xa = fmax(xa, u0);
+            xb = fmin(xb, u1);
+        } else if (fabs(b) >= kp.xi[a] + 1e-9) {
+            xa = 1e30;
+        }
+    }
+    lo = T.sz[0];
+    hi = -1;
+    if (xa <= xb) {
+        const double X0 = s.R[0] - (double)T.lo[0];
+        lo = max(0, (int)floor(X0 + xa - ROW_EPS) + 1);
+        hi = min(T.sz[0] - 1, (int)ceil(X0 + xb + ROW_EPS) - 1);
+    }
+}
+
+// Covered x-range of tile row r from the support ranges of the rows: a node is covered when it
+// or one of its six axis neighbours is inside, so the row's own range widened by one node and
+// the ranges of its four neighbouring rows. Empty rows (lo > hi) add nothing.
+__device__ __forceinline__ void covered_row(const short* rlo, const short* rhi, int r, int sx, int sy, int sz,
+                                            int& lo, int& hi)
+{
+    const int ty = r % sy, tz = r / sy;
+    lo = sx;
+    hi = -1;
+    if (rlo[r] <= rhi[r]) {
+        lo = rlo[r] - 1;
+        hi = rhi[r] + 1;
+    }
+    if (ty > 0) { lo = min(lo, (int)rlo[r - 1]); hi = max(hi, (int)rhi[r - 1]); }
+    if (ty + 1 < sy) { lo = min(lo, (int)rlo[r + 1]); hi = max(hi, (int)rhi[r + 1]); }
+    if (tz > 0) { lo = min(lo, (int)rlo[r - sy]); hi = max(hi, (int)rhi[r - sy]); }
+    if (tz + 1 < sz) { lo = min(lo, (int)rlo[r + sy]); hi = max(hi, (int)rhi[r + sy]); }
+    lo = max(lo, 0);
+    hi = min(hi, sx - 1);
+}
 
 // block index -> position in the spatially sorted cell order, so that each XCD (blocks are
 // dealt to the eight XCDs round-robin) works on one contiguous, spatially compact chunk and
@@ -347,46 +398,20 @@ __device__ void map_couple_tile(int i, unsigned char* smem, const RbcState* __re
     }
     const unsigned sx = T.sz[0], sy = T.sz[1], sz = T.sz[2], sxy = sx * sy, total = sxy * sz;
     const unsigned rows = sy * sz;
-    // Conservative x-range of the support on each tile row (y, z): the body coordinates are
-    // affine in x, y_a = Q_xa d_x + b_a, and |y_a| < xi_a cuts an interval; the exact test
-    // below decides each node, the range (widened by one node) only skips nodes that are
-    // certainly outside.
+    // support range of each tile row (the exact test below decides each node; the ranges only
+    // skip nodes that are certainly outside), then the covered range of each row
     for (unsigned r = tid; r < rows; r += MC_THREADS) {
-        const int ty = (int)(r % sy), tz = (int)(r / sy);
-        const double dy = (double)(T.lo[1] + ty) - s.R[1], dz = (double)(T.lo[2] + tz) - s.R[2];
-        double xa = -1e30, xb = 1e30;
-        for (int a = 0; a < 3; ++a) {
-            const double qa = s.Q[a], b = s.Q[3 + a] * dy + s.Q[6 + a] * dz;
-            if (fabs(qa) > 1e-12) {
-                double u0 = (-kp.xi[a] - b) / qa, u1 = (kp.xi[a] - b) / qa;
-                if (u0 > u1) { const double t_ = u0; u0 = u1; u1 = t_; }
-                xa = fmax(xa, u0);
-                xb = fmin(xb, u1);
-            } else if (fabs(b) >= kp.xi[a] + 1e-9) {
-                xa = 1e30;
-            }
-        }
-        int lo = (int)sx, hi = -1;
-        if (xa <= xb) {
-            const double X0 = s.R[0] - (double)T.lo[0];
-            lo = max(0, (int)floor(X0 + xa) - 1);
-            hi = min((int)sx - 1, (int)ceil(X0 + xb) + 1);
-        }
+        int lo, hi;
+        support_row(s, kp, T, (int)(r % sy), (int)(r / sy), lo, hi);
         rlo[r] = (short)lo;
         rhi[r] = (short)hi;
     }
     __syncthreads();
-    // covered range of a row: its own support range widened by one and the ranges of the
-    // four neighbouring rows (a node is covered when it or an axis neighbour is inside)
     for (unsigned r = tid; r < rows; r += MC_THREADS) {
-        const int ty = (int)(r % sy), tz = (int)(r / sy);
-        int lo = rlo[r] - 1, hi = rhi[r] + 1;
-        if (ty > 0) { lo = min(lo, (int)rlo[r - 1]); hi = max(hi, (int)rhi[r - 1]); }
-        if (ty + 1 < (int)sy) { lo = min(lo, (int)rlo[r + 1]); hi = max(hi, (int)rhi[r + 1]); }
-        if (tz > 0) { lo = min(lo, (int)rlo[r - sy]); hi = max(hi, (int)rhi[r - sy]); }
-        if (tz + 1 < (int)sz) { lo = min(lo, (int)rlo[r + sy]); hi = max(hi, (int)rhi[r + sy]); }
-        clo[r] = (short)max(lo, 0);
-        chi[r] = (short)min(hi, (int)sx - 1);
+        int lo, hi;
+        covered_row(rlo, rhi, (int)r, (int)sx, (int)sy, (int)sz, lo, hi);
+        clo[r] = (short)lo;
+        chi[r] = (short)hi;
     }
     __syncthreads();
     const RT s0 = RT(2.0 / kp.xi[0]), s1 = RT(2.0 / kp.xi[1]), s2 = RT(2.0 / kp.xi[2]);
@@ -601,44 +626,18 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
     }
     const int sx = T.sz[0], sy = T.sz[1], sz = T.sz[2];
     const int rows = sy * sz;
-    // support x-range of each row, widened by one node (see map_couple_tile)
-    const double X0 = s.R[0] - (double)T.lo[0];
-    double iq[3];
-    for (int a = 0; a < 3; ++a) iq[a] = fabs(s.Q[a]) > 1e-12 ? 1.0 / s.Q[a] : 0.0;
+    // support range of each row (as in map_couple_tile), then the covered range of each row
+    // and its length (kept in off[] until the scan)
     for (int r = lane; r < rows; r += 64) {
-        const int ty = r % sy, tz = r / sy;
-        const double dy = (double)(T.lo[1] + ty) - s.R[1], dz = (double)(T.lo[2] + tz) - s.R[2];
-        double xa = -1e30, xb = 1e30;
-        for (int a = 0; a < 3; ++a) {
-            const double qa = s.Q[a], b = s.Q[3 + a] * dy + s.Q[6 + a] * dz;
-            if (fabs(qa) > 1e-12) {
-                double u0 = (-kp.xi[a] - b) * iq[a], u1 = (kp.xi[a] - b) * iq[a];
-                if (u0 > u1) { const double t_ = u0; u0 = u1; u1 = t_; }
-                xa = fmax(xa, u0);
-                xb = fmin(xb, u1);
-            } else if (fabs(b) >= kp.xi[a] + 1e-9) {
-                xa = 1e30;
-            }
-        }
-        int lo = sx, hi = -1;
-        if (xa <= xb) {
-            lo = max(0, (int)floor(X0 + xa) - 1);
-            hi = min(sx - 1, (int)ceil(X0 + xb) + 1);
-        }
+        int lo, hi;
+        support_row(s, kp, T, r % sy, r / sy, lo, hi);
         tlo[r] = (short)lo;
         thi[r] = (short)hi;
     }
     __syncthreads();
-    // covered range of each row and its length (kept in off[] until the scan)
     for (int r = lane; r < rows; r += 64) {
-        const int ty = r % sy, tz = r / sy;
-        int lo = tlo[r] - 1, hi = thi[r] + 1;
-        if (ty > 0) { lo = min(lo, (int)tlo[r - 1]); hi = max(hi, (int)thi[r - 1]); }
-        if (ty + 1 < sy) { lo = min(lo, (int)tlo[r + 1]); hi = max(hi, (int)thi[r + 1]); }
-        if (tz > 0) { lo = min(lo, (int)tlo[r - sy]); hi = max(hi, (int)thi[r - sy]); }
-        if (tz + 1 < sz) { lo = min(lo, (int)tlo[r + sy]); hi = max(hi, (int)thi[r + sy]); }
-        lo = max(lo, 0);
-        hi = min(hi, sx - 1);
+        int lo, hi;
+        covered_row(tlo, thi, r, sx, sy, sz, lo, hi);
         clo[r] = (short)lo;
         off[r] = (short)max(0, hi - lo + 1);
     }
