@@ -55,6 +55,29 @@ def measured_traffic(workload: str, storage: str, layout: str):
     return d.get("bytes_per_launch")
 
 
+# The map pass's algorithmic bytes per cell (FP32 / FP64 reals): for each covered node (391.6
+# per cell on average for the (4, 4, 1.5) support over sampled orientations and offsets) its
+# node word (4 B), u (3 reals), its coverage count read and written (8 B), the slot id (4 B) and
+# the entry (raw, grad raw: 4 reals); for each inside node (191.9 per cell) sigma (6 reals).
+MAP_COVERED_PER_CELL, MAP_INSIDE_PER_CELL = 391.6, 191.9
+
+
+def map_bytes_per_cell(storage: str) -> float:
+    r = 8 if storage == "f64" else 4
+    return MAP_COVERED_PER_CELL * (4 + 3 * r + 8 + 4 + 4 * r) + MAP_INSIDE_PER_CELL * 6 * r
+
+
+def map_pass_record(storage: str, n_cells: int, map_ms: float):
+    """The map pass (one launch per step): its mean duration from HIP events and its
+    algorithmic bytes (map_bytes_per_cell x cells) over that duration."""
+    if n_cells == 0 or map_ms <= 0:
+        return None
+    b = map_bytes_per_cell(storage) * n_cells
+    return {"ms_per_launch": round(map_ms, 5), "algorithmic_bytes_per_cell": round(map_bytes_per_cell(storage), 1),
+            "hbm_gbs_algorithmic": round(b / (map_ms * 1e-3) / 1e9, 1),
+            "frac": round(b / (map_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+
+
 def workload(name: str, storage: str):
     from paper_1107_4889_amd import synth
 
@@ -604,6 +627,9 @@ def main():
     ap.add_argument("--tt-alpha-scale", type=float, default=1.0,
                     help="multiply the paper's alpha values (the balance of the elongational torque "
                          "against the rotational friction)")
+    ap.add_argument("--cpu-baseline-only", action="store_true",
+                    help="time only the oracle on the host, on the workload itself (--cpu-steps steps)")
+    ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--layout", default="auto", choices=["auto", "dense", "compact"],
                     help="storage layout of the per-node planes (auto: compact for sparse geometries)")
     ap.add_argument("--precision", action="store_true",
@@ -646,6 +672,11 @@ def main():
     from paper_1107_4889_amd import lbrbc
 
     cfg, solid, pl, desc = workload(args.workload, args.storage)
+    if args.cpu_baseline_only:
+        n_fluid = int((solid == 0).sum())
+        rec = cpu_baseline(cfg, solid, pl, n_fluid, hematocrit=None, steps=args.cpu_steps)
+        print(json.dumps({"workload": desc, "cpu_baseline": rec}), flush=True)
+        return
     cfg["layout"] = LAYOUTS[args.layout]
     print(f"[bench] {desc}", file=sys.stderr, flush=True)
     sim = lbrbc.Simulation(cfg, solid, R=pl.R, Q=pl.Q)
@@ -663,6 +694,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     sc_ms, step_ev_ms = sim.lb_kernel_time()
+    map_ms = sim.lb_map_time()
     sim.lb_set_timing(False)
     sim.lb_sync()
     obs = sim.lb_observe()
@@ -705,6 +737,7 @@ def main():
             "algorithmic_bytes_per_lu": 2 * 19 * STORAGE_BYTES[args.storage],
             "hbm_gbs_algorithmic": round(achieved, 1),
         },
+        "map_pass": map_pass_record(args.storage, len(pl.R), map_ms),
         "roofline": {
             "bound": "hbm",
             "achieved": round(achieved, 1),

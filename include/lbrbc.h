@@ -274,6 +274,9 @@ void lb_destroy(lb_ctx ctx);
  * switched on, 0 if none. */
 lb_status lb_set_timing(lb_ctx ctx, int on);
 lb_status lb_kernel_time(lb_ctx ctx, double* sc_ms, double* step_ms);
+/* The same events also bracket the map pass of every step (the one-wavefront pass and the
+ * full-tile pass behind it): its average duration (ms) since timing was switched on, 0 if none. */
+lb_status lb_map_time(lb_ctx ctx, double* map_ms);
 
 #ifdef __cplusplus
 }

@@ -335,15 +335,11 @@ __device__ __forceinline__ void stream_collide_node(const PL& pl, const uint32_t
     const RT d3 = drho * RT(1.0 / 3.0);
     const RT z0 = RT(0);
     if (put_u) {
-        __builtin_nontemporal_store(live ? ux : z0, at32(pl.vel(0), n));
-        __builtin_nontemporal_store(live ? uy : z0, at32(pl.vel(1), n));
-        __builtin_nontemporal_store(live ? uz : z0, at32(pl.vel(2), n));
-        __builtin_nontemporal_store(live ? ks * (pxx - d3 - rho * ux * ux) : z0, at32(pl.str(0), n));
-        __builtin_nontemporal_store(live ? ks * (pyy - d3 - rho * uy * uy) : z0, at32(pl.str(1), n));
-        __builtin_nontemporal_store(live ? ks * (pzz - d3 - rho * uz * uz) : z0, at32(pl.str(2), n));
-        __builtin_nontemporal_store(live ? ks * (pxy - rho * ux * uy) : z0, at32(pl.str(3), n));
-        __builtin_nontemporal_store(live ? ks * (pxz - rho * ux * uz) : z0, at32(pl.str(4), n));
-        __builtin_nontemporal_store(live ? ks * (pyz - rho * uy * uz) : z0, at32(pl.str(5), n));
+        store_vel_nt(vel_of(pl.u, n), live ? ux : z0, live ? uy : z0, live ? uz : z0);
+        store_str_nt(str_of(pl.sig, n), live ? ks * (pxx - d3 - rho * ux * ux) : z0,
+                     live ? ks * (pyy - d3 - rho * uy * uy) : z0, live ? ks * (pzz - d3 - rho * uz * uz) : z0,
+                     live ? ks * (pxy - rho * ux * uy) : z0, live ? ks * (pxz - rho * ux * uz) : z0,
+                     live ? ks * (pyz - rho * uy * uz) : z0);
     }
     // (the boundary kernel still reads, and then clears, the counts at the open planes and
     // at the nodes it extrapolates from)
@@ -434,14 +430,14 @@ __global__ __launch_bounds__(256) void k_open_bc(
     spread_at<RT>(n, cn, mp, gat, kp, gb, thb);
     const RT om = RT(1) / ((RT)kp.tau0 + (RT)kp.delta * thb);
 #pragma unroll
-    for (int a = 0; a < 6; ++a) sout[(long long)a * kp.ld + n] = RT(0);
+    for (int a = 0; a < 6; ++a) str_of(sout, n)[a] = RT(0);
     // with clear_counts this thread is the only reader of the counts at n and ni (the inner
     // node of one plane node): it clears them for the next step's map pass once read
     if (clear_counts && cn) mp.cnt[n] = 0u;
     if (!(wi & NW_FLUID)) {
         for (int p = 0; p < 19; ++p)
             store_pop<ST, RT>(fout + (size_t)p * (size_t)kp.ld, (unsigned)n, RT(w_(p)) * (rb - RT(1)), kp, (unsigned)p);
-        for (int a = 0; a < 3; ++a) uout[(long long)a * kp.ld + n] = RT(0);
+        for (int a = 0; a < 3; ++a) vel_of(uout, n)[a] = RT(0);
         return;
     }
     RT f[19];
@@ -475,9 +471,10 @@ __global__ __launch_bounds__(256) void k_open_bc(
         const RT fei = feq_shift<RT>(p, drho, rho, ux, uy, uz, usq);
         store_pop<ST, RT>(fout + (size_t)p * (size_t)kp.ld, (unsigned)n, feb + (RT(1) - om) * (f[p] - fei), kp, (unsigned)p);
     }
-    uout[n] = ux;
-    uout[kp.ld + n] = uy;
-    uout[2 * kp.ld + n] = uz;
+    RT* uo = vel_of(uout, n);
+    uo[0] = ux;
+    uo[1] = uy;
+    uo[2] = uz;
 }
 
 // ---- spread-field probe: g and T per fluid node (same device function as the step) -------
@@ -536,7 +533,7 @@ __global__ __launch_bounds__(256) void k_observe_partials(const ST* __restrict__
         acc[1] += px;
         acc[2] += py;
         acc[3] += pz;
-        acc[4] += (double)u[2 * kp.ld + n];
+        acc[4] += (double)vel_of(u, (unsigned)n)[2];
         acc[5] += 1.0;
     }
     __shared__ double red[6][256];
@@ -574,7 +571,7 @@ __global__ __launch_bounds__(256) void k_wss(const RT* __restrict__ sig,
     if (k >= nwn) return;
     const long long n = wn_node[k];
     double s[6];
-    for (int a = 0; a < 6; ++a) s[a] = (double)sig[(long long)a * kp.ld + n];
+    for (int a = 0; a < 6; ++a) s[a] = (double)str_of(sig, (unsigned)n)[a];
     const double n0 = wn_nrm[3 * k], n1 = wn_nrm[3 * k + 1], n2 = wn_nrm[3 * k + 2];
     const double t0 = s[0] * n0 + s[3] * n1 + s[4] * n2;
     const double t1 = s[3] * n0 + s[1] * n1 + s[5] * n2;
@@ -656,8 +653,8 @@ void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword
         pl.in[p] = (const ST*)fin + p * ld;
         pl.out[p] = (ST*)fout + p * ld;
     }
-    for (int a = 0; a < 3; ++a) pl.u[a] = (RT*)u + a * ld;
-    for (int a = 0; a < 6; ++a) pl.sig[a] = (RT*)sig + a * ld;
+    pl.u = (RT*)u;
+    pl.sig = (RT*)sig;
     const auto mp = map_planes<RT>(ids, vals, cnt, kp);
     const Gather<RT>* g = (const Gather<RT>*)gat;
     if (kp.compact) {

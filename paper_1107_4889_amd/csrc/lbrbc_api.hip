@@ -582,7 +582,7 @@ struct lb_ctx_s {
     // timing of the stream-collide kernel and of whole steps
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> sc_pairs;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> sc_pairs, map_pairs;
     hipEvent_t step_t0 = nullptr, step_t1 = nullptr;
     int timed_steps = 0;
     bool step_t0_set = false;
@@ -768,7 +768,19 @@ void enqueue_step(lb_ctx c, bool last)
             }
             if (c->dirty[p])
                 launch_clear_counts(b.cnt, kp.N, b.ovf, s);
+            hipEvent_t m0 = nullptr, m1 = nullptr;
+            if (c->timing && (int)c->map_pairs.size() < MAX_TIMED && c->ev_pool.size() >= 4) {
+                m0 = c->ev_pool.back();
+                c->ev_pool.pop_back();
+                m1 = c->ev_pool.back();
+                c->ev_pool.pop_back();
+                (void)hipEventRecord(m0, s);
+            }
             launch_map_couple<RT>(b, kp, s);
+            if (m0) {
+                (void)hipEventRecord(m1, s);
+                c->map_pairs.emplace_back(m0, m1);
+            }
             c->map_parity = p;
             if (!forked) {
                 launch_gay_berne(c->cb, kp, s);
@@ -1071,8 +1083,10 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
     if (e != hipSuccess) return init_fail(c, LB_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return init_fail(c, LB_EHIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+    // (on the context's stream: a copy on the null stream would wait for other streams)
     unsigned err = 0;
-    e = hipMemcpy(&err, b.err, 4, hipMemcpyDeviceToHost);
+    e = hipMemcpyAsync(&err, b.err, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return init_fail(c, LB_EHIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
     if (err & ERR_OVERLAP) return init_fail(c, LB_EOVERLAP, "Gay-Berne pair at rho <= 0 in the initial state");
     if (n_rbc >= SIDE_STREAM_MIN_CELLS) {
@@ -1178,15 +1192,27 @@ lb_status lb_batch_capture(lb_ctx* ctxs, int n, int nsteps, lb_graph* out)
         // did in between (e.g. rbc_couple): counts left clean are read and left as they are
         c->dirty[0] = true;
     }
+    // an error left by earlier work of this thread would read as a launch error of the capture
+    const hipError_t pending = hipGetLastError();
+    if (pending != hipSuccess) {
+        for (int i = 0; i < n; ++i) ctxs[i]->dirty[0] = sv[i].dirty0;
+        return fail(ctxs[0], LB_EHIP, std::string("lb_batch_capture: error pending before the capture: ") +
+                                          hipGetErrorString(pending));
+    }
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
         for (int i = 0; i < n; ++i) ctxs[i]->dirty[0] = sv[i].dirty0;
         return fail(ctxs[0], LB_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
     }
-    for (int k = 0; k < nsteps; ++k)
+    // the first launch error (launch checks are synchronous, also under capture)
+    hipError_t launch_err = hipSuccess;
+    for (int k = 0; k < nsteps && launch_err == hipSuccess; ++k) {
         for (int g = 0; g < n; g += FUSE_MAX) enqueue_fused_step(ctxs + g, std::min(FUSE_MAX, n - g));
+        launch_err = hipGetLastError();
+    }
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(s, &graph);
+    if (launch_err != hipSuccess && e == hipSuccess) e = launch_err;
     // nothing ran: the host state is what it was (an even step count returns the buffers)
     for (int i = 0; i < n; ++i) {
         lb_ctx c = ctxs[i];
@@ -1196,8 +1222,13 @@ lb_status lb_batch_capture(lb_ctx* ctxs, int n, int nsteps, lb_graph* out)
         c->dirty[0] = sv[i].dirty0;
         c->map_parity = sv[i].map_parity;
     }
-    if (e != hipSuccess || !graph)
-        return fail(ctxs[0], LB_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    if (e != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(ctxs[0], LB_EHIP,
+                    std::string("hipStreamEndCapture: ") + hipGetErrorString(e) +
+                        (launch_err != hipSuccess ? std::string("; first launch error: ") + hipGetErrorString(launch_err)
+                                                  : std::string()));
+    }
     hipGraphExec_t exec = nullptr;
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
@@ -1457,18 +1488,21 @@ lb_status lb_get_fields(lb_ctx c, double* f, double* u, double* sigma, double* g
             for (size_t n = 0; n < N; ++n)
                 f[p * N + n] = w_(p) + (ks[n] < 0 ? 0.0 : load_stored(h.data(), p * ld + ks[n], S, inv));
     }
-    auto planes = [&](size_t off, int k, double* out) -> lb_status {
+    // inter = true: node-interleaved (u, sigma: element k * comps + a), else planes a * ld + k
+    auto planes = [&](size_t off, int k, double* out, bool inter) -> lb_status {
         std::vector<char> h(k * ld * rs);
         HIPCHK(c, hipMemcpy(h.data(), c->base + off, h.size(), hipMemcpyDeviceToHost));
         for (int a = 0; a < k; ++a)
-            for (size_t n = 0; n < N; ++n) out[n * k + a] = ks[n] < 0 ? 0.0 : load_real(h.data(), a * ld + ks[n], S);
+            for (size_t n = 0; n < N; ++n)
+                out[n * k + a] = ks[n] < 0 ? 0.0
+                                           : load_real(h.data(), inter ? (size_t)ks[n] * k + a : a * ld + ks[n], S);
         return LB_OK;
     };
     lb_status r;
-    if (u && (r = planes(c->lay.u, 3, u)) != LB_OK) return r;
-    if (sigma && (r = planes(c->lay.sig, 6, sigma)) != LB_OK) return r;
-    if (g && (r = planes(c->lay.gdbg, 3, g)) != LB_OK) return r;
-    if (relax && (r = planes(c->lay.tdbg, 1, relax)) != LB_OK) return r;
+    if (u && (r = planes(c->lay.u, 3, u, true)) != LB_OK) return r;
+    if (sigma && (r = planes(c->lay.sig, 6, sigma, true)) != LB_OK) return r;
+    if (g && (r = planes(c->lay.gdbg, 3, g, false)) != LB_OK) return r;
+    if (relax && (r = planes(c->lay.tdbg, 1, relax, false)) != LB_OK) return r;
     return st;
 }
 
@@ -1490,11 +1524,12 @@ lb_status lb_set_fields(lb_ctx c, const double* f, const double* u, const double
                 if (ks[n] >= 0) store_value(h.data(), p * ld + ks[n], S, f[p * N + n] - w_(p), scale);
         HIPCHK(c, hipMemcpy(c->fA, h.data(), h.size(), hipMemcpyHostToDevice));
     }
+    // u and sigma are node-interleaved on the device (element k * comps + a)
     auto planes = [&](size_t off, int k, const double* in) -> lb_status {
         std::vector<char> h(k * ld * rs, 0);
         for (int a = 0; a < k; ++a)
             for (size_t n = 0; n < N; ++n)
-                if (ks[n] >= 0) store_real(h.data(), a * ld + ks[n], S, in[n * k + a]);
+                if (ks[n] >= 0) store_real(h.data(), (size_t)ks[n] * k + a, S, in[n * k + a]);
         HIPCHK(c, hipMemcpy(c->base + off, h.data(), h.size(), hipMemcpyHostToDevice));
         return LB_OK;
     };
@@ -1727,15 +1762,17 @@ lb_status lb_set_timing(lb_ctx c, int on)
 {
     if (!c) return LB_EINVAL;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (auto& pr : c->sc_pairs) {
-        c->ev_pool.push_back(pr.first);
-        c->ev_pool.push_back(pr.second);
+    for (auto* pairs : {&c->sc_pairs, &c->map_pairs}) {
+        for (auto& pr : *pairs) {
+            c->ev_pool.push_back(pr.first);
+            c->ev_pool.push_back(pr.second);
+        }
+        pairs->clear();
     }
-    c->sc_pairs.clear();
     c->timed_steps = 0;
     c->step_t0_set = false;
     if (on && c->ev_pool.empty()) {
-        for (int k = 0; k < 2 * MAX_TIMED; ++k) {
+        for (int k = 0; k < 4 * MAX_TIMED; ++k) {
             hipEvent_t e;
             HIPCHK(c, hipEventCreate(&e));
             c->ev_pool.push_back(e);
@@ -1766,15 +1803,30 @@ lb_status lb_kernel_time(lb_ctx c, double* sc_ms, double* step_ms)
     return LB_OK;
 }
 
+lb_status lb_map_time(lb_ctx c, double* map_ms)
+{
+    if (!c || !map_ms) return LB_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double tot = 0;
+    for (auto& pr : c->map_pairs) {
+        float ms = 0;
+        HIPCHK(c, hipEventElapsedTime(&ms, pr.first, pr.second));
+        tot += ms;
+    }
+    *map_ms = c->map_pairs.empty() ? 0.0 : tot / c->map_pairs.size();
+    return LB_OK;
+}
+
 void lb_destroy(lb_ctx c)
 {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
     release_side(c);
-    for (auto& pr : c->sc_pairs) {
-        (void)hipEventDestroy(pr.first);
-        (void)hipEventDestroy(pr.second);
-    }
+    for (auto* pairs : {&c->sc_pairs, &c->map_pairs})
+        for (auto& pr : *pairs) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->step_t0) (void)hipEventDestroy(c->step_t0);
     if (c->step_t1) (void)hipEventDestroy(c->step_t1);

@@ -240,17 +240,54 @@ struct MapPlanes {
     uint32_t* cnt;
 };
 
+// Velocity and stress are stored node-interleaved, u[3k + a] and sigma[6k + q] (q: xx yy zz xy
+// xz yz): the map pass reads them at the few consecutive covered nodes of each support row, so
+// one node's components share a cache line instead of sitting in 3 and 6 separate planes. The
+// stream-collide writes them for consecutive nodes, which stays contiguous per wavefront.
+template <typename RT>
+__device__ __forceinline__ RT* vel_of(RT* u, unsigned k) { return u + 3 * (size_t)k; }
+template <typename RT>
+__device__ __forceinline__ const RT* vel_of(const RT* u, unsigned k) { return u + 3 * (size_t)k; }
+template <typename RT>
+__device__ __forceinline__ RT* str_of(RT* s, unsigned k) { return s + 6 * (size_t)k; }
+template <typename RT>
+__device__ __forceinline__ const RT* str_of(const RT* s, unsigned k) { return s + 6 * (size_t)k; }
+
+// streaming (non-temporal) stores of one node's u and sigma as a few vector stores
+template <typename RT>
+__device__ __forceinline__ void store_vel_nt(RT* p, RT a, RT b, RT c)
+{
+    if constexpr (sizeof(RT) == 4) {
+        // one 12-byte store (the 3-vector's store size; its 16-byte allocation size is not used)
+        typedef RT V3 __attribute__((ext_vector_type(3), aligned(4)));
+        const V3 v = {a, b, c};
+        __builtin_nontemporal_store(v, reinterpret_cast<V3*>(p));
+    } else {
+        // a 3-vector of doubles is stored as 32 bytes: element stores instead
+        __builtin_nontemporal_store(a, p);
+        __builtin_nontemporal_store(b, p + 1);
+        __builtin_nontemporal_store(c, p + 2);
+    }
+}
+template <typename RT>
+__device__ __forceinline__ void store_str_nt(RT* p, RT s0, RT s1, RT s2, RT s3, RT s4, RT s5)
+{
+    typedef RT V2 __attribute__((ext_vector_type(2)));   // 6k elements: aligned to 2 elements
+    const V2 a = {s0, s1}, b = {s2, s3}, c = {s4, s5};
+    __builtin_nontemporal_store(a, reinterpret_cast<V2*>(p));
+    __builtin_nontemporal_store(b, reinterpret_cast<V2*>(p + 2));
+    __builtin_nontemporal_store(c, reinterpret_cast<V2*>(p + 4));
+}
+
 // per-plane pointers of one stream-collide launch (kernel argument)
 template <typename ST, typename RT>
 struct Planes {
     const ST* in[19];
     ST* out[19];
-    RT* u[3];
-    RT* sig[6];
+    RT* u;
+    RT* sig;
     __device__ const ST* src(int p) const { return in[p]; }
     __device__ ST* dst(int p) const { return out[p]; }
-    __device__ RT* vel(int a) const { return u[a]; }
-    __device__ RT* str(int a) const { return sig[a]; }
 };
 // the same planes from the buffer bases and the plane stride (fused multi-lattice launches)
 template <typename ST, typename RT>
@@ -262,8 +299,6 @@ struct PlanesLd {
     unsigned long long ld;
     __device__ const ST* src(int p) const { return fin + (unsigned long long)p * ld; }
     __device__ ST* dst(int p) const { return fout + (unsigned long long)p * ld; }
-    __device__ RT* vel(int a) const { return u + (unsigned long long)a * ld; }
-    __device__ RT* str(int a) const { return sig + (unsigned long long)a * ld; }
 };
 
 // ---- Peskin four-point kernel at r = 2|y|/xi (the normalised 1-D profile) ----------------

@@ -498,7 +498,8 @@ __device__ void map_couple_tile(int i, unsigned char* smem, const RbcState* __re
         const RT gx = RT(0.5) * ((xp ? raw[t + 1] : RT(0)) - (xm ? raw[t - 1] : RT(0)));
         const RT gy = RT(0.5) * ((yp ? raw[t + sx] : RT(0)) - (ym ? raw[t - sx] : RT(0)));
         const RT gz = RT(0.5) * ((zp ? raw[t + sxy] : RT(0)) - (zm ? raw[t - sxy] : RT(0)));
-        const RT ux = u[n], uy = u[ld + n], uz = u[2 * ld + n];
+        const RT* un = vel_of(u, n);
+        const RT ux = un[0], uy = un[1], uz = un[2];
         const uint32_t old = atomicAdd(cnt + n, 1u);
         const int slot = (int)old;
         const int e = (i << kp.ent_shift) | j;
@@ -525,8 +526,8 @@ __device__ void map_couple_tile(int i, unsigned char* smem, const RbcState* __re
         const RT g2 = hx * hx + hy * hy + hz * hz;
         const RT il = g2 > RT(0) ? fast_rsqrt(g2) : RT(0);
         const RT nx_ = hx * il, ny_ = hy * il, nz_ = hz * il;
-        const RT sxx = sig[n], syy = sig[ld + n], szz = sig[2 * ld + n];
-        const RT sxy_ = sig[3 * ld + n], sxz = sig[4 * ld + n], syz = sig[5 * ld + n];
+        const RT* sn = str_of(sig, n);
+        const RT sxx = sn[0], syy = sn[1], szz = sn[2], sxy_ = sn[3], sxz = sn[4], syz = sn[5];
         const RT t0 = sxx * nx_ + sxy_ * ny_ + sxz * nz_;
         const RT t1 = sxy_ * nx_ + syy * ny_ + syz * nz_;
         const RT t2 = sxz * nx_ + syz * ny_ + szz * nz_;
@@ -615,6 +616,7 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
     short* off = clo + tm * tm;
     RT* val = reinterpret_cast<RT*>(smem + (((size_t)4 * tm * tm + 2 + 15) & ~(size_t)15));
     unsigned short* rowof = reinterpret_cast<unsigned short*>(val + cap);
+    int* kof = reinterpret_cast<int*>(rowof + ((cap + 1) & ~1));   // storage index per candidate
     short* tlo = reinterpret_cast<short*>(val);          // support ranges (before val is used)
     short* thi = tlo + tm * tm;
 
@@ -702,19 +704,21 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
     constexpr int P1_GROUP = 4;
     auto pass1 = [&](auto inner) {
         for (int c0 = lane; c0 < total; c0 += 64 * P1_GROUP) {
-            int Xg[P1_GROUP], Yg[P1_GROUP], Zg[P1_GROUP];
+            int Xg[P1_GROUP], Yg[P1_GROUP], Zg[P1_GROUP], kg[P1_GROUP];
             uint32_t wg[P1_GROUP];
 #pragma unroll
             for (int g = 0; g < P1_GROUP; ++g) {
                 const int c = c0 + 64 * g;
                 wg[g] = 0u;
                 Xg[g] = Yg[g] = Zg[g] = 0;
+                kg[g] = -1;
                 if (c < total) {
                     const int yz = rowof[c];
                     const int ty = yz & 255, tz = yz >> 8, r = ty + tz * sy, tx = clo[r] + (c - off[r]);
                     int X = T.lo[0] + tx, Y = T.lo[1] + ty, Z = T.lo[2] + tz;
                     if (wrap3(inner, X, Y, Z)) {
                         const int kst = storage_of(segmap, kp, X, Y, Z);
+                        kg[g] = kst;
                         wg[g] = kst >= 0 ? nodeword[kst] : 0u;
                     }
                     Xg[g] = X;
@@ -741,6 +745,7 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
                     }
                 }
                 val[c] = v;
+                kof[c] = kg[g];
             }
         }
     };
@@ -751,52 +756,65 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
     const RT invS = S > RT(0) ? RT(1) / S : RT(0);
     __syncthreads();
 
-    // pass 2: covered candidates (fluid, and inside or next to an inside node)
-    auto at = [&](int r, int x) -> RT {
-        const int d = x - clo[r], b = off[r];
-        return (d >= 0 && d < off[r + 1] - b) ? val[b + d] : RT(-2);
-    };
+    // pass 2: covered candidates (fluid, and inside or next to an inside node). The LDS reads
+    // go in three independent batches (the candidate's value and row; the row tables of its
+    // row and the four neighbouring rows; the six neighbour values), and each covered node
+    // issues its loads and its slot atomic together.
     // the j-th covered node in candidate order fills the cell's entry j
     RT acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const size_t ld = (size_t)kp.ld;
     const unsigned long long below = (1ull << lane) - 1ull;
     int jbase = 0;
+    // index of x in a row's candidates, from the row's (first x, first index, end index); -1 outside
+    auto cand = [](int x, int cl, int o, int e) { const int d = x - cl; return (d >= 0 && d < e - o) ? o + d : -1; };
     auto pass2 = [&](auto inner) {
         for (int c0 = 0; c0 < total; c0 += 64) {
             const int c = c0 + lane;
-            const RT v = c < total ? val[c] : RT(-2);
-            int r = 0, ty = 0, tz = 0, tx = 0;
-            RT vxm = RT(-2), vxp = RT(-2), vym = RT(-2), vyp = RT(-2), vzm = RT(-2), vzp = RT(-2);
-            bool cov = false;
-            if (v > RT(-1.5)) {
-                const int yz = rowof[c];
-                ty = yz & 255;
-                tz = yz >> 8;
-                r = ty + tz * sy;
-                tx = clo[r] + (c - off[r]);
-                vxm = at(r, tx - 1);
-                vxp = at(r, tx + 1);
-                if (ty > 0) vym = at(r - 1, tx);
-                if (ty + 1 < sy) vyp = at(r + 1, tx);
-                if (tz > 0) vzm = at(r - sy, tx);
-                if (tz + 1 < sz) vzp = at(r + sy, tx);
-                cov = v >= RT(0) || vxm >= RT(0) || vxp >= RT(0) || vym >= RT(0) || vyp >= RT(0) ||
-                      vzm >= RT(0) || vzp >= RT(0);
-            }
+            const bool live = c < total;
+            const int cc = live ? c : 0;
+            const RT v0 = val[cc];
+            const int yz = rowof[cc];
+            const int kn = kof[cc];
+            const RT v = live ? v0 : RT(-2);
+            const int ty = yz & 255, tz = yz >> 8, r = ty + tz * sy;
+            const bool hym = ty > 0, hyp = ty + 1 < sy, hzm = tz > 0, hzp = tz + 1 < sz;
+            const int rym = hym ? r - 1 : r, ryp = hyp ? r + 1 : r, rzm = hzm ? r - sy : r, rzp = hzp ? r + sy : r;
+            const int cl0 = clo[r], o0 = off[r], e0 = off[r + 1];
+            const int cl1 = clo[rym], o1 = off[rym], e1 = off[rym + 1];
+            const int cl2 = clo[ryp], o2 = off[ryp], e2 = off[ryp + 1];
+            const int cl3 = clo[rzm], o3 = off[rzm], e3 = off[rzm + 1];
+            const int cl4 = clo[rzp], o4 = off[rzp], e4 = off[rzp + 1];
+            const int tx = cl0 + (cc - o0);
+            const int ixm = cand(tx - 1, cl0, o0, e0), ixp = cand(tx + 1, cl0, o0, e0);
+            const int iym = hym ? cand(tx, cl1, o1, e1) : -1, iyp = hyp ? cand(tx, cl2, o2, e2) : -1;
+            const int izm = hzm ? cand(tx, cl3, o3, e3) : -1, izp = hzp ? cand(tx, cl4, o4, e4) : -1;
+            const RT m2 = RT(-2);
+            const RT axm = val[max(ixm, 0)], axp = val[max(ixp, 0)], aym = val[max(iym, 0)];
+            const RT ayp = val[max(iyp, 0)], azm = val[max(izm, 0)], azp = val[max(izp, 0)];
+            const RT vxm = ixm >= 0 ? axm : m2, vxp = ixp >= 0 ? axp : m2, vym = iym >= 0 ? aym : m2;
+            const RT vyp = iyp >= 0 ? ayp : m2, vzm = izm >= 0 ? azm : m2, vzp = izp >= 0 ? azp : m2;
+            const bool cov = v > RT(-1.5) &&
+                             (v >= RT(0) || vxm >= RT(0) || vxp >= RT(0) || vym >= RT(0) || vyp >= RT(0) ||
+                              vzm >= RT(0) || vzp >= RT(0));
             const unsigned long long m = __ballot(cov);
             const int j = jbase + (int)__popcll(m & below);
             jbase += (int)__popcll(m);
             if (!cov) continue;
             const bool in = v >= RT(0);
-            int X = T.lo[0] + tx, Y = T.lo[1] + ty, Z = T.lo[2] + tz;
-            wrap3(inner, X, Y, Z);
-            const unsigned n = (unsigned)storage_of(segmap, kp, X, Y, Z);   // covered nodes are fluid
+            const unsigned n = (unsigned)kn;   // covered nodes are fluid: stored
             const RT z0 = RT(0);
             const RT rr = in ? v : z0;
             const RT gx = RT(0.5) * (max(vxp, z0) - max(vxm, z0));
             const RT gy = RT(0.5) * (max(vyp, z0) - max(vym, z0));
             const RT gz = RT(0.5) * (max(vzp, z0) - max(vzm, z0));
-            const RT ux = *at32(u, n), uy = *at32(u + ld, n), uz = *at32(u + 2 * ld, n);
+            const RT* un = vel_of(u, n);
+            const RT ux = un[0], uy = un[1], uz = un[2];
+            // the stress at inside nodes, loaded beside u before the atomic's result is needed
+            RT sg[6] = {z0, z0, z0, z0, z0, z0};
+            if (in) {
+                const RT* sn = str_of(sig, n);
+                for (int q = 0; q < 6; ++q) sg[q] = sn[q];
+            }
             const uint32_t old = atomicAdd(cnt + n, 1u);
             const int slot = (int)old;
             const int e = (i << kp.ent_shift) | j;
@@ -822,8 +840,9 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
             const RT g2 = hx * hx + hy * hy + hz * hz;
             const RT il = g2 > RT(0) ? fast_rsqrt(g2) : RT(0);
             const RT nx_ = hx * il, ny_ = hy * il, nz_ = hz * il;
-            const RT sxx = *at32(sig, n), syy = *at32(sig + ld, n), szz = *at32(sig + 2 * ld, n);
-            const RT sxy_ = *at32(sig + 3 * ld, n), sxz = *at32(sig + 4 * ld, n), syz = *at32(sig + 5 * ld, n);
+            const RT sxx = sg[0], syy = sg[1], szz = sg[2], sxy_ = sg[3], sxz = sg[4], syz = sg[5];
+            int X = T.lo[0] + tx, Y = T.lo[1] + ty, Z = T.lo[2] + tz;
+            wrap3(inner, X, Y, Z);
             const RT t0 = sxx * nx_ + sxy_ * ny_ + sxz * nz_;
             const RT t1 = sxy_ * nx_ + syy * ny_ + syz * nz_;
             const RT t2 = sxz * nx_ + syz * ny_ + szz * nz_;
@@ -853,7 +872,7 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
 }
 
 template <typename RT>
-__global__ __launch_bounds__(64) void k_map_couple(const RbcState* __restrict__ st,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_map_couple(const RbcState* __restrict__ st,
                                                    RbcCouple* __restrict__ cp,
                                                    Gather<RT>* __restrict__ gat,
                                                    const uint32_t* __restrict__ nodeword,
@@ -1216,7 +1235,7 @@ __global__ __launch_bounds__(256) void kf_sort(const FusedArgs fa)
 }
 
 template <typename RT>
-__global__ __launch_bounds__(64) void kf_map(const FusedArgs fa)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void kf_map(const FusedArgs fa)
 {
     extern __shared__ unsigned char smem[];
     int lb;
@@ -1316,7 +1335,7 @@ static inline unsigned grid8(long long units, int per_block)
 
 size_t map_couple_lds(int tile_max, int cand_cap, int real_bytes)
 {
-    return (((size_t)4 * tile_max * tile_max + 2 + 15) & ~(size_t)15) + (size_t)cand_cap * (real_bytes + 2);
+    return (((size_t)4 * tile_max * tile_max + 2 + 15) & ~(size_t)15) + (size_t)cand_cap * (real_bytes + 2 + 4) + 4;
 }
 
 size_t map_couple_tile_lds(int tile_max, int real_bytes)

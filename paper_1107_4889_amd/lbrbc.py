@@ -32,7 +32,7 @@ SYMBOLS = ["lb_query_footprint", "lb_init", "lb_step", "rbc_couple", "rbc_collid
            "rbc_collide_static", "lb_batch_capture", "lb_graph_launch", "lb_graph_destroy",
            "lb_sync",
            "lb_last_error",
-           "lb_destroy", "lb_set_timing", "lb_kernel_time"]
+           "lb_destroy", "lb_set_timing", "lb_kernel_time", "lb_map_time"]
 
 
 class LbError(RuntimeError):
@@ -112,6 +112,7 @@ _sig = {
     "lb_destroy": [_P],
     "lb_set_timing": [_P, ctypes.c_int],
     "lb_kernel_time": [_P, _D, _D],
+    "lb_map_time": [_P, _D],
 }
 for _n, _a in _sig.items():
     _f = getattr(_lib, _n)
@@ -370,6 +371,11 @@ class Simulation:
         a, b = ctypes.c_double(0), ctypes.c_double(0)
         self._chk(_lib.lb_kernel_time(self.h, ctypes.byref(a), ctypes.byref(b)), "lb_kernel_time")
         return a.value, b.value
+
+    def lb_map_time(self) -> float:
+        a = ctypes.c_double(0)
+        self._chk(_lib.lb_map_time(self.h, ctypes.byref(a)), "lb_map_time")
+        return a.value
 
 
 def lb_batch_step(sims, nsteps):

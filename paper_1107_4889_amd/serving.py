@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import hashlib
 import heapq
+import threading
 import time
 from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
@@ -112,6 +113,10 @@ class Server:
         self._fp: dict = {}
         self.pending: list = []      # (request, footprint, future of its set-up)
         self.pool = ThreadPoolExecutor(max_workers=1)
+        # A stream capture must not overlap a set-up on the worker thread: the set-up allocates
+        # device memory and synchronises, which can invalidate the capture. A capture runs only
+        # when it gets this lock at once; otherwise the chunk runs without a graph.
+        self._capture_lock = threading.Lock()
 
     # -- admission ------------------------------------------------------------------------
     def footprint(self, req: Request) -> int:
@@ -131,10 +136,11 @@ class Server:
 
     def _setup(self, req: Request):
         """Context of a request on its own stream (lb_init waits for that stream only)."""
-        stream = torch.cuda.Stream(device=self.device)
-        sim = lbrbc.Simulation(req.cfg, req.solid, R=req.R if len(req.R) else None,
-                               Q=req.Q if len(req.R) else None, device=self.device,
-                               stream=stream)
+        with self._capture_lock:
+            stream = torch.cuda.Stream(device=self.device)
+            sim = lbrbc.Simulation(req.cfg, req.solid, R=req.R if len(req.R) else None,
+                                   Q=req.Q if len(req.R) else None, device=self.device,
+                                   stream=stream)
         return sim, stream
 
     def _admit(self):
@@ -165,14 +171,21 @@ class Server:
             self.active[req.rid].footprint = fp
 
     # -- stepping -------------------------------------------------------------------------
-    def _graph_for(self, a: _Active):
-        """Capture `chunk` steps of this request once (even count: the A/B parity returns)."""
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.stream(a.stream):
-            with torch.cuda.graph(g, stream=a.stream):
-                a.sim.lb_step(self.chunk)
+    def _graph_for(self, a: _Active) -> bool:
+        """Capture `chunk` steps of this request once (even count: the A/B parity returns).
+        False, and nothing captured, while a set-up is running."""
+        if not self._capture_lock.acquire(blocking=False):
+            return False
+        try:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.stream(a.stream):
+                with torch.cuda.graph(g, stream=a.stream):
+                    a.sim.lb_step(self.chunk)
+        finally:
+            self._capture_lock.release()
         a.graph = g
         a.graph_steps = self.chunk
+        return True
 
     def _enqueue(self):
         if self.fused:
@@ -184,9 +197,7 @@ class Server:
                 continue
             n = min(self.chunk, left)
             a.done_steps += n
-            if self.use_graphs and n == self.chunk:
-                if a.graph is None:
-                    self._graph_for(a)
+            if self.use_graphs and n == self.chunk and (a.graph is not None or self._graph_for(a)):
                 with torch.cuda.stream(a.stream):
                     a.graph.replay()
                 ev = torch.cuda.Event()
@@ -211,13 +222,9 @@ class Server:
         if not todo:
             return
         counts = [min(self.chunk, a.req.steps - a.done_steps) for a in todo]
-        if self.use_graphs and all(n == self.chunk for n in counts):
-            key = tuple(a.req.rid for a in todo)
-            if key != self._bkey:
-                self._drop_graph()
-                self._bgraph = lbrbc.BatchGraph([a.sim for a in todo], self.chunk)
-                self._bkey = key
-                self.captures += 1
+        key = tuple(a.req.rid for a in todo)
+        if (self.use_graphs and all(n == self.chunk for n in counts) and
+                (key == self._bkey or self._capture_batch(todo, key))):
             self._bgraph.launch()
             self.graph_launches += 1
         else:
@@ -228,6 +235,20 @@ class Server:
         for a, n in zip(todo, counts):
             a.done_steps += n
             a.events.append(ev)
+
+    def _capture_batch(self, todo, key) -> bool:
+        """Capture the chunk for this composition of the resident set; False, and nothing
+        captured, while a set-up is running."""
+        if not self._capture_lock.acquire(blocking=False):
+            return False
+        try:
+            self._drop_graph()
+            self._bgraph = lbrbc.BatchGraph([a.sim for a in todo], self.chunk)
+        finally:
+            self._capture_lock.release()
+        self._bkey = key
+        self.captures += 1
+        return True
 
     def _drop_graph(self):
         """Retire the current batch graph; it is freed once its last replay has finished
