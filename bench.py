@@ -197,8 +197,8 @@ def run_serving(args):
     lu = sum(r.n_fluid * r.steps for r in results)
     desc = (f"serving: {len(tr)} requests, Poisson arrivals at {args.rate:g}/s, "
             "straight tubes and 20-degree chevrons (1:1), R ~ U(8, 32), length "
-            "~ U(4, 16) R, target hematocrit ~ U(0.2, 0.5) (random sequential "
-            "addition: achieved values reported), steps ~ U{500..5000}, "
+            "~ U(4, 16) R, target hematocrit ~ U(0.2, 0.5) (placement by inflation: "
+            "achieved values reported), steps ~ U{500..5000}, "
             f"{args.storage} storage")
     record = {
         "aggregate_mlups": round(sm["aggregate_mlups"], 2),

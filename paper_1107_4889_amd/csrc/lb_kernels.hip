@@ -144,7 +144,24 @@ struct NodeAt {
     unsigned k;       // storage index
     int x, y, z;      // lattice coordinates
     int x0;           // compact layout: first x of the node's segment
+    unsigned salt;    // step term of the BF16 stochastic rounding, shifted past the direction bits
 };
+
+// The step counter of a context: the stream-collide of step s (A/B parity par) reads
+// ctr[par] = s and one of its threads writes ctr[par ^ 1] = s + 1 for the next step, so no
+// launch reads the word it writes. The counter lives in device memory: captured graphs and fused
+// launches advance it too. Its value salts the BF16 stochastic rounding (0 for other storages).
+template <typename ST>
+__device__ __forceinline__ unsigned step_salt(unsigned* ctr, int par, const KParams& kp, bool writer)
+{
+    unsigned v = 0;
+    if (std::is_same<ST, bf16_t>::value && kp.bf16_sr) v = __builtin_amdgcn_readfirstlane(ctr[par]);
+    if (writer) {
+        const unsigned c = ctr[par];
+        ctr[par ^ 1] = c + 1u;
+    }
+    return v << 5;
+}
 
 template <bool CMP, int P>
 __device__ __forceinline__ unsigned source_of(const NodeAt& a, const SegNb& nb, const KParams& kp)
@@ -217,7 +234,7 @@ template <typename ST, typename RT, typename PL, int P>
 __device__ __forceinline__ void collide_pair(const RT* f, const PL& pl, unsigned n,
                                              RT drho, RT rho, RT ux, RT uy, RT uz, RT usq,
                                              const RT g[3], RT gu, RT om, RT kf, RT k2, RT k3,
-                                             const KParams& kp, bool live, bool put)
+                                             const KParams& kp, bool live, bool put, unsigned slt)
 {
     constexpr int Q = P + 1;
     const RT w = RT(w_(P));
@@ -228,8 +245,8 @@ __device__ __forceinline__ void collide_pair(const RT* f, const PL& pl, unsigned
     const RT fs = kf * w * (k2 * gc * uc - k3 * gu);
     const RT fa = kf * w * RT(3) * gc;
     if (put) {
-        store_pop<ST, RT>(pl.dst(P), n, live ? f[P] - om * (f[P] - sym - asym) + fs + fa : RT(0), kp, P);
-        store_pop<ST, RT>(pl.dst(Q), n, live ? f[Q] - om * (f[Q] - sym + asym) + fs - fa : RT(0), kp, Q);
+        store_pop<ST, RT>(pl.dst(P), n, live ? f[P] - om * (f[P] - sym - asym) + fs + fa : RT(0), kp, P | slt);
+        store_pop<ST, RT>(pl.dst(Q), n, live ? f[Q] - om * (f[Q] - sym + asym) + fs - fa : RT(0), kp, Q | slt);
     }
 }
 
@@ -237,10 +254,11 @@ template <typename ST, typename RT, typename PL, int... Ps>
 __device__ __forceinline__ void collide_pairs(const RT* f, const PL& pl, unsigned n,
                                               RT drho, RT rho, RT ux, RT uy, RT uz, RT usq,
                                               const RT g[3], RT gu, RT om, RT kf, RT k2, RT k3,
-                                              const KParams& kp, bool live, bool put,
+                                              const KParams& kp, bool live, bool put, unsigned slt,
                                               std::integer_sequence<int, Ps...>)
 {
-    (collide_pair<ST, RT, PL, 2 * Ps + 1>(f, pl, n, drho, rho, ux, uy, uz, usq, g, gu, om, kf, k2, k3, kp, live, put), ...);
+    (collide_pair<ST, RT, PL, 2 * Ps + 1>(f, pl, n, drho, rho, ux, uy, uz, usq, g, gu, om, kf, k2, k3, kp, live, put,
+                                          slt), ...);
 }
 
 // ---- fused spreading + stream + collide (Sec. II A, Eqs. 1-8) -----------------------------
@@ -324,9 +342,9 @@ __device__ __forceinline__ void stream_collide_node(const PL& pl, const uint32_t
         const RT w0 = RT(w_(0));
         const RT fe0 = w0 * (drho - RT(1.5) * rho * usq);
         const RT F0 = -kf * w0 * k3 * gu;
-        if (put_f) store_pop<ST, RT>(pl.dst(0), n, live ? f[0] - om * (f[0] - fe0) + F0 : RT(0), kp, 0u);
+        if (put_f) store_pop<ST, RT>(pl.dst(0), n, live ? f[0] - om * (f[0] - fe0) + F0 : RT(0), kp, at.salt);
     }
-    collide_pairs<ST, RT>(f, pl, n, drho, rho, ux, uy, uz, usq, g, gu, om, kf, k2, k3, kp, live, put_f,
+    collide_pairs<ST, RT>(f, pl, n, drho, rho, ux, uy, uz, usq, g, gu, om, kf, k2, k3, kp, live, put_f, at.salt,
                           std::make_integer_sequence<int, 9>{});
 
     // stress of the non-equilibrium part: sigma = -(1 - 1/(2T)) sum c c (f - f^eq), with
@@ -365,13 +383,13 @@ __device__ __forceinline__ void stream_collide_segment(const PL& pl, const uint3
                                                        const MapPlanes<RT>& mp,
                                                        const Gather<RT>* __restrict__ gat,
                                                        const KParams& kp, unsigned* __restrict__ err,
-                                                       const SegTables& tab, int s)
+                                                       const SegTables& tab, int s, unsigned slt)
 {
     s = __builtin_amdgcn_readfirstlane(s);
     const int4 sg = tab.seg[s];
     SegNb nb;
     load_segnb(tab.nb, s, nb);
-    const NodeAt at{((unsigned)s << 6) | threadIdx.x, sg.x + (int)threadIdx.x, sg.y, sg.z, sg.x};
+    const NodeAt at{((unsigned)s << 6) | threadIdx.x, sg.x + (int)threadIdx.x, sg.y, sg.z, sg.x, slt};
     stream_collide_node<ST, RT, PL, CLEAR, true>(pl, nodeword, mp, gat, kp, err, at, nb);
 }
 
@@ -380,10 +398,12 @@ template <typename ST, typename RT, bool CLEAR>
 __global__ __launch_bounds__(256) void k_stream_collide_cmp(
     const Planes<ST, RT> pl, const uint32_t* __restrict__ nodeword, const MapPlanes<RT> mp,
     const Gather<RT>* __restrict__ gat, KParams kp, unsigned* __restrict__ err, const SegTables tab,
-    int nseg)
+    int nseg, unsigned* __restrict__ ctr, int par)
 {
-    const int s = (int)xcd_tile() * 4 + (int)threadIdx.y;
-    if (s < nseg) stream_collide_segment<ST, RT, Planes<ST, RT>, CLEAR>(pl, nodeword, mp, gat, kp, err, tab, s);
+    const unsigned t = xcd_tile();
+    const unsigned slt = step_salt<ST>(ctr, par, kp, t == 0 && threadIdx.x == 0 && threadIdx.y == 0);
+    const int s = (int)t * 4 + (int)threadIdx.y;
+    if (s < nseg) stream_collide_segment<ST, RT, Planes<ST, RT>, CLEAR>(pl, nodeword, mp, gat, kp, err, tab, s, slt);
 }
 
 // dense layout: tiles of 64 x 4 nodes (a wavefront spans 64 consecutive x)
@@ -391,16 +411,18 @@ template <typename ST, typename RT, bool CLEAR>
 __global__ __launch_bounds__(256) void k_stream_collide(
     const Planes<ST, RT> pl, const uint32_t* __restrict__ nodeword, const MapPlanes<RT> mp,
     const Gather<RT>* __restrict__ gat, KParams kp, unsigned* __restrict__ err, unsigned nbx,
-    unsigned nby, unsigned ntiles)
+    unsigned nby, unsigned ntiles, unsigned* __restrict__ ctr, int par)
 {
     const unsigned t = xcd_tile();
     if (t >= ntiles) return;
+    const unsigned slt = step_salt<ST>(ctr, par, kp, t == 0 && threadIdx.x == 0 && threadIdx.y == 0);
     const unsigned r = t / nbx;
     const int x = (int)(t - r * nbx) * 64 + threadIdx.x;
     const int y = (int)(r % nby) * 4 + threadIdx.y;
     const int z = (int)(r / nby);
     if (x < kp.nx && y < kp.ny) {
-        const NodeAt at{(unsigned)x + (unsigned)kp.nx * ((unsigned)y + (unsigned)kp.ny * (unsigned)z), x, y, z, 0};
+        const NodeAt at{(unsigned)x + (unsigned)kp.nx * ((unsigned)y + (unsigned)kp.ny * (unsigned)z), x, y, z, 0,
+                        slt};
         stream_collide_node<ST, RT, Planes<ST, RT>, CLEAR, false>(pl, nodeword, mp, gat, kp, err, at, SegNb{});
     }
 }
@@ -413,10 +435,12 @@ __global__ __launch_bounds__(256) void k_open_bc(
     const ST* __restrict__ fin, ST* __restrict__ fout, const uint32_t* __restrict__ nodeword,
     const int4* __restrict__ planes, int nplane, const MapPlanes<RT> mp,
     const Gather<RT>* __restrict__ gat, RT* __restrict__ uout, RT* __restrict__ sout, KParams kp,
-    const SegTables tab, int clear_counts)
+    const SegTables tab, int clear_counts, unsigned* __restrict__ ctr, int par)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nplane) return;
+    // the step term of this step's stream-collide (which has written only the other word)
+    const unsigned slt = step_salt<ST>(ctr, par, kp, false);
     const int4 pq = planes[q];
     const unsigned n = (unsigned)pq.x;
     const int x = pq.z & 0xffff;
@@ -436,7 +460,8 @@ __global__ __launch_bounds__(256) void k_open_bc(
     if (clear_counts && cn) mp.cnt[n] = 0u;
     if (!(wi & NW_FLUID)) {
         for (int p = 0; p < 19; ++p)
-            store_pop<ST, RT>(fout + (size_t)p * (size_t)kp.ld, (unsigned)n, RT(w_(p)) * (rb - RT(1)), kp, (unsigned)p);
+            store_pop<ST, RT>(fout + (size_t)p * (size_t)kp.ld, (unsigned)n, RT(w_(p)) * (rb - RT(1)), kp,
+                              (unsigned)p | slt);
         for (int a = 0; a < 3; ++a) vel_of(uout, n)[a] = RT(0);
         return;
     }
@@ -469,7 +494,8 @@ __global__ __launch_bounds__(256) void k_open_bc(
     for (int p = 0; p < 19; ++p) {
         const RT feb = feq_shift<RT>(p, rb - RT(1), rb, ux, uy, uz, usq);
         const RT fei = feq_shift<RT>(p, drho, rho, ux, uy, uz, usq);
-        store_pop<ST, RT>(fout + (size_t)p * (size_t)kp.ld, (unsigned)n, feb + (RT(1) - om) * (f[p] - fei), kp, (unsigned)p);
+        store_pop<ST, RT>(fout + (size_t)p * (size_t)kp.ld, (unsigned)n, feb + (RT(1) - om) * (f[p] - fei), kp,
+                          (unsigned)p | slt);
     }
     RT* uo = vel_of(uout, n);
     uo[0] = ux;
@@ -619,12 +645,13 @@ __global__ __launch_bounds__(256) void kf_stream(const FusedArgs fa)
     const PlanesLd<ST, RT> pl{(const ST*)(odd ? d.fB : d.fA), (ST*)(odd ? d.fA : d.fB), (RT*)d.b.u,
                               (RT*)d.b.sig, (unsigned long long)kp.ld};
     const MapPlanes<RT> mp = map_planes_dev<RT>(d.b.map_ids, d.b.map_vals, d.b.cnt, kp);
+    const unsigned slt = step_salt<ST>(d.b.step_ctr, odd ? 1 : 0, kp, lb == 0 && threadIdx.x == 0 && threadIdx.y == 0);
     if (kp.compact) {
         // four stored segments per block, one per wavefront
         const int s = lb * 4 + (int)threadIdx.y;
         if ((long long)s * 64 < kp.N)
             stream_collide_segment<ST, RT, PlanesLd<ST, RT>, true>(pl, d.b.nodeword, mp, (const Gather<RT>*)d.b.gat,
-                                                                   kp, d.b.err, d.b.tab, s);
+                                                                   kp, d.b.err, d.b.tab, s, slt);
         return;
     }
     // dense layout: flat node order (no idle lanes on lattices narrower than, or not a multiple
@@ -634,7 +661,7 @@ __global__ __launch_bounds__(256) void kf_stream(const FusedArgs fa)
     const unsigned nxy = (unsigned)kp.nx * (unsigned)kp.ny;
     const int z = (int)(n / nxy), rem = (int)(n - (unsigned)z * nxy);
     const int y = rem / kp.nx, x = rem - y * kp.nx;
-    const NodeAt at{n, x, y, z, 0};
+    const NodeAt at{n, x, y, z, 0, slt};
     stream_collide_node<ST, RT, PlanesLd<ST, RT>, true, false>(pl, d.b.nodeword, mp, (const Gather<RT>*)d.b.gat,
                                                                kp, d.b.err, at, SegNb{});
 }
@@ -644,7 +671,7 @@ template <typename ST, typename RT>
 void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword, const int* ids,
                            const void* vals, uint32_t* cnt, const void* gat, void* u, void* sig,
                            const KParams& kp, unsigned* err, bool clear_counts, const SegTables& tab,
-                           int nseg, hipStream_t st)
+                           int nseg, unsigned* ctr, int par, hipStream_t st)
 {
     if (kp.compact && nseg <= 0) return;
     Planes<ST, RT> pl;
@@ -661,10 +688,10 @@ void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword
         const dim3 grid(((unsigned)((nseg + 3) / 4) + 7u) / 8u * 8u);
         if (clear_counts)
             hipLaunchKernelGGL((k_stream_collide_cmp<ST, RT, true>), grid, dim3(64, 4, 1), 0, st, pl, nodeword, mp, g,
-                               kp, err, tab, nseg);
+                               kp, err, tab, nseg, ctr, par);
         else
             hipLaunchKernelGGL((k_stream_collide_cmp<ST, RT, false>), grid, dim3(64, 4, 1), 0, st, pl, nodeword, mp,
-                               g, kp, err, tab, nseg);
+                               g, kp, err, tab, nseg, ctr, par);
         return;
     }
     const unsigned nbx = (unsigned)((kp.nx + 63) / 64), nby = (unsigned)((kp.ny + 3) / 4);
@@ -672,22 +699,23 @@ void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword
     const dim3 grid((ntiles + 7u) / 8u * 8u);
     if (clear_counts)
         hipLaunchKernelGGL((k_stream_collide<ST, RT, true>), grid, dim3(64, 4, 1), 0, st, pl, nodeword, mp, g, kp,
-                           err, nbx, nby, ntiles);
+                           err, nbx, nby, ntiles, ctr, par);
     else
         hipLaunchKernelGGL((k_stream_collide<ST, RT, false>), grid, dim3(64, 4, 1), 0, st, pl, nodeword, mp, g, kp,
-                           err, nbx, nby, ntiles);
+                           err, nbx, nby, ntiles, ctr, par);
 }
 
 template <typename ST, typename RT>
 void launch_open_bc(const void* fin, void* fout, const uint32_t* nodeword, const int4* planes,
                     int nplane, const int* ids, const void* vals, uint32_t* cnt, const void* gat, void* u,
-                    void* sig, const KParams& kp, const SegTables& tab, bool clear_counts, hipStream_t st)
+                    void* sig, const KParams& kp, const SegTables& tab, bool clear_counts, unsigned* ctr,
+                    int par, hipStream_t st)
 {
     if (nplane <= 0) return;
     hipLaunchKernelGGL((k_open_bc<ST, RT>), dim3((nplane + 255) / 256), dim3(256), 0, st,
                        (const ST*)fin, (ST*)fout, nodeword, planes, nplane,
                        map_planes<RT>(ids, vals, cnt, kp), (const Gather<RT>*)gat, (RT*)u, (RT*)sig, kp,
-                       tab, clear_counts ? 1 : 0);
+                       tab, clear_counts ? 1 : 0, ctr, par);
 }
 
 template <typename RT>
@@ -737,11 +765,12 @@ void launch_fused_lattice(const FusedArgs& fa, int stage, hipStream_t st)
     template void launch_stream_collide<ST, RT>(const void*, void*, const uint32_t*, const int*,  \
                                                 const void*, uint32_t*, const void*, void*, void*, \
                                                 const KParams&, unsigned*, bool, const SegTables&, \
-                                                int, hipStream_t);                                \
+                                                int, unsigned*, int, hipStream_t);                \
     template void launch_open_bc<ST, RT>(const void*, void*, const uint32_t*, const int4*,        \
                                          int, const int*, const void*, uint32_t*, const void*,    \
                                          void*, void*,                                            \
-                                         const KParams&, const SegTables&, bool, hipStream_t);    \
+                                         const KParams&, const SegTables&, bool, unsigned*, int,  \
+                                         hipStream_t);                                            \
     template void launch_observe<ST, RT>(const void*, const uint32_t*, const void*,               \
                                          const KParams&, double*, int, double*, hipStream_t);
 INST_ST(double, double)

@@ -458,7 +458,7 @@ std::string build_geometry(const lb_config& c, const uint8_t* solid, int n_rbc, 
 struct Layout {
     size_t fA, fB, u, sig, gdbg, tdbg, nodeword, map_ids[2], map_vals[2], cnt[2], ovf, st, cp, gat, cellid, cell_cnt, cell_off,
         cell_part, cell_ids, wall_xyz, wcell_off, wcell_ids, wn_node, wn_nrm, wss, wss_acc, planes, segs, segnb,
-        segmap, partials, obs_out, err, slot, total;
+        segmap, partials, obs_out, err, step_ctr, slot, total;
 };
 
 Layout layout(const lb_config& c, const Geometry& g, int n_rbc)
@@ -511,6 +511,7 @@ Layout layout(const lb_config& c, const Geometry& g, int n_rbc)
     L.partials = take(6 * OBS_BLOCKS * 8);
     L.obs_out = take(8 * 8);
     L.err = take(4);
+    L.step_ctr = take(8);
     L.slot = take(sizeof(SlotDesc));
     L.total = o;
     return L;
@@ -600,6 +601,8 @@ struct lb_ctx_s {
     }
     // stored segments of the compact layout (0 in the dense one)
     int nseg() const { return (int)(geo.segs.size() / 4); }
+    // 0 while the current populations are in buffer A, 1 in buffer B (flips every step)
+    int ab_parity() { return fA == at<void>(lay.fA) ? 0 : 1; }
 };
 
 namespace {
@@ -809,7 +812,8 @@ void enqueue_step(lb_ctx c, bool last)
         }
         launch_stream_collide<ST, RT>(c->fA, c->fB, b.nodeword, b.map_ids, b.map_vals, b.cnt,
                                       c->cb.gat, c->at<void>(c->lay.u), c->at<void>(c->lay.sig), kp,
-                                      c->cb.err, sc_clears && c->nrbc > 0, c->cb.tab, c->nseg(), s);
+                                      c->cb.err, sc_clears && c->nrbc > 0, c->cb.tab, c->nseg(), c->cb.step_ctr,
+                                      c->ab_parity(), s);
         if (e0) {
             (void)hipEventRecord(e1, s);
             c->sc_pairs.emplace_back(e0, e1);
@@ -818,7 +822,7 @@ void enqueue_step(lb_ctx c, bool last)
             launch_open_bc<ST, RT>(c->fA, c->fB, b.nodeword, c->at<int4>(c->lay.planes),
                                    (int)c->geo.planes.size() / 4, b.map_ids, b.map_vals, b.cnt, c->cb.gat,
                                    c->at<void>(c->lay.u), c->at<void>(c->lay.sig), kp, c->cb.tab,
-                                   sc_clears && c->nrbc > 0, s);
+                                   sc_clears && c->nrbc > 0, c->cb.step_ctr, c->ab_parity(), s);
         if (c->wss_on)
             launch_wss<RT>(c->at<void>(c->lay.sig), c->at<long long>(c->lay.wn_node),
                            c->at<double>(c->lay.wn_nrm), (int)c->geo.wn_node.size(), kp, nullptr,
@@ -1026,6 +1030,7 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
     b.tab.seg = c->at<int4>(L.segs);
     b.tab.nb = c->at<int>(L.segnb);
     b.tab.map = c->at<int>(L.segmap);
+    b.step_ctr = c->at<unsigned>(L.step_ctr);
 
     hipStream_t s = c->stream;
     auto h2d = [&](size_t off, const void* src, size_t bytes) {
@@ -1748,6 +1753,11 @@ lb_status lb_load(lb_ctx c, const void* buf, size_t bytes)
     p += sb;
     if (wb) HIPCHK(c, hipMemcpy(c->at<double>(c->lay.wss_acc), p, wb, hipMemcpyHostToDevice));
     c->step = h.step;
+    {
+        // the device step counter (the BF16 rounding's step term) continues from the saved step
+        const unsigned ctr = (unsigned)h.step;
+        HIPCHK(c, hipMemcpy(c->cb.step_ctr + c->ab_parity(), &ctr, 4, hipMemcpyHostToDevice));
+    }
     c->wss_count = h.wss_count;
     c->wss_on = h.wss_on;
     HIPCHK(c, hipMemset(c->cb.err, 0, 4));

@@ -16,12 +16,13 @@ template <typename ST, typename RT>
 void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword, const int* ids,
                            const void* vals, uint32_t* cnt, const void* gat, void* u, void* sig,
                            const KParams& kp, unsigned* err, bool clear_counts, const SegTables& tab,
-                           int nseg, hipStream_t st);
+                           int nseg, unsigned* ctr, int par, hipStream_t st);
 // planes: per open-plane node (k, k of its inner neighbour, x | y << 16, z)
 template <typename ST, typename RT>
 void launch_open_bc(const void* fin, void* fout, const uint32_t* nodeword, const int4* planes,
                     int nplane, const int* ids, const void* vals, uint32_t* cnt, const void* gat, void* u,
-                    void* sig, const KParams& kp, const SegTables& tab, bool clear_counts, hipStream_t st);
+                    void* sig, const KParams& kp, const SegTables& tab, bool clear_counts, unsigned* ctr,
+                    int par, hipStream_t st);
 template <typename RT>
 void launch_spread_field(const uint32_t* nodeword, const int* ids, const void* vals, uint32_t* cnt,
                          const void* gat, void* g, void* t, const KParams& kp, hipStream_t st);
@@ -51,6 +52,7 @@ struct CellBuffers {
     const int* wcell_ids; // [nwall]
     uint32_t* nodeword;   // static bits per node (fluid, bounce-back, wall, open planes)
     SegTables tab;        // compact layout: stored segments, their neighbours, the segment map
+    unsigned* step_ctr;   // [2] step counter, read and advanced by the stream-collide
     // one of the two coverage sets (chosen by the step's parity)
     int* map_ids;         // [cap * ld] entry index per coverage slot
     void* map_vals;       // [entries * 4] RT: raw kernel and its gradient per entry

@@ -610,8 +610,8 @@ def serving_trace(n_requests: int, rate_hz: float, seed: int = 2011, r_range=(8.
     """A seeded stream of vessel requests: Poisson arrivals (exponential gaps at `rate_hz`),
     periodic tubes of radius R ~ U(r_range) and length k R with k ~ U(k_range), straight or,
     with probability `bent_fraction`, a chevron with a 20-degree bend; target hematocrit
-    ~ U(h_range) (random sequential addition only unless `fill`: the achieved value is
-    returned); steps ~ U{steps_range}. Returns a list of dicts in arrival order."""
+    ~ U(h_range) (placed by place_cells; the achieved value is returned); steps
+    ~ U{steps_range}. Returns a list of dicts in arrival order."""
     rng = np.random.default_rng(seed)
     t = 0.0
     jobs, arrivals = [], []
