@@ -295,15 +295,17 @@ __device__ __forceinline__ bool wrap_coord(int& X, int L, int per)
 // (xa - ROW_EPS, xb + ROW_EPS): ROW_EPS is far above the rounding of either computation (a few
 // ulps of coordinates below 2^11). The range is [lo, hi] in tile coordinates, empty when lo > hi.
 constexpr double ROW_EPS = 1e-7;
-__device__ __forceinline__ void support_row(const RbcState& s, const KParams& kp, const Tile& T, int ty, int tz,
-                                            int& lo, int& hi)
+// iq[a] = 1 / Q_xa (0 where |Q_xa| <= 1e-12), computed once per cell: a product differs from the
+// quotient by an ulp, far below ROW_EPS
+__device__ __forceinline__ void support_row(const RbcState& s, const KParams& kp, const Tile& T, const double* iq,
+                                            int ty, int tz, int& lo, int& hi)
 {
     const double dy = (double)(T.lo[1] + ty) - s.R[1], dz = (double)(T.lo[2] + tz) - s.R[2];
     double xa = -1e30, xb = 1e30;
     for (int a = 0; a < 3; ++a) {
         const double qa = s.Q[a], b = s.Q[3 + a] * dy + s.Q[6 + a] * dz;
         if (fabs(qa) > 1e-12) {
-            double u0 = (-kp.xi[a] - b) / qa, u1 = (kp.xi[a] - b) / qa;
+            double u0 = (-kp.xi[a] - b) * iq[a], u1 = (kp.xi[a] - b) * iq[a];
             if (u0 > u1) { const double t_ = u0; u0 = u1; u1 = t_; }
             xa = fmax(xa, u0);
             xb = fmin(xb, u1);
@@ -400,9 +402,11 @@ __device__ void map_couple_tile(int i, unsigned char* smem, const RbcState* __re
     const unsigned rows = sy * sz;
     // support range of each tile row (the exact test below decides each node; the ranges only
     // skip nodes that are certainly outside), then the covered range of each row
+    double iq[3];
+    for (int a = 0; a < 3; ++a) iq[a] = fabs(s.Q[a]) > 1e-12 ? 1.0 / s.Q[a] : 0.0;
     for (unsigned r = tid; r < rows; r += MC_THREADS) {
         int lo, hi;
-        support_row(s, kp, T, (int)(r % sy), (int)(r / sy), lo, hi);
+        support_row(s, kp, T, iq, (int)(r % sy), (int)(r / sy), lo, hi);
         rlo[r] = (short)lo;
         rhi[r] = (short)hi;
     }
@@ -630,9 +634,11 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
     const int rows = sy * sz;
     // support range of each row (as in map_couple_tile), then the covered range of each row
     // and its length (kept in off[] until the scan)
+    double iq[3];
+    for (int a = 0; a < 3; ++a) iq[a] = fabs(s.Q[a]) > 1e-12 ? 1.0 / s.Q[a] : 0.0;
     for (int r = lane; r < rows; r += 64) {
         int lo, hi;
-        support_row(s, kp, T, r % sy, r / sy, lo, hi);
+        support_row(s, kp, T, iq, r % sy, r / sy, lo, hi);
         tlo[r] = (short)lo;
         thi[r] = (short)hi;
     }
