@@ -844,12 +844,47 @@ bool fusable(lb_ctx c, lb_ctx first)
            !c->wss_on && !c->timing;
 }
 
+// A second stream (default priority) per device for the fused batches' cell work, as the side
+// stream of a single context: the Gay-Berne stage (it needs only the cell list) runs beside the
+// count clearing and the map pass, and the kick (it needs the map pass) beside the
+// stream-collide; the next step's first stage waits for the kick. Events fork and join it.
+// Created on the first batch call of a device (never during a capture); the mutex keeps one host
+// thread at a time enqueuing with the shared events. A batch call ends joined.
+struct FusedSide {
+    std::mutex mu;
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, mapped = nullptr, join = nullptr;
+    bool ready = false;
+};
+
+FusedSide* fused_side(int dev)
+{
+    static std::mutex create_mu;
+    static FusedSide table[SCRATCH_MAX_DEVICES];
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(create_mu);
+    FusedSide& f = table[dev];
+    if (!f.ready) {
+        int cur = 0;
+        if (hipGetDevice(&cur) != hipSuccess || cur != dev) return nullptr;
+        if (hipStreamCreateWithFlags(&f.side, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        if (hipEventCreateWithFlags(&f.fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&f.mapped, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&f.join, hipEventDisableTiming) != hipSuccess)
+            return nullptr;
+        f.ready = true;
+    }
+    return &f;
+}
+
 // one step of n contexts (n <= FUSE_MAX): rb1 + binning, scan, scatter, sort, count clearing,
-// map + interpolation (and the overflow pass), Gay-Berne, second half, stream-collide; each
-// stage is one launch over all contexts
-void enqueue_fused_step(lb_ctx* cs, int n)
+// map + interpolation (and the overflow pass), Gay-Berne, second half, stream-collide; each stage
+// is one launch over all contexts. With fs, the Gay-Berne stage and the kick run on its stream.
+void enqueue_fused_step(lb_ctx* cs, int n, FusedSide* fs)
 {
     hipStream_t s = cs[0]->stream;
+    // the previous step's kick (a no-op wait at the first step of a batch: already joined)
+    if (fs) (void)hipStreamWaitEvent(s, fs->join, 0);
     FusedArgs fa;
     fa.n = n;
     fa.parity = 0;
@@ -890,14 +925,28 @@ void enqueue_fused_step(lb_ctx* cs, int n)
             fa.start[n] = tot;
             launch_fused_lattice<ST, RT>(fa, FS_CLEAR, s);
         }
+        if (fs) {
+            starts(FS_GB);
+            (void)hipEventRecord(fs->fork, s);
+            (void)hipStreamWaitEvent(fs->side, fs->fork, 0);
+            launch_fused_cells<RT>(fa, FS_GB, 0, fs->side);
+        }
         starts(FS_MAP);
         launch_fused_cells<RT>(fa, FS_MAP, lds_map, s);
         starts(FS_MAP_TILE);
         launch_fused_cells<RT>(fa, FS_MAP_TILE, lds_tile, s);
-        starts(FS_GB);
-        launch_fused_cells<RT>(fa, FS_GB, 0, s);
-        starts(FS_RB2);
-        launch_fused_cells<RT>(fa, FS_RB2, 0, s);
+        if (fs) {
+            (void)hipEventRecord(fs->mapped, s);
+            (void)hipStreamWaitEvent(fs->side, fs->mapped, 0);
+            starts(FS_RB2);
+            launch_fused_cells<RT>(fa, FS_RB2, 0, fs->side);
+            (void)hipEventRecord(fs->join, fs->side);
+        } else {
+            starts(FS_GB);
+            launch_fused_cells<RT>(fa, FS_GB, 0, s);
+            starts(FS_RB2);
+            launch_fused_cells<RT>(fa, FS_RB2, 0, s);
+        }
         starts(FS_STREAM);
         launch_fused_lattice<ST, RT>(fa, FS_STREAM, s);
     });
@@ -1138,14 +1187,18 @@ lb_status lb_batch_step(lb_ctx* ctxs, const int* nsteps, int n)
         fuse = fuse && fusable(ctxs[i], ctxs[0]);
     }
     if (fuse) {
+        FusedSide* fs = fused_side(ctxs[0]->device);
+        std::unique_lock<std::mutex> lock;
+        if (fs) lock = std::unique_lock<std::mutex>(fs->mu);
         std::vector<lb_ctx> act;
         for (int k = 0; k < most; ++k) {
             act.clear();
             for (int i = 0; i < n; ++i)
                 if (k < nsteps[i]) act.push_back(ctxs[i]);
             for (size_t g = 0; g < act.size(); g += FUSE_MAX)
-                enqueue_fused_step(act.data() + g, (int)std::min<size_t>(FUSE_MAX, act.size() - g));
+                enqueue_fused_step(act.data() + g, (int)std::min<size_t>(FUSE_MAX, act.size() - g), fs);
         }
+        if (fs) (void)hipStreamWaitEvent(ctxs[0]->stream, fs->join, 0);
     } else {
         for (int k = 0; k < most; ++k)
             for (int i = 0; i < n; ++i)
@@ -1197,6 +1250,10 @@ lb_status lb_batch_capture(lb_ctx* ctxs, int n, int nsteps, lb_graph* out)
         // did in between (e.g. rbc_couple): counts left clean are read and left as they are
         c->dirty[0] = true;
     }
+    // the side stream of the Gay-Berne stage exists before the capture starts
+    FusedSide* fs = fused_side(ctxs[0]->device);
+    std::unique_lock<std::mutex> lock;
+    if (fs) lock = std::unique_lock<std::mutex>(fs->mu);
     // an error left by earlier work of this thread would read as a launch error of the capture
     const hipError_t pending = hipGetLastError();
     if (pending != hipSuccess) {
@@ -1212,9 +1269,11 @@ lb_status lb_batch_capture(lb_ctx* ctxs, int n, int nsteps, lb_graph* out)
     // the first launch error (launch checks are synchronous, also under capture)
     hipError_t launch_err = hipSuccess;
     for (int k = 0; k < nsteps && launch_err == hipSuccess; ++k) {
-        for (int g = 0; g < n; g += FUSE_MAX) enqueue_fused_step(ctxs + g, std::min(FUSE_MAX, n - g));
+        for (int g = 0; g < n; g += FUSE_MAX) enqueue_fused_step(ctxs + g, std::min(FUSE_MAX, n - g), fs);
         launch_err = hipGetLastError();
     }
+    // the last kick rejoins the capturing stream
+    if (fs) (void)hipStreamWaitEvent(s, fs->join, 0);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(s, &graph);
     if (launch_err != hipSuccess && e == hipSuccess) e = launch_err;
