@@ -227,7 +227,10 @@ lb_status lb_load(lb_ctx ctx, const void* buf, size_t bytes);
  * - When all contexts share one stream and one storage type, and none has open boundaries,
  *   WSS accumulation or kernel timing on, each stage of a step is ONE launch over all the
  *   contexts still stepping (fused multi-lattice kernels, up to 64 contexts per launch);
- *   the results are bitwise those of stepping each context alone.
+ *   the results are bitwise those of stepping each context alone. The Gay-Berne stage and the
+ *   kick run on a second stream of the library's (one per device, default priority, created
+ *   at the first batch call), forked from and joined back into the contexts' stream by events;
+ *   the call returns with the contexts' stream holding all its work.
  * - Otherwise the contexts' steps are interleaved step by step on their own streams, so
  *   their kernels can overlap on the device.
  * nsteps[i] < 0 or a NULL context: LB_EINVAL; a poisoned context: LB_ESTATE (nothing is
