@@ -14,7 +14,9 @@
  * Conventions (all lattice units, h = 1, mesh spacing 1, c^2 = 1/3):
  *   - node (x, y, z) has flat index n = x + nx*(y + ny*z) and sits at the point (x, y, z);
  *   - host arrays: solid[n] (uint8, 1 = solid); per node vectors [n*3 + a]; stress per node
- *     [n*6 + k], k = xx, yy, zz, xy, xz, yz; populations [p*N + n] (unshifted f);
+ *     [n*6 + k], k = xx, yy, zz, xy, xz, yz; populations [p*N + n] (unshifted f). Host
+ *     arrays are in this lattice order whatever storage layout the device uses
+ *     (lb_config.layout);
  *   - D3Q19 order: 0 rest; 1-6 = +x, -x, +y, -y, +z, -z; 7-18 = (+1,+1,0), (-1,-1,0),
  *     (+1,-1,0), (-1,+1,0), (+1,0,+1), (-1,0,-1), (+1,0,-1), (-1,0,+1), (0,+1,+1),
  *     (0,-1,-1), (0,+1,-1), (0,-1,+1);

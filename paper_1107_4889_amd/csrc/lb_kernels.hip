@@ -295,7 +295,11 @@ __device__ __forceinline__ void stream_collide_node(const PL& pl, const uint32_t
         const unsigned long long m = (hi == 63 ? ~0ull : (2ull << hi) - 1ull) & ~((1ull << lo) - 1ull);
         return (lv & m) != 0ull;
     };
-    const bool put_f = line_has_fluid((unsigned)sizeof(ST)), put_u = line_has_fluid((unsigned)sizeof(RT));
+    // u and sigma are node-interleaved, records of 3 and 6 reals that need not divide a line:
+    // the window of lanes around this one is then approximate, and a live lane always stores
+    const bool put_f = line_has_fluid((unsigned)sizeof(ST));
+    const bool put_v = live || line_has_fluid(3u * (unsigned)sizeof(RT));
+    const bool put_s = live || line_has_fluid(6u * (unsigned)sizeof(RT));
     RT f[19];
     if (live) {
         pull_all_fast<ST, RT, CMP>(f, pl, at, nb, kp, std::make_integer_sequence<int, 19>{});
@@ -352,13 +356,12 @@ __device__ __forceinline__ void stream_collide_node(const PL& pl, const uint32_t
     const RT ks = -(RT(1) - RT(0.5) * om);
     const RT d3 = drho * RT(1.0 / 3.0);
     const RT z0 = RT(0);
-    if (put_u) {
-        store_vel_nt(vel_of(pl.u, n), live ? ux : z0, live ? uy : z0, live ? uz : z0);
+    if (put_v) store_vel_nt(vel_of(pl.u, n), live ? ux : z0, live ? uy : z0, live ? uz : z0);
+    if (put_s)
         store_str_nt(str_of(pl.sig, n), live ? ks * (pxx - d3 - rho * ux * ux) : z0,
                      live ? ks * (pyy - d3 - rho * uy * uy) : z0, live ? ks * (pzz - d3 - rho * uz * uz) : z0,
                      live ? ks * (pxy - rho * ux * uy) : z0, live ? ks * (pxz - rho * ux * uz) : z0,
                      live ? ks * (pyz - rho * uy * uz) : z0);
-    }
     // (the boundary kernel still reads, and then clears, the counts at the open planes and
     // at the nodes it extrapolates from)
     if (CLEAR && line_has_fluid(4u))
