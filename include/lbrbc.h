@@ -199,7 +199,10 @@ lb_status lb_wss_accumulate(lb_ctx ctx, int on);
 
 /* Host copies of the fields; any pointer may be NULL. f: [19*N] unshifted populations
  * (post-collision of the last step); u: [3N]; sigma: [6N]; g: [3N] spread force density
- * and relax: [N] local relaxation time from the last rbc_couple. */
+ * and relax: [N] local relaxation time from the last rbc_couple. The device keeps u and
+ * sigma in the compute precision, or in 16 bits for the 16-bit storages (BF16 rounded to
+ * nearest even; FP16 holding 4096 times the value): the values returned, and those
+ * lb_set_fields stores, carry that rounding. */
 lb_status lb_get_fields(lb_ctx ctx, double* f, double* u, double* sigma, double* g,
                         double* relax);
 /* Overwrite the fluid state from host arrays (any may be NULL); clears a device fault. */

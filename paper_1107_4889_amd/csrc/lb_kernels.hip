@@ -295,11 +295,12 @@ __device__ __forceinline__ void stream_collide_node(const PL& pl, const uint32_t
         const unsigned long long m = (hi == 63 ? ~0ull : (2ull << hi) - 1ull) & ~((1ull << lo) - 1ull);
         return (lv & m) != 0ull;
     };
-    // u and sigma are node-interleaved, records of 3 and 6 reals that need not divide a line:
-    // the window of lanes around this one is then approximate, and a live lane always stores
+    // u and sigma are node-interleaved, records that need not divide a line: the window of
+    // lanes around this one is then approximate, and a live lane always stores
+    using FT = typename PL::FT;
     const bool put_f = line_has_fluid((unsigned)sizeof(ST));
-    const bool put_v = live || line_has_fluid(3u * (unsigned)sizeof(RT));
-    const bool put_s = live || line_has_fluid(6u * (unsigned)sizeof(RT));
+    const bool put_v = live || line_has_fluid(vel_stride<FT>() * (unsigned)sizeof(FT));
+    const bool put_s = live || line_has_fluid(6u * (unsigned)sizeof(FT));
     RT f[19];
     if (live) {
         pull_all_fast<ST, RT, CMP>(f, pl, at, nb, kp, std::make_integer_sequence<int, 19>{});
@@ -409,9 +410,11 @@ __global__ __launch_bounds__(256) void k_stream_collide_cmp(
     if (s < nseg) stream_collide_segment<ST, RT, Planes<ST, RT>, CLEAR>(pl, nodeword, mp, gat, kp, err, tab, s, slt);
 }
 
-// dense layout: tiles of 64 x 4 nodes (a wavefront spans 64 consecutive x)
+// dense layout: tiles of 64 x 4 nodes (a wavefront spans 64 consecutive x). With FP32
+// arithmetic the kernel is held to 72 VGPRs, seven wavefronts per SIMD (the 16-bit storages
+// gained 3% over six; FP32 storage was unchanged)
 template <typename ST, typename RT, bool CLEAR>
-__global__ __launch_bounds__(256) void k_stream_collide(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(RT) == 4 ? 7 : 1))) void k_stream_collide(
     const Planes<ST, RT> pl, const uint32_t* __restrict__ nodeword, const MapPlanes<RT> mp,
     const Gather<RT>* __restrict__ gat, KParams kp, unsigned* __restrict__ err, unsigned nbx,
     unsigned nby, unsigned ntiles, unsigned* __restrict__ ctr, int par)
@@ -437,7 +440,8 @@ template <typename ST, typename RT>
 __global__ __launch_bounds__(256) void k_open_bc(
     const ST* __restrict__ fin, ST* __restrict__ fout, const uint32_t* __restrict__ nodeword,
     const int4* __restrict__ planes, int nplane, const MapPlanes<RT> mp,
-    const Gather<RT>* __restrict__ gat, RT* __restrict__ uout, RT* __restrict__ sout, KParams kp,
+    const Gather<RT>* __restrict__ gat, typename FieldOf<ST, RT>::T* __restrict__ uout,
+    typename FieldOf<ST, RT>::T* __restrict__ sout, KParams kp,
     const SegTables tab, int clear_counts, unsigned* __restrict__ ctr, int par)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -456,8 +460,8 @@ __global__ __launch_bounds__(256) void k_open_bc(
     const uint32_t cn = mp.cnt[n], cni = inner_fluid ? mp.cnt[ni] : 0u;
     spread_at<RT>(n, cn, mp, gat, kp, gb, thb);
     const RT om = RT(1) / ((RT)kp.tau0 + (RT)kp.delta * thb);
-#pragma unroll
-    for (int a = 0; a < 6; ++a) str_of(sout, n)[a] = RT(0);
+    const RT z0 = RT(0);
+    store_str_nt(str_of(sout, n), z0, z0, z0, z0, z0, z0);
     // with clear_counts this thread is the only reader of the counts at n and ni (the inner
     // node of one plane node): it clears them for the next step's map pass once read
     if (clear_counts && cn) mp.cnt[n] = 0u;
@@ -465,7 +469,7 @@ __global__ __launch_bounds__(256) void k_open_bc(
         for (int p = 0; p < 19; ++p)
             store_pop<ST, RT>(fout + (size_t)p * (size_t)kp.ld, (unsigned)n, RT(w_(p)) * (rb - RT(1)), kp,
                               (unsigned)p | slt);
-        for (int a = 0; a < 3; ++a) vel_of(uout, n)[a] = RT(0);
+        store_vel_nt(vel_of(uout, n), z0, z0, z0);
         return;
     }
     RT f[19];
@@ -500,10 +504,7 @@ __global__ __launch_bounds__(256) void k_open_bc(
         store_pop<ST, RT>(fout + (size_t)p * (size_t)kp.ld, (unsigned)n, feb + (RT(1) - om) * (f[p] - fei), kp,
                           (unsigned)p | slt);
     }
-    RT* uo = vel_of(uout, n);
-    uo[0] = ux;
-    uo[1] = uy;
-    uo[2] = uz;
+    store_vel_nt(vel_of(uout, n), ux, uy, uz);
 }
 
 // ---- spread-field probe: g and T per fluid node (same device function as the step) -------
@@ -543,7 +544,7 @@ __global__ __launch_bounds__(256) void k_clear_counts(uint32_t* __restrict__ cnt
 template <typename ST, typename RT>
 __global__ __launch_bounds__(256) void k_observe_partials(const ST* __restrict__ f,
                                                           const uint32_t* __restrict__ nodeword,
-                                                          const RT* __restrict__ u, KParams kp,
+                                                          const void* __restrict__ u, KParams kp,
                                                           double* __restrict__ partials)
 {
     double acc[6] = {0, 0, 0, 0, 0, 0};   // mass, px, py, pz, sum uz, n_fluid
@@ -562,7 +563,9 @@ __global__ __launch_bounds__(256) void k_observe_partials(const ST* __restrict__
         acc[1] += px;
         acc[2] += py;
         acc[3] += pz;
-        acc[4] += (double)vel_of(u, (unsigned)n)[2];
+        RT un[3];
+        load_vel<RT>(u, (unsigned)n, kp, un);
+        acc[4] += (double)un[2];
         acc[5] += 1.0;
     }
     __shared__ double red[6][256];
@@ -590,7 +593,7 @@ __global__ void k_observe_final(const double* __restrict__ partials, int nblk, d
 
 // ---- wall shear stress at wall-adjacent nodes (FP64) ----------------------------------------
 template <typename RT>
-__global__ __launch_bounds__(256) void k_wss(const RT* __restrict__ sig,
+__global__ __launch_bounds__(256) void k_wss(const void* __restrict__ sig,
                                              const long long* __restrict__ wn_node,
                                              const double* __restrict__ wn_nrm, int nwn, KParams kp,
                                              double* __restrict__ wss, double* __restrict__ acc,
@@ -600,7 +603,9 @@ __global__ __launch_bounds__(256) void k_wss(const RT* __restrict__ sig,
     if (k >= nwn) return;
     const long long n = wn_node[k];
     double s[6];
-    for (int a = 0; a < 6; ++a) s[a] = (double)str_of(sig, (unsigned)n)[a];
+    RT sv[6];
+    load_str<RT>(sig, (unsigned)n, kp, sv);
+    for (int a = 0; a < 6; ++a) s[a] = (double)sv[a];
     const double n0 = wn_nrm[3 * k], n1 = wn_nrm[3 * k + 1], n2 = wn_nrm[3 * k + 2];
     const double t0 = s[0] * n0 + s[3] * n1 + s[4] * n2;
     const double t1 = s[3] * n0 + s[1] * n1 + s[5] * n2;
@@ -645,8 +650,9 @@ __global__ __launch_bounds__(256) void kf_stream(const FusedArgs fa)
     const SlotDesc& d = *fa.slot[sl];
     const KParams kp = d.kp;
     const bool odd = (fa.parity >> sl) & 1ull;
-    const PlanesLd<ST, RT> pl{(const ST*)(odd ? d.fB : d.fA), (ST*)(odd ? d.fA : d.fB), (RT*)d.b.u,
-                              (RT*)d.b.sig, (unsigned long long)kp.ld};
+    using FT = typename FieldOf<ST, RT>::T;
+    const PlanesLd<ST, RT> pl{(const ST*)(odd ? d.fB : d.fA), (ST*)(odd ? d.fA : d.fB), (FT*)d.b.u,
+                              (FT*)d.b.sig, (unsigned long long)kp.ld};
     const MapPlanes<RT> mp = map_planes_dev<RT>(d.b.map_ids, d.b.map_vals, d.b.cnt, kp);
     const unsigned slt = step_salt<ST>(d.b.step_ctr, odd ? 1 : 0, kp, lb == 0 && threadIdx.x == 0 && threadIdx.y == 0);
     if (kp.compact) {
@@ -683,8 +689,8 @@ void launch_stream_collide(const void* fin, void* fout, const uint32_t* nodeword
         pl.in[p] = (const ST*)fin + p * ld;
         pl.out[p] = (ST*)fout + p * ld;
     }
-    pl.u = (RT*)u;
-    pl.sig = (RT*)sig;
+    pl.u = (typename Planes<ST, RT>::FT*)u;
+    pl.sig = (typename Planes<ST, RT>::FT*)sig;
     const auto mp = map_planes<RT>(ids, vals, cnt, kp);
     const Gather<RT>* g = (const Gather<RT>*)gat;
     if (kp.compact) {
@@ -717,7 +723,8 @@ void launch_open_bc(const void* fin, void* fout, const uint32_t* nodeword, const
     if (nplane <= 0) return;
     hipLaunchKernelGGL((k_open_bc<ST, RT>), dim3((nplane + 255) / 256), dim3(256), 0, st,
                        (const ST*)fin, (ST*)fout, nodeword, planes, nplane,
-                       map_planes<RT>(ids, vals, cnt, kp), (const Gather<RT>*)gat, (RT*)u, (RT*)sig, kp,
+                       map_planes<RT>(ids, vals, cnt, kp), (const Gather<RT>*)gat,
+                       (typename FieldOf<ST, RT>::T*)u, (typename FieldOf<ST, RT>::T*)sig, kp,
                        tab, clear_counts ? 1 : 0, ctr, par);
 }
 
@@ -741,7 +748,7 @@ void launch_observe(const void* f, const uint32_t* nodeword, const void* u, cons
                     double* partials, int nblk, double* out, hipStream_t st)
 {
     hipLaunchKernelGGL((k_observe_partials<ST, RT>), dim3(nblk), dim3(256), 0, st, (const ST*)f,
-                       nodeword, (const RT*)u, kp, partials);
+                       nodeword, u, kp, partials);
     hipLaunchKernelGGL(k_observe_final, dim3(1), dim3(64), 0, st, partials, nblk, out);
 }
 
@@ -750,7 +757,7 @@ void launch_wss(const void* sig, const long long* wn_node, const double* wn_nrm,
                 const KParams& kp, double* wss, double* acc, int accumulate, hipStream_t st)
 {
     if (nwn <= 0) return;
-    hipLaunchKernelGGL((k_wss<RT>), dim3((nwn + 255) / 256), dim3(256), 0, st, (const RT*)sig,
+    hipLaunchKernelGGL((k_wss<RT>), dim3((nwn + 255) / 256), dim3(256), 0, st, sig,
                        wn_node, wn_nrm, nwn, kp, wss, acc, accumulate);
 }
 

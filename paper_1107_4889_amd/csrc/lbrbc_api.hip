@@ -30,6 +30,11 @@ constexpr double COMPACT_MAX_FRACTION = 0.6;
 
 int storage_bytes(int s) { return s == LB_F64 ? 8 : (s == LB_F32 ? 4 : 2); }
 int real_bytes(int s) { return s == LB_F64 ? 8 : 4; }
+// u and sigma elements: the compute precision, or 16 bits (BF16, or FP16 times 2^12) for the
+// 16-bit storages, whose velocity record is padded to four elements
+int field_bytes(int s) { return storage_bytes(s); }
+int vel_stride(int s) { return field_bytes(s) == 2 ? 4 : 3; }
+constexpr double FIELD16_SCALE_HOST = 4096.0;
 
 // ---- host geometry tables --------------------------------------------------------------------
 struct Geometry {
@@ -477,8 +482,9 @@ Layout layout(const lb_config& c, const Geometry& g, int n_rbc)
     };
     L.fA = take(19 * ld * ss);
     L.fB = take(19 * ld * ss);
-    L.u = take(3 * ld * rs);
-    L.sig = take(6 * ld * rs);
+    const size_t fs = field_bytes(c.storage);
+    L.u = take(vel_stride(c.storage) * ld * fs);
+    L.sig = take(6 * ld * fs);
     L.gdbg = take(3 * ld * rs);
     L.tdbg = take(ld * rs);
     L.nodeword = take(ld * 4);
@@ -703,6 +709,17 @@ void store_real(void* p, size_t i, int storage, double v)
     if (storage == LB_F64) ((double*)p)[i] = v;
     else ((float*)p)[i] = (float)v;
 }
+// one element of u or sigma (the same roundings as the device's field stores)
+double load_field(const void* p, size_t i, int storage)
+{
+    if (field_bytes(storage) != 2) return load_real(p, i, storage);
+    return load_stored(p, i, storage, 1.0 / FIELD16_SCALE_HOST);
+}
+void store_field(void* p, size_t i, int storage, double v)
+{
+    if (field_bytes(storage) != 2) store_real(p, i, storage, v);
+    else store_value(p, i, storage, v, FIELD16_SCALE_HOST);
+}
 
 lb_status check_fault(lb_ctx c)
 {
@@ -887,6 +904,7 @@ void enqueue_fused_step(lb_ctx* cs, int n, FusedSide* fs)
     if (fs) (void)hipStreamWaitEvent(s, fs->join, 0);
     FusedArgs fa;
     fa.n = n;
+    fa.field16 = cs[0]->kp.field16;
     fa.parity = 0;
     size_t lds_map = 0, lds_tile = 0;
     for (int i = 0; i < n; ++i) {
@@ -1045,6 +1063,7 @@ lb_status lb_init(const lb_config* cfg, const uint8_t* solid, const lb_rbc* cell
     kp.tile_max = g.tile_max;
     kp.cand_cap = g.cand_cap;
     kp.bf16_sr = C.storage == LB_BF16 && !C.bf16_nearest ? 1 : 0;
+    kp.field16 = C.storage == LB_BF16 ? 1 : (C.storage == LB_F16 ? 2 : 0);
     kp.moving_walls = 0;
     for (int a = 0; a < 3; ++a) {
         kp.uw_lo[a] = C.wall_u_lo[a];
@@ -1552,21 +1571,28 @@ lb_status lb_get_fields(lb_ctx c, double* f, double* u, double* sigma, double* g
             for (size_t n = 0; n < N; ++n)
                 f[p * N + n] = w_(p) + (ks[n] < 0 ? 0.0 : load_stored(h.data(), p * ld + ks[n], S, inv));
     }
-    // inter = true: node-interleaved (u, sigma: element k * comps + a), else planes a * ld + k
-    auto planes = [&](size_t off, int k, double* out, bool inter) -> lb_status {
-        std::vector<char> h(k * ld * rs);
+    // the fields u and sigma: node-interleaved records of `stride` elements (element
+    // k * stride + a); the debug planes g and T: compute precision, planes a * ld + k
+    auto fields = [&](size_t off, int k, int stride, double* out) -> lb_status {
+        std::vector<char> h(stride * ld * field_bytes(S));
         HIPCHK(c, hipMemcpy(h.data(), c->base + off, h.size(), hipMemcpyDeviceToHost));
         for (int a = 0; a < k; ++a)
             for (size_t n = 0; n < N; ++n)
-                out[n * k + a] = ks[n] < 0 ? 0.0
-                                           : load_real(h.data(), inter ? (size_t)ks[n] * k + a : a * ld + ks[n], S);
+                out[n * k + a] = ks[n] < 0 ? 0.0 : load_field(h.data(), (size_t)ks[n] * stride + a, S);
+        return LB_OK;
+    };
+    auto planes = [&](size_t off, int k, double* out) -> lb_status {
+        std::vector<char> h(k * ld * rs);
+        HIPCHK(c, hipMemcpy(h.data(), c->base + off, h.size(), hipMemcpyDeviceToHost));
+        for (int a = 0; a < k; ++a)
+            for (size_t n = 0; n < N; ++n) out[n * k + a] = ks[n] < 0 ? 0.0 : load_real(h.data(), a * ld + ks[n], S);
         return LB_OK;
     };
     lb_status r;
-    if (u && (r = planes(c->lay.u, 3, u, true)) != LB_OK) return r;
-    if (sigma && (r = planes(c->lay.sig, 6, sigma, true)) != LB_OK) return r;
-    if (g && (r = planes(c->lay.gdbg, 3, g, false)) != LB_OK) return r;
-    if (relax && (r = planes(c->lay.tdbg, 1, relax, false)) != LB_OK) return r;
+    if (u && (r = fields(c->lay.u, 3, vel_stride(S), u)) != LB_OK) return r;
+    if (sigma && (r = fields(c->lay.sig, 6, 6, sigma)) != LB_OK) return r;
+    if (g && (r = planes(c->lay.gdbg, 3, g)) != LB_OK) return r;
+    if (relax && (r = planes(c->lay.tdbg, 1, relax)) != LB_OK) return r;
     return st;
 }
 
@@ -1588,18 +1614,18 @@ lb_status lb_set_fields(lb_ctx c, const double* f, const double* u, const double
                 if (ks[n] >= 0) store_value(h.data(), p * ld + ks[n], S, f[p * N + n] - w_(p), scale);
         HIPCHK(c, hipMemcpy(c->fA, h.data(), h.size(), hipMemcpyHostToDevice));
     }
-    // u and sigma are node-interleaved on the device (element k * comps + a)
-    auto planes = [&](size_t off, int k, const double* in) -> lb_status {
-        std::vector<char> h(k * ld * rs, 0);
+    // u and sigma are node-interleaved records of `stride` elements on the device
+    auto fields = [&](size_t off, int k, int stride, const double* in) -> lb_status {
+        std::vector<char> h(stride * ld * field_bytes(S), 0);
         for (int a = 0; a < k; ++a)
             for (size_t n = 0; n < N; ++n)
-                if (ks[n] >= 0) store_real(h.data(), (size_t)ks[n] * k + a, S, in[n * k + a]);
+                if (ks[n] >= 0) store_field(h.data(), (size_t)ks[n] * stride + a, S, in[n * k + a]);
         HIPCHK(c, hipMemcpy(c->base + off, h.data(), h.size(), hipMemcpyHostToDevice));
         return LB_OK;
     };
     lb_status r;
-    if (u && (r = planes(c->lay.u, 3, u)) != LB_OK) return r;
-    if (sigma && (r = planes(c->lay.sig, 6, sigma)) != LB_OK) return r;
+    if (u && (r = fields(c->lay.u, 3, vel_stride(S), u)) != LB_OK) return r;
+    if (sigma && (r = fields(c->lay.sig, 6, 6, sigma)) != LB_OK) return r;
     HIPCHK(c, hipMemset(c->cb.err, 0, 4));
     c->poisoned = false;
     c->fault = 0;
@@ -1727,7 +1753,7 @@ lb_status rbc_get_map(lb_ctx c, int* off, int* ids, long long* len)
 // Version 2 also records the lattice shape, the FP16 scale, the BF16 rounding mode and a
 // hash of the node words (geometry and boundary flags): a checkpoint loads only into a context
 // whose stored populations mean the same thing.
-constexpr int CKPT_VERSION = 2;
+constexpr int CKPT_VERSION = 3;
 struct CkptHeader {
     char magic[8];
     int version, storage, nrbc, nwn;
@@ -1742,7 +1768,9 @@ lb_status lb_save(lb_ctx c, void* buf, size_t* bytes)
 {
     if (!c || !bytes) return LB_EINVAL;
     const size_t ld = (size_t)c->kp.ld;
-    const size_t fb = 19 * ld * storage_bytes(c->cfg.storage), rb = 9 * ld * real_bytes(c->cfg.storage);
+    const size_t fb = 19 * ld * storage_bytes(c->cfg.storage);
+    const size_t ub = vel_stride(c->cfg.storage) * ld * field_bytes(c->cfg.storage),
+                 sgb = 6 * ld * field_bytes(c->cfg.storage), rb = ub + sgb;
     const size_t sb = c->nrbc * sizeof(RbcState), wb = c->geo.wn_node.size() * 8;
     const size_t need = sizeof(CkptHeader) + fb + rb + sb + wb;
     if (!buf) {
@@ -1772,9 +1800,8 @@ lb_status lb_save(lb_ctx c, void* buf, size_t* bytes)
     p += sizeof h;
     HIPCHK(c, hipMemcpy(p, c->fA, fb, hipMemcpyDeviceToHost));
     p += fb;
-    HIPCHK(c, hipMemcpy(p, c->base + c->lay.u, 3 * ld * real_bytes(c->cfg.storage), hipMemcpyDeviceToHost));
-    HIPCHK(c, hipMemcpy(p + 3 * ld * real_bytes(c->cfg.storage), c->base + c->lay.sig,
-                        6 * ld * real_bytes(c->cfg.storage), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(p, c->base + c->lay.u, ub, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(p + ub, c->base + c->lay.sig, sgb, hipMemcpyDeviceToHost));
     p += rb;
     if (sb) HIPCHK(c, hipMemcpy(p, c->cb.st, sb, hipMemcpyDeviceToHost));
     p += sb;
@@ -1789,7 +1816,9 @@ lb_status lb_load(lb_ctx c, const void* buf, size_t bytes)
     CkptHeader h;
     std::memcpy(&h, buf, sizeof h);
     const size_t ld = (size_t)c->kp.ld;
-    const size_t fb = 19 * ld * storage_bytes(c->cfg.storage), rb = 9 * ld * real_bytes(c->cfg.storage);
+    const size_t fb = 19 * ld * storage_bytes(c->cfg.storage);
+    const size_t ub = vel_stride(c->cfg.storage) * ld * field_bytes(c->cfg.storage),
+                 sgb = 6 * ld * field_bytes(c->cfg.storage), rb = ub + sgb;
     const size_t sb = c->nrbc * sizeof(RbcState), wb = c->geo.wn_node.size() * 8;
     if (std::memcmp(h.magic, "LBRBCCK1", 8) != 0 || h.version != CKPT_VERSION)
         return fail(c, LB_EINVAL, "not a checkpoint of this library version");
@@ -1804,9 +1833,8 @@ lb_status lb_load(lb_ctx c, const void* buf, size_t bytes)
     const char* p = (const char*)buf + sizeof h;
     HIPCHK(c, hipMemcpy(c->fA, p, fb, hipMemcpyHostToDevice));
     p += fb;
-    HIPCHK(c, hipMemcpy(c->base + c->lay.u, p, 3 * ld * real_bytes(c->cfg.storage), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(c->base + c->lay.sig, p + 3 * ld * real_bytes(c->cfg.storage),
-                        6 * ld * real_bytes(c->cfg.storage), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->base + c->lay.u, p, ub, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->base + c->lay.sig, p + ub, sgb, hipMemcpyHostToDevice));
     p += rb;
     if (sb) HIPCHK(c, hipMemcpy(c->cb.st, p, sb, hipMemcpyHostToDevice));
     p += sb;

@@ -79,6 +79,7 @@ struct KParams {
     int bf16_sr;      // BF16 storage with stochastic rounding
     int moving_walls; // wall_u_lo or wall_u_hi nonzero
     double uw_lo[3], uw_hi[3];   // velocities of the solid nodes below / from the mid-plane y = ny/2
+    int field16;      // u and sigma in 16 bits: 0 no (compute precision), 1 BF16, 2 FP16 times 2^12
 };
 
 // ---- compact layout -------------------------------------------------------------------------
@@ -244,22 +245,68 @@ struct MapPlanes {
 // xz yz): the map pass reads them at the few consecutive covered nodes of each support row, so
 // one node's components share a cache line instead of sitting in 3 and 6 separate planes. The
 // stream-collide writes them for consecutive nodes, which stays contiguous per wavefront.
-template <typename RT>
-__device__ __forceinline__ RT* vel_of(RT* u, unsigned k) { return u + 3 * (size_t)k; }
-template <typename RT>
-__device__ __forceinline__ const RT* vel_of(const RT* u, unsigned k) { return u + 3 * (size_t)k; }
-template <typename RT>
-__device__ __forceinline__ RT* str_of(RT* s, unsigned k) { return s + 6 * (size_t)k; }
-template <typename RT>
-__device__ __forceinline__ const RT* str_of(const RT* s, unsigned k) { return s + 6 * (size_t)k; }
+// Their element type is the compute precision for FP64 and FP32 storage. The 16-bit storages
+// keep them in 16 bits as well (KParams::field16): BF16 rounded to nearest even, or FP16
+// holding the value times 2^12 (|value| < 16; the velocity is bounded by 0.3 and the stress far
+// below that). A 16-bit velocity record is padded to four elements, so that a node's u is one
+// aligned 8-byte word and its sigma three 4-byte words.
+template <typename ST, typename RT>
+struct FieldOf {
+    using T = RT;
+};
+template <>
+struct FieldOf<bf16_t, float> {
+    using T = bf16_t;
+};
+template <>
+struct FieldOf<_Float16, float> {
+    using T = _Float16;
+};
+constexpr float FIELD16_SCALE = 4096.0f, FIELD16_INV = 1.0f / 4096.0f;
+template <typename FT>
+constexpr unsigned vel_stride() { return sizeof(FT) == 2 ? 4u : 3u; }
+
+template <typename FT>
+__device__ __forceinline__ FT* vel_of(FT* u, unsigned k) { return u + vel_stride<FT>() * (size_t)k; }
+template <typename FT>
+__device__ __forceinline__ const FT* vel_of(const FT* u, unsigned k) { return u + vel_stride<FT>() * (size_t)k; }
+template <typename FT>
+__device__ __forceinline__ FT* str_of(FT* s, unsigned k) { return s + 6 * (size_t)k; }
+template <typename FT>
+__device__ __forceinline__ const FT* str_of(const FT* s, unsigned k) { return s + 6 * (size_t)k; }
+
+// 16-bit field codes (low 16 bits of the result)
+__device__ __forceinline__ uint32_t bf16_rne_bits(float v)
+{
+    const uint32_t u = __float_as_uint(v);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return 0x7fc0u;
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+template <typename FT>
+__device__ __forceinline__ uint32_t field_code(float v)
+{
+    if constexpr (std::is_same<FT, bf16_t>::value) return bf16_rne_bits(v);
+    else return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(v * FIELD16_SCALE));
+}
+__device__ __forceinline__ float field_value(uint32_t h, int mode)
+{
+    h &= 0xffffu;
+    return mode == 1 ? __uint_as_float(h << 16)
+                     : (float)__builtin_bit_cast(_Float16, (uint16_t)h) * FIELD16_INV;
+}
 
 // streaming (non-temporal) stores of one node's u and sigma as a few vector stores
-template <typename RT>
-__device__ __forceinline__ void store_vel_nt(RT* p, RT a, RT b, RT c)
+template <typename FT, typename RT>
+__device__ __forceinline__ void store_vel_nt(FT* p, RT a, RT b, RT c)
 {
-    if constexpr (sizeof(RT) == 4) {
+    if constexpr (sizeof(FT) == 2) {
+        // the padded record: one 8-byte store
+        typedef uint32_t V2 __attribute__((ext_vector_type(2)));
+        const V2 v = {field_code<FT>(a) | field_code<FT>(b) << 16, field_code<FT>(c)};
+        __builtin_nontemporal_store(v, reinterpret_cast<V2*>(p));
+    } else if constexpr (sizeof(FT) == 4) {
         // one 12-byte store (the 3-vector's store size; its 16-byte allocation size is not used)
-        typedef RT V3 __attribute__((ext_vector_type(3), aligned(4)));
+        typedef FT V3 __attribute__((ext_vector_type(3), aligned(4)));
         const V3 v = {a, b, c};
         __builtin_nontemporal_store(v, reinterpret_cast<V3*>(p));
     } else {
@@ -269,33 +316,87 @@ __device__ __forceinline__ void store_vel_nt(RT* p, RT a, RT b, RT c)
         __builtin_nontemporal_store(c, p + 2);
     }
 }
-template <typename RT>
-__device__ __forceinline__ void store_str_nt(RT* p, RT s0, RT s1, RT s2, RT s3, RT s4, RT s5)
+template <typename FT, typename RT>
+__device__ __forceinline__ void store_str_nt(FT* p, RT s0, RT s1, RT s2, RT s3, RT s4, RT s5)
 {
-    typedef RT V2 __attribute__((ext_vector_type(2)));   // 6k elements: aligned to 2 elements
-    const V2 a = {s0, s1}, b = {s2, s3}, c = {s4, s5};
-    __builtin_nontemporal_store(a, reinterpret_cast<V2*>(p));
-    __builtin_nontemporal_store(b, reinterpret_cast<V2*>(p + 2));
-    __builtin_nontemporal_store(c, reinterpret_cast<V2*>(p + 4));
+    if constexpr (sizeof(FT) == 2) {
+        // 12 bytes at 12k: one 3-word store
+        typedef uint32_t V3 __attribute__((ext_vector_type(3), aligned(4)));
+        const V3 v = {field_code<FT>(s0) | field_code<FT>(s1) << 16, field_code<FT>(s2) | field_code<FT>(s3) << 16,
+                      field_code<FT>(s4) | field_code<FT>(s5) << 16};
+        __builtin_nontemporal_store(v, reinterpret_cast<V3*>(p));
+    } else {
+        typedef FT V2 __attribute__((ext_vector_type(2)));   // 6k elements: aligned to 2 elements
+        const V2 a = {s0, s1}, b = {s2, s3}, c = {s4, s5};
+        __builtin_nontemporal_store(a, reinterpret_cast<V2*>(p));
+        __builtin_nontemporal_store(b, reinterpret_cast<V2*>(p + 2));
+        __builtin_nontemporal_store(c, reinterpret_cast<V2*>(p + 4));
+    }
+}
+
+// one node's u and sigma in the compute precision, from fields of either element type (the
+// per-cell and reduction kernels serve every storage of a compute precision). FM: the field mode
+// (KParams::field16) when the caller's instantiation fixes it, or -1 to read it from kp.
+template <typename RT, int FM = -1>
+__device__ __forceinline__ void load_vel(const void* u, unsigned k, const KParams& kp, RT out[3])
+{
+    if constexpr (sizeof(RT) == 4 && FM != 0) {
+        const int m = FM > 0 ? FM : kp.field16;
+        if (m) {
+            typedef uint32_t V2 __attribute__((ext_vector_type(2)));
+            const V2 w = *(reinterpret_cast<const V2*>(u) + k);
+            out[0] = field_value(w.x, m);
+            out[1] = field_value(w.x >> 16, m);
+            out[2] = field_value(w.y, m);
+            return;
+        }
+    }
+    const RT* p = static_cast<const RT*>(u) + 3 * (size_t)k;
+    out[0] = p[0];
+    out[1] = p[1];
+    out[2] = p[2];
+}
+template <typename RT, int FM = -1>
+__device__ __forceinline__ void load_str(const void* s, unsigned k, const KParams& kp, RT out[6])
+{
+    if constexpr (sizeof(RT) == 4 && FM != 0) {
+        const int m = FM > 0 ? FM : kp.field16;
+        if (m) {
+            const uint32_t* p = static_cast<const uint32_t*>(s) + 3 * (size_t)k;
+            const uint32_t w0 = p[0], w1 = p[1], w2 = p[2];
+            out[0] = field_value(w0, m);
+            out[1] = field_value(w0 >> 16, m);
+            out[2] = field_value(w1, m);
+            out[3] = field_value(w1 >> 16, m);
+            out[4] = field_value(w2, m);
+            out[5] = field_value(w2 >> 16, m);
+            return;
+        }
+    }
+    const RT* p = static_cast<const RT*>(s) + 6 * (size_t)k;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) out[q] = p[q];
 }
 
 // per-plane pointers of one stream-collide launch (kernel argument)
 template <typename ST, typename RT>
 struct Planes {
+    using FT = typename FieldOf<ST, RT>::T;
     const ST* in[19];
     ST* out[19];
-    RT* u;
-    RT* sig;
+    FT* u;
+    FT* sig;
     __device__ const ST* src(int p) const { return in[p]; }
     __device__ ST* dst(int p) const { return out[p]; }
 };
 // the same planes from the buffer bases and the plane stride (fused multi-lattice launches)
 template <typename ST, typename RT>
 struct PlanesLd {
+    using FT = typename FieldOf<ST, RT>::T;
     const ST* fin;
     ST* fout;
-    RT* u;
-    RT* sig;
+    FT* u;
+    FT* sig;
     unsigned long long ld;
     __device__ const ST* src(int p) const { return fin + (unsigned long long)p * ld; }
     __device__ ST* dst(int p) const { return fout + (unsigned long long)p * ld; }

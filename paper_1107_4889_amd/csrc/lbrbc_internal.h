@@ -78,6 +78,7 @@ struct FusedArgs {
     const SlotDesc* slot[FUSE_MAX];
     int start[FUSE_MAX + 1];
     int n;
+    int field16;          // KParams::field16 of the slots (host side: selects the map pass)
     unsigned long long parity;
 };
 // one step of every slot; every slot has the same storage type ST/RT, no open boundary and

@@ -378,7 +378,7 @@ __device__ void map_couple_tile(int i, unsigned char* smem, const RbcState* __re
                                 const uint32_t* __restrict__ nodeword, const int* __restrict__ segmap,
                                 uint32_t* __restrict__ cnt,
                                 int* __restrict__ ids, RT* __restrict__ vals,
-                                const RT* __restrict__ u, const RT* __restrict__ sig,
+                                const void* __restrict__ u, const void* __restrict__ sig,
                                 const KParams& kp, unsigned* __restrict__ err)
 {
     const int tm = kp.tile_max;
@@ -502,7 +502,8 @@ __device__ void map_couple_tile(int i, unsigned char* smem, const RbcState* __re
         const RT gx = RT(0.5) * ((xp ? raw[t + 1] : RT(0)) - (xm ? raw[t - 1] : RT(0)));
         const RT gy = RT(0.5) * ((yp ? raw[t + sx] : RT(0)) - (ym ? raw[t - sx] : RT(0)));
         const RT gz = RT(0.5) * ((zp ? raw[t + sxy] : RT(0)) - (zm ? raw[t - sxy] : RT(0)));
-        const RT* un = vel_of(u, n);
+        RT un[3];
+        load_vel<RT>(u, n, kp, un);
         const RT ux = un[0], uy = un[1], uz = un[2];
         const uint32_t old = atomicAdd(cnt + n, 1u);
         const int slot = (int)old;
@@ -530,7 +531,8 @@ __device__ void map_couple_tile(int i, unsigned char* smem, const RbcState* __re
         const RT g2 = hx * hx + hy * hy + hz * hz;
         const RT il = g2 > RT(0) ? fast_rsqrt(g2) : RT(0);
         const RT nx_ = hx * il, ny_ = hy * il, nz_ = hz * il;
-        const RT* sn = str_of(sig, n);
+        RT sn[6];
+        load_str<RT>(sig, n, kp, sn);
         const RT sxx = sn[0], syy = sn[1], szz = sn[2], sxy_ = sn[3], sxz = sn[4], syz = sn[5];
         const RT t0 = sxx * nx_ + sxy_ * ny_ + sxz * nz_;
         const RT t1 = sxy_ * nx_ + syy * ny_ + syz * nz_;
@@ -576,8 +578,8 @@ __global__ __launch_bounds__(MC_THREADS) void k_map_couple_tile(const RbcState* 
                                                                 int* __restrict__ ids,
                                                                 RT* __restrict__ vals,
                                                                 const int* __restrict__ ovf,
-                                                                const RT* __restrict__ u,
-                                                                const RT* __restrict__ sig,
+                                                                const void* __restrict__ u,
+                                                                const void* __restrict__ sig,
                                                                 KParams kp,
                                                                 unsigned* __restrict__ err)
 {
@@ -599,7 +601,7 @@ __global__ __launch_bounds__(MC_THREADS) void k_map_couple_tile(const RbcState* 
 // the covered range of every row contains the support range of the row and of its four
 // neighbouring rows. More candidates than kp.cand_cap: the cell goes to the overflow list
 // ovf[1 + k] (count ovf[0]) for k_map_couple_tile.
-template <typename RT>
+template <typename RT, int FM>
 __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
                                                 const RbcState* __restrict__ st,
                                                 RbcCouple* __restrict__ cp,
@@ -608,8 +610,8 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
                                                 const int* __restrict__ segmap, uint32_t* __restrict__ cnt,
                                                 int* __restrict__ ids, RT* __restrict__ vals,
                                                 const int* __restrict__ order,
-                                                const RT* __restrict__ u,
-                                                const RT* __restrict__ sig, const KParams& kp,
+                                                const void* __restrict__ u,
+                                                const void* __restrict__ sig, const KParams& kp,
                                                 unsigned* __restrict__ err, int* __restrict__ ovf)
 {
     const int i = order[k];
@@ -813,14 +815,12 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
             const RT gx = RT(0.5) * (max(vxp, z0) - max(vxm, z0));
             const RT gy = RT(0.5) * (max(vyp, z0) - max(vym, z0));
             const RT gz = RT(0.5) * (max(vzp, z0) - max(vzm, z0));
-            const RT* un = vel_of(u, n);
+            RT un[3];
+            load_vel<RT, FM>(u, n, kp, un);
             const RT ux = un[0], uy = un[1], uz = un[2];
             // the stress at inside nodes, loaded beside u before the atomic's result is needed
             RT sg[6] = {z0, z0, z0, z0, z0, z0};
-            if (in) {
-                const RT* sn = str_of(sig, n);
-                for (int q = 0; q < 6; ++q) sg[q] = sn[q];
-            }
+            if (in) load_str<RT, FM>(sig, n, kp, sg);
             const uint32_t old = atomicAdd(cnt + n, 1u);
             const int slot = (int)old;
             const int e = (i << kp.ent_shift) | j;
@@ -877,7 +877,8 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
     }
 }
 
-template <typename RT>
+// FM: the field mode of u and sigma (KParams::field16), fixed per instantiation
+template <typename RT, int FM>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_map_couple(const RbcState* __restrict__ st,
                                                    RbcCouple* __restrict__ cp,
                                                    Gather<RT>* __restrict__ gat,
@@ -885,15 +886,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
                                                    const int* __restrict__ segmap, uint32_t* __restrict__ cnt,
                                                    int* __restrict__ ids, RT* __restrict__ vals,
                                                    const int* __restrict__ order,
-                                                   const RT* __restrict__ u,
-                                                   const RT* __restrict__ sig, KParams kp,
+                                                   const void* __restrict__ u,
+                                                   const void* __restrict__ sig, KParams kp,
                                                    unsigned* __restrict__ err,
                                                    int* __restrict__ ovf)
 {
     extern __shared__ unsigned char smem[];
     const int k = xcd_chunk_index(1);
     if (k < kp.nrbc)
-        map_couple_cell<RT>(k, smem, st, cp, gat, nodeword, segmap, cnt, ids, vals, order, u, sig, kp, err, ovf);
+        map_couple_cell<RT, FM>(k, smem, st, cp, gat, nodeword, segmap, cnt, ids, vals, order, u, sig, kp, err, ovf);
 }
 
 // ---- S5: Gay-Berne forces and torques (Sec. II E, Eqs. 24-28; App. B) -----------------------
@@ -1240,7 +1241,7 @@ __global__ __launch_bounds__(256) void kf_sort(const FusedArgs fa)
     if (c < d.kp.ncell[0] * d.kp.ncell[1] * d.kp.ncell[2]) sort_cell(d.b.cell_off, d.b.cell_ids, d.b.cell_cnt, c);
 }
 
-template <typename RT>
+template <typename RT, int FM>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void kf_map(const FusedArgs fa)
 {
     extern __shared__ unsigned char smem[];
@@ -1248,10 +1249,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void kf
     const SlotDesc& d = *fa.slot[fused_slot(fa, lb)];
     const KParams kp = d.kp;
     if (lb < kp.nrbc)
-        map_couple_cell<RT>(lb, smem, d.b.st, d.b.cp, (Gather<RT>*)d.b.gat, d.b.nodeword, d.b.tab.map, d.b.cnt,
+        map_couple_cell<RT, FM>(lb, smem, d.b.st, d.b.cp, (Gather<RT>*)d.b.gat, d.b.nodeword, d.b.tab.map, d.b.cnt,
                             d.b.map_ids,
                             (RT*)d.b.map_vals,
-                            d.b.cell_ids, (const RT*)d.b.u, (const RT*)d.b.sig, kp, d.b.err, d.b.ovf);
+                            d.b.cell_ids, d.b.u, d.b.sig, kp, d.b.err, d.b.ovf);
 }
 
 template <typename RT>
@@ -1266,7 +1267,7 @@ __global__ __launch_bounds__(MC_THREADS) void kf_map_tile(const FusedArgs fa)
         map_couple_tile<RT>(d.b.ovf[1 + b], smem, d.b.st, d.b.cp, (Gather<RT>*)d.b.gat, d.b.nodeword, d.b.tab.map,
                             d.b.cnt,
                             d.b.map_ids,
-                            (RT*)d.b.map_vals, (const RT*)d.b.u, (const RT*)d.b.sig, kp, d.b.err);
+                            (RT*)d.b.map_vals, d.b.u, d.b.sig, kp, d.b.err);
 }
 
 __global__ __launch_bounds__(256) void kf_gb(const FusedArgs fa)
@@ -1352,20 +1353,34 @@ size_t map_couple_tile_lds(int tile_max, int real_bytes)
     return ((t3 * (real_bytes + 1) + 1) & ~(size_t)1) + 2 * (t3 + MC_THREADS);
 }
 
+// the map pass instantiated for the field mode of u and sigma (FP32 arithmetic: compute
+// precision, BF16 or scaled FP16; FP64 arithmetic: compute precision only)
+template <typename RT, typename F>
+static void with_field_mode(int field16, F&& f)
+{
+    if constexpr (sizeof(RT) == 4) {
+        if (field16 == 1) return f(std::integral_constant<int, 1>{});
+        if (field16 == 2) return f(std::integral_constant<int, 2>{});
+    }
+    f(std::integral_constant<int, 0>{});
+}
+
 template <typename RT>
 void launch_map_couple(const CellBuffers& b, const KParams& kp, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_map_couple<RT>), dim3(grid8(kp.nrbc, 1)), dim3(64),
-                       map_couple_lds(kp.tile_max, kp.cand_cap, (int)sizeof(RT)), st, b.st, b.cp,
-                       (Gather<RT>*)b.gat, b.nodeword, b.tab.map, b.cnt, b.map_ids, (RT*)b.map_vals, b.cell_ids,
-                       (const RT*)b.u,
-                       (const RT*)b.sig, kp, b.err, b.ovf);
+    auto go = [&](auto fm) {
+        hipLaunchKernelGGL((k_map_couple<RT, decltype(fm)::value>), dim3(grid8(kp.nrbc, 1)), dim3(64),
+                           map_couple_lds(kp.tile_max, kp.cand_cap, (int)sizeof(RT)), st, b.st, b.cp,
+                           (Gather<RT>*)b.gat, b.nodeword, b.tab.map, b.cnt, b.map_ids, (RT*)b.map_vals,
+                           b.cell_ids, b.u, b.sig, kp, b.err, b.ovf);
+    };
+    with_field_mode<RT>(kp.field16, go);
     // the overflow list is short (normally empty): a small grid loops over it
     hipLaunchKernelGGL((k_map_couple_tile<RT>), dim3(64), dim3(MC_THREADS),
                        map_couple_tile_lds(kp.tile_max, (int)sizeof(RT)), st, b.st, b.cp,
                        (Gather<RT>*)b.gat, b.nodeword, b.tab.map, b.cnt, b.map_ids, (RT*)b.map_vals, b.ovf,
-                       (const RT*)b.u,
-                       (const RT*)b.sig, kp, b.err);
+                       b.u,
+                       b.sig, kp, b.err);
 }
 
 __global__ __launch_bounds__(256) void k_zero_ints(int* __restrict__ p, long long n)
@@ -1431,7 +1446,11 @@ void launch_fused_cells(const FusedArgs& fa, int stage, size_t lds, hipStream_t 
     case FS_SCAN: hipLaunchKernelGGL(kf_scan, dim3(g), dim3(SCAN_THREADS), 0, st, fa); break;
     case FS_SCATTER: hipLaunchKernelGGL(kf_scatter, dim3(g), dim3(256), 0, st, fa); break;
     case FS_SORT: hipLaunchKernelGGL(kf_sort, dim3(g), dim3(256), 0, st, fa); break;
-    case FS_MAP: hipLaunchKernelGGL((kf_map<RT>), dim3(g), dim3(64), lds, st, fa); break;
+    case FS_MAP:
+        with_field_mode<RT>(fa.field16, [&](auto fm) {
+            hipLaunchKernelGGL((kf_map<RT, decltype(fm)::value>), dim3(g), dim3(64), lds, st, fa);
+        });
+        break;
     case FS_MAP_TILE: hipLaunchKernelGGL((kf_map_tile<RT>), dim3(g), dim3(MC_THREADS), lds, st, fa); break;
     case FS_GB: hipLaunchKernelGGL(kf_gb, dim3(g), dim3(256), 0, st, fa); break;
     case FS_RB2: hipLaunchKernelGGL(kf_kick, dim3(g), dim3(128), 0, st, fa); break;
