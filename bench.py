@@ -215,6 +215,10 @@ def run_serving(args):
         "chunk_steps": args.chunk,
         "hip_graphs": bool(args.graphs),
         "fused_launches": bool(args.fused),
+        # fused: one launch per stage over every resident request (cell binning, scan, scatter,
+        # sort, map pass, overflow map pass, Gay-Berne, kick, stream-collide); otherwise the
+        # same stages per request
+        "kernel_launches_per_step": 9 if args.fused else "9-11 per request",
         "budget_gib": args.budget_gib,
         "max_active": args.max_active,
         "mean_queue_wait_s": round(float(np.mean([r.admitted - r.arrival for r in results])), 4),
