@@ -1068,6 +1068,28 @@ __device__ __forceinline__ void gay_berne_cell(int k, const RbcState* __restrict
     const double smin_cc = sqrt(4.0 * amin * amin);
     double F[3] = {0, 0, 0}, tl[3] = {0, 0, 0};
     const double rcc2 = kp.rc_pair * kp.rc_pair, rcw2 = kp.rc_wall * kp.rc_wall;
+    // Pairs beyond the cut-off shell are skipped before the contact distance sigma is formed:
+    // gb_pair returns nothing for them (rho^6 > 2, i.e. R - sigma > (2^(1/6) - 1) sigma_min).
+    // Cell-cell: sigma^2 = 2 R^2 / (r^T H^-1 r) <= 2 r^T H r / R^2 for the symmetric positive
+    // definite H = A_i + A_j (Cauchy-Schwarz), with r^T A r = sum_k s_k^2 ((Q^T r)_k)^2.
+    // Cell-wall: H = A_i + a_w^2 1 is diagonal in the body frame, sigma^2 = 2 R^2 / sum_k
+    // (Q_i^T r)_k^2 / (s_k^2 + a_w^2). A margin of 1e-9 (1 + R) keeps every pair the rounding
+    // of either form could leave in range, so the forces and the overlap flag are unchanged.
+    const double shell = exp2(1.0 / 6.0) - 1.0;
+    const double dcc = shell * smin_cc, dcw = shell * kp.sigmin_wall;
+    auto body_sq = [&](const double* Q, const double* r, const double* wk) {
+        double q = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double y = Q[0 * 3 + k] * r[0] + Q[1 * 3 + k] * r[1] + Q[2 * 3 + k] * r[2];
+            q += wk[k] * y * y;
+        }
+        return q;
+    };
+    double s2[3], hw[3];
+    for (int k = 0; k < 3; ++k) {
+        s2[k] = kp.axes[k] * kp.axes[k];
+        hw[k] = 1.0 / (s2[k] + kp.a_wall * kp.a_wall);
+    }
     int bad = 0;
     const CandidateRanges& rc = ranges[wv][0];
     for (int e = lane; e < rc.total; e += 64) {
@@ -1075,7 +1097,13 @@ __device__ __forceinline__ void gay_berne_cell(int k, const RbcState* __restrict
         if (j == i) continue;
         double r[3];
         for (int a = 0; a < 3; ++a) r[a] = min_img(Ri[a] - st[j].R[a], box_len(kp, a), kp.per[a]);
-        if (r[0] * r[0] + r[1] * r[1] + r[2] * r[2] > rcc2) continue;
+        const double R2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        if (R2 > rcc2) continue;
+        {
+            const double R = sqrt(R2);
+            const double sub = sqrt(2.0 * (body_sq(Qi, r, s2) + body_sq(st[j].Q, r, s2)) / R2);
+            if (R - sub > dcc + 1e-9 * (1.0 + R)) continue;
+        }
         double Aj[9], Hi[9];
         shape_matrix(kp, st[j].Q, Aj);
         gb_inverse(Ai, Aj, Hi);
@@ -1091,7 +1119,13 @@ __device__ __forceinline__ void gay_berne_cell(int k, const RbcState* __restrict
             double r[3];
             for (int a = 0; a < 3; ++a)
                 r[a] = min_img(Ri[a] - (double)wall_xyz[3 * wq + a], box_len(kp, a), kp.per[a]);
-            if (r[0] * r[0] + r[1] * r[1] + r[2] * r[2] > rcw2) continue;
+            const double R2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            if (R2 > rcw2) continue;
+            {
+                const double R = sqrt(R2);
+                const double sig = sqrt(2.0 * R2 / body_sq(Qi, r, hw));
+                if (R - sig > dcw + 1e-9 * (1.0 + R)) continue;
+            }
             bad |= gb_pair(kp, r, Ai, Hw, kp.sigmin_wall, F, tl);
         }
     }
@@ -1270,12 +1304,14 @@ __global__ __launch_bounds__(MC_THREADS) void kf_map_tile(const FusedArgs fa)
                             (RT*)d.b.map_vals, d.b.u, d.b.sig, kp, d.b.err);
 }
 
-__global__ __launch_bounds__(256) void kf_gb(const FusedArgs fa)
+// one cell per one-wavefront block, as k_gay_berne: beside the map pass and the stream-collide
+// a block needing several wave slots at once waits long for them
+__global__ __launch_bounds__(64) void kf_gb(const FusedArgs fa)
 {
     int lb;
     const SlotDesc& d = *fa.slot[fused_slot(fa, lb)];
     const KParams kp = d.kp;
-    const int k = lb * 4 + (int)(threadIdx.x >> 6);
+    const int k = lb;
     if (k < kp.nrbc)
         gay_berne_cell(k, d.b.st, d.b.cp[0].Fm, d.b.cp[0].Tm, COUPLE_STRIDE, d.b.cell_ids, d.b.cell_off,
                        d.b.cell_ids, d.b.wall_xyz, d.b.wcell_off, d.b.wcell_ids, kp, d.b.err);
@@ -1429,7 +1465,7 @@ int fused_blocks(const KParams& kp, int stage)
     case FS_CLEAR: return cells > 0 ? (int)nblk(kp.N, 256) : 0;
     case FS_MAP: return cells;
     case FS_MAP_TILE: return cells > 0 ? FUSED_TILE_BLOCKS : 0;
-    case FS_GB: return (int)nblk(cells, 4);
+    case FS_GB: return cells;
     case FS_RB2: return (int)nblk(cells, 128);
     case FS_STREAM: return (int)nblk(kp.N, 256);
     default: return 0;
@@ -1452,7 +1488,7 @@ void launch_fused_cells(const FusedArgs& fa, int stage, size_t lds, hipStream_t 
         });
         break;
     case FS_MAP_TILE: hipLaunchKernelGGL((kf_map_tile<RT>), dim3(g), dim3(MC_THREADS), lds, st, fa); break;
-    case FS_GB: hipLaunchKernelGGL(kf_gb, dim3(g), dim3(256), 0, st, fa); break;
+    case FS_GB: hipLaunchKernelGGL(kf_gb, dim3(g), dim3(64), 0, st, fa); break;
     case FS_RB2: hipLaunchKernelGGL(kf_kick, dim3(g), dim3(128), 0, st, fa); break;
     default: break;
     }
