@@ -862,15 +862,15 @@ bool fusable(lb_ctx c, lb_ctx first)
 }
 
 // A second stream (default priority) per device for the fused batches' cell work, as the side
-// stream of a single context: the Gay-Berne stage (it needs only the cell list) runs beside the
-// count clearing and the map pass, and the kick (it needs the map pass) beside the
-// stream-collide; the next step's first stage waits for the kick. Events fork and join it.
-// Created on the first batch call of a device (never during a capture); the mutex keeps one host
-// thread at a time enqueuing with the shared events. A batch call ends joined.
+// stream of a single context: after the map passes, the Gay-Berne stage and the kick (it needs
+// both) run beside the stream-collide; the next step's first stage waits for the kick. Events
+// fork and join it. Created on the first batch call of a device (never during a capture); the
+// mutex keeps one host thread at a time enqueuing with the shared events. A batch call ends
+// joined.
 struct FusedSide {
     std::mutex mu;
     hipStream_t side = nullptr;
-    hipEvent_t fork = nullptr, mapped = nullptr, join = nullptr;
+    hipEvent_t mapped = nullptr, join = nullptr;
     bool ready = false;
 };
 
@@ -885,8 +885,7 @@ FusedSide* fused_side(int dev)
         int cur = 0;
         if (hipGetDevice(&cur) != hipSuccess || cur != dev) return nullptr;
         if (hipStreamCreateWithFlags(&f.side, hipStreamNonBlocking) != hipSuccess) return nullptr;
-        if (hipEventCreateWithFlags(&f.fork, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&f.mapped, hipEventDisableTiming) != hipSuccess ||
+        if (hipEventCreateWithFlags(&f.mapped, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&f.join, hipEventDisableTiming) != hipSuccess)
             return nullptr;
         f.ready = true;
@@ -943,19 +942,17 @@ void enqueue_fused_step(lb_ctx* cs, int n, FusedSide* fs)
             fa.start[n] = tot;
             launch_fused_lattice<ST, RT>(fa, FS_CLEAR, s);
         }
-        if (fs) {
-            starts(FS_GB);
-            (void)hipEventRecord(fs->fork, s);
-            (void)hipStreamWaitEvent(fs->side, fs->fork, 0);
-            launch_fused_cells<RT>(fa, FS_GB, 0, fs->side);
-        }
         starts(FS_MAP);
         launch_fused_cells<RT>(fa, FS_MAP, lds_map, s);
         starts(FS_MAP_TILE);
         launch_fused_cells<RT>(fa, FS_MAP_TILE, lds_tile, s);
         if (fs) {
+            // the Gay-Berne stage and the kick run beside the stream-collide (beside the map
+            // passes they held the overflow pass's blocks back)
             (void)hipEventRecord(fs->mapped, s);
             (void)hipStreamWaitEvent(fs->side, fs->mapped, 0);
+            starts(FS_GB);
+            launch_fused_cells<RT>(fa, FS_GB, 0, fs->side);
             starts(FS_RB2);
             launch_fused_cells<RT>(fa, FS_RB2, 0, fs->side);
             (void)hipEventRecord(fs->join, fs->side);
