@@ -174,7 +174,8 @@ def run_serving(args):
 
     def req(d, arrival=None):
         cfg = dict(nx=d["nx"], ny=d["ny"], nz=d["nz"], periodic=(0, 0, 1), tau0=0.8,
-                   g_ext=(0.0, 0.0, 1e-6), storage=args.storage, f16_scale=2.0 ** 21)
+                   g_ext=(0.0, 0.0, 1e-6), storage=args.storage, f16_scale=2.0 ** 21,
+                   layout=LAYOUTS[getattr(args, "layout", "auto")])
         return Request(rid=d["rid"], arrival=d["arrival"] if arrival is None else arrival,
                        cfg=cfg, solid=d["solid"], R=d["R"], Q=d["Q"], steps=d["steps"])
 
