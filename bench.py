@@ -63,11 +63,10 @@ MAP_COVERED_PER_CELL, MAP_INSIDE_PER_CELL = 391.6, 191.9
 
 
 def map_bytes_per_cell(storage: str) -> float:
-    # r: compute precision (the coverage entries); v: u and sigma elements (16 bits for the
-    # 16-bit storages)
-    r = 8 if storage == "f64" else 4
+    # v: the element of u, sigma and the coverage entries (the compute precision; 16 bits for
+    # the 16-bit storages)
     v = {"f64": 8, "f32": 4}.get(storage, 2)
-    return MAP_COVERED_PER_CELL * (4 + 3 * v + 8 + 4 + 4 * r) + MAP_INSIDE_PER_CELL * 6 * v
+    return MAP_COVERED_PER_CELL * (4 + 3 * v + 8 + 4 + 4 * v) + MAP_INSIDE_PER_CELL * 6 * v
 
 
 def map_pass_record(storage: str, n_cells: int, map_ms: float):

@@ -12,7 +12,7 @@ static MapPlanes<RT> map_planes(const int* ids, const void* vals, uint32_t* cnt,
 {
     MapPlanes<RT> mp;
     for (int k = 0; k < CAP_MAX; ++k) mp.ids[k] = ids + (k < kp.cap ? (size_t)k * (size_t)kp.ld : 0);
-    mp.vals0 = (const RT*)vals;
+    mp.vals0 = vals;
     mp.cnt = cnt;
     return mp;
 }
@@ -41,7 +41,8 @@ __device__ __forceinline__ void sort_keys(int* key)
     }
 }
 
-template <typename RT, int CN>
+// FM: the field mode (entries in 16 bits for the 16-bit storages), or -1 to read it from kp
+template <typename RT, int CN, int FM>
 __device__ __forceinline__ void spread_slots(unsigned n, int cnt, const MapPlanes<RT>& mp,
                                              const Gather<RT>* __restrict__ gat, const KParams& kp,
                                              RT g[3], RT& theta)
@@ -59,8 +60,8 @@ __device__ __forceinline__ void spread_slots(unsigned n, int cnt, const MapPlane
 #pragma unroll
         for (int j = 0; j + 1 < CN; ++j) key[j] = key[j + 1];
         const int i = e >> kp.ent_shift;
-        const RT* v = mp.vals0 + 4 * (size_t)e;
-        const RT r0 = v[0], gx = v[1], gy = v[2], gz = v[3];
+        RT r0, gx, gy, gz;
+        load_entry<RT, FM>(mp.vals0, (size_t)e, kp, r0, gx, gy, gz);
         const Gather<RT>& G = gat[i];
         const RT invS = G.invS;
         const RT dh = r0 * invS;
@@ -73,7 +74,7 @@ __device__ __forceinline__ void spread_slots(unsigned n, int cnt, const MapPlane
     }
 }
 
-template <typename RT>
+template <typename RT, int FM>
 __device__ __forceinline__ void spread_at(unsigned n, uint32_t count, const MapPlanes<RT>& mp,
                                           const Gather<RT>* __restrict__ gat, const KParams& kp,
                                           RT g[3], RT& theta)
@@ -85,9 +86,9 @@ __device__ __forceinline__ void spread_at(unsigned n, uint32_t count, const MapP
     int cnt = (int)min(count, (uint32_t)kp.cap);
     // wave-uniform choice of the slot network
     if (!__any(cnt > 0)) return;
-    if (!__any(cnt > 4)) spread_slots<RT, 4>(n, cnt, mp, gat, kp, g, theta);
-    else if (!__any(cnt > 8)) spread_slots<RT, 8>(n, cnt, mp, gat, kp, g, theta);
-    else spread_slots<RT, CAP_MAX>(n, cnt, mp, gat, kp, g, theta);
+    if (!__any(cnt > 4)) spread_slots<RT, 4, FM>(n, cnt, mp, gat, kp, g, theta);
+    else if (!__any(cnt > 8)) spread_slots<RT, 8, FM>(n, cnt, mp, gat, kp, g, theta);
+    else spread_slots<RT, CAP_MAX, FM>(n, cnt, mp, gat, kp, g, theta);
 }
 
 // ---- pull sources in the compact layout -----------------------------------------------------
@@ -311,7 +312,7 @@ __device__ __forceinline__ void stream_collide_node(const PL& pl, const uint32_t
     }
 
     RT g[3], theta;
-    spread_at<RT>(n, cnum, mp, gat, kp, g, theta);
+    spread_at<RT, field_mode_of<ST>()>(n, cnum, mp, gat, kp, g, theta);
 
     // moments of the shifted populations: density excess, momentum, second moments
     RT drho = RT(0), mx = RT(0), my = RT(0), mz = RT(0);
@@ -458,7 +459,7 @@ __global__ __launch_bounds__(256) void k_open_bc(
     const RT rb = z == 0 ? (RT)kp.rho_in : (RT)kp.rho_out;
     RT gb[3], thb;
     const uint32_t cn = mp.cnt[n], cni = inner_fluid ? mp.cnt[ni] : 0u;
-    spread_at<RT>(n, cn, mp, gat, kp, gb, thb);
+    spread_at<RT, field_mode_of<ST>()>(n, cn, mp, gat, kp, gb, thb);
     const RT om = RT(1) / ((RT)kp.tau0 + (RT)kp.delta * thb);
     const RT z0 = RT(0);
     store_str_nt(str_of(sout, n), z0, z0, z0, z0, z0, z0);
@@ -485,7 +486,7 @@ __global__ __launch_bounds__(256) void k_open_bc(
         pull_all<ST, RT, false>(f, fin, at, wi, SegNb{}, kp, std::make_integer_sequence<int, 19>{});
     }
     RT gi[3], thi;
-    spread_at<RT>(ni, cni, mp, gat, kp, gi, thi);
+    spread_at<RT, field_mode_of<ST>()>(ni, cni, mp, gat, kp, gi, thi);
     if (clear_counts && cni) mp.cnt[ni] = 0u;
     RT drho = 0, mx = 0, my = 0, mz = 0;
     for (int p = 0; p < 19; ++p) {
@@ -524,7 +525,7 @@ __global__ __launch_bounds__(256) void k_spread_field(const uint32_t* __restrict
         return;
     }
     RT g[3], th;
-    spread_at<RT>((unsigned)n, mp.cnt[n], mp, gat, kp, g, th);
+    spread_at<RT, -1>((unsigned)n, mp.cnt[n], mp, gat, kp, g, th);
     gout[n] = g[0];
     gout[kp.ld + n] = g[1];
     gout[2 * kp.ld + n] = g[2];
@@ -625,7 +626,7 @@ __device__ __forceinline__ MapPlanes<RT> map_planes_dev(const int* ids, const vo
     MapPlanes<RT> mp;
 #pragma unroll
     for (int k = 0; k < CAP_MAX; ++k) mp.ids[k] = ids + (k < kp.cap ? (size_t)k * (size_t)kp.ld : 0);
-    mp.vals0 = (const RT*)vals;
+    mp.vals0 = vals;
     mp.cnt = cnt;
     return mp;
 }

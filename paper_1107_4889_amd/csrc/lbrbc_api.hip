@@ -491,7 +491,9 @@ Layout layout(const lb_config& c, const Geometry& g, int n_rbc)
     // two coverage sets, alternating with the step's parity
     for (int p = 0; p < 2; ++p) {
         L.map_ids[p] = take(n_rbc > 0 ? (size_t)cap * ld * 4 : 4);
-        L.map_vals[p] = take(n_rbc > 0 ? ((size_t)n_rbc << g.ent_shift) * 4 * rs : 4);
+        // coverage entries: four values in the compute precision, or in 16 bits for the
+        // 16-bit storages
+        L.map_vals[p] = take(n_rbc > 0 ? ((size_t)n_rbc << g.ent_shift) * 4 * (fs == 2 ? 2 : rs) : 4);
         L.cnt[p] = take(ld * 4);   // read at every fluid node, with or without cells
     }
     L.ovf = take(((size_t)n_rbc + 1) * 4);

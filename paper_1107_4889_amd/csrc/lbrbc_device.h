@@ -237,7 +237,7 @@ __device__ __forceinline__ double fast_rsqrt(double x) { return 1.0 / sqrt(x); }
 template <typename RT>
 struct MapPlanes {
     const int* ids[CAP_MAX];
-    const RT* vals0;
+    const void* vals0;   // entries (see store_entry)
     uint32_t* cnt;
 };
 
@@ -376,6 +376,65 @@ __device__ __forceinline__ void load_str(const void* s, unsigned k, const KParam
     const RT* p = static_cast<const RT*>(s) + 6 * (size_t)k;
 #pragma unroll
     for (int q = 0; q < 6; ++q) out[q] = p[q];
+}
+
+// field mode of a storage (KParams::field16) at compile time
+template <typename ST>
+constexpr int field_mode_of()
+{
+    return std::is_same<ST, bf16_t>::value ? 1 : (std::is_same<ST, _Float16>::value ? 2 : 0);
+}
+
+// Coverage entry e: (raw kernel, grad raw) of one (cell, covered node) pair, written by the map
+// pass and read by the spreading. Four values in the compute precision; for the 16-bit storages
+// four FP16 values holding 2^8 times the value (raw <= 1/8 and |grad raw| <= 1/8 for the Peskin
+// kernel), one 8-byte word. FM as for load_vel.
+constexpr float ENTRY16_SCALE = 256.0f, ENTRY16_INV = 1.0f / 256.0f;
+__device__ __forceinline__ uint32_t entry_code(float v)
+{
+    return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(v * ENTRY16_SCALE));
+}
+__device__ __forceinline__ float entry_value(uint32_t h)
+{
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(h & 0xffffu)) * ENTRY16_INV;
+}
+template <typename RT, int FM = -1>
+__device__ __forceinline__ void store_entry(void* vals, size_t e, const KParams& kp, RT r, RT gx, RT gy, RT gz)
+{
+    if constexpr (sizeof(RT) == 4 && FM != 0) {
+        if (FM > 0 || kp.field16) {
+            typedef uint32_t V2 __attribute__((ext_vector_type(2)));
+            const V2 w = {entry_code(r) | entry_code(gx) << 16, entry_code(gy) | entry_code(gz) << 16};
+            *(reinterpret_cast<V2*>(vals) + e) = w;
+            return;
+        }
+    }
+    RT* v = static_cast<RT*>(vals) + 4 * e;
+    v[0] = r;
+    v[1] = gx;
+    v[2] = gy;
+    v[3] = gz;
+}
+template <typename RT, int FM = -1>
+__device__ __forceinline__ void load_entry(const void* vals, size_t e, const KParams& kp, RT& r, RT& gx, RT& gy,
+                                           RT& gz)
+{
+    if constexpr (sizeof(RT) == 4 && FM != 0) {
+        if (FM > 0 || kp.field16) {
+            typedef uint32_t V2 __attribute__((ext_vector_type(2)));
+            const V2 w = *(reinterpret_cast<const V2*>(vals) + e);
+            r = entry_value(w.x);
+            gx = entry_value(w.x >> 16);
+            gy = entry_value(w.y);
+            gz = entry_value(w.y >> 16);
+            return;
+        }
+    }
+    const RT* v = static_cast<const RT*>(vals) + 4 * e;
+    r = v[0];
+    gx = v[1];
+    gy = v[2];
+    gz = v[3];
 }
 
 // per-plane pointers of one stream-collide launch (kernel argument)

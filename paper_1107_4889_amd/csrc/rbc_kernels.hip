@@ -377,7 +377,7 @@ __device__ void map_couple_tile(int i, unsigned char* smem, const RbcState* __re
                                 RbcCouple* __restrict__ cp, Gather<RT>* __restrict__ gat,
                                 const uint32_t* __restrict__ nodeword, const int* __restrict__ segmap,
                                 uint32_t* __restrict__ cnt,
-                                int* __restrict__ ids, RT* __restrict__ vals,
+                                int* __restrict__ ids, void* __restrict__ vals,
                                 const void* __restrict__ u, const void* __restrict__ sig,
                                 const KParams& kp, unsigned* __restrict__ err)
 {
@@ -510,11 +510,7 @@ __device__ void map_couple_tile(int i, unsigned char* smem, const RbcState* __re
         const int e = (i << kp.ent_shift) | j;
         if (slot < kp.cap && j < (1 << kp.ent_shift)) {
             ids[(size_t)slot * ld + n] = e;
-            RT* v = vals + 4 * (size_t)e;
-            v[0] = r;
-            v[1] = gx;
-            v[2] = gy;
-            v[3] = gz;
+            store_entry<RT>(vals, (size_t)e, kp, r, gx, gy, gz);
         } else {
             atomicOr(err, ERR_CAPACITY);
         }
@@ -576,7 +572,7 @@ __global__ __launch_bounds__(MC_THREADS) void k_map_couple_tile(const RbcState* 
                                                                 const int* __restrict__ segmap,
                                                                 uint32_t* __restrict__ cnt,
                                                                 int* __restrict__ ids,
-                                                                RT* __restrict__ vals,
+                                                                void* __restrict__ vals,
                                                                 const int* __restrict__ ovf,
                                                                 const void* __restrict__ u,
                                                                 const void* __restrict__ sig,
@@ -608,7 +604,7 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
                                                 Gather<RT>* __restrict__ gat,
                                                 const uint32_t* __restrict__ nodeword,
                                                 const int* __restrict__ segmap, uint32_t* __restrict__ cnt,
-                                                int* __restrict__ ids, RT* __restrict__ vals,
+                                                int* __restrict__ ids, void* __restrict__ vals,
                                                 const int* __restrict__ order,
                                                 const void* __restrict__ u,
                                                 const void* __restrict__ sig, const KParams& kp,
@@ -826,11 +822,7 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
             const int e = (i << kp.ent_shift) | j;
             if (slot < kp.cap && j < (1 << kp.ent_shift)) {
                 ids[(size_t)slot * ld + n] = e;
-                RT* w4 = vals + 4 * (size_t)e;
-                w4[0] = rr;
-                w4[1] = gx;
-                w4[2] = gy;
-                w4[3] = gz;
+                store_entry<RT, FM>(vals, (size_t)e, kp, rr, gx, gy, gz);
             } else {
                 atomicOr(err, ERR_CAPACITY);
             }
@@ -884,7 +876,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
                                                    Gather<RT>* __restrict__ gat,
                                                    const uint32_t* __restrict__ nodeword,
                                                    const int* __restrict__ segmap, uint32_t* __restrict__ cnt,
-                                                   int* __restrict__ ids, RT* __restrict__ vals,
+                                                   int* __restrict__ ids, void* __restrict__ vals,
                                                    const int* __restrict__ order,
                                                    const void* __restrict__ u,
                                                    const void* __restrict__ sig, KParams kp,
@@ -1285,7 +1277,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void kf
     if (lb < kp.nrbc)
         map_couple_cell<RT, FM>(lb, smem, d.b.st, d.b.cp, (Gather<RT>*)d.b.gat, d.b.nodeword, d.b.tab.map, d.b.cnt,
                             d.b.map_ids,
-                            (RT*)d.b.map_vals,
+                            d.b.map_vals,
                             d.b.cell_ids, d.b.u, d.b.sig, kp, d.b.err, d.b.ovf);
 }
 
@@ -1301,7 +1293,7 @@ __global__ __launch_bounds__(MC_THREADS) void kf_map_tile(const FusedArgs fa)
         map_couple_tile<RT>(d.b.ovf[1 + b], smem, d.b.st, d.b.cp, (Gather<RT>*)d.b.gat, d.b.nodeword, d.b.tab.map,
                             d.b.cnt,
                             d.b.map_ids,
-                            (RT*)d.b.map_vals, d.b.u, d.b.sig, kp, d.b.err);
+                            d.b.map_vals, d.b.u, d.b.sig, kp, d.b.err);
 }
 
 // one cell per one-wavefront block, as k_gay_berne: beside the map pass and the stream-collide
@@ -1407,14 +1399,14 @@ void launch_map_couple(const CellBuffers& b, const KParams& kp, hipStream_t st)
     auto go = [&](auto fm) {
         hipLaunchKernelGGL((k_map_couple<RT, decltype(fm)::value>), dim3(grid8(kp.nrbc, 1)), dim3(64),
                            map_couple_lds(kp.tile_max, kp.cand_cap, (int)sizeof(RT)), st, b.st, b.cp,
-                           (Gather<RT>*)b.gat, b.nodeword, b.tab.map, b.cnt, b.map_ids, (RT*)b.map_vals,
+                           (Gather<RT>*)b.gat, b.nodeword, b.tab.map, b.cnt, b.map_ids, b.map_vals,
                            b.cell_ids, b.u, b.sig, kp, b.err, b.ovf);
     };
     with_field_mode<RT>(kp.field16, go);
     // the overflow list is short (normally empty): a small grid loops over it
     hipLaunchKernelGGL((k_map_couple_tile<RT>), dim3(64), dim3(MC_THREADS),
                        map_couple_tile_lds(kp.tile_max, (int)sizeof(RT)), st, b.st, b.cp,
-                       (Gather<RT>*)b.gat, b.nodeword, b.tab.map, b.cnt, b.map_ids, (RT*)b.map_vals, b.ovf,
+                       (Gather<RT>*)b.gat, b.nodeword, b.tab.map, b.cnt, b.map_ids, b.map_vals, b.ovf,
                        b.u,
                        b.sig, kp, b.err);
 }
