@@ -20,9 +20,8 @@
  *   8. pull stream + BGK collision with body force (Eqs. 1-8), halfway bounce-back
  * Steps 4 uses the velocity and stress stored by step 8 of the previous step.
  *
- * Parity partly unpinned: the stress torque T^S of step 4 (Eq. 16). Its symmetries, its sign
- * and its linearity in alpha are pinned; no closed form fixes its magnitude, which the tests
- * check only against the GPU path.
+ * The stress torque T^S of step 4 (Eq. 16) is pinned by its symmetries, its sign, its
+ * linearity in alpha and a four-node configuration whose value is worked out by hand.
  */
 #include "lbrbc_oracle.h"
 
