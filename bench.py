@@ -55,10 +55,11 @@ def measured_traffic(workload: str, storage: str, layout: str):
     return d.get("bytes_per_launch")
 
 
-# The map pass's algorithmic bytes per cell (FP32 / FP64 reals): for each covered node (391.6
-# per cell on average for the (4, 4, 1.5) support over sampled orientations and offsets) its
-# node word (4 B), u (3 reals), its coverage count read and written (8 B), the slot id (4 B) and
-# the entry (raw, grad raw: 4 reals); for each inside node (191.9 per cell) sigma (6 reals).
+# The map pass's algorithmic bytes per cell: for each covered node (391.6 per cell on average
+# for the (4, 4, 1.5) support over sampled orientations and offsets) its node word (4 B), u (3
+# elements), its coverage count read and written (8 B), the slot id (4 B) and the entry (raw,
+# grad raw: 4 elements); for each inside node (191.9 per cell) sigma (6 elements). Elements are
+# in the compute precision, 16 bits for the 16-bit storages.
 MAP_COVERED_PER_CELL, MAP_INSIDE_PER_CELL = 391.6, 191.9
 
 

@@ -79,7 +79,8 @@ struct KParams {
     int bf16_sr;      // BF16 storage with stochastic rounding
     int moving_walls; // wall_u_lo or wall_u_hi nonzero
     double uw_lo[3], uw_hi[3];   // velocities of the solid nodes below / from the mid-plane y = ny/2
-    int field16;      // u and sigma in 16 bits: 0 no (compute precision), 1 BF16, 2 FP16 times 2^12
+    int field16;      // 16-bit storages: u and sigma in BF16 (1) or FP16 times 2^12 (2), coverage
+                      // entries in FP16 times 2^8 (both); 0: all in the compute precision
 };
 
 // ---- compact layout -------------------------------------------------------------------------
