@@ -89,6 +89,42 @@ def test_graph_every_replay_matches_eager():
         assert o_e.mass == o_g.mass and o_e.flow_rate == o_g.flow_rate
 
 
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_fused_batch_16bit_equals_each_alone(storage):
+    """The fused stages of the 16-bit storages (u, sigma and the coverage entries in 16 bits,
+    BF16 with its step-salted stochastic rounding) give each context the bits it gets alone."""
+    import hashlib
+
+    import torch
+
+    from paper_1107_4889_amd import lbrbc
+
+    reqs = _requests(3, seed=81, steps=(30, 30))
+    cases = [(dict(r.cfg, storage=storage, f16_scale=2.0 ** 21), r.solid, r.R, r.Q) for r in reqs]
+    nsteps = [24, 36, 30]
+    print(f"fused {storage}: {len(cases)} contexts", flush=True)
+
+    def digest(sim):
+        return hashlib.sha1(sim.lb_save()[88:]).hexdigest()
+
+    alone = []
+    for (cfg, solid, R, Q), n in zip(cases, nsteps):
+        sim = lbrbc.Simulation(cfg, solid, R=R, Q=Q)
+        sim.lb_step(n)
+        sim.lb_sync()
+        alone.append(digest(sim))
+        del sim
+    shared = torch.cuda.Stream()
+    sims = [lbrbc.Simulation(cfg, solid, R=R, Q=Q, stream=shared) for cfg, solid, R, Q in cases]
+    for sim in sims:
+        sim.lb_step(4)
+    lbrbc.lb_batch_step(sims, [n - 4 for n in nsteps])
+    torch.cuda.synchronize()
+    for k, (sim, d) in enumerate(zip(sims, alone)):
+        assert sim.lb_observe().flags == 0
+        assert digest(sim) == d, k
+
+
 def test_fused_batch_equals_each_alone():
     """lb_batch_step over contexts on one stream runs each stage as one launch for all of them
     (fused); each context ends bitwise where it ends when stepped alone. The mix has different
