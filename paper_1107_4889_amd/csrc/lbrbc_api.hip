@@ -1601,7 +1601,6 @@ lb_status lb_set_fields(lb_ctx c, const double* f, const double* u, const double
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const int S = c->cfg.storage;
     const size_t N = (size_t)c->geo.nodes, ld = (size_t)c->kp.ld;
-    const size_t rs = real_bytes(S);
     // nodes that are not stored (compact layout) are solid: their values are dropped
     std::vector<long long> ks(N);
     for (size_t n = 0; n < N; ++n) ks[n] = c->geo.store_of((long long)n, c->cfg.nx, c->cfg.ny);
@@ -1748,10 +1747,11 @@ lb_status rbc_get_map(lb_ctx c, int* off, int* ids, long long* len)
     return st;
 }
 
-// checkpoint: header, populations (storage precision), u, sigma, cell states, WSS sums
-// Version 2 also records the lattice shape, the FP16 scale, the BF16 rounding mode and a
-// hash of the node words (geometry and boundary flags): a checkpoint loads only into a context
-// whose stored populations mean the same thing.
+// checkpoint: header, populations (storage precision), u, sigma (their element type and
+// record layout), cell states, WSS sums. The header records the lattice shape, the FP16 scale,
+// the BF16 rounding mode and a hash of the node words (geometry and boundary flags): a
+// checkpoint loads only into a context whose stored values mean the same thing. Version 3: u and
+// sigma of the 16-bit storages in 16 bits.
 constexpr int CKPT_VERSION = 3;
 struct CkptHeader {
     char magic[8];
