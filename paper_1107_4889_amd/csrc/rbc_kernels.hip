@@ -694,9 +694,12 @@ __device__ __forceinline__ void map_couple_cell(int k, unsigned char* smem,
     }
     auto wrap3 = [&](auto inner, int& X, int& Y, int& Z) -> bool {
         if constexpr (decltype(inner)::value) return true;
-        else
-            return wrap_coord(X, kp.nx, kp.per[0]) & wrap_coord(Y, kp.ny, kp.per[1]) &
-                   wrap_coord(Z, kp.nz, kp.per[2]);
+        else {
+            // every axis is wrapped (no short-circuit): the three coordinates are all updated
+            const int in_x = wrap_coord(X, kp.nx, kp.per[0]), in_y = wrap_coord(Y, kp.ny, kp.per[1]),
+                      in_z = wrap_coord(Z, kp.nz, kp.per[2]);
+            return in_x && in_y && in_z;
+        }
     };
     auto mimg = [&](auto inner, double d, double L, int per) -> double {
         if constexpr (decltype(inner)::value) return d;
