@@ -65,6 +65,37 @@ def test_bifurcation_with_cells_f64_and_f32():
     assert np.linalg.norm(u32 - ref.u()[fl]) / np.linalg.norm(ref.u()[fl]) < 1e-4
 
 
+@pytest.mark.parametrize("storage,bar", [("bf16", 1e-2), ("f16", 2e-3)])
+def test_bifurcation_with_cells_16bit(storage, bar):
+    """The open planes and the compact layout in the 16-bit storages (their u, sigma and coverage
+    entries in 16 bits), against the FP64 oracle at the 16-bit velocity targets."""
+    from paper_1107_4889_amd import lbrbc
+
+    nx, ny, nz = 48, 40, 64
+    solid = synth.y_bifurcation(nx, ny, nz, r_parent=10.0, r_daughter=8.0, z_branch=36.0)
+    pl = synth.place_cells(solid[16:nz - 16], synth.AXES, 12, seed=5, periodic=(0, 0, 0))
+    R = pl.R + np.array([0.0, 0.0, 16.0])
+    cfg = dict(nx=nx, ny=ny, nz=nz, periodic=(0, 0, 0), tau0=0.8, open_z=1, rho_in=1.002,
+               rho_out=0.998)
+    print(f"Y-bifurcation 48x40x64, {len(R)} cells, {storage}: oracle 40 steps", flush=True)
+    ref = orc.Oracle(cfg, solid, R=R, Q=pl.Q)
+    assert ref.step(40) == 0
+    fl = solid.reshape(-1) == 0
+    ur = ref.u()[fl]
+    for layout in (2, 1):           # compact, then dense
+        sim = lbrbc.Simulation(dict(cfg, storage=storage, f16_scale=2.0 ** 21, layout=layout), solid,
+                               R=R, Q=pl.Q)
+        assert sim.lb_observe().compact == (1 if layout == 2 else 0)
+        sim.lb_step(40)
+        assert sim.lb_observe().flags == 0
+        u = sim.lb_get_fields(f=False, sigma=False)["u"][fl]
+        err = np.linalg.norm(u - ur) / np.linalg.norm(ur)
+        print(f"{storage}, layout {layout}: u rel L2 {err:.3e}", flush=True)
+        assert err < bar
+        assert np.abs(sim.rbc_get_state()[0] - ref.rbc()[0]).max() < 1e-5
+        del sim
+
+
 def test_cells_covering_the_open_planes_f64():
     """Cells whose supports cover the inlet and outlet planes and the layers the boundary
     extrapolates from: the boundary kernel reads the coverage counts there after the
