@@ -58,9 +58,11 @@ def test_graph_replay_matches_eager():
         assert e.digest == g.digest, (e.rid, e.steps)
 
 
-def test_graph_every_replay_matches_eager():
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_graph_every_replay_matches_eager(storage):
     """Each replay of a captured 16-step chunk leaves the state an eager 16-step chunk does;
-    eager work (observables, syncs) runs between the replays."""
+    eager work (observables, syncs) runs between the replays. In BF16 the stochastic rounding's
+    step term comes from the device counter, which every replay advances."""
     import hashlib
 
     import torch
@@ -68,9 +70,10 @@ def test_graph_every_replay_matches_eager():
     from paper_1107_4889_amd import lbrbc
 
     r = _requests(1, seed=79, steps=(64, 64))[0]
+    cfg = dict(r.cfg, storage=storage)
     s_e, s_g = torch.cuda.Stream(), torch.cuda.Stream()
-    eager = lbrbc.Simulation(r.cfg, r.solid, R=r.R, Q=r.Q, stream=s_e)
-    graph = lbrbc.Simulation(r.cfg, r.solid, R=r.R, Q=r.Q, stream=s_g)
+    eager = lbrbc.Simulation(cfg, r.solid, R=r.R, Q=r.Q, stream=s_e)
+    graph = lbrbc.Simulation(cfg, r.solid, R=r.R, Q=r.Q, stream=s_g)
     g = torch.cuda.CUDAGraph()
     torch.cuda.synchronize()
     with torch.cuda.stream(s_g):
