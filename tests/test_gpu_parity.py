@@ -181,10 +181,14 @@ def test_coupled_100_steps_f32_and_16bit(lb, small, ref100):
     print("velocity rel-L2 vs FP64 oracle after 100 coupled steps:", errs)
 
 
-def test_bitwise_repeatable_and_checkpoint(lb, small):
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
+def test_bitwise_repeatable_and_checkpoint(lb, small, storage):
+    """Two runs agree bit for bit, and a checkpoint taken halfway resumes to the same bits
+    (in BF16 including the stochastic rounding's step term, which the checkpoint restores)."""
     solid, pl, cfg = small
-    a = lb.Simulation(dict(cfg, storage="f32"), solid, R=pl.R, Q=pl.Q)
-    b = lb.Simulation(dict(cfg, storage="f32"), solid, R=pl.R, Q=pl.Q)
+    cfg = dict(cfg, storage=storage, f16_scale=2.0 ** 21)
+    a = lb.Simulation(cfg, solid, R=pl.R, Q=pl.Q)
+    b = lb.Simulation(cfg, solid, R=pl.R, Q=pl.Q)
     a.lb_step(20)
     blob = a.lb_save()
     a.lb_step(20)
@@ -192,10 +196,12 @@ def test_bitwise_repeatable_and_checkpoint(lb, small):
     fa, fb = a.lb_get_fields(), b.lb_get_fields()
     assert np.array_equal(fa["f"], fb["f"]) and np.array_equal(fa["u"], fb["u"])
     assert np.array_equal(a.rbc_get_state()[0], b.rbc_get_state()[0])
-    c = lb.Simulation(dict(cfg, storage="f32"), solid, R=pl.R, Q=pl.Q)
+    c = lb.Simulation(cfg, solid, R=pl.R, Q=pl.Q)
     c.lb_load(blob)
     c.lb_step(20)
-    assert np.array_equal(c.lb_get_fields()["f"], fa["f"])
+    fc = c.lb_get_fields()
+    assert np.array_equal(fc["f"], fa["f"]) and np.array_equal(fc["u"], fa["u"])
+    assert np.array_equal(fc["sigma"], fa["sigma"])
     assert np.array_equal(c.rbc_get_state()[1], a.rbc_get_state()[1])
     assert c.lb_observe().step == 40
 
