@@ -34,7 +34,7 @@ int real_bytes(int s) { return s == LB_F64 ? 8 : 4; }
 // 16-bit storages, whose velocity record is padded to four elements
 int field_bytes(int s) { return storage_bytes(s); }
 int vel_stride(int s) { return field_bytes(s) == 2 ? 4 : 3; }
-constexpr double FIELD16_SCALE_HOST = 4096.0;
+constexpr double FIELD16_SCALE_HOST = FIELD16_SCALE;   // the device's FP16 field scale
 
 // ---- host geometry tables --------------------------------------------------------------------
 struct Geometry {
